@@ -1,0 +1,152 @@
+/*
+ * rpf.h -- C ABI of the rpForests kNN library for AMD MI355X (gfx950).
+ *
+ * kNN search by random projection forests (Yan, Wang, Wang, Wang, Li, arXiv 1812.11689):
+ *   - rpf_build     grows an ensemble of T random projection trees over the points U
+ *                   (Alg. 3 lines 1-3 with Alg. 1 and Alg. 2; median split point, Sec. 2);
+ *   - rpf_all_knn   finds the K nearest neighbours of every point of U among the union
+ *                   of its leaves (Alg. 3 with Q = U, lines 4-10);
+ *   - rpf_query     lets external queries fall through every tree and searches the union
+ *                   of the reached leaves (Alg. 3 lines 4-10).
+ *
+ * Conventions for every entry point
+ *   - Array arguments named *_dev are DEVICE pointers of the current HIP device; host
+ *     pointers are named *_host.  Sizes are element counts.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it and
+ *     the call returns without waiting, unless stated otherwise.  Device faults surface
+ *     at a later call or at stream synchronisation as RPF_EDEVICE.
+ *   - Every call returns an rpf_status; rpf_last_error() gives a message (thread-local).
+ *     On an error, outputs are left untouched and *out handles are set to NULL.
+ *   - No C++ exception crosses this boundary.
+ *
+ * Arithmetic (a reading of Sec. 2 / Alg. 1 / Alg. 3, which fix no arithmetic):
+ *   - projection p = r.x in binary64: 32 partial sums by j mod 32 of exact binary32 x
+ *     binary32 products, then a balanced adjacent-pair tree, then + 0.0;
+ *   - split: members ordered by the key (p, original index); the floor(m/2) smallest go
+ *     left; split value c = p of the member of rank floor(m/2);
+ *   - neighbours are ranked by (D, index) with D the binary64 squared Euclidean distance
+ *     (32 partial sums of fma(delta, delta, s), same tree); reported distances are
+ *     (float)sqrt(D).
+ */
+#ifndef RPF_H
+#define RPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPF_OK = 0,
+    RPF_EINVAL = -1,    /* invalid argument (sizes, null pointers, non-finite inputs)      */
+    RPF_ENOMEM = -2,    /* the plan exceeds mem_budget_bytes, or a device allocation failed */
+    RPF_EDEVICE = -3,   /* a HIP runtime or kernel error                                   */
+    RPF_EBUSY = -4,     /* a serving queue is full                                          */
+    RPF_ENOTREADY = -5, /* a polled request has not finished                                */
+    RPF_EINTERNAL = -6  /* an internal invariant failed                                     */
+} rpf_status;
+
+/* Split point rule.  Only the median (Sec. 2, "choose the median") is implemented. */
+typedef enum { RPF_SPLIT_MEDIAN = 0 } rpf_split;
+
+/* Precision of the candidate distance tiles (the MFMA Gram products).  Whatever the tile
+ * precision, the returned neighbours are the exact top-K of the leaf union under the
+ * binary64 ranking: tile distances only prune, with rigorous error bounds, and the
+ * surviving candidates are re-ranked in binary32 and, near the K-th distance, binary64. */
+typedef enum { RPF_DIST_FP32 = 0, RPF_DIST_BF16 = 1, RPF_DIST_FP16 = 2 } rpf_dist_prec;
+
+typedef struct rpf_forest rpf_forest; /* opaque; owns all of its device memory */
+
+typedef struct {
+    int32_t n_trees;     /* T >= 1 (Alg. 3, ensemble size)                                  */
+    int32_t leaf_size;   /* n0 >= 1: a node is split iff it holds more than n0 points, so
+                            every leaf holds at most n0 (Alg. 1, n_s = n0 + 1)              */
+    int32_t n_try;       /* nTry >= 1 random directions per node, the one with the largest
+                            spread of projections is used (Alg. 2); 1 = basic rpTree        */
+    int32_t split_rule;  /* rpf_split; must be RPF_SPLIT_MEDIAN                             */
+    int32_t dist_prec;   /* rpf_dist_prec for the candidate tiles                           */
+    int32_t reserved;    /* must be 0                                                       */
+    const float *directions_dev; /* random directions (Alg. 1 line 8, Alg. 2 line 3), binary32
+                            [n_trees][2^L - 1][n_try][d], row h-1 for heap node h (root 1,
+                            children 2h, 2h+1), L = rpf_depth(n, leaf_size).  Required; it is
+                            copied, so the caller may free it once the build's work ends.   */
+    uint64_t mem_budget_bytes; /* 0 = unlimited; otherwise rpf_build fails with RPF_ENOMEM
+                            when the forest's device memory would exceed it                 */
+} rpf_params;
+
+/* Tree depth L = number of split levels for n points and leaf size n0 (host only). */
+int32_t rpf_depth(int64_t n, int32_t leaf_size);
+
+/* Grow the forest over X_dev (binary32 [n][d], row-major, finite values; copied).
+ * n >= 1, d >= 1, n < 2^31.  On success *out owns the forest; free it with rpf_free. */
+rpf_status rpf_build(const float *X_dev, int64_t n, int32_t d, const rpf_params *params,
+                     void *stream, rpf_forest **out);
+
+/* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
+ * exclude_self = 1 drops each point from its own candidate set.  1 <= K <= n - exclude_self.
+ * Rows shorter than K (|N_q| < K) are padded with (-1, +inf). */
+rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self,
+                       int32_t *out_idx_dev, float *out_dist_dev, void *stream);
+
+/* External queries (Alg. 3 lines 4-10): Q_dev binary32 [m][d] (finite), m >= 0,
+ * 1 <= K <= n.  Outputs [m][K] as for rpf_all_knn. */
+rpf_status rpf_query(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t K,
+                     int32_t *out_idx_dev, float *out_dist_dev, void *stream);
+
+/* Route queries only (Alg. 3 lines 5-7): out_leaf_dev int32 [T][m] = heap id of the leaf
+ * each query reaches in each tree (right child iff projection >= split value). */
+rpf_status rpf_route(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t *out_leaf_dev,
+                     void *stream);
+
+/* Release the forest.  rpf_free(NULL) is a no-op returning RPF_OK.  Synchronises the
+ * device before freeing. */
+rpf_status rpf_free(rpf_forest *f);
+
+/* Introspection for parity tests.  Tree t in [0, T).  Device outputs:
+ *   split_dev double [2^L-1], split_idx_dev int32 [2^L-1], chosen_dev int32 [2^L-1]
+ *   (NaN / -1 / -1 where the heap slot is not an internal node), perm_dev int32 [n] (the
+ *   leaves left to right, members ascending), leaf_of_dev int32 [n] (heap id of the leaf
+ *   holding each point).  Any output pointer may be NULL. */
+rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split_dev,
+                         int32_t *split_idx_dev, int32_t *chosen_dev, int32_t *perm_dev,
+                         int32_t *leaf_of_dev, void *stream);
+
+typedef struct {
+    int64_t n;
+    int32_t d, n_trees, leaf_size, n_try, depth, dist_prec;
+    int64_t n_leaves;
+    uint64_t device_bytes;   /* device memory owned by the forest */
+} rpf_info;
+
+rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);
+
+/* Counters of the last rpf_all_knn / rpf_query on this forest (host, synchronises the
+ * stream): rows that fell back to the exhaustive candidate scan because a pruning buffer
+ * overflowed, and the total number of candidates re-ranked in binary32 / binary64. */
+typedef struct {
+    int64_t rows, fallback_rows, reranked32, reranked64;
+} rpf_knn_stats;
+
+rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out_host, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around every kernel
+ * of the library (off by default).  rpf_profile_read copies up to `cap` records. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double algo_bytes;  /* algorithmic bytes moved by these launches (see each kernel) */
+    double algo_flops;  /* algorithmic flops of these launches                          */
+} rpf_profile_record;
+
+rpf_status rpf_profile_enable(int32_t on);
+rpf_status rpf_profile_reset(void);
+rpf_status rpf_profile_read(rpf_profile_record *out_host, int32_t cap, int32_t *count);
+
+const char *rpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPF_H */

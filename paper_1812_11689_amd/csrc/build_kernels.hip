@@ -1,0 +1,820 @@
+// Tree growth (Alg. 1 with the median split point of Sec. 2, direction choice of Alg. 2),
+// level-synchronous over all trees: at level l every internal node of every tree is a
+// contiguous segment of that tree's permutation, and one launch processes all of them
+// (grid.y = tree).  Per node: project the members onto the node's direction (binary64,
+// canonical order), select the member of rank floor(m/2) in (p, index) order, and
+// partition stably so that both children stay in ascending original index.
+//
+// Two paths:
+//   - segments of at most kLarge members: one workgroup per (segment, tree) does the whole
+//     step in LDS (k_level_small);
+//   - larger segments: chunked projection with a fused first-digit histogram, radix
+//     passes narrowing an 11-bit digit of the 96-bit key (p, index) per pass until at most
+//     kCandCap candidates remain, an in-block select over the candidates, then a stable
+//     chunked partition (count, scan, scatter).
+#include "rpf_internal.h"
+
+namespace rpf {
+
+// ================================================================ small segments: fused level
+
+__device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &excl, uint32_t &total) {
+    // 256 threads = 4 waves
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t wb = 0, tot = 0;
+    for (int k = 0; k < 4; k++) {
+        uint32_t c = s_w[k];
+        if (k < w) wb += c;
+        tot += c;
+    }
+    excl = wb + x - v;
+    total = tot;
+    __syncthreads();
+}
+
+// canon_sum over s[0..m) in place (s has room for the power-of-two padding P2 >= m)
+__device__ inline double block_canon_sum(double *s, int m) {
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    for (int i = m + threadIdx.x; i < P2; i += blockDim.x) s[i] = 0.0;
+    __syncthreads();
+    for (int h = 1; h < P2; h <<= 1) {
+        for (int i = 2 * h * threadIdx.x; i < P2; i += 2 * h * blockDim.x) s[i] = s[i] + s[i + h];
+        __syncthreads();
+    }
+    double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+template <bool VEC>
+__device__ inline void project_segment(const float *__restrict__ X, int d, const float *s_r,
+                                       const int32_t *s_perm, int m, double *s_p) {
+    const int g = threadIdx.x & 7, pt = threadIdx.x >> 3;
+    const int per = blockDim.x >> 3;
+    for (int base = 0; base < m; base += per) {
+        int i = base + pt;
+        int ii = i < m ? i : 0;
+        double p = group8_dot64<VEC>(X + (int64_t)s_perm[ii] * d, s_r, d, g);
+        if (g == 0 && i < m) s_p[i] = p;
+    }
+}
+
+// LDS layout: perm[m] int32 | key[m] u64 | dir[d] | hist[256] | misc ; nTry>1 adds p[m], tree[P2]
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_level_small(
+    const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
+    const SegDesc *__restrict__ segs, const int32_t *__restrict__ perm_in,
+    int32_t *__restrict__ perm_out, int64_t n, double *__restrict__ split,
+    int32_t *__restrict__ split_idx, int32_t *__restrict__ chosen, int32_t *__restrict__ err) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int t = blockIdx.y;
+    const SegDesc sg = segs[blockIdx.x];
+    const int m = sg.size;
+    const int tid = threadIdx.x;
+    int32_t *s_perm = reinterpret_cast<int32_t *>(smem);
+    uint64_t *s_key = reinterpret_cast<uint64_t *>(smem + ((4 * m + 15) & ~15));
+    float *s_r = reinterpret_cast<float *>(s_key + m);
+    uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_r + ((d + 3) & ~3));
+    uint32_t *s_misc = s_hist + 256;  // 16 words
+    double *s_p = reinterpret_cast<double *>(s_misc + 16);
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    double *s_tree = s_p + m;
+
+    const int32_t *pin = perm_in + (int64_t)t * n + sg.off;
+    for (int i = tid; i < m; i += blockDim.x) s_perm[i] = pin[i];
+    const float *Rn = R + ((int64_t)t * H + (sg.heap - 1)) * n_try * (int64_t)d;
+
+    int ch = 0;
+    if (n_try > 1) {  // Alg. 2: keep the try with the largest spread S2 (first wins ties)
+        double best = 0.0;
+        int best_i = -1;
+        for (int k = 0; k < n_try; k++) {
+            __syncthreads();
+            for (int j = tid; j < d; j += blockDim.x) s_r[j] = Rn[(int64_t)k * d + j];
+            __syncthreads();
+            project_segment<VEC>(X, d, s_r, s_perm, m, s_p);
+            __syncthreads();
+            for (int i = tid; i < m; i += blockDim.x) s_tree[i] = s_p[i];
+            double s1 = block_canon_sum(s_tree, m);
+            double mu = s1 / (double)m;
+            for (int i = tid; i < m; i += blockDim.x) {
+                double dev = s_p[i] - mu;
+                s_tree[i] = __dmul_rn(dev, dev);
+            }
+            double s2 = block_canon_sum(s_tree, m);
+            if (s2 > best) { best = s2; best_i = k; }
+        }
+        ch = best_i < 0 ? 0 : best_i;
+    }
+    __syncthreads();
+    for (int j = tid; j < d; j += blockDim.x) s_r[j] = Rn[(int64_t)ch * d + j];
+    __syncthreads();
+    {
+        const int g = tid & 7, pt = tid >> 3;
+        for (int base = 0; base < m; base += 32) {
+            int i = base + pt;
+            int ii = i < m ? i : 0;
+            double p = group8_dot64<VEC>(X + (int64_t)s_perm[ii] * d, s_r, d, g);
+            if (g == 0 && i < m) s_key[i] = key_of(p);
+        }
+    }
+    __syncthreads();
+
+    // ---- select rank floor(m/2) in (key, index) order: 8-bit radix passes over the 96-bit key
+    uint64_t phi = 0;
+    uint32_t plo = 0;
+    int nbits = 0;
+    uint32_t rank = (uint32_t)(m / 2), cnt = (uint32_t)m;
+    while (cnt > 1 && nbits < 96) {
+        const int lo_bit = 88 - nbits;
+        const unsigned __int128 P = key96(phi, plo);
+        s_hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < m; i += blockDim.x) {
+            unsigned __int128 K = key96(s_key[i], (uint32_t)s_perm[i]);
+            if (nbits == 0 || (K >> (96 - nbits)) == (P >> (96 - nbits)))
+                atomicAdd(&s_hist[(uint32_t)(K >> lo_bit) & 255u], 1u);
+        }
+        __syncthreads();
+        uint32_t v = s_hist[tid], excl, total;
+        block_excl_scan256(v, s_misc, excl, total);
+        if (excl <= rank && rank < excl + v) {
+            s_misc[8] = tid;
+            s_misc[9] = excl;
+            s_misc[10] = v;
+        }
+        __syncthreads();
+        const uint32_t b = s_misc[8];
+        rank -= s_misc[9];
+        cnt = s_misc[10];
+        unsigned __int128 NP = P | ((unsigned __int128)b << lo_bit);
+        phi = (uint64_t)(NP >> 32);
+        plo = (uint32_t)NP;
+        nbits += 8;
+        __syncthreads();
+    }
+    if (nbits < 96) {  // exactly one key matches the prefix: it is the median
+        const unsigned __int128 P = key96(phi, plo);
+        for (int i = tid; i < m; i += blockDim.x) {
+            unsigned __int128 K = key96(s_key[i], (uint32_t)s_perm[i]);
+            if ((K >> (96 - nbits)) == (P >> (96 - nbits))) {
+                s_misc[12] = (uint32_t)s_key[i];
+                s_misc[13] = (uint32_t)(s_key[i] >> 32);
+                s_misc[14] = (uint32_t)s_perm[i];
+            }
+        }
+        __syncthreads();
+        phi = ((uint64_t)s_misc[13] << 32) | s_misc[12];
+        plo = s_misc[14];
+    }
+
+    // ---- stable partition: left = keys below (c, c_idx), in position (= index) order
+    const int half = m / 2;
+    int32_t *pout = perm_out + (int64_t)t * n + sg.off;
+    uint32_t lefts = 0;
+    for (int base = 0; base < m; base += 256) {
+        const int i = base + tid;
+        const bool valid = i < m;
+        const bool left = valid && key_less(s_key[i], (uint32_t)s_perm[i], phi, plo);
+        uint32_t excl, total;
+        block_excl_scan256(left ? 1u : 0u, s_misc, excl, total);
+        if (valid) {
+            uint32_t lb = lefts + excl;
+            int pos = left ? (int)lb : half + (i - (int)lb);
+            if (pos >= 0 && pos < m) pout[pos] = s_perm[i];  // always true when the select is consistent
+        }
+        lefts += total;
+    }
+    if (tid == 0) {
+        const int64_t hs = (int64_t)t * H + (sg.heap - 1);
+        split[hs] = val_of(phi);
+        split_idx[hs] = (int32_t)plo;
+        chosen[hs] = ch;
+        if (lefts != (uint32_t)half) atomicOr(err, 1);
+    }
+}
+
+// ================================================================ large segments
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_proj_chunks(
+    const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
+    const SegDesc *__restrict__ segs, const ChunkDesc *__restrict__ chunks,
+    const int32_t *__restrict__ perm, int64_t n, SelState *__restrict__ state, int nseg,
+    int mode,  // 0: final projection -> keys + digit-0 histogram; 1: raw projection of try `tr`
+    int tr, uint64_t *__restrict__ keys, double *__restrict__ praw, uint32_t *__restrict__ hist) {
+    __shared__ __align__(16) float s_r[1024];
+    __shared__ uint32_t s_hist[kDigitBins];
+    const int t = blockIdx.y;
+    const ChunkDesc c = chunks[blockIdx.x];
+    const SegDesc sg = segs[c.seg];
+    const int tid = threadIdx.x;
+    const SelState *st = state + (int64_t)t * nseg + c.seg;
+    const int ch = mode == 0 ? st->chosen : tr;
+    const float *Rn = R + (((int64_t)t * H + (sg.heap - 1)) * n_try + ch) * (int64_t)d;
+    const int32_t *pp = perm + (int64_t)t * n;
+    if (mode == 0)
+        for (int b = tid; b < kDigitBins; b += 256) s_hist[b] = 0;
+    const int g = tid & 7, pt = tid >> 3;
+    if (d <= 1024) {  // longer directions are read from global memory by the scalar loop below
+        for (int j = tid; j < d; j += 256) s_r[j] = Rn[j];
+        __syncthreads();
+        for (int base = 0; base < c.len; base += 32) {
+            const int i = base + pt;
+            const int64_t s = c.start + (i < c.len ? i : 0);
+            double p = group8_dot64<VEC>(X + (int64_t)pp[s] * d, s_r, d, g);
+            if (g == 0 && i < c.len) {
+                if (mode == 0) {
+                    uint64_t u = key_of(p);
+                    keys[(int64_t)t * n + s] = u;
+                    atomicAdd(&s_hist[(uint32_t)(u >> 53)], 1u);
+                } else {
+                    praw[(int64_t)t * n + s] = p;
+                }
+            }
+        }
+    } else {
+        for (int base = 0; base < c.len; base += 32) {
+            const int i = base + pt;
+            const int64_t s = c.start + (i < c.len ? i : 0);
+            double p = group8_dot64<false>(X + (int64_t)pp[s] * d, Rn, d, g);
+            if (g == 0 && i < c.len) {
+                if (mode == 0) {
+                    uint64_t u = key_of(p);
+                    keys[(int64_t)t * n + s] = u;
+                    atomicAdd(&s_hist[(uint32_t)(u >> 53)], 1u);
+                } else {
+                    praw[(int64_t)t * n + s] = p;
+                }
+            }
+        }
+    }
+    if (mode == 0) {
+        __syncthreads();
+        uint32_t *gh = hist + ((int64_t)t * nseg + c.seg) * kDigitBins;
+        for (int b = tid; b < kDigitBins; b += 256)
+            if (s_hist[b]) atomicAdd(&gh[b], s_hist[b]);
+    }
+}
+
+__global__ void k_sel_init(const SegDesc *__restrict__ segs, int nseg, int T, SelState *state) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nseg * T) return;
+    const SegDesc sg = segs[i % nseg];
+    SelState s;
+    s.pfx_hi = 0;
+    s.pfx_lo = 0;
+    s.nbits = 0;
+    s.rank = sg.size / 2;
+    s.cnt = sg.size;
+    s.mode = SEL_HIST;
+    s.chosen = 0;
+    s.best_s2 = 0.0;
+    s.s1 = 0.0;
+    state[i] = s;
+}
+
+// digit j covers key bits [lo_bit, lo_bit + width) of the 96-bit key, from the top
+__device__ inline int digit_width(int j) { return j < 8 ? 11 : 8; }
+
+__global__ __launch_bounds__(256) void k_sel_scan(SelState *__restrict__ state, int nseg,
+                                                  uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_w[8];
+    __shared__ uint32_t s_res[4];
+    const int t = blockIdx.y, k = blockIdx.x, tid = threadIdx.x;
+    SelState *stp = state + (int64_t)t * nseg + k;
+    const int mode = stp->mode;
+    if (mode == SEL_COMPACT) {
+        if (tid == 0) stp->mode = SEL_GATHERED;
+        return;
+    }
+    if (mode != SEL_HIST) return;
+    const int j = stp->nbits / kDigitBits;
+    const int w = digit_width(j);
+    const int lo_bit = 96 - stp->nbits - w;
+    uint32_t *h = hist + ((int64_t)t * nseg + k) * kDigitBins;
+    const int nb = 1 << w;
+    const int per = nb / 256;  // 8 (11-bit digit) or 1 (8-bit digit)
+    uint32_t loc[8];
+    uint32_t sum = 0;
+    for (int q = 0; q < per; q++) {
+        loc[q] = h[tid * per + q];
+        sum += loc[q];
+    }
+    uint32_t excl;
+    // block exclusive scan of per-thread sums (64-bit ranks fit in 32 bits: segments < 2^31)
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        uint32_t x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wv] = x;
+        __syncthreads();
+        uint32_t wb = 0;
+        for (int q = 0; q < 4; q++)
+            if (q < wv) wb += s_w[q];
+        excl = wb + x - sum;
+    }
+    const uint32_t rank = (uint32_t)stp->rank;
+    if (excl <= rank && rank < excl + sum) {
+        uint32_t c = excl;
+        for (int q = 0; q < per; q++) {
+            if (rank < c + loc[q]) {
+                s_res[0] = tid * per + q;
+                s_res[1] = c;
+                s_res[2] = loc[q];
+                break;
+            }
+            c += loc[q];
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < per; q++) h[tid * per + q] = 0;  // ready for the next digit
+    if (tid == 0) {
+        const uint32_t b = s_res[0];
+        unsigned __int128 P = key96(stp->pfx_hi, stp->pfx_lo) | ((unsigned __int128)b << lo_bit);
+        stp->pfx_hi = (uint64_t)(P >> 32);
+        stp->pfx_lo = (uint32_t)P;
+        stp->nbits += w;
+        stp->rank = rank - s_res[1];
+        stp->cnt = s_res[2];
+        if (stp->nbits == 96) stp->mode = SEL_DONE;
+        else if (stp->cnt <= kCandCap) stp->mode = SEL_COMPACT;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sel_pass(const ChunkDesc *__restrict__ chunks,
+                                                  const uint64_t *__restrict__ keys,
+                                                  const int32_t *__restrict__ perm, int64_t n,
+                                                  SelState *__restrict__ state, int nseg,
+                                                  uint32_t *__restrict__ hist,
+                                                  Cand *__restrict__ cand,
+                                                  uint32_t *__restrict__ cand_cnt) {
+    __shared__ uint32_t s_hist[kDigitBins];
+    __shared__ uint32_t s_w[8];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const ChunkDesc c = chunks[blockIdx.x];
+    const SelState st = state[(int64_t)t * nseg + c.seg];
+    if (st.mode != SEL_HIST && st.mode != SEL_COMPACT) return;
+    const unsigned __int128 P = key96(st.pfx_hi, st.pfx_lo);
+    const int sh = 96 - st.nbits;
+    const uint64_t *kk = keys + (int64_t)t * n;
+    const int32_t *pp = perm + (int64_t)t * n;
+    if (st.mode == SEL_HIST) {
+        const int j = st.nbits / kDigitBits;
+        const int w = digit_width(j);
+        const int lo_bit = 96 - st.nbits - w;
+        const uint32_t msk = (1u << w) - 1;
+        for (int b = tid; b < kDigitBins; b += 256) s_hist[b] = 0;
+        __syncthreads();
+        for (int i = tid; i < c.len; i += 256) {
+            const int64_t s = c.start + i;
+            unsigned __int128 K = key96(kk[s], (uint32_t)pp[s]);
+            if (st.nbits == 0 || (K >> sh) == (P >> sh)) atomicAdd(&s_hist[(uint32_t)(K >> lo_bit) & msk], 1u);
+        }
+        __syncthreads();
+        uint32_t *gh = hist + ((int64_t)t * nseg + c.seg) * kDigitBins;
+        for (int b = tid; b < kDigitBins; b += 256)
+            if (s_hist[b]) atomicAdd(&gh[b], s_hist[b]);
+    } else {
+        // gather the keys matching the prefix (at most kCandCap of them in the segment)
+        uint32_t mine = 0;
+        for (int i = tid; i < c.len; i += 256) {
+            const int64_t s = c.start + i;
+            unsigned __int128 K = key96(kk[s], (uint32_t)pp[s]);
+            mine += ((K >> sh) == (P >> sh)) ? 1u : 0u;
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+        uint32_t x = mine;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wv] = x;
+        __syncthreads();
+        uint32_t wb = 0, total = 0;
+        for (int q = 0; q < 4; q++) {
+            if (q < wv) wb += s_w[q];
+            total += s_w[q];
+        }
+        if (total == 0) return;
+        if (tid == 0) s_w[4] = atomicAdd(&cand_cnt[(int64_t)t * nseg + c.seg], total);
+        __syncthreads();
+        uint32_t pos = s_w[4] + wb + x - mine;
+        Cand *cc = cand + ((int64_t)t * nseg + c.seg) * kCandCap;
+        for (int i = tid; i < c.len; i += 256) {
+            const int64_t s = c.start + i;
+            unsigned __int128 K = key96(kk[s], (uint32_t)pp[s]);
+            if ((K >> sh) == (P >> sh)) {
+                if (pos < (uint32_t)kCandCap) cc[pos] = Cand{kk[s], (uint32_t)pp[s], 0u};
+                pos++;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sel_finish(const SegDesc *__restrict__ segs,
+                                                    SelState *__restrict__ state, int nseg,
+                                                    const Cand *__restrict__ cand,
+                                                    const uint32_t *__restrict__ cand_cnt,
+                                                    int64_t H, double *__restrict__ split,
+                                                    int32_t *__restrict__ split_idx,
+                                                    int32_t *__restrict__ chosen,
+                                                    int32_t *__restrict__ err) {
+    __shared__ uint64_t s_hi[kCandCap];
+    __shared__ uint32_t s_lo[kCandCap];
+    const int t = blockIdx.y, k = blockIdx.x, tid = threadIdx.x;
+    SelState *stp = state + (int64_t)t * nseg + k;
+    const SelState st = *stp;
+    __syncthreads();
+    if (st.mode == SEL_GATHERED) {
+        const uint32_t cnt = cand_cnt[(int64_t)t * nseg + k];
+        if (cnt != (uint32_t)st.cnt || cnt > (uint32_t)kCandCap) {
+            if (tid == 0) atomicOr(err, 2);
+            return;
+        }
+        const Cand *cc = cand + ((int64_t)t * nseg + k) * kCandCap;
+        for (uint32_t i = tid; i < cnt; i += 256) {
+            s_hi[i] = cc[i].hi;
+            s_lo[i] = cc[i].lo;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < cnt; i += 256) {
+            uint32_t below = 0;
+            for (uint32_t q = 0; q < cnt; q++) below += key_less(s_hi[q], s_lo[q], s_hi[i], s_lo[i]) ? 1u : 0u;
+            if (below == (uint32_t)st.rank) {
+                stp->pfx_hi = s_hi[i];
+                stp->pfx_lo = s_lo[i];
+                stp->nbits = 96;
+                stp->mode = SEL_DONE;
+            }
+        }
+        __syncthreads();
+    } else if (st.mode != SEL_DONE) {
+        if (tid == 0) atomicOr(err, 4);
+        return;
+    }
+    if (tid == 0) {
+        const SelState fin = *stp;
+        const int64_t hs = (int64_t)t * H + (segs[k].heap - 1);
+        split[hs] = val_of(fin.pfx_hi);
+        split_idx[hs] = (int32_t)fin.pfx_lo;
+        chosen[hs] = fin.chosen;
+        if (fin.mode != SEL_DONE) atomicOr(err, 8);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_part_count(const ChunkDesc *__restrict__ chunks, int nchunk,
+                                                    const uint64_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ perm, int64_t n,
+                                                    const SelState *__restrict__ state, int nseg,
+                                                    uint32_t *__restrict__ lcount) {
+    __shared__ uint32_t s_w[4];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const ChunkDesc c = chunks[blockIdx.x];
+    const SelState st = state[(int64_t)t * nseg + c.seg];
+    uint32_t mine = 0;
+    for (int i = tid; i < c.len; i += 256) {
+        const int64_t s = c.start + i;
+        mine += key_less(keys[(int64_t)t * n + s], (uint32_t)perm[(int64_t)t * n + s], st.pfx_hi, st.pfx_lo) ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+    if ((tid & 63) == 0) s_w[tid >> 6] = mine;
+    __syncthreads();
+    if (tid == 0) lcount[(int64_t)t * nchunk + blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+__global__ void k_part_scan(const SegDesc *__restrict__ segs, const ChunkDesc *__restrict__ chunks,
+                            int nchunk, int nseg, uint32_t *__restrict__ lcount,
+                            int32_t *__restrict__ err) {
+    // lcount[t][c] becomes the number of left members before chunk c within its segment
+    const int t = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    const SegDesc sg = segs[k];
+    uint32_t run = 0;
+    for (int q = 0; q < sg.nchunk; q++) {
+        uint32_t *p = lcount + (int64_t)t * nchunk + sg.chunk0 + q;
+        uint32_t v = *p;
+        *p = run;
+        run += v;
+    }
+    if (run != (uint32_t)(sg.size / 2)) atomicOr(err, 16);
+}
+
+__global__ __launch_bounds__(256) void k_part_scatter(const SegDesc *__restrict__ segs,
+                                                      const ChunkDesc *__restrict__ chunks, int nchunk,
+                                                      const uint64_t *__restrict__ keys,
+                                                      const int32_t *__restrict__ perm_in,
+                                                      int32_t *__restrict__ perm_out, int64_t n,
+                                                      const SelState *__restrict__ state, int nseg,
+                                                      const uint32_t *__restrict__ lbase) {
+    __shared__ uint32_t s_w[16];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const ChunkDesc c = chunks[blockIdx.x];
+    const SegDesc sg = segs[c.seg];
+    const SelState st = state[(int64_t)t * nseg + c.seg];
+    const int64_t half = sg.size / 2;
+    uint32_t lefts = lbase[(int64_t)t * nchunk + blockIdx.x];
+    const int64_t rel0 = c.start - sg.off;  // chunk position within the segment
+    int32_t *pout = perm_out + (int64_t)t * n + sg.off;
+    for (int base = 0; base < c.len; base += 256) {
+        const int i = base + tid;
+        const bool valid = i < c.len;
+        const int64_t s = c.start + (valid ? i : 0);
+        const int32_t id = perm_in[(int64_t)t * n + s];
+        const bool left = valid && key_less(keys[(int64_t)t * n + s], (uint32_t)id, st.pfx_hi, st.pfx_lo);
+        uint32_t excl, total;
+        block_excl_scan256(left ? 1u : 0u, s_w, excl, total);
+        if (valid) {
+            const int64_t lb = (int64_t)lefts + excl;
+            const int64_t rel = rel0 + i;
+            const int64_t pos = left ? lb : half + (rel - lb);
+            if (pos >= 0 && pos < sg.size) pout[pos] = id;  // always true when the select is consistent
+        }
+        lefts += total;
+    }
+}
+
+// ---- Alg. 2 on large segments: canonical sums over aligned power-of-two chunks
+
+// partial canon_sum of one chunk: of p (what = 0) or of (p - mu)^2 (what = 1)
+__global__ __launch_bounds__(256) void k_chunk_sum(const ChunkDesc *__restrict__ chunks, int nchunk,
+                                                   const SegDesc *__restrict__ segs,
+                                                   const double *__restrict__ praw, int64_t n,
+                                                   const SelState *__restrict__ state, int nseg,
+                                                   int what, double *__restrict__ part) {
+    __shared__ double s[kChunk];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const ChunkDesc c = chunks[blockIdx.x];
+    const SegDesc sg = segs[c.seg];
+    const double mu = what ? state[(int64_t)t * nseg + c.seg].s1 / (double)sg.size : 0.0;
+    for (int i = tid; i < kChunk; i += 256) {
+        double v = 0.0;
+        if (i < c.len) {
+            double p = praw[(int64_t)t * n + c.start + i];
+            if (what) {
+                double dev = p - mu;
+                v = __dmul_rn(dev, dev);
+            } else {
+                v = p;
+            }
+        }
+        s[i] = v;
+    }
+    __syncthreads();
+    for (int h = 1; h < kChunk; h <<= 1) {
+        for (int i = 2 * h * tid; i < kChunk; i += 2 * h * 256) s[i] = s[i] + s[i + h];
+        __syncthreads();
+    }
+    if (tid == 0) part[(int64_t)t * nchunk + blockIdx.x] = s[0];
+}
+
+// combine chunk partials of each segment by the same tree; what = 0 stores S1, what = 1
+// compares S2 with the best so far (Alg. 2: strictly larger wins)
+__global__ void k_seg_sum(const SegDesc *__restrict__ segs, int nseg, int nchunk,
+                          double *__restrict__ part, SelState *__restrict__ state, int what, int tr) {
+    const int t = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    const SegDesc sg = segs[k];
+    // pairwise tree over the chunk partials in place; a missing right operand is the +0.0
+    // padding, and x + 0.0 == x for the non-negative-zero-free values summed here
+    double *v = part + (int64_t)t * nchunk + sg.chunk0;
+    for (int h = 1; h < sg.nchunk; h <<= 1)
+        for (int i = 0; i + h < sg.nchunk; i += 2 * h) v[i] = v[i] + v[i + h];
+    SelState *st = state + (int64_t)t * nseg + k;
+    if (what == 0) {
+        st->s1 = v[0];
+    } else if (v[0] > st->best_s2) {
+        st->best_s2 = v[0];
+        st->chosen = tr;
+    }
+}
+
+__global__ void k_copy_segments(const LeafDesc *__restrict__ segs, int nseg,
+                                const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                int64_t n) {
+    const int t = blockIdx.y;
+    const LeafDesc sg = segs[blockIdx.x];
+    for (int i = threadIdx.x; i < sg.size; i += blockDim.x)
+        out[(int64_t)t * n + sg.off + i] = in[(int64_t)t * n + sg.off + i];
+}
+
+__global__ void k_iota(int32_t *__restrict__ perm, int64_t n) {
+    const int t = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        perm[(int64_t)t * n + i] = (int32_t)i;
+}
+
+// ================================================================ leaves (neighbourhoods)
+
+// leaf_of, leaf centroid mu (binary32 mean of the members), and the leaf-ordered, centred
+// copy Xc[t][pos][0..dp) in the tile precision, with |Xc row|^2 (binary32, of the stored
+// low-precision values) and |x - mu| (binary32) per position.
+template <typename T>
+__device__ inline T to_tile(float v);
+template <>
+__device__ inline float to_tile<float>(float v) { return v; }
+template <>
+__device__ inline __bf16 to_tile<__bf16>(float v) { return (__bf16)v; }
+template <>
+__device__ inline _Float16 to_tile<_Float16>(float v) { return (_Float16)v; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_finalize(
+    const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
+    const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
+    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
+    extern __shared__ __align__(16) float s_mu[];  // dp floats + 4*1024 partial sums
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const LeafDesc lf = leaves[blockIdx.x];
+    const int32_t *pp = perm + (int64_t)t * n + lf.off;
+    for (int i = tid; i < lf.size; i += 256) leaf_of[(int64_t)t * n + pp[i]] = lf.heap;
+    // mean: thread j sums column j over the members in order
+    for (int j = tid; j < dp; j += 256) {
+        float s = 0.f;
+        if (j < d)
+            for (int i = 0; i < lf.size; i++) s += X[(int64_t)pp[i] * d + j];
+        float mu = j < d ? s / (float)lf.size : 0.f;
+        s_mu[j] = mu;
+        if (j < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + j] = mu;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int i = wv; i < lf.size; i += 4) {
+        const float *x = X + (int64_t)pp[i] * d;
+        T *out = Xc + ((int64_t)t * n + lf.off + i) * dp;
+        float na = 0.f, ra = 0.f;
+        bool over = false;
+        for (int j = lane; j < dp; j += 64) {
+            float a = j < d ? x[j] - s_mu[j] : 0.f;
+            over |= fabsf(a) > range_max;
+            T q = to_tile<T>(a);
+            out[j] = q;
+            float qf = (float)q;
+            na = __builtin_fmaf(qf, qf, na);
+            ra = __builtin_fmaf(a, a, ra);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            na += __shfl_xor(na, o, 64);
+            ra += __shfl_xor(ra, o, 64);
+        }
+        uint64_t ov = __ballot(over);
+        if (lane == 0) nrm[(int64_t)t * n + lf.off + i] = make_float2(na, ov ? INFINITY : sqrtf(ra));
+    }
+}
+
+// ================================================================ launchers
+
+size_t level_small_lds(int max_m, int d, int n_try) {
+    size_t lds = ((4 * (size_t)max_m + 15) & ~(size_t)15) + 8 * (size_t)max_m + 4 * (size_t)((d + 3) & ~3) +
+                 4 * (256 + 16);
+    lds = (lds + 7) & ~(size_t)7;
+    if (n_try > 1) {
+        int P2 = 1;
+        while (P2 < max_m) P2 <<= 1;
+        lds += 8 * (size_t)max_m + 8 * (size_t)P2;
+    }
+    return lds;
+}
+
+void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H,
+                        int n_try, const SegDesc *segs, int nseg, int max_m, int T,
+                        const int32_t *pin, int32_t *pout, int64_t n, double *split,
+                        int32_t *split_idx, int32_t *chosen, int32_t *err) {
+    const size_t lds = level_small_lds(max_m, d, n_try);
+    dim3 grid(nseg, T);
+    if (vec) {
+        hipFuncSetAttribute((const void *)k_level_small<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_level_small<true>, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n,
+                           split, split_idx, chosen, err);
+    } else {
+        hipFuncSetAttribute((const void *)k_level_small<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_level_small<false>, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n,
+                           split, split_idx, chosen, err);
+    }
+    launch_check(s, "k_level_small");
+}
+
+size_t cand_bytes() { return sizeof(Cand); }
+
+template <bool VEC>
+static void proj_chunks(hipStream_t s, dim3 gc, const float *X, int d, const float *R, int64_t H, int n_try,
+                        const SegDesc *segs, const ChunkDesc *chunks, const int32_t *pin, int64_t n,
+                        const LargeBufs &b, int nseg, int mode, int tr) {
+    hipLaunchKernelGGL(k_proj_chunks<VEC>, gc, dim3(256), 0, s, X, d, R, H, n_try, segs, chunks, pin, n, b.state,
+                       nseg, mode, tr, b.keys, b.praw, b.hist);
+    launch_check(s, "k_proj_chunks");
+}
+
+void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H,
+                        int n_try, const SegDesc *segs, int nseg, const ChunkDesc *chunks, int nchunk,
+                        int T, const int32_t *pin, int32_t *pout, int64_t n, double *split,
+                        int32_t *split_idx, int32_t *chosen, int32_t *err, const LargeBufs &b,
+                        double proj_bytes) {
+    dim3 gs(nseg, T), gc(nchunk, T);
+    hipLaunchKernelGGL(k_sel_init, dim3((nseg * T + 255) / 256), dim3(256), 0, s, segs, nseg, T, b.state);
+    launch_check(s, "k_sel_init");
+    hipMemsetAsync(b.hist, 0, sizeof(uint32_t) * kDigitBins * (size_t)nseg * T, s);
+    hipMemsetAsync(b.cand_cnt, 0, sizeof(uint32_t) * (size_t)nseg * T, s);
+    launch_check(s, "select memsets");
+    if (n_try > 1) {
+        for (int tr = 0; tr < n_try; tr++) {
+            {
+                ProfScope ps(s, "proj_try", proj_bytes, 0);
+                if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr);
+                else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr);
+            }
+            for (int what = 0; what < 2; what++) {
+                hipLaunchKernelGGL(k_chunk_sum, gc, dim3(256), 0, s, chunks, nchunk, segs, b.praw, n, b.state,
+                                   nseg, what, b.part);
+                launch_check(s, "k_chunk_sum");
+                hipLaunchKernelGGL(k_seg_sum, dim3((nseg + 63) / 64, T), dim3(64), 0, s, segs, nseg, nchunk, b.part,
+                                   b.state, what, tr);
+                launch_check(s, "k_seg_sum");
+            }
+        }
+    }
+    {
+        ProfScope ps(s, "proj_chunks", proj_bytes, 0);
+        if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0);
+        else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0);
+    }
+    {
+        ProfScope ps(s, "select_passes", 0, 0);
+        for (int j = 0; j < kNumDigits; j++) {
+            hipLaunchKernelGGL(k_sel_scan, gs, dim3(256), 0, s, b.state, nseg, b.hist);
+            launch_check(s, "k_sel_scan");
+            if (j + 1 < kNumDigits) {
+                hipLaunchKernelGGL(k_sel_pass, gc, dim3(256), 0, s, chunks, b.keys, pin, n, b.state, nseg, b.hist,
+                                   b.cand, b.cand_cnt);
+                launch_check(s, "k_sel_pass");
+            }
+        }
+        hipLaunchKernelGGL(k_sel_finish, gs, dim3(256), 0, s, segs, b.state, nseg, b.cand, b.cand_cnt, H, split,
+                           split_idx, chosen, err);
+        launch_check(s, "k_sel_finish");
+    }
+    {
+        ProfScope ps(s, "partition", 0, 0);
+        hipLaunchKernelGGL(k_part_count, gc, dim3(256), 0, s, chunks, nchunk, b.keys, pin, n, b.state, nseg,
+                           b.lcount);
+        launch_check(s, "k_part_count");
+        hipLaunchKernelGGL(k_part_scan, dim3((nseg + 63) / 64, T), dim3(64), 0, s, segs, chunks, nchunk, nseg,
+                           b.lcount, err);
+        launch_check(s, "k_part_scan");
+        hipLaunchKernelGGL(k_part_scatter, gc, dim3(256), 0, s, segs, chunks, nchunk, b.keys, pin, pout, n, b.state,
+                           nseg, b.lcount);
+        launch_check(s, "k_part_scatter");
+    }
+}
+
+void launch_copy_segments(hipStream_t s, const LeafDesc *segs, int nseg, int T, const int32_t *in,
+                          int32_t *out, int64_t n) {
+    if (nseg == 0) return;
+    hipLaunchKernelGGL(k_copy_segments, dim3(nseg, T), dim3(256), 0, s, segs, nseg, in, out, n);
+    launch_check(s, "k_copy_segments");
+}
+
+void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T) {
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_iota, dim3(blocks, T), dim3(256), 0, s, perm, n);
+    launch_check(s, "k_iota");
+}
+
+template <typename T>
+static void leaf_finalize(hipStream_t s, dim3 grid, size_t lds, const float *X, int d, int dp,
+                          const LeafDesc *leaves, int nleaf, const int32_t *perm, int64_t n, int32_t *leaf_of,
+                          float *centroid, void *Xc, float2 *nrm, float range_max) {
+    hipLaunchKernelGGL(k_leaf_finalize<T>, grid, dim3(256), lds, s, X, d, dp, leaves, nleaf, perm, n, leaf_of,
+                       centroid, (T *)Xc, nrm, range_max);
+    launch_check(s, "k_leaf_finalize");
+}
+
+void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves,
+                          int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
+                          void *Xc, float2 *nrm) {
+    dim3 grid(nleaf, T);
+    const size_t lds = sizeof(float) * (size_t)dp;
+    if (prec == RPF_DIST_BF16)
+        leaf_finalize<__bf16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+    else if (prec == RPF_DIST_FP16)
+        leaf_finalize<_Float16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 60000.f);
+    else
+        leaf_finalize<float>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+}
+
+}  // namespace rpf

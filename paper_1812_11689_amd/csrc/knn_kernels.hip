@@ -1,0 +1,1088 @@
+// Candidate stage of Alg. 3: N_q = union of q's leaves over the T trees, exact distances,
+// K closest.  Exactness is kept while the bulk arithmetic runs in low precision:
+//
+//  1. Tiles (k_tile): for every tree and leaf, the Gram matrix of the leaf's rows (or of
+//     the queries routed to the leaf against the leaf's rows) runs on MFMA over leaf-centred
+//     copies in binary32 / bfloat16 / float16 with binary32 accumulation.  Each pair gets a
+//     rigorous interval [lb, ub] for its squared distance:
+//        Dt = |a|^2 + |b|^2 - 2 a.b (tile values),  e = E (|a|^2 + |b|^2),
+//        delta = C (|a'| + |b'|) with a' = a - mu in binary32,
+//        lb = (max(0, sqrt(max(0, Dt - e)) - delta))^2,  ub = (sqrt(Dt + e) + delta)^2,
+//     E covering the accumulation (2 gamma_{d+2}, doubled for the unknown MFMA order) and
+//     C the rounding of the centred copy.  A pair is kept iff lb <= tau(row).
+//  2. Phase I (the first tree, tau = +inf) keeps every pair; k_merge_init sets
+//     tau(row) = K-th smallest ub and keeps the pairs with lb <= tau.
+//  3. Phase II (the other trees) keeps pairs with lb <= tau(row) only.  Every true
+//     neighbour passes in every tree that holds it, since lb <= D <= K-th D <= tau.
+//  4. k_final: dedup by index, tau' = K-th smallest ub, rerank {lb <= tau'} with the
+//     canonical binary32 distance, then the canonical binary64 distance on the window
+//     D32 <= D32_(K) (1 + w) (w covers the binary32 error), order by (D64, index).
+//  5. Rows whose buffers overflowed take k_fallback: the exhaustive union in binary64.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "rpf_internal.h"
+
+namespace rpf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+struct TileCfg;
+template <>
+struct TileCfg<RPF_DIST_FP32> {
+    using T = float;
+    static constexpr int KC = 32, LDW = 33, KSTEP = 2;
+};
+template <>
+struct TileCfg<RPF_DIST_BF16> {
+    using T = __bf16;
+    static constexpr int KC = 64, LDW = 72, KSTEP = 16;
+};
+template <>
+struct TileCfg<RPF_DIST_FP16> {
+    using T = _Float16;
+    static constexpr int KC = 64, LDW = 72, KSTEP = 16;
+};
+
+template <int PREC>
+__device__ inline f32x16 mfma_step(const typename TileCfg<PREC>::T *sa, const typename TileCfg<PREC>::T *sb,
+                                   f32x16 acc) {
+    if constexpr (PREC == RPF_DIST_FP32) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(*sa, *sb, acc, 0, 0, 0);
+    } else if constexpr (PREC == RPF_DIST_BF16) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8 *>(sa),
+                                                       *reinterpret_cast<const bf16x8 *>(sb), acc, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(*reinterpret_cast<const f16x8 *>(sa),
+                                                      *reinterpret_cast<const f16x8 *>(sb), acc, 0, 0, 0);
+    }
+}
+
+template <int PREC>
+__device__ inline void stage_rows(typename TileCfg<PREC>::T *s, const typename TileCfg<PREC>::T *g, int rows,
+                                  int rows_pad, int dp, int k0, int nthreads) {
+    using C = TileCfg<PREC>;
+    using T = typename C::T;
+    if constexpr (PREC == RPF_DIST_FP32) {
+        constexpr int VPR = C::KC / 4;  // float4 per row chunk
+        for (int v = threadIdx.x; v < rows_pad * VPR; v += nthreads) {
+            const int r = v / VPR, c = (v % VPR) * 4;
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < rows && k0 + c < dp) val = *reinterpret_cast<const float4 *>(g + (int64_t)r * dp + k0 + c);
+            T *dst = s + r * C::LDW + c;
+            dst[0] = val.x;
+            dst[1] = val.y;
+            dst[2] = val.z;
+            dst[3] = val.w;
+        }
+    } else {
+        constexpr int VPR = C::KC / 8;  // 16-byte vectors of 8 elements
+        for (int v = threadIdx.x; v < rows_pad * VPR; v += nthreads) {
+            const int r = v / VPR, c = (v % VPR) * 8;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (r < rows && k0 + c < dp) val = *reinterpret_cast<const uint4 *>(g + (int64_t)r * dp + k0 + c);
+            *reinterpret_cast<uint4 *>(s + r * C::LDW + c) = val;
+        }
+    }
+}
+
+struct BoundCoef {
+    float e;      // E: accumulation error per unit of |a|^2 + |b|^2
+    float c;      // C: centred-copy rounding per unit of |a'| + |b'|
+    float eta;    // absolute rounding floor of the copy (float16 subnormals), times sqrt(d)
+};
+
+__device__ inline void pair_bounds(float na, float nb, float ra, float rb, float g, BoundCoef bc, float &lb,
+                                   float &ub) {
+    const float Dt = na + nb - 2.f * g;
+    const float e = bc.e * (na + nb);
+    const float delta = bc.c * (ra + rb) + bc.eta;
+    const float lo = fmaxf(Dt - e, 0.f);
+    const float ls = fmaxf(sqrtf(lo) - delta, 0.f);
+    const float hs = sqrtf(fmaxf(Dt + e, 0.f)) + delta;
+    lb = ls * ls * (1.f - 1e-6f);
+    ub = hs * hs * (1.f + 1e-6f);
+    if (!(ra < INFINITY) || !(rb < INFINITY) || !(lb == lb) || !(ub == ub)) {  // out of the copy's range
+        lb = 0.f;
+        ub = INFINITY;
+    }
+}
+
+// One tile job per block: A rows x B rows of one leaf (or query group x leaf), MB waves,
+// wave w owns A rows [32w, 32w + 32) against all B rows.
+template <int MB, int PREC>
+__global__ __launch_bounds__(64 * MB) void k_tile(
+    const TileJob *__restrict__ jobs, const void *__restrict__ A_, const void *__restrict__ B_, int dp,
+    int64_t a_stride_tree, int64_t b_stride_tree, const float2 *__restrict__ a_nrm, const float2 *__restrict__ b_nrm,
+    const int32_t *__restrict__ a_dest, const int32_t *__restrict__ b_pt, BoundCoef bc,
+    const float *__restrict__ tau, int exclude_self, int32_t *__restrict__ cnt, Ent *__restrict__ ent, int cap) {
+    using C = TileCfg<PREC>;
+    using T = typename C::T;
+    constexpr int M = 32 * MB;
+    constexpr int NT = 64 * MB;
+    __shared__ __align__(16) T s_a[M * C::LDW];
+    __shared__ __align__(16) T s_b[M * C::LDW];
+    __shared__ float s_na[M], s_ra[M], s_nb[M], s_rb[M], s_phi[M], s_tau[M];
+    __shared__ int32_t s_dst[M], s_bpt[M];
+    __shared__ uint32_t s_cnt[M], s_base[M];
+    __shared__ float s_bmax[2];
+
+    const TileJob job = jobs[blockIdx.x];
+    const int t = job.tree;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const bool same = job.same != 0;
+    const T *A = reinterpret_cast<const T *>(A_) + (t * a_stride_tree + job.a_off) * dp;
+    const T *B = reinterpret_cast<const T *>(B_) + (t * b_stride_tree + job.b_off) * dp;
+    const float2 *an = a_nrm + t * a_stride_tree + job.a_off;
+    const float2 *bn = b_nrm + t * b_stride_tree + job.b_off;
+    const int32_t *ad = a_dest + t * a_stride_tree + job.a_off;
+    const int32_t *bp = b_pt + t * b_stride_tree + job.b_off;
+
+    for (int r = tid; r < M; r += NT) {
+        if (r < job.a_rows) {
+            float2 q = an[r];
+            s_na[r] = q.x;
+            s_ra[r] = q.y;
+            int dst = ad[r];
+            s_dst[r] = dst;
+            s_tau[r] = tau ? tau[dst] : INFINITY;
+        } else {
+            s_na[r] = 0.f;
+            s_ra[r] = 0.f;
+            s_dst[r] = -1;
+            s_tau[r] = -1.f;
+        }
+        if (r < job.b_rows) {
+            float2 q = bn[r];
+            s_nb[r] = q.x;
+            s_rb[r] = q.y;
+            s_bpt[r] = bp[r];
+        } else {
+            s_nb[r] = 0.f;
+            s_rb[r] = 0.f;
+            s_bpt[r] = -1;
+        }
+        s_cnt[r] = 0;
+    }
+    __syncthreads();
+    if (tid < 64) {  // largest |b|^2 and |b'| of the tile, for the cheap per-row threshold
+        float mn = 0.f, mr = 0.f;
+        for (int r = lane; r < job.b_rows; r += 64) {
+            mn = fmaxf(mn, s_nb[r]);
+            mr = fmaxf(mr, s_rb[r]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmaxf(mn, __shfl_xor(mn, o, 64));
+            mr = fmaxf(mr, __shfl_xor(mr, o, 64));
+        }
+        if (lane == 0) {
+            s_bmax[0] = mn;
+            s_bmax[1] = mr;
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < M; r += NT) {
+        // necessary condition for lb <= tau:  |b|^2 - 2 a.b <= phi(row), with the per-pair
+        // error terms replaced by their largest value over the tile's B rows
+        const float tv = s_tau[r];
+        float phi;
+        if (!(tv < INFINITY)) {
+            phi = INFINITY;
+        } else if (tv < 0.f) {
+            phi = -INFINITY;
+        } else {
+            const float dmax = bc.c * (s_ra[r] + s_bmax[1]) + bc.eta;
+            const float emax = bc.e * (s_na[r] + s_bmax[0]);
+            const float st = sqrtf(tv / (1.f - 1e-6f)) + dmax;
+            const float th = st * st + emax;
+            phi = (th - s_na[r]) + 1e-5f * (th + s_na[r] + s_bmax[0]) + 1e-30f;
+            if (!(s_ra[r] < INFINITY) || !(s_bmax[1] < INFINITY)) phi = INFINITY;
+        }
+        s_phi[r] = phi;
+    }
+
+    f32x16 acc[MB];
+#pragma unroll
+    for (int cb = 0; cb < MB; cb++)
+        for (int v = 0; v < 16; v++) acc[cb][v] = 0.f;
+    const int nbb = (job.b_rows + 31) >> 5;
+    const bool active = 32 * w < job.a_rows;
+    const int fr = lane & 31;
+    const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
+    const int a_pad = ((job.a_rows + 31) >> 5) << 5;
+    const int b_pad = nbb << 5;
+    for (int k0 = 0; k0 < dp; k0 += C::KC) {
+        __syncthreads();
+        stage_rows<PREC>(s_a, A, job.a_rows, a_pad, dp, k0, NT);
+        if (!same) stage_rows<PREC>(s_b, B, job.b_rows, b_pad, dp, k0, NT);
+        __syncthreads();
+        const T *sb_base = same ? s_a : s_b;
+        int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
+        kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
+        if (active) {
+            for (int kk = 0; kk < kmax; kk += C::KSTEP) {
+                const T *pa = s_a + (32 * w + fr) * C::LDW + kk + fk;
+#pragma unroll
+                for (int cb = 0; cb < MB; cb++) {
+                    if (cb < nbb) {
+                        const T *pb = sb_base + (32 * cb + fr) * C::LDW + kk + fk;
+                        acc[cb] = mfma_step<PREC>(pa, pb, acc[cb]);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- epilogue: sweep 1 counts the kept pairs per row, sweep 2 writes them
+    for (int sweep = 0; sweep < 2; sweep++) {
+        if (active) {
+#pragma unroll
+            for (int cb = 0; cb < MB; cb++) {
+                if (cb >= nbb) continue;
+                const int col = 32 * cb + (lane & 31);
+                const bool colok = col < job.b_rows;
+                const float nb = s_nb[col];
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int row = 32 * w + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const float g = acc[cb][v];
+                    if (colok && row < job.a_rows && __builtin_fmaf(-2.f, g, nb) <= s_phi[row] &&
+                        !(same && exclude_self && row == col)) {
+                        float lb, ub;
+                        pair_bounds(s_na[row], nb, s_ra[row], s_rb[col], g, bc, lb, ub);
+                        if (lb <= s_tau[row]) {
+                            if (sweep == 0) {
+                                atomicAdd(&s_cnt[row], 1u);
+                            } else {
+                                const uint32_t slot = s_base[row] + atomicAdd(&s_cnt[row], 1u);
+                                if (slot < (uint32_t)cap) {
+                                    Ent e;
+                                    e.idx = s_bpt[col];
+                                    e.lb = lb;
+                                    e.ub = ub;
+                                    e.pad = 0;
+                                    ent[(int64_t)s_dst[row] * cap + slot] = e;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (sweep == 0) {
+            for (int r = tid; r < job.a_rows; r += NT) {
+                const uint32_t c = s_cnt[r];
+                s_base[r] = c ? (uint32_t)atomicAdd(&cnt[s_dst[r]], (int32_t)c) : 0u;
+                s_cnt[r] = 0;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- wave-level selection
+
+// k-th smallest (0-based) of `c` 32-bit keys held in LDS (per-wave region), radix 8 bits.
+__device__ inline uint32_t wave_kth_lds(const uint32_t *vals, int c, int k, uint32_t *hist) {
+    const int lane = lane_id();
+    uint32_t prefix = 0;
+    uint32_t rank = (uint32_t)k;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = lane; b < 256; b += 64) hist[b] = 0;
+        wave_sync();
+        for (int i = lane; i < c; i += 64) {
+            const uint32_t v = vals[i];
+            if (shift == 24 || (v >> (shift + 8)) == (prefix >> (shift + 8))) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+        }
+        wave_sync();
+        uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+        uint32_t sum = h0 + h1 + h2 + h3, x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const uint32_t excl = x - sum;
+        uint32_t mybin = 0xffffffffu, mybefore = 0;
+        if (excl <= rank && rank < excl + sum) {
+            uint32_t cc = excl;
+            uint32_t hh[4] = {h0, h1, h2, h3};
+            for (int q = 0; q < 4; q++) {
+                if (rank < cc + hh[q]) {
+                    mybin = 4 * lane + q;
+                    mybefore = cc;
+                    break;
+                }
+                cc += hh[q];
+            }
+        }
+        const uint64_t who = __ballot(mybin != 0xffffffffu);
+        const int src = __builtin_ctzll(who);
+        const uint32_t bin = __shfl(mybin, src, 64);
+        const uint32_t before = __shfl(mybefore, src, 64);
+        prefix |= bin << shift;
+        rank -= before;
+        wave_sync();
+    }
+    return prefix;
+}
+
+__device__ inline uint32_t fkey(float f) {  // non-negative floats (and +inf) order as uint32
+    return __float_as_uint(f);
+}
+
+// Phase I merge: tau(row) = K-th smallest ub among the first tree's pairs; keep lb <= tau.
+__global__ __launch_bounds__(256) void k_merge_init(int64_t nrows, int K, int32_t *__restrict__ cnt,
+                                                    const Ent *__restrict__ ent, int cap,
+                                                    float *__restrict__ tau, Ent *__restrict__ list,
+                                                    int32_t *__restrict__ lcnt, int lcap) {
+    __shared__ uint32_t s_v[4][512];
+    __shared__ uint32_t s_h[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t a = (int64_t)blockIdx.x * 4 + w;
+    if (a >= nrows) return;
+    const int c0 = cnt[a];
+    const int c = c0 < cap ? c0 : cap;
+    const Ent *e = ent + a * cap;
+    for (int i = lane; i < c; i += 64) s_v[w][i] = fkey(e[i].ub);
+    wave_sync();
+    float tv = INFINITY;
+    if (c >= K) tv = __uint_as_float(wave_kth_lds(s_v[w], c, K - 1, s_h[w]));
+    const float tp = tv * (1.f + 1e-6f);
+    uint32_t kept = 0;
+    for (int base = 0; base < c; base += 64) {
+        const int i = base + lane;
+        Ent x;
+        bool keep = false;
+        if (i < c) {
+            x = e[i];
+            keep = x.lb <= tp;
+        }
+        const uint64_t mk = __ballot(keep);
+        const uint32_t pos = kept + mask_rank(mk);
+        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = x;
+        kept += __popcll(mk);
+    }
+    wave_sync();
+    if (lane == 0) {
+        lcnt[a] = (c0 > cap) ? lcap + 1 : (int32_t)kept;
+        tau[a] = tp;
+        cnt[a] = 0;
+    }
+}
+
+// ---------------------------------------------------------------- final merge and rerank
+
+constexpr int kHT = 1024;      // per-row hash table for dedup
+constexpr int kMaxCand = 640;  // list + emissions per row handled by k_final
+
+struct FinalArgs {
+    const Ent *list;
+    const int32_t *lcnt;
+    int lcap;
+    const int32_t *cnt;
+    const Ent *ent;
+    int cap;
+    int K;
+    const float *X;     // data rows [n][d]
+    const float *Qr;    // query rows [nrows][d] (X itself for all-points)
+    int d;
+    float win;          // relative window on D32 for the binary64 re-rank
+    int32_t *out_idx;
+    float *out_dist;
+    int32_t *fb_list;   // rows for the exhaustive fallback
+    int32_t *fb_cnt;
+    unsigned long long *stats;  // [rows, fallback, reranked32, reranked64]
+};
+
+template <bool VEC>
+__global__ __launch_bounds__(64) void k_final(FinalArgs A, int64_t nrows) {
+    __shared__ int32_t s_key[kHT];
+    __shared__ uint32_t s_lb[kHT], s_ub[kHT];
+    __shared__ int32_t s_idx[kMaxCand];
+    __shared__ uint32_t s_v[kMaxCand];
+    __shared__ float s_lbv[kMaxCand];
+    __shared__ double s_d64[1024];
+    __shared__ int32_t s_widx[1024];
+    __shared__ uint32_t s_h[256];
+    extern __shared__ __align__(16) float s_q[];  // query row, d floats
+    const int lane = threadIdx.x;
+    const int64_t a = blockIdx.x;
+    if (a >= nrows) return;
+    const int K = A.K;
+    const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kMaxCand) {
+        if (lane == 0) {
+            const int slot = atomicAdd(A.fb_cnt, 1);
+            A.fb_list[slot] = (int32_t)a;
+            atomicAdd(&A.stats[1], 1ull);
+        }
+        return;
+    }
+    for (int i = lane; i < kHT; i += 64) {
+        s_key[i] = -1;
+        s_lb[i] = 0u;
+        s_ub[i] = 0xffffffffu;
+    }
+    for (int j = lane; j < A.d; j += 64) s_q[j] = A.Qr[a * A.d + j];
+    wave_sync();
+    for (int i = lane; i < c1 + c2; i += 64) {
+        const Ent e = i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)];
+        uint32_t h = ((uint32_t)e.idx * 2654435761u) >> 22;
+        while (true) {
+            const int old = atomicCAS(&s_key[h], -1, e.idx);
+            if (old == -1 || old == e.idx) {
+                atomicMax(&s_lb[h], fkey(e.lb));   // intersect the intervals of duplicates
+                atomicMin(&s_ub[h], fkey(e.ub));
+                break;
+            }
+            h = (h + 1) & (kHT - 1);
+        }
+    }
+    wave_sync();
+    int nd = 0;
+    for (int base = 0; base < kHT; base += 64) {
+        const int i = base + lane;
+        const bool occ = s_key[i] >= 0;
+        const uint64_t mk = __ballot(occ);
+        if (occ) {
+            const int p = nd + mask_rank(mk);
+            s_idx[p] = s_key[i];
+            s_v[p] = s_ub[i];
+            s_lbv[p] = __uint_as_float(s_lb[i]);
+        }
+        nd += __popcll(mk);
+    }
+    wave_sync();
+    float tv = INFINITY;
+    if (nd >= K) tv = __uint_as_float(wave_kth_lds(s_v, nd, K - 1, s_h));
+    const float tp = tv * (1.f + 1e-6f);
+    // rerank set R = {lb <= tau'} (compacted in place)
+    int nr = 0;
+    for (int base = 0; base < nd; base += 64) {
+        const int i = base + lane;
+        const bool keep = i < nd && s_lbv[i] <= tp;
+        const uint64_t mk = __ballot(keep);
+        const int idx = i < nd ? s_idx[i] : 0;
+        wave_sync();
+        if (keep) s_idx[nr + mask_rank(mk)] = idx;
+        nr += __popcll(mk);
+        wave_sync();
+    }
+    // canonical binary32 distances, 8 lanes per candidate
+    const int g = lane & 7, grp = lane >> 3;
+    for (int base = 0; base < nr; base += 8) {
+        const int i = base + grp;
+        const int b = s_idx[i < nr ? i : 0];
+        const float D32 = group8_dist32<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
+        if (g == 0 && i < nr) s_v[i] = fkey(D32);
+    }
+    wave_sync();
+    float d32k = INFINITY;
+    if (nr >= K) d32k = __uint_as_float(wave_kth_lds(s_v, nr, K - 1, s_h));
+    const float wcut = d32k * (1.f + A.win);
+    int nw = 0;
+    for (int base = 0; base < nr; base += 64) {
+        const int i = base + lane;
+        const bool keep = i < nr && __uint_as_float(s_v[i]) <= wcut;
+        const uint64_t mk = __ballot(keep);
+        if (keep && nw + mask_rank(mk) < 1024) s_widx[nw + mask_rank(mk)] = s_idx[i];
+        nw += __popcll(mk);
+    }
+    wave_sync();
+    if (nw > 1024) {  // pathological window (massive distance ties): exhaustive path
+        if (lane == 0) {
+            const int slot = atomicAdd(A.fb_cnt, 1);
+            A.fb_list[slot] = (int32_t)a;
+            atomicAdd(&A.stats[1], 1ull);
+        }
+        return;
+    }
+    for (int base = 0; base < nw; base += 8) {
+        const int i = base + grp;
+        const int b = s_widx[i < nw ? i : 0];
+        const double D64 = group8_dist64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
+        if (g == 0 && i < nw) s_d64[i] = D64;
+    }
+    int P2 = 1;
+    while (P2 < nw) P2 <<= 1;
+    for (int i = nw + lane; i < P2; i += 64) {
+        s_d64[i] = INFINITY;
+        s_widx[i] = 0x7fffffff;
+    }
+    wave_sync();
+    // bitonic sort of (D64, idx) ascending
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = lane; i < P2 / 2; i += 64) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double dl = s_d64[lo], dh = s_d64[hi];
+                const int il = s_widx[lo], ih = s_widx[hi];
+                const bool gt = dl > dh || (dl == dh && il > ih);
+                if (gt == up) {
+                    s_d64[lo] = dh;
+                    s_d64[hi] = dl;
+                    s_widx[lo] = ih;
+                    s_widx[hi] = il;
+                }
+            }
+            wave_sync();
+        }
+    }
+    for (int k = lane; k < K; k += 64) {
+        const bool ok = k < nw;
+        A.out_idx[a * K + k] = ok ? s_widx[k] : -1;
+        A.out_dist[a * K + k] = ok ? (float)sqrt(s_d64[k]) : INFINITY;
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], 1ull);
+        atomicAdd(&A.stats[2], (unsigned long long)nr);
+        atomicAdd(&A.stats[3], (unsigned long long)nw);
+    }
+}
+
+// ---------------------------------------------------------------- exhaustive fallback
+
+struct FallbackArgs {
+    const int32_t *fb_list;
+    const int32_t *fb_cnt;
+    const float *X;
+    const float *Qr;
+    int d;
+    int K;
+    int T;
+    int64_t n;
+    const int32_t *perm;        // [T][n]
+    const int32_t *row_leaf;    // [T][nrows] heap id of each row's leaf
+    int64_t nrows;
+    const int32_t *heap_leaf;   // heap id -> leaf index
+    const LeafDesc *leaves;
+    int32_t exclude_self;       // all-points: row a is point a
+    int32_t *out_idx;
+    float *out_dist;
+};
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
+    __shared__ double s_cd[512];
+    __shared__ int32_t s_ci[512];
+    __shared__ double s_td[256];
+    __shared__ int32_t s_ti[256];
+    __shared__ int s_tn;
+    extern __shared__ __align__(16) float s_q[];
+    const int tid = threadIdx.x, g = tid & 7, grp = tid >> 3;
+    const int nfb = *F.fb_cnt;
+    const int K = F.K;  // <= 256 on this path
+    for (int q = blockIdx.x; q < nfb; q += gridDim.x) {
+        const int64_t a = F.fb_list[q];
+        __syncthreads();
+        for (int j = tid; j < F.d; j += 256) s_q[j] = F.Qr[a * F.d + j];
+        if (tid == 0) s_tn = 0;
+        __syncthreads();
+        for (int t = 0; t < F.T; t++) {
+            const int heap = F.row_leaf[(int64_t)t * F.nrows + a];
+            const LeafDesc lf = F.leaves[F.heap_leaf[heap]];
+            for (int base = 0; base < lf.size; base += 256) {
+                // distances of up to 256 members, 8 lanes per member
+                for (int sub = 0; sub < 256; sub += 32) {
+                    const int i = base + sub + grp;
+                    const int ii = i < lf.size ? i : 0;
+                    const int b = F.perm[(int64_t)t * F.n + lf.off + ii];
+                    const double D = group8_dist64<VEC>(s_q, F.X + (int64_t)b * F.d, F.d, g);
+                    if (g == 0) {
+                        const bool ok = i < lf.size && !(F.exclude_self && b == a);
+                        s_cd[sub + grp] = ok ? D : INFINITY;
+                        s_ci[sub + grp] = ok ? b : 0x7fffffff;
+                    }
+                }
+                for (int i = 256 + tid; i < 512; i += 256) {
+                    s_cd[i] = INFINITY;
+                    s_ci[i] = 0x7fffffff;
+                }
+                __syncthreads();
+                // append the current top list, then sort 512 by (D, idx)
+                for (int i = tid; i < s_tn; i += 256) {
+                    s_cd[256 + i] = s_td[i];
+                    s_ci[256 + i] = s_ti[i];
+                }
+                __syncthreads();
+                for (int size = 2; size <= 512; size <<= 1)
+                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                        const int i = tid;
+                        const int lo = 2 * i - (i & (stride - 1));
+                        const int hi = lo + stride;
+                        const bool up = (lo & size) == 0;
+                        const double dl = s_cd[lo], dh = s_cd[hi];
+                        const int il = s_ci[lo], ih = s_ci[hi];
+                        const bool gtr = dl > dh || (dl == dh && il > ih);
+                        if (gtr == up) {
+                            s_cd[lo] = dh;
+                            s_cd[hi] = dl;
+                            s_ci[lo] = ih;
+                            s_ci[hi] = il;
+                        }
+                        __syncthreads();
+                    }
+                if (tid == 0) {  // K smallest distinct (equal index implies equal distance)
+                    int nt = 0;
+                    for (int i = 0; i < 512 && nt < K; i++) {
+                        if (s_ci[i] == 0x7fffffff) break;
+                        if (nt > 0 && s_ti[nt - 1] == s_ci[i]) continue;
+                        s_td[nt] = s_cd[i];
+                        s_ti[nt] = s_ci[i];
+                        nt++;
+                    }
+                    s_tn = nt;
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = tid; k < K; k += 256) {
+            const bool ok = k < s_tn;
+            F.out_idx[a * K + k] = ok ? s_ti[k] : -1;
+            F.out_dist[a * K + k] = ok ? (float)sqrt(s_td[k]) : INFINITY;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- routing (Alg. 3, lines 5-7)
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_route(const float *__restrict__ Q, int64_t m, int d,
+                                               const float *__restrict__ R, int64_t H, int n_try,
+                                               const int32_t *__restrict__ chosen, const double *__restrict__ split,
+                                               int64_t n, int n0, int32_t *__restrict__ out_leaf) {
+    const int t = blockIdx.y;
+    const int g = threadIdx.x & 7;
+    const int64_t q = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int64_t qq = q < m ? q : 0;
+    const float *x = Q + qq * d;
+    int64_t h = 1, size = n;
+    while (size > n0) {  // the 8 lanes of a group follow the same query
+        const int64_t hs = (int64_t)t * H + (h - 1);
+        const float *r = R + (hs * n_try + chosen[hs]) * (int64_t)d;
+        const double p = group8_dot64<VEC>(x, r, d, g);
+        const bool right = p >= split[hs];
+        size = right ? size - size / 2 : size / 2;
+        h = 2 * h + (right ? 1 : 0);
+    }
+    if (g == 0 && q < m) out_leaf[(int64_t)t * m + q] = (int32_t)h;
+}
+
+// ================================================================ query preparation
+
+// group routed queries by (tree, leaf): counts, offsets, then the grouped order
+__global__ void k_group_count(const int32_t *__restrict__ qleaf, int64_t m, const int32_t *__restrict__ heap_leaf,
+                              int64_t nleaf, int32_t *__restrict__ gcount) {
+    const int t = blockIdx.y;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&gcount[(int64_t)t * nleaf + heap_leaf[qleaf[(int64_t)t * m + q]]], 1);
+}
+
+__global__ __launch_bounds__(1024) void k_group_scan(const int32_t *__restrict__ gcount, int64_t nleaf,
+                                                     int32_t *__restrict__ goff) {
+    __shared__ int32_t s_w[16];
+    __shared__ int32_t s_run;
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nleaf; base += 1024) {
+        const int64_t i = base + tid;
+        const int32_t v = i < nleaf ? gcount[(int64_t)t * nleaf + i] : 0;
+        int32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        int32_t wb = 0, tot = 0;
+        for (int k = 0; k < 16; k++) {
+            if (k < w) wb += s_w[k];
+            tot += s_w[k];
+        }
+        if (i < nleaf) goff[(int64_t)t * nleaf + i] = s_run + wb + x - v;
+        __syncthreads();
+        if (tid == 0) s_run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_group_fill(const int32_t *__restrict__ qleaf, int64_t m, const int32_t *__restrict__ heap_leaf,
+                             int64_t nleaf, const int32_t *__restrict__ goff, int32_t *__restrict__ gfill,
+                             int32_t *__restrict__ qorder, int32_t *__restrict__ qgleaf) {
+    const int t = blockIdx.y;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t li = heap_leaf[qleaf[(int64_t)t * m + q]];
+        const int32_t pos = goff[(int64_t)t * nleaf + li] + atomicAdd(&gfill[(int64_t)t * nleaf + li], 1);
+        qorder[(int64_t)t * m + pos] = (int32_t)q;
+        qgleaf[(int64_t)t * m + pos] = li;
+    }
+}
+
+// one tile job per (A chunk of a non-empty group) x (B tile of the leaf); tree 0 -> list 0
+__global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int64_t nleaf,
+                            const LeafDesc *__restrict__ leaves, int TR, TileJob *__restrict__ jobs0,
+                            TileJob *__restrict__ jobs1, int32_t *__restrict__ njobs) {
+    const int t = blockIdx.y;
+    for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < nleaf; li += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = gcount[(int64_t)t * nleaf + li];
+        if (c == 0) continue;
+        const LeafDesc lf = leaves[li];
+        const int na = (c + TR - 1) / TR, nb = (lf.size + TR - 1) / TR;
+        for (int I = 0; I < na; I++)
+            for (int J = 0; J < nb; J++) {
+                TileJob j;
+                j.a_off = goff[(int64_t)t * nleaf + li] + (int64_t)I * TR;
+                j.b_off = lf.off + (int64_t)J * TR;
+                j.a_rows = min(TR, c - I * TR);
+                j.b_rows = min(TR, lf.size - J * TR);
+                j.tree = t;
+                j.same = 0;
+                const int slot = atomicAdd(&njobs[t == 0 ? 0 : 1], 1);
+                (t == 0 ? jobs0 : jobs1)[slot] = j;
+            }
+    }
+}
+
+// leaf-centred query copies in the tile precision, with the same norms as the data copies
+template <typename T>
+__global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q, int64_t m, int d, int dp,
+                                                    const int32_t *__restrict__ qorder,
+                                                    const int32_t *__restrict__ qgleaf,
+                                                    const float *__restrict__ centroid, int64_t nleaf,
+                                                    T *__restrict__ Qc, float2 *__restrict__ qnrm, float range_max) {
+    const int t = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t pos = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pos >= m) return;
+    const int64_t q = qorder[(int64_t)t * m + pos];
+    const float *mu = centroid + ((int64_t)t * nleaf + qgleaf[(int64_t)t * m + pos]) * d;
+    T *out = Qc + ((int64_t)t * m + pos) * dp;
+    float na = 0.f, ra = 0.f;
+    bool over = false;
+    for (int j = lane; j < dp; j += 64) {
+        const float a = j < d ? Q[q * d + j] - mu[j] : 0.f;
+        over |= fabsf(a) > range_max;
+        const T v = (T)a;
+        out[j] = v;
+        const float vf = (float)v;
+        na = __builtin_fmaf(vf, vf, na);
+        ra = __builtin_fmaf(a, a, ra);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        na += __shfl_xor(na, o, 64);
+        ra += __shfl_xor(ra, o, 64);
+    }
+    const uint64_t ov = __ballot(over);
+    if (lane == 0) qnrm[(int64_t)t * m + pos] = make_float2(na, ov ? INFINITY : sqrtf(ra));
+}
+
+// ================================================================ host launch sequences
+
+static BoundCoef bound_coef(int prec, int d) {
+    const double u32 = ldexp(1.0, -24);
+    const double ulp = prec == RPF_DIST_BF16 ? ldexp(1.0, -8) : prec == RPF_DIST_FP16 ? ldexp(1.0, -11) : 0.0;
+    const double k = d + 2;
+    const double gam = k * u32 / (1.0 - k * u32);
+    BoundCoef bc;
+    bc.e = (float)(2.0 * 2.0 * gam * 1.01);
+    bc.c = (float)((ulp + u32 + ulp * u32) * (1.0 + (d + 4) * u32) * 1.01);
+    bc.eta = prec == RPF_DIST_FP16 ? (float)(2.0 * ldexp(1.0, -25) * sqrt((double)d) * 1.01) : 0.f;
+    return bc;
+}
+
+static float rerank_window(int d) {
+    const double u32 = ldexp(1.0, -24);
+    const double eps = (ceil(d / 32.0) + 8.0) * u32;
+    return (float)std::max(2e-6, 2.5 * eps + 4.0 * u32);
+}
+
+template <int MB, int PREC>
+static void tile_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B, int dp,
+                        int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
+                        const int32_t *bp, BoundCoef bc, const float *tau, int excl, int32_t *cnt, Ent *ent, int cap) {
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL((k_tile<MB, PREC>), dim3((unsigned)njobs), dim3(64 * MB), 0, s, jobs, A, B, dp, as, bs, an, bn,
+                       ad, bp, bc, tau, excl, cnt, ent, cap);
+    launch_check(s, "k_tile");
+}
+
+template <int PREC>
+static void tile_dispatch_mb(int MB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B,
+                             int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
+                             const int32_t *bp, BoundCoef bc, const float *tau, int excl, int32_t *cnt, Ent *ent,
+                             int cap) {
+    switch (MB) {
+    case 1: tile_launch<1, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
+    case 2: tile_launch<2, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
+    case 4: tile_launch<4, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
+    default: tile_launch<8, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
+    }
+}
+
+static void tile_dispatch(int prec, int MB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A,
+                          const void *B, int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn,
+                          const int32_t *ad, const int32_t *bp, BoundCoef bc, const float *tau, int excl,
+                          int32_t *cnt, Ent *ent, int cap) {
+    if (prec == RPF_DIST_BF16)
+        tile_dispatch_mb<RPF_DIST_BF16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+    else if (prec == RPF_DIST_FP16)
+        tile_dispatch_mb<RPF_DIST_FP16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+    else
+        tile_dispatch_mb<RPF_DIST_FP32>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+}
+
+// stream-ordered workspace
+struct Workspace {
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    bool ok = true;
+    explicit Workspace(hipStream_t st) : s(st) {}
+    template <typename P>
+    P *get(size_t bytes) {
+        void *p = nullptr;
+        if (!bytes) bytes = 16;
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+            ok = false;
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        return static_cast<P *>(p);
+    }
+    ~Workspace() {
+        for (void *p : ptrs) hipFreeAsync(p, s);
+    }
+};
+
+static void keep_pool_memory(int dev) {
+    static bool done[64] = {false};
+    if (dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[dev] = true;
+}
+
+// common candidate stage once the tile jobs, A rows and per-row metadata are known
+struct CandStage {
+    int64_t rows;          // number of result rows (n or m)
+    const TileJob *jobs0;  // Phase I jobs (first tree)
+    const TileJob *jobs1;  // Phase II jobs (other trees)
+    int64_t njobs0, njobs1;
+    const void *A;
+    int64_t a_stride;
+    const float2 *a_nrm;
+    const int32_t *a_dest;
+    const float *Qr;       // binary32 rows of the result rows
+    const int32_t *row_leaf;  // [T][rows] heap ids (fallback)
+    int excl;
+};
+
+static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
+                                 float *out_dist, hipStream_t s) {
+    Workspace ws(s);
+    const int64_t rows = cs.rows;
+    const int cap = std::min(512, std::max(256, v.max_leaf));
+    const int lcap = 128;
+    float *tau = ws.get<float>(rows * 4);
+    int32_t *cnt = ws.get<int32_t>(rows * 4);
+    Ent *ent = ws.get<Ent>((size_t)rows * cap * sizeof(Ent));
+    Ent *list = ws.get<Ent>((size_t)rows * lcap * sizeof(Ent));
+    int32_t *lcnt = ws.get<int32_t>(rows * 4);
+    int32_t *fb_list = ws.get<int32_t>(rows * 4);
+    int32_t *fb_cnt = ws.get<int32_t>(16);
+    if (!ws.ok) return fail(RPF_ENOMEM, "kNN workspace allocation failed");
+    hipMemsetAsync(cnt, 0, rows * 4, s);
+    hipMemsetAsync(fb_cnt, 0, 16, s);
+    hipMemsetAsync(v.stats, 0, 32, s);
+    const BoundCoef bc = bound_coef(v.prec, v.d);
+    const int MB = v.job_mb;
+    const double tile_flops0 = 0, tile_flops1 = 0;
+    (void)tile_flops0;
+    (void)tile_flops1;
+    {
+        ProfScope ps(s, "tile_phase1", 0, 0);
+        tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
+                      cs.a_dest, v.perm, bc, nullptr, cs.excl, cnt, ent, cap);
+    }
+    {
+        ProfScope ps(s, "merge_init", 0, 0);
+        hipLaunchKernelGGL(k_merge_init, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cnt, ent, cap,
+                           tau, list, lcnt, lcap);
+        launch_check(s, "k_merge_init");
+    }
+    if (cs.njobs1 > 0) {
+        ProfScope ps(s, "tile_phase2", 0, 0);
+        tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
+                      cs.a_dest, v.perm, bc, tau, cs.excl, cnt, ent, cap);
+    }
+    FinalArgs fa;
+    fa.list = list; fa.lcnt = lcnt; fa.lcap = lcap; fa.cnt = cnt; fa.ent = ent; fa.cap = cap; fa.K = K;
+    fa.X = v.X; fa.Qr = cs.Qr; fa.d = v.d; fa.win = rerank_window(v.d); fa.out_idx = out_idx;
+    fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.stats = v.stats;
+    const bool vec = (v.d % 4) == 0;
+    {
+        ProfScope ps(s, "final_rerank", 0, 0);
+        if (vec)
+            hipLaunchKernelGGL(k_final<true>, dim3((unsigned)rows), dim3(64), v.d * 4, s, fa, rows);
+        else
+            hipLaunchKernelGGL(k_final<false>, dim3((unsigned)rows), dim3(64), v.d * 4, s, fa, rows);
+        launch_check(s, "k_final");
+    }
+    FallbackArgs fb;
+    fb.fb_list = fb_list; fb.fb_cnt = fb_cnt; fb.X = v.X; fb.Qr = cs.Qr; fb.d = v.d; fb.K = K; fb.T = v.T;
+    fb.n = v.n; fb.perm = v.perm; fb.row_leaf = cs.row_leaf; fb.nrows = rows; fb.heap_leaf = v.heap_leaf;
+    fb.leaves = v.leaves; fb.exclude_self = cs.excl; fb.out_idx = out_idx; fb.out_dist = out_dist;
+    {
+        ProfScope ps(s, "fallback", 0, 0);
+        const unsigned nb = (unsigned)std::min<int64_t>(rows, 1024);
+        if (vec)
+            hipLaunchKernelGGL(k_fallback<true>, dim3(nb), dim3(256), v.d * 4, s, fb);
+        else
+            hipLaunchKernelGGL(k_fallback<false>, dim3(nb), dim3(256), v.d * 4, s, fb);
+        launch_check(s, "k_fallback");
+    }
+    const std::string le = take_launch_error();
+    if (!le.empty()) return fail(RPF_EDEVICE, "kNN: " + le);
+    return RPF_OK;
+}
+
+rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s) {
+    const ForestView v = view(f);
+    int dev = 0;
+    hipGetDevice(&dev);
+    keep_pool_memory(dev);
+    CandStage cs;
+    cs.rows = v.n;
+    cs.jobs0 = v.jobs;
+    cs.jobs1 = v.jobs + v.n_jobs_tree;
+    cs.njobs0 = v.n_jobs_tree;
+    cs.njobs1 = v.n_jobs_tree * (v.T - 1);
+    cs.A = v.Xc;
+    cs.a_stride = v.n;
+    cs.a_nrm = v.nrm;
+    cs.a_dest = v.perm;
+    cs.Qr = v.X;
+    cs.row_leaf = v.leaf_of;
+    cs.excl = exclude_self;
+    return run_cand_stage(v, cs, K, out_idx, out_dist, s);
+}
+
+rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s) {
+    const ForestView v = view(f);
+    const bool vec = (v.d % 4) == 0 && ((uintptr_t)Q % 16) == 0;
+    dim3 grid((unsigned)((m + 31) / 32), v.T);
+    ProfScope ps(s, "route", (double)m * v.T * (v.L * (8.0 * v.d + 16)), 0);
+    if (vec)
+        hipLaunchKernelGGL(k_route<true>, grid, dim3(256), 0, s, Q, m, v.d, v.R, v.H, v.n_try, v.chosen, v.split, v.n,
+                           v.n0, out_leaf);
+    else
+        hipLaunchKernelGGL(k_route<false>, grid, dim3(256), 0, s, Q, m, v.d, v.R, v.H, v.n_try, v.chosen, v.split,
+                           v.n, v.n0, out_leaf);
+    launch_check(s, "k_route");
+    const std::string le = take_launch_error();
+    if (!le.empty()) return fail(RPF_EDEVICE, "route: " + le);
+    return RPF_OK;
+}
+
+rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
+                     hipStream_t s) {
+    const ForestView v = view(f);
+    int dev = 0;
+    hipGetDevice(&dev);
+    keep_pool_memory(dev);
+    {   // queries must be finite (one synchronisation)
+        int32_t *flag = nullptr;
+        if (hipMallocAsync((void **)&flag, 16, s) != hipSuccess) return fail(RPF_ENOMEM, "rpf_query: allocation");
+        hipMemsetAsync(flag, 0, 16, s);
+        launch_nonfinite(s, Q, m * v.d, flag);
+        int32_t h = 0;
+        hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
+        hipFreeAsync(flag, s);
+        rpf_status st = check_hip(hipStreamSynchronize(s), "rpf_query input check");
+        if (st != RPF_OK) return st;
+        if (h) return fail(RPF_EINVAL, "rpf_query: Q holds NaN or Inf");
+    }
+    Workspace ws(s);
+    const int T = v.T;
+    const int64_t nleaf = v.nleaf;
+    const int TR = 32 * v.job_mb;
+    const size_t esz = v.prec == RPF_DIST_FP32 ? 4 : 2;
+    int32_t *qleaf = ws.get<int32_t>((size_t)T * m * 4);
+    int32_t *gcount = ws.get<int32_t>((size_t)T * nleaf * 4);
+    int32_t *goff = ws.get<int32_t>((size_t)T * nleaf * 4);
+    int32_t *gfill = ws.get<int32_t>((size_t)T * nleaf * 4);
+    int32_t *qorder = ws.get<int32_t>((size_t)T * m * 4);
+    int32_t *qgleaf = ws.get<int32_t>((size_t)T * m * 4);
+    void *Qc = ws.get<void>((size_t)T * m * v.dp * esz);
+    float2 *qnrm = ws.get<float2>((size_t)T * m * 8);
+    const int nbt = (v.max_leaf + TR - 1) / TR;
+    const int64_t jcap0 = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
+    const int64_t jcap1 = jcap0 * (T > 1 ? T - 1 : 1);
+    TileJob *jobs0 = ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob));
+    TileJob *jobs1 = ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob));
+    int32_t *njobs = ws.get<int32_t>(16);
+    if (!ws.ok) return fail(RPF_ENOMEM, "rpf_query: workspace allocation failed");
+    rpf_status st = route(f, Q, m, qleaf, s);
+    if (st != RPF_OK) return st;
+    hipMemsetAsync(gcount, 0, (size_t)T * nleaf * 4, s);
+    hipMemsetAsync(gfill, 0, (size_t)T * nleaf * 4, s);
+    hipMemsetAsync(njobs, 0, 16, s);
+    const unsigned qb = (unsigned)std::min<int64_t>((m + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_group_count, dim3(qb, T), dim3(256), 0, s, qleaf, m, v.heap_leaf, nleaf, gcount);
+    hipLaunchKernelGGL(k_group_scan, dim3(T), dim3(1024), 0, s, gcount, nleaf, goff);
+    hipLaunchKernelGGL(k_group_fill, dim3(qb, T), dim3(256), 0, s, qleaf, m, v.heap_leaf, nleaf, goff, gfill, qorder,
+                       qgleaf);
+    const unsigned lb_ = (unsigned)std::min<int64_t>((nleaf + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_make_jobs, dim3(lb_, T), dim3(256), 0, s, gcount, goff, nleaf, v.leaves, TR, jobs0, jobs1,
+                       njobs);
+    launch_check(s, "query grouping");
+    {
+        dim3 g((unsigned)((m + 3) / 4), T);
+        if (v.prec == RPF_DIST_BF16)
+            hipLaunchKernelGGL(k_query_prep<__bf16>, g, dim3(256), 0, s, Q, m, v.d, v.dp, qorder, qgleaf, v.centroid,
+                               nleaf, (__bf16 *)Qc, qnrm, 3.0e38f);
+        else if (v.prec == RPF_DIST_FP16)
+            hipLaunchKernelGGL(k_query_prep<_Float16>, g, dim3(256), 0, s, Q, m, v.d, v.dp, qorder, qgleaf,
+                               v.centroid, nleaf, (_Float16 *)Qc, qnrm, 60000.f);
+        else
+            hipLaunchKernelGGL(k_query_prep<float>, g, dim3(256), 0, s, Q, m, v.d, v.dp, qorder, qgleaf, v.centroid,
+                               nleaf, (float *)Qc, qnrm, 3.0e38f);
+    }
+    // the job counts are needed to size the tile grids: read them back (small, one sync)
+    launch_check(s, "k_query_prep");
+    int32_t nj[2] = {0, 0};
+    hipMemcpyAsync(nj, njobs, 8, hipMemcpyDeviceToHost, s);
+    st = check_hip(hipStreamSynchronize(s), "rpf_query grouping");
+    if (st != RPF_OK) return st;
+    {
+        const std::string le = take_launch_error();
+        if (!le.empty()) return fail(RPF_EDEVICE, "rpf_query: " + le);
+    }
+    CandStage cs;
+    cs.rows = m;
+    cs.jobs0 = jobs0;
+    cs.jobs1 = jobs1;
+    cs.njobs0 = nj[0];
+    cs.njobs1 = T > 1 ? nj[1] : 0;
+    cs.A = Qc;
+    cs.a_stride = m;
+    cs.a_nrm = qnrm;
+    cs.a_dest = qorder;
+    cs.Qr = Q;
+    cs.row_leaf = qleaf;
+    cs.excl = 0;
+    return run_cand_stage(v, cs, K, out_idx, out_dist, s);
+}
+
+}  // namespace rpf

@@ -1,0 +1,657 @@
+// C ABI of the rpForests library: argument checks, the closed-form tree plan, device
+// memory, and the launch sequences of rpf_build / rpf_all_knn / rpf_query.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rpf_internal.h"
+
+namespace rpf {
+
+// ---- launchers defined in build_kernels.hip / knn_kernels.hip
+size_t cand_bytes();
+size_t level_small_lds(int max_m, int d, int n_try);
+void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, int n_try,
+                        const SegDesc *segs, int nseg, int max_m, int T, const int32_t *pin, int32_t *pout,
+                        int64_t n, double *split, int32_t *split_idx, int32_t *chosen, int32_t *err);
+void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, int n_try,
+                        const SegDesc *segs, int nseg, const ChunkDesc *chunks, int nchunk, int T,
+                        const int32_t *pin, int32_t *pout, int64_t n, double *split, int32_t *split_idx,
+                        int32_t *chosen, int32_t *err, const LargeBufs &b, double proj_bytes);
+void launch_copy_segments(hipStream_t s, const LeafDesc *segs, int nseg, int T, const int32_t *in, int32_t *out,
+                          int64_t n);
+void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T);
+void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves,
+                          int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
+                          void *Xc, float2 *nrm);
+void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
+
+rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s);
+rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
+                     hipStream_t s);
+rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s);
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+rpf_status fail(rpf_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+rpf_status check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return RPF_OK;
+    return fail(e == hipErrorOutOfMemory ? RPF_ENOMEM : RPF_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static thread_local std::string g_launch_err;
+
+void launch_check(hipStream_t s, const char *name) {
+    static const bool sync = [] {
+        const char *e = getenv("RPF_SYNC_CHECK");
+        return e && e[0] == '1';
+    }();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
+    if (e != hipSuccess && g_launch_err.empty()) g_launch_err = std::string(name) + ": " + hipGetErrorString(e);
+}
+
+std::string take_launch_error() {
+    std::string r;
+    r.swap(g_launch_err);
+    return r;
+}
+
+// ---------------------------------------------------------------- profiling
+
+struct ProfRec {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, flops = 0;
+};
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::map<std::string, ProfRec> g_prof;
+static std::vector<Pending> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t get_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+}
+
+void prof_begin(hipStream_t s, const char *name, double bytes, double flops, void **tok) {
+    *tok = nullptr;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    Pending *p = new Pending{name, get_event(), get_event(), bytes, flops};
+    hipEventRecord(p->a, s);
+    *tok = p;
+}
+
+void prof_end(hipStream_t s, void *tok) {
+    if (!tok) return;
+    Pending *p = static_cast<Pending *>(tok);
+    hipEventRecord(p->b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back(*p);
+    delete p;
+}
+
+static void prof_drain() {
+    for (auto &p : g_pending) {
+        hipEventSynchronize(p.b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        ProfRec &r = g_prof[p.name];
+        r.launches++;
+        r.ms += ms;
+        r.bytes += p.bytes;
+        r.flops += p.flops;
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+// ---------------------------------------------------------------- validation kernels
+
+__global__ void k_nonfinite(const float *__restrict__ x, int64_t count, int32_t *flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag) {
+    if (count <= 0) return;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, x, count, flag);
+}
+
+}  // namespace rpf
+
+using namespace rpf;
+
+// ---------------------------------------------------------------- the forest
+
+struct rpf_forest {
+    int64_t n = 0;
+    int32_t d = 0, T = 0, n0 = 0, n_try = 0, L = 0, prec = 0, dp = 0;
+    int64_t H = 0;
+    int device = 0;
+    // persistent device arrays
+    float *X = nullptr;          // [n][d]
+    float *R = nullptr;          // [T][H][n_try][d]
+    double *split = nullptr;     // [T][H]
+    int32_t *split_idx = nullptr;
+    int32_t *chosen = nullptr;
+    int32_t *perm[2] = {nullptr, nullptr};
+    int final_buf = 0;
+    int32_t *leaf_of = nullptr;  // [T][n]
+    float *centroid = nullptr;   // [T][nleaf][d]
+    void *Xc = nullptr;          // [T][n][dp] leaf-ordered, centred, tile precision
+    float2 *nrm = nullptr;       // [T][n] (|Xc row|^2, |x - mu|)
+    int32_t *err = nullptr;      // device error flags of the build kernels
+    int32_t *heap_leaf = nullptr;  // heap id -> leaf index
+    // descriptors
+    SegDesc *d_segs = nullptr;
+    ChunkDesc *d_chunks = nullptr;
+    LeafDesc *d_leaves = nullptr;
+    LeafDesc *d_copy = nullptr;
+    TileJob *d_jobs = nullptr;   // all-points tile jobs
+    int64_t n_jobs_tree = 0;     // jobs per tree
+    int job_mb = 8;
+    std::vector<LeafDesc> leaves;
+    int max_leaf = 0;
+    uint64_t bytes = 0;
+    // stats of the last kNN call
+    unsigned long long *stats = nullptr;  // [4]
+    mutable std::mutex mu;
+};
+
+namespace rpf {
+
+struct LevelPlan {
+    std::vector<SegDesc> segs;     // internal nodes
+    std::vector<ChunkDesc> chunks; // multi-block path
+    std::vector<LeafDesc> copy;    // leaves formed at or before this level (carried over)
+    int max_m = 0;
+    bool large = false;
+    int64_t seg_off = 0, chunk_off = 0, copy_off = 0;  // offsets into the device descriptor arrays
+};
+
+static int depth_of(int64_t n, int64_t n0) {
+    int L = 0;
+    while ((n + ((int64_t)1 << L) - 1) >> L > n0) L++;
+    return L;
+}
+
+static int lds_limit(int dev) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    return v;
+}
+
+}  // namespace rpf
+
+extern "C" {
+
+int32_t rpf_depth(int64_t n, int32_t leaf_size) {
+    if (n < 1 || leaf_size < 1) return -1;
+    return depth_of(n, leaf_size);
+}
+
+const char *rpf_last_error(void) { return g_err.c_str(); }
+
+rpf_status rpf_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return RPF_OK;
+}
+
+rpf_status rpf_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    g_prof.clear();
+    return RPF_OK;
+}
+
+rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count) {
+    if (!count || (cap > 0 && !out)) return fail(RPF_EINVAL, "rpf_profile_read: null pointer");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    int32_t k = 0;
+    for (auto &kv : g_prof) {
+        if (k < cap) {
+            memset(&out[k], 0, sizeof(out[k]));
+            strncpy(out[k].name, kv.first.c_str(), sizeof(out[k].name) - 1);
+            out[k].launches = kv.second.launches;
+            out[k].total_ms = kv.second.ms;
+            out[k].algo_bytes = kv.second.bytes;
+            out[k].algo_flops = kv.second.flops;
+        }
+        k++;
+    }
+    *count = k;
+    return RPF_OK;
+}
+
+static void free_forest_memory(rpf_forest *f) {
+    void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
+                    f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
+                    f->d_copy, f->d_jobs, f->stats};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+}
+
+rpf_status rpf_free(rpf_forest *f) {
+    if (!f) return RPF_OK;
+    hipDeviceSynchronize();
+    free_forest_memory(f);
+    delete f;
+    return RPF_OK;
+}
+
+rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream, rpf_forest **out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(RPF_EINVAL, "rpf_build: out is NULL");
+    if (!X) return fail(RPF_EINVAL, "rpf_build: X is NULL");
+    if (!p) return fail(RPF_EINVAL, "rpf_build: params is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: n must be in [1, 2^31)");
+    if (d < 1) return fail(RPF_EINVAL, "rpf_build: d must be >= 1");
+    if (p->n_trees < 1 || p->n_trees > 65535) return fail(RPF_EINVAL, "rpf_build: n_trees must be in [1, 65535]");
+    if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
+    if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
+    if (p->split_rule != RPF_SPLIT_MEDIAN) return fail(RPF_EINVAL, "rpf_build: only the median split rule is implemented");
+    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_FP16)
+        return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
+    if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
+    const int L = depth_of(n, p->leaf_size);
+    if (L > 30) return fail(RPF_EINVAL, "rpf_build: tree deeper than 30 levels");
+    const int64_t H = ((int64_t)1 << L) - 1;
+    if (H > 0 && !p->directions_dev) return fail(RPF_EINVAL, "rpf_build: directions_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int T = p->n_trees, n0 = p->leaf_size, n_try = p->n_try;
+
+    int dev = 0;
+    hipGetDevice(&dev);
+
+    // ---- plan (closed form: the median rule makes the shape data-independent)
+    std::vector<LevelPlan> levels(L);
+    std::vector<LeafDesc> leaves;
+    {
+        struct Node { int64_t heap, off, size; };
+        std::vector<Node> cur{{1, 0, n}};
+        std::vector<LeafDesc> formed;
+        for (int l = 0; l <= L; l++) {
+            std::vector<Node> next;
+            for (auto &nd : cur) {
+                if (nd.size > n0 && l < L) {
+                    levels[l].segs.push_back(SegDesc{nd.off, (int32_t)nd.size, (int32_t)nd.heap, 0, 0});
+                    levels[l].max_m = std::max<int>(levels[l].max_m, (int)nd.size);
+                    next.push_back({2 * nd.heap, nd.off, nd.size / 2});
+                    next.push_back({2 * nd.heap + 1, nd.off + nd.size / 2, nd.size - nd.size / 2});
+                } else {
+                    formed.push_back(LeafDesc{nd.off, (int32_t)nd.size, (int32_t)nd.heap});
+                }
+            }
+            if (l < L) levels[l].copy = formed;  // leaves carried into this level's output
+            cur.swap(next);
+        }
+        leaves = formed;
+        std::sort(leaves.begin(), leaves.end(), [](const LeafDesc &a, const LeafDesc &b) { return a.off < b.off; });
+    }
+    const int lds_max = lds_limit(dev);
+    int small_max = kLarge;
+    while (small_max > 2 && level_small_lds(small_max, d, n_try) > (size_t)lds_max) small_max /= 2;
+    int64_t max_seg_large = 0, max_chunk_large = 0;
+    int64_t nseg_tot = 0, nchunk_tot = 0, ncopy_tot = 0;
+    for (auto &lv : levels) {
+        lv.large = lv.max_m > small_max;
+        lv.seg_off = nseg_tot;
+        lv.copy_off = ncopy_tot;
+        lv.chunk_off = nchunk_tot;
+        if (lv.large) {
+            for (auto &sg : lv.segs) {
+                sg.chunk0 = (int32_t)lv.chunks.size();
+                sg.nchunk = (int32_t)((sg.size + kChunk - 1) / kChunk);
+                for (int q = 0; q < sg.nchunk; q++) {
+                    int64_t st = sg.off + (int64_t)q * kChunk;
+                    int32_t len = (int32_t)std::min<int64_t>(kChunk, sg.off + sg.size - st);
+                    lv.chunks.push_back(ChunkDesc{st, len, (int32_t)(&sg - lv.segs.data())});
+                }
+            }
+            max_seg_large = std::max<int64_t>(max_seg_large, (int64_t)lv.segs.size());
+            max_chunk_large = std::max<int64_t>(max_chunk_large, (int64_t)lv.chunks.size());
+        }
+        nseg_tot += lv.segs.size();
+        nchunk_tot += lv.chunks.size();
+        ncopy_tot += lv.copy.size();
+    }
+
+    // ---- memory plan
+    const int prec = p->dist_prec;
+    const int dp = (d + 7) & ~7;
+    const size_t esz = prec == RPF_DIST_FP32 ? 4 : 2;
+    const int64_t nleaf = (int64_t)leaves.size();
+    int max_leaf = 0;
+    for (auto &lf : leaves) max_leaf = std::max(max_leaf, (int)lf.size);
+    uint64_t bytes = 0;
+    bytes += (uint64_t)n * d * 4;                        // X
+    bytes += (uint64_t)T * H * n_try * d * 4;            // R
+    bytes += (uint64_t)T * H * (8 + 4 + 4);              // split, split_idx, chosen
+    bytes += (uint64_t)2 * T * n * 4;                    // perm x2
+    bytes += (uint64_t)T * n * 4;                        // leaf_of
+    bytes += (uint64_t)T * nleaf * d * 4;                // centroid
+    bytes += (uint64_t)T * n * dp * esz;                 // Xc
+    bytes += (uint64_t)T * n * 8;                        // nrm
+    uint64_t tmp_bytes = 0;
+    if (max_seg_large > 0) {
+        tmp_bytes += (uint64_t)T * n * 8;                                      // keys
+        if (n_try > 1) tmp_bytes += (uint64_t)T * n * 8;                       // praw
+        tmp_bytes += (uint64_t)T * max_seg_large * (sizeof(SelState) + 4 * kDigitBins + cand_bytes() * kCandCap + 4);
+        tmp_bytes += (uint64_t)T * max_chunk_large * (4 + 8);
+    }
+    if (p->mem_budget_bytes && bytes + tmp_bytes > p->mem_budget_bytes)
+        return fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(bytes + tmp_bytes) +
+                                    " bytes, over mem_budget_bytes");
+
+    rpf_forest *f = new rpf_forest();
+    f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
+    f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
+    f->bytes = bytes;
+
+    auto bail = [&](rpf_status st) {
+        hipStreamSynchronize(s);
+        free_forest_memory(f);
+        delete f;
+        return st;
+    };
+#define RPF_ALLOC(ptr, sz)                                                                     \
+    do {                                                                                       \
+        size_t _sz = (size_t)(sz);                                                             \
+        if (_sz) {                                                                             \
+            rpf_status _st = check_hip(hipMalloc((void **)&(ptr), _sz), "hipMalloc " #ptr);   \
+            if (_st != RPF_OK) return bail(RPF_ENOMEM);                                        \
+        }                                                                                      \
+    } while (0)
+
+    RPF_ALLOC(f->X, (size_t)n * d * 4);
+    RPF_ALLOC(f->R, (size_t)T * H * n_try * d * 4);
+    RPF_ALLOC(f->split, (size_t)T * H * 8);
+    RPF_ALLOC(f->split_idx, (size_t)T * H * 4);
+    RPF_ALLOC(f->chosen, (size_t)T * H * 4);
+    RPF_ALLOC(f->perm[0], (size_t)T * n * 4);
+    RPF_ALLOC(f->perm[1], (size_t)T * n * 4);
+    RPF_ALLOC(f->leaf_of, (size_t)T * n * 4);
+    RPF_ALLOC(f->centroid, (size_t)T * nleaf * d * 4);
+    RPF_ALLOC(f->Xc, (size_t)T * n * dp * esz);
+    RPF_ALLOC(f->nrm, (size_t)T * n * 8);
+    RPF_ALLOC(f->err, 64);
+    RPF_ALLOC(f->stats, 64);
+    RPF_ALLOC(f->heap_leaf, ((size_t)4 << L) * sizeof(int32_t));  // heap ids < 2^(L+1)
+    if (nseg_tot) RPF_ALLOC(f->d_segs, nseg_tot * sizeof(SegDesc));
+    if (nchunk_tot) RPF_ALLOC(f->d_chunks, nchunk_tot * sizeof(ChunkDesc));
+    RPF_ALLOC(f->d_leaves, nleaf * sizeof(LeafDesc));
+    if (ncopy_tot) RPF_ALLOC(f->d_copy, ncopy_tot * sizeof(LeafDesc));
+
+    // ---- inputs: copy, then reject non-finite values (one synchronisation)
+    rpf_status st;
+    if ((st = check_hip(hipMemcpyAsync(f->X, X, (size_t)n * d * 4, hipMemcpyDeviceToDevice, s), "copy X")) != RPF_OK)
+        return bail(st);
+    if (H > 0 &&
+        (st = check_hip(hipMemcpyAsync(f->R, p->directions_dev, (size_t)T * H * n_try * d * 4, hipMemcpyDeviceToDevice, s),
+                        "copy directions")) != RPF_OK)
+        return bail(st);
+    hipMemsetAsync(f->err, 0, 64, s);
+    hipMemsetAsync(f->stats, 0, 64, s);
+    launch_nonfinite(s, f->X, n * d, f->err);
+    launch_nonfinite(s, f->R, T * H * n_try * d, f->err + 1);
+    launch_check(s, "nonfinite check");
+    int32_t flags[2] = {0, 0};
+    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 8, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
+    if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);
+    if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
+    if (flags[1]) { fail(RPF_EINVAL, "rpf_build: directions hold NaN or Inf"); return bail(RPF_EINVAL); }
+    hipMemsetAsync(f->err, 0, 64, s);
+
+    // ---- descriptors
+    {
+        std::vector<SegDesc> all_segs;
+        std::vector<ChunkDesc> all_chunks;
+        std::vector<LeafDesc> all_copy;
+        for (auto &lv : levels) {
+            all_segs.insert(all_segs.end(), lv.segs.begin(), lv.segs.end());
+            all_chunks.insert(all_chunks.end(), lv.chunks.begin(), lv.chunks.end());
+            all_copy.insert(all_copy.end(), lv.copy.begin(), lv.copy.end());
+        }
+        if (nseg_tot) hipMemcpy(f->d_segs, all_segs.data(), nseg_tot * sizeof(SegDesc), hipMemcpyHostToDevice);
+        if (nchunk_tot) hipMemcpy(f->d_chunks, all_chunks.data(), nchunk_tot * sizeof(ChunkDesc), hipMemcpyHostToDevice);
+        if (ncopy_tot) hipMemcpy(f->d_copy, all_copy.data(), ncopy_tot * sizeof(LeafDesc), hipMemcpyHostToDevice);
+        hipMemcpy(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice);
+        std::vector<int32_t> hl((size_t)4 << L, -1);
+        for (size_t i = 0; i < leaves.size(); i++) hl[leaves[i].heap] = (int32_t)i;
+        hipMemcpy(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice);
+    }
+    launch_check(s, "descriptor upload");
+    hipMemsetAsync(f->split_idx, 0xff, (size_t)T * H * 4, s);
+    hipMemsetAsync(f->chosen, 0xff, (size_t)T * H * 4, s);
+    {   // NaN for heap slots that are not internal nodes
+        std::vector<double> nan_row((size_t)T * H, NAN);
+        if (H) hipMemcpy(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice);
+    }
+
+    // ---- temporaries of the multi-block path
+    LargeBufs lb{};
+    std::vector<void *> tmps;
+    auto talloc = [&](void **ptr, size_t sz) -> bool {
+        if (!sz) { *ptr = nullptr; return true; }
+        if (hipMallocAsync(ptr, sz, s) != hipSuccess) return false;
+        tmps.push_back(*ptr);
+        return true;
+    };
+    bool ok = true;
+    if (max_seg_large > 0) {
+        ok &= talloc((void **)&lb.keys, (size_t)T * n * 8);
+        if (n_try > 1) ok &= talloc((void **)&lb.praw, (size_t)T * n * 8);
+        ok &= talloc((void **)&lb.state, (size_t)T * max_seg_large * sizeof(SelState));
+        ok &= talloc((void **)&lb.hist, (size_t)T * max_seg_large * 4 * kDigitBins);
+        ok &= talloc((void **)&lb.cand, (size_t)T * max_seg_large * cand_bytes() * kCandCap);
+        ok &= talloc((void **)&lb.cand_cnt, (size_t)T * max_seg_large * 4);
+        ok &= talloc((void **)&lb.lcount, (size_t)T * max_chunk_large * 4);
+        ok &= talloc((void **)&lb.part, (size_t)T * max_chunk_large * 8);
+    }
+    if (!ok) {
+        for (void *q : tmps) hipFreeAsync(q, s);
+        fail(RPF_ENOMEM, "rpf_build: temporary allocation failed");
+        return bail(RPF_ENOMEM);
+    }
+
+    // ---- levels
+    const bool vec = (d % 4) == 0;
+    launch_iota(s, f->perm[0], n, T);
+    launch_check(s, "iota");
+    int cur = 0;
+    for (int l = 0; l < L; l++) {
+        LevelPlan &lv = levels[l];
+        const int32_t *pin = f->perm[cur];
+        int32_t *pout = f->perm[cur ^ 1];
+        launch_copy_segments(s, f->d_copy + lv.copy_off, (int)lv.copy.size(), T, pin, pout, n);
+        launch_check(s, "copy_segments");
+        int64_t members = 0;
+        for (auto &sg : lv.segs) members += sg.size;
+        const double proj_bytes = (double)T * members * (4.0 * d + 4 + 8);
+        if (!lv.large) {
+            ProfScope ps(s, "level_small", (double)T * members * (4.0 * d + 8), 0);
+            launch_level_small(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
+                               lv.max_m, T, pin, pout, n, f->split, f->split_idx, f->chosen, f->err);
+            launch_check(s, "level_small");
+        } else {
+            launch_level_large(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
+                               f->d_chunks + lv.chunk_off, (int)lv.chunks.size(), T, pin, pout, n, f->split,
+                               f->split_idx, f->chosen, f->err, lb, proj_bytes);
+            launch_check(s, "level_large");
+        }
+        cur ^= 1;
+    }
+    f->final_buf = cur;
+    {
+        ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * (double)esz + 16), 0);
+        launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of,
+                             f->centroid, f->Xc, f->nrm);
+        launch_check(s, "leaf_finalize");
+    }
+    for (void *q : tmps) hipFreeAsync(q, s);
+    launch_check(s, "rpf_build tail");
+    {
+        const std::string le = take_launch_error();
+        if (!le.empty()) {
+            fail(RPF_EDEVICE, "rpf_build: " + le);
+            return bail(RPF_EDEVICE);
+        }
+    }
+
+    // all-points tile jobs (same leaf shapes in every tree)
+    {
+        int MB = 8;
+        if (max_leaf <= 32) MB = 1;
+        else if (max_leaf <= 64) MB = 2;
+        else if (max_leaf <= 128) MB = 4;
+        const int TR = 32 * MB;
+        std::vector<TileJob> jobs;
+        for (int t = 0; t < T; t++)
+            for (auto &lf : leaves) {
+                const int nt = (lf.size + TR - 1) / TR;
+                for (int I = 0; I < nt; I++)
+                    for (int J = 0; J < nt; J++) {
+                        TileJob j;
+                        j.a_off = lf.off + (int64_t)I * TR;
+                        j.b_off = lf.off + (int64_t)J * TR;
+                        j.a_rows = std::min(TR, lf.size - I * TR);
+                        j.b_rows = std::min(TR, lf.size - J * TR);
+                        j.tree = t;
+                        j.same = I == J;
+                        jobs.push_back(j);
+                    }
+            }
+        f->n_jobs_tree = (int64_t)jobs.size() / T;
+        f->job_mb = MB;
+        RPF_ALLOC(f->d_jobs, jobs.size() * sizeof(TileJob));
+        hipMemcpy(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice);
+        f->bytes += jobs.size() * sizeof(TileJob);
+    }
+#undef RPF_ALLOC
+    *out = f;
+    return RPF_OK;
+}
+
+rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self, int32_t *out_idx, float *out_dist,
+                       void *stream) {
+    if (!f) return fail(RPF_EINVAL, "rpf_all_knn: forest is NULL");
+    if (!out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_all_knn: output is NULL");
+    if (exclude_self != 0 && exclude_self != 1) return fail(RPF_EINVAL, "rpf_all_knn: exclude_self must be 0 or 1");
+    if (K < 1 || K > f->n - exclude_self) return fail(RPF_EINVAL, "rpf_all_knn: K must be in [1, n - exclude_self]");
+    if (K > 256) return fail(RPF_EINVAL, "rpf_all_knn: K above 256 is not supported");
+    return knn_all(f, K, exclude_self, out_idx, out_dist, (hipStream_t)stream);
+}
+
+rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, int32_t *out_idx, float *out_dist,
+                     void *stream) {
+    if (!f) return fail(RPF_EINVAL, "rpf_query: forest is NULL");
+    if (m < 0) return fail(RPF_EINVAL, "rpf_query: m must be >= 0");
+    if (m == 0) return RPF_OK;
+    if (!Q || !out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_query: NULL pointer");
+    if (K < 1 || K > f->n) return fail(RPF_EINVAL, "rpf_query: K must be in [1, n]");
+    if (K > 256) return fail(RPF_EINVAL, "rpf_query: K above 256 is not supported");
+    return knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
+}
+
+rpf_status rpf_route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, void *stream) {
+    if (!f) return fail(RPF_EINVAL, "rpf_route: forest is NULL");
+    if (m < 0) return fail(RPF_EINVAL, "rpf_route: m must be >= 0");
+    if (m == 0) return RPF_OK;
+    if (!Q || !out_leaf) return fail(RPF_EINVAL, "rpf_route: NULL pointer");
+    return route(f, Q, m, out_leaf, (hipStream_t)stream);
+}
+
+rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split, int32_t *split_idx, int32_t *chosen,
+                         int32_t *perm, int32_t *leaf_of, void *stream) {
+    if (!f) return fail(RPF_EINVAL, "rpf_tree_dump: forest is NULL");
+    if (tree < 0 || tree >= f->T) return fail(RPF_EINVAL, "rpf_tree_dump: tree out of range");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t H = f->H, n = f->n;
+    if (split && H) hipMemcpyAsync(split, f->split + tree * H, H * 8, hipMemcpyDeviceToDevice, s);
+    if (split_idx && H) hipMemcpyAsync(split_idx, f->split_idx + tree * H, H * 4, hipMemcpyDeviceToDevice, s);
+    if (chosen && H) hipMemcpyAsync(chosen, f->chosen + tree * H, H * 4, hipMemcpyDeviceToDevice, s);
+    if (perm) hipMemcpyAsync(perm, f->perm[f->final_buf] + tree * n, n * 4, hipMemcpyDeviceToDevice, s);
+    if (leaf_of) hipMemcpyAsync(leaf_of, f->leaf_of + tree * n, n * 4, hipMemcpyDeviceToDevice, s);
+    return check_hip(hipGetLastError(), "rpf_tree_dump");
+}
+
+rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
+    if (!f || !out) return fail(RPF_EINVAL, "rpf_forest_info: NULL pointer");
+    out->n = f->n;
+    out->d = f->d;
+    out->n_trees = f->T;
+    out->leaf_size = f->n0;
+    out->n_try = f->n_try;
+    out->depth = f->L;
+    out->dist_prec = f->prec;
+    out->n_leaves = (int64_t)f->leaves.size();
+    out->device_bytes = f->bytes;
+    int32_t err = 0;
+    hipDeviceSynchronize();
+    hipMemcpy(&err, f->err, 4, hipMemcpyDeviceToHost);
+    if (err) return fail(RPF_EINTERNAL, "rpf_forest_info: build kernels flagged error " + std::to_string(err));
+    return RPF_OK;
+}
+
+rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *stream) {
+    if (!f || !out) return fail(RPF_EINVAL, "rpf_last_knn_stats: NULL pointer");
+    unsigned long long v[4];
+    hipMemcpyAsync(v, f->stats, sizeof(v), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_last_knn_stats");
+    if (st != RPF_OK) return st;
+    out->rows = (int64_t)v[0] + (int64_t)v[1];
+    out->fallback_rows = (int64_t)v[1];
+    out->reranked32 = (int64_t)v[2];
+    out->reranked64 = (int64_t)v[3];
+    return RPF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- read-only view for the kNN launchers
+namespace rpf {
+ForestView view(const rpf_forest *f) {
+    ForestView v;
+    v.n = f->n; v.H = f->H; v.d = f->d; v.T = f->T; v.n0 = f->n0; v.n_try = f->n_try; v.L = f->L;
+    v.prec = f->prec; v.dp = f->dp; v.max_leaf = f->max_leaf; v.job_mb = f->job_mb;
+    v.X = f->X; v.R = f->R; v.centroid = f->centroid; v.split = f->split; v.chosen = f->chosen;
+    v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
+    v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;
+    v.n_jobs_tree = f->n_jobs_tree; v.stats = f->stats;
+    return v;
+}
+}  // namespace rpf

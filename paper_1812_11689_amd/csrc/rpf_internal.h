@@ -1,0 +1,272 @@
+// Internal declarations of the rpForests HIP library (gfx950, wave64).
+//
+// Canonical arithmetic (the library's reading of Sec. 2 / Alg. 3, which fix no order):
+//   projection  p = r.x : 32 partial sums s_c over j = c (mod 32), j ascending, of the exact
+//               binary64 products (double)x_j*(double)r_j; a balanced adjacent-pair tree over
+//               s_0..s_31; + 0.0.
+//   distance    D = |a-b|^2 : the same 32 classes with s_c <- fma(delta, delta, s_c),
+//               delta = a_j - b_j rounded in the working precision (binary64 or binary32).
+//   sums        canon_sum(v[0..m)) : v padded with +0.0 to a power of two, adjacent pairs
+//               added level by level.
+// On the GPU eight lanes share one vector: lane g in [0,8) owns classes 4g..4g+3, reads
+// the float4 at j = 32k + 4g, and the tree is (s0+s1)+(s2+s3) inside the lane followed by
+// butterflies over lane distance 1, 2, 4 -- the same tree, operation for operation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/rpf.h"
+
+namespace rpf {
+
+constexpr int kLarge = 4096;      // segments above this size use the multi-block path
+constexpr int kChunk = 4096;      // positions per block on the multi-block path (power of 2)
+constexpr int kDigitBits = 11;    // radix digit of the multi-block median select
+constexpr int kDigitBins = 1 << kDigitBits;
+constexpr int kNumDigits = 9;     // 96-bit key (p, index): 8 digits of 11 bits + 1 of 8
+constexpr int kCandCap = 1024;    // candidates gathered for the final in-block select
+
+// ---------------------------------------------------------------- descriptors
+
+struct SegDesc {      // one internal node of a level (same shape for every tree)
+    int64_t off;      // first position in the node-ordered permutation
+    int32_t size;     // number of members m
+    int32_t heap;     // heap id h (root 1)
+    int32_t chunk0;   // multi-block path: first chunk of this segment
+    int32_t nchunk;   // multi-block path: number of chunks
+};
+
+struct ChunkDesc {
+    int64_t start;    // first position
+    int32_t len;      // <= kChunk
+    int32_t seg;      // segment index within the level
+};
+
+struct LeafDesc {
+    int64_t off;      // first position of the leaf in the permutation
+    int32_t size;
+    int32_t heap;
+};
+
+// multi-block median select state, one per (tree, segment)
+enum : int32_t { SEL_HIST = 0, SEL_COMPACT = 1, SEL_GATHERED = 2, SEL_DONE = 3 };
+
+struct SelState {
+    uint64_t pfx_hi;   // prefix of the 96-bit key found so far (top nbits valid)
+    uint32_t pfx_lo;
+    int32_t nbits;
+    int64_t rank;      // rank of the target among the keys that match the prefix
+    int64_t cnt;       // number of keys that match the prefix
+    int32_t mode;
+    int32_t chosen;    // chosen try (Alg. 2)
+    double best_s2;    // Alg. 2 running best spread
+    double s1;         // Alg. 2 scratch: sum of projections of the current try
+};
+
+struct Ent {           // one pruning candidate: point index and bounds on its squared distance
+    int32_t idx;
+    float lb;
+    float ub;
+    int32_t pad;
+};
+
+
+struct Cand {          // a key gathered for the in-block median select
+    uint64_t hi;
+    uint32_t lo;
+    uint32_t pad;
+};
+
+struct LargeBufs {     // temporaries of the multi-block level path
+    uint64_t *keys;
+    double *praw;
+    SelState *state;
+    uint32_t *hist;
+    Cand *cand;
+    uint32_t *cand_cnt;
+    uint32_t *lcount;
+    double *part;
+};
+
+struct TileJob {       // one MFMA tile: A rows x B rows (<= 32*MB each) of one tree
+    int64_t a_off;     // first A row (position in the per-tree A arrays)
+    int64_t b_off;     // first B row (position in the per-tree leaf-ordered arrays)
+    int32_t a_rows;
+    int32_t b_rows;
+    int32_t tree;
+    int32_t same;      // 1: A and B are the same positions (all-points diagonal tile)
+};
+
+// read-only view of a forest for the kNN launchers
+struct ForestView {
+    int64_t n, H;
+    int d, T, n0, n_try, L, prec, dp, max_leaf, job_mb;
+    const float *X, *R, *centroid;
+    const double *split;
+    const int32_t *chosen, *perm, *leaf_of, *heap_leaf;
+    const void *Xc;
+    const float2 *nrm;
+    const LeafDesc *leaves;
+    int64_t nleaf;
+    const TileJob *jobs;
+    int64_t n_jobs_tree;
+    unsigned long long *stats;
+};
+ForestView view(const rpf_forest *f);
+
+rpf_status fail(rpf_status st, const std::string &msg);
+rpf_status check_hip(hipError_t e, const char *what);
+void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
+// records the first failing launch of the calling thread (name + HIP error); with
+// RPF_SYNC_CHECK=1 in the environment it also synchronises after every launch
+void launch_check(hipStream_t s, const char *name);
+std::string take_launch_error();
+
+// ---------------------------------------------------------------- order-preserving keys
+
+__host__ __device__ inline uint64_t key_of(double p) {
+    uint64_t b;
+    __builtin_memcpy(&b, &p, 8);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__host__ __device__ inline double val_of(uint64_t u) {
+    uint64_t b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    double p;
+    __builtin_memcpy(&p, &b, 8);
+    return p;
+}
+
+__device__ inline bool key_less(uint64_t hi, uint32_t lo, uint64_t phi, uint32_t plo) {
+    return hi < phi || (hi == phi && lo < plo);
+}
+
+__device__ inline unsigned __int128 key96(uint64_t hi, uint32_t lo) {
+    return ((unsigned __int128)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+__device__ inline int mask_rank(uint64_t mask) {  // set bits of mask below this lane
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+__device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ inline float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// ---------------------------------------------------------------- canonical arithmetic
+
+// Projection of row x onto r (r usually staged in LDS) by an aligned group of 8 lanes;
+// every lane of the group returns p.  VEC: d % 4 == 0 and x, r 16-byte aligned.
+template <bool VEC>
+__device__ inline double group8_dot64(const float *__restrict__ x, const float *__restrict__ r,
+                                      int d, int g) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (VEC) {
+        for (int j = 4 * g; j < d; j += 32) {
+            float4 xv = *reinterpret_cast<const float4 *>(x + j);
+            float4 rv = *reinterpret_cast<const float4 *>(r + j);
+            s0 = s0 + (double)xv.x * (double)rv.x;
+            s1 = s1 + (double)xv.y * (double)rv.y;
+            s2 = s2 + (double)xv.z * (double)rv.z;
+            s3 = s3 + (double)xv.w * (double)rv.w;
+        }
+    } else {
+        for (int j = 4 * g; j < d; j += 32) {
+            s0 = s0 + (double)x[j] * (double)r[j];
+            if (j + 1 < d) s1 = s1 + (double)x[j + 1] * (double)r[j + 1];
+            if (j + 2 < d) s2 = s2 + (double)x[j + 2] * (double)r[j + 2];
+            if (j + 3 < d) s3 = s3 + (double)x[j + 3] * (double)r[j + 3];
+        }
+    }
+    double v = (s0 + s1) + (s2 + s3);
+    v = v + shfl_xor_d(v, 1);
+    v = v + shfl_xor_d(v, 2);
+    v = v + shfl_xor_d(v, 4);
+    return v + 0.0;
+}
+
+template <bool VEC>
+__device__ inline double group8_dist64(const float *__restrict__ a, const float *__restrict__ b,
+                                       int d, int g) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int j = 4 * g; j < d; j += 32) {
+        if (VEC) {
+            float4 av = *reinterpret_cast<const float4 *>(a + j);
+            float4 bv = *reinterpret_cast<const float4 *>(b + j);
+            double e0 = (double)av.x - (double)bv.x, e1 = (double)av.y - (double)bv.y;
+            double e2 = (double)av.z - (double)bv.z, e3 = (double)av.w - (double)bv.w;
+            s0 = __builtin_fma(e0, e0, s0);
+            s1 = __builtin_fma(e1, e1, s1);
+            s2 = __builtin_fma(e2, e2, s2);
+            s3 = __builtin_fma(e3, e3, s3);
+        } else {
+            double e0 = (double)a[j] - (double)b[j];
+            s0 = __builtin_fma(e0, e0, s0);
+            if (j + 1 < d) { double e = (double)a[j + 1] - (double)b[j + 1]; s1 = __builtin_fma(e, e, s1); }
+            if (j + 2 < d) { double e = (double)a[j + 2] - (double)b[j + 2]; s2 = __builtin_fma(e, e, s2); }
+            if (j + 3 < d) { double e = (double)a[j + 3] - (double)b[j + 3]; s3 = __builtin_fma(e, e, s3); }
+        }
+    }
+    double v = (s0 + s1) + (s2 + s3);
+    v = v + shfl_xor_d(v, 1);
+    v = v + shfl_xor_d(v, 2);
+    v = v + shfl_xor_d(v, 4);
+    return v;
+}
+
+template <bool VEC>
+__device__ inline float group8_dist32(const float *__restrict__ a, const float *__restrict__ b,
+                                      int d, int g) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    for (int j = 4 * g; j < d; j += 32) {
+        if (VEC) {
+            float4 av = *reinterpret_cast<const float4 *>(a + j);
+            float4 bv = *reinterpret_cast<const float4 *>(b + j);
+            float e0 = av.x - bv.x, e1 = av.y - bv.y, e2 = av.z - bv.z, e3 = av.w - bv.w;
+            s0 = __builtin_fmaf(e0, e0, s0);
+            s1 = __builtin_fmaf(e1, e1, s1);
+            s2 = __builtin_fmaf(e2, e2, s2);
+            s3 = __builtin_fmaf(e3, e3, s3);
+        } else {
+            float e0 = a[j] - b[j];
+            s0 = __builtin_fmaf(e0, e0, s0);
+            if (j + 1 < d) { float e = a[j + 1] - b[j + 1]; s1 = __builtin_fmaf(e, e, s1); }
+            if (j + 2 < d) { float e = a[j + 2] - b[j + 2]; s2 = __builtin_fmaf(e, e, s2); }
+            if (j + 3 < d) { float e = a[j + 3] - b[j + 3]; s3 = __builtin_fmaf(e, e, s3); }
+        }
+    }
+    float v = (s0 + s1) + (s2 + s3);
+    v = v + shfl_xor_f(v, 1);
+    v = v + shfl_xor_f(v, 2);
+    v = v + shfl_xor_f(v, 4);
+    return v;
+}
+
+// ---------------------------------------------------------------- host-side launch helpers
+
+struct Prof;  // per-kernel event timing (rpf_api.hip)
+void prof_begin(hipStream_t s, const char *name, double bytes, double flops, void **tok);
+void prof_end(hipStream_t s, void *tok);
+
+struct ProfScope {
+    hipStream_t s;
+    void *tok = nullptr;
+    ProfScope(hipStream_t s_, const char *name, double bytes = 0, double flops = 0) : s(s_) {
+        prof_begin(s, name, bytes, flops, &tok);
+    }
+    ~ProfScope() { prof_end(s, tok); }
+};
+
+}  // namespace rpf

@@ -1,0 +1,227 @@
+"""ctypes binding of the rpForests HIP library (include/rpf.h).
+
+Argument marshalling only: every step of the path runs in the library's kernels.  Torch
+tensors provide device memory and the current HIP stream.  The library must be built
+(`python -m paper_1812_11689_amd.build`); loading fails loudly when it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpf.so")
+
+RPF_OK, RPF_EINVAL, RPF_ENOMEM, RPF_EDEVICE, RPF_EBUSY, RPF_ENOTREADY, RPF_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+_STATUS = {0: "RPF_OK", -1: "RPF_EINVAL", -2: "RPF_ENOMEM", -3: "RPF_EDEVICE", -4: "RPF_EBUSY",
+           -5: "RPF_ENOTREADY", -6: "RPF_EINTERNAL"}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "rpf_free", "rpf_tree_dump",
+           "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
+           "rpf_profile_read", "rpf_last_error"]
+
+
+class RpfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_trees", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32),
+                ("split_rule", ctypes.c_int32), ("dist_prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("directions_dev", ctypes.c_void_p), ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("n_trees", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("dist_prec", ctypes.c_int32), ("n_leaves", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
+
+
+class KnnStats(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("fallback_rows", ctypes.c_int64), ("reranked32", ctypes.c_int64),
+                ("reranked64", ctypes.c_int64)]
+
+
+class ProfileRecord(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double), ("algo_flops", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"rpForests HIP library not built: {path} is missing "
+                           "(run `python -m paper_1812_11689_amd.build`)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.rpf_depth.restype = i32
+    lib.rpf_depth.argtypes = [i64, i32]
+    lib.rpf_build.restype = i32
+    lib.rpf_build.argtypes = [vp, i64, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    lib.rpf_all_knn.restype = i32
+    lib.rpf_all_knn.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.rpf_query.restype = i32
+    lib.rpf_query.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.rpf_route.restype = i32
+    lib.rpf_route.argtypes = [vp, vp, i64, vp, vp]
+    lib.rpf_free.restype = i32
+    lib.rpf_free.argtypes = [vp]
+    lib.rpf_tree_dump.restype = i32
+    lib.rpf_tree_dump.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.rpf_forest_info.restype = i32
+    lib.rpf_forest_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.rpf_last_knn_stats.restype = i32
+    lib.rpf_last_knn_stats.argtypes = [vp, ctypes.POINTER(KnnStats), vp]
+    lib.rpf_profile_enable.restype = i32
+    lib.rpf_profile_enable.argtypes = [i32]
+    lib.rpf_profile_reset.restype = i32
+    lib.rpf_profile_reset.argtypes = []
+    lib.rpf_profile_read.restype = i32
+    lib.rpf_profile_read.argtypes = [ctypes.POINTER(ProfileRecord), i32, ctypes.POINTER(i32)]
+    lib.rpf_last_error.restype = ctypes.c_char_p
+    lib.rpf_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != RPF_OK:
+        raise RpfError(st, load().rpf_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def depth(n: int, leaf_size: int) -> int:
+    return load().rpf_depth(n, leaf_size)
+
+
+class Forest:
+    """A forest resident in device memory; owns its library handle."""
+
+    def __init__(self, handle, n, d, n_trees, leaf_size, n_try, L):
+        self._h = handle
+        self.n, self.d, self.n_trees, self.leaf_size, self.n_try, self.depth = n, d, n_trees, leaf_size, n_try, L
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("forest was freed")
+        return self._h
+
+    def all_knn(self, K: int, exclude_self: bool = True, stream=None):
+        idx = torch.empty((self.n, K), dtype=torch.int32, device="cuda")
+        dist = torch.empty((self.n, K), dtype=torch.float32, device="cuda")
+        _check(load().rpf_all_knn(self.handle, K, int(exclude_self), idx.data_ptr(), dist.data_ptr(),
+                                  _stream(stream)))
+        return idx, dist
+
+    def query(self, Q: torch.Tensor, K: int, stream=None, out=None):
+        Q = _dev(Q, torch.float32)
+        m = Q.shape[0]
+        if out is None:
+            idx = torch.empty((m, K), dtype=torch.int32, device="cuda")
+            dist = torch.empty((m, K), dtype=torch.float32, device="cuda")
+        else:
+            idx, dist = out
+        _check(load().rpf_query(self.handle, Q.data_ptr(), m, K, idx.data_ptr(), dist.data_ptr(), _stream(stream)))
+        return idx, dist
+
+    def route(self, Q: torch.Tensor, stream=None):
+        Q = _dev(Q, torch.float32)
+        out = torch.empty((self.n_trees, Q.shape[0]), dtype=torch.int32, device="cuda")
+        _check(load().rpf_route(self.handle, Q.data_ptr(), Q.shape[0], out.data_ptr(), _stream(stream)))
+        return out
+
+    def tree_dump(self, t: int, stream=None):
+        H = (1 << self.depth) - 1
+        split = torch.empty(max(H, 1), dtype=torch.float64, device="cuda")
+        sidx = torch.empty(max(H, 1), dtype=torch.int32, device="cuda")
+        chosen = torch.empty(max(H, 1), dtype=torch.int32, device="cuda")
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        leaf_of = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(load().rpf_tree_dump(self.handle, t, split.data_ptr(), sidx.data_ptr(), chosen.data_ptr(),
+                                    perm.data_ptr(), leaf_of.data_ptr(), _stream(stream)))
+        return dict(split=split[:H], split_idx=sidx[:H], chosen=chosen[:H], perm=perm, leaf_of=leaf_of)
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().rpf_forest_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def knn_stats(self, stream=None) -> dict:
+        st = KnnStats()
+        _check(load().rpf_last_knn_stats(self.handle, ctypes.byref(st), _stream(stream)))
+        return {k: getattr(st, k) for k, _ in KnnStats._fields_}
+
+    def free(self):
+        if self._h is not None:
+            _check(load().rpf_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
+          dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None) -> Forest:
+    """Grow a forest over X (float32 [n][d] on the device) with the given directions
+    (float32 [n_trees][2^L-1][n_try][d] on the device, L = depth(n, leaf_size))."""
+    X = _dev(X, torch.float32)
+    n, d = X.shape
+    L = depth(n, leaf_size) if n >= 1 and leaf_size >= 1 else 0
+    dptr = None
+    if directions is not None:
+        directions = _dev(directions, torch.float32)
+        dptr = directions.data_ptr()
+    p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
+               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+               directions_dev=dptr, mem_budget_bytes=mem_budget_bytes)
+    h = ctypes.c_void_p()
+    _check(load().rpf_build(X.data_ptr(), n, d, ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+    return Forest(h, n, d, n_trees, leaf_size, n_try, L)
+
+
+def profile_enable(on: bool = True):
+    _check(load().rpf_profile_enable(int(on)))
+
+
+def profile_reset():
+    _check(load().rpf_profile_reset())
+
+
+def profile_read() -> dict:
+    cap = 64
+    recs = (ProfileRecord * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(load().rpf_profile_read(recs, cap, ctypes.byref(cnt)))
+    out = {}
+    for r in recs[: min(cnt.value, cap)]:
+        out[r.name.decode()] = dict(launches=r.launches, total_ms=r.total_ms, algo_bytes=r.algo_bytes,
+                                    algo_flops=r.algo_flops)
+    return out

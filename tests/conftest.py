@@ -3,6 +3,10 @@ import sys
 
 import pytest
 
+# attribute any device error to the launch that caused it (the library synchronises after
+# every launch when this is set; the benchmark does not set it)
+os.environ.setdefault("RPF_SYNC_CHECK", "1")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -1,0 +1,104 @@
+"""GPU parity of the candidate stage (Alg. 3): neighbour indices bit-exact against the
+oracle (ranked by the binary64 distance, ties by index) and distances within 1e-5
+relative, for binary32, bfloat16 and float16 tiles, all-points and external queries."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.helpers import problem
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+def _gpu_forest(x, R, T, n0, n_try=1, prec="fp32"):
+    from paper_1812_11689_amd import rpf
+    X = torch.from_numpy(x).cuda()
+    Rd = torch.from_numpy(np.ascontiguousarray(R[:T])).cuda()
+    return rpf.build(X, T, n0, Rd, n_try=n_try, dist_prec=prec)
+
+
+def _compare(gi, gd, ri, rd):
+    np.testing.assert_array_equal(gi, ri)
+    fin = np.isfinite(rd)
+    assert np.array_equal(np.isfinite(gd), fin)
+    np.testing.assert_allclose(gd[fin], rd[fin], rtol=RTOL, atol=0)
+
+
+ALL = [
+    # name, n, d, T, n0, K, prec, kind, dup, excl
+    ("mixture_10k_fp32", 10_000, 16, 4, 50, 10, "fp32", "mixture", 0, 1),
+    ("mixture_10k_bf16", 10_000, 16, 4, 50, 10, "bf16", "mixture", 0, 1),
+    ("mixture_10k_fp16", 10_000, 16, 4, 50, 10, "fp16", "mixture", 0, 1),
+    ("aniso_d128_fp32", 20_000, 128, 4, 256, 20, "fp32", "aniso", 0, 1),
+    ("aniso_d128_bf16", 20_000, 128, 4, 256, 20, "bf16", "aniso", 0, 1),
+    ("quant_d784_bf16", 4000, 784, 3, 200, 10, "bf16", "quant", 0, 1),
+    ("include_self", 3000, 8, 3, 40, 5, "fp32", "mixture", 0, 0),
+    ("duplicates", 6000, 8, 3, 30, 8, "fp32", "mixture", 5, 1),
+    ("d33", 4000, 33, 3, 40, 7, "fp16", "mixture", 0, 1),
+    ("wide_exponents", 3000, 24, 3, 50, 6, "fp32", "wide", 0, 1),
+    ("k_above_leaf", 2000, 6, 3, 30, 60, "fp32", "mixture", 0, 1),
+    ("single_leaf", 300, 5, 2, 300, 9, "bf16", "mixture", 0, 1),
+    ("tiny", 40, 3, 2, 4, 3, "fp32", "mixture", 0, 1),
+    ("k1", 5000, 10, 5, 20, 1, "fp16", "mixture", 0, 1),
+]
+
+
+@pytest.mark.parametrize("case", ALL, ids=[c[0] for c in ALL])
+def test_all_knn_matches_oracle(case):
+    name, n, d, T, n0, K, prec, kind, dup, excl = case
+    print(f"[all_knn] {name} n={n} d={d} T={T} n0={n0} K={K} {prec}", flush=True)
+    x, R = problem(n, d, T, n0, seed=len(name) + 100, kind=kind, dup_every=dup)
+    ref = oracle.build_forest(x, R, T, n0)
+    ri, rd = oracle.all_knn(ref, K, exclude_self=bool(excl))
+    f = _gpu_forest(x, R, T, n0, prec=prec)
+    gi, gd = f.all_knn(K, exclude_self=bool(excl))
+    torch.cuda.synchronize()
+    _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
+    st = f.knn_stats()
+    print(f"    stats {st}", flush=True)
+    f.free()
+
+
+QUERY = [
+    ("q_fp32", 12_000, 16, 4, 50, 10, "fp32", 2000),
+    ("q_bf16", 12_000, 64, 4, 100, 10, "bf16", 1500),
+    ("q_fp16", 12_000, 96, 5, 256, 20, "fp16", 1000),
+    ("q_one", 5000, 16, 3, 30, 5, "fp32", 1),
+]
+
+
+@pytest.mark.parametrize("case", QUERY, ids=[c[0] for c in QUERY])
+def test_query_matches_oracle(case):
+    name, n, d, T, n0, K, prec, m = case
+    print(f"[query] {name} n={n} d={d} T={T} n0={n0} K={K} m={m} {prec}", flush=True)
+    x, R = problem(n, d, T, n0, seed=len(name) + 200)
+    q, _ = problem(m, d, 1, n0, seed=len(name) + 300)
+    q[: m // 10] *= 3.0  # some outliers
+    ref = oracle.build_forest(x, R, T, n0)
+    ri, rd = oracle.query_knn(ref, q, K)
+    f = _gpu_forest(x, R, T, n0, prec=prec)
+    gi, gd = f.query(torch.from_numpy(q).cuda(), K)
+    torch.cuda.synchronize()
+    _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
+    f.free()
+
+
+def test_all_knn_twice_bit_identical():
+    x, R = problem(9000, 32, 4, 64, seed=77)
+    f = _gpu_forest(x, R, 4, 64, prec="bf16")
+    a = f.all_knn(12)
+    b = f.all_knn(12)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_single_leaf_is_brute_force():
+    # leaf size >= n: one leaf per tree, the forest result is the exact kNN
+    x, R = problem(500, 6, 2, 500, seed=31)
+    f = _gpu_forest(x, R, 2, 500)
+    gi, gd = f.all_knn(10)
+    bi, bd = oracle.bruteforce(x, x, 10, np.arange(500))
+    _compare(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd)
