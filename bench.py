@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the rpForests kNN path on one MI355X.
+
+One step = the whole hot path on one batch: grow the forest (rpf_build) over the
+1M x 128 anisotropic Gaussian mixture (T = 32 trees, leaf size 256) and find the K = 20
+nearest neighbours of every point among the union of its leaves (rpf_all_knn), then
+release the forest.  Inputs are resident in device memory before the timed region.
+
+Prints one JSON line: whole-job throughput in queries/s (points whose exact top-K over
+the leaf union is produced per second) with binary32 tiles, the same with bfloat16 tiles
+plus re-rank, the recall against exact brute force on a sample of points, the roofline
+of the dominant kernel (timed with HIP events on the launch stream, inside the library)
+and the CPU oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kNN queries/s at ≥0.99 recall, FP32 vs BF16+rerank; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=None, help="fewer points (same recipe), for quick checks")
+    ap.add_argument("--recall-sample", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--cpu-trees", type=int, default=0, help="trees for the CPU baseline (0 = all)")
+    return ap.parse_args()
+
+
+def exact_knn_sample(X, pts, K):
+    """Exact K nearest neighbours (excluding self) of the sampled points, by binary64
+    distances on the device -- the ground truth of the recall measurement."""
+    import torch
+    Xd = X.double()
+    nrm = (Xd * Xd).sum(1)
+    out = []
+    for s in range(0, len(pts), 256):
+        p = pts[s:s + 256]
+        q = Xd[p]
+        D = nrm[p][:, None] + nrm[None, :] - 2.0 * (q @ Xd.T)
+        D[torch.arange(len(p)), p] = float("inf")
+        out.append(torch.topk(D, K, dim=1, largest=False).indices)
+    return torch.cat(out).cpu().numpy()
+
+
+def recall_of(found, truth):
+    hit = 0
+    for f, t in zip(found, truth):
+        hit += len(set(f.tolist()) & set(t.tolist()))
+    return hit / truth.size
+
+
+def roofline(prof):
+    best = None
+    for name, r in prof.items():
+        if r["algo_bytes"] <= 0 and r["algo_flops"] <= 0:
+            continue
+        if best is None or r["total_ms"] > prof[best]["total_ms"]:
+            best = name
+    if best is None:
+        return None, None
+    r = prof[best]
+    avg_s = r["total_ms"] / r["launches"] / 1e3
+    if r["algo_flops"] > 0:
+        peak = BF16_MFMA_PEAK_TFLOPS if r.get("prec") == "bf16" else FP32_MFMA_PEAK_TFLOPS
+        ach = r["algo_flops"] / r["launches"] / avg_s / 1e12
+        return best, {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                      "frac": round(ach / peak, 4), "traffic": None}
+    ach = r["algo_bytes"] / r["launches"] / avg_s / 1e9
+    return best, {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
+                                   "by trees is a design note only)"}))
+        sys.exit(2)
+    import torch
+    from paper_1812_11689_amd import rpf
+    from paper_1812_11689_amd import workloads as W
+
+    t0 = time.time()
+    w = W.make_config(2, n=args.n)
+    n, d = w.x.shape
+    T, n0, K = w.n_trees, w.leaf_size, w.k
+    L = rpf.depth(n, n0)
+    R = W.directions(w.dir_seed, T, (1 << L) - 1, 1, d)
+    X = torch.from_numpy(w.x).cuda()
+    Rd = torch.from_numpy(R).cuda()
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    print(f"# workload {w.name}: n={n} d={d} T={T} n0={n0} K={K} L={L} (generated in {gen_s:.1f}s)",
+          file=sys.stderr, flush=True)
+
+    def step(prec):
+        f = rpf.build(X, T, n0, Rd, dist_prec=prec)
+        idx, dist = f.all_knn(K)
+        f.free()
+        return idx, dist
+
+    def measure(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        rpf.profile_reset()
+        rpf.profile_enable(True)
+        times = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            idx, dist = step(prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        rpf.profile_enable(False)
+        prof = rpf.profile_read()
+        return idx, dist, elapsed, times, prof
+
+    idx32, _, el32, times32, prof32 = measure("fp32", args.steps, args.warmup)
+    print(f"# fp32: {el32 / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    res_bf16 = None
+    if not args.no_bf16:
+        idx16, _, el16, times16, prof16 = measure("bf16", args.steps, 1)
+        print(f"# bf16: {el16 / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        same = bool(torch.equal(idx16, idx32))
+        res_bf16 = dict(value=round(n * args.steps / el16, 1), ms_per_step=round(el16 / args.steps * 1e3, 3),
+                        identical_to_fp32=same,
+                        breakdown_ms_per_step={k: round(v["total_ms"] / args.steps, 3) for k, v in
+                                               sorted(prof16.items(), key=lambda kv: -kv[1]["total_ms"])})
+
+    # recall against exact brute force on a seeded sample of points
+    rng = np.random.default_rng(W.SEED_BASE + 300 + 2)
+    pts = np.sort(rng.choice(n, size=min(args.recall_sample, n), replace=False))
+    truth = exact_knn_sample(X, torch.from_numpy(pts).cuda(), K)
+    recall = recall_of(idx32.cpu().numpy()[pts], truth)
+
+    for name, r in prof32.items():
+        r["prec"] = "fp32"
+    dom, roof = roofline(prof32)
+    breakdown = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(prof32.items(), key=lambda kv: -kv[1]["total_ms"])}
+
+    f = rpf.build(X, T, n0, Rd, dist_prec="fp32")
+    f.all_knn(K)
+    st = f.knn_stats()
+    f.free()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, R, pts[:500], K, args.cpu_trees)
+
+    ms = el32 / args.steps * 1e3
+    line = {
+        "metric": METRIC,
+        "value": round(n * args.steps / el32, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "d": d, "n_trees": T, "leaf_size": n0, "K": K,
+                   "tile_prec": "fp32", "split_projection": "f64", "rerank": "fp32+f64"},
+        "recall": round(recall, 5),
+        "step_ms_p50": round(float(np.percentile(times32, 50)) * 1e3, 3),
+        "step_ms_p99": round(float(np.percentile(times32, 99)) * 1e3, 3),
+        "bf16_rerank": res_bf16,
+        "knn_stats": st,
+        "breakdown_ms_per_step": breakdown,
+        "roofline_kernel": dom,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, R, sample_pts, K, cpu_trees):
+    """The oracle as it stands, on the host cores: the forest build timed in full on all n
+    points (all T trees, or `cpu_trees` of them scaled by T/cpu_trees), plus all-points kNN
+    timed on a seeded sample of points and extrapolated linearly to n."""
+    import oracle
+    oracle.build(force=False)
+    n = w.x.shape[0]
+    T = w.n_trees if not cpu_trees else min(cpu_trees, w.n_trees)
+    t0 = time.perf_counter()
+    f = oracle.build_forest(w.x, R, T, w.leaf_size)
+    t_build = (time.perf_counter() - t0) * (w.n_trees / T)
+    t0 = time.perf_counter()
+    oracle.all_knn(f, K, points=sample_pts)
+    t_knn = (time.perf_counter() - t0) * (n / len(sample_pts)) * (w.n_trees / T)
+    return {"value": round(n / (t_build + t_knn), 1), "unit": "queries/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"build of {T} of {w.n_trees} trees on all {n} points (scaled by {w.n_trees}/{T}) + "
+                      f"kNN of {len(sample_pts)} sampled points extrapolated to {n}",
+            "build_s": round(t_build, 2), "knn_s_extrapolated": round(t_knn, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -9,7 +9,7 @@ import importlib
 
 
 def __getattr__(name):
-    if name in ("rpf", "workloads"):
+    if name in ("rpf", "workloads", "build"):  # submodules (`build` compiles the library)
         return importlib.import_module(f"{__name__}.{name}")
     mod = importlib.import_module(f"{__name__}.rpf")
     return getattr(mod, name)

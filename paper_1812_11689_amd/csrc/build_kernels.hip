@@ -18,27 +18,6 @@ namespace rpf {
 
 // ================================================================ small segments: fused level
 
-__device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &excl, uint32_t &total) {
-    // 256 threads = 4 waves
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) s_w[w] = x;
-    __syncthreads();
-    uint32_t wb = 0, tot = 0;
-    for (int k = 0; k < 4; k++) {
-        uint32_t c = s_w[k];
-        if (k < w) wb += c;
-        tot += c;
-    }
-    excl = wb + x - v;
-    total = tot;
-    __syncthreads();
-}
-
 // canon_sum over s[0..m) in place (s has room for the power-of-two padding P2 >= m)
 __device__ inline double block_canon_sum(double *s, int m) {
     int P2 = 1;
@@ -637,22 +616,38 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
     const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
     const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
     float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
-    extern __shared__ __align__(16) float s_mu[];  // dp floats + 4*1024 partial sums
+    extern __shared__ __align__(16) float s_mu[];  // dp floats, then 4 x dp partial sums
     const int t = blockIdx.y, tid = threadIdx.x;
     const LeafDesc lf = leaves[blockIdx.x];
     const int32_t *pp = perm + (int64_t)t * n + lf.off;
     for (int i = tid; i < lf.size; i += 256) leaf_of[(int64_t)t * n + pp[i]] = lf.heap;
-    // mean: thread j sums column j over the members in order
+    // mean: wave w sums rows w, w+4, ... (lane j holds columns j, j+64, ...), then the four
+    // partial sums are added in wave order -- a fixed order, so the centroid is reproducible
+    const int lane = tid & 63, wv = tid >> 6;
+    float *s_part = s_mu + dp;  // [4][dp]
+    for (int j0 = 0; j0 < dp; j0 += 64 * 8) {
+        float acc[8];
+        for (int q = 0; q < 8; q++) acc[q] = 0.f;
+        for (int i = wv; i < lf.size; i += 4) {
+            const float *x = X + (int64_t)pp[i] * d;
+            for (int q = 0; q < 8; q++) {
+                const int j = j0 + 64 * q + lane;
+                if (j < d) acc[q] += x[j];
+            }
+        }
+        for (int q = 0; q < 8; q++) {
+            const int j = j0 + 64 * q + lane;
+            if (j < dp) s_part[wv * dp + j] = acc[q];
+        }
+    }
+    __syncthreads();
     for (int j = tid; j < dp; j += 256) {
-        float s = 0.f;
-        if (j < d)
-            for (int i = 0; i < lf.size; i++) s += X[(int64_t)pp[i] * d + j];
-        float mu = j < d ? s / (float)lf.size : 0.f;
+        const float sum = ((s_part[j] + s_part[dp + j]) + s_part[2 * dp + j]) + s_part[3 * dp + j];
+        const float mu = j < d ? sum / (float)lf.size : 0.f;
         s_mu[j] = mu;
         if (j < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + j] = mu;
     }
     __syncthreads();
-    const int lane = tid & 63, wv = tid >> 6;
     for (int i = wv; i < lf.size; i += 4) {
         const float *x = X + (int64_t)pp[i] * d;
         T *out = Xc + ((int64_t)t * n + lf.off + i) * dp;
@@ -808,7 +803,7 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm) {
     dim3 grid(nleaf, T);
-    const size_t lds = sizeof(float) * (size_t)dp;
+    const size_t lds = sizeof(float) * 5 * (size_t)dp;
     if (prec == RPF_DIST_BF16)
         leaf_finalize<__bf16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
     else if (prec == RPF_DIST_FP16)

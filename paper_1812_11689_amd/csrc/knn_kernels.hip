@@ -286,6 +286,194 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     }
 }
 
+// All-points tile of one leaf whose rows all fit (m <= 32 NB): the Gram matrix is symmetric,
+// so only blocks (i, j) with i <= j run on MFMA and an off-diagonal block emits both
+// (row -> col) and (col -> row).  Wave w owns block rows w and nb-1-w (nb + 1 blocks per
+// wave), which balances the triangle; both operands come from the same LDS tile.
+template <int NB, int PREC>
+__global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
+    const TileJob *__restrict__ jobs, const void *__restrict__ A_, int dp, int64_t stride_tree,
+    const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, const float *__restrict__ tau,
+    int exclude_self, int32_t *__restrict__ cnt, Ent *__restrict__ ent, int cap) {
+    using C = TileCfg<PREC>;
+    using T = typename C::T;
+    constexpr int M = 32 * NB;
+    constexpr int NW = NB >= 2 ? NB / 2 : 1;
+    constexpr int NT = 64 * NW;
+    constexpr int SLOTS = NB >= 2 ? NB + 1 : 1;
+    __shared__ __align__(16) T s_a[M * C::LDW];
+    __shared__ float s_n[M], s_r[M], s_phi[M], s_tau[M];
+    __shared__ int32_t s_pt[M];
+    __shared__ uint32_t s_cnt[M], s_base[M];
+    __shared__ float s_max[2];
+
+    const TileJob job = jobs[blockIdx.x];
+    const int t = job.tree;
+    const int m = job.a_rows;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const T *A = reinterpret_cast<const T *>(A_) + (t * stride_tree + job.a_off) * dp;
+    const float2 *an = nrm + t * stride_tree + job.a_off;
+    const int32_t *ap = pt + t * stride_tree + job.a_off;
+    for (int r = tid; r < M; r += NT) {
+        if (r < m) {
+            const float2 q = an[r];
+            s_n[r] = q.x;
+            s_r[r] = q.y;
+            const int p = ap[r];
+            s_pt[r] = p;
+            s_tau[r] = tau ? tau[p] : INFINITY;
+        } else {
+            s_n[r] = 0.f;
+            s_r[r] = 0.f;
+            s_pt[r] = -1;
+            s_tau[r] = -1.f;
+        }
+        s_cnt[r] = 0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        float mn = 0.f, mr = 0.f;
+        for (int r = lane; r < m; r += 64) {
+            mn = fmaxf(mn, s_n[r]);
+            mr = fmaxf(mr, s_r[r]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmaxf(mn, __shfl_xor(mn, o, 64));
+            mr = fmaxf(mr, __shfl_xor(mr, o, 64));
+        }
+        if (lane == 0) {
+            s_max[0] = mn;
+            s_max[1] = mr;
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < M; r += NT) {
+        const float tv = s_tau[r];
+        float phi;
+        if (!(tv < INFINITY)) {
+            phi = INFINITY;
+        } else if (tv < 0.f) {
+            phi = -INFINITY;
+        } else {
+            const float dmax = bc.c * (s_r[r] + s_max[1]) + bc.eta;
+            const float emax = bc.e * (s_n[r] + s_max[0]);
+            const float st = sqrtf(tv / (1.f - 1e-6f)) + dmax;
+            const float th = st * st + emax;
+            phi = (th - s_n[r]) + 1e-5f * (th + s_n[r] + s_max[0]) + 1e-30f;
+            if (!(s_r[r] < INFINITY) || !(s_max[1] < INFINITY)) phi = INFINITY;
+        }
+        s_phi[r] = phi;
+    }
+
+    const int nb = (m + 31) >> 5;
+    const int r1 = w, r2 = nb - 1 - w;
+    const bool wave_on = r1 <= r2;
+    const int len1 = nb - r1;
+    // slot sl of this wave -> Gram block (i, j), i <= j; -1 when unused
+    auto slot_block = [&](int sl, int &bi, int &bj) {
+        if (!wave_on) {
+            bi = bj = -1;
+        } else if (sl < len1) {
+            bi = r1;
+            bj = r1 + sl;
+        } else if (r2 > r1 && sl - len1 < nb - r2) {
+            bi = r2;
+            bj = r2 + (sl - len1);
+        } else {
+            bi = bj = -1;
+        }
+    };
+    f32x16 acc[SLOTS];
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; sl++)
+#pragma unroll
+        for (int v = 0; v < 16; v++) acc[sl][v] = 0.f;
+    const int fr = lane & 31;
+    const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
+    const int m_pad = nb << 5;
+    for (int k0 = 0; k0 < dp; k0 += C::KC) {
+        __syncthreads();
+        stage_rows<PREC>(s_a, A, m, m_pad, dp, k0, NT);
+        __syncthreads();
+        int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
+        kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
+        if (wave_on) {
+            for (int kk = 0; kk < kmax; kk += C::KSTEP) {
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; sl++) {
+                    int bi, bj;
+                    slot_block(sl, bi, bj);
+                    if (bi >= 0) {
+                        const T *pa = s_a + (32 * bi + fr) * C::LDW + kk + fk;
+                        const T *pb = s_a + (32 * bj + fr) * C::LDW + kk + fk;
+                        acc[sl] = mfma_step<PREC>(pa, pb, acc[sl]);
+                    }
+                }
+            }
+        }
+    }
+
+    for (int sweep = 0; sweep < 2; sweep++) {
+        if (wave_on) {
+            for (int sl = 0; sl < SLOTS; sl++) {  // rolled: one slot's accumulators at a time
+                int bi, bj;
+                slot_block(sl, bi, bj);
+                if (bi < 0) continue;
+                f32x16 cur = acc[0];
+#pragma unroll
+                for (int q = 1; q < SLOTS; q++)
+                    if (q == sl) cur = acc[q];
+                const bool diag = bi == bj;
+                const int col = 32 * bj + (lane & 31);
+                const bool colok = col < m;
+                const float ncol = s_n[col];
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    if (!colok || row >= m) continue;
+                    const float g = cur[v];
+                    const float nrow = s_n[row];
+                    // row -> col (every block; the diagonal skips the point itself)
+                    const bool f1 = __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] && !(exclude_self && row == col);
+                    // col -> row (off-diagonal blocks only: the diagonal block holds both orders)
+                    const bool f2 = !diag && __builtin_fmaf(-2.f, g, nrow) <= s_phi[col];
+                    if (!(f1 || f2)) continue;
+                    float lb, ub;
+                    pair_bounds(nrow, ncol, s_r[row], s_r[col], g, bc, lb, ub);
+                    for (int dir = 0; dir < 2; dir++) {
+                        const bool fd = dir == 0 ? f1 : f2;
+                        const int a = dir == 0 ? row : col;
+                        const int b = dir == 0 ? col : row;
+                        if (!fd || !(lb <= s_tau[a])) continue;
+                        if (sweep == 0) {
+                            atomicAdd(&s_cnt[a], 1u);
+                        } else {
+                            const uint32_t slot = s_base[a] + atomicAdd(&s_cnt[a], 1u);
+                            if (slot < (uint32_t)cap) {
+                                Ent e;
+                                e.idx = s_pt[b];
+                                e.lb = lb;
+                                e.ub = ub;
+                                e.pad = 0;
+                                ent[(int64_t)s_pt[a] * cap + slot] = e;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (sweep == 0) {
+            for (int r = tid; r < m; r += NT) {
+                const uint32_t c = s_cnt[r];
+                s_base[r] = c ? (uint32_t)atomicAdd(&cnt[s_pt[r]], (int32_t)c) : 0u;
+                s_cnt[r] = 0;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- wave-level selection
 
 // k-th smallest (0-based) of `c` 32-bit keys held in LDS (per-wave region), radix 8 bits.
@@ -336,23 +524,119 @@ __device__ inline uint32_t fkey(float f) {  // non-negative floats (and +inf) or
     return __float_as_uint(f);
 }
 
-// Phase I merge: tau(row) = K-th smallest ub among the first tree's pairs; keep lb <= tau.
-__global__ __launch_bounds__(256) void k_merge_init(int64_t nrows, int K, int32_t *__restrict__ cnt,
-                                                    const Ent *__restrict__ ent, int cap,
-                                                    float *__restrict__ tau, Ent *__restrict__ list,
-                                                    int32_t *__restrict__ lcnt, int lcap) {
-    __shared__ uint32_t s_v[4][512];
+// k-th smallest (0-based) of the flagged 32-bit keys held Q per lane, radix 8 bits
+template <int Q>
+__device__ inline uint32_t wave_kth_regs(const uint32_t (&v)[Q], const bool (&ok)[Q], int k, uint32_t *hist) {
+    const int lane = lane_id();
+    uint32_t prefix = 0, rank = (uint32_t)k;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = lane; b < 256; b += 64) hist[b] = 0;
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < Q; q++)
+            if (ok[q] && (shift == 24 || (v[q] >> (shift + 8)) == (prefix >> (shift + 8))))
+                atomicAdd(&hist[(v[q] >> shift) & 255u], 1u);
+        wave_sync();
+        const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+        const uint32_t sum = h0 + h1 + h2 + h3;
+        uint32_t x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const uint32_t excl = x - sum;
+        uint32_t mybin = 0xffffffffu, mybefore = 0;
+        if (excl <= rank && rank < excl + sum) {
+            uint32_t cc = excl;
+            const uint32_t hh[4] = {h0, h1, h2, h3};
+            for (int q = 0; q < 4; q++) {
+                if (rank < cc + hh[q]) {
+                    mybin = 4 * lane + q;
+                    mybefore = cc;
+                    break;
+                }
+                cc += hh[q];
+            }
+        }
+        const uint64_t who = __ballot(mybin != 0xffffffffu);
+        const int src = __builtin_ctzll(who);
+        prefix |= __shfl(mybin, src, 64) << shift;
+        rank -= __shfl(mybefore, src, 64);
+        wave_sync();
+    }
+    return prefix;
+}
+
+// Phase I merge (one wave per row).  The row's entries come from the first B trees, where
+// every index occurs at most once per tree, so the (K*B)-th smallest ub of the multiset is
+// an upper bound of tau = K-th smallest ub over distinct indices (ub of an index = its
+// smallest ub), and the entries with ub below it hold every index's minimal entry that
+// matters.  tau is computed exactly on that small set; the list keeps every entry with
+// lb <= tau (duplicates included: the final merge removes them).
+constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
+constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
+constexpr int kSetCap = 512;
+
+__global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int32_t *__restrict__ cnt,
+                                                     const Ent *__restrict__ ent, int cap, float *__restrict__ tau,
+                                                     Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap) {
+    __shared__ uint32_t s_u[4][kMergeCap];
     __shared__ uint32_t s_h[4][256];
+    __shared__ int32_t s_si[4][kSetCap];
+    __shared__ uint32_t s_su[4][kSetCap];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
     const int c0 = cnt[a];
-    const int c = c0 < cap ? c0 : cap;
     const Ent *e = ent + a * cap;
-    for (int i = lane; i < c; i += 64) s_v[w][i] = fkey(e[i].ub);
+    bool over = c0 > cap || c0 > kMergeCap;
+    const int c = over ? 0 : c0;
+    for (int i = lane; i < c; i += 64) s_u[w][i] = fkey(e[i].ub);
+    wave_sync();
+    const int kb = K * B;
+    uint32_t theta = 0xffffffffu;
+    if (c >= kb) theta = wave_kth_lds(s_u[w], c, kb - 1, s_h[w]);
+    // the small set S = {ub <= theta}
+    int ns = 0;
+    for (int base = 0; base < c; base += 64) {
+        const int i = base + lane;
+        const bool in = i < c && s_u[w][i] <= theta;
+        const uint64_t mk = __ballot(in);
+        const int pos = ns + mask_rank(mk);
+        if (in && pos < kSetCap) {
+            s_si[w][pos] = e[i].idx;
+            s_su[w][pos] = s_u[w][i];
+        }
+        ns += __popcll(mk);
+    }
     wave_sync();
     float tv = INFINITY;
-    if (c >= K) tv = __uint_as_float(wave_kth_lds(s_v[w], c, K - 1, s_h[w]));
+    if (ns > kSetCap) {
+        over = true;
+    } else {
+        // representatives: the entry of smallest (ub, position) among equal indices
+        uint32_t repv[kSetCap / 64];
+        bool rep[kSetCap / 64];
+        int nrep = 0;
+#pragma unroll
+        for (int q = 0; q < kSetCap / 64; q++) {
+            const int i = lane + 64 * q;
+            rep[q] = i < ns;
+            repv[q] = 0;
+            if (rep[q]) {
+                const int id = s_si[w][i];
+                const uint32_t u = s_su[w][i];
+                repv[q] = u;
+                for (int j = 0; j < ns; j++)
+                    if (s_si[w][j] == id && (s_su[w][j] < u || (s_su[w][j] == u && j < i))) {
+                        rep[q] = false;
+                        break;
+                    }
+            }
+            nrep += __popcll(__ballot(rep[q]));
+        }
+        if (nrep >= K) tv = __uint_as_float(wave_kth_regs<kSetCap / 64>(repv, rep, K - 1, s_h[w]));
+    }
     const float tp = tv * (1.f + 1e-6f);
     uint32_t kept = 0;
     for (int base = 0; base < c; base += 64) {
@@ -370,16 +654,19 @@ __global__ __launch_bounds__(256) void k_merge_init(int64_t nrows, int K, int32_
     }
     wave_sync();
     if (lane == 0) {
-        lcnt[a] = (c0 > cap) ? lcap + 1 : (int32_t)kept;
-        tau[a] = tp;
+        lcnt[a] = over ? lcap + 1 : (int32_t)kept;
+        tau[a] = over ? INFINITY : tp;
         cnt[a] = 0;
     }
 }
 
 // ---------------------------------------------------------------- final merge and rerank
 
-constexpr int kHT = 1024;      // per-row hash table for dedup
-constexpr int kMaxCand = 640;  // list + emissions per row handled by k_final
+constexpr int kFinalQ = 12;                // entries per lane
+constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
+constexpr int kHT = 1024;                  // per-row hash table (indices) for the dedup
+constexpr int kRCap = 512;                 // rerank set per row
+constexpr int kWCap = 256;                 // binary64 window per row
 
 struct FinalArgs {
     const Ent *list;
@@ -400,137 +687,135 @@ struct FinalArgs {
     unsigned long long *stats;  // [rows, fallback, reranked32, reranked64]
 };
 
+__device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
+    const int slot = atomicAdd(A.fb_cnt, 1);
+    A.fb_list[slot] = (int32_t)a;
+    atomicAdd(&A.stats[1], 1ull);
+}
+
+// One wave per result row, four rows per block.  Entries stay in registers; an LDS hash
+// of indices marks the first copy of every index (any copy's interval is valid for it).
 template <bool VEC>
-__global__ __launch_bounds__(64) void k_final(FinalArgs A, int64_t nrows) {
-    __shared__ int32_t s_key[kHT];
-    __shared__ uint32_t s_lb[kHT], s_ub[kHT];
-    __shared__ int32_t s_idx[kMaxCand];
-    __shared__ uint32_t s_v[kMaxCand];
-    __shared__ float s_lbv[kMaxCand];
-    __shared__ double s_d64[1024];
-    __shared__ int32_t s_widx[1024];
-    __shared__ uint32_t s_h[256];
-    extern __shared__ __align__(16) float s_q[];  // query row, d floats
-    const int lane = threadIdx.x;
-    const int64_t a = blockIdx.x;
+__global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
+    __shared__ int32_t s_key[4][kHT];
+    __shared__ int32_t s_r[4][kRCap];
+    __shared__ uint32_t s_d[4][kRCap];
+    __shared__ int32_t s_wi[4][kWCap];
+    __shared__ double s_wd[4][kWCap];
+    __shared__ uint32_t s_h[4][256];
+    extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
+    const int dq = (A.d + 3) & ~3;
+    float *s_q = s_qall + w * dq;
     const int K = A.K;
     const int c1 = A.lcnt[a], c2 = A.cnt[a];
-    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kMaxCand) {
-        if (lane == 0) {
-            const int slot = atomicAdd(A.fb_cnt, 1);
-            A.fb_list[slot] = (int32_t)a;
-            atomicAdd(&A.stats[1], 1ull);
-        }
+    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kFinalCap) {
+        if (lane == 0) push_fallback(A, a);
         return;
     }
-    for (int i = lane; i < kHT; i += 64) {
-        s_key[i] = -1;
-        s_lb[i] = 0u;
-        s_ub[i] = 0xffffffffu;
-    }
+    for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
     for (int j = lane; j < A.d; j += 64) s_q[j] = A.Qr[a * A.d + j];
     wave_sync();
-    for (int i = lane; i < c1 + c2; i += 64) {
-        const Ent e = i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)];
-        uint32_t h = ((uint32_t)e.idx * 2654435761u) >> 22;
-        while (true) {
-            const int old = atomicCAS(&s_key[h], -1, e.idx);
-            if (old == -1 || old == e.idx) {
-                atomicMax(&s_lb[h], fkey(e.lb));   // intersect the intervals of duplicates
-                atomicMin(&s_ub[h], fkey(e.ub));
-                break;
-            }
-            h = (h + 1) & (kHT - 1);
-        }
-    }
-    wave_sync();
+    int32_t eidx[kFinalQ];
+    uint32_t elb[kFinalQ], eub[kFinalQ];
+    bool first[kFinalQ];
     int nd = 0;
-    for (int base = 0; base < kHT; base += 64) {
-        const int i = base + lane;
-        const bool occ = s_key[i] >= 0;
-        const uint64_t mk = __ballot(occ);
-        if (occ) {
-            const int p = nd + mask_rank(mk);
-            s_idx[p] = s_key[i];
-            s_v[p] = s_ub[i];
-            s_lbv[p] = __uint_as_float(s_lb[i]);
+#pragma unroll
+    for (int q = 0; q < kFinalQ; q++) {
+        const int i = lane + 64 * q;
+        first[q] = false;
+        eidx[q] = -1;
+        elb[q] = eub[q] = 0;
+        if (i < c1 + c2) {
+            const Ent e = i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)];
+            eidx[q] = e.idx;
+            elb[q] = fkey(e.lb);
+            eub[q] = fkey(e.ub);
+            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> 22;
+            while (true) {
+                const int old = atomicCAS(&s_key[w][h], -1, e.idx);
+                if (old == -1) {
+                    first[q] = true;
+                    break;
+                }
+                if (old == e.idx) break;
+                h = (h + 1) & (kHT - 1);
+            }
         }
-        nd += __popcll(mk);
+        nd += __popcll(__ballot(first[q]));
     }
     wave_sync();
     float tv = INFINITY;
-    if (nd >= K) tv = __uint_as_float(wave_kth_lds(s_v, nd, K - 1, s_h));
-    const float tp = tv * (1.f + 1e-6f);
-    // rerank set R = {lb <= tau'} (compacted in place)
-    int nr = 0;
-    for (int base = 0; base < nd; base += 64) {
-        const int i = base + lane;
-        const bool keep = i < nd && s_lbv[i] <= tp;
-        const uint64_t mk = __ballot(keep);
-        const int idx = i < nd ? s_idx[i] : 0;
-        wave_sync();
-        if (keep) s_idx[nr + mask_rank(mk)] = idx;
+    if (nd >= K) tv = __uint_as_float(wave_kth_regs<kFinalQ>(eub, first, K - 1, s_h[w]));
+    const uint32_t tp = fkey(tv * (1.f + 1e-6f));
+    int nr = 0;  // rerank set R = {first copies with lb <= tau'}
+#pragma unroll
+    for (int q = 0; q < kFinalQ; q++) {
+        const bool in = first[q] && elb[q] <= tp;
+        const uint64_t mk = __ballot(in);
+        const int pos = nr + mask_rank(mk);
+        if (in && pos < kRCap) s_r[w][pos] = eidx[q];
         nr += __popcll(mk);
-        wave_sync();
     }
-    // canonical binary32 distances, 8 lanes per candidate
+    wave_sync();
+    if (nr > kRCap) {
+        if (lane == 0) push_fallback(A, a);
+        return;
+    }
     const int g = lane & 7, grp = lane >> 3;
     for (int base = 0; base < nr; base += 8) {
         const int i = base + grp;
-        const int b = s_idx[i < nr ? i : 0];
+        const int b = s_r[w][i < nr ? i : 0];
         const float D32 = group8_dist32<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
-        if (g == 0 && i < nr) s_v[i] = fkey(D32);
+        if (g == 0 && i < nr) s_d[w][i] = fkey(D32);
     }
     wave_sync();
     float d32k = INFINITY;
-    if (nr >= K) d32k = __uint_as_float(wave_kth_lds(s_v, nr, K - 1, s_h));
+    if (nr >= K) d32k = __uint_as_float(wave_kth_lds(s_d[w], nr, K - 1, s_h[w]));
     const float wcut = d32k * (1.f + A.win);
     int nw = 0;
     for (int base = 0; base < nr; base += 64) {
         const int i = base + lane;
-        const bool keep = i < nr && __uint_as_float(s_v[i]) <= wcut;
-        const uint64_t mk = __ballot(keep);
-        if (keep && nw + mask_rank(mk) < 1024) s_widx[nw + mask_rank(mk)] = s_idx[i];
+        const bool in = i < nr && __uint_as_float(s_d[w][i]) <= wcut;
+        const uint64_t mk = __ballot(in);
+        const int pos = nw + mask_rank(mk);
+        if (in && pos < kWCap) s_wi[w][pos] = s_r[w][i];
         nw += __popcll(mk);
     }
     wave_sync();
-    if (nw > 1024) {  // pathological window (massive distance ties): exhaustive path
-        if (lane == 0) {
-            const int slot = atomicAdd(A.fb_cnt, 1);
-            A.fb_list[slot] = (int32_t)a;
-            atomicAdd(&A.stats[1], 1ull);
-        }
+    if (nw > kWCap) {  // pathological window (massive distance ties): exhaustive path
+        if (lane == 0) push_fallback(A, a);
         return;
     }
     for (int base = 0; base < nw; base += 8) {
         const int i = base + grp;
-        const int b = s_widx[i < nw ? i : 0];
+        const int b = s_wi[w][i < nw ? i : 0];
         const double D64 = group8_dist64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
-        if (g == 0 && i < nw) s_d64[i] = D64;
+        if (g == 0 && i < nw) s_wd[w][i] = D64;
     }
     int P2 = 1;
     while (P2 < nw) P2 <<= 1;
     for (int i = nw + lane; i < P2; i += 64) {
-        s_d64[i] = INFINITY;
-        s_widx[i] = 0x7fffffff;
+        s_wd[w][i] = INFINITY;
+        s_wi[w][i] = 0x7fffffff;
     }
     wave_sync();
-    // bitonic sort of (D64, idx) ascending
-    for (int size = 2; size <= P2; size <<= 1) {
+    for (int size = 2; size <= P2; size <<= 1) {  // bitonic sort by (D64, index)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = lane; i < P2 / 2; i += 64) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
-                const double dl = s_d64[lo], dh = s_d64[hi];
-                const int il = s_widx[lo], ih = s_widx[hi];
+                const double dl = s_wd[w][lo], dh = s_wd[w][hi];
+                const int il = s_wi[w][lo], ih = s_wi[w][hi];
                 const bool gt = dl > dh || (dl == dh && il > ih);
                 if (gt == up) {
-                    s_d64[lo] = dh;
-                    s_d64[hi] = dl;
-                    s_widx[lo] = ih;
-                    s_widx[hi] = il;
+                    s_wd[w][lo] = dh;
+                    s_wd[w][hi] = dl;
+                    s_wi[w][lo] = ih;
+                    s_wi[w][hi] = il;
                 }
             }
             wave_sync();
@@ -538,8 +823,8 @@ __global__ __launch_bounds__(64) void k_final(FinalArgs A, int64_t nrows) {
     }
     for (int k = lane; k < K; k += 64) {
         const bool ok = k < nw;
-        A.out_idx[a * K + k] = ok ? s_widx[k] : -1;
-        A.out_dist[a * K + k] = ok ? (float)sqrt(s_d64[k]) : INFINITY;
+        A.out_idx[a * K + k] = ok ? s_wi[w][k] : -1;
+        A.out_dist[a * K + k] = ok ? (float)sqrt(s_wd[w][k]) : INFINITY;
     }
     if (lane == 0) {
         atomicAdd(&A.stats[0], 1ull);
@@ -727,9 +1012,9 @@ __global__ void k_group_fill(const int32_t *__restrict__ qleaf, int64_t m, const
     }
 }
 
-// one tile job per (A chunk of a non-empty group) x (B tile of the leaf); tree 0 -> list 0
+// one tile job per (A chunk of a non-empty group) x (B tile of the leaf); the first trees -> list 0
 __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int64_t nleaf,
-                            const LeafDesc *__restrict__ leaves, int TR, TileJob *__restrict__ jobs0,
+                            const LeafDesc *__restrict__ leaves, int TR, int nfirst, TileJob *__restrict__ jobs0,
                             TileJob *__restrict__ jobs1, int32_t *__restrict__ njobs) {
     const int t = blockIdx.y;
     for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < nleaf; li += (int64_t)gridDim.x * blockDim.x) {
@@ -746,8 +1031,9 @@ __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *_
                 j.b_rows = min(TR, lf.size - J * TR);
                 j.tree = t;
                 j.same = 0;
-                const int slot = atomicAdd(&njobs[t == 0 ? 0 : 1], 1);
-                (t == 0 ? jobs0 : jobs1)[slot] = j;
+                const bool first = t < nfirst;
+                const int slot = atomicAdd(&njobs[first ? 0 : 1], 1);
+                (first ? jobs0 : jobs1)[slot] = j;
             }
     }
 }
@@ -786,6 +1072,11 @@ __global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q,
 }
 
 // ================================================================ host launch sequences
+
+// Phase I trees: at most kFirstTrees, and K * B must leave room in the merge's small set
+static int first_trees(int T, int K) {
+    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K}));
+}
 
 static BoundCoef bound_coef(int prec, int d) {
     const double u32 = ldexp(1.0, -24);
@@ -886,14 +1177,56 @@ struct CandStage {
     const float *Qr;       // binary32 rows of the result rows
     const int32_t *row_leaf;  // [T][rows] heap ids (fallback)
     int excl;
+    double flops0, flops1;  // useful Gram flops of the Phase I / Phase II tiles (0 if unknown)
+    double bytes0, bytes1;  // tile-operand bytes of the two phases
+    bool sym;               // all-points with one tile per leaf: symmetric kernel
+    int B;                  // trees of Phase I
 };
+
+template <int NB, int PREC>
+static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
+                       const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau, int excl, int32_t *cnt,
+                       Ent *ent, int cap) {
+    if (njobs <= 0) return;
+    constexpr int NT = NB >= 2 ? 32 * NB : 64;
+    hipLaunchKernelGGL((k_tile_sym<NB, PREC>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt,
+                       bc, tau, excl, cnt, ent, cap);
+    launch_check(s, "k_tile_sym");
+}
+
+template <int PREC>
+static void sym_dispatch_nb(int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
+                            int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau,
+                            int excl, int32_t *cnt, Ent *ent, int cap) {
+    switch (NB) {
+    case 1: sym_launch<1, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
+    case 2: sym_launch<2, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
+    case 4: sym_launch<4, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
+    default: sym_launch<8, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
+    }
+}
+
+static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
+                         int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau,
+                         int excl, int32_t *cnt, Ent *ent, int cap) {
+    if (prec == RPF_DIST_BF16)
+        sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+    else if (prec == RPF_DIST_FP16)
+        sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+    else
+        sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+}
 
 static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
                                  float *out_dist, hipStream_t s) {
     Workspace ws(s);
     const int64_t rows = cs.rows;
-    const int cap = std::min(512, std::max(256, v.max_leaf));
-    const int lcap = 128;
+    // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
+    // threshold of the union of those leaves
+    const int lcap = 256;
+    const int cap1 = v.max_leaf * cs.B;
+    const int cap2 = kFinalCap - lcap;
+    const int cap = std::max(cap1, cap2);
     float *tau = ws.get<float>(rows * 4);
     int32_t *cnt = ws.get<int32_t>(rows * 4);
     Ent *ent = ws.get<Ent>((size_t)rows * cap * sizeof(Ent));
@@ -907,36 +1240,43 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     hipMemsetAsync(v.stats, 0, 32, s);
     const BoundCoef bc = bound_coef(v.prec, v.d);
     const int MB = v.job_mb;
-    const double tile_flops0 = 0, tile_flops1 = 0;
-    (void)tile_flops0;
-    (void)tile_flops1;
     {
-        ProfScope ps(s, "tile_phase1", 0, 0);
-        tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
-                      cs.a_dest, v.perm, bc, nullptr, cs.excl, cnt, ent, cap);
+        ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
+        if (cs.sym)
+            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, nullptr, cs.excl, cnt,
+                         ent, cap);
+        else
+            tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
+                          cs.a_dest, v.perm, bc, nullptr, cs.excl, cnt, ent, cap);
     }
     {
-        ProfScope ps(s, "merge_init", 0, 0);
-        hipLaunchKernelGGL(k_merge_init, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cnt, ent, cap,
-                           tau, list, lcnt, lcap);
-        launch_check(s, "k_merge_init");
+        ProfScope ps(s, "merge_first", 0, 0);
+        hipLaunchKernelGGL(k_merge_first, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B, cnt, ent,
+                           cap, tau, list, lcnt, lcap);
+        launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0) {
-        ProfScope ps(s, "tile_phase2", 0, 0);
-        tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
-                      cs.a_dest, v.perm, bc, tau, cs.excl, cnt, ent, cap);
+        ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
+        if (cs.sym)
+            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, tau, cs.excl, cnt,
+                         ent, cap2);
+        else
+            tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
+                          cs.a_dest, v.perm, bc, tau, cs.excl, cnt, ent, cap2);
     }
     FinalArgs fa;
-    fa.list = list; fa.lcnt = lcnt; fa.lcap = lcap; fa.cnt = cnt; fa.ent = ent; fa.cap = cap; fa.K = K;
+    fa.list = list; fa.lcnt = lcnt; fa.lcap = lcap; fa.cnt = cnt; fa.ent = ent; fa.cap = cap2; fa.K = K;
     fa.X = v.X; fa.Qr = cs.Qr; fa.d = v.d; fa.win = rerank_window(v.d); fa.out_idx = out_idx;
     fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.stats = v.stats;
     const bool vec = (v.d % 4) == 0;
     {
         ProfScope ps(s, "final_rerank", 0, 0);
+        const size_t lds = 4 * sizeof(float) * (size_t)((v.d + 3) & ~3);
+        const dim3 grid((unsigned)((rows + 3) / 4));
         if (vec)
-            hipLaunchKernelGGL(k_final<true>, dim3((unsigned)rows), dim3(64), v.d * 4, s, fa, rows);
+            hipLaunchKernelGGL(k_final<true>, grid, dim3(256), lds, s, fa, rows);
         else
-            hipLaunchKernelGGL(k_final<false>, dim3((unsigned)rows), dim3(64), v.d * 4, s, fa, rows);
+            hipLaunchKernelGGL(k_final<false>, grid, dim3(256), lds, s, fa, rows);
         launch_check(s, "k_final");
     }
     FallbackArgs fb;
@@ -964,10 +1304,11 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     keep_pool_memory(dev);
     CandStage cs;
     cs.rows = v.n;
+    cs.B = first_trees(v.T, K);
     cs.jobs0 = v.jobs;
-    cs.jobs1 = v.jobs + v.n_jobs_tree;
-    cs.njobs0 = v.n_jobs_tree;
-    cs.njobs1 = v.n_jobs_tree * (v.T - 1);
+    cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
+    cs.njobs0 = v.n_jobs_tree * cs.B;
+    cs.njobs1 = v.n_jobs_tree * (v.T - cs.B);
     cs.A = v.Xc;
     cs.a_stride = v.n;
     cs.a_nrm = v.nrm;
@@ -975,6 +1316,12 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     cs.Qr = v.X;
     cs.row_leaf = v.leaf_of;
     cs.excl = exclude_self;
+    const double esz = v.prec == RPF_DIST_FP32 ? 4.0 : 2.0;
+    cs.flops0 = v.tile_flops_tree * cs.B;
+    cs.flops1 = v.tile_flops_tree * (v.T - cs.B);
+    cs.bytes0 = (double)v.n * v.dp * esz * cs.B;
+    cs.bytes1 = (double)v.n * v.dp * esz * (v.T - cs.B);
+    cs.sym = v.max_leaf <= 32 * v.job_mb;  // every leaf is a single diagonal tile
     return run_cand_stage(v, cs, K, out_idx, out_dist, s);
 }
 
@@ -1027,8 +1374,10 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     void *Qc = ws.get<void>((size_t)T * m * v.dp * esz);
     float2 *qnrm = ws.get<float2>((size_t)T * m * 8);
     const int nbt = (v.max_leaf + TR - 1) / TR;
-    const int64_t jcap0 = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
-    const int64_t jcap1 = jcap0 * (T > 1 ? T - 1 : 1);
+    const int nfirst = first_trees(T, K);
+    const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
+    const int64_t jcap0 = jcap_tree * nfirst;
+    const int64_t jcap1 = jcap_tree * (T > nfirst ? T - nfirst : 1);
     TileJob *jobs0 = ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob));
     TileJob *jobs1 = ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob));
     int32_t *njobs = ws.get<int32_t>(16);
@@ -1044,8 +1393,8 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     hipLaunchKernelGGL(k_group_fill, dim3(qb, T), dim3(256), 0, s, qleaf, m, v.heap_leaf, nleaf, goff, gfill, qorder,
                        qgleaf);
     const unsigned lb_ = (unsigned)std::min<int64_t>((nleaf + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_make_jobs, dim3(lb_, T), dim3(256), 0, s, gcount, goff, nleaf, v.leaves, TR, jobs0, jobs1,
-                       njobs);
+    hipLaunchKernelGGL(k_make_jobs, dim3(lb_, T), dim3(256), 0, s, gcount, goff, nleaf, v.leaves, TR, nfirst, jobs0,
+                       jobs1, njobs);
     launch_check(s, "query grouping");
     {
         dim3 g((unsigned)((m + 3) / 4), T);
@@ -1073,8 +1422,9 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     cs.rows = m;
     cs.jobs0 = jobs0;
     cs.jobs1 = jobs1;
+    cs.B = nfirst;
     cs.njobs0 = nj[0];
-    cs.njobs1 = T > 1 ? nj[1] : 0;
+    cs.njobs1 = T > nfirst ? nj[1] : 0;
     cs.A = Qc;
     cs.a_stride = m;
     cs.a_nrm = qnrm;
@@ -1082,6 +1432,8 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     cs.Qr = Q;
     cs.row_leaf = qleaf;
     cs.excl = 0;
+    cs.flops0 = cs.flops1 = cs.bytes0 = cs.bytes1 = 0;
+    cs.sym = false;
     return run_cand_stage(v, cs, K, out_idx, out_dist, s);
 }
 

@@ -182,6 +182,7 @@ struct rpf_forest {
     TileJob *d_jobs = nullptr;   // all-points tile jobs
     int64_t n_jobs_tree = 0;     // jobs per tree
     int job_mb = 8;
+    double tile_flops_tree = 0;
     std::vector<LeafDesc> leaves;
     int max_leaf = 0;
     uint64_t bytes = 0;
@@ -556,6 +557,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
                     }
             }
         f->n_jobs_tree = (int64_t)jobs.size() / T;
+        for (auto &lf : leaves) f->tile_flops_tree += 2.0 * d * (double)lf.size * (double)lf.size;
         f->job_mb = MB;
         RPF_ALLOC(f->d_jobs, jobs.size() * sizeof(TileJob));
         hipMemcpy(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice);
@@ -651,7 +653,7 @@ ForestView view(const rpf_forest *f) {
     v.X = f->X; v.R = f->R; v.centroid = f->centroid; v.split = f->split; v.chosen = f->chosen;
     v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
     v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;
-    v.n_jobs_tree = f->n_jobs_tree; v.stats = f->stats;
+    v.n_jobs_tree = f->n_jobs_tree; v.tile_flops_tree = f->tile_flops_tree; v.stats = f->stats;
     return v;
 }
 }  // namespace rpf

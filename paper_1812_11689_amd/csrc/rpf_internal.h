@@ -113,6 +113,7 @@ struct ForestView {
     int64_t nleaf;
     const TileJob *jobs;
     int64_t n_jobs_tree;
+    double tile_flops_tree;  // useful Gram flops of one tree's all-points tiles
     unsigned long long *stats;
 };
 ForestView view(const rpf_forest *f);
@@ -164,6 +165,28 @@ __device__ inline int mask_rank(uint64_t mask) {  // set bits of mask below this
 
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 __device__ inline float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// exclusive scan over a 256-thread block (4 waves); s_w needs 4 words
+__device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &excl, uint32_t &total) {
+    // 256 threads = 4 waves
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t wb = 0, tot = 0;
+    for (int k = 0; k < 4; k++) {
+        uint32_t c = s_w[k];
+        if (k < w) wb += c;
+        tot += c;
+    }
+    excl = wb + x - v;
+    total = tot;
+    __syncthreads();
+}
 
 // ---------------------------------------------------------------- canonical arithmetic
 
