@@ -123,7 +123,10 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);
 
 /* Counters of the last rpf_all_knn / rpf_query on this forest (host, synchronises the
  * stream): rows that fell back to the exhaustive candidate scan because a pruning buffer
- * overflowed, and the total number of candidates re-ranked in binary32 / binary64. */
+ * overflowed, and the total number of candidates re-ranked in binary32 / binary64.
+ * Returns RPF_EINTERNAL when the last call met a candidate index outside [0, n) in its
+ * pruning buffers (an internal error: such rows are recomputed by the exhaustive scan,
+ * never dereferenced, so the outputs stay correct). */
 typedef struct {
     int64_t rows, fallback_rows, reranked32, reranked64;
 } rpf_knn_stats;

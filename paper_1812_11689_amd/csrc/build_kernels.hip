@@ -615,27 +615,55 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_finalize(
     const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
     const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
-    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
-    extern __shared__ __align__(16) float s_mu[];  // dp floats, then 4 x dp partial sums
+    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max, int ids_in_lds) {
+    extern __shared__ __align__(16) float s_mu[];  // dp floats, then 4 x dp partial sums, then members
     const int t = blockIdx.y, tid = threadIdx.x;
     const LeafDesc lf = leaves[blockIdx.x];
+    const int m = lf.size;
+    float *s_part = s_mu + dp;
     const int32_t *pp = perm + (int64_t)t * n + lf.off;
-    for (int i = tid; i < lf.size; i += 256) leaf_of[(int64_t)t * n + pp[i]] = lf.heap;
-    // mean: wave w sums rows w, w+4, ... (lane j holds columns j, j+64, ...), then the four
-    // partial sums are added in wave order -- a fixed order, so the centroid is reproducible
+    // member ids: staged in LDS when the launch reserved room for them, else read in place
+    int32_t *s_lds_id = reinterpret_cast<int32_t *>(s_part + 4 * dp);
+    const int32_t *s_id = ids_in_lds ? s_lds_id : pp;
+    for (int i = tid; i < m; i += 256) {
+        const int id = pp[i];
+        if (ids_in_lds) s_lds_id[i] = id;
+        leaf_of[(int64_t)t * n + id] = lf.heap;
+    }
+    __syncthreads();
+    // mean: wave w sums rows w, w+4, ... in order (lane j holds columns j, j+64, ...); four
+    // rows are loaded before they are added, then the four partial sums are added in wave
+    // order -- a fixed order, so the centroid is reproducible
     const int lane = tid & 63, wv = tid >> 6;
-    float *s_part = s_mu + dp;  // [4][dp]
-    for (int j0 = 0; j0 < dp; j0 += 64 * 8) {
-        float acc[8];
-        for (int q = 0; q < 8; q++) acc[q] = 0.f;
-        for (int i = wv; i < lf.size; i += 4) {
-            const float *x = X + (int64_t)pp[i] * d;
-            for (int q = 0; q < 8; q++) {
+    for (int j0 = 0; j0 < dp; j0 += 64 * 4) {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        int i = wv;
+        for (; i + 12 < m; i += 16) {
+            float v[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const float *x = X + (int64_t)s_id[i + 4 * r] * d;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int j = j0 + 64 * q + lane;
+                    v[r][q] = j < d ? x[j] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) acc[q] += v[r][q];
+        }
+        for (; i < m; i += 4) {
+            const float *x = X + (int64_t)s_id[i] * d;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
                 const int j = j0 + 64 * q + lane;
-                if (j < d) acc[q] += x[j];
+                acc[q] += j < d ? x[j] : 0.f;
             }
         }
-        for (int q = 0; q < 8; q++) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
             const int j = j0 + 64 * q + lane;
             if (j < dp) s_part[wv * dp + j] = acc[q];
         }
@@ -643,31 +671,57 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
     __syncthreads();
     for (int j = tid; j < dp; j += 256) {
         const float sum = ((s_part[j] + s_part[dp + j]) + s_part[2 * dp + j]) + s_part[3 * dp + j];
-        const float mu = j < d ? sum / (float)lf.size : 0.f;
+        const float mu = j < d ? sum / (float)m : 0.f;
         s_mu[j] = mu;
         if (j < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + j] = mu;
     }
     __syncthreads();
-    for (int i = wv; i < lf.size; i += 4) {
-        const float *x = X + (int64_t)pp[i] * d;
-        T *out = Xc + ((int64_t)t * n + lf.off + i) * dp;
-        float na = 0.f, ra = 0.f;
-        bool over = false;
-        for (int j = lane; j < dp; j += 64) {
-            float a = j < d ? x[j] - s_mu[j] : 0.f;
-            over |= fabsf(a) > range_max;
-            T q = to_tile<T>(a);
-            out[j] = q;
-            float qf = (float)q;
-            na = __builtin_fmaf(qf, qf, na);
-            ra = __builtin_fmaf(a, a, ra);
+    // centred copy in the tile precision and its norms, two rows per wave at a time
+    for (int i0 = wv; i0 < m; i0 += 8) {
+        float na[2] = {0.f, 0.f}, ra[2] = {0.f, 0.f};
+        bool over[2] = {false, false};
+        for (int j0 = 0; j0 < dp; j0 += 64 * 4) {
+            float xv[2][4];
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const int i = i0 + 4 * r;
+                const float *x = X + (int64_t)s_id[i < m ? i : i0] * d;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int j = j0 + 64 * q + lane;
+                    xv[r][q] = j < d ? x[j] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const int i = i0 + 4 * r;
+                if (i >= m) continue;
+                T *out = Xc + ((int64_t)t * n + lf.off + i) * dp;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int j = j0 + 64 * q + lane;
+                    if (j >= dp) continue;
+                    const float a = j < d ? xv[r][q] - s_mu[j] : 0.f;
+                    over[r] |= fabsf(a) > range_max;
+                    const T qv = to_tile<T>(a);
+                    out[j] = qv;
+                    const float qf = (float)qv;
+                    na[r] = __builtin_fmaf(qf, qf, na[r]);
+                    ra[r] = __builtin_fmaf(a, a, ra[r]);
+                }
+            }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            na += __shfl_xor(na, o, 64);
-            ra += __shfl_xor(ra, o, 64);
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            float x = na[r], y = ra[r];
+            for (int o = 32; o > 0; o >>= 1) {
+                x += __shfl_xor(x, o, 64);
+                y += __shfl_xor(y, o, 64);
+            }
+            const uint64_t ov = __ballot(over[r]);
+            const int i = i0 + 4 * r;
+            if (lane == 0 && i < m) nrm[(int64_t)t * n + lf.off + i] = make_float2(x, ov ? INFINITY : sqrtf(y));
         }
-        uint64_t ov = __ballot(over);
-        if (lane == 0) nrm[(int64_t)t * n + lf.off + i] = make_float2(na, ov ? INFINITY : sqrtf(ra));
     }
 }
 
@@ -793,23 +847,30 @@ void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T) {
 template <typename T>
 static void leaf_finalize(hipStream_t s, dim3 grid, size_t lds, const float *X, int d, int dp,
                           const LeafDesc *leaves, int nleaf, const int32_t *perm, int64_t n, int32_t *leaf_of,
-                          float *centroid, void *Xc, float2 *nrm, float range_max) {
+                          float *centroid, void *Xc, float2 *nrm, float range_max, int ids_in_lds) {
+    hipFuncSetAttribute((const void *)k_leaf_finalize<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_leaf_finalize<T>, grid, dim3(256), lds, s, X, d, dp, leaves, nleaf, perm, n, leaf_of,
-                       centroid, (T *)Xc, nrm, range_max);
+                       centroid, (T *)Xc, nrm, range_max, ids_in_lds);
     launch_check(s, "k_leaf_finalize");
+}
+
+size_t leaf_finalize_lds(int dp, int max_leaf, bool ids) {
+    return sizeof(float) * 5 * (size_t)dp + (ids ? sizeof(int32_t) * (size_t)max_leaf : 0);
 }
 
 void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves,
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
-                          void *Xc, float2 *nrm) {
+                          void *Xc, float2 *nrm, int max_leaf, int lds_limit) {
     dim3 grid(nleaf, T);
-    const size_t lds = sizeof(float) * 5 * (size_t)dp;
+    const int ids = leaf_finalize_lds(dp, max_leaf, true) <= (size_t)lds_limit ? 1 : 0;
+    const size_t lds = leaf_finalize_lds(dp, max_leaf, ids != 0);
     if (prec == RPF_DIST_BF16)
-        leaf_finalize<__bf16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+        leaf_finalize<__bf16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f, ids);
     else if (prec == RPF_DIST_FP16)
-        leaf_finalize<_Float16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 60000.f);
+        leaf_finalize<_Float16>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 60000.f,
+                                ids);
     else
-        leaf_finalize<float>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+        leaf_finalize<float>(s, grid, lds, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f, ids);
 }
 
 }  // namespace rpf

@@ -15,12 +15,13 @@
 //  3. Phase II (the other trees) keeps pairs with lb <= tau(row) only.  Every true
 //     neighbour passes in every tree that holds it, since lb <= D <= K-th D <= tau.
 //  4. k_final: dedup by index, tau' = K-th smallest ub, rerank {lb <= tau'} with the
-//     canonical binary32 distance, then the canonical binary64 distance on the window
-//     D32 <= D32_(K) (1 + w) (w covers the binary32 error), order by (D64, index).
+//     canonical binary32 distance; the window D32 <= D32_(K) (1 + w) (w covers the
+//     binary32 error) is ordered by the canonical binary64 distance and the index.
 //  5. Rows whose buffers overflowed take k_fallback: the exhaustive union in binary64.
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "rpf_internal.h"
@@ -113,14 +114,70 @@ __device__ inline void pair_bounds(float na, float nb, float ra, float rb, float
     }
 }
 
+// Where a tile's pairs go.
+//  mode 0 (Phase I, the first trees): every pair of the leaf, at the fixed slot
+//          row * cap + (tree - t0) * ML + (position of the column in its leaf);
+//  mode 1 (Phase II): pairs with lb <= tau(row), appended at row * cap + atomic count.
+struct TileOut {
+    int mode;
+    int t0;
+    int ML;
+    int cap;
+    Ent *ent;          // mode 1 records
+    int32_t *cnt;      // mode 1 counters
+    const float *tau;  // mode 1 thresholds
+    int32_t *pidx;     // mode 0: index / lb / ub arrays (-1, +inf, +inf where empty)
+    float *plb;
+    float *pub;
+};
+
+constexpr int kQueue = 512;  // per-wave queue of Phase II pairs that pass the cheap test
+
+__device__ inline Ent make_ent(int idx, float lb, float ub) {
+    Ent e;
+    e.idx = idx;
+    e.lb = lb;
+    e.ub = ub;
+    e.pad = 0;
+    return e;
+}
+
+__device__ inline Ent invalid_rec() { return make_ent(-1, INFINITY, INFINITY); }
+
+__device__ inline void put_first(const TileOut &o, int64_t slot, int idx, float lb, float ub) {
+    o.pidx[slot] = idx;
+    o.plb[slot] = lb;
+    o.pub[slot] = ub;
+}
+
+__device__ inline void put_first_empty(const TileOut &o, int64_t slot) { put_first(o, slot, -1, INFINITY, INFINITY); }
+
+__device__ inline void emit_filtered(const TileOut &o, int a_pt, int b_pt, float lb, float ub) {
+    const int slot = atomicAdd(&o.cnt[a_pt], 1);
+    if (slot < o.cap) o.ent[(int64_t)a_pt * o.cap + slot] = make_ent(b_pt, lb, ub);
+}
+
+// per-row threshold of the cheap test  |b|^2 - 2 a.b <= phi(row),  a necessary condition for
+// lb <= tau(row) with the per-pair error terms replaced by their largest value over the tile
+__device__ inline float cheap_phi(float tv, float na, float ra, float nmax, float rmax, BoundCoef bc) {
+    if (!(tv < INFINITY)) return INFINITY;
+    if (tv < 0.f) return -INFINITY;
+    if (!(ra < INFINITY) || !(rmax < INFINITY)) return INFINITY;
+    const float dmax = bc.c * (ra + rmax) + bc.eta;
+    const float emax = bc.e * (na + nmax);
+    const float st = sqrtf(tv / (1.f - 1e-6f)) + dmax;
+    const float th = st * st + emax;
+    return (th - na) + 1e-5f * (th + na + nmax) + 1e-30f;
+}
+
 // One tile job per block: A rows x B rows of one leaf (or query group x leaf), MB waves,
 // wave w owns A rows [32w, 32w + 32) against all B rows.
 template <int MB, int PREC>
 __global__ __launch_bounds__(64 * MB) void k_tile(
     const TileJob *__restrict__ jobs, const void *__restrict__ A_, const void *__restrict__ B_, int dp,
     int64_t a_stride_tree, int64_t b_stride_tree, const float2 *__restrict__ a_nrm, const float2 *__restrict__ b_nrm,
-    const int32_t *__restrict__ a_dest, const int32_t *__restrict__ b_pt, BoundCoef bc,
-    const float *__restrict__ tau, int exclude_self, int32_t *__restrict__ cnt, Ent *__restrict__ ent, int cap) {
+    const int32_t *__restrict__ a_dest, const int32_t *__restrict__ b_pt, BoundCoef bc, int exclude_self,
+    TileOut out) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * MB;
@@ -129,12 +186,14 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     __shared__ __align__(16) T s_b[M * C::LDW];
     __shared__ float s_na[M], s_ra[M], s_nb[M], s_rb[M], s_phi[M], s_tau[M];
     __shared__ int32_t s_dst[M], s_bpt[M];
-    __shared__ uint32_t s_cnt[M], s_base[M];
     __shared__ float s_bmax[2];
+    __shared__ uint32_t s_qn[MB];
+    __shared__ uint2 s_que[MB][kQueue];
 
     const TileJob job = jobs[blockIdx.x];
     const int t = job.tree;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     const bool same = job.same != 0;
     const T *A = reinterpret_cast<const T *>(A_) + (t * a_stride_tree + job.a_off) * dp;
     const T *B = reinterpret_cast<const T *>(B_) + (t * b_stride_tree + job.b_off) * dp;
@@ -142,15 +201,16 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     const float2 *bn = b_nrm + t * b_stride_tree + job.b_off;
     const int32_t *ad = a_dest + t * a_stride_tree + job.a_off;
     const int32_t *bp = b_pt + t * b_stride_tree + job.b_off;
+    const int tb = t - out.t0;
 
     for (int r = tid; r < M; r += NT) {
         if (r < job.a_rows) {
-            float2 q = an[r];
+            const float2 q = an[r];
             s_na[r] = q.x;
             s_ra[r] = q.y;
-            int dst = ad[r];
+            const int dst = ad[r];
             s_dst[r] = dst;
-            s_tau[r] = tau ? tau[dst] : INFINITY;
+            s_tau[r] = out.mode == 1 ? out.tau[dst] : INFINITY;
         } else {
             s_na[r] = 0.f;
             s_ra[r] = 0.f;
@@ -158,7 +218,7 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
             s_tau[r] = -1.f;
         }
         if (r < job.b_rows) {
-            float2 q = bn[r];
+            const float2 q = bn[r];
             s_nb[r] = q.x;
             s_rb[r] = q.y;
             s_bpt[r] = bp[r];
@@ -167,10 +227,10 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
             s_rb[r] = 0.f;
             s_bpt[r] = -1;
         }
-        s_cnt[r] = 0;
     }
+    if (tid < MB) s_qn[tid] = 0;
     __syncthreads();
-    if (tid < 64) {  // largest |b|^2 and |b'| of the tile, for the cheap per-row threshold
+    if (tid < 64) {
         float mn = 0.f, mr = 0.f;
         for (int r = lane; r < job.b_rows; r += 64) {
             mn = fmaxf(mn, s_nb[r]);
@@ -186,32 +246,24 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
         }
     }
     __syncthreads();
-    for (int r = tid; r < M; r += NT) {
-        // necessary condition for lb <= tau:  |b|^2 - 2 a.b <= phi(row), with the per-pair
-        // error terms replaced by their largest value over the tile's B rows
-        const float tv = s_tau[r];
-        float phi;
-        if (!(tv < INFINITY)) {
-            phi = INFINITY;
-        } else if (tv < 0.f) {
-            phi = -INFINITY;
-        } else {
-            const float dmax = bc.c * (s_ra[r] + s_bmax[1]) + bc.eta;
-            const float emax = bc.e * (s_na[r] + s_bmax[0]);
-            const float st = sqrtf(tv / (1.f - 1e-6f)) + dmax;
-            const float th = st * st + emax;
-            phi = (th - s_na[r]) + 1e-5f * (th + s_na[r] + s_bmax[0]) + 1e-30f;
-            if (!(s_ra[r] < INFINITY) || !(s_bmax[1] < INFINITY)) phi = INFINITY;
+    for (int r = tid; r < M; r += NT) s_phi[r] = cheap_phi(s_tau[r], s_na[r], s_ra[r], s_bmax[0], s_bmax[1], bc);
+    if (out.mode == 0) {  // Phase I: the slots no pair of this tile fills (past the leaf, self)
+        const bool last = job.b_pos + job.b_rows == job.leaf_m;
+        for (int r = tid; r < job.a_rows; r += NT) {
+            const int64_t er = (int64_t)s_dst[r] * out.cap + (int64_t)tb * out.ML;
+            if (last)
+                for (int c = job.leaf_m; c < out.ML; c++) put_first_empty(out, er + c);
+            if (same && exclude_self) put_first_empty(out, er + job.b_pos + r);
         }
-        s_phi[r] = phi;
     }
 
     f32x16 acc[MB];
 #pragma unroll
     for (int cb = 0; cb < MB; cb++)
+#pragma unroll
         for (int v = 0; v < 16; v++) acc[cb][v] = 0.f;
     const int nbb = (job.b_rows + 31) >> 5;
-    const bool active = 32 * w < job.a_rows;
+    const bool active = 32 * wu < job.a_rows;
     const int fr = lane & 31;
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
     const int a_pad = ((job.a_rows + 31) >> 5) << 5;
@@ -226,7 +278,7 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
         if (active) {
             for (int kk = 0; kk < kmax; kk += C::KSTEP) {
-                const T *pa = s_a + (32 * w + fr) * C::LDW + kk + fk;
+                const T *pa = s_a + (32 * wu + fr) * C::LDW + kk + fk;
 #pragma unroll
                 for (int cb = 0; cb < MB; cb++) {
                     if (cb < nbb) {
@@ -237,64 +289,72 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
             }
         }
     }
+    if (!active) return;
 
-    // ---- epilogue: sweep 1 counts the kept pairs per row, sweep 2 writes them
-    for (int sweep = 0; sweep < 2; sweep++) {
-        if (active) {
+    if (out.mode == 0) {
 #pragma unroll
-            for (int cb = 0; cb < MB; cb++) {
-                if (cb >= nbb) continue;
-                const int col = 32 * cb + (lane & 31);
-                const bool colok = col < job.b_rows;
-                const float nb = s_nb[col];
+        for (int cb = 0; cb < MB; cb++) {
+            if (cb >= nbb) continue;
+            const int col = 32 * cb + (lane & 31);
+            if (col >= job.b_rows) continue;
+            const float nb = s_nb[col], rb = s_rb[col];
+            const int bpt = s_bpt[col];
 #pragma unroll
-                for (int v = 0; v < 16; v++) {
-                    const int row = 32 * w + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    const float g = acc[cb][v];
-                    if (colok && row < job.a_rows && __builtin_fmaf(-2.f, g, nb) <= s_phi[row] &&
-                        !(same && exclude_self && row == col)) {
-                        float lb, ub;
-                        pair_bounds(s_na[row], nb, s_ra[row], s_rb[col], g, bc, lb, ub);
-                        if (lb <= s_tau[row]) {
-                            if (sweep == 0) {
-                                atomicAdd(&s_cnt[row], 1u);
-                            } else {
-                                const uint32_t slot = s_base[row] + atomicAdd(&s_cnt[row], 1u);
-                                if (slot < (uint32_t)cap) {
-                                    Ent e;
-                                    e.idx = s_bpt[col];
-                                    e.lb = lb;
-                                    e.ub = ub;
-                                    e.pad = 0;
-                                    ent[(int64_t)s_dst[row] * cap + slot] = e;
-                                }
-                            }
-                        }
-                    }
+            for (int v = 0; v < 16; v++) {
+                const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (row >= job.a_rows || (same && exclude_self && row == col)) continue;
+                float lb, ub;
+                pair_bounds(s_na[row], nb, s_ra[row], rb, acc[cb][v], bc, lb, ub);
+                put_first(out, (int64_t)s_dst[row] * out.cap + (int64_t)tb * out.ML + job.b_pos + col, bpt, lb, ub);
+            }
+        }
+        return;
+    }
+    // Phase II: cheap test over every pair, exact bounds only for the few that pass
+    uint32_t *qn = &s_qn[wu];
+    uint2 *que = s_que[wu];
+#pragma unroll
+    for (int cb = 0; cb < MB; cb++) {
+        if (cb >= nbb) continue;
+        const int col = 32 * cb + (lane & 31);
+        const bool colok = col < job.b_rows;
+        const float nb = s_nb[col];
+#pragma unroll
+        for (int v = 0; v < 16; v++) {
+            const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const bool p = colok && __builtin_fmaf(-2.f, acc[cb][v], nb) <= s_phi[row] &&
+                           !(same && exclude_self && row == col);
+            if (p) {
+                const uint32_t pos = atomicAdd(qn, 1u);
+                if (pos < (uint32_t)kQueue) {
+                    que[pos] = make_uint2((uint32_t)row | ((uint32_t)col << 8), __float_as_uint(acc[cb][v]));
+                } else {  // queue full (rare): bounds and emission right here
+                    float lb, ub;
+                    pair_bounds(s_na[row], nb, s_ra[row], s_rb[col], acc[cb][v], bc, lb, ub);
+                    if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
                 }
             }
         }
-        __syncthreads();
-        if (sweep == 0) {
-            for (int r = tid; r < job.a_rows; r += NT) {
-                const uint32_t c = s_cnt[r];
-                s_base[r] = c ? (uint32_t)atomicAdd(&cnt[s_dst[r]], (int32_t)c) : 0u;
-                s_cnt[r] = 0;
-            }
-            __syncthreads();
-        }
+    }
+    wave_sync();
+    const uint32_t nq = min(*qn, (uint32_t)kQueue);
+    for (uint32_t i = lane; i < nq; i += 64) {
+        const uint2 e = que[i];
+        const int row = e.x & 255, col = (e.x >> 8) & 255;
+        float lb, ub;
+        pair_bounds(s_na[row], s_nb[col], s_ra[row], s_rb[col], __uint_as_float(e.y), bc, lb, ub);
+        if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
     }
 }
 
 // All-points tile of one leaf whose rows all fit (m <= 32 NB): the Gram matrix is symmetric,
 // so only blocks (i, j) with i <= j run on MFMA and an off-diagonal block emits both
-// (row -> col) and (col -> row).  Wave w owns block rows w and nb-1-w (nb + 1 blocks per
+// (row -> col) and (col -> row).  Wave w owns block rows w and NB-1-w (NB + 1 blocks per
 // wave), which balances the triangle; both operands come from the same LDS tile.
-template <int NB, int PREC>
+template <int NB, int PREC, int MODE>
 __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
     const TileJob *__restrict__ jobs, const void *__restrict__ A_, int dp, int64_t stride_tree,
-    const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, const float *__restrict__ tau,
-    int exclude_self, int32_t *__restrict__ cnt, Ent *__restrict__ ent, int cap) {
+    const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, int exclude_self, TileOut out) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
@@ -304,16 +364,19 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
     __shared__ __align__(16) T s_a[M * C::LDW];
     __shared__ float s_n[M], s_r[M], s_phi[M], s_tau[M];
     __shared__ int32_t s_pt[M];
-    __shared__ uint32_t s_cnt[M], s_base[M];
     __shared__ float s_max[2];
+    __shared__ uint32_t s_qn[NW];
+    __shared__ uint2 s_que[NW][kQueue];
 
     const TileJob job = jobs[blockIdx.x];
     const int t = job.tree;
     const int m = job.a_rows;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform (scalar) wave index
     const T *A = reinterpret_cast<const T *>(A_) + (t * stride_tree + job.a_off) * dp;
     const float2 *an = nrm + t * stride_tree + job.a_off;
     const int32_t *ap = pt + t * stride_tree + job.a_off;
+    const int tb = t - out.t0;
     for (int r = tid; r < M; r += NT) {
         if (r < m) {
             const float2 q = an[r];
@@ -321,15 +384,15 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
             s_r[r] = q.y;
             const int p = ap[r];
             s_pt[r] = p;
-            s_tau[r] = tau ? tau[p] : INFINITY;
+            s_tau[r] = MODE == 1 ? out.tau[p] : INFINITY;
         } else {
             s_n[r] = 0.f;
             s_r[r] = 0.f;
             s_pt[r] = -1;
             s_tau[r] = -1.f;
         }
-        s_cnt[r] = 0;
     }
+    if (tid < NW) s_qn[tid] = 0;
     __syncthreads();
     if (tid < 64) {
         float mn = 0.f, mr = 0.f;
@@ -347,36 +410,23 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
         }
     }
     __syncthreads();
-    for (int r = tid; r < M; r += NT) {
-        const float tv = s_tau[r];
-        float phi;
-        if (!(tv < INFINITY)) {
-            phi = INFINITY;
-        } else if (tv < 0.f) {
-            phi = -INFINITY;
-        } else {
-            const float dmax = bc.c * (s_r[r] + s_max[1]) + bc.eta;
-            const float emax = bc.e * (s_n[r] + s_max[0]);
-            const float st = sqrtf(tv / (1.f - 1e-6f)) + dmax;
-            const float th = st * st + emax;
-            phi = (th - s_n[r]) + 1e-5f * (th + s_n[r] + s_max[0]) + 1e-30f;
-            if (!(s_r[r] < INFINITY) || !(s_max[1] < INFINITY)) phi = INFINITY;
+    for (int r = tid; r < M; r += NT) s_phi[r] = cheap_phi(s_tau[r], s_n[r], s_r[r], s_max[0], s_max[1], bc);
+    if constexpr (MODE == 0) {  // Phase I: the slots no pair fills (past the leaf, and self)
+        for (int r = tid; r < m; r += NT) {
+            const int64_t er = (int64_t)s_pt[r] * out.cap + (int64_t)tb * out.ML;
+            for (int c = m; c < out.ML; c++) put_first_empty(out, er + c);
+            if (exclude_self) put_first_empty(out, er + r);
         }
-        s_phi[r] = phi;
     }
 
-    const int nb = (m + 31) >> 5;
-    const int r1 = w, r2 = nb - 1 - w;
-    const bool wave_on = r1 <= r2;
-    const int len1 = nb - r1;
-    // slot sl of this wave -> Gram block (i, j), i <= j; -1 when unused
+    // every leaf of the launch has more than 32 (NB/2) rows, so the NB x NB block grid is
+    // used as is; padding rows are zero in LDS and skipped by the epilogue
     auto slot_block = [&](int sl, int &bi, int &bj) {
-        if (!wave_on) {
-            bi = bj = -1;
-        } else if (sl < len1) {
+        const int r1 = wu, r2 = NB - 1 - wu, len1 = NB - r1;
+        if (sl < len1) {
             bi = r1;
             bj = r1 + sl;
-        } else if (r2 > r1 && sl - len1 < nb - r2) {
+        } else if (r2 > r1 && sl - len1 < NB - r2) {
             bi = r2;
             bj = r2 + (sl - len1);
         } else {
@@ -390,87 +440,99 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
         for (int v = 0; v < 16; v++) acc[sl][v] = 0.f;
     const int fr = lane & 31;
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
-    const int m_pad = nb << 5;
+    int sbi[SLOTS], sbj[SLOTS];  // scalar block coordinates of every slot of this wave
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; sl++) slot_block(sl, sbi[sl], sbj[sl]);
     for (int k0 = 0; k0 < dp; k0 += C::KC) {
         __syncthreads();
-        stage_rows<PREC>(s_a, A, m, m_pad, dp, k0, NT);
+        stage_rows<PREC>(s_a, A, m, M, dp, k0, NT);
         __syncthreads();
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
-        if (wave_on) {
-            for (int kk = 0; kk < kmax; kk += C::KSTEP) {
+        const T *base = s_a + fr * C::LDW + fk;
+        using Frag = typename std::conditional<PREC == RPF_DIST_FP32, float, uint4>::type;
+        for (int kk = 0; kk < kmax; kk += C::KSTEP) {
+            Frag fa[SLOTS], fb[SLOTS];  // all fragment loads of the step first, then the MFMAs
 #pragma unroll
-                for (int sl = 0; sl < SLOTS; sl++) {
-                    int bi, bj;
-                    slot_block(sl, bi, bj);
-                    if (bi >= 0) {
-                        const T *pa = s_a + (32 * bi + fr) * C::LDW + kk + fk;
-                        const T *pb = s_a + (32 * bj + fr) * C::LDW + kk + fk;
-                        acc[sl] = mfma_step<PREC>(pa, pb, acc[sl]);
-                    }
+            for (int sl = 0; sl < SLOTS; sl++) {
+                fa[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbi[sl] * C::LDW + kk);
+                fb[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbj[sl] * C::LDW + kk);
+            }
+#pragma unroll
+            for (int sl = 0; sl < SLOTS; sl++)
+                acc[sl] = mfma_step<PREC>(reinterpret_cast<const T *>(&fa[sl]), reinterpret_cast<const T *>(&fb[sl]),
+                                          acc[sl]);
+        }
+    }
+
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int sl = 0; sl < SLOTS; sl++) {
+            const int bi = sbi[sl], bj = sbj[sl];
+            const bool diag = bi == bj;
+            const int col = 32 * bj + (lane & 31);
+            if (col < m) {
+                const float ncol = s_n[col], rcol = s_r[col];
+                const int pcol = s_pt[col];
+                const int64_t ecol = (int64_t)pcol * out.cap + (int64_t)tb * out.ML;
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    if (row >= m || (diag && (row > col || (row == col && exclude_self)))) continue;
+                    float lb, ub;
+                    pair_bounds(s_n[row], ncol, s_r[row], rcol, acc[sl][v], bc, lb, ub);
+                    put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, pcol, lb, ub);
+                    if (row != col) put_first(out, ecol + row, s_pt[row], lb, ub);
+                }
+            }
+        }
+        return;
+    }
+    if constexpr (MODE == 1) {
+    // Phase II: a cheap test over every pair (both directions); exact bounds only for the
+    // few that pass, through a per-wave LDS queue
+    uint32_t *qn = &s_qn[wu];
+    uint2 *que = s_que[wu];
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; sl++) {
+        const int bi = sbi[sl], bj = sbj[sl];
+        const bool diag = bi == bj;
+        const int col = 32 * bj + (lane & 31);
+        const bool colok = col < m;
+        const float ncol = s_n[col];
+        const float phicol = s_phi[col];
+#pragma unroll
+        for (int v = 0; v < 16; v++) {
+            const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const float g = acc[sl][v];
+            const bool p1 = colok && __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] &&
+                            !(diag && (row > col || (row == col && exclude_self)));
+            const bool p2 = (!diag || row < col) && row < m && __builtin_fmaf(-2.f, g, s_n[row]) <= phicol;
+            if (p1 || p2) {
+                const uint32_t pos = atomicAdd(qn, 1u);
+                if (pos < (uint32_t)kQueue) {
+                    que[pos] = make_uint2((uint32_t)row | ((uint32_t)col << 8) | ((p1 ? 1u : 0u) << 16) |
+                                              ((p2 ? 1u : 0u) << 17),
+                                          __float_as_uint(g));
+                } else {  // queue full (rare): bounds and emission right here
+                    float lb, ub;
+                    pair_bounds(s_n[row], ncol, s_r[row], s_r[col], g, bc, lb, ub);
+                    if (p1 && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
+                    if (p2 && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
                 }
             }
         }
     }
-
-    for (int sweep = 0; sweep < 2; sweep++) {
-        if (wave_on) {
-            for (int sl = 0; sl < SLOTS; sl++) {  // rolled: one slot's accumulators at a time
-                int bi, bj;
-                slot_block(sl, bi, bj);
-                if (bi < 0) continue;
-                f32x16 cur = acc[0];
-#pragma unroll
-                for (int q = 1; q < SLOTS; q++)
-                    if (q == sl) cur = acc[q];
-                const bool diag = bi == bj;
-                const int col = 32 * bj + (lane & 31);
-                const bool colok = col < m;
-                const float ncol = s_n[col];
-#pragma unroll
-                for (int v = 0; v < 16; v++) {
-                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    if (!colok || row >= m) continue;
-                    const float g = cur[v];
-                    const float nrow = s_n[row];
-                    // row -> col (every block; the diagonal skips the point itself)
-                    const bool f1 = __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] && !(exclude_self && row == col);
-                    // col -> row (off-diagonal blocks only: the diagonal block holds both orders)
-                    const bool f2 = !diag && __builtin_fmaf(-2.f, g, nrow) <= s_phi[col];
-                    if (!(f1 || f2)) continue;
-                    float lb, ub;
-                    pair_bounds(nrow, ncol, s_r[row], s_r[col], g, bc, lb, ub);
-                    for (int dir = 0; dir < 2; dir++) {
-                        const bool fd = dir == 0 ? f1 : f2;
-                        const int a = dir == 0 ? row : col;
-                        const int b = dir == 0 ? col : row;
-                        if (!fd || !(lb <= s_tau[a])) continue;
-                        if (sweep == 0) {
-                            atomicAdd(&s_cnt[a], 1u);
-                        } else {
-                            const uint32_t slot = s_base[a] + atomicAdd(&s_cnt[a], 1u);
-                            if (slot < (uint32_t)cap) {
-                                Ent e;
-                                e.idx = s_pt[b];
-                                e.lb = lb;
-                                e.ub = ub;
-                                e.pad = 0;
-                                ent[(int64_t)s_pt[a] * cap + slot] = e;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (sweep == 0) {
-            for (int r = tid; r < m; r += NT) {
-                const uint32_t c = s_cnt[r];
-                s_base[r] = c ? (uint32_t)atomicAdd(&cnt[s_pt[r]], (int32_t)c) : 0u;
-                s_cnt[r] = 0;
-            }
-            __syncthreads();
-        }
+    wave_sync();
+    const uint32_t nq = min(*qn, (uint32_t)kQueue);
+    for (uint32_t i = lane; i < nq; i += 64) {
+        const uint2 e = que[i];
+        const int row = e.x & 255, col = (e.x >> 8) & 255;
+        float lb, ub;
+        pair_bounds(s_n[row], s_n[col], s_r[row], s_r[col], __uint_as_float(e.y), bc, lb, ub);
+        if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
+        if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
+    }
     }
 }
 
@@ -577,9 +639,11 @@ constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
 constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
 constexpr int kSetCap = 512;
 
-__global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int32_t *__restrict__ cnt,
-                                                     const Ent *__restrict__ ent, int cap, float *__restrict__ tau,
-                                                     Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap) {
+__global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int ML,
+                                                     const int32_t *__restrict__ pidx, const float *__restrict__ plb,
+                                                     const float *__restrict__ pub, int cap, float *__restrict__ tau,
+                                                     Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap,
+                                                     int32_t *__restrict__ cnt) {
     __shared__ uint32_t s_u[4][kMergeCap];
     __shared__ uint32_t s_h[4][256];
     __shared__ int32_t s_si[4][kSetCap];
@@ -587,25 +651,31 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
-    const int c0 = cnt[a];
-    const Ent *e = ent + a * cap;
-    bool over = c0 > cap || c0 > kMergeCap;
-    const int c = over ? 0 : c0;
-    for (int i = lane; i < c; i += 64) s_u[w][i] = fkey(e[i].ub);
+    const int64_t base_slot = a * cap;
+    const int c = B * ML;  // fixed slots of the first B trees; empty ones hold +inf bounds
+    bool over = c > kMergeCap;
+    int nv = 0;  // valid (finite ub) slots
+    for (int i = lane; i < (over ? 0 : c); i += 64) {
+        const uint32_t u = fkey(pub[base_slot + i]);
+        s_u[w][i] = u;
+        nv += u < 0x7f800000u ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
     wave_sync();
     const int kb = K * B;
-    uint32_t theta = 0xffffffffu;
-    if (c >= kb) theta = wave_kth_lds(s_u[w], c, kb - 1, s_h[w]);
-    // the small set S = {ub <= theta}
+    uint32_t theta = 0x7f800000u;  // +inf
+    if (!over && nv >= kb) theta = wave_kth_lds(s_u[w], c, kb - 1, s_h[w]);
+    // the small set S = {valid slots with ub <= theta}
     int ns = 0;
-    for (int base = 0; base < c; base += 64) {
-        const int i = base + lane;
-        const bool in = i < c && s_u[w][i] <= theta;
+    for (int b0 = 0; b0 < (over ? 0 : c); b0 += 64) {
+        const int i = b0 + lane;
+        const uint32_t u = i < c ? s_u[w][i] : 0xffffffffu;
+        const bool in = u <= theta && u < 0x7f800000u;
         const uint64_t mk = __ballot(in);
         const int pos = ns + mask_rank(mk);
         if (in && pos < kSetCap) {
-            s_si[w][pos] = e[i].idx;
-            s_su[w][pos] = s_u[w][i];
+            s_si[w][pos] = pidx[base_slot + i];
+            s_su[w][pos] = u;
         }
         ns += __popcll(mk);
     }
@@ -613,7 +683,7 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     float tv = INFINITY;
     if (ns > kSetCap) {
         over = true;
-    } else {
+    } else if (!over) {
         // representatives: the entry of smallest (ub, position) among equal indices
         uint32_t repv[kSetCap / 64];
         bool rep[kSetCap / 64];
@@ -639,17 +709,19 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     }
     const float tp = tv * (1.f + 1e-6f);
     uint32_t kept = 0;
-    for (int base = 0; base < c; base += 64) {
-        const int i = base + lane;
-        Ent x;
-        bool keep = false;
-        if (i < c) {
-            x = e[i];
-            keep = x.lb <= tp;
-        }
+    for (int b0 = 0; b0 < (over ? 0 : c); b0 += 64) {
+        const int i = b0 + lane;
+        // lanes past the row's c slots read nothing: with tau = +inf (fewer distinct
+        // candidates than K) their lb = +inf would pass lb <= tau and the read would land in
+        // the next row's slots, or past the index array for the last row.  Validity of a
+        // slot comes from its index (-1 marks an empty one), never from its bounds.
+        const bool slot = i < c;
+        const float lb = slot ? plb[base_slot + i] : INFINITY;
+        const int id = slot && lb <= tp ? pidx[base_slot + i] : -1;
+        const bool keep = id >= 0;
         const uint64_t mk = __ballot(keep);
         const uint32_t pos = kept + mask_rank(mk);
-        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = x;
+        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = make_ent(id, lb, __uint_as_float(s_u[w][i]));
         kept += __popcll(mk);
     }
     wave_sync();
@@ -665,7 +737,7 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 constexpr int kFinalQ = 12;                // entries per lane
 constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
 constexpr int kHT = 1024;                  // per-row hash table (indices) for the dedup
-constexpr int kRCap = 512;                 // rerank set per row
+constexpr int kRCap = kHT / 2;             // rerank set per row (its doubles reuse the hash table)
 constexpr int kWCap = 256;                 // binary64 window per row
 
 struct FinalArgs {
@@ -684,7 +756,8 @@ struct FinalArgs {
     float *out_dist;
     int32_t *fb_list;   // rows for the exhaustive fallback
     int32_t *fb_cnt;
-    unsigned long long *stats;  // [rows, fallback, reranked32, reranked64]
+    int64_t npts;       // rows of X: every candidate index lies in [0, npts)
+    unsigned long long *stats;  // [rows, fallback, reranked32, reranked64, bad_index]
 };
 
 __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
@@ -697,7 +770,7 @@ __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
 // of indices marks the first copy of every index (any copy's interval is valid for it).
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
-    __shared__ int32_t s_key[4][kHT];
+    __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
     __shared__ int32_t s_r[4][kRCap];
     __shared__ uint32_t s_d[4][kRCap];
     __shared__ int32_t s_wi[4][kWCap];
@@ -722,14 +795,16 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     uint32_t elb[kFinalQ], eub[kFinalQ];
     bool first[kFinalQ];
     int nd = 0;
+    bool bad = false;  // an index outside [0, npts) is an internal error, never dereferenced
 #pragma unroll
     for (int q = 0; q < kFinalQ; q++) {
         const int i = lane + 64 * q;
         first[q] = false;
         eidx[q] = -1;
         elb[q] = eub[q] = 0;
-        if (i < c1 + c2) {
-            const Ent e = i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)];
+        const Ent e = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+        bad |= e.idx < -1 || (int64_t)e.idx >= A.npts;
+        if (e.idx >= 0 && (int64_t)e.idx < A.npts) {
             eidx[q] = e.idx;
             elb[q] = fkey(e.lb);
             eub[q] = fkey(e.ub);
@@ -747,6 +822,13 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         nd += __popcll(__ballot(first[q]));
     }
     wave_sync();
+    if (__ballot(bad)) {  // counted for the host to report; the row is recomputed exhaustively
+        if (lane == 0) {
+            atomicAdd(&A.stats[4], 1ull);
+            push_fallback(A, a);
+        }
+        return;
+    }
     float tv = INFINITY;
     if (nd >= K) tv = __uint_as_float(wave_kth_regs<kFinalQ>(eub, first, K - 1, s_h[w]));
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
@@ -764,36 +846,41 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         if (lane == 0) push_fallback(A, a);
         return;
     }
+    // one gather of every candidate row gives both canonical distances; the hash table is
+    // dead by now and holds the binary64 values
+    double *s_dd = reinterpret_cast<double *>(s_key[w]);  // kHT int32 = kRCap doubles
     const int g = lane & 7, grp = lane >> 3;
     for (int base = 0; base < nr; base += 8) {
         const int i = base + grp;
         const int b = s_r[w][i < nr ? i : 0];
-        const float D32 = group8_dist32<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
-        if (g == 0 && i < nr) s_d[w][i] = fkey(D32);
+        float D32;
+        double D64;
+        group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
+        if (g == 0 && i < nr) {
+            s_d[w][i] = fkey(D32);
+            s_dd[i] = D64;
+        }
     }
     wave_sync();
     float d32k = INFINITY;
     if (nr >= K) d32k = __uint_as_float(wave_kth_lds(s_d[w], nr, K - 1, s_h[w]));
     const float wcut = d32k * (1.f + A.win);
-    int nw = 0;
+    int nw = 0;  // the window: binary32 distance within w of the K-th; ordered in binary64
     for (int base = 0; base < nr; base += 64) {
         const int i = base + lane;
         const bool in = i < nr && __uint_as_float(s_d[w][i]) <= wcut;
         const uint64_t mk = __ballot(in);
         const int pos = nw + mask_rank(mk);
-        if (in && pos < kWCap) s_wi[w][pos] = s_r[w][i];
+        if (in && pos < kWCap) {
+            s_wi[w][pos] = s_r[w][i];
+            s_wd[w][pos] = s_dd[i];
+        }
         nw += __popcll(mk);
     }
     wave_sync();
     if (nw > kWCap) {  // pathological window (massive distance ties): exhaustive path
         if (lane == 0) push_fallback(A, a);
         return;
-    }
-    for (int base = 0; base < nw; base += 8) {
-        const int i = base + grp;
-        const int b = s_wi[w][i < nw ? i : 0];
-        const double D64 = group8_dist64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g);
-        if (g == 0 && i < nw) s_wd[w][i] = D64;
     }
     int P2 = 1;
     while (P2 < nw) P2 <<= 1;
@@ -1031,6 +1118,8 @@ __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *_
                 j.b_rows = min(TR, lf.size - J * TR);
                 j.tree = t;
                 j.same = 0;
+                j.b_pos = J * TR;
+                j.leaf_m = lf.size;
                 const bool first = t < nfirst;
                 const int slot = atomicAdd(&njobs[first ? 0 : 1], 1);
                 (first ? jobs0 : jobs1)[slot] = j;
@@ -1099,36 +1188,34 @@ static float rerank_window(int d) {
 template <int MB, int PREC>
 static void tile_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B, int dp,
                         int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
-                        const int32_t *bp, BoundCoef bc, const float *tau, int excl, int32_t *cnt, Ent *ent, int cap) {
+                        const int32_t *bp, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
     hipLaunchKernelGGL((k_tile<MB, PREC>), dim3((unsigned)njobs), dim3(64 * MB), 0, s, jobs, A, B, dp, as, bs, an, bn,
-                       ad, bp, bc, tau, excl, cnt, ent, cap);
+                       ad, bp, bc, excl, out);
     launch_check(s, "k_tile");
 }
 
 template <int PREC>
 static void tile_dispatch_mb(int MB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B,
                              int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
-                             const int32_t *bp, BoundCoef bc, const float *tau, int excl, int32_t *cnt, Ent *ent,
-                             int cap) {
+                             const int32_t *bp, BoundCoef bc, int excl, const TileOut &out) {
     switch (MB) {
-    case 1: tile_launch<1, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
-    case 2: tile_launch<2, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
-    case 4: tile_launch<4, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
-    default: tile_launch<8, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap); break;
+    case 1: tile_launch<1, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out); break;
+    case 2: tile_launch<2, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out); break;
+    case 4: tile_launch<4, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out); break;
+    default: tile_launch<8, PREC>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out); break;
     }
 }
 
 static void tile_dispatch(int prec, int MB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A,
                           const void *B, int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn,
-                          const int32_t *ad, const int32_t *bp, BoundCoef bc, const float *tau, int excl,
-                          int32_t *cnt, Ent *ent, int cap) {
+                          const int32_t *ad, const int32_t *bp, BoundCoef bc, int excl, const TileOut &out) {
     if (prec == RPF_DIST_BF16)
-        tile_dispatch_mb<RPF_DIST_BF16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+        tile_dispatch_mb<RPF_DIST_BF16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out);
     else if (prec == RPF_DIST_FP16)
-        tile_dispatch_mb<RPF_DIST_FP16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+        tile_dispatch_mb<RPF_DIST_FP16>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out);
     else
-        tile_dispatch_mb<RPF_DIST_FP32>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, tau, excl, cnt, ent, cap);
+        tile_dispatch_mb<RPF_DIST_FP32>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out);
 }
 
 // stream-ordered workspace
@@ -1153,7 +1240,7 @@ struct Workspace {
     }
 };
 
-static void keep_pool_memory(int dev) {
+void keep_pool_memory(int dev) {
     static bool done[64] = {false};
     if (dev < 0 || dev >= 64 || done[dev]) return;
     hipMemPool_t pool;
@@ -1185,36 +1272,39 @@ struct CandStage {
 
 template <int NB, int PREC>
 static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
-                       const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau, int excl, int32_t *cnt,
-                       Ent *ent, int cap) {
+                       const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
     constexpr int NT = NB >= 2 ? 32 * NB : 64;
-    hipLaunchKernelGGL((k_tile_sym<NB, PREC>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt,
-                       bc, tau, excl, cnt, ent, cap);
+    if (out.mode == 0)
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm,
+                           pt, bc, excl, out);
+    else
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm,
+                           pt, bc, excl, out);
     launch_check(s, "k_tile_sym");
 }
 
 template <int PREC>
 static void sym_dispatch_nb(int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
-                            int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau,
-                            int excl, int32_t *cnt, Ent *ent, int cap) {
+                            int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl,
+                            const TileOut &out) {
     switch (NB) {
-    case 1: sym_launch<1, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
-    case 2: sym_launch<2, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
-    case 4: sym_launch<4, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
-    default: sym_launch<8, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap); break;
+    case 1: sym_launch<1, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
+    case 2: sym_launch<2, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
+    case 4: sym_launch<4, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
+    default: sym_launch<8, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
     }
 }
 
 static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
-                         int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, const float *tau,
-                         int excl, int32_t *cnt, Ent *ent, int cap) {
+                         int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl,
+                         const TileOut &out) {
     if (prec == RPF_DIST_BF16)
-        sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+        sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
     else if (prec == RPF_DIST_FP16)
-        sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+        sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
     else
-        sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, tau, excl, cnt, ent, cap);
+        sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
 }
 
 static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
@@ -1224,12 +1314,18 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
     // threshold of the union of those leaves
     const int lcap = 256;
-    const int cap1 = v.max_leaf * cs.B;
-    const int cap2 = kFinalCap - lcap;
-    const int cap = std::max(cap1, cap2);
+    const int cap1 = v.max_leaf * cs.B;  // Phase I slots per row (index / lb / ub arrays)
+    const int cap2 = kFinalCap - lcap;   // Phase II records per row
+    // the Phase II records reuse the Phase I arrays, dead once the first merge has run
+    const size_t first_bytes = (size_t)rows * cap1 * 12;
+    const size_t second_bytes = (size_t)rows * cap2 * sizeof(Ent);
+    uint8_t *region = ws.get<uint8_t>(std::max(first_bytes, second_bytes) + 256);
     float *tau = ws.get<float>(rows * 4);
     int32_t *cnt = ws.get<int32_t>(rows * 4);
-    Ent *ent = ws.get<Ent>((size_t)rows * cap * sizeof(Ent));
+    Ent *ent = reinterpret_cast<Ent *>(region);
+    int32_t *pidx = reinterpret_cast<int32_t *>(region);
+    float *plb = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 4);
+    float *pub = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 8);
     Ent *list = ws.get<Ent>((size_t)rows * lcap * sizeof(Ent));
     int32_t *lcnt = ws.get<int32_t>(rows * 4);
     int32_t *fb_list = ws.get<int32_t>(rows * 4);
@@ -1237,37 +1333,52 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     if (!ws.ok) return fail(RPF_ENOMEM, "kNN workspace allocation failed");
     hipMemsetAsync(cnt, 0, rows * 4, s);
     hipMemsetAsync(fb_cnt, 0, 16, s);
-    hipMemsetAsync(v.stats, 0, 32, s);
+    hipMemsetAsync(v.stats, 0, 40, s);
     const BoundCoef bc = bound_coef(v.prec, v.d);
     const int MB = v.job_mb;
+    TileOut o1;
+    o1.mode = 0;
+    o1.t0 = 0;
+    o1.ML = v.max_leaf;
+    o1.cap = cap1;
+    o1.ent = nullptr;
+    o1.cnt = cnt;
+    o1.tau = nullptr;
+    o1.pidx = pidx;
+    o1.plb = plb;
+    o1.pub = pub;
     {
         ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, nullptr, cs.excl, cnt,
-                         ent, cap);
+            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, cs.excl, o1);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
-                          cs.a_dest, v.perm, bc, nullptr, cs.excl, cnt, ent, cap);
+                          cs.a_dest, v.perm, bc, cs.excl, o1);
     }
     {
         ProfScope ps(s, "merge_first", 0, 0);
-        hipLaunchKernelGGL(k_merge_first, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B, cnt, ent,
-                           cap, tau, list, lcnt, lcap);
+        hipLaunchKernelGGL(k_merge_first, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B,
+                           v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
         launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0) {
+        TileOut o2 = o1;
+        o2.mode = 1;
+        o2.cap = cap2;
+        o2.tau = tau;
+        o2.ent = ent;
         ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, tau, cs.excl, cnt,
-                         ent, cap2);
+            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, cs.excl, o2);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
-                          cs.a_dest, v.perm, bc, tau, cs.excl, cnt, ent, cap2);
+                          cs.a_dest, v.perm, bc, cs.excl, o2);
     }
     FinalArgs fa;
     fa.list = list; fa.lcnt = lcnt; fa.lcap = lcap; fa.cnt = cnt; fa.ent = ent; fa.cap = cap2; fa.K = K;
     fa.X = v.X; fa.Qr = cs.Qr; fa.d = v.d; fa.win = rerank_window(v.d); fa.out_idx = out_idx;
-    fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.stats = v.stats;
+    fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.npts = v.n;
+    fa.stats = v.stats;
     const bool vec = (v.d % 4) == 0;
     {
         ProfScope ps(s, "final_rerank", 0, 0);

@@ -30,7 +30,7 @@ void launch_copy_segments(hipStream_t s, const LeafDesc *segs, int nseg, int T, 
 void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T);
 void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves,
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
-                          void *Xc, float2 *nrm);
+                          void *Xc, float2 *nrm, int max_leaf, int lds_limit);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
 
 rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s);
@@ -258,12 +258,15 @@ rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count
     return RPF_OK;
 }
 
+// forest arrays come from the device's stream-ordered pool (kept warm), so repeated
+// build / free cycles reuse memory instead of mapping fresh pages
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
                     f->d_copy, f->d_jobs, f->stats};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) hipFreeAsync(p, nullptr);
+    hipStreamSynchronize(nullptr);
 }
 
 rpf_status rpf_free(rpf_forest *f) {
@@ -281,6 +284,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     if (!p) return fail(RPF_EINVAL, "rpf_build: params is NULL");
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: n must be in [1, 2^31)");
     if (d < 1) return fail(RPF_EINVAL, "rpf_build: d must be >= 1");
+    if (d > 4096) return fail(RPF_EINVAL, "rpf_build: d above 4096 is not supported (per-block staging)");
     if (p->n_trees < 1 || p->n_trees > 65535) return fail(RPF_EINVAL, "rpf_build: n_trees must be in [1, 65535]");
     if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
     if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
@@ -378,6 +382,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         return fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(bytes + tmp_bytes) +
                                     " bytes, over mem_budget_bytes");
 
+    keep_pool_memory(dev);
     rpf_forest *f = new rpf_forest();
     f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
     f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
@@ -389,13 +394,13 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         delete f;
         return st;
     };
-#define RPF_ALLOC(ptr, sz)                                                                     \
-    do {                                                                                       \
-        size_t _sz = (size_t)(sz);                                                             \
-        if (_sz) {                                                                             \
-            rpf_status _st = check_hip(hipMalloc((void **)&(ptr), _sz), "hipMalloc " #ptr);   \
-            if (_st != RPF_OK) return bail(RPF_ENOMEM);                                        \
-        }                                                                                      \
+#define RPF_ALLOC(ptr, sz)                                                                            \
+    do {                                                                                              \
+        size_t _sz = (size_t)(sz);                                                                    \
+        if (_sz) {                                                                                    \
+            rpf_status _st = check_hip(hipMallocAsync((void **)&(ptr), _sz, s), "allocation " #ptr); \
+            if (_st != RPF_OK) return bail(RPF_ENOMEM);                                               \
+        }                                                                                             \
     } while (0)
 
     RPF_ALLOC(f->X, (size_t)n * d * 4);
@@ -417,6 +422,29 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     RPF_ALLOC(f->d_leaves, nleaf * sizeof(LeafDesc));
     if (ncopy_tot) RPF_ALLOC(f->d_copy, ncopy_tot * sizeof(LeafDesc));
 
+    // ---- descriptors (host copies stay alive until the synchronisation below)
+    std::vector<SegDesc> all_segs;
+    std::vector<ChunkDesc> all_chunks;
+    std::vector<LeafDesc> all_copy;
+    for (auto &lv : levels) {
+        all_segs.insert(all_segs.end(), lv.segs.begin(), lv.segs.end());
+        all_chunks.insert(all_chunks.end(), lv.chunks.begin(), lv.chunks.end());
+        all_copy.insert(all_copy.end(), lv.copy.begin(), lv.copy.end());
+    }
+    std::vector<int32_t> hl((size_t)4 << L, -1);
+    for (size_t i = 0; i < leaves.size(); i++) hl[leaves[i].heap] = (int32_t)i;
+    std::vector<double> nan_row((size_t)T * H, NAN);
+    if (nseg_tot) hipMemcpyAsync(f->d_segs, all_segs.data(), nseg_tot * sizeof(SegDesc), hipMemcpyHostToDevice, s);
+    if (nchunk_tot)
+        hipMemcpyAsync(f->d_chunks, all_chunks.data(), nchunk_tot * sizeof(ChunkDesc), hipMemcpyHostToDevice, s);
+    if (ncopy_tot) hipMemcpyAsync(f->d_copy, all_copy.data(), ncopy_tot * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
+    if (H) hipMemcpyAsync(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice, s);
+    hipMemsetAsync(f->split_idx, 0xff, (size_t)T * H * 4, s);
+    hipMemsetAsync(f->chosen, 0xff, (size_t)T * H * 4, s);
+    launch_check(s, "descriptor upload");
+
     // ---- inputs: copy, then reject non-finite values (one synchronisation)
     rpf_status st;
     if ((st = check_hip(hipMemcpyAsync(f->X, X, (size_t)n * d * 4, hipMemcpyDeviceToDevice, s), "copy X")) != RPF_OK)
@@ -436,32 +464,6 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
     if (flags[1]) { fail(RPF_EINVAL, "rpf_build: directions hold NaN or Inf"); return bail(RPF_EINVAL); }
     hipMemsetAsync(f->err, 0, 64, s);
-
-    // ---- descriptors
-    {
-        std::vector<SegDesc> all_segs;
-        std::vector<ChunkDesc> all_chunks;
-        std::vector<LeafDesc> all_copy;
-        for (auto &lv : levels) {
-            all_segs.insert(all_segs.end(), lv.segs.begin(), lv.segs.end());
-            all_chunks.insert(all_chunks.end(), lv.chunks.begin(), lv.chunks.end());
-            all_copy.insert(all_copy.end(), lv.copy.begin(), lv.copy.end());
-        }
-        if (nseg_tot) hipMemcpy(f->d_segs, all_segs.data(), nseg_tot * sizeof(SegDesc), hipMemcpyHostToDevice);
-        if (nchunk_tot) hipMemcpy(f->d_chunks, all_chunks.data(), nchunk_tot * sizeof(ChunkDesc), hipMemcpyHostToDevice);
-        if (ncopy_tot) hipMemcpy(f->d_copy, all_copy.data(), ncopy_tot * sizeof(LeafDesc), hipMemcpyHostToDevice);
-        hipMemcpy(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice);
-        std::vector<int32_t> hl((size_t)4 << L, -1);
-        for (size_t i = 0; i < leaves.size(); i++) hl[leaves[i].heap] = (int32_t)i;
-        hipMemcpy(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice);
-    }
-    launch_check(s, "descriptor upload");
-    hipMemsetAsync(f->split_idx, 0xff, (size_t)T * H * 4, s);
-    hipMemsetAsync(f->chosen, 0xff, (size_t)T * H * 4, s);
-    {   // NaN for heap slots that are not internal nodes
-        std::vector<double> nan_row((size_t)T * H, NAN);
-        if (H) hipMemcpy(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice);
-    }
 
     // ---- temporaries of the multi-block path
     LargeBufs lb{};
@@ -520,7 +522,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     {
         ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * (double)esz + 16), 0);
         launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of,
-                             f->centroid, f->Xc, f->nrm);
+                             f->centroid, f->Xc, f->nrm, max_leaf, lds_max);
         launch_check(s, "leaf_finalize");
     }
     for (void *q : tmps) hipFreeAsync(q, s);
@@ -553,6 +555,8 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
                         j.b_rows = std::min(TR, lf.size - J * TR);
                         j.tree = t;
                         j.same = I == J;
+                        j.b_pos = J * TR;
+                        j.leaf_m = lf.size;
                         jobs.push_back(j);
                     }
             }
@@ -560,7 +564,8 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         for (auto &lf : leaves) f->tile_flops_tree += 2.0 * d * (double)lf.size * (double)lf.size;
         f->job_mb = MB;
         RPF_ALLOC(f->d_jobs, jobs.size() * sizeof(TileJob));
-        hipMemcpy(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice);
+        hipMemcpyAsync(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s);
+        hipStreamSynchronize(s);  // the host job list dies with this scope
         f->bytes += jobs.size() * sizeof(TileJob);
     }
 #undef RPF_ALLOC
@@ -631,10 +636,13 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
 
 rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *stream) {
     if (!f || !out) return fail(RPF_EINVAL, "rpf_last_knn_stats: NULL pointer");
-    unsigned long long v[4];
+    unsigned long long v[5];
     hipMemcpyAsync(v, f->stats, sizeof(v), hipMemcpyDeviceToHost, (hipStream_t)stream);
     rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_last_knn_stats");
     if (st != RPF_OK) return st;
+    if (v[4] != 0)
+        return fail(RPF_EINTERNAL, "rpf_last_knn_stats: " + std::to_string(v[4]) +
+                                       " rows met a candidate index outside the data set (recomputed exhaustively)");
     out->rows = (int64_t)v[0] + (int64_t)v[1];
     out->fallback_rows = (int64_t)v[1];
     out->reranked32 = (int64_t)v[2];

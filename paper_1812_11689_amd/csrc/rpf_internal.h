@@ -98,6 +98,8 @@ struct TileJob {       // one MFMA tile: A rows x B rows (<= 32*MB each) of one 
     int32_t b_rows;
     int32_t tree;
     int32_t same;      // 1: A and B are the same positions (all-points diagonal tile)
+    int32_t b_pos;     // offset of the first B row inside its leaf
+    int32_t leaf_m;    // size of the leaf the B rows belong to
 };
 
 // read-only view of a forest for the kNN launchers
@@ -124,6 +126,7 @@ void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *fla
 // records the first failing launch of the calling thread (name + HIP error); with
 // RPF_SYNC_CHECK=1 in the environment it also synchronises after every launch
 void launch_check(hipStream_t s, const char *name);
+void keep_pool_memory(int dev);  // keep the stream-ordered pool's memory between calls
 std::string take_launch_error();
 
 // ---------------------------------------------------------------- order-preserving keys
@@ -275,6 +278,51 @@ __device__ inline float group8_dist32(const float *__restrict__ a, const float *
     v = v + shfl_xor_f(v, 2);
     v = v + shfl_xor_f(v, 4);
     return v;
+}
+
+// both canonical distances from one read of the two rows (binary32 and binary64 classes)
+template <bool VEC>
+__device__ inline void group8_dist32_64(const float *__restrict__ a, const float *__restrict__ b, int d, int g,
+                                        float &D32, double &D64) {
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int j = 4 * g; j < d; j += 32) {
+        float4 av, bv;
+        if (VEC) {
+            av = *reinterpret_cast<const float4 *>(a + j);
+            bv = *reinterpret_cast<const float4 *>(b + j);
+        } else {
+            av.x = a[j];
+            bv.x = b[j];
+            av.y = j + 1 < d ? a[j + 1] : 0.f;
+            bv.y = j + 1 < d ? b[j + 1] : 0.f;
+            av.z = j + 2 < d ? a[j + 2] : 0.f;
+            bv.z = j + 2 < d ? b[j + 2] : 0.f;
+            av.w = j + 3 < d ? a[j + 3] : 0.f;
+            bv.w = j + 3 < d ? b[j + 3] : 0.f;
+        }
+        const float e0 = av.x - bv.x, e1 = av.y - bv.y, e2 = av.z - bv.z, e3 = av.w - bv.w;
+        f0 = __builtin_fmaf(e0, e0, f0);
+        f1 = __builtin_fmaf(e1, e1, f1);
+        f2 = __builtin_fmaf(e2, e2, f2);
+        f3 = __builtin_fmaf(e3, e3, f3);
+        const double d0 = (double)av.x - (double)bv.x, d1 = (double)av.y - (double)bv.y;
+        const double d2 = (double)av.z - (double)bv.z, d3 = (double)av.w - (double)bv.w;
+        s0 = __builtin_fma(d0, d0, s0);
+        s1 = __builtin_fma(d1, d1, s1);
+        s2 = __builtin_fma(d2, d2, s2);
+        s3 = __builtin_fma(d3, d3, s3);
+    }
+    float v = (f0 + f1) + (f2 + f3);
+    v = v + shfl_xor_f(v, 1);
+    v = v + shfl_xor_f(v, 2);
+    v = v + shfl_xor_f(v, 4);
+    D32 = v;
+    double u = (s0 + s1) + (s2 + s3);
+    u = u + shfl_xor_d(u, 1);
+    u = u + shfl_xor_d(u, 2);
+    u = u + shfl_xor_d(u, 4);
+    D64 = u;
 }
 
 // ---------------------------------------------------------------- host-side launch helpers
