@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--recall-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
     ap.add_argument("--cpu-trees", type=int, default=1,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
@@ -113,6 +115,14 @@ def main():
     gen_s = time.time() - t0
     print(f"# workload {w.name}: n={n} d={d} T={T} n0={n0} K={K} L={L} (generated in {gen_s:.1f}s)",
           file=sys.stderr, flush=True)
+
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written", file=sys.stderr, flush=True)
+        del src, dst
 
     def step(prec):
         f = rpf.build(X, T, n0, Rd, dist_prec=prec)

@@ -123,12 +123,16 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);
 
 /* Counters of the last rpf_all_knn / rpf_query on this forest (host, synchronises the
  * stream): rows that fell back to the exhaustive candidate scan because a pruning buffer
- * overflowed, and the total number of candidates re-ranked in binary32 / binary64.
+ * overflowed, the total number of candidates re-ranked in binary32 / binary64, and the
+ * candidate records that reached the final merge (kept from the first trees' leaves, and
+ * emitted by the remaining trees below the row's threshold; rows that overflowed count
+ * what they attempted).
  * Returns RPF_EINTERNAL when the last call met a candidate index outside [0, n) in its
  * pruning buffers (an internal error: such rows are recomputed by the exhaustive scan,
  * never dereferenced, so the outputs stay correct). */
 typedef struct {
     int64_t rows, fallback_rows, reranked32, reranked64;
+    int64_t first_phase_kept, second_phase_emitted;
 } rpf_knn_stats;
 
 rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out_host, void *stream);
@@ -146,6 +150,14 @@ typedef struct {
 rpf_status rpf_profile_enable(int32_t on);
 rpf_status rpf_profile_reset(void);
 rpf_status rpf_profile_read(rpf_profile_record *out_host, int32_t cap, int32_t *count);
+
+/* Device memory of forests and of the per-call kNN workspaces comes from a cache kept by
+ * the library: blocks obtained from hipMalloc are reused by later calls (a block last used
+ * on another stream is ordered behind that use by an event) and are not returned to the
+ * runtime when a forest is freed.  This call hipFree's every idle cached block of `device`
+ * (device < 0: of every device); blocks in use by live forests or running calls stay.  The
+ * cache also empties itself once when an allocation fails, before it reports RPF_ENOMEM. */
+rpf_status rpf_release_cached_memory(int32_t device);
 
 const char *rpf_last_error(void);
 

@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",
 ]
-SOURCES = ["rpf_api.hip", "build_kernels.hip", "knn_kernels.hip"]
+SOURCES = ["rpf_api.hip", "build_kernels.hip", "knn_kernels.hip", "device_cache.hip"]
 
 
 def _compile(src: str) -> str:
@@ -41,7 +41,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 3) -> str:
+def build(jobs: int = 4) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -757,13 +757,19 @@ struct FinalArgs {
     int32_t *fb_list;   // rows for the exhaustive fallback
     int32_t *fb_cnt;
     int64_t npts;       // rows of X: every candidate index lies in [0, npts)
-    unsigned long long *stats;  // [rows, fallback, reranked32, reranked64, bad_index]
+    unsigned long long *stats;  // [kStatSlots][8]: rows, fallback, reranked32, reranked64, bad_index,
+                                //                 kept1, emitted2 (summed over slots by the host)
 };
+
+// counters are spread over slots by block so that a million rows do not meet on one address
+__device__ inline void stat_add(const FinalArgs &A, int i, unsigned long long v) {
+    atomicAdd(&A.stats[(blockIdx.x & (kStatSlots - 1)) * 8 + i], v);
+}
 
 __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
     const int slot = atomicAdd(A.fb_cnt, 1);
     A.fb_list[slot] = (int32_t)a;
-    atomicAdd(&A.stats[1], 1ull);
+    stat_add(A, 1, 1ull);
 }
 
 // One wave per result row, four rows per block.  Entries stay in registers; an LDS hash
@@ -784,6 +790,10 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     float *s_q = s_qall + w * dq;
     const int K = A.K;
     const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    if (lane == 0) {
+        stat_add(A, 5, (unsigned long long)max(c1, 0));
+        stat_add(A, 6, (unsigned long long)max(c2, 0));
+    }
     if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kFinalCap) {
         if (lane == 0) push_fallback(A, a);
         return;
@@ -824,7 +834,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     wave_sync();
     if (__ballot(bad)) {  // counted for the host to report; the row is recomputed exhaustively
         if (lane == 0) {
-            atomicAdd(&A.stats[4], 1ull);
+            stat_add(A, 4, 1ull);
             push_fallback(A, a);
         }
         return;
@@ -914,9 +924,9 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         A.out_dist[a * K + k] = ok ? (float)sqrt(s_wd[w][k]) : INFINITY;
     }
     if (lane == 0) {
-        atomicAdd(&A.stats[0], 1ull);
-        atomicAdd(&A.stats[2], (unsigned long long)nr);
-        atomicAdd(&A.stats[3], (unsigned long long)nw);
+        stat_add(A, 0, 1ull);
+        stat_add(A, 2, (unsigned long long)nr);
+        stat_add(A, 3, (unsigned long long)nw);
     }
 }
 
@@ -1218,7 +1228,7 @@ static void tile_dispatch(int prec, int MB, hipStream_t s, int64_t njobs, const 
         tile_dispatch_mb<RPF_DIST_FP32>(MB, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, excl, out);
 }
 
-// stream-ordered workspace
+// per-call workspace from the caching allocator; blocks go back ordered after the call's work
 struct Workspace {
     hipStream_t s;
     std::vector<void *> ptrs;
@@ -1226,9 +1236,8 @@ struct Workspace {
     explicit Workspace(hipStream_t st) : s(st) {}
     template <typename P>
     P *get(size_t bytes) {
-        void *p = nullptr;
-        if (!bytes) bytes = 16;
-        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        void *p = cache_alloc(bytes ? bytes : 16, s);
+        if (!p) {
             ok = false;
             return nullptr;
         }
@@ -1236,20 +1245,9 @@ struct Workspace {
         return static_cast<P *>(p);
     }
     ~Workspace() {
-        for (void *p : ptrs) hipFreeAsync(p, s);
+        for (void *p : ptrs) cache_free(p, s);
     }
 };
-
-void keep_pool_memory(int dev) {
-    static bool done[64] = {false};
-    if (dev < 0 || dev >= 64 || done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done[dev] = true;
-}
 
 // common candidate stage once the tile jobs, A rows and per-row metadata are known
 struct CandStage {
@@ -1333,7 +1331,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     if (!ws.ok) return fail(RPF_ENOMEM, "kNN workspace allocation failed");
     hipMemsetAsync(cnt, 0, rows * 4, s);
     hipMemsetAsync(fb_cnt, 0, 16, s);
-    hipMemsetAsync(v.stats, 0, 40, s);
+    hipMemsetAsync(v.stats, 0, kStatSlots * 8 * 8, s);
     const BoundCoef bc = bound_coef(v.prec, v.d);
     const int MB = v.job_mb;
     TileOut o1;
@@ -1412,7 +1410,6 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     const ForestView v = view(f);
     int dev = 0;
     hipGetDevice(&dev);
-    keep_pool_memory(dev);
     CandStage cs;
     cs.rows = v.n;
     cs.B = first_trees(v.T, K);
@@ -1458,15 +1455,14 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     const ForestView v = view(f);
     int dev = 0;
     hipGetDevice(&dev);
-    keep_pool_memory(dev);
     {   // queries must be finite (one synchronisation)
-        int32_t *flag = nullptr;
-        if (hipMallocAsync((void **)&flag, 16, s) != hipSuccess) return fail(RPF_ENOMEM, "rpf_query: allocation");
+        int32_t *flag = static_cast<int32_t *>(cache_alloc(16, s));
+        if (!flag) return fail(RPF_ENOMEM, "rpf_query: allocation");
         hipMemsetAsync(flag, 0, 16, s);
         launch_nonfinite(s, Q, m * v.d, flag);
         int32_t h = 0;
         hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
-        hipFreeAsync(flag, s);
+        cache_free(flag, s);
         rpf_status st = check_hip(hipStreamSynchronize(s), "rpf_query input check");
         if (st != RPF_OK) return st;
         if (h) return fail(RPF_EINVAL, "rpf_query: Q holds NaN or Inf");

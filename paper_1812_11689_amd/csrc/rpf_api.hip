@@ -258,15 +258,13 @@ rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count
     return RPF_OK;
 }
 
-// forest arrays come from the device's stream-ordered pool (kept warm), so repeated
-// build / free cycles reuse memory instead of mapping fresh pages
+// forest arrays come from the library's caching allocator, so repeated build / free
+// cycles reuse device blocks instead of mapping fresh pages; callers synchronise first
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
                     f->d_copy, f->d_jobs, f->stats};
-    for (void *p : ptrs)
-        if (p) hipFreeAsync(p, nullptr);
-    hipStreamSynchronize(nullptr);
+    for (void *p : ptrs) cache_free(p, nullptr);
 }
 
 rpf_status rpf_free(rpf_forest *f) {
@@ -382,7 +380,6 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         return fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(bytes + tmp_bytes) +
                                     " bytes, over mem_budget_bytes");
 
-    keep_pool_memory(dev);
     rpf_forest *f = new rpf_forest();
     f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
     f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
@@ -398,8 +395,11 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     do {                                                                                              \
         size_t _sz = (size_t)(sz);                                                                    \
         if (_sz) {                                                                                    \
-            rpf_status _st = check_hip(hipMallocAsync((void **)&(ptr), _sz, s), "allocation " #ptr); \
-            if (_st != RPF_OK) return bail(RPF_ENOMEM);                                               \
+            (ptr) = static_cast<std::remove_reference_t<decltype(ptr)>>(cache_alloc(_sz, s));                                \
+            if (!(ptr)) {                                                                             \
+                fail(RPF_ENOMEM, "rpf_build: device allocation of " #ptr " failed");                 \
+                return bail(RPF_ENOMEM);                                                              \
+            }                                                                                         \
         }                                                                                             \
     } while (0)
 
@@ -415,7 +415,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     RPF_ALLOC(f->Xc, (size_t)T * n * dp * esz);
     RPF_ALLOC(f->nrm, (size_t)T * n * 8);
     RPF_ALLOC(f->err, 64);
-    RPF_ALLOC(f->stats, 64);
+    RPF_ALLOC(f->stats, kStatSlots * 8 * 8);
     RPF_ALLOC(f->heap_leaf, ((size_t)4 << L) * sizeof(int32_t));  // heap ids < 2^(L+1)
     if (nseg_tot) RPF_ALLOC(f->d_segs, nseg_tot * sizeof(SegDesc));
     if (nchunk_tot) RPF_ALLOC(f->d_chunks, nchunk_tot * sizeof(ChunkDesc));
@@ -454,7 +454,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
                         "copy directions")) != RPF_OK)
         return bail(st);
     hipMemsetAsync(f->err, 0, 64, s);
-    hipMemsetAsync(f->stats, 0, 64, s);
+    hipMemsetAsync(f->stats, 0, kStatSlots * 8 * 8, s);
     launch_nonfinite(s, f->X, n * d, f->err);
     launch_nonfinite(s, f->R, T * H * n_try * d, f->err + 1);
     launch_check(s, "nonfinite check");
@@ -470,7 +470,8 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     std::vector<void *> tmps;
     auto talloc = [&](void **ptr, size_t sz) -> bool {
         if (!sz) { *ptr = nullptr; return true; }
-        if (hipMallocAsync(ptr, sz, s) != hipSuccess) return false;
+        *ptr = cache_alloc(sz, s);
+        if (!*ptr) return false;
         tmps.push_back(*ptr);
         return true;
     };
@@ -486,7 +487,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         ok &= talloc((void **)&lb.part, (size_t)T * max_chunk_large * 8);
     }
     if (!ok) {
-        for (void *q : tmps) hipFreeAsync(q, s);
+        for (void *q : tmps) cache_free(q, s);
         fail(RPF_ENOMEM, "rpf_build: temporary allocation failed");
         return bail(RPF_ENOMEM);
     }
@@ -525,7 +526,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
                              f->centroid, f->Xc, f->nrm, max_leaf, lds_max);
         launch_check(s, "leaf_finalize");
     }
-    for (void *q : tmps) hipFreeAsync(q, s);
+    for (void *q : tmps) cache_free(q, s);
     launch_check(s, "rpf_build tail");
     {
         const std::string le = take_launch_error();
@@ -636,10 +637,12 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
 
 rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *stream) {
     if (!f || !out) return fail(RPF_EINVAL, "rpf_last_knn_stats: NULL pointer");
-    unsigned long long v[5];
-    hipMemcpyAsync(v, f->stats, sizeof(v), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    unsigned long long slots[kStatSlots * 8], v[8] = {};
+    hipMemcpyAsync(slots, f->stats, sizeof(slots), hipMemcpyDeviceToHost, (hipStream_t)stream);
     rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_last_knn_stats");
     if (st != RPF_OK) return st;
+    for (int k = 0; k < kStatSlots; k++)
+        for (int i = 0; i < 8; i++) v[i] += slots[k * 8 + i];
     if (v[4] != 0)
         return fail(RPF_EINTERNAL, "rpf_last_knn_stats: " + std::to_string(v[4]) +
                                        " rows met a candidate index outside the data set (recomputed exhaustively)");
@@ -647,6 +650,8 @@ rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *str
     out->fallback_rows = (int64_t)v[1];
     out->reranked32 = (int64_t)v[2];
     out->reranked64 = (int64_t)v[3];
+    out->first_phase_kept = (int64_t)v[5];
+    out->second_phase_emitted = (int64_t)v[6];
     return RPF_OK;
 }
 

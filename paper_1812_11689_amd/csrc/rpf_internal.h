@@ -126,7 +126,13 @@ void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *fla
 // records the first failing launch of the calling thread (name + HIP error); with
 // RPF_SYNC_CHECK=1 in the environment it also synchronises after every launch
 void launch_check(hipStream_t s, const char *name);
-void keep_pool_memory(int dev);  // keep the stream-ordered pool's memory between calls
+// caching device allocator (device_cache.hip): blocks stay with the library and are reused;
+// a block returned on one stream is safe to hand to another (event-ordered)
+constexpr int kStatSlots = 64;  // kNN counters: [kStatSlots][8] unsigned 64-bit, summed on the host
+void *cache_alloc(size_t bytes, hipStream_t s);  // nullptr when the device is out of memory
+void cache_free(void *p, hipStream_t s);          // p's last use is the work queued on s
+uint64_t cache_held_bytes(int dev);
+void cache_release(int dev);                      // hipFree idle blocks (dev < 0: every device)
 std::string take_launch_error();
 
 // ---------------------------------------------------------------- order-preserving keys

@@ -22,7 +22,7 @@ PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "rpf_free", "rpf_tree_dump",
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
-           "rpf_profile_read", "rpf_last_error"]
+           "rpf_profile_read", "rpf_release_cached_memory", "rpf_last_error"]
 
 
 class RpfError(RuntimeError):
@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
 
 class KnnStats(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int64), ("fallback_rows", ctypes.c_int64), ("reranked32", ctypes.c_int64),
-                ("reranked64", ctypes.c_int64)]
+                ("reranked64", ctypes.c_int64), ("first_phase_kept", ctypes.c_int64),
+                ("second_phase_emitted", ctypes.c_int64)]
 
 
 class ProfileRecord(ctypes.Structure):
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.rpf_profile_reset.argtypes = []
     lib.rpf_profile_read.restype = i32
     lib.rpf_profile_read.argtypes = [ctypes.POINTER(ProfileRecord), i32, ctypes.POINTER(i32)]
+    lib.rpf_release_cached_memory.restype = i32
+    lib.rpf_release_cached_memory.argtypes = [i32]
     lib.rpf_last_error.restype = ctypes.c_char_p
     lib.rpf_last_error.argtypes = []
     _lib = lib
@@ -225,3 +228,8 @@ def profile_read() -> dict:
         out[r.name.decode()] = dict(launches=r.launches, total_ms=r.total_ms, algo_bytes=r.algo_bytes,
                                     algo_flops=r.algo_flops)
     return out
+
+
+def release_cached_memory(device: int = -1):
+    """Return the library's idle cached device blocks to the runtime."""
+    _check(load().rpf_release_cached_memory(device))
