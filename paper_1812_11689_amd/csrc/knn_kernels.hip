@@ -348,25 +348,26 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
 }
 
 // All-points tile of one leaf whose rows all fit (m <= 32 NB): the Gram matrix is symmetric,
-// so only blocks (i, j) with i <= j run on MFMA and an off-diagonal block emits both
-// (row -> col) and (col -> row).  Wave w owns block rows w and NB-1-w (NB + 1 blocks per
-// wave), which balances the triangle; both operands come from the same LDS tile.
+// so only blocks (i, j) with i <= j run on MFMA and an off-diagonal block serves both
+// (row -> col) and (col -> row).  Block rows p and NB-1-p form a pair of NB + 1 blocks,
+// split between two waves (ceil and floor of half), so NB waves share the triangle evenly;
+// both operands come from the same LDS tile.  Blocks wholly past the leaf are skipped.
 template <int NB, int PREC, int MODE>
-__global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
+__global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
     const TileJob *__restrict__ jobs, const void *__restrict__ A_, int dp, int64_t stride_tree,
     const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, int exclude_self, TileOut out) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
-    constexpr int NW = NB >= 2 ? NB / 2 : 1;
+    constexpr int NW = NB >= 2 ? NB : 1;
     constexpr int NT = 64 * NW;
-    constexpr int SLOTS = NB >= 2 ? NB + 1 : 1;
+    constexpr int PAIR = NB + 1;
+    constexpr int SLOTS = NB >= 2 ? (PAIR + 1) / 2 : 1;
     __shared__ __align__(16) T s_a[M * C::LDW];
     __shared__ float s_n[M], s_r[M], s_phi[M], s_tau[M];
     __shared__ int32_t s_pt[M];
     __shared__ float s_max[2];
-    __shared__ uint32_t s_qn[NW];
-    __shared__ uint2 s_que[NW][kQueue];
+    __shared__ uint2 s_que[MODE == 1 ? NW : 1][MODE == 1 ? kQueue : 1];
 
     const TileJob job = jobs[blockIdx.x];
     const int t = job.tree;
@@ -392,7 +393,6 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
             s_tau[r] = -1.f;
         }
     }
-    if (tid < NW) s_qn[tid] = 0;
     __syncthreads();
     if (tid < 64) {
         float mn = 0.f, mr = 0.f;
@@ -419,20 +419,29 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
         }
     }
 
-    // every leaf of the launch has more than 32 (NB/2) rows, so the NB x NB block grid is
-    // used as is; padding rows are zero in LDS and skipped by the epilogue
-    auto slot_block = [&](int sl, int &bi, int &bj) {
-        const int r1 = wu, r2 = NB - 1 - wu, len1 = NB - r1;
-        if (sl < len1) {
-            bi = r1;
-            bj = r1 + sl;
-        } else if (r2 > r1 && sl - len1 < NB - r2) {
-            bi = r2;
-            bj = r2 + (sl - len1);
+    // scalar block coordinates of every slot of this wave; act = the block holds leaf rows
+    int sbi[SLOTS], sbj[SLOTS];
+    bool act[SLOTS];
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; sl++) {
+        int bi = -1, bj = -1;
+        if (NB == 1) {
+            bi = bj = 0;
         } else {
-            bi = bj = -1;
+            const int p = wu >> 1, q = (wu & 1) * SLOTS + sl;
+            const int r1 = p, r2 = NB - 1 - p, len1 = NB - r1;
+            if (q < len1) {
+                bi = r1;
+                bj = r1 + q;
+            } else if (q < PAIR) {
+                bi = r2;
+                bj = r2 + (q - len1);
+            }
         }
-    };
+        act[sl] = bj >= 0 && 32 * bj < m;
+        sbi[sl] = bi < 0 ? 0 : bi;
+        sbj[sl] = bj < 0 ? 0 : bj;
+    }
     f32x16 acc[SLOTS];
 #pragma unroll
     for (int sl = 0; sl < SLOTS; sl++)
@@ -440,9 +449,6 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
         for (int v = 0; v < 16; v++) acc[sl][v] = 0.f;
     const int fr = lane & 31;
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
-    int sbi[SLOTS], sbj[SLOTS];  // scalar block coordinates of every slot of this wave
-#pragma unroll
-    for (int sl = 0; sl < SLOTS; sl++) slot_block(sl, sbi[sl], sbj[sl]);
     for (int k0 = 0; k0 < dp; k0 += C::KC) {
         __syncthreads();
         stage_rows<PREC>(s_a, A, m, M, dp, k0, NT);
@@ -460,14 +466,16 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
             }
 #pragma unroll
             for (int sl = 0; sl < SLOTS; sl++)
-                acc[sl] = mfma_step<PREC>(reinterpret_cast<const T *>(&fa[sl]), reinterpret_cast<const T *>(&fb[sl]),
-                                          acc[sl]);
+                if (act[sl])
+                    acc[sl] = mfma_step<PREC>(reinterpret_cast<const T *>(&fa[sl]),
+                                              reinterpret_cast<const T *>(&fb[sl]), acc[sl]);
         }
     }
 
     if constexpr (MODE == 0) {
 #pragma unroll
         for (int sl = 0; sl < SLOTS; sl++) {
+            if (!act[sl]) continue;
             const int bi = sbi[sl], bj = sbj[sl];
             const bool diag = bi == bj;
             const int col = 32 * bj + (lane & 31);
@@ -489,201 +497,185 @@ __global__ __launch_bounds__(NB >= 2 ? 32 * NB : 64) void k_tile_sym(
         return;
     }
     if constexpr (MODE == 1) {
-    // Phase II: a cheap test over every pair (both directions); exact bounds only for the
-    // few that pass, through a per-wave LDS queue
-    uint32_t *qn = &s_qn[wu];
-    uint2 *que = s_que[wu];
+        // Phase II: a cheap test over every pair (both directions); the pairs that pass are
+        // compacted by ballot into a per-wave LDS queue, whose exact bounds and emissions
+        // run when it would overflow and at the end (wave-uniform decisions throughout)
+        uint2 *que = s_que[wu];
+        uint32_t qc = 0;
+        auto flush = [&](uint32_t nq) {
+            wave_sync();
+            for (uint32_t i = lane; i < nq; i += 64) {
+                const uint2 e = que[i];
+                const int row = e.x & 255, col = (e.x >> 8) & 255;
+                float lb, ub;
+                pair_bounds(s_n[row], s_n[col], s_r[row], s_r[col], __uint_as_float(e.y), bc, lb, ub);
+                if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
+                if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
+            }
+            wave_sync();
+        };
 #pragma unroll
-    for (int sl = 0; sl < SLOTS; sl++) {
-        const int bi = sbi[sl], bj = sbj[sl];
-        const bool diag = bi == bj;
-        const int col = 32 * bj + (lane & 31);
-        const bool colok = col < m;
-        const float ncol = s_n[col];
-        const float phicol = s_phi[col];
+        for (int sl = 0; sl < SLOTS; sl++) {
+            if (!act[sl]) continue;
+            const int bi = sbi[sl], bj = sbj[sl];
+            const bool diag = bi == bj;
+            const int col = 32 * bj + (lane & 31);
+            const bool colok = col < m;
+            const float ncol = s_n[col];
+            const float phicol = s_phi[col];
 #pragma unroll
-        for (int v = 0; v < 16; v++) {
-            const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            const float g = acc[sl][v];
-            const bool p1 = colok && __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] &&
-                            !(diag && (row > col || (row == col && exclude_self)));
-            const bool p2 = (!diag || row < col) && row < m && __builtin_fmaf(-2.f, g, s_n[row]) <= phicol;
-            if (p1 || p2) {
-                const uint32_t pos = atomicAdd(qn, 1u);
-                if (pos < (uint32_t)kQueue) {
-                    que[pos] = make_uint2((uint32_t)row | ((uint32_t)col << 8) | ((p1 ? 1u : 0u) << 16) |
-                                              ((p2 ? 1u : 0u) << 17),
-                                          __float_as_uint(g));
-                } else {  // queue full (rare): bounds and emission right here
-                    float lb, ub;
-                    pair_bounds(s_n[row], ncol, s_r[row], s_r[col], g, bc, lb, ub);
-                    if (p1 && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
-                    if (p2 && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
+            for (int h = 0; h < 2; h++) {
+                uint32_t bits = 0;  // (p1, p2) of the 8 values of this half, two bits each
+                uint64_t mk[8];
+                uint32_t tot = 0;
+#pragma unroll
+                for (int v8 = 0; v8 < 8; v8++) {
+                    const int v = 8 * h + v8;
+                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const float g = acc[sl][v];
+                    const bool p1 = colok && __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] &&
+                                    !(diag && (row > col || (row == col && exclude_self)));
+                    const bool p2 = (!diag || row < col) && row < m && __builtin_fmaf(-2.f, g, s_n[row]) <= phicol;
+                    bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
+                    mk[v8] = __ballot(p1 || p2);
+                    tot += (uint32_t)__popcll(mk[v8]);
+                }
+                if (qc + tot > (uint32_t)kQueue) {
+                    flush(qc);
+                    qc = 0;
+                }
+#pragma unroll
+                for (int v8 = 0; v8 < 8; v8++) {
+                    const int v = 8 * h + v8;
+                    const uint32_t f = (bits >> (2 * v8)) & 3u;
+                    if (f) {
+                        const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        que[qc + mask_rank(mk[v8])] =
+                            make_uint2((uint32_t)row | ((uint32_t)col << 8) | (f << 16), __float_as_uint(acc[sl][v]));
+                    }
+                    qc += (uint32_t)__popcll(mk[v8]);
                 }
             }
         }
-    }
-    wave_sync();
-    const uint32_t nq = min(*qn, (uint32_t)kQueue);
-    for (uint32_t i = lane; i < nq; i += 64) {
-        const uint2 e = que[i];
-        const int row = e.x & 255, col = (e.x >> 8) & 255;
-        float lb, ub;
-        pair_bounds(s_n[row], s_n[col], s_r[row], s_r[col], __uint_as_float(e.y), bc, lb, ub);
-        if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
-        if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
-    }
+        flush(qc);
     }
 }
 
 // ---------------------------------------------------------------- wave-level selection
 
-// k-th smallest (0-based) of `c` 32-bit keys held in LDS (per-wave region), radix 8 bits.
-__device__ inline uint32_t wave_kth_lds(const uint32_t *vals, int c, int k, uint32_t *hist) {
-    const int lane = lane_id();
-    uint32_t prefix = 0;
-    uint32_t rank = (uint32_t)k;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = lane; b < 256; b += 64) hist[b] = 0;
-        wave_sync();
-        for (int i = lane; i < c; i += 64) {
-            const uint32_t v = vals[i];
-            if (shift == 24 || (v >> (shift + 8)) == (prefix >> (shift + 8))) atomicAdd(&hist[(v >> shift) & 255u], 1u);
-        }
-        wave_sync();
-        uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-        uint32_t sum = h0 + h1 + h2 + h3, x = sum;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        const uint32_t excl = x - sum;
-        uint32_t mybin = 0xffffffffu, mybefore = 0;
-        if (excl <= rank && rank < excl + sum) {
-            uint32_t cc = excl;
-            uint32_t hh[4] = {h0, h1, h2, h3};
-            for (int q = 0; q < 4; q++) {
-                if (rank < cc + hh[q]) {
-                    mybin = 4 * lane + q;
-                    mybefore = cc;
-                    break;
-                }
-                cc += hh[q];
-            }
-        }
-        const uint64_t who = __ballot(mybin != 0xffffffffu);
-        const int src = __builtin_ctzll(who);
-        const uint32_t bin = __shfl(mybin, src, 64);
-        const uint32_t before = __shfl(mybefore, src, 64);
-        prefix |= bin << shift;
-        rank -= before;
-        wave_sync();
-    }
-    return prefix;
-}
-
 __device__ inline uint32_t fkey(float f) {  // non-negative floats (and +inf) order as uint32
     return __float_as_uint(f);
 }
 
-// k-th smallest (0-based) of the flagged 32-bit keys held Q per lane, radix 8 bits
+__device__ inline uint32_t wave_min_u32(uint32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
+    return x;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o, 64));
+    return x;
+}
+
+// An upper bound of the k-th smallest (0-based) of the flagged keys held Q per lane (the
+// wave holds more than k of them), within 2^13 key units of it: 2^-10 relative for the
+// bit patterns of normal non-negative floats.  The bits the smallest and largest key share
+// are fixed; each lower bit down to bit 13 is then set, from the top, exactly when at most
+// k keys lie below the candidate, counted by ballots: no LDS and no atomics.  Every use
+// below is a threshold whose correctness only needs a value at or above the exact one.
 template <int Q>
-__device__ inline uint32_t wave_kth_regs(const uint32_t (&v)[Q], const bool (&ok)[Q], int k, uint32_t *hist) {
-    const int lane = lane_id();
-    uint32_t prefix = 0, rank = (uint32_t)k;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = lane; b < 256; b += 64) hist[b] = 0;
-        wave_sync();
+__device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], const bool (&ok)[Q], int k) {
+    constexpr int kLow = 13;
+    uint32_t lo = 0xffffffffu, hi = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++)
-            if (ok[q] && (shift == 24 || (v[q] >> (shift + 8)) == (prefix >> (shift + 8))))
-                atomicAdd(&hist[(v[q] >> shift) & 255u], 1u);
-        wave_sync();
-        const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-        const uint32_t sum = h0 + h1 + h2 + h3;
-        uint32_t x = sum;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+    for (int q = 0; q < Q; q++)
+        if (ok[q]) {
+            lo = min(lo, v[q]);
+            hi = max(hi, v[q]);
         }
-        const uint32_t excl = x - sum;
-        uint32_t mybin = 0xffffffffu, mybefore = 0;
-        if (excl <= rank && rank < excl + sum) {
-            uint32_t cc = excl;
-            const uint32_t hh[4] = {h0, h1, h2, h3};
-            for (int q = 0; q < 4; q++) {
-                if (rank < cc + hh[q]) {
-                    mybin = 4 * lane + q;
-                    mybefore = cc;
-                    break;
-                }
-                cc += hh[q];
-            }
-        }
-        const uint64_t who = __ballot(mybin != 0xffffffffu);
-        const int src = __builtin_ctzll(who);
-        prefix |= __shfl(mybin, src, 64) << shift;
-        rank -= __shfl(mybefore, src, 64);
-        wave_sync();
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    if (lo >= hi) return lo;
+    const int hb = 31 - __builtin_clz(lo ^ hi);
+    if (hb < kLow) return hi;
+    uint32_t ans = hb >= 31 ? 0u : (lo & ~((2u << hb) - 1u));
+    for (int b = hb; b >= kLow; b--) {
+        const uint32_t t = ans | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < Q; q++) c += __popcll(__ballot(ok[q] && v[q] < t));
+        if (c <= k) ans = t;
     }
-    return prefix;
+    return min(ans | ((1u << kLow) - 1u), hi);
 }
 
 // Phase I merge (one wave per row).  The row's entries come from the first B trees, where
 // every index occurs at most once per tree, so the (K*B)-th smallest ub of the multiset is
 // an upper bound of tau = K-th smallest ub over distinct indices (ub of an index = its
 // smallest ub), and the entries with ub below it hold every index's minimal entry that
-// matters.  tau is computed exactly on that small set; the list keeps every entry with
-// lb <= tau (duplicates included: the final merge removes them).
+// matters.  tau is bounded from above on that small set; the list keeps every entry with
+// lb <= tau (duplicates included: the final merge removes them).  Every slot of the row is
+// loaded at the start (Q per lane), so a wave waits on memory once.
 constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
 constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
 constexpr int kSetCap = 512;
 
+template <int Q>
 __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int ML,
                                                      const int32_t *__restrict__ pidx, const float *__restrict__ plb,
                                                      const float *__restrict__ pub, int cap, float *__restrict__ tau,
                                                      Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap,
                                                      int32_t *__restrict__ cnt) {
-    __shared__ uint32_t s_u[4][kMergeCap];
-    __shared__ uint32_t s_h[4][256];
     __shared__ int32_t s_si[4][kSetCap];
     __shared__ uint32_t s_su[4][kSetCap];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
     const int64_t base_slot = a * cap;
-    const int c = B * ML;  // fixed slots of the first B trees; empty ones hold +inf bounds
-    bool over = c > kMergeCap;
-    int nv = 0;  // valid (finite ub) slots
-    for (int i = lane; i < (over ? 0 : c); i += 64) {
-        const uint32_t u = fkey(pub[base_slot + i]);
-        s_u[w][i] = u;
-        nv += u < 0x7f800000u ? 1 : 0;
+    const int c = B * ML;  // fixed slots of the first B trees
+    if (c > 64 * Q) {      // leaves above kMergeCap points: the row takes the exhaustive path
+        if (lane == 0) {
+            lcnt[a] = lcap + 1;
+            tau[a] = INFINITY;
+            cnt[a] = 0;
+        }
+        return;
     }
-    for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o, 64);
-    wave_sync();
+    uint32_t u[Q];
+    float l[Q];
+    bool fin[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int i = lane + 64 * q;
+        const bool in = i < c;
+        u[q] = in ? fkey(pub[base_slot + i]) : 0xffffffffu;
+        l[q] = in ? plb[base_slot + i] : INFINITY;
+    }
+    int nv = 0;  // finite-ub slots (empty slots hold +inf bounds)
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        fin[q] = u[q] < 0x7f800000u;
+        nv += __popcll(__ballot(fin[q]));
+    }
     const int kb = K * B;
-    uint32_t theta = 0x7f800000u;  // +inf
-    if (!over && nv >= kb) theta = wave_kth_lds(s_u[w], c, kb - 1, s_h[w]);
-    // the small set S = {valid slots with ub <= theta}
+    const uint32_t theta = nv >= kb ? wave_kth_upper<Q>(u, fin, kb - 1) : 0x7f800000u;
+    // the small set S = {finite slots with ub <= theta}
     int ns = 0;
-    for (int b0 = 0; b0 < (over ? 0 : c); b0 += 64) {
-        const int i = b0 + lane;
-        const uint32_t u = i < c ? s_u[w][i] : 0xffffffffu;
-        const bool in = u <= theta && u < 0x7f800000u;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const bool in = fin[q] && u[q] <= theta;
         const uint64_t mk = __ballot(in);
         const int pos = ns + mask_rank(mk);
         if (in && pos < kSetCap) {
-            s_si[w][pos] = pidx[base_slot + i];
-            s_su[w][pos] = u;
+            s_si[w][pos] = pidx[base_slot + lane + 64 * q];
+            s_su[w][pos] = u[q];
         }
         ns += __popcll(mk);
     }
     wave_sync();
+    const bool over = ns > kSetCap;
     float tv = INFINITY;
-    if (ns > kSetCap) {
-        over = true;
-    } else if (!over) {
+    if (!over) {
         // representatives: the entry of smallest (ub, position) among equal indices
         uint32_t repv[kSetCap / 64];
         bool rep[kSetCap / 64];
@@ -695,36 +687,36 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
             repv[q] = 0;
             if (rep[q]) {
                 const int id = s_si[w][i];
-                const uint32_t u = s_su[w][i];
-                repv[q] = u;
+                const uint32_t uu = s_su[w][i];
+                repv[q] = uu;
                 for (int j = 0; j < ns; j++)
-                    if (s_si[w][j] == id && (s_su[w][j] < u || (s_su[w][j] == u && j < i))) {
+                    if (s_si[w][j] == id && (s_su[w][j] < uu || (s_su[w][j] == uu && j < i))) {
                         rep[q] = false;
                         break;
                     }
             }
             nrep += __popcll(__ballot(rep[q]));
         }
-        if (nrep >= K) tv = __uint_as_float(wave_kth_regs<kSetCap / 64>(repv, rep, K - 1, s_h[w]));
+        if (nrep >= K) tv = __uint_as_float(wave_kth_upper<kSetCap / 64>(repv, rep, K - 1));
     }
     const float tp = tv * (1.f + 1e-6f);
     uint32_t kept = 0;
-    for (int b0 = 0; b0 < (over ? 0 : c); b0 += 64) {
-        const int i = b0 + lane;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int i = lane + 64 * q;
         // lanes past the row's c slots read nothing: with tau = +inf (fewer distinct
         // candidates than K) their lb = +inf would pass lb <= tau and the read would land in
         // the next row's slots, or past the index array for the last row.  Validity of a
-        // slot comes from its index (-1 marks an empty one), never from its bounds.
-        const bool slot = i < c;
-        const float lb = slot ? plb[base_slot + i] : INFINITY;
-        const int id = slot && lb <= tp ? pidx[base_slot + i] : -1;
+        // slot comes from its index (-1 marks an empty one), never from its bounds: a pair
+        // outside the copy's range carries lb = 0, ub = +inf and is kept.
+        const bool cand = !over && i < c && l[q] <= tp;
+        const int id = cand ? pidx[base_slot + i] : -1;
         const bool keep = id >= 0;
         const uint64_t mk = __ballot(keep);
         const uint32_t pos = kept + mask_rank(mk);
-        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = make_ent(id, lb, __uint_as_float(s_u[w][i]));
+        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = make_ent(id, l[q], __uint_as_float(u[q]));
         kept += __popcll(mk);
     }
-    wave_sync();
     if (lane == 0) {
         lcnt[a] = over ? lcap + 1 : (int32_t)kept;
         tau[a] = over ? INFINITY : tp;
@@ -781,7 +773,6 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     __shared__ uint32_t s_d[4][kRCap];
     __shared__ int32_t s_wi[4][kWCap];
     __shared__ double s_wd[4][kWCap];
-    __shared__ uint32_t s_h[4][256];
     extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
@@ -806,13 +797,18 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     bool first[kFinalQ];
     int nd = 0;
     bool bad = false;  // an index outside [0, npts) is an internal error, never dereferenced
+    Ent ev[kFinalQ];   // every record of the row is loaded first: the wave waits on memory once
 #pragma unroll
     for (int q = 0; q < kFinalQ; q++) {
         const int i = lane + 64 * q;
+        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+    }
+#pragma unroll
+    for (int q = 0; q < kFinalQ; q++) {
         first[q] = false;
         eidx[q] = -1;
         elb[q] = eub[q] = 0;
-        const Ent e = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+        const Ent e = ev[q];
         bad |= e.idx < -1 || (int64_t)e.idx >= A.npts;
         if (e.idx >= 0 && (int64_t)e.idx < A.npts) {
             eidx[q] = e.idx;
@@ -840,7 +836,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         return;
     }
     float tv = INFINITY;
-    if (nd >= K) tv = __uint_as_float(wave_kth_regs<kFinalQ>(eub, first, K - 1, s_h[w]));
+    if (nd >= K) tv = __uint_as_float(wave_kth_upper<kFinalQ>(eub, first, K - 1));
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
     int nr = 0;  // rerank set R = {first copies with lb <= tau'}
 #pragma unroll
@@ -873,7 +869,17 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     }
     wave_sync();
     float d32k = INFINITY;
-    if (nr >= K) d32k = __uint_as_float(wave_kth_lds(s_d[w], nr, K - 1, s_h[w]));
+    if (nr >= K) {
+        uint32_t dv[kRCap / 64];
+        bool dok[kRCap / 64];
+#pragma unroll
+        for (int q = 0; q < kRCap / 64; q++) {
+            const int i = lane + 64 * q;
+            dok[q] = i < nr;
+            dv[q] = dok[q] ? s_d[w][i] : 0u;
+        }
+        d32k = __uint_as_float(wave_kth_upper<kRCap / 64>(dv, dok, K - 1));
+    }
     const float wcut = d32k * (1.f + A.win);
     int nw = 0;  // the window: binary32 distance within w of the K-th; ordered in binary64
     for (int base = 0; base < nr; base += 64) {
@@ -1173,8 +1179,10 @@ __global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q,
 // ================================================================ host launch sequences
 
 // Phase I trees: at most kFirstTrees, and K * B must leave room in the merge's small set
-static int first_trees(int T, int K) {
-    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K}));
+// trees of Phase I: at most kFirstTrees, and few enough that the K B smallest bounds fit the
+// representative set and the B ML slots of a row fit one wave's registers
+static int first_trees(int T, int K, int max_leaf) {
+    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K, kMergeCap / std::max(max_leaf, 1)}));
 }
 
 static BoundCoef bound_coef(int prec, int d) {
@@ -1272,7 +1280,7 @@ template <int NB, int PREC>
 static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
                        const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
-    constexpr int NT = NB >= 2 ? 32 * NB : 64;
+    constexpr int NT = NB >= 2 ? 64 * NB : 64;
     if (out.mode == 0)
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm,
                            pt, bc, excl, out);
@@ -1355,8 +1363,12 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     }
     {
         ProfScope ps(s, "merge_first", 0, 0);
-        hipLaunchKernelGGL(k_merge_first, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B,
-                           v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
+        if (cap1 <= 1024)
+            hipLaunchKernelGGL(k_merge_first<16>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B,
+                               v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
+        else
+            hipLaunchKernelGGL(k_merge_first<kMergeCap / 64>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows,
+                               K, cs.B, v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
         launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0) {
@@ -1412,7 +1424,7 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     hipGetDevice(&dev);
     CandStage cs;
     cs.rows = v.n;
-    cs.B = first_trees(v.T, K);
+    cs.B = first_trees(v.T, K, v.max_leaf);
     cs.jobs0 = v.jobs;
     cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
     cs.njobs0 = v.n_jobs_tree * cs.B;
@@ -1481,7 +1493,7 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     void *Qc = ws.get<void>((size_t)T * m * v.dp * esz);
     float2 *qnrm = ws.get<float2>((size_t)T * m * 8);
     const int nbt = (v.max_leaf + TR - 1) / TR;
-    const int nfirst = first_trees(T, K);
+    const int nfirst = first_trees(T, K, v.max_leaf);
     const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
     const int64_t jcap0 = jcap_tree * nfirst;
     const int64_t jcap1 = jcap_tree * (T > nfirst ? T - nfirst : 1);
