@@ -28,6 +28,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "kNN queries/s at ≥0.99 recall, FP32 vs BF16+rerank; p50/p99 latency"
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T32.md")
+# kernel behind each timed record of the library, for the fp32 run of the 1M x 128 workload
+RECORD_KERNEL = {
+    "tile_phase2": "k_tile_sym<8, 0, 1>",
+    "tile_phase1": "k_tile_sym<8, 0, 0>",
+    "proj_chunks": "k_proj_chunks<true>",
+    "level_small": "k_level_small<true>",
+    "leaf_finalize": "k_leaf_finalize<float>",
+    "merge_first": "k_merge_first<16>",
+    "final_rerank": "k_final<true>",
+}
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
@@ -42,6 +54,11 @@ def parse():
     ap.add_argument("--recall-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
+                         "--copy-probe into per-kernel HBM traffic (markdown on stdout) and exit")
+    ap.add_argument("--kt-summary", metavar="DIR", help="summarise a rocprofv3 --kernel-trace --stats run "
+                                                        "(markdown on stdout) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
     ap.add_argument("--cpu-trees", type=int, default=1,
@@ -93,8 +110,108 @@ def roofline(prof):
                   "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
 
+def source_hash():
+    """Hash of the HIP sources: traffic figures are valid only for the kernels they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1812_11689_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _csv_rows(d, suffix):
+    import csv
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                with open(os.path.join(root, f)) as fh:
+                    return list(csv.DictReader(fh))
+    raise SystemExit(f"no *{suffix} under {d}")
+
+
+def _short(name):
+    name = name.split("(")[0]
+    for pre in ("void ", "rpf::"):
+        name = name.replace(pre, "")
+    return name.strip()
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Per-kernel HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the counter reads for the plain copy of --copy-probe MiB."""
+    fr = _csv_rows(fetch_dir, "counter_collection.csv")
+    wr = _csv_rows(write_dir, "counter_collection.csv")
+    probe_w = max((r for r in wr if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    probe_id = probe_w["Dispatch_Id"]
+    probe_f = next(r for r in fr if r["Dispatch_Id"] == probe_id)
+    probe_bytes = round(float(probe_w["Counter_Value"]) / 1024.0) * (1 << 20)  # whole MiB written
+    kf = probe_bytes / (float(probe_f["Counter_Value"]) * 1024.0)
+    kw = probe_bytes / (float(probe_w["Counter_Value"]) * 1024.0)
+    agg = {}
+    for rows, key in ((fr, "fetch"), (wr, "write")):
+        for r in rows:
+            k = _short(r["Kernel_Name"])
+            a = agg.setdefault(k, {"fetch": [], "write": []})
+            a[key].append(float(r["Counter_Value"]) * 1024.0)
+    out = {"source_hash": source_hash(), "probe_bytes": probe_bytes, "fetch_scale": round(kf, 4),
+           "write_scale": round(kw, 4), "kernels": {}}
+    lines = ["| kernel | dispatches | FETCH_SIZE GB/dispatch | WRITE_SIZE GB/dispatch | HBM GB/dispatch (scaled) |",
+             "|---|---|---|---|---|"]
+    for k, a in sorted(agg.items(), key=lambda kv: -sum(kv[1]["fetch"]) - sum(kv[1]["write"])):
+        if not a["fetch"] or not a["write"] or not k.startswith("k_"):  # the library's kernels only
+            continue
+        f = sum(a["fetch"]) / len(a["fetch"])
+        w = sum(a["write"]) / len(a["write"])
+        tot = f * kf + w * kw
+        out["kernels"][k] = {"dispatches": len(a["fetch"]), "bytes_per_dispatch": round(tot)}
+        if len(lines) < 24:
+            lines.append(f"| {k} | {len(a['fetch'])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {tot / 1e9:.3f} |")
+    print(f"Copy probe: {probe_bytes / 2**30:.2f} GiB read and written; FETCH_SIZE reads "
+          f"{float(probe_f['Counter_Value']) * 1024 / 2**30:.3f} GiB of it (scale {kf:.4f}), WRITE_SIZE "
+          f"{float(probe_w['Counter_Value']) * 1024 / 2**30:.3f} GiB (scale {kw:.4f}).\n")
+    print("\n".join(lines))
+    print("\nMachine-readable (read by bench.py while the HIP sources hash to source_hash):\n")
+    print(json.dumps(out))
+
+
+def kt_summary(d):
+    rows = _csv_rows(d, "kernel_stats.csv")
+    print("| kernel | calls | total ms | average us | share |")
+    print("|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+        print(f"| {_short(r['Name'])[:70]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+              f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+
+
+def traffic_for(record):
+    """HBM bytes per launch of a timed record, from the committed counter summary, or None
+    when there is none or the kernels changed since it was taken."""
+    kname = RECORD_KERNEL.get(record)
+    if not kname or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        js = [ln for ln in fh if ln.startswith("{")]
+    if not js:
+        return None
+    t = json.loads(js[-1])
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t["kernels"].get(kname)
+    return None if k is None else k["bytes_per_dispatch"]
+
+
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    if args.kt_summary:
+        kt_summary(args.kt_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "by trees is a design note only)"}))
@@ -171,6 +288,10 @@ def main():
     for name, r in prof32.items():
         r["prec"] = "fp32"
     dom, roof = roofline(prof32)
+    if roof is not None and dom is not None:
+        tr = traffic_for(dom)
+        roof["traffic"] = None if tr is None else {"bytes_per_launch": tr, "unit": "B",
+                                                   "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
     breakdown = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(prof32.items(), key=lambda kv: -kv[1]["total_ms"])}
 
     f = rpf.build(X, T, n0, Rd, dist_prec="fp32")

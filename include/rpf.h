@@ -3,11 +3,11 @@
  *
  * kNN search by random projection forests (Yan, Wang, Wang, Wang, Li, arXiv 1812.11689):
  *   - rpf_build     grows an ensemble of T random projection trees over the points U
- *                   (Alg. 3 lines 1-3 with Alg. 1 and Alg. 2; median split point, Sec. 2);
+ *                   (Alg. 3, forest growth, with Alg. 1 and Alg. 2; median split, Sec. 2);
  *   - rpf_all_knn   finds the K nearest neighbours of every point of U among the union
- *                   of its leaves (Alg. 3 with Q = U, lines 4-10);
+ *                   of its leaves (Alg. 3 search with Q = U);
  *   - rpf_query     lets external queries fall through every tree and searches the union
- *                   of the reached leaves (Alg. 3 lines 4-10).
+ *                   of the reached leaves (Alg. 3 search).
  *
  * Conventions for every entry point
  *   - Array arguments named *_dev are DEVICE pointers of the current HIP device; host
@@ -67,7 +67,7 @@ typedef struct {
     int32_t split_rule;  /* rpf_split; must be RPF_SPLIT_MEDIAN                             */
     int32_t dist_prec;   /* rpf_dist_prec for the candidate tiles                           */
     int32_t reserved;    /* must be 0                                                       */
-    const float *directions_dev; /* random directions (Alg. 1 line 8, Alg. 2 line 3), binary32
+    const float *directions_dev; /* random directions (Alg. 1 and Alg. 2), binary32
                             [n_trees][2^L - 1][n_try][d], row h-1 for heap node h (root 1,
                             children 2h, 2h+1), L = rpf_depth(n, leaf_size).  Required; it is
                             copied, so the caller may free it once the build's work ends.   */
@@ -89,12 +89,12 @@ rpf_status rpf_build(const float *X_dev, int64_t n, int32_t d, const rpf_params 
 rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self,
                        int32_t *out_idx_dev, float *out_dist_dev, void *stream);
 
-/* External queries (Alg. 3 lines 4-10): Q_dev binary32 [m][d] (finite), m >= 0,
+/* External queries (Alg. 3 search): Q_dev binary32 [m][d] (finite), m >= 0,
  * 1 <= K <= n.  Outputs [m][K] as for rpf_all_knn. */
 rpf_status rpf_query(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t K,
                      int32_t *out_idx_dev, float *out_dist_dev, void *stream);
 
-/* Route queries only (Alg. 3 lines 5-7): out_leaf_dev int32 [T][m] = heap id of the leaf
+/* Route queries only (Alg. 3 descent): out_leaf_dev int32 [T][m] = heap id of the leaf
  * each query reaches in each tree (right child iff projection >= split value). */
 rpf_status rpf_route(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t *out_leaf_dev,
                      void *stream);

@@ -120,7 +120,7 @@ class Forest:
 
 
 def build_forest(x, R, n_trees: int, n0: int, n_try: int = 1) -> Forest:
-    """Alg. 3 lines 1-3 with Alg. 1/2: grow `n_trees` trees over x with directions R
+    """Alg. 3 (forest growth) with Alg. 1/2: grow `n_trees` trees over x with directions R
     [T][2^L-1][n_try][d] (R may hold more trees; the first n_trees are used)."""
     x = _f32(x)
     n, d = x.shape

@@ -230,7 +230,7 @@ static void grow_tree(const float *X, int64_t n, int d, const float *Rt, int n_t
     free(leaves);
 }
 
-/* Alg. 3, lines 1-3: grow T independent trees.  R is [T][2^L-1][n_try][d].
+/* Alg. 3, forest growth: grow T independent trees.  R is [T][2^L-1][n_try][d].
  * Outputs split/split_idx/chosen [T][2^L-1], perm and leaf_of [T][n].  Returns L. */
 int rpfo_build(const float *X, int64_t n, int d, const float *R, int T, int n_try, int64_t n0,
                double *split, int32_t *split_idx, int32_t *chosen, int32_t *perm,
@@ -245,7 +245,7 @@ int rpfo_build(const float *X, int64_t n, int d, const float *R, int T, int n_tr
     return L;
 }
 
-/* Alg. 3, lines 5-7: let each query fall through every tree.  At an internal node h the
+/* Alg. 3, descent: let each query fall through every tree.  At an internal node h the
  * query goes to the right child iff its projection onto the node's chosen direction is
  * >= the split value (W_R = {P >= c}).  Output: heap id of the leaf, [T][m]. */
 void rpfo_route(const float *R, int T, int n_try, int d, int64_t n, int64_t n0,
@@ -286,7 +286,7 @@ static int cmp_i32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-/* Alg. 3, lines 8-10 for a batch of queries whose leaves are known: N_q = union over trees
+/* Alg. 3, union of the reached leaves and exact ranking, for a batch of queries whose leaves are known: N_q = union over trees
  * of the members of q's leaf (minus q itself if self[q] >= 0), exact distances to every
  * member of N_q, the K closest by (D, index).  out_dist holds sqrt(D).  qleaf is [T][m]. */
 void rpfo_knn(const float *X, int64_t n, int d, int T, int64_t n0, const int32_t *perm,

@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
     }
 }
 
-// ---------------------------------------------------------------- routing (Alg. 3, lines 5-7)
+// ---------------------------------------------------------------- routing (Alg. 3, descent of a query through each tree)
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_route(const float *__restrict__ Q, int64_t m, int d,
