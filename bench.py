@@ -61,6 +61,9 @@ def parse():
                                                         "(markdown on stdout) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-n", type=int, default=None, help="points of the served forest (default: 4M)")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving measurement")
     ap.add_argument("--cpu-trees", type=int, default=1,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
@@ -299,6 +302,12 @@ def main():
     st = f.knn_stats()
     f.free()
 
+    serving = None
+    if not args.no_serve:
+        del X, Rd
+        torch.cuda.empty_cache()
+        serving = serving_leg(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, R, pts[:500], K, args.cpu_trees)
@@ -328,8 +337,106 @@ def main():
         "roofline_kernel": dom,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
+
+
+def serving_leg(args):
+    """Continuous-batching server over the resident 4M x 96 forest (T 64, n0 256): a closed
+    burst of requests gives the saturated rate; an open-loop Poisson stream at 0.8 of it gives
+    request latency.  Batch sizes lognormal (median 64, sigma 1.5) in [1, 4096], K uniform over
+    {1, 10, 100}; queries from the served mixture with 5 % uniform outliers."""
+    import torch
+    from paper_1812_11689_amd import rpf
+    from paper_1812_11689_amd import workloads as W
+
+    t0 = time.time()
+    w = W.make_config(4, n=args.serve_n)
+    n, d = w.x.shape
+    T, n0 = w.n_trees, w.leaf_size
+    L = rpf.depth(n, n0)
+    X = torch.from_numpy(w.x).cuda()
+    R = torch.from_numpy(W.directions(w.dir_seed, T, (1 << L) - 1, 1, d)).cuda()
+    nreq = args.serve_requests
+    seed = W.SEED_BASE + 200 + 4
+    _, sizes, ks = W.serving_requests(seed, nreq, 1.0)
+    pool = int(sizes.sum())
+    Qh = W.mixture_queries(seed, w.x, pool, 1000, mean_seed=W.SEED_BASE + 4)
+    Q = torch.from_numpy(Qh).cuda()
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    reqs = [(Q[offs[i]:offs[i + 1]], int(ks[i])) for i in range(nreq)]
+    outs = [(torch.empty((int(sizes[i]), int(ks[i])), dtype=torch.int32, device="cuda"),
+             torch.empty((int(sizes[i]), int(ks[i])), dtype=torch.float32, device="cuda")) for i in range(nreq)]
+    torch.cuda.synchronize()
+    print(f"# serving workload {w.name}: n={n} d={d} T={T} n0={n0}, {nreq} requests, {pool} rows "
+          f"(generated in {time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    res = {"workload": w.name, "requests": nreq, "rows": pool,
+           "batch_rows": "lognormal(ln 64, 1.5) in [1, 4096]", "K": "uniform {1, 10, 100}"}
+
+    def run(prec):
+        f = rpf.build(X, T, n0, R, dist_prec=prec)
+        torch.cuda.synchronize()
+        srv = rpf.Server(f, slots=4, max_batch_rows=8192)
+        # warm-up
+        for q, k in reqs[:64]:
+            srv.wait(srv.submit(q, k))
+        # closed burst: every request queued at once
+        srv.reset_stats()
+        ts = [srv.submit(q, k, out=o) for (q, k), o in zip(reqs, outs)]
+        for t in ts:
+            srv.wait(t)
+        burst = srv.stats()
+        rate = burst["requests"] / (burst["rows"] / burst["rows_per_s"])  # requests/s at saturation
+        # open loop at 0.8 of the saturated request rate
+        srv.reset_stats()
+        arr, _, _ = W.serving_requests(seed + 1, nreq, 0.8 * rate)
+        start = time.perf_counter()
+        ts = []
+        for i, ((q, k), o) in enumerate(zip(reqs, outs)):
+            now = time.perf_counter() - start
+            if arr[i] > now:
+                time.sleep(arr[i] - now)
+            ts.append(srv.submit(q, k, out=o))
+        for t in ts:
+            srv.wait(t)
+        ol = srv.stats()
+        srv.close()
+        out = {"saturated_rows_per_s": round(burst["rows_per_s"], 1),
+               "saturated_requests_per_s": round(rate, 1),
+               "burst_mean_batch_rows": round(burst["mean_batch_rows"], 1),
+               "open_loop": {"offered_requests_per_s": round(0.8 * rate, 1),
+                             "rows_per_s": round(ol["rows_per_s"], 1),
+                             "p50_ms": round(ol["p50_s"] * 1e3, 3), "p99_ms": round(ol["p99_s"] * 1e3, 3),
+                             "max_ms": round(ol["max_s"] * 1e3, 3),
+                             "mean_batch_rows": round(ol["mean_batch_rows"], 1)}}
+        print(f"# serving {prec}: {out}", file=sys.stderr, flush=True)
+        return f, out
+
+    f16, res["fp16"] = run("fp16")
+    # recall of the fp16 results on the first requests' rows (K as requested)
+    Xd = X.double()
+    nrm = (Xd * Xd).sum(1)
+    hit = tot = 0
+    for i in range(nreq):
+        if tot >= 1500:
+            break
+        q, k = reqs[i]
+        qd = q[:16].double()  # at most 16 rows of a request: [16][n] binary64 distances
+        D = nrm[None, :] - 2.0 * (qd @ Xd.T)
+        truth = torch.topk(D, k, dim=1, largest=False).indices.cpu().numpy()
+        got = outs[i][0][:16].cpu().numpy()
+        for a, b in zip(got, truth):
+            hit += len(set(a.tolist()) & set(b.tolist()))
+        tot += truth.size
+    res["recall_fp16"] = round(hit / max(tot, 1), 5)
+    res["recall_sample_neighbours"] = tot
+    f16.free()
+    del Xd, nrm
+    torch.cuda.empty_cache()
+    f32, res["fp32"] = run("fp32")
+    f32.free()
+    return res
 
 
 def cpu_baseline(w, R, sample_pts, K, cpu_trees):

@@ -151,6 +151,60 @@ rpf_status rpf_profile_enable(int32_t on);
 rpf_status rpf_profile_reset(void);
 rpf_status rpf_profile_read(rpf_profile_record *out_host, int32_t cap, int32_t *count);
 
+/* Device bytes one rpf_query call of m queries with this K takes for its workspace (an
+ * estimate from above, host only; the serving loop admits batches by it). */
+rpf_status rpf_query_workspace_bytes(const rpf_forest *f, int64_t m, int32_t K, uint64_t *bytes_host);
+
+/* ---- Serving loop: continuous batching of query requests over a resident forest.
+ *
+ * Requests (m query rows, K; Alg. 3 search) are queued by rpf_server_submit and served by
+ * `slots` worker threads, each with its own HIP stream.  A free slot takes the oldest
+ * waiting request together with every later waiting request of the same K, up to
+ * max_batch_rows rows in all, and runs them as one rpf_query batch; requests arriving while
+ * batches run wait for the next free slot.  A batch is admitted only while the workspace
+ * bytes of the batches in flight (rpf_query_workspace_bytes plus staging) stay within
+ * mem_budget_bytes (0 = unlimited); a batch that alone exceeds it still runs when nothing
+ * else does.  Each request's result is exactly what rpf_query gives for it alone.
+ *
+ * Ownership: Q_dev, out_idx_dev and out_dist_dev belong to the caller and must stay valid
+ * until the request is collected by rpf_server_poll (done = 1) or rpf_server_wait.  Q_dev
+ * is read after the work already queued on the submitting `stream` (an event orders it);
+ * the outputs hold the result once the request is collected.  The forest must outlive the
+ * server.  All server calls are thread-safe.  Latency = from the submit call to the
+ * completion of the request's batch. */
+typedef struct rpf_server rpf_server;
+
+typedef struct {
+    int32_t slots;            /* worker threads / streams, 1..16                            */
+    int32_t reserved;         /* must be 0                                                  */
+    int64_t max_batch_rows;   /* rows of one batch (a single larger request runs alone)     */
+    int64_t max_queue;        /* waiting requests; rpf_server_submit returns RPF_EBUSY above */
+    uint64_t mem_budget_bytes;
+} rpf_server_config;
+
+typedef struct {
+    int64_t requests, rows, batches;    /* completed since creation or the last reset */
+    double mean_batch_rows;
+    double p50_s, p99_s, max_s;         /* request latency percentiles (seconds)      */
+    double rows_per_s;                  /* rows completed / (last completion - first submit) */
+} rpf_server_report;
+
+rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, rpf_server **out);
+/* Non-blocking.  RPF_EBUSY when max_queue requests are waiting; RPF_EINVAL for m < 1 or K
+ * outside [1, min(n, 256)].  *ticket_host identifies the request. */
+rpf_status rpf_server_submit(rpf_server *srv, const float *Q_dev, int64_t m, int32_t K, int32_t *out_idx_dev,
+                             float *out_dist_dev, void *stream, uint64_t *ticket_host);
+/* RPF_ENOTREADY (done = 0) while the request runs; once done (done = 1) the request's own
+ * status is returned and the ticket is released. */
+rpf_status rpf_server_poll(rpf_server *srv, uint64_t ticket, int32_t *done_host, double *latency_s_host);
+/* Blocks until the request is done; returns its status and releases the ticket. */
+rpf_status rpf_server_wait(rpf_server *srv, uint64_t ticket, double *latency_s_host);
+rpf_status rpf_server_stats(rpf_server *srv, rpf_server_report *out_host);
+rpf_status rpf_server_reset_stats(rpf_server *srv);
+/* Serves every waiting request, stops the workers and frees the server (NULL: no-op).
+ * Requests not collected are released with it. */
+rpf_status rpf_server_destroy(rpf_server *srv);
+
 /* Device memory of forests and of the per-call kNN workspaces comes from a cache kept by
  * the library: blocks obtained from hipMalloc are reused by later calls (a block last used
  * on another stream is ordered behind that use by an event) and are not returned to the

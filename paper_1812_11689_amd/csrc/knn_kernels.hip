@@ -726,6 +726,7 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 
 // ---------------------------------------------------------------- final merge and rerank
 
+constexpr int kListCap = 256;              // Phase I list records per row
 constexpr int kFinalQ = 12;                // entries per lane
 constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
 constexpr int kHT = 1024;                  // per-row hash table (indices) for the dedup
@@ -1319,7 +1320,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     const int64_t rows = cs.rows;
     // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
     // threshold of the union of those leaves
-    const int lcap = 256;
+    const int lcap = kListCap;
     const int cap1 = v.max_leaf * cs.B;  // Phase I slots per row (index / lb / ub arrays)
     const int cap2 = kFinalCap - lcap;   // Phase II records per row
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
@@ -1554,6 +1555,26 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     cs.flops0 = cs.flops1 = cs.bytes0 = cs.bytes1 = 0;
     cs.sym = false;
     return run_cand_stage(v, cs, K, out_idx, out_dist, s);
+}
+
+// device bytes one knn_query call of m queries takes from the allocator (its workspace)
+uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
+    const ForestView v = view(f);
+    const int64_t T = v.T, nleaf = v.nleaf;
+    const int TR = 32 * v.job_mb;
+    const uint64_t esz = v.prec == RPF_DIST_FP32 ? 4 : 2;
+    const int nbt = (v.max_leaf + TR - 1) / TR;
+    const int B = first_trees(v.T, K, v.max_leaf);
+    const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
+    uint64_t b = 0;
+    b += (uint64_t)T * m * 4 * 3;                  // leaf per tree, order, group leaf
+    b += (uint64_t)T * nleaf * 4 * 3;              // group counts, offsets, fill
+    b += (uint64_t)T * m * v.dp * esz + (uint64_t)T * m * 8;  // centred queries and norms
+    b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob);
+    const uint64_t cap1 = (uint64_t)v.max_leaf * B, cap2 = kFinalCap - kListCap;
+    b += std::max(m * cap1 * 12, m * cap2 * sizeof(Ent)) + 256;
+    b += (uint64_t)m * 4 * 4 + (uint64_t)m * kListCap * sizeof(Ent) + 16 * 3;
+    return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
 }
 
 }  // namespace rpf

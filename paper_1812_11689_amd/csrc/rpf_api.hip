@@ -33,10 +33,6 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
 
-rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s);
-rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
-                     hipStream_t s);
-rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s);
 
 // ---------------------------------------------------------------- errors
 
@@ -595,6 +591,13 @@ rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, 
     return knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
 }
 
+rpf_status rpf_query_workspace_bytes(const rpf_forest *f, int64_t m, int32_t K, uint64_t *bytes) {
+    if (!f || !bytes) return fail(RPF_EINVAL, "rpf_query_workspace_bytes: NULL pointer");
+    if (m < 0 || K < 1 || K > 256) return fail(RPF_EINVAL, "rpf_query_workspace_bytes: m >= 0 and 1 <= K <= 256");
+    *bytes = m == 0 ? 0 : query_workspace_bytes(f, m, K);
+    return RPF_OK;
+}
+
 rpf_status rpf_route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, void *stream) {
     if (!f) return fail(RPF_EINVAL, "rpf_route: forest is NULL");
     if (m < 0) return fail(RPF_EINVAL, "rpf_route: m must be >= 0");
@@ -659,6 +662,9 @@ rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *str
 
 // ---------------------------------------------------------------- read-only view for the kNN launchers
 namespace rpf {
+int64_t forest_points(const rpf_forest *f) { return f->n; }
+int32_t forest_dim(const rpf_forest *f) { return f->d; }
+
 ForestView view(const rpf_forest *f) {
     ForestView v;
     v.n = f->n; v.H = f->H; v.d = f->d; v.T = f->T; v.n0 = f->n0; v.n_try = f->n_try; v.L = f->L;

@@ -120,6 +120,15 @@ struct ForestView {
 };
 ForestView view(const rpf_forest *f);
 
+// entry points of the search (knn_kernels.hip), shared by the C ABI and the server
+rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s);
+rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
+                     hipStream_t s);
+rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s);
+uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K);
+int64_t forest_points(const rpf_forest *f);
+int32_t forest_dim(const rpf_forest *f);
+
 rpf_status fail(rpf_status st, const std::string &msg);
 rpf_status check_hip(hipError_t e, const char *what);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);

@@ -1,0 +1,356 @@
+// Serving loop over a resident forest: continuous batching of kNN query requests.
+//
+// Requests (a block of m query rows and K, Alg. 3 search) are queued by rpf_server_submit
+// and served by `slots` worker threads, each with its own HIP stream.  A free slot takes
+// the oldest waiting request together with every later waiting request of the same K, up
+// to max_batch_rows rows, and runs them as one batch through the query path (routing,
+// grouping by leaf, MFMA tiles, merge, re-rank); the outputs of the batch are contiguous
+// per request and are copied back to each request's own arrays.  Requests that arrive
+// while batches run wait for the next free slot, and a batch is admitted only while the
+// workspace bytes of the batches in flight stay within the memory budget, so work of
+// several batches overlaps on the device without over-committing memory.
+//
+// The result of a request does not depend on its batch: the query path returns the exact
+// top-K of the request's leaf union under the binary64 ranking.
+//
+// Latency of a request = time from its submit call to the completion of its batch, seen by
+// the slot thread after a stream synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rpf_internal.h"
+
+namespace rpf {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    const float *Q = nullptr;
+    int64_t m = 0;
+    int32_t K = 0;
+    int32_t *out_idx = nullptr;
+    float *out_dist = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: Q holds its values
+    Clock::time_point t_submit, t_done;
+    int state = 0;               // 0 waiting, 1 running, 2 done
+    rpf_status status = RPF_OK;
+    std::string err;
+};
+
+}  // namespace
+}  // namespace rpf
+
+struct rpf_server {
+    const rpf_forest *f = nullptr;
+    int device = 0;
+    rpf_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_work;  // slots wait for requests / memory
+    std::condition_variable cv_done;  // waiters wait for completions
+    std::deque<rpf::Request *> waiting;
+    std::unordered_map<uint64_t, rpf::Request *> live;  // submitted, not yet collected
+    std::vector<std::thread> threads;
+    std::vector<hipStream_t> streams;
+    uint64_t next_ticket = 1;
+    uint64_t inflight_bytes = 0;
+    int running_batches = 0;
+    bool stop = false;
+    // statistics since creation or the last reset
+    std::vector<double> lat;
+    int64_t rows_done = 0, requests_done = 0, batches = 0, batch_rows = 0;
+    rpf::Clock::time_point t_first, t_last;
+    bool have_first = false;
+};
+
+namespace rpf {
+namespace {
+
+void finish(rpf_server *sv, std::vector<Request *> &batch, rpf_status st, const std::string &err, uint64_t bytes) {
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->inflight_bytes -= bytes;
+    sv->running_batches--;
+    int64_t rows = 0;
+    for (Request *r : batch) {
+        r->t_done = now;
+        r->status = st;
+        r->err = err;
+        r->state = 2;
+        rows += r->m;
+        if (st == RPF_OK) {
+            sv->lat.push_back(std::chrono::duration<double>(now - r->t_submit).count());
+            sv->rows_done += r->m;
+            sv->requests_done++;
+        }
+    }
+    sv->batches++;
+    sv->batch_rows += rows;
+    sv->t_last = now;
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
+}
+
+void slot_main(rpf_server *sv, int slot) {
+    hipSetDevice(sv->device);
+    hipStream_t s = sv->streams[slot];
+    const int d = forest_dim(sv->f);
+    for (;;) {
+        std::vector<Request *> batch;
+        uint64_t bytes = 0;
+        int64_t rows = 0;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            for (;;) {
+                if (sv->stop && sv->waiting.empty()) return;
+                if (!sv->waiting.empty()) {
+                    // the oldest request and every later one of the same K, up to the row cap
+                    Request *head = sv->waiting.front();
+                    const int K = head->K;
+                    int64_t r = 0;
+                    std::vector<size_t> pick;
+                    for (size_t i = 0; i < sv->waiting.size(); i++) {
+                        Request *q = sv->waiting[i];
+                        if (q->K != K) continue;
+                        if (!pick.empty() && r + q->m > sv->cfg.max_batch_rows) break;
+                        pick.push_back(i);
+                        r += q->m;
+                    }
+                    const uint64_t need = query_workspace_bytes(sv->f, r, K) +
+                                          (pick.size() > 1 ? (uint64_t)r * ((uint64_t)d * 4 + (uint64_t)K * 8) : 0);
+                    if (sv->running_batches == 0 || sv->inflight_bytes + need <= sv->cfg.mem_budget_bytes) {
+                        for (size_t k = pick.size(); k-- > 0;) {
+                            batch.push_back(sv->waiting[pick[k]]);
+                            sv->waiting.erase(sv->waiting.begin() + (long)pick[k]);
+                        }
+                        std::reverse(batch.begin(), batch.end());
+                        for (Request *q : batch) q->state = 1;
+                        sv->inflight_bytes += need;
+                        sv->running_batches++;
+                        bytes = need;
+                        rows = r;
+                        break;
+                    }
+                }
+                sv->cv_work.wait(lk);
+            }
+        }
+        // run the batch on this slot's stream
+        for (Request *q : batch) hipStreamWaitEvent(s, q->ready, 0);
+        rpf_status st = RPF_OK;
+        std::string err;
+        const int K = batch[0]->K;
+        if (batch.size() == 1) {
+            Request *q = batch[0];
+            st = knn_query(sv->f, q->Q, q->m, K, q->out_idx, q->out_dist, s);
+        } else {
+            float *Qb = static_cast<float *>(cache_alloc((size_t)rows * d * 4, s));
+            int32_t *ib = static_cast<int32_t *>(cache_alloc((size_t)rows * K * 4, s));
+            float *db = static_cast<float *>(cache_alloc((size_t)rows * K * 4, s));
+            if (!Qb || !ib || !db) {
+                st = fail(RPF_ENOMEM, "rpf_server: batch staging allocation failed");
+            } else {
+                int64_t off = 0;
+                for (Request *q : batch) {
+                    hipMemcpyAsync(Qb + off * d, q->Q, (size_t)q->m * d * 4, hipMemcpyDeviceToDevice, s);
+                    off += q->m;
+                }
+                st = knn_query(sv->f, Qb, rows, K, ib, db, s);
+                if (st == RPF_OK) {
+                    off = 0;
+                    for (Request *q : batch) {
+                        hipMemcpyAsync(q->out_idx, ib + off * K, (size_t)q->m * K * 4, hipMemcpyDeviceToDevice, s);
+                        hipMemcpyAsync(q->out_dist, db + off * K, (size_t)q->m * K * 4, hipMemcpyDeviceToDevice, s);
+                        off += q->m;
+                    }
+                }
+            }
+            cache_free(Qb, s);
+            cache_free(ib, s);
+            cache_free(db, s);
+        }
+        if (st != RPF_OK) err = rpf_last_error();
+        const rpf_status sync = check_hip(hipStreamSynchronize(s), "rpf_server batch");
+        if (st == RPF_OK && sync != RPF_OK) {
+            st = sync;
+            err = rpf_last_error();
+        }
+        finish(sv, batch, st, err, bytes);
+    }
+}
+
+}  // namespace
+}  // namespace rpf
+
+using namespace rpf;
+
+extern "C" {
+
+rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, rpf_server **out) {
+    if (out) *out = nullptr;
+    if (!f || !cfg || !out) return fail(RPF_EINVAL, "rpf_server_create: NULL pointer");
+    if (cfg->slots < 1 || cfg->slots > 16) return fail(RPF_EINVAL, "rpf_server_create: slots must be in [1, 16]");
+    if (cfg->max_batch_rows < 1) return fail(RPF_EINVAL, "rpf_server_create: max_batch_rows must be >= 1");
+    if (cfg->max_queue < 1) return fail(RPF_EINVAL, "rpf_server_create: max_queue must be >= 1");
+    rpf_server *sv = new rpf_server();
+    sv->f = f;
+    sv->cfg = *cfg;
+    if (sv->cfg.mem_budget_bytes == 0) sv->cfg.mem_budget_bytes = UINT64_MAX;
+    hipGetDevice(&sv->device);
+    for (int i = 0; i < cfg->slots; i++) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t t : sv->streams) hipStreamDestroy(t);
+            delete sv;
+            return fail(RPF_EDEVICE, "rpf_server_create: stream creation failed");
+        }
+        sv->streams.push_back(s);
+    }
+    for (int i = 0; i < cfg->slots; i++) sv->threads.emplace_back(slot_main, sv, i);
+    *out = sv;
+    return RPF_OK;
+}
+
+rpf_status rpf_server_submit(rpf_server *sv, const float *Q, int64_t m, int32_t K, int32_t *out_idx,
+                             float *out_dist, void *stream, uint64_t *ticket) {
+    if (ticket) *ticket = 0;
+    if (!sv || !ticket) return fail(RPF_EINVAL, "rpf_server_submit: NULL pointer");
+    if (m < 1) return fail(RPF_EINVAL, "rpf_server_submit: m must be >= 1");
+    if (!Q || !out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_server_submit: NULL array");
+    if (K < 1 || K > forest_points(sv->f) || K > 256)
+        return fail(RPF_EINVAL, "rpf_server_submit: K must be in [1, min(n, 256)]");
+    Request *r = new Request();
+    if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(r->ready, (hipStream_t)stream) != hipSuccess) {
+        if (r->ready) hipEventDestroy(r->ready);
+        delete r;
+        return fail(RPF_EDEVICE, "rpf_server_submit: event on the submitting stream failed");
+    }
+    r->Q = Q;
+    r->m = m;
+    r->K = K;
+    r->out_idx = out_idx;
+    r->out_dist = out_dist;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) {
+            hipEventDestroy(r->ready);
+            delete r;
+            return fail(RPF_EINVAL, "rpf_server_submit: server is shutting down");
+        }
+        if ((int64_t)sv->waiting.size() >= sv->cfg.max_queue) {
+            hipEventDestroy(r->ready);
+            delete r;
+            return fail(RPF_EBUSY, "rpf_server_submit: queue full");
+        }
+        r->ticket = sv->next_ticket++;
+        if (!sv->have_first) {
+            sv->t_first = r->t_submit;
+            sv->have_first = true;
+        }
+        sv->waiting.push_back(r);
+        sv->live[r->ticket] = r;
+    }
+    sv->cv_work.notify_one();
+    *ticket = r->ticket;
+    return RPF_OK;
+}
+
+static rpf_status collect(rpf_server *sv, std::unique_lock<std::mutex> &lk, uint64_t ticket, double *latency) {
+    auto it = sv->live.find(ticket);
+    Request *r = it->second;
+    sv->live.erase(it);
+    lk.unlock();
+    const rpf_status st = r->status;
+    if (latency) *latency = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    if (st != RPF_OK) fail(st, r->err);
+    hipEventDestroy(r->ready);
+    delete r;
+    return st;
+}
+
+rpf_status rpf_server_poll(rpf_server *sv, uint64_t ticket, int32_t *done, double *latency) {
+    if (done) *done = 0;
+    if (!sv || !done) return fail(RPF_EINVAL, "rpf_server_poll: NULL pointer");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return fail(RPF_EINVAL, "rpf_server_poll: unknown ticket");
+    if (it->second->state != 2) return RPF_ENOTREADY;
+    *done = 1;
+    return collect(sv, lk, ticket, latency);
+}
+
+rpf_status rpf_server_wait(rpf_server *sv, uint64_t ticket, double *latency) {
+    if (!sv) return fail(RPF_EINVAL, "rpf_server_wait: NULL pointer");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return fail(RPF_EINVAL, "rpf_server_wait: unknown ticket");
+    Request *r = it->second;
+    sv->cv_done.wait(lk, [&] { return r->state == 2; });
+    return collect(sv, lk, ticket, latency);
+}
+
+rpf_status rpf_server_stats(rpf_server *sv, rpf_server_report *out) {
+    if (!sv || !out) return fail(RPF_EINVAL, "rpf_server_stats: NULL pointer");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = rpf_server_report{};
+    out->requests = sv->requests_done;
+    out->rows = sv->rows_done;
+    out->batches = sv->batches;
+    out->mean_batch_rows = sv->batches ? (double)sv->batch_rows / (double)sv->batches : 0.0;
+    if (!sv->lat.empty()) {
+        std::vector<double> v = sv->lat;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(p * (double)v.size()) - 1);
+            return v[i];
+        };
+        out->p50_s = pct(0.50);
+        out->p99_s = pct(0.99);
+        out->max_s = v.back();
+    }
+    if (sv->have_first && sv->rows_done > 0) {
+        const double span = std::chrono::duration<double>(sv->t_last - sv->t_first).count();
+        out->rows_per_s = span > 0 ? (double)sv->rows_done / span : 0.0;
+    }
+    return RPF_OK;
+}
+
+rpf_status rpf_server_reset_stats(rpf_server *sv) {
+    if (!sv) return fail(RPF_EINVAL, "rpf_server_reset_stats: NULL pointer");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->lat.clear();
+    sv->rows_done = sv->requests_done = sv->batches = sv->batch_rows = 0;
+    sv->have_first = false;
+    return RPF_OK;
+}
+
+rpf_status rpf_server_destroy(rpf_server *sv) {
+    if (!sv) return RPF_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    for (auto &t : sv->threads) t.join();  // the slots drain every waiting request first
+    for (hipStream_t s : sv->streams) hipStreamDestroy(s);
+    for (auto &kv : sv->live) {
+        hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
+    delete sv;
+    return RPF_OK;
+}
+
+}  // extern "C"

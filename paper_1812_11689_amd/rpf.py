@@ -22,7 +22,9 @@ PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "rpf_free", "rpf_tree_dump",
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
-           "rpf_profile_read", "rpf_release_cached_memory", "rpf_last_error"]
+           "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
+           "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
+           "rpf_server_destroy", "rpf_last_error"]
 
 
 class RpfError(RuntimeError):
@@ -52,6 +54,17 @@ class KnnStats(ctypes.Structure):
 class ProfileRecord(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("algo_bytes", ctypes.c_double), ("algo_flops", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_batch_rows", ctypes.c_int64),
+                ("max_queue", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("rows", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("mean_batch_rows", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("rows_per_s", ctypes.c_double)]
 
 
 _lib = None
@@ -91,6 +104,23 @@ def load(path: str = LIB_PATH):
     lib.rpf_profile_reset.argtypes = []
     lib.rpf_profile_read.restype = i32
     lib.rpf_profile_read.argtypes = [ctypes.POINTER(ProfileRecord), i32, ctypes.POINTER(i32)]
+    u64 = ctypes.c_uint64
+    lib.rpf_query_workspace_bytes.restype = i32
+    lib.rpf_query_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(u64)]
+    lib.rpf_server_create.restype = i32
+    lib.rpf_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.rpf_server_submit.restype = i32
+    lib.rpf_server_submit.argtypes = [vp, vp, i64, i32, vp, vp, vp, ctypes.POINTER(u64)]
+    lib.rpf_server_poll.restype = i32
+    lib.rpf_server_poll.argtypes = [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    lib.rpf_server_wait.restype = i32
+    lib.rpf_server_wait.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
+    lib.rpf_server_stats.restype = i32
+    lib.rpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.rpf_server_reset_stats.restype = i32
+    lib.rpf_server_reset_stats.argtypes = [vp]
+    lib.rpf_server_destroy.restype = i32
+    lib.rpf_server_destroy.argtypes = [vp]
     lib.rpf_release_cached_memory.restype = i32
     lib.rpf_release_cached_memory.argtypes = [i32]
     lib.rpf_last_error.restype = ctypes.c_char_p
@@ -169,6 +199,11 @@ class Forest:
                                     perm.data_ptr(), leaf_of.data_ptr(), _stream(stream)))
         return dict(split=split[:H], split_idx=sidx[:H], chosen=chosen[:H], perm=perm, leaf_of=leaf_of)
 
+    def query_workspace_bytes(self, m: int, K: int) -> int:
+        b = ctypes.c_uint64(0)
+        _check(load().rpf_query_workspace_bytes(self.handle, m, K, ctypes.byref(b)))
+        return b.value
+
     def info(self) -> dict:
         inf = Info()
         _check(load().rpf_forest_info(self.handle, ctypes.byref(inf)))
@@ -233,3 +268,69 @@ def profile_read() -> dict:
 def release_cached_memory(device: int = -1):
     """Return the library's idle cached device blocks to the runtime."""
     _check(load().rpf_release_cached_memory(device))
+
+
+class Server:
+    """Continuous-batching query server over a resident forest (the library's serving loop).
+    submit() is non-blocking and returns a ticket; the caller keeps Q and the outputs alive
+    until the request is collected by poll() or wait()."""
+
+    def __init__(self, forest: Forest, slots: int = 4, max_batch_rows: int = 8192, max_queue: int = 1 << 16,
+                 mem_budget_bytes: int = 0):
+        self.forest = forest
+        cfg = ServerConfig(slots=slots, reserved=0, max_batch_rows=max_batch_rows, max_queue=max_queue,
+                           mem_budget_bytes=mem_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(load().rpf_server_create(forest.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, Q: torch.Tensor, K: int, out=None, stream=None) -> int:
+        Q = _dev(Q, torch.float32)
+        m = Q.shape[0]
+        if out is None:
+            out = (torch.empty((m, K), dtype=torch.int32, device=Q.device),
+                   torch.empty((m, K), dtype=torch.float32, device=Q.device))
+        t = ctypes.c_uint64(0)
+        _check(load().rpf_server_submit(self._h, Q.data_ptr(), m, K, out[0].data_ptr(), out[1].data_ptr(),
+                                        _stream(stream), ctypes.byref(t)))
+        self._keep[t.value] = (Q, out)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(idx, dist, latency_s) once done, else None."""
+        done = ctypes.c_int32(0)
+        lat = ctypes.c_double(0.0)
+        st = load().rpf_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(lat))
+        if st == RPF_ENOTREADY:
+            return None
+        _, out = self._keep.pop(ticket)
+        _check(st)
+        return out[0], out[1], lat.value
+
+    def wait(self, ticket: int):
+        lat = ctypes.c_double(0.0)
+        st = load().rpf_server_wait(self._h, ticket, ctypes.byref(lat))
+        _, out = self._keep.pop(ticket)
+        _check(st)
+        return out[0], out[1], lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(load().rpf_server_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _check(load().rpf_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h is not None:
+            _check(load().rpf_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

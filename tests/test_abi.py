@@ -66,3 +66,27 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.rpf_forest_info(None, None) == rpf.RPF_EINVAL
     cnt = ctypes.c_int32(-1)
     assert lib.rpf_profile_read(None, 0, ctypes.byref(cnt)) == rpf.RPF_OK and cnt.value >= 0
+
+
+def test_server_and_workspace_arguments_rejected_without_device():
+    lib = rpf.load()
+    fake = ctypes.c_void_p(0x1000)
+    cfg = rpf.ServerConfig(slots=2, reserved=0, max_batch_rows=1024, max_queue=16, mem_budget_bytes=0)
+    h = ctypes.c_void_p(1234)
+    assert lib.rpf_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert h.value is None
+    for field, bad in [("slots", 0), ("slots", 17), ("max_batch_rows", 0), ("max_queue", 0)]:
+        c = rpf.ServerConfig(slots=2, reserved=0, max_batch_rows=1024, max_queue=16, mem_budget_bytes=0)
+        setattr(c, field, bad)
+        assert lib.rpf_server_create(fake, ctypes.byref(c), ctypes.byref(h)) == rpf.RPF_EINVAL, field
+    t = ctypes.c_uint64(5)
+    assert lib.rpf_server_submit(None, fake, 10, 5, fake, fake, None, ctypes.byref(t)) == rpf.RPF_EINVAL
+    assert t.value == 0
+    done = ctypes.c_int32(3)
+    assert lib.rpf_server_poll(None, 1, ctypes.byref(done), None) == rpf.RPF_EINVAL and done.value == 0
+    assert lib.rpf_server_wait(None, 1, None) == rpf.RPF_EINVAL
+    assert lib.rpf_server_stats(None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_server_reset_stats(None) == rpf.RPF_EINVAL
+    assert lib.rpf_server_destroy(None) == rpf.RPF_OK
+    b = ctypes.c_uint64(0)
+    assert lib.rpf_query_workspace_bytes(None, 10, 5, ctypes.byref(b)) == rpf.RPF_EINVAL
