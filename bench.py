@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--only-serve", action="store_true", help="run the serving leg alone (profiling)")
     ap.add_argument("--serve-n", type=int, default=None, help="points of the served forest (default: 4M)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving measurement")
     ap.add_argument("--cpu-trees", type=int, default=1,
@@ -223,6 +224,9 @@ def main():
     from paper_1812_11689_amd import rpf
     from paper_1812_11689_amd import workloads as W
 
+    if args.only_serve:
+        print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
     t0 = time.time()
     w = W.make_config(2, n=args.n)
     n, d = w.x.shape

@@ -64,6 +64,30 @@ __device__ inline f32x16 mfma_step(const typename TileCfg<PREC>::T *sa, const ty
     }
 }
 
+// MFMA operand of one lane: one binary32, or eight 16-bit values
+template <int PREC>
+struct MfmaOperand {
+    using type = float;
+};
+template <>
+struct MfmaOperand<RPF_DIST_BF16> {
+    using type = bf16x8;
+};
+template <>
+struct MfmaOperand<RPF_DIST_FP16> {
+    using type = f16x8;
+};
+
+template <int PREC>
+__device__ inline f32x16 mfma_op(typename MfmaOperand<PREC>::type a, typename MfmaOperand<PREC>::type b, f32x16 acc) {
+    if constexpr (PREC == RPF_DIST_FP32)
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    else if constexpr (PREC == RPF_DIST_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+}
+
 template <int PREC>
 __device__ inline void stage_rows(typename TileCfg<PREC>::T *s, const typename TileCfg<PREC>::T *g, int rows,
                                   int rows_pad, int dp, int k0, int nthreads) {
@@ -456,7 +480,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
         const T *base = s_a + fr * C::LDW + fk;
-        using Frag = typename std::conditional<PREC == RPF_DIST_FP32, float, uint4>::type;
+        using Frag = typename MfmaOperand<PREC>::type;
         for (int kk = 0; kk < kmax; kk += C::KSTEP) {
             Frag fa[SLOTS], fb[SLOTS];  // all fragment loads of the step first, then the MFMAs
 #pragma unroll
@@ -466,9 +490,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             }
 #pragma unroll
             for (int sl = 0; sl < SLOTS; sl++)
-                if (act[sl])
-                    acc[sl] = mfma_step<PREC>(reinterpret_cast<const T *>(&fa[sl]),
-                                              reinterpret_cast<const T *>(&fb[sl]), acc[sl]);
+                if (act[sl]) acc[sl] = mfma_op<PREC>(fa[sl], fb[sl], acc[sl]);
         }
     }
 
@@ -558,6 +580,110 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             }
         }
         flush(qc);
+    }
+}
+
+// Query tiles for small groups: a group of at most QS queries that reached the same leaf
+// (one leaf block), against every row of the block.  One wave per job, eight lanes per
+// candidate row (16-byte coalesced reads straight from HBM), each lane keeping its fixed
+// share of the group's centred query copy in registers; the 8-lane partial products are
+// combined by shuffles.  Same stored operands and the same rigorous bounds as the MFMA
+// tiles (products of two tile-precision values accumulated in binary32, any order), and
+// the same outputs: Phase I fixed slots (mode 0) or records below the row's threshold
+// (mode 1).  A GEMV-shaped job moves the leaf block once per query group and does no MFMA
+// work on padding rows, which at a few queries per leaf is most of a 32-row MFMA block.
+template <int PREC, int QS, int NCH>
+__global__ __launch_bounds__(256) void k_qtile(const TileJob *__restrict__ jobs, int64_t njobs,
+                                               const void *__restrict__ A_, const void *__restrict__ B_, int dp,
+                                               int64_t a_stride_tree, int64_t b_stride_tree,
+                                               const float2 *__restrict__ a_nrm, const float2 *__restrict__ b_nrm,
+                                               const int32_t *__restrict__ a_dest, const int32_t *__restrict__ b_pt,
+                                               BoundCoef bc, TileOut out) {
+    using T = typename TileCfg<PREC>::T;
+    constexpr int EPC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+    const int lane = threadIdx.x & 63, g = lane & 7, grp = lane >> 3;
+    const int64_t jid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (jid >= njobs) return;
+    const TileJob job = jobs[jid];
+    const int t = job.tree;
+    const int nchunk = dp / EPC;  // 16-byte chunks per row (dp is a multiple of 8 elements);
+                                  // lane g takes chunks g, g + 8, ... (<= NCH of them by the launch)
+    const T *A = reinterpret_cast<const T *>(A_) + (t * a_stride_tree + job.a_off) * dp;
+    const T *B = reinterpret_cast<const T *>(B_) + (t * b_stride_tree + job.b_off) * dp;
+    const int na_rows = job.a_rows;  // <= QS by the launch
+    float qv[NCH][EPC][QS];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++)
+#pragma unroll
+        for (int e = 0; e < EPC; e++)
+#pragma unroll
+            for (int qi = 0; qi < QS; qi++) qv[ch][e][qi] = 0.f;
+#pragma unroll
+    for (int qi = 0; qi < QS; qi++) {
+        if (qi >= na_rows) continue;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ch++) {
+            if (g + 8 * ch >= nchunk) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(A + (int64_t)qi * dp + (g + 8 * ch) * EPC);
+            T pv[EPC];
+            __builtin_memcpy(pv, &v, sizeof(v));  // bytes -> elements (no aliasing through pointers)
+#pragma unroll
+            for (int e = 0; e < EPC; e++) qv[ch][e][qi] = (float)pv[e];
+        }
+    }
+    // this lane's query (g < rows of the group) for the bounds and the outputs
+    const int qme = g < na_rows ? g : 0;
+    const float2 aq = a_nrm[t * a_stride_tree + job.a_off + qme];
+    const int dst = a_dest[t * a_stride_tree + job.a_off + qme];
+    const float tq = out.mode == 1 ? out.tau[dst] : INFINITY;
+    const int tb = t - out.t0;
+    if (out.mode == 0 && job.b_pos + job.b_rows == job.leaf_m) {  // slots past the leaf
+        for (int qi = 0; qi < na_rows; qi++) {
+            const int dq = a_dest[t * a_stride_tree + job.a_off + qi];
+            const int64_t er = (int64_t)dq * out.cap + (int64_t)tb * out.ML;
+            for (int c = job.leaf_m + lane; c < out.ML; c += 64) put_first_empty(out, er + c);
+        }
+    }
+    for (int r0 = 0; r0 < job.b_rows; r0 += 8) {
+        const int r = r0 + grp;
+        const bool rok = r < job.b_rows;
+        const T *row = B + (int64_t)(rok ? r : 0) * dp;
+        float acc[QS];
+#pragma unroll
+        for (int qi = 0; qi < QS; qi++) acc[qi] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ch++) {
+            if (g + 8 * ch >= nchunk) continue;
+            const uint4 v = *reinterpret_cast<const uint4 *>(row + (g + 8 * ch) * EPC);
+            T pv[EPC];
+            __builtin_memcpy(pv, &v, sizeof(v));
+#pragma unroll
+            for (int e = 0; e < EPC; e++) {
+                const float x = (float)pv[e];
+#pragma unroll
+                for (int qi = 0; qi < QS; qi++) acc[qi] = __builtin_fmaf(x, qv[ch][e][qi], acc[qi]);
+            }
+        }
+#pragma unroll
+        for (int qi = 0; qi < QS; qi++) {
+            acc[qi] += __shfl_xor(acc[qi], 1, 64);
+            acc[qi] += __shfl_xor(acc[qi], 2, 64);
+            acc[qi] += __shfl_xor(acc[qi], 4, 64);
+        }
+        if (rok && g < na_rows) {
+            float gq = acc[0];
+#pragma unroll
+            for (int qi = 1; qi < QS; qi++)
+                if (g == qi) gq = acc[qi];
+            const float2 nb = b_nrm[t * b_stride_tree + job.b_off + r];
+            const int bpt = b_pt[t * b_stride_tree + job.b_off + r];
+            float lb, ub;
+            pair_bounds(aq.x, nb.x, aq.y, nb.y, gq, bc, lb, ub);
+            if (out.mode == 0)
+                put_first(out, (int64_t)dst * out.cap + (int64_t)tb * out.ML + job.b_pos + r, bpt, lb, ub);
+            else if (lb <= tq)
+                emit_filtered(out, dst, bpt, lb, ub);
+        }
     }
 }
 
@@ -1118,8 +1244,9 @@ __global__ void k_group_fill(const int32_t *__restrict__ qleaf, int64_t m, const
 
 // one tile job per (A chunk of a non-empty group) x (B tile of the leaf); the first trees -> list 0
 __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int64_t nleaf,
-                            const LeafDesc *__restrict__ leaves, int TR, int nfirst, TileJob *__restrict__ jobs0,
-                            TileJob *__restrict__ jobs1, int32_t *__restrict__ njobs) {
+                            const LeafDesc *__restrict__ leaves, int TR, int nfirst, int qs, TileJob *__restrict__ jobs0,
+                            TileJob *__restrict__ jobs1, TileJob *__restrict__ sjobs0, TileJob *__restrict__ sjobs1,
+                            int32_t *__restrict__ njobs) {
     const int t = blockIdx.y;
     for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < nleaf; li += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = gcount[(int64_t)t * nleaf + li];
@@ -1138,8 +1265,9 @@ __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *_
                 j.b_pos = J * TR;
                 j.leaf_m = lf.size;
                 const bool first = t < nfirst;
-                const int slot = atomicAdd(&njobs[first ? 0 : 1], 1);
-                (first ? jobs0 : jobs1)[slot] = j;
+                const bool small = c <= qs;  // a few queries: the GEMV-shaped kernel
+                const int slot = atomicAdd(&njobs[(first ? 0 : 1) + (small ? 2 : 0)], 1);
+                (small ? (first ? sjobs0 : sjobs1) : (first ? jobs0 : jobs1))[slot] = j;
             }
     }
 }
@@ -1275,7 +1403,52 @@ struct CandStage {
     double bytes0, bytes1;  // tile-operand bytes of the two phases
     bool sym;               // all-points with one tile per leaf: symmetric kernel
     int B;                  // trees of Phase I
+    const TileJob *sjobs0 = nullptr, *sjobs1 = nullptr;  // query groups of <= qs rows (GEMV-shaped)
+    int64_t nsjobs0 = 0, nsjobs1 = 0;
 };
+
+// group size and chunks per lane of the GEMV-shaped query kernel (64 registers of query per
+// lane); 0 = every job goes to the MFMA tiles
+static int qtile_qs(int prec, int dp) {
+    if (dp <= 128) return 4;
+    if (dp <= 256) return 2;
+    if (dp <= 512) return 1;
+    return 0;
+}
+
+template <int PREC, int QS, int NCH>
+static void qtile_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B, int dp,
+                         int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
+                         const int32_t *bp, BoundCoef bc, const TileOut &out) {
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL((k_qtile<PREC, QS, NCH>), dim3((unsigned)((njobs + 3) / 4)), dim3(256), 0, s, jobs, njobs, A, B,
+                       dp, as, bs, an, bn, ad, bp, bc, out);
+    launch_check(s, "k_qtile");
+}
+
+template <int PREC>
+static void qtile_dispatch_p(int qs, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, const void *B,
+                             int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
+                             const int32_t *bp, BoundCoef bc, const TileOut &out) {
+    constexpr int E = PREC == RPF_DIST_FP32 ? 4 : 8;  // elements per 16-byte chunk
+    if (qs == 4)
+        qtile_launch<PREC, 4, 128 / (8 * E)>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+    else if (qs == 2)
+        qtile_launch<PREC, 2, 256 / (8 * E)>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+    else if (qs == 1)
+        qtile_launch<PREC, 1, 512 / (8 * E)>(s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+}
+
+static void qtile_dispatch(int prec, int qs, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A,
+                           const void *B, int dp, int64_t as, int64_t bs, const float2 *an, const float2 *bn,
+                           const int32_t *ad, const int32_t *bp, BoundCoef bc, const TileOut &out) {
+    if (prec == RPF_DIST_BF16)
+        qtile_dispatch_p<RPF_DIST_BF16>(qs, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+    else if (prec == RPF_DIST_FP16)
+        qtile_dispatch_p<RPF_DIST_FP16>(qs, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+    else
+        qtile_dispatch_p<RPF_DIST_FP32>(qs, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
+}
 
 template <int NB, int PREC>
 static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
@@ -1361,6 +1534,8 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
         else
             tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o1);
+        qtile_dispatch(v.prec, qtile_qs(v.prec, v.dp), s, cs.nsjobs0, cs.sjobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n,
+                       cs.a_nrm, v.nrm, cs.a_dest, v.perm, bc, o1);
     }
     {
         ProfScope ps(s, "merge_first", 0, 0);
@@ -1372,7 +1547,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
                                K, cs.B, v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
         launch_check(s, "k_merge_first");
     }
-    if (cs.njobs1 > 0) {
+    if (cs.njobs1 > 0 || cs.nsjobs1 > 0) {
         TileOut o2 = o1;
         o2.mode = 1;
         o2.cap = cap2;
@@ -1384,6 +1559,8 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
         else
             tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o2);
+        qtile_dispatch(v.prec, qtile_qs(v.prec, v.dp), s, cs.nsjobs1, cs.sjobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n,
+                       cs.a_nrm, v.nrm, cs.a_dest, v.perm, bc, o2);
     }
     FinalArgs fa;
     fa.list = list; fa.lcnt = lcnt; fa.lcap = lcap; fa.cnt = cnt; fa.ent = ent; fa.cap = cap2; fa.K = K;
@@ -1500,6 +1677,9 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     const int64_t jcap1 = jcap_tree * (T > nfirst ? T - nfirst : 1);
     TileJob *jobs0 = ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob));
     TileJob *jobs1 = ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob));
+    const int qs = qtile_qs(v.prec, v.dp);
+    TileJob *sjobs0 = qs ? ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob)) : nullptr;
+    TileJob *sjobs1 = qs ? ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob)) : nullptr;
     int32_t *njobs = ws.get<int32_t>(16);
     if (!ws.ok) return fail(RPF_ENOMEM, "rpf_query: workspace allocation failed");
     rpf_status st = route(f, Q, m, qleaf, s);
@@ -1513,8 +1693,8 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     hipLaunchKernelGGL(k_group_fill, dim3(qb, T), dim3(256), 0, s, qleaf, m, v.heap_leaf, nleaf, goff, gfill, qorder,
                        qgleaf);
     const unsigned lb_ = (unsigned)std::min<int64_t>((nleaf + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_make_jobs, dim3(lb_, T), dim3(256), 0, s, gcount, goff, nleaf, v.leaves, TR, nfirst, jobs0,
-                       jobs1, njobs);
+    hipLaunchKernelGGL(k_make_jobs, dim3(lb_, T), dim3(256), 0, s, gcount, goff, nleaf, v.leaves, TR, nfirst, qs,
+                       jobs0, jobs1, sjobs0, sjobs1, njobs);
     launch_check(s, "query grouping");
     {
         dim3 g((unsigned)((m + 3) / 4), T);
@@ -1530,8 +1710,8 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     }
     // the job counts are needed to size the tile grids: read them back (small, one sync)
     launch_check(s, "k_query_prep");
-    int32_t nj[2] = {0, 0};
-    hipMemcpyAsync(nj, njobs, 8, hipMemcpyDeviceToHost, s);
+    int32_t nj[4] = {0, 0, 0, 0};
+    hipMemcpyAsync(nj, njobs, 16, hipMemcpyDeviceToHost, s);
     st = check_hip(hipStreamSynchronize(s), "rpf_query grouping");
     if (st != RPF_OK) return st;
     {
@@ -1545,6 +1725,10 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     cs.B = nfirst;
     cs.njobs0 = nj[0];
     cs.njobs1 = T > nfirst ? nj[1] : 0;
+    cs.sjobs0 = sjobs0;
+    cs.sjobs1 = sjobs1;
+    cs.nsjobs0 = nj[2];
+    cs.nsjobs1 = T > nfirst ? nj[3] : 0;
     cs.A = Qc;
     cs.a_stride = m;
     cs.a_nrm = qnrm;
@@ -1570,7 +1754,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     b += (uint64_t)T * m * 4 * 3;                  // leaf per tree, order, group leaf
     b += (uint64_t)T * nleaf * 4 * 3;              // group counts, offsets, fill
     b += (uint64_t)T * m * v.dp * esz + (uint64_t)T * m * 8;  // centred queries and norms
-    b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob);
+    b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob) * (qtile_qs(v.prec, v.dp) ? 2 : 1);
     const uint64_t cap1 = (uint64_t)v.max_leaf * B, cap2 = kFinalCap - kListCap;
     b += std::max(m * cap1 * 12, m * cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 4 + (uint64_t)m * kListCap * sizeof(Ent) + 16 * 3;

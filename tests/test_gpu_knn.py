@@ -82,6 +82,13 @@ QUERY = [
     ("q_bf16", 12_000, 64, 4, 100, 10, "bf16", 1500),
     ("q_fp16", 12_000, 96, 5, 256, 20, "fp16", 1000),
     ("q_one", 5000, 16, 3, 30, 5, "fp32", 1),
+    # few queries per leaf: groups of <= 4 (d <= 128), <= 2 (d <= 256) and 1 (d <= 512) query
+    # rows take the GEMV-shaped kernel; d not a multiple of the 16-byte chunk
+    ("q_sparse_fp32_d40", 20_000, 40, 4, 30, 10, "fp32", 300),
+    ("q_sparse_fp16_d20", 20_000, 20, 4, 30, 7, "fp16", 400),
+    ("q_sparse_bf16_d200", 8000, 200, 3, 40, 8, "bf16", 150),
+    ("q_sparse_fp32_d360", 6000, 360, 3, 40, 6, "fp32", 100),
+    ("q_sparse_fp16_d600", 5000, 600, 3, 40, 6, "fp16", 60),
 ]
 
 
