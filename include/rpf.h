@@ -83,6 +83,32 @@ int32_t rpf_depth(int64_t n, int32_t leaf_size);
 rpf_status rpf_build(const float *X_dev, int64_t n, int32_t d, const rpf_params *params,
                      void *stream, rpf_forest **out);
 
+/* ---- Many independent data sets of the same dimension in one forest.
+ *
+ * X_dev holds the data sets one after the other (binary32 [sum n_i][d]); n_host[i] >= 1 is
+ * the size of data set i.  Every data set gets its own T trees (same n_trees, leaf_size,
+ * n_try, dist_prec), grown together with all the others, level by level, in the same
+ * launches; leaves never mix data sets.  directions_dev is [n_trees][sum H_i][n_try][d] with
+ * H_i = 2^L_i - 1, L_i = rpf_depth(n_i, leaf_size): row hbase_i + h - 1 is node h of data set
+ * i, hbase_i = sum over j < i of H_j (rpf_batch_info gives it).  Each data set's forest is
+ * exactly the forest rpf_build grows over it alone with its own rows of the directions.
+ * rpf_all_knn on such a forest searches every point within its own data set and returns
+ * indices within that data set; rpf_query and rpf_route return RPF_EINVAL.  In
+ * rpf_tree_dump, split arrays are [sum H_i] (global node ids) and leaf_of holds global leaf
+ * ids lbase_i + h. */
+typedef struct {
+    int64_t offset;          /* first point of the data set in X                            */
+    int64_t n;
+    int32_t depth;           /* L_i                                                         */
+    int32_t reserved;
+    int64_t heap_base;       /* hbase_i: global id of internal node h is hbase_i + h        */
+    int64_t leaf_heap_base;  /* lbase_i: global id of leaf h is lbase_i + h                 */
+} rpf_batch_entry;
+
+rpf_status rpf_build_batched(const float *X_dev, const int64_t *n_host, int32_t count, int32_t d,
+                             const rpf_params *params, void *stream, rpf_forest **out);
+rpf_status rpf_batch_info(const rpf_forest *f, int32_t index, rpf_batch_entry *out_host);
+
 /* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
  * exclude_self = 1 drops each point from its own candidate set.  1 <= K <= n - exclude_self.
  * Rows shorter than K (|N_q| < K) are padded with (-1, +inf). */
@@ -113,10 +139,12 @@ rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split_dev,
                          int32_t *leaf_of_dev, void *stream);
 
 typedef struct {
-    int64_t n;
+    int64_t n;               /* points (all data sets of a batched forest)                  */
     int32_t d, n_trees, leaf_size, n_try, depth, dist_prec;
     int64_t n_leaves;
-    uint64_t device_bytes;   /* device memory owned by the forest */
+    uint64_t device_bytes;   /* device memory owned by the forest                           */
+    int32_t batch_count;     /* data sets (1 unless built by rpf_build_batched)             */
+    int32_t reserved;
 } rpf_info;
 
 rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);

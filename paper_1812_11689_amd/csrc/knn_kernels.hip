@@ -1167,6 +1167,32 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
     }
 }
 
+// ---------------------------------------------------------------- batched forests
+
+// neighbour indices of a forest over several data sets: global point index -> index within
+// the row's own data set (candidates never leave a data set, so one offset per row)
+__global__ void k_localize(int32_t *__restrict__ idx, int64_t rows, int K, const int64_t *__restrict__ off,
+                           int count) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = count - 1;  // last data set whose offset is <= r
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t base = (int32_t)off[lo];
+        int32_t *row = idx + r * K;
+        for (int k = 0; k < K; k++)
+            if (row[k] >= 0) row[k] -= base;
+    }
+}
+
+void launch_localize(int32_t *idx, int64_t rows, int K, const int64_t *off, int count, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((rows + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_localize, dim3(blocks), dim3(256), 0, s, idx, rows, K, off, count);
+    launch_check(s, "k_localize");
+}
+
 // ---------------------------------------------------------------- routing (Alg. 3, descent of a query through each tree)
 
 template <bool VEC>

@@ -32,6 +32,7 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
+void launch_localize(int32_t *idx, int64_t rows, int K, const int64_t *off, int count, hipStream_t s);
 
 
 // ---------------------------------------------------------------- errors
@@ -182,8 +183,11 @@ struct rpf_forest {
     std::vector<LeafDesc> leaves;
     int max_leaf = 0;
     uint64_t bytes = 0;
+    // batched forests: one root per data set (a single data set is the one-root case)
+    std::vector<rpf_batch_entry> batch;
+    int64_t *d_batch_off = nullptr;       // [count + 1] first point of every data set, then n
     // stats of the last kNN call
-    unsigned long long *stats = nullptr;  // [4]
+    unsigned long long *stats = nullptr;  // [kStatSlots][8]
     mutable std::mutex mu;
 };
 
@@ -259,7 +263,7 @@ rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
-                    f->d_copy, f->d_jobs, f->stats};
+                    f->d_copy, f->d_jobs, f->stats, f->d_batch_off};
     for (void *p : ptrs) cache_free(p, nullptr);
 }
 
@@ -271,12 +275,27 @@ rpf_status rpf_free(rpf_forest *f) {
     return RPF_OK;
 }
 
-rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream, rpf_forest **out) {
+}  // extern "C"
+
+// Grow the forest over `count` data sets concatenated in X ([sum n_i][d]); every data set is
+// an independent root whose trees advance with all the others, level by level, in the same
+// launches.  Internal node h (heap id, root 1) of data set i has the global id hbase_i + h,
+// with hbase_i = sum over j < i of (2^L_j - 1): the direction and split arrays are
+// [T][sum H_i] and the kernels index them as for one tree.  Leaf h of data set i has the id
+// lbase_i + h, lbase_i = sum over j < i of 2^(L_j + 1), in leaf_of and in the leaf table.
+static rpf_status build_impl(const float *X, const int64_t *sizes, int count, int32_t d, const rpf_params *p,
+                             void *stream, rpf_forest **out) {
     if (out) *out = nullptr;
     if (!out) return fail(RPF_EINVAL, "rpf_build: out is NULL");
     if (!X) return fail(RPF_EINVAL, "rpf_build: X is NULL");
     if (!p) return fail(RPF_EINVAL, "rpf_build: params is NULL");
-    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: n must be in [1, 2^31)");
+    if (!sizes || count < 1) return fail(RPF_EINVAL, "rpf_build: no data set");
+    int64_t n = 0;
+    for (int i = 0; i < count; i++) {
+        if (sizes[i] < 1) return fail(RPF_EINVAL, "rpf_build: every data set needs n >= 1");
+        n += sizes[i];
+        if (n >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: n must be in [1, 2^31)");
+    }
     if (d < 1) return fail(RPF_EINVAL, "rpf_build: d must be >= 1");
     if (d > 4096) return fail(RPF_EINVAL, "rpf_build: d above 4096 is not supported (per-block staging)");
     if (p->n_trees < 1 || p->n_trees > 65535) return fail(RPF_EINVAL, "rpf_build: n_trees must be in [1, 65535]");
@@ -286,9 +305,23 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_FP16)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
     if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
-    const int L = depth_of(n, p->leaf_size);
-    if (L > 30) return fail(RPF_EINVAL, "rpf_build: tree deeper than 30 levels");
-    const int64_t H = ((int64_t)1 << L) - 1;
+    std::vector<rpf_batch_entry> roots(count);
+    int L = 0;
+    int64_t H = 0, LB = 0;
+    for (int i = 0; i < count; i++) {
+        rpf_batch_entry &r = roots[i];
+        r.offset = i ? roots[i - 1].offset + roots[i - 1].n : 0;
+        r.n = sizes[i];
+        r.depth = depth_of(sizes[i], p->leaf_size);
+        if (r.depth > 30) return fail(RPF_EINVAL, "rpf_build: tree deeper than 30 levels");
+        r.reserved = 0;
+        r.heap_base = H;
+        r.leaf_heap_base = LB;
+        H += ((int64_t)1 << r.depth) - 1;
+        LB += (int64_t)2 << r.depth;
+        L = std::max(L, (int)r.depth);
+    }
+    if (H >= ((int64_t)1 << 31) || LB >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: too many tree nodes");
     if (H > 0 && !p->directions_dev) return fail(RPF_EINVAL, "rpf_build: directions_dev is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int T = p->n_trees, n0 = p->leaf_size, n_try = p->n_try;
@@ -300,19 +333,21 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     std::vector<LevelPlan> levels(L);
     std::vector<LeafDesc> leaves;
     {
-        struct Node { int64_t heap, off, size; };
-        std::vector<Node> cur{{1, 0, n}};
+        struct Node { int64_t heap, off, size; int root; };  // heap: id within its data set
+        std::vector<Node> cur;
+        for (int i = 0; i < count; i++) cur.push_back({1, roots[i].offset, roots[i].n, i});
         std::vector<LeafDesc> formed;
         for (int l = 0; l <= L; l++) {
             std::vector<Node> next;
             for (auto &nd : cur) {
-                if (nd.size > n0 && l < L) {
-                    levels[l].segs.push_back(SegDesc{nd.off, (int32_t)nd.size, (int32_t)nd.heap, 0, 0});
+                const rpf_batch_entry &r = roots[nd.root];
+                if (nd.size > n0 && l < r.depth) {
+                    levels[l].segs.push_back(SegDesc{nd.off, (int32_t)nd.size, (int32_t)(r.heap_base + nd.heap), 0, 0});
                     levels[l].max_m = std::max<int>(levels[l].max_m, (int)nd.size);
-                    next.push_back({2 * nd.heap, nd.off, nd.size / 2});
-                    next.push_back({2 * nd.heap + 1, nd.off + nd.size / 2, nd.size - nd.size / 2});
+                    next.push_back({2 * nd.heap, nd.off, nd.size / 2, nd.root});
+                    next.push_back({2 * nd.heap + 1, nd.off + nd.size / 2, nd.size - nd.size / 2, nd.root});
                 } else {
-                    formed.push_back(LeafDesc{nd.off, (int32_t)nd.size, (int32_t)nd.heap});
+                    formed.push_back(LeafDesc{nd.off, (int32_t)nd.size, (int32_t)(r.leaf_heap_base + nd.heap)});
                 }
             }
             if (l < L) levels[l].copy = formed;  // leaves carried into this level's output
@@ -380,6 +415,7 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
     f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
     f->bytes = bytes;
+    f->batch = roots;
 
     auto bail = [&](rpf_status st) {
         hipStreamSynchronize(s);
@@ -412,7 +448,8 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     RPF_ALLOC(f->nrm, (size_t)T * n * 8);
     RPF_ALLOC(f->err, 64);
     RPF_ALLOC(f->stats, kStatSlots * 8 * 8);
-    RPF_ALLOC(f->heap_leaf, ((size_t)4 << L) * sizeof(int32_t));  // heap ids < 2^(L+1)
+    RPF_ALLOC(f->heap_leaf, ((size_t)LB + 1) * sizeof(int32_t));  // leaf ids < lbase + 2^(L+1)
+    RPF_ALLOC(f->d_batch_off, ((size_t)count + 1) * sizeof(int64_t));
     if (nseg_tot) RPF_ALLOC(f->d_segs, nseg_tot * sizeof(SegDesc));
     if (nchunk_tot) RPF_ALLOC(f->d_chunks, nchunk_tot * sizeof(ChunkDesc));
     RPF_ALLOC(f->d_leaves, nleaf * sizeof(LeafDesc));
@@ -427,8 +464,12 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
         all_chunks.insert(all_chunks.end(), lv.chunks.begin(), lv.chunks.end());
         all_copy.insert(all_copy.end(), lv.copy.begin(), lv.copy.end());
     }
-    std::vector<int32_t> hl((size_t)4 << L, -1);
+    std::vector<int32_t> hl((size_t)LB + 1, -1);
     for (size_t i = 0; i < leaves.size(); i++) hl[leaves[i].heap] = (int32_t)i;
+    std::vector<int64_t> boff((size_t)count + 1);
+    for (int i = 0; i < count; i++) boff[i] = roots[i].offset;
+    boff[count] = n;
+    hipMemcpyAsync(f->d_batch_off, boff.data(), boff.size() * 8, hipMemcpyHostToDevice, s);
     std::vector<double> nan_row((size_t)T * H, NAN);
     if (nseg_tot) hipMemcpyAsync(f->d_segs, all_segs.data(), nseg_tot * sizeof(SegDesc), hipMemcpyHostToDevice, s);
     if (nchunk_tot)
@@ -570,6 +611,26 @@ rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, 
     return RPF_OK;
 }
 
+extern "C" {
+
+rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream, rpf_forest **out) {
+    return build_impl(X, &n, 1, d, p, stream, out);
+}
+
+rpf_status rpf_build_batched(const float *X, const int64_t *n_host, int32_t count, int32_t d, const rpf_params *p,
+                             void *stream, rpf_forest **out) {
+    if (out) *out = nullptr;
+    if (!n_host || count < 1) return fail(RPF_EINVAL, "rpf_build_batched: need count >= 1 sizes");
+    return build_impl(X, n_host, count, d, p, stream, out);
+}
+
+rpf_status rpf_batch_info(const rpf_forest *f, int32_t i, rpf_batch_entry *out) {
+    if (!f || !out) return fail(RPF_EINVAL, "rpf_batch_info: NULL pointer");
+    if (i < 0 || i >= (int32_t)f->batch.size()) return fail(RPF_EINVAL, "rpf_batch_info: data set out of range");
+    *out = f->batch[i];
+    return RPF_OK;
+}
+
 rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self, int32_t *out_idx, float *out_dist,
                        void *stream) {
     if (!f) return fail(RPF_EINVAL, "rpf_all_knn: forest is NULL");
@@ -577,7 +638,11 @@ rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self, int
     if (exclude_self != 0 && exclude_self != 1) return fail(RPF_EINVAL, "rpf_all_knn: exclude_self must be 0 or 1");
     if (K < 1 || K > f->n - exclude_self) return fail(RPF_EINVAL, "rpf_all_knn: K must be in [1, n - exclude_self]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_all_knn: K above 256 is not supported");
-    return knn_all(f, K, exclude_self, out_idx, out_dist, (hipStream_t)stream);
+    const rpf_status st = knn_all(f, K, exclude_self, out_idx, out_dist, (hipStream_t)stream);
+    if (st != RPF_OK || f->batch.size() < 2) return st;
+    launch_localize(out_idx, f->n, K, f->d_batch_off, (int)f->batch.size(), (hipStream_t)stream);
+    const std::string le = take_launch_error();
+    return le.empty() ? RPF_OK : fail(RPF_EDEVICE, "rpf_all_knn: " + le);
 }
 
 rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, int32_t *out_idx, float *out_dist,
@@ -588,6 +653,7 @@ rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, 
     if (!Q || !out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_query: NULL pointer");
     if (K < 1 || K > f->n) return fail(RPF_EINVAL, "rpf_query: K must be in [1, n]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_query: K above 256 is not supported");
+    if (f->batch.size() > 1) return fail(RPF_EINVAL, "rpf_query: the forest holds several data sets");
     return knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
 }
 
@@ -600,6 +666,7 @@ rpf_status rpf_query_workspace_bytes(const rpf_forest *f, int64_t m, int32_t K, 
 
 rpf_status rpf_route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, void *stream) {
     if (!f) return fail(RPF_EINVAL, "rpf_route: forest is NULL");
+    if (f->batch.size() > 1) return fail(RPF_EINVAL, "rpf_route: the forest holds several data sets");
     if (m < 0) return fail(RPF_EINVAL, "rpf_route: m must be >= 0");
     if (m == 0) return RPF_OK;
     if (!Q || !out_leaf) return fail(RPF_EINVAL, "rpf_route: NULL pointer");
@@ -631,6 +698,8 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
     out->dist_prec = f->prec;
     out->n_leaves = (int64_t)f->leaves.size();
     out->device_bytes = f->bytes;
+    out->batch_count = (int32_t)f->batch.size();
+    out->reserved = 0;
     int32_t err = 0;
     hipDeviceSynchronize();
     hipMemcpy(&err, f->err, 4, hipMemcpyDeviceToHost);

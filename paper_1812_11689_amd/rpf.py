@@ -24,7 +24,7 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_destroy", "rpf_last_error"]
+           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_last_error"]
 
 
 class RpfError(RuntimeError):
@@ -42,7 +42,13 @@ class Params(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("n_trees", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("dist_prec", ctypes.c_int32), ("n_leaves", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
+                ("dist_prec", ctypes.c_int32), ("n_leaves", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
+                ("batch_count", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchEntry(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("n", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("heap_base", ctypes.c_int64), ("leaf_heap_base", ctypes.c_int64)]
 
 
 class KnnStats(ctypes.Structure):
@@ -121,6 +127,10 @@ def load(path: str = LIB_PATH):
     lib.rpf_server_reset_stats.argtypes = [vp]
     lib.rpf_server_destroy.restype = i32
     lib.rpf_server_destroy.argtypes = [vp]
+    lib.rpf_build_batched.restype = i32
+    lib.rpf_build_batched.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    lib.rpf_batch_info.restype = i32
+    lib.rpf_batch_info.argtypes = [vp, i32, ctypes.POINTER(BatchEntry)]
     lib.rpf_release_cached_memory.restype = i32
     lib.rpf_release_cached_memory.argtypes = [i32]
     lib.rpf_last_error.restype = ctypes.c_char_p
@@ -188,8 +198,11 @@ class Forest:
         _check(load().rpf_route(self.handle, Q.data_ptr(), Q.shape[0], out.data_ptr(), _stream(stream)))
         return out
 
+    def _nodes(self) -> int:
+        return (1 << self.depth) - 1
+
     def tree_dump(self, t: int, stream=None):
-        H = (1 << self.depth) - 1
+        H = self._nodes()
         split = torch.empty(max(H, 1), dtype=torch.float64, device="cuda")
         sidx = torch.empty(max(H, 1), dtype=torch.int32, device="cuda")
         chosen = torch.empty(max(H, 1), dtype=torch.int32, device="cuda")
@@ -243,6 +256,63 @@ def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tenso
     h = ctypes.c_void_p()
     _check(load().rpf_build(X.data_ptr(), n, d, ctypes.byref(p), _stream(stream), ctypes.byref(h)))
     return Forest(h, n, d, n_trees, leaf_size, n_try, L)
+
+
+class BatchedForest(Forest):
+    """A forest over several data sets of the same d, grown together (rpf_build_batched)."""
+
+    def _nodes(self) -> int:
+        return sum((1 << depth(n, self.leaf_size)) - 1 for n in self.sizes)
+
+    def entries(self):
+        out = []
+        for i in range(self.count):
+            e = BatchEntry()
+            _check(load().rpf_batch_info(self.handle, i, ctypes.byref(e)))
+            out.append({k: getattr(e, k) for k, _ in BatchEntry._fields_})
+        return out
+
+    def all_knn_split(self, K: int, exclude_self: bool = True, stream=None):
+        """all_knn, split into one (idx, dist) pair per data set (indices within the set)."""
+        idx, dist = self.all_knn(K, exclude_self, stream)
+        return [(idx[e["offset"]:e["offset"] + e["n"]], dist[e["offset"]:e["offset"] + e["n"]])
+                for e in self.entries()]
+
+
+def batched_directions_rows(sizes, leaf_size: int):
+    """Heap-node count H_i of every data set and the row offset hbase_i of its directions."""
+    Hs = [(1 << depth(int(n), leaf_size)) - 1 for n in sizes]
+    base = [0]
+    for h in Hs[:-1]:
+        base.append(base[-1] + h)
+    return Hs, base
+
+
+def build_batched(Xs, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
+                  dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None) -> BatchedForest:
+    """Grow one forest per data set (same d) in shared launches.  Xs: list of float32 [n_i][d]
+    device tensors (or one concatenated tensor with `sizes` given as a list of (X, n) pairs);
+    directions: float32 [n_trees][sum H_i][n_try][d] on the device (see batched_directions_rows)."""
+    sizes = [int(x.shape[0]) for x in Xs]
+    d = int(Xs[0].shape[1])
+    if any(int(x.shape[1]) != d for x in Xs):
+        raise ValueError("every data set of one batched forest needs the same d")
+    X = torch.cat([_dev(x, torch.float32) for x in Xs]) if len(Xs) > 1 else _dev(Xs[0], torch.float32)
+    dptr = None
+    if directions is not None:
+        directions = _dev(directions, torch.float32)
+        dptr = directions.data_ptr()
+    p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
+               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+               directions_dev=dptr, mem_budget_bytes=mem_budget_bytes)
+    ns = (ctypes.c_int64 * len(sizes))(*sizes)
+    h = ctypes.c_void_p()
+    _check(load().rpf_build_batched(X.data_ptr(), ns, len(sizes), d, ctypes.byref(p), _stream(stream),
+                                    ctypes.byref(h)))
+    f = BatchedForest(h, sum(sizes), d, n_trees, leaf_size, n_try, max(depth(n, leaf_size) for n in sizes))
+    f.count = len(sizes)
+    f.sizes = sizes
+    return f
 
 
 def profile_enable(on: bool = True):
