@@ -109,6 +109,32 @@ rpf_status rpf_build_batched(const float *X_dev, const int64_t *n_host, int32_t 
                              const rpf_params *params, void *stream, rpf_forest **out);
 rpf_status rpf_batch_info(const rpf_forest *f, int32_t index, rpf_batch_entry *out_host);
 
+/* ---- A build and all-points search of fixed shapes, recorded once and replayed.
+ *
+ * rpf_plan_create plans a forest over `count` data sets of sizes n_host (as
+ * rpf_build_batched; count = 1 is one data set) and allocates every buffer: the inputs X
+ * [sum n_i][d] and directions [n_trees][sum H_i][n_try][d], and the outputs [sum n_i][K]
+ * (indices within each data set).  It records, as one HIP graph, the input checks, every
+ * level of every tree, the leaf pass, the candidate stage and the index localisation (no
+ * allocation, synchronisation or memset inside).  params->directions_dev is not used.
+ * rpf_plan_buffers returns the device buffers: write X and the directions, then
+ * rpf_plan_launch runs the whole graph on `stream` (asynchronous); rpf_plan_check
+ * synchronises the stream and reports non-finite inputs (RPF_EINVAL) or an internal error.
+ * Every launch rebuilds the forest from the current buffer contents; rpf_plan_forest gives
+ * the forest of the last launch for introspection (rpf_tree_dump, rpf_forest_info); it must
+ * not be freed, and rpf_all_knn / rpf_query on it are allowed between launches.  Launches of
+ * one plan must not overlap. */
+typedef struct rpf_plan rpf_plan;
+
+rpf_status rpf_plan_create(const int64_t *n_host, int32_t count, int32_t d, const rpf_params *params,
+                           int32_t K, int32_t exclude_self, void *stream, rpf_plan **out);
+rpf_status rpf_plan_buffers(rpf_plan *plan, float **X_dev, float **directions_dev, int32_t **out_idx_dev,
+                            float **out_dist_dev);
+rpf_status rpf_plan_launch(rpf_plan *plan, void *stream);
+rpf_status rpf_plan_check(rpf_plan *plan, void *stream);
+const rpf_forest *rpf_plan_forest(const rpf_plan *plan);
+rpf_status rpf_plan_destroy(rpf_plan *plan);
+
 /* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
  * exclude_self = 1 drops each point from its own candidate set.  1 <= K <= n - exclude_self.
  * Rows shorter than K (|N_q| < K) are padded with (-1, +inf). */

@@ -776,8 +776,9 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
     dim3 gs(nseg, T), gc(nchunk, T);
     hipLaunchKernelGGL(k_sel_init, dim3((nseg * T + 255) / 256), dim3(256), 0, s, segs, nseg, T, b.state);
     launch_check(s, "k_sel_init");
-    hipMemsetAsync(b.hist, 0, sizeof(uint32_t) * kDigitBins * (size_t)nseg * T, s);
-    hipMemsetAsync(b.cand_cnt, 0, sizeof(uint32_t) * (size_t)nseg * T, s);
+    // fill kernels, not memsets: the level may be recorded in a graph
+    fill_u32(b.hist, (int64_t)kDigitBins * nseg * T, 0, s);
+    fill_u32(b.cand_cnt, (int64_t)nseg * T, 0, s);
     launch_check(s, "select memsets");
     if (n_try > 1) {
         for (int tr = 0; tr < n_try; tr++) {

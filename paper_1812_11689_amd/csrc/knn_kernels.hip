@@ -1513,33 +1513,65 @@ static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const T
         sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
 }
 
-static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
-                                 float *out_dist, hipStream_t s) {
-    Workspace ws(s);
+// device buffers of the candidate stage (one call)
+struct CandWs {
+    int lcap = 0, cap1 = 0, cap2 = 0;
+    uint8_t *region = nullptr;  // Phase I index / lb / ub arrays, then the Phase II records
+    float *tau = nullptr;
+    int32_t *cnt = nullptr, *lcnt = nullptr, *fb_list = nullptr, *fb_cnt = nullptr;
+    Ent *list = nullptr;
+};
+
+// Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
+// threshold of the union of those leaves.  `get` hands out device bytes (nullptr = failure).
+template <typename Get>
+static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
-    // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
-    // threshold of the union of those leaves
-    const int lcap = kListCap;
-    const int cap1 = v.max_leaf * cs.B;  // Phase I slots per row (index / lb / ub arrays)
-    const int cap2 = kFinalCap - lcap;   // Phase II records per row
+    w.lcap = kListCap;
+    w.cap1 = v.max_leaf * cs.B;      // Phase I slots per row (index / lb / ub arrays)
+    w.cap2 = kFinalCap - w.lcap;     // Phase II records per row
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
-    const size_t first_bytes = (size_t)rows * cap1 * 12;
-    const size_t second_bytes = (size_t)rows * cap2 * sizeof(Ent);
-    uint8_t *region = ws.get<uint8_t>(std::max(first_bytes, second_bytes) + 256);
-    float *tau = ws.get<float>(rows * 4);
-    int32_t *cnt = ws.get<int32_t>(rows * 4);
+    const size_t first_bytes = (size_t)rows * w.cap1 * 12;
+    const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
+    w.region = static_cast<uint8_t *>(get(std::max(first_bytes, second_bytes) + 256));
+    w.tau = static_cast<float *>(get(rows * 4));
+    w.cnt = static_cast<int32_t *>(get(rows * 4));
+    w.list = static_cast<Ent *>(get((size_t)rows * w.lcap * sizeof(Ent)));
+    w.lcnt = static_cast<int32_t *>(get(rows * 4));
+    w.fb_list = static_cast<int32_t *>(get(rows * 4));
+    w.fb_cnt = static_cast<int32_t *>(get(16));
+    return w.region && w.tau && w.cnt && w.list && w.lcnt && w.fb_list && w.fb_cnt;
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t count, uint32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// a small fill kernel rather than a memset, so the launch sequence can be recorded in a graph
+void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s) {
+    if (count <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t *>(p), count, value);
+    launch_check(s, "k_fill_u32");
+}
+
+// the candidate stage as launches only (no allocation, no synchronisation)
+static void cand_launches(const ForestView &v, const CandStage &cs, int K, const CandWs &w, int32_t *out_idx,
+                          float *out_dist, hipStream_t s) {
+    const int64_t rows = cs.rows;
+    const int lcap = w.lcap, cap1 = w.cap1, cap2 = w.cap2;
+    uint8_t *region = w.region;
+    float *tau = w.tau;
+    int32_t *cnt = w.cnt, *lcnt = w.lcnt, *fb_list = w.fb_list, *fb_cnt = w.fb_cnt;
+    Ent *list = w.list;
     Ent *ent = reinterpret_cast<Ent *>(region);
     int32_t *pidx = reinterpret_cast<int32_t *>(region);
     float *plb = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 4);
     float *pub = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 8);
-    Ent *list = ws.get<Ent>((size_t)rows * lcap * sizeof(Ent));
-    int32_t *lcnt = ws.get<int32_t>(rows * 4);
-    int32_t *fb_list = ws.get<int32_t>(rows * 4);
-    int32_t *fb_cnt = ws.get<int32_t>(16);
-    if (!ws.ok) return fail(RPF_ENOMEM, "kNN workspace allocation failed");
-    hipMemsetAsync(cnt, 0, rows * 4, s);
-    hipMemsetAsync(fb_cnt, 0, 16, s);
-    hipMemsetAsync(v.stats, 0, kStatSlots * 8 * 8, s);
+    fill_u32(cnt, rows, 0, s);
+    fill_u32(fb_cnt, 4, 0, s);
+    fill_u32(v.stats, kStatSlots * 8 * 2, 0, s);
     const BoundCoef bc = bound_coef(v.prec, v.d);
     const int MB = v.job_mb;
     TileOut o1;
@@ -1617,15 +1649,21 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
             hipLaunchKernelGGL(k_fallback<false>, dim3(nb), dim3(256), v.d * 4, s, fb);
         launch_check(s, "k_fallback");
     }
+}
+
+static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
+                                 float *out_dist, hipStream_t s) {
+    Workspace ws(s);
+    CandWs w;
+    if (!cand_ws_alloc(v, cs, [&](size_t b) { return ws.get<void>(b); }, w) || !ws.ok)
+        return fail(RPF_ENOMEM, "kNN workspace allocation failed");
+    cand_launches(v, cs, K, w, out_idx, out_dist, s);
     const std::string le = take_launch_error();
     if (!le.empty()) return fail(RPF_EDEVICE, "kNN: " + le);
     return RPF_OK;
 }
 
-rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s) {
-    const ForestView v = view(f);
-    int dev = 0;
-    hipGetDevice(&dev);
+static CandStage all_points_stage(const ForestView &v, int K, int exclude_self) {
     CandStage cs;
     cs.rows = v.n;
     cs.B = first_trees(v.T, K, v.max_leaf);
@@ -1646,7 +1684,49 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     cs.bytes0 = (double)v.n * v.dp * esz * cs.B;
     cs.bytes1 = (double)v.n * v.dp * esz * (v.T - cs.B);
     cs.sym = v.max_leaf <= 32 * v.job_mb;  // every leaf is a single diagonal tile
-    return run_cand_stage(v, cs, K, out_idx, out_dist, s);
+    return cs;
+}
+
+rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s) {
+    const ForestView v = view(f);
+    return run_cand_stage(v, all_points_stage(v, K, exclude_self), K, out_idx, out_dist, s);
+}
+
+// All-points search with a workspace that lives as long as the plan: the launches can be
+// recorded once and replayed.
+struct KnnAllPlan {
+    int K = 0, excl = 0;
+    std::vector<void *> blocks;
+    CandWs w;
+};
+
+KnnAllPlan *knn_all_plan_create(const rpf_forest *f, int K, int exclude_self, hipStream_t s) {
+    const ForestView v = view(f);
+    KnnAllPlan *p = new KnnAllPlan();
+    p->K = K;
+    p->excl = exclude_self;
+    const CandStage cs = all_points_stage(v, K, exclude_self);
+    const bool ok = cand_ws_alloc(v, cs, [&](size_t b) {
+        void *q = cache_alloc(b ? b : 16, s);
+        if (q) p->blocks.push_back(q);
+        return q;
+    }, p->w);
+    if (!ok) {
+        knn_all_plan_destroy(p, s);
+        return nullptr;
+    }
+    return p;
+}
+
+void knn_all_plan_launch(const KnnAllPlan *p, const rpf_forest *f, int32_t *out_idx, float *out_dist, hipStream_t s) {
+    const ForestView v = view(f);
+    cand_launches(v, all_points_stage(v, p->K, p->excl), p->K, p->w, out_idx, out_dist, s);
+}
+
+void knn_all_plan_destroy(KnnAllPlan *p, hipStream_t s) {
+    if (!p) return;
+    for (void *q : p->blocks) cache_free(q, s);
+    delete p;
 }
 
 rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s) {
@@ -1674,7 +1754,7 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     {   // queries must be finite (one synchronisation)
         int32_t *flag = static_cast<int32_t *>(cache_alloc(16, s));
         if (!flag) return fail(RPF_ENOMEM, "rpf_query: allocation");
-        hipMemsetAsync(flag, 0, 16, s);
+        fill_u32(flag, 4, 0, s);
         launch_nonfinite(s, Q, m * v.d, flag);
         int32_t h = 0;
         hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
@@ -1710,9 +1790,9 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     if (!ws.ok) return fail(RPF_ENOMEM, "rpf_query: workspace allocation failed");
     rpf_status st = route(f, Q, m, qleaf, s);
     if (st != RPF_OK) return st;
-    hipMemsetAsync(gcount, 0, (size_t)T * nleaf * 4, s);
-    hipMemsetAsync(gfill, 0, (size_t)T * nleaf * 4, s);
-    hipMemsetAsync(njobs, 0, 16, s);
+    fill_u32(gcount, (int64_t)T * nleaf, 0, s);
+    fill_u32(gfill, (int64_t)T * nleaf, 0, s);
+    fill_u32(njobs, 4, 0, s);
     const unsigned qb = (unsigned)std::min<int64_t>((m + 255) / 256, 1024);
     hipLaunchKernelGGL(k_group_count, dim3(qb, T), dim3(256), 0, s, qleaf, m, v.heap_leaf, nleaf, gcount);
     hipLaunchKernelGGL(k_group_scan, dim3(T), dim3(1024), 0, s, gcount, nleaf, goff);

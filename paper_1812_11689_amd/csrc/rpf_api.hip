@@ -39,6 +39,11 @@ void launch_localize(int32_t *idx, int64_t rows, int K, const int64_t *off, int 
 
 static thread_local std::string g_err;
 
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 rpf_status fail(rpf_status st, const std::string &msg) {
     g_err = msg;
     return st;
@@ -58,7 +63,7 @@ void launch_check(hipStream_t s, const char *name) {
         return e && e[0] == '1';
     }();
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && sync && !capturing(s)) e = hipStreamSynchronize(s);
     if (e != hipSuccess && g_launch_err.empty()) g_launch_err = std::string(name) + ": " + hipGetErrorString(e);
 }
 
@@ -99,7 +104,7 @@ static hipEvent_t get_event() {
 void prof_begin(hipStream_t s, const char *name, double bytes, double flops, void **tok) {
     *tok = nullptr;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || capturing(s)) return;  // a recorded graph carries no timing events
     Pending *p = new Pending{name, get_event(), get_event(), bytes, flops};
     hipEventRecord(p->a, s);
     *tok = p;
@@ -152,6 +157,17 @@ using namespace rpf;
 
 // ---------------------------------------------------------------- the forest
 
+namespace rpf {
+struct LevelPlan {
+    std::vector<SegDesc> segs;     // internal nodes
+    std::vector<ChunkDesc> chunks; // multi-block path
+    std::vector<LeafDesc> copy;    // leaves formed at or before this level (carried over)
+    int max_m = 0;
+    bool large = false;
+    int64_t seg_off = 0, chunk_off = 0, copy_off = 0;  // offsets into the device descriptor arrays
+};
+}  // namespace rpf
+
 struct rpf_forest {
     int64_t n = 0;
     int32_t d = 0, T = 0, n0 = 0, n_try = 0, L = 0, prec = 0, dp = 0;
@@ -183,6 +199,11 @@ struct rpf_forest {
     std::vector<LeafDesc> leaves;
     int max_leaf = 0;
     uint64_t bytes = 0;
+    // the closed-form plan of the build, kept so the build launches can be replayed
+    std::vector<rpf::LevelPlan> levels;
+    rpf::LargeBufs lb{};         // temporaries of the multi-block levels
+    std::vector<void *> tmps;    // their blocks (released after a one-shot build)
+    int lds_max = 0;
     // batched forests: one root per data set (a single data set is the one-root case)
     std::vector<rpf_batch_entry> batch;
     int64_t *d_batch_off = nullptr;       // [count + 1] first point of every data set, then n
@@ -193,14 +214,7 @@ struct rpf_forest {
 
 namespace rpf {
 
-struct LevelPlan {
-    std::vector<SegDesc> segs;     // internal nodes
-    std::vector<ChunkDesc> chunks; // multi-block path
-    std::vector<LeafDesc> copy;    // leaves formed at or before this level (carried over)
-    int max_m = 0;
-    bool large = false;
-    int64_t seg_off = 0, chunk_off = 0, copy_off = 0;  // offsets into the device descriptor arrays
-};
+
 
 static int depth_of(int64_t n, int64_t n0) {
     int L = 0;
@@ -265,6 +279,8 @@ static void free_forest_memory(rpf_forest *f) {
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
                     f->d_copy, f->d_jobs, f->stats, f->d_batch_off};
     for (void *p : ptrs) cache_free(p, nullptr);
+    for (void *p : f->tmps) cache_free(p, nullptr);
+    f->tmps.clear();
 }
 
 rpf_status rpf_free(rpf_forest *f) {
@@ -283,11 +299,10 @@ rpf_status rpf_free(rpf_forest *f) {
 // with hbase_i = sum over j < i of (2^L_j - 1): the direction and split arrays are
 // [T][sum H_i] and the kernels index them as for one tree.  Leaf h of data set i has the id
 // lbase_i + h, lbase_i = sum over j < i of 2^(L_j + 1), in leaf_of and in the leaf table.
-static rpf_status build_impl(const float *X, const int64_t *sizes, int count, int32_t d, const rpf_params *p,
-                             void *stream, rpf_forest **out) {
+static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, const rpf_params *p, void *stream,
+                                 rpf_forest **out, bool need_directions = true) {
     if (out) *out = nullptr;
     if (!out) return fail(RPF_EINVAL, "rpf_build: out is NULL");
-    if (!X) return fail(RPF_EINVAL, "rpf_build: X is NULL");
     if (!p) return fail(RPF_EINVAL, "rpf_build: params is NULL");
     if (!sizes || count < 1) return fail(RPF_EINVAL, "rpf_build: no data set");
     int64_t n = 0;
@@ -322,7 +337,7 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
         L = std::max(L, (int)r.depth);
     }
     if (H >= ((int64_t)1 << 31) || LB >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: too many tree nodes");
-    if (H > 0 && !p->directions_dev) return fail(RPF_EINVAL, "rpf_build: directions_dev is NULL");
+    if (need_directions && H > 0 && !p->directions_dev) return fail(RPF_EINVAL, "rpf_build: directions_dev is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int T = p->n_trees, n0 = p->leaf_size, n_try = p->n_try;
 
@@ -478,38 +493,17 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
     hipMemcpyAsync(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
     if (H) hipMemcpyAsync(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice, s);
-    hipMemsetAsync(f->split_idx, 0xff, (size_t)T * H * 4, s);
-    hipMemsetAsync(f->chosen, 0xff, (size_t)T * H * 4, s);
+    fill_u32(f->split_idx, (int64_t)T * H, 0xffffffffu, s);
+    fill_u32(f->chosen, (int64_t)T * H, 0xffffffffu, s);
     launch_check(s, "descriptor upload");
 
-    // ---- inputs: copy, then reject non-finite values (one synchronisation)
-    rpf_status st;
-    if ((st = check_hip(hipMemcpyAsync(f->X, X, (size_t)n * d * 4, hipMemcpyDeviceToDevice, s), "copy X")) != RPF_OK)
-        return bail(st);
-    if (H > 0 &&
-        (st = check_hip(hipMemcpyAsync(f->R, p->directions_dev, (size_t)T * H * n_try * d * 4, hipMemcpyDeviceToDevice, s),
-                        "copy directions")) != RPF_OK)
-        return bail(st);
-    hipMemsetAsync(f->err, 0, 64, s);
-    hipMemsetAsync(f->stats, 0, kStatSlots * 8 * 8, s);
-    launch_nonfinite(s, f->X, n * d, f->err);
-    launch_nonfinite(s, f->R, T * H * n_try * d, f->err + 1);
-    launch_check(s, "nonfinite check");
-    int32_t flags[2] = {0, 0};
-    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 8, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
-    if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);
-    if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
-    if (flags[1]) { fail(RPF_EINVAL, "rpf_build: directions hold NaN or Inf"); return bail(RPF_EINVAL); }
-    hipMemsetAsync(f->err, 0, 64, s);
-
-    // ---- temporaries of the multi-block path
-    LargeBufs lb{};
-    std::vector<void *> tmps;
+    // ---- temporaries of the multi-block path (kept by the forest until released)
+    LargeBufs &lb = f->lb;
     auto talloc = [&](void **ptr, size_t sz) -> bool {
         if (!sz) { *ptr = nullptr; return true; }
         *ptr = cache_alloc(sz, s);
         if (!*ptr) return false;
-        tmps.push_back(*ptr);
+        f->tmps.push_back(*ptr);
         return true;
     };
     bool ok = true;
@@ -524,54 +518,11 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
         ok &= talloc((void **)&lb.part, (size_t)T * max_chunk_large * 8);
     }
     if (!ok) {
-        for (void *q : tmps) cache_free(q, s);
         fail(RPF_ENOMEM, "rpf_build: temporary allocation failed");
         return bail(RPF_ENOMEM);
     }
-
-    // ---- levels
-    const bool vec = (d % 4) == 0;
-    launch_iota(s, f->perm[0], n, T);
-    launch_check(s, "iota");
-    int cur = 0;
-    for (int l = 0; l < L; l++) {
-        LevelPlan &lv = levels[l];
-        const int32_t *pin = f->perm[cur];
-        int32_t *pout = f->perm[cur ^ 1];
-        launch_copy_segments(s, f->d_copy + lv.copy_off, (int)lv.copy.size(), T, pin, pout, n);
-        launch_check(s, "copy_segments");
-        int64_t members = 0;
-        for (auto &sg : lv.segs) members += sg.size;
-        const double proj_bytes = (double)T * members * (4.0 * d + 4 + 8);
-        if (!lv.large) {
-            ProfScope ps(s, "level_small", (double)T * members * (4.0 * d + 8), 0);
-            launch_level_small(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
-                               lv.max_m, T, pin, pout, n, f->split, f->split_idx, f->chosen, f->err);
-            launch_check(s, "level_small");
-        } else {
-            launch_level_large(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
-                               f->d_chunks + lv.chunk_off, (int)lv.chunks.size(), T, pin, pout, n, f->split,
-                               f->split_idx, f->chosen, f->err, lb, proj_bytes);
-            launch_check(s, "level_large");
-        }
-        cur ^= 1;
-    }
-    f->final_buf = cur;
-    {
-        ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * (double)esz + 16), 0);
-        launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of,
-                             f->centroid, f->Xc, f->nrm, max_leaf, lds_max);
-        launch_check(s, "leaf_finalize");
-    }
-    for (void *q : tmps) cache_free(q, s);
-    launch_check(s, "rpf_build tail");
-    {
-        const std::string le = take_launch_error();
-        if (!le.empty()) {
-            fail(RPF_EDEVICE, "rpf_build: " + le);
-            return bail(RPF_EDEVICE);
-        }
-    }
+    f->levels = levels;
+    f->lds_max = lds_max;
 
     // all-points tile jobs (same leaf shapes in every tree)
     {
@@ -611,6 +562,98 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
     return RPF_OK;
 }
 
+// The build proper: launches only (no allocation, no synchronisation, no memset), so a
+// stream capture can record it.  X and the directions must be in place.
+static void build_launches(rpf_forest *f, hipStream_t s) {
+    const int64_t n = f->n, H = f->H;
+    const int d = f->d, T = f->T, n_try = f->n_try, dp = f->dp, prec = f->prec;
+    const double esz = prec == RPF_DIST_FP32 ? 4.0 : 2.0;
+    const int64_t nleaf = (int64_t)f->leaves.size();
+    const bool vec = (d % 4) == 0;
+    launch_iota(s, f->perm[0], n, T);
+    launch_check(s, "iota");
+    int cur = 0;
+    for (size_t l = 0; l < f->levels.size(); l++) {
+        LevelPlan &lv = f->levels[l];
+        const int32_t *pin = f->perm[cur];
+        int32_t *pout = f->perm[cur ^ 1];
+        launch_copy_segments(s, f->d_copy + lv.copy_off, (int)lv.copy.size(), T, pin, pout, n);
+        launch_check(s, "copy_segments");
+        int64_t members = 0;
+        for (auto &sg : lv.segs) members += sg.size;
+        const double proj_bytes = (double)T * members * (4.0 * d + 4 + 8);
+        if (!lv.large) {
+            ProfScope ps(s, "level_small", (double)T * members * (4.0 * d + 8), 0);
+            launch_level_small(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
+                               lv.max_m, T, pin, pout, n, f->split, f->split_idx, f->chosen, f->err);
+            launch_check(s, "level_small");
+        } else {
+            launch_level_large(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
+                               f->d_chunks + lv.chunk_off, (int)lv.chunks.size(), T, pin, pout, n, f->split,
+                               f->split_idx, f->chosen, f->err, f->lb, proj_bytes);
+            launch_check(s, "level_large");
+        }
+        cur ^= 1;
+    }
+    f->final_buf = cur;
+    ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * esz + 16), 0);
+    launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of, f->centroid,
+                         f->Xc, f->nrm, f->max_leaf, f->lds_max);
+    launch_check(s, "leaf_finalize");
+}
+
+static void release_temporaries(rpf_forest *f, hipStream_t s) {
+    for (void *q : f->tmps) cache_free(q, s);
+    f->tmps.clear();
+    f->lb = LargeBufs{};
+}
+
+static rpf_status build_impl(const float *X, const int64_t *sizes, int count, int32_t d, const rpf_params *p,
+                             void *stream, rpf_forest **out) {
+    if (out) *out = nullptr;
+    if (!X) return fail(RPF_EINVAL, "rpf_build: X is NULL");
+    rpf_forest *f = nullptr;
+    rpf_status st = prepare_forest(sizes, count, d, p, stream, &f);
+    if (st != RPF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    auto bail = [&](rpf_status e) {
+        hipStreamSynchronize(s);
+        free_forest_memory(f);
+        delete f;
+        return e;
+    };
+    const int64_t n = f->n, H = f->H;
+    const int T = f->T, n_try = f->n_try;
+    // ---- inputs: copy, then reject non-finite values (one synchronisation)
+    if ((st = check_hip(hipMemcpyAsync(f->X, X, (size_t)n * d * 4, hipMemcpyDeviceToDevice, s), "copy X")) != RPF_OK)
+        return bail(st);
+    if (H > 0 &&
+        (st = check_hip(hipMemcpyAsync(f->R, p->directions_dev, (size_t)T * H * n_try * d * 4, hipMemcpyDeviceToDevice, s),
+                        "copy directions")) != RPF_OK)
+        return bail(st);
+    fill_u32(f->err, 16, 0, s);
+    fill_u32(f->stats, kStatSlots * 8 * 2, 0, s);
+    launch_nonfinite(s, f->X, n * d, f->err);
+    launch_nonfinite(s, f->R, T * H * n_try * d, f->err + 1);
+    launch_check(s, "nonfinite check");
+    int32_t flags[2] = {0, 0};
+    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 8, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
+    if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);
+    if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
+    if (flags[1]) { fail(RPF_EINVAL, "rpf_build: directions hold NaN or Inf"); return bail(RPF_EINVAL); }
+    fill_u32(f->err, 16, 0, s);
+    build_launches(f, s);
+    release_temporaries(f, s);
+    launch_check(s, "rpf_build tail");
+    const std::string le = take_launch_error();
+    if (!le.empty()) {
+        fail(RPF_EDEVICE, "rpf_build: " + le);
+        return bail(RPF_EDEVICE);
+    }
+    *out = f;
+    return RPF_OK;
+}
+
 extern "C" {
 
 rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream, rpf_forest **out) {
@@ -622,6 +665,132 @@ rpf_status rpf_build_batched(const float *X, const int64_t *n_host, int32_t coun
     if (out) *out = nullptr;
     if (!n_host || count < 1) return fail(RPF_EINVAL, "rpf_build_batched: need count >= 1 sizes");
     return build_impl(X, n_host, count, d, p, stream, out);
+}
+
+}  // extern "C"
+
+// A build and all-points search of fixed shapes recorded once as a HIP graph: one graph
+// launch runs the input checks, every level of every data set's trees, the leaf pass, the
+// candidate stage and the index localisation, with every buffer owned by the plan.
+struct rpf_plan {
+    rpf_forest *f = nullptr;
+    KnnAllPlan *knn = nullptr;
+    int32_t *out_idx = nullptr;
+    float *out_dist = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int K = 0;
+};
+
+static void plan_free(rpf_plan *pl) {
+    if (!pl) return;
+    hipDeviceSynchronize();
+    if (pl->exec) hipGraphExecDestroy(pl->exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    if (pl->cap) hipStreamDestroy(pl->cap);
+    knn_all_plan_destroy(pl->knn, nullptr);
+    cache_free(pl->out_idx, nullptr);
+    cache_free(pl->out_dist, nullptr);
+    if (pl->f) {
+        free_forest_memory(pl->f);
+        delete pl->f;
+    }
+    delete pl;
+}
+
+extern "C" {
+
+rpf_status rpf_plan_create(const int64_t *n_host, int32_t count, int32_t d, const rpf_params *p, int32_t K,
+                           int32_t exclude_self, void *stream, rpf_plan **out) {
+    if (out) *out = nullptr;
+    if (!out || !n_host || count < 1) return fail(RPF_EINVAL, "rpf_plan_create: NULL pointer or count < 1");
+    if (exclude_self != 0 && exclude_self != 1) return fail(RPF_EINVAL, "rpf_plan_create: exclude_self must be 0 or 1");
+    if (K < 1 || K > 256) return fail(RPF_EINVAL, "rpf_plan_create: K must be in [1, 256]");
+    hipStream_t s = (hipStream_t)stream;
+    rpf_plan *pl = new rpf_plan();
+    pl->K = K;
+    rpf_status st = prepare_forest(n_host, count, d, p, stream, &pl->f, false);
+    if (st != RPF_OK) {
+        delete pl;
+        return st;
+    }
+    rpf_forest *f = pl->f;
+    if (K > f->n - exclude_self) {
+        plan_free(pl);
+        return fail(RPF_EINVAL, "rpf_plan_create: K must be <= n - exclude_self");
+    }
+    pl->knn = knn_all_plan_create(f, K, exclude_self, s);
+    pl->out_idx = static_cast<int32_t *>(cache_alloc((size_t)f->n * K * 4, s));
+    pl->out_dist = static_cast<float *>(cache_alloc((size_t)f->n * K * 4, s));
+    if (!pl->knn || !pl->out_idx || !pl->out_dist) {
+        plan_free(pl);
+        return fail(RPF_ENOMEM, "rpf_plan_create: device allocation failed");
+    }
+    if ((st = check_hip(hipStreamSynchronize(s), "rpf_plan_create")) != RPF_OK ||
+        (st = check_hip(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "rpf_plan_create stream")) != RPF_OK) {
+        plan_free(pl);
+        return st;
+    }
+    take_launch_error();
+    hipStream_t c = pl->cap;
+    if ((st = check_hip(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal), "begin capture")) != RPF_OK) {
+        plan_free(pl);
+        return st;
+    }
+    fill_u32(f->err, 16, 0, c);
+    launch_nonfinite(c, f->X, f->n * f->d, f->err + 2);
+    launch_nonfinite(c, f->R, (int64_t)f->T * f->H * f->n_try * f->d, f->err + 3);
+    build_launches(f, c);
+    knn_all_plan_launch(pl->knn, f, pl->out_idx, pl->out_dist, c);
+    if (count > 1) launch_localize(pl->out_idx, f->n, K, f->d_batch_off, count, c);
+    const hipError_t ec = hipStreamEndCapture(c, &pl->graph);
+    const std::string le = take_launch_error();
+    if (ec != hipSuccess || !le.empty() || !pl->graph) {
+        fail(RPF_EDEVICE, "rpf_plan_create: recording failed: " + (le.empty() ? std::string(hipGetErrorString(ec)) : le));
+        plan_free(pl);
+        return RPF_EDEVICE;
+    }
+    if ((st = check_hip(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0), "graph instantiate")) != RPF_OK) {
+        plan_free(pl);
+        return st;
+    }
+    *out = pl;
+    return RPF_OK;
+}
+
+rpf_status rpf_plan_buffers(rpf_plan *pl, float **X_dev, float **directions_dev, int32_t **out_idx_dev,
+                            float **out_dist_dev) {
+    if (!pl) return fail(RPF_EINVAL, "rpf_plan_buffers: NULL plan");
+    if (X_dev) *X_dev = pl->f->X;
+    if (directions_dev) *directions_dev = pl->f->R;
+    if (out_idx_dev) *out_idx_dev = pl->out_idx;
+    if (out_dist_dev) *out_dist_dev = pl->out_dist;
+    return RPF_OK;
+}
+
+rpf_status rpf_plan_launch(rpf_plan *pl, void *stream) {
+    if (!pl) return fail(RPF_EINVAL, "rpf_plan_launch: NULL plan");
+    return check_hip(hipGraphLaunch(pl->exec, (hipStream_t)stream), "rpf_plan_launch");
+}
+
+rpf_status rpf_plan_check(rpf_plan *pl, void *stream) {
+    if (!pl) return fail(RPF_EINVAL, "rpf_plan_check: NULL plan");
+    int32_t flags[4] = {0, 0, 0, 0};
+    hipMemcpyAsync(flags, pl->f->err, 16, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    const rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_plan_check");
+    if (st != RPF_OK) return st;
+    if (flags[2]) return fail(RPF_EINVAL, "rpf_plan_check: X holds NaN or Inf");
+    if (flags[3]) return fail(RPF_EINVAL, "rpf_plan_check: directions hold NaN or Inf");
+    if (flags[0]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[0]));
+    return RPF_OK;
+}
+
+const rpf_forest *rpf_plan_forest(const rpf_plan *pl) { return pl ? pl->f : nullptr; }
+
+rpf_status rpf_plan_destroy(rpf_plan *pl) {
+    plan_free(pl);
+    return RPF_OK;
 }
 
 rpf_status rpf_batch_info(const rpf_forest *f, int32_t i, rpf_batch_entry *out) {

@@ -126,9 +126,15 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
                      hipStream_t s);
 rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s);
 uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K);
+struct KnnAllPlan;  // all-points search with a persistent workspace (recordable launches)
+KnnAllPlan *knn_all_plan_create(const rpf_forest *f, int K, int exclude_self, hipStream_t s);
+void knn_all_plan_launch(const KnnAllPlan *p, const rpf_forest *f, int32_t *out_idx, float *out_dist, hipStream_t s);
+void knn_all_plan_destroy(KnnAllPlan *p, hipStream_t s);
+void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);
 int32_t forest_dim(const rpf_forest *f);
 
+bool capturing(hipStream_t s);  // a stream capture (graph recording) is active on s
 rpf_status fail(rpf_status st, const std::string &msg);
 rpf_status check_hip(hipError_t e, const char *what);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);

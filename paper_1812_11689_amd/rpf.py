@@ -24,7 +24,8 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_last_error"]
+           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_buffers",
+           "rpf_plan_launch", "rpf_plan_check", "rpf_plan_forest", "rpf_plan_destroy", "rpf_last_error"]
 
 
 class RpfError(RuntimeError):
@@ -131,6 +132,19 @@ def load(path: str = LIB_PATH):
     lib.rpf_build_batched.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     lib.rpf_batch_info.restype = i32
     lib.rpf_batch_info.argtypes = [vp, i32, ctypes.POINTER(BatchEntry)]
+    lib.rpf_plan_create.restype = i32
+    lib.rpf_plan_create.argtypes = [ctypes.POINTER(i64), i32, i32, ctypes.POINTER(Params), i32, i32, vp,
+                                    ctypes.POINTER(vp)]
+    lib.rpf_plan_buffers.restype = i32
+    lib.rpf_plan_buffers.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.rpf_plan_launch.restype = i32
+    lib.rpf_plan_launch.argtypes = [vp, vp]
+    lib.rpf_plan_check.restype = i32
+    lib.rpf_plan_check.argtypes = [vp, vp]
+    lib.rpf_plan_forest.restype = vp
+    lib.rpf_plan_forest.argtypes = [vp]
+    lib.rpf_plan_destroy.restype = i32
+    lib.rpf_plan_destroy.argtypes = [vp]
     lib.rpf_release_cached_memory.restype = i32
     lib.rpf_release_cached_memory.argtypes = [i32]
     lib.rpf_last_error.restype = ctypes.c_char_p
@@ -313,6 +327,75 @@ def build_batched(Xs, n_trees: int, leaf_size: int, directions: torch.Tensor | N
     f.count = len(sizes)
     f.sizes = sizes
     return f
+
+
+class _DeviceArray:
+    """A device buffer of the library seen by torch without a copy (CUDA array interface)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 3, "strides": None}
+
+
+def _view(ptr: int, shape, dtype) -> torch.Tensor:
+    typestr = {torch.float32: "<f4", torch.int32: "<i4"}[dtype]
+    return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device="cuda")
+
+
+class Plan:
+    """Build + all-points search of fixed shapes recorded as one HIP graph (rpf_plan_*).
+    Write `X` and `directions` (plan-owned device tensors), call launch(), read `idx`/`dist`."""
+
+    def __init__(self, sizes, d: int, n_trees: int, leaf_size: int, K: int, exclude_self: bool = True,
+                 n_try: int = 1, dist_prec: str = "fp32", stream=None):
+        self.sizes = [int(n) for n in sizes]
+        self.d, self.n_trees, self.leaf_size, self.n_try, self.K = d, n_trees, leaf_size, n_try, K
+        p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
+                   dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+                   directions_dev=None, mem_budget_bytes=0)
+        ns = (ctypes.c_int64 * len(self.sizes))(*self.sizes)
+        h = ctypes.c_void_p()
+        _check(load().rpf_plan_create(ns, len(self.sizes), d, ctypes.byref(p), K, int(exclude_self),
+                                      _stream(stream), ctypes.byref(h)))
+        self._h = h
+        xp, rp, ip, dp_ = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load().rpf_plan_buffers(h, ctypes.byref(xp), ctypes.byref(rp), ctypes.byref(ip), ctypes.byref(dp_)))
+        n = sum(self.sizes)
+        H = sum((1 << depth(m, leaf_size)) - 1 for m in self.sizes)
+        self.X = _view(xp.value, (n, d), torch.float32)
+        self.directions = _view(rp.value, (n_trees, H, n_try, d), torch.float32) if H else None
+        self.idx = _view(ip.value, (n, K), torch.int32)
+        self.dist = _view(dp_.value, (n, K), torch.float32)
+        fp = load().rpf_plan_forest(h)
+        self.forest = (BatchedForest if len(self.sizes) > 1 else Forest)(
+            ctypes.c_void_p(fp), n, d, n_trees, leaf_size, n_try, max(depth(m, leaf_size) for m in self.sizes))
+        self.forest.count, self.forest.sizes = len(self.sizes), self.sizes
+        self.forest.free = lambda: None  # owned by the plan
+
+    def launch(self, stream=None):
+        _check(load().rpf_plan_launch(self._h, _stream(stream)))
+
+    def check(self, stream=None):
+        _check(load().rpf_plan_check(self._h, _stream(stream)))
+
+    def split(self):
+        """(idx, dist) per data set, views of the plan's outputs."""
+        out, o = [], 0
+        for m in self.sizes:
+            out.append((self.idx[o:o + m], self.dist[o:o + m]))
+            o += m
+        return out
+
+    def close(self):
+        if self._h is not None:
+            _check(load().rpf_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

@@ -90,3 +90,23 @@ def test_server_and_workspace_arguments_rejected_without_device():
     assert lib.rpf_server_destroy(None) == rpf.RPF_OK
     b = ctypes.c_uint64(0)
     assert lib.rpf_query_workspace_bytes(None, 10, 5, ctypes.byref(b)) == rpf.RPF_EINVAL
+
+
+def test_plan_arguments_rejected_without_device():
+    lib = rpf.load()
+    p = rpf.Params(n_trees=2, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, reserved=0,
+                   directions_dev=None, mem_budget_bytes=0)
+    h = ctypes.c_void_p(1234)
+    ns = (ctypes.c_int64 * 2)(100, 200)
+    assert lib.rpf_plan_create(None, 2, 4, ctypes.byref(p), 5, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert h.value is None
+    assert lib.rpf_plan_create(ns, 0, 4, ctypes.byref(p), 5, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, 2, 4, ctypes.byref(p), 0, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, 2, 4, ctypes.byref(p), 5, 2, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_launch(None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_check(None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_buffers(None, None, None, None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_forest(None) is None
+    assert lib.rpf_plan_destroy(None) == rpf.RPF_OK
+    assert lib.rpf_build_batched(ctypes.c_void_p(0x1000), None, 2, 4, ctypes.byref(p), None,
+                                 ctypes.byref(h)) == rpf.RPF_EINVAL
