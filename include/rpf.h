@@ -109,30 +109,59 @@ rpf_status rpf_build_batched(const float *X_dev, const int64_t *n_host, int32_t 
                              const rpf_params *params, void *stream, rpf_forest **out);
 rpf_status rpf_batch_info(const rpf_forest *f, int32_t index, rpf_batch_entry *out_host);
 
-/* ---- A build and all-points search of fixed shapes, recorded once and replayed.
+/* ---- Build and all-points search of many data sets, recorded once and replayed.
  *
- * rpf_plan_create plans a forest over `count` data sets of sizes n_host (as
- * rpf_build_batched; count = 1 is one data set) and allocates every buffer: the inputs X
- * [sum n_i][d] and directions [n_trees][sum H_i][n_try][d], and the outputs [sum n_i][K]
- * (indices within each data set).  It records, as one HIP graph, the input checks, every
- * level of every tree, the leaf pass, the candidate stage and the index localisation (no
+ * rpf_plan_create plans `count` data sets (sizes n_host, dimensions d_host; same n_trees,
+ * leaf_size, n_try, dist_prec, K): they are grouped by dimension and each group is cut into
+ * parts of at most max_part_points points (<= 0: 4 Mi; a data set is never split).  Every
+ * part is one forest over its data sets, as rpf_build_batched grows it.  The plan allocates
+ * every buffer -- per part the inputs X [rows][d] and directions [n_trees][n_nodes][n_try][d]
+ * and the outputs [rows][K] (indices within each data set) -- and records, as one HIP graph,
+ * part after part: the input checks, every level of every tree, the leaf pass, the
+ * candidate stage (one workspace shared by all parts) and the index localisation (no
  * allocation, synchronisation or memset inside).  params->directions_dev is not used.
- * rpf_plan_buffers returns the device buffers: write X and the directions, then
- * rpf_plan_launch runs the whole graph on `stream` (asynchronous); rpf_plan_check
- * synchronises the stream and reports non-finite inputs (RPF_EINVAL) or an internal error.
- * Every launch rebuilds the forest from the current buffer contents; rpf_plan_forest gives
- * the forest of the last launch for introspection (rpf_tree_dump, rpf_forest_info); it must
- * not be freed, and rpf_all_knn / rpf_query on it are allowed between launches.  Launches of
- * one plan must not overlap. */
+ *   rpf_plan_entry_of: where data set i lives (part, first row, first node of its trees);
+ *   rpf_plan_part: the device buffers of part k, and its forest for introspection (owned by
+ *     the plan; it reflects the last launch);
+ *   rpf_plan_launch: runs the whole graph on `stream` (asynchronous; launches of one plan
+ *     must not overlap); every launch rebuilds from the current buffer contents;
+ *   rpf_plan_check: synchronises `stream`, reports non-finite inputs (RPF_EINVAL) or an
+ *     internal error of the build kernels;
+ *   rpf_plan_tune: launches once, then times the candidate stage of every part for several
+ *     first-phase tree counts (the trees whose leaves are kept whole and set the pruning
+ *     threshold), keeps the fastest per part and records the graph again; the results do
+ *     not depend on the choice. */
 typedef struct rpf_plan rpf_plan;
 
-rpf_status rpf_plan_create(const int64_t *n_host, int32_t count, int32_t d, const rpf_params *params,
-                           int32_t K, int32_t exclude_self, void *stream, rpf_plan **out);
-rpf_status rpf_plan_buffers(rpf_plan *plan, float **X_dev, float **directions_dev, int32_t **out_idx_dev,
-                            float **out_dist_dev);
+typedef struct {
+    int32_t part, index_in_part, d, reserved;
+    int64_t n;
+    int64_t row;         /* first row of the data set in its part's X and outputs            */
+    int64_t heap_base;   /* its internal node h is node heap_base + h of the part's trees    */
+    int64_t n_nodes;     /* 2^L - 1 internal-node slots of each of its trees                 */
+} rpf_plan_entry;
+
+typedef struct {
+    int64_t rows;
+    int32_t d, n_sets;
+    int64_t n_nodes;                 /* sum of n_nodes over the part's data sets             */
+    float *X_dev;                    /* [rows][d]                                            */
+    float *directions_dev;           /* [n_trees][n_nodes][n_try][d]                         */
+    int32_t *out_idx_dev;            /* [rows][K]                                            */
+    float *out_dist_dev;             /* [rows][K]                                            */
+    const rpf_forest *forest;        /* not to be freed                                      */
+    int32_t first_trees, reserved;
+} rpf_plan_part_info;
+
+rpf_status rpf_plan_create(const int64_t *n_host, const int32_t *d_host, int32_t count, const rpf_params *params,
+                           int32_t K, int32_t exclude_self, int64_t max_part_points, void *stream,
+                           rpf_plan **out);
+rpf_status rpf_plan_info(const rpf_plan *plan, int32_t *n_parts_host, int32_t *count_host);
+rpf_status rpf_plan_part(const rpf_plan *plan, int32_t part, rpf_plan_part_info *out_host);
+rpf_status rpf_plan_entry_of(const rpf_plan *plan, int32_t index, rpf_plan_entry *out_host);
 rpf_status rpf_plan_launch(rpf_plan *plan, void *stream);
 rpf_status rpf_plan_check(rpf_plan *plan, void *stream);
-const rpf_forest *rpf_plan_forest(const rpf_plan *plan);
+rpf_status rpf_plan_tune(rpf_plan *plan, void *stream, double *tuned_ms_host);
 rpf_status rpf_plan_destroy(rpf_plan *plan);
 
 /* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].

@@ -1522,14 +1522,21 @@ struct CandWs {
     Ent *list = nullptr;
 };
 
+// Per-row capacities of the merged list and of the Phase II records, from K and the number
+// of Phase II trees (about K (T - B) / 2 records per row were measured on mixtures; twice that
+// plus a margin keeps overflow, which sends a row to the exhaustive path, rare).
+static void cand_caps(int K, int T, int B, int &lcap, int &cap2) {
+    lcap = std::min(kListCap, std::max(64, 8 * K));
+    cap2 = std::min(kFinalCap - lcap, std::max(128, K * std::max(T - B, 0) + 64));
+}
+
 // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
 // threshold of the union of those leaves.  `get` hands out device bytes (nullptr = failure).
 template <typename Get>
-static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, Get get, CandWs &w) {
+static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
-    w.lcap = kListCap;
+    cand_caps(K, v.T, cs.B, w.lcap, w.cap2);
     w.cap1 = v.max_leaf * cs.B;      // Phase I slots per row (index / lb / ub arrays)
-    w.cap2 = kFinalCap - w.lcap;     // Phase II records per row
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
     const size_t first_bytes = (size_t)rows * w.cap1 * 12;
     const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
@@ -1655,7 +1662,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
                                  float *out_dist, hipStream_t s) {
     Workspace ws(s);
     CandWs w;
-    if (!cand_ws_alloc(v, cs, [&](size_t b) { return ws.get<void>(b); }, w) || !ws.ok)
+    if (!cand_ws_alloc(v, cs, K, [&](size_t b) { return ws.get<void>(b); }, w) || !ws.ok)
         return fail(RPF_ENOMEM, "kNN workspace allocation failed");
     cand_launches(v, cs, K, w, out_idx, out_dist, s);
     const std::string le = take_launch_error();
@@ -1663,10 +1670,15 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
     return RPF_OK;
 }
 
-static CandStage all_points_stage(const ForestView &v, int K, int exclude_self) {
+// largest first-phase tree count the merge supports for this forest and K
+static int max_first_trees(const ForestView &v, int K) {
+    return std::max(1, std::min({v.T, (kSetCap - 64) / K, kMergeCap / std::max(v.max_leaf, 1)}));
+}
+
+static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, int B = 0) {
     CandStage cs;
     cs.rows = v.n;
-    cs.B = first_trees(v.T, K, v.max_leaf);
+    cs.B = B > 0 ? std::min(B, max_first_trees(v, K)) : first_trees(v.T, K, v.max_leaf);
     cs.jobs0 = v.jobs;
     cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
     cs.njobs0 = v.n_jobs_tree * cs.B;
@@ -1692,38 +1704,71 @@ rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_id
     return run_cand_stage(v, all_points_stage(v, K, exclude_self), K, out_idx, out_dist, s);
 }
 
-// All-points search with a workspace that lives as long as the plan: the launches can be
-// recorded once and replayed.
-struct KnnAllPlan {
+// All-points search of several forests (parts) run one after the other with one workspace,
+// sized for the largest part and the largest first-phase tree count it will be given: the
+// launches can be recorded once and replayed.
+struct KnnShared {
     int K = 0, excl = 0;
     std::vector<void *> blocks;
-    CandWs w;
+    CandWs w;  // base pointers; each part derives its capacities
 };
 
-KnnAllPlan *knn_all_plan_create(const rpf_forest *f, int K, int exclude_self, hipStream_t s) {
-    const ForestView v = view(f);
-    KnnAllPlan *p = new KnnAllPlan();
+KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const std::vector<int> &maxB, int K,
+                             int exclude_self, hipStream_t s) {
+    KnnShared *p = new KnnShared();
     p->K = K;
     p->excl = exclude_self;
-    const CandStage cs = all_points_stage(v, K, exclude_self);
-    const bool ok = cand_ws_alloc(v, cs, [&](size_t b) {
+    size_t b_region = 0, b_rows = 0, b_list = 0;
+    for (size_t i = 0; i < parts.size(); i++) {
+        const ForestView v = view(parts[i]);
+        const CandStage cs = all_points_stage(v, K, exclude_self, maxB[i]);
+        int lcap = 0, cap2 = 0;
+        cand_caps(K, v.T, cs.B, lcap, cap2);
+        // capacities grow with B for cap1 and shrink for cap2: take each over 1..B
+        for (int B = 1; B <= cs.B; B++) {
+            cand_caps(K, v.T, B, lcap, cap2);
+            const size_t cap1 = (size_t)v.max_leaf * B;
+            b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 12, (size_t)v.n * cap2 * sizeof(Ent)) + 256);
+            b_list = std::max(b_list, (size_t)v.n * lcap * sizeof(Ent));
+        }
+        b_rows = std::max(b_rows, (size_t)v.n * 4);
+    }
+    auto get = [&](size_t b) {
         void *q = cache_alloc(b ? b : 16, s);
         if (q) p->blocks.push_back(q);
         return q;
-    }, p->w);
-    if (!ok) {
-        knn_all_plan_destroy(p, s);
+    };
+    CandWs &w = p->w;
+    w.region = static_cast<uint8_t *>(get(b_region));
+    w.tau = static_cast<float *>(get(b_rows));
+    w.cnt = static_cast<int32_t *>(get(b_rows));
+    w.list = static_cast<Ent *>(get(b_list));
+    w.lcnt = static_cast<int32_t *>(get(b_rows));
+    w.fb_list = static_cast<int32_t *>(get(b_rows));
+    w.fb_cnt = static_cast<int32_t *>(get(16));
+    if (!w.region || !w.tau || !w.cnt || !w.list || !w.lcnt || !w.fb_list || !w.fb_cnt) {
+        knn_shared_destroy(p, s);
         return nullptr;
     }
     return p;
 }
 
-void knn_all_plan_launch(const KnnAllPlan *p, const rpf_forest *f, int32_t *out_idx, float *out_dist, hipStream_t s) {
+// first-phase tree count actually used for a part (B = 0: the default rule)
+int knn_part_first_trees(const rpf_forest *f, int K, int B) {
     const ForestView v = view(f);
-    cand_launches(v, all_points_stage(v, p->K, p->excl), p->K, p->w, out_idx, out_dist, s);
+    return all_points_stage(v, K, 0, B).B;
 }
 
-void knn_all_plan_destroy(KnnAllPlan *p, hipStream_t s) {
+void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *out_idx, float *out_dist, hipStream_t s) {
+    const ForestView v = view(f);
+    const CandStage cs = all_points_stage(v, p->K, p->excl, B);
+    CandWs w = p->w;
+    cand_caps(p->K, v.T, cs.B, w.lcap, w.cap2);
+    w.cap1 = v.max_leaf * cs.B;
+    cand_launches(v, cs, p->K, w, out_idx, out_dist, s);
+}
+
+void knn_shared_destroy(KnnShared *p, hipStream_t s) {
     if (!p) return;
     for (void *q : p->blocks) cache_free(q, s);
     delete p;
@@ -1861,9 +1906,11 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     b += (uint64_t)T * nleaf * 4 * 3;              // group counts, offsets, fill
     b += (uint64_t)T * m * v.dp * esz + (uint64_t)T * m * 8;  // centred queries and norms
     b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob) * (qtile_qs(v.prec, v.dp) ? 2 : 1);
-    const uint64_t cap1 = (uint64_t)v.max_leaf * B, cap2 = kFinalCap - kListCap;
-    b += std::max(m * cap1 * 12, m * cap2 * sizeof(Ent)) + 256;
-    b += (uint64_t)m * 4 * 4 + (uint64_t)m * kListCap * sizeof(Ent) + 16 * 3;
+    int lcap = 0, cap2 = 0;
+    cand_caps(K, v.T, B, lcap, cap2);
+    const uint64_t cap1 = (uint64_t)v.max_leaf * B;
+    b += std::max(m * cap1 * 12, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
+    b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
 }
 

@@ -669,19 +669,30 @@ rpf_status rpf_build_batched(const float *X, const int64_t *n_host, int32_t coun
 
 }  // extern "C"
 
-// A build and all-points search of fixed shapes recorded once as a HIP graph: one graph
-// launch runs the input checks, every level of every data set's trees, the leaf pass, the
-// candidate stage and the index localisation, with every buffer owned by the plan.
-struct rpf_plan {
+// A build and all-points search of fixed shapes recorded once as a HIP graph.  The data
+// sets are grouped by dimension and each group is cut into parts of bounded size (data sets
+// are never split); every part is one forest over its data sets.  One graph launch runs,
+// part after part, the input checks, every level of every tree, the leaf pass, the
+// candidate stage (one workspace shared by all parts) and the index localisation.
+struct PlanPart {
     rpf_forest *f = nullptr;
-    KnnAllPlan *knn = nullptr;
+    std::vector<int> sets;     // data set indices, in order
     int32_t *out_idx = nullptr;
     float *out_dist = nullptr;
+    int B = 0;                 // first-phase trees (0: default rule; set by the tuner)
+};
+
+struct rpf_plan {
+    std::vector<PlanPart> parts;
+    std::vector<rpf_plan_entry> entries;
+    KnnShared *knn = nullptr;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int K = 0;
+    int K = 0, excl = 0, count = 0;
 };
+
+constexpr int kTuneB[] = {2, 3, 4, 6, 8};  // first-phase tree counts the tuner tries
 
 static void plan_free(rpf_plan *pl) {
     if (!pl) return;
@@ -689,69 +700,126 @@ static void plan_free(rpf_plan *pl) {
     if (pl->exec) hipGraphExecDestroy(pl->exec);
     if (pl->graph) hipGraphDestroy(pl->graph);
     if (pl->cap) hipStreamDestroy(pl->cap);
-    knn_all_plan_destroy(pl->knn, nullptr);
-    cache_free(pl->out_idx, nullptr);
-    cache_free(pl->out_dist, nullptr);
-    if (pl->f) {
-        free_forest_memory(pl->f);
-        delete pl->f;
+    knn_shared_destroy(pl->knn, nullptr);
+    for (auto &pt : pl->parts) {
+        cache_free(pt.out_idx, nullptr);
+        cache_free(pt.out_dist, nullptr);
+        if (pt.f) {
+            free_forest_memory(pt.f);
+            delete pt.f;
+        }
     }
     delete pl;
 }
 
+static rpf_status plan_record(rpf_plan *pl) {
+    if (pl->exec) hipGraphExecDestroy(pl->exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+    take_launch_error();
+    hipStream_t c = pl->cap;
+    rpf_status st = check_hip(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (st != RPF_OK) return st;
+    for (auto &pt : pl->parts) {
+        rpf_forest *f = pt.f;
+        fill_u32(f->err, 16, 0, c);
+        launch_nonfinite(c, f->X, f->n * f->d, f->err + 2);
+        launch_nonfinite(c, f->R, (int64_t)f->T * f->H * f->n_try * f->d, f->err + 3);
+        build_launches(f, c);
+        knn_part_launch(pl->knn, f, pt.B, pt.out_idx, pt.out_dist, c);
+        if (pt.sets.size() > 1) launch_localize(pt.out_idx, f->n, pl->K, f->d_batch_off, (int)pt.sets.size(), c);
+    }
+    const hipError_t ec = hipStreamEndCapture(c, &pl->graph);
+    const std::string le = take_launch_error();
+    if (ec != hipSuccess || !le.empty() || !pl->graph)
+        return fail(RPF_EDEVICE, "rpf_plan: recording failed: " + (le.empty() ? std::string(hipGetErrorString(ec)) : le));
+    return check_hip(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
 extern "C" {
 
-rpf_status rpf_plan_create(const int64_t *n_host, int32_t count, int32_t d, const rpf_params *p, int32_t K,
-                           int32_t exclude_self, void *stream, rpf_plan **out) {
+rpf_status rpf_plan_create(const int64_t *n_host, const int32_t *d_host, int32_t count, const rpf_params *p, int32_t K,
+                           int32_t exclude_self, int64_t max_part_points, void *stream, rpf_plan **out) {
     if (out) *out = nullptr;
-    if (!out || !n_host || count < 1) return fail(RPF_EINVAL, "rpf_plan_create: NULL pointer or count < 1");
+    if (!out || !n_host || !d_host || !p || count < 1)
+        return fail(RPF_EINVAL, "rpf_plan_create: NULL pointer or count < 1");
     if (exclude_self != 0 && exclude_self != 1) return fail(RPF_EINVAL, "rpf_plan_create: exclude_self must be 0 or 1");
     if (K < 1 || K > 256) return fail(RPF_EINVAL, "rpf_plan_create: K must be in [1, 256]");
+    for (int i = 0; i < count; i++)
+        if (n_host[i] < 1 || d_host[i] < 1) return fail(RPF_EINVAL, "rpf_plan_create: every data set needs n, d >= 1");
+    if (max_part_points <= 0) max_part_points = (int64_t)4 << 20;
     hipStream_t s = (hipStream_t)stream;
     rpf_plan *pl = new rpf_plan();
     pl->K = K;
-    rpf_status st = prepare_forest(n_host, count, d, p, stream, &pl->f, false);
-    if (st != RPF_OK) {
-        delete pl;
-        return st;
+    pl->excl = exclude_self;
+    pl->count = count;
+    // group by d (first appearance), then cut each group into parts of <= max_part_points
+    std::vector<int32_t> dims;
+    for (int i = 0; i < count; i++)
+        if (std::find(dims.begin(), dims.end(), d_host[i]) == dims.end()) dims.push_back(d_host[i]);
+    for (int32_t d : dims) {
+        PlanPart cur;
+        int64_t pts = 0;
+        for (int i = 0; i < count; i++) {
+            if (d_host[i] != d) continue;
+            if (!cur.sets.empty() && pts + n_host[i] > max_part_points) {
+                pl->parts.push_back(cur);
+                cur = PlanPart();
+                pts = 0;
+            }
+            cur.sets.push_back(i);
+            pts += n_host[i];
+        }
+        if (!cur.sets.empty()) pl->parts.push_back(cur);
     }
-    rpf_forest *f = pl->f;
-    if (K > f->n - exclude_self) {
+    pl->entries.resize(count);
+    std::vector<const rpf_forest *> fs;
+    std::vector<int> maxB;
+    for (size_t k = 0; k < pl->parts.size(); k++) {
+        PlanPart &pt = pl->parts[k];
+        std::vector<int64_t> sizes;
+        for (int i : pt.sets) sizes.push_back(n_host[i]);
+        const int32_t d = d_host[pt.sets[0]];
+        rpf_status st = prepare_forest(sizes.data(), (int)sizes.size(), d, p, stream, &pt.f, false);
+        if (st != RPF_OK) {
+            plan_free(pl);
+            return st;
+        }
+        if (K > pt.f->n - exclude_self) {
+            plan_free(pl);
+            return fail(RPF_EINVAL, "rpf_plan_create: K must be <= n - exclude_self of every part");
+        }
+        pt.out_idx = static_cast<int32_t *>(cache_alloc((size_t)pt.f->n * K * 4, s));
+        pt.out_dist = static_cast<float *>(cache_alloc((size_t)pt.f->n * K * 4, s));
+        if (!pt.out_idx || !pt.out_dist) {
+            plan_free(pl);
+            return fail(RPF_ENOMEM, "rpf_plan_create: device allocation failed");
+        }
+        for (size_t j = 0; j < pt.sets.size(); j++) {
+            const rpf_batch_entry &e = pt.f->batch[j];
+            rpf_plan_entry &pe = pl->entries[pt.sets[j]];
+            pe.part = (int32_t)k;
+            pe.index_in_part = (int32_t)j;
+            pe.d = d;
+            pe.reserved = 0;
+            pe.n = e.n;
+            pe.row = e.offset;
+            pe.heap_base = e.heap_base;
+            pe.n_nodes = ((int64_t)1 << e.depth) - 1;
+        }
+        fs.push_back(pt.f);
+        maxB.push_back(knn_part_first_trees(pt.f, K, kTuneB[sizeof(kTuneB) / sizeof(kTuneB[0]) - 1]));
+    }
+    pl->knn = knn_shared_create(fs, maxB, K, exclude_self, s);
+    if (!pl->knn) {
         plan_free(pl);
-        return fail(RPF_EINVAL, "rpf_plan_create: K must be <= n - exclude_self");
+        return fail(RPF_ENOMEM, "rpf_plan_create: kNN workspace allocation failed");
     }
-    pl->knn = knn_all_plan_create(f, K, exclude_self, s);
-    pl->out_idx = static_cast<int32_t *>(cache_alloc((size_t)f->n * K * 4, s));
-    pl->out_dist = static_cast<float *>(cache_alloc((size_t)f->n * K * 4, s));
-    if (!pl->knn || !pl->out_idx || !pl->out_dist) {
-        plan_free(pl);
-        return fail(RPF_ENOMEM, "rpf_plan_create: device allocation failed");
-    }
+    rpf_status st;
     if ((st = check_hip(hipStreamSynchronize(s), "rpf_plan_create")) != RPF_OK ||
-        (st = check_hip(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "rpf_plan_create stream")) != RPF_OK) {
-        plan_free(pl);
-        return st;
-    }
-    take_launch_error();
-    hipStream_t c = pl->cap;
-    if ((st = check_hip(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal), "begin capture")) != RPF_OK) {
-        plan_free(pl);
-        return st;
-    }
-    fill_u32(f->err, 16, 0, c);
-    launch_nonfinite(c, f->X, f->n * f->d, f->err + 2);
-    launch_nonfinite(c, f->R, (int64_t)f->T * f->H * f->n_try * f->d, f->err + 3);
-    build_launches(f, c);
-    knn_all_plan_launch(pl->knn, f, pl->out_idx, pl->out_dist, c);
-    if (count > 1) launch_localize(pl->out_idx, f->n, K, f->d_batch_off, count, c);
-    const hipError_t ec = hipStreamEndCapture(c, &pl->graph);
-    const std::string le = take_launch_error();
-    if (ec != hipSuccess || !le.empty() || !pl->graph) {
-        fail(RPF_EDEVICE, "rpf_plan_create: recording failed: " + (le.empty() ? std::string(hipGetErrorString(ec)) : le));
-        plan_free(pl);
-        return RPF_EDEVICE;
-    }
-    if ((st = check_hip(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0), "graph instantiate")) != RPF_OK) {
+        (st = check_hip(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "rpf_plan_create stream")) != RPF_OK ||
+        (st = plan_record(pl)) != RPF_OK) {
         plan_free(pl);
         return st;
     }
@@ -759,13 +827,35 @@ rpf_status rpf_plan_create(const int64_t *n_host, int32_t count, int32_t d, cons
     return RPF_OK;
 }
 
-rpf_status rpf_plan_buffers(rpf_plan *pl, float **X_dev, float **directions_dev, int32_t **out_idx_dev,
-                            float **out_dist_dev) {
-    if (!pl) return fail(RPF_EINVAL, "rpf_plan_buffers: NULL plan");
-    if (X_dev) *X_dev = pl->f->X;
-    if (directions_dev) *directions_dev = pl->f->R;
-    if (out_idx_dev) *out_idx_dev = pl->out_idx;
-    if (out_dist_dev) *out_dist_dev = pl->out_dist;
+rpf_status rpf_plan_info(const rpf_plan *pl, int32_t *n_parts, int32_t *count) {
+    if (!pl) return fail(RPF_EINVAL, "rpf_plan_info: NULL plan");
+    if (n_parts) *n_parts = (int32_t)pl->parts.size();
+    if (count) *count = pl->count;
+    return RPF_OK;
+}
+
+rpf_status rpf_plan_part(const rpf_plan *pl, int32_t k, rpf_plan_part_info *out) {
+    if (!pl || !out) return fail(RPF_EINVAL, "rpf_plan_part: NULL pointer");
+    if (k < 0 || k >= (int32_t)pl->parts.size()) return fail(RPF_EINVAL, "rpf_plan_part: part out of range");
+    const PlanPart &pt = pl->parts[k];
+    out->rows = pt.f->n;
+    out->d = pt.f->d;
+    out->n_sets = (int32_t)pt.sets.size();
+    out->n_nodes = pt.f->H;
+    out->X_dev = pt.f->X;
+    out->directions_dev = pt.f->R;
+    out->out_idx_dev = pt.out_idx;
+    out->out_dist_dev = pt.out_dist;
+    out->forest = pt.f;
+    out->first_trees = knn_part_first_trees(pt.f, pl->K, pt.B);
+    out->reserved = 0;
+    return RPF_OK;
+}
+
+rpf_status rpf_plan_entry_of(const rpf_plan *pl, int32_t i, rpf_plan_entry *out) {
+    if (!pl || !out) return fail(RPF_EINVAL, "rpf_plan_entry_of: NULL pointer");
+    if (i < 0 || i >= pl->count) return fail(RPF_EINVAL, "rpf_plan_entry_of: data set out of range");
+    *out = pl->entries[i];
     return RPF_OK;
 }
 
@@ -776,17 +866,62 @@ rpf_status rpf_plan_launch(rpf_plan *pl, void *stream) {
 
 rpf_status rpf_plan_check(rpf_plan *pl, void *stream) {
     if (!pl) return fail(RPF_EINVAL, "rpf_plan_check: NULL plan");
-    int32_t flags[4] = {0, 0, 0, 0};
-    hipMemcpyAsync(flags, pl->f->err, 16, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    std::vector<int32_t> flags(4 * pl->parts.size(), 0);
+    for (size_t k = 0; k < pl->parts.size(); k++)
+        hipMemcpyAsync(&flags[4 * k], pl->parts[k].f->err, 16, hipMemcpyDeviceToHost, (hipStream_t)stream);
     const rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_plan_check");
     if (st != RPF_OK) return st;
-    if (flags[2]) return fail(RPF_EINVAL, "rpf_plan_check: X holds NaN or Inf");
-    if (flags[3]) return fail(RPF_EINVAL, "rpf_plan_check: directions hold NaN or Inf");
-    if (flags[0]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[0]));
+    for (size_t k = 0; k < pl->parts.size(); k++) {
+        if (flags[4 * k + 2]) return fail(RPF_EINVAL, "rpf_plan_check: X holds NaN or Inf (part " + std::to_string(k) + ")");
+        if (flags[4 * k + 3])
+            return fail(RPF_EINVAL, "rpf_plan_check: directions hold NaN or Inf (part " + std::to_string(k) + ")");
+        if (flags[4 * k]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[4 * k]));
+    }
     return RPF_OK;
 }
 
-const rpf_forest *rpf_plan_forest(const rpf_plan *pl) { return pl ? pl->f : nullptr; }
+rpf_status rpf_plan_tune(rpf_plan *pl, void *stream, double *tuned_ms) {
+    if (!pl) return fail(RPF_EINVAL, "rpf_plan_tune: NULL plan");
+    hipStream_t s = (hipStream_t)stream;
+    rpf_status st = rpf_plan_launch(pl, stream);  // forests built from the current inputs
+    if (st != RPF_OK || (st = rpf_plan_check(pl, stream)) != RPF_OK) return st;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    double total = 0;
+    for (auto &pt : pl->parts) {
+        double best = 1e300;
+        int bestB = pt.B;
+        std::vector<int> tried;
+        for (int b : kTuneB) {
+            const int B = knn_part_first_trees(pt.f, pl->K, b);
+            if (std::find(tried.begin(), tried.end(), B) != tried.end()) continue;
+            tried.push_back(B);
+            double ms = 1e300;
+            for (int rep = 0; rep < 3; rep++) {  // first run warms up, the best of the others counts
+                hipEventRecord(e0, s);
+                knn_part_launch(pl->knn, pt.f, B, pt.out_idx, pt.out_dist, s);
+                hipEventRecord(e1, s);
+                hipEventSynchronize(e1);
+                float t = 0;
+                hipEventElapsedTime(&t, e0, e1);
+                if (rep) ms = std::min(ms, (double)t);
+            }
+            if (ms < best) {
+                best = ms;
+                bestB = B;
+            }
+        }
+        pt.B = bestB;
+        total += best;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    const std::string le = take_launch_error();
+    if (!le.empty()) return fail(RPF_EDEVICE, "rpf_plan_tune: " + le);
+    if (tuned_ms) *tuned_ms = total;
+    return plan_record(pl);  // the outputs are recomputed by the next launch
+}
 
 rpf_status rpf_plan_destroy(rpf_plan *pl) {
     plan_free(pl);

@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/rpf.h"
 
@@ -126,10 +127,14 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
                      hipStream_t s);
 rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, hipStream_t s);
 uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K);
-struct KnnAllPlan;  // all-points search with a persistent workspace (recordable launches)
-KnnAllPlan *knn_all_plan_create(const rpf_forest *f, int K, int exclude_self, hipStream_t s);
-void knn_all_plan_launch(const KnnAllPlan *p, const rpf_forest *f, int32_t *out_idx, float *out_dist, hipStream_t s);
-void knn_all_plan_destroy(KnnAllPlan *p, hipStream_t s);
+// all-points search of several forests (parts) sharing one persistent workspace (recordable
+// launches); maxB[i] bounds the first-phase tree count part i will be launched with
+struct KnnShared;
+KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const std::vector<int> &maxB, int K,
+                             int exclude_self, hipStream_t s);
+int knn_part_first_trees(const rpf_forest *f, int K, int B);
+void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *out_idx, float *out_dist, hipStream_t s);
+void knn_shared_destroy(KnnShared *p, hipStream_t s);
 void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);
 int32_t forest_dim(const rpf_forest *f);

@@ -24,8 +24,9 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_buffers",
-           "rpf_plan_launch", "rpf_plan_check", "rpf_plan_forest", "rpf_plan_destroy", "rpf_last_error"]
+           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
+           "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
+           "rpf_plan_destroy", "rpf_last_error"]
 
 
 class RpfError(RuntimeError):
@@ -72,6 +73,19 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("rows", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("mean_batch_rows", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
                 ("max_s", ctypes.c_double), ("rows_per_s", ctypes.c_double)]
+
+
+class PlanEntry(ctypes.Structure):
+    _fields_ = [("part", ctypes.c_int32), ("index_in_part", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64), ("row", ctypes.c_int64),
+                ("heap_base", ctypes.c_int64), ("n_nodes", ctypes.c_int64)]
+
+
+class PlanPartInfo(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("d", ctypes.c_int32), ("n_sets", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("X_dev", ctypes.c_void_p), ("directions_dev", ctypes.c_void_p),
+                ("out_idx_dev", ctypes.c_void_p), ("out_dist_dev", ctypes.c_void_p), ("forest", ctypes.c_void_p),
+                ("first_trees", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -133,16 +147,20 @@ def load(path: str = LIB_PATH):
     lib.rpf_batch_info.restype = i32
     lib.rpf_batch_info.argtypes = [vp, i32, ctypes.POINTER(BatchEntry)]
     lib.rpf_plan_create.restype = i32
-    lib.rpf_plan_create.argtypes = [ctypes.POINTER(i64), i32, i32, ctypes.POINTER(Params), i32, i32, vp,
-                                    ctypes.POINTER(vp)]
-    lib.rpf_plan_buffers.restype = i32
-    lib.rpf_plan_buffers.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.rpf_plan_create.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i32), i32, ctypes.POINTER(Params), i32, i32,
+                                    i64, vp, ctypes.POINTER(vp)]
+    lib.rpf_plan_info.restype = i32
+    lib.rpf_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.rpf_plan_part.restype = i32
+    lib.rpf_plan_part.argtypes = [vp, i32, ctypes.POINTER(PlanPartInfo)]
+    lib.rpf_plan_entry_of.restype = i32
+    lib.rpf_plan_entry_of.argtypes = [vp, i32, ctypes.POINTER(PlanEntry)]
     lib.rpf_plan_launch.restype = i32
     lib.rpf_plan_launch.argtypes = [vp, vp]
     lib.rpf_plan_check.restype = i32
     lib.rpf_plan_check.argtypes = [vp, vp]
-    lib.rpf_plan_forest.restype = vp
-    lib.rpf_plan_forest.argtypes = [vp]
+    lib.rpf_plan_tune.restype = i32
+    lib.rpf_plan_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.rpf_plan_destroy.restype = i32
     lib.rpf_plan_destroy.argtypes = [vp]
     lib.rpf_release_cached_memory.restype = i32
@@ -343,34 +361,53 @@ def _view(ptr: int, shape, dtype) -> torch.Tensor:
 
 
 class Plan:
-    """Build + all-points search of fixed shapes recorded as one HIP graph (rpf_plan_*).
-    Write `X` and `directions` (plan-owned device tensors), call launch(), read `idx`/`dist`."""
+    """Build + all-points search of many data sets recorded as one HIP graph (rpf_plan_*).
+    set_inputs() writes the points and directions into the plan's buffers, launch() runs the
+    graph, result(i) views data set i's (idx, dist)."""
 
-    def __init__(self, sizes, d: int, n_trees: int, leaf_size: int, K: int, exclude_self: bool = True,
-                 n_try: int = 1, dist_prec: str = "fp32", stream=None):
+    def __init__(self, sizes, dims, n_trees: int, leaf_size: int, K: int, exclude_self: bool = True,
+                 n_try: int = 1, dist_prec: str = "fp32", max_part_points: int = 0, stream=None):
         self.sizes = [int(n) for n in sizes]
-        self.d, self.n_trees, self.leaf_size, self.n_try, self.K = d, n_trees, leaf_size, n_try, K
+        self.dims = [int(d) for d in dims] if not isinstance(dims, int) else [int(dims)] * len(self.sizes)
+        self.n_trees, self.leaf_size, self.n_try, self.K = n_trees, leaf_size, n_try, K
         p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
                    dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
                    directions_dev=None, mem_budget_bytes=0)
-        ns = (ctypes.c_int64 * len(self.sizes))(*self.sizes)
+        c = len(self.sizes)
+        ns = (ctypes.c_int64 * c)(*self.sizes)
+        ds = (ctypes.c_int32 * c)(*self.dims)
         h = ctypes.c_void_p()
-        _check(load().rpf_plan_create(ns, len(self.sizes), d, ctypes.byref(p), K, int(exclude_self),
+        _check(load().rpf_plan_create(ns, ds, c, ctypes.byref(p), K, int(exclude_self), max_part_points,
                                       _stream(stream), ctypes.byref(h)))
         self._h = h
-        xp, rp, ip, dp_ = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
-        _check(load().rpf_plan_buffers(h, ctypes.byref(xp), ctypes.byref(rp), ctypes.byref(ip), ctypes.byref(dp_)))
-        n = sum(self.sizes)
-        H = sum((1 << depth(m, leaf_size)) - 1 for m in self.sizes)
-        self.X = _view(xp.value, (n, d), torch.float32)
-        self.directions = _view(rp.value, (n_trees, H, n_try, d), torch.float32) if H else None
-        self.idx = _view(ip.value, (n, K), torch.int32)
-        self.dist = _view(dp_.value, (n, K), torch.float32)
-        fp = load().rpf_plan_forest(h)
-        self.forest = (BatchedForest if len(self.sizes) > 1 else Forest)(
-            ctypes.c_void_p(fp), n, d, n_trees, leaf_size, n_try, max(depth(m, leaf_size) for m in self.sizes))
-        self.forest.count, self.forest.sizes = len(self.sizes), self.sizes
-        self.forest.free = lambda: None  # owned by the plan
+        npart = ctypes.c_int32(0)
+        _check(load().rpf_plan_info(h, ctypes.byref(npart), None))
+        self.parts = []
+        for k in range(npart.value):
+            pi = PlanPartInfo()
+            _check(load().rpf_plan_part(h, k, ctypes.byref(pi)))
+            self.parts.append({
+                "rows": pi.rows, "d": pi.d, "n_sets": pi.n_sets, "n_nodes": pi.n_nodes,
+                "X": _view(pi.X_dev, (pi.rows, pi.d), torch.float32),
+                "directions": _view(pi.directions_dev, (n_trees, pi.n_nodes, n_try, pi.d), torch.float32)
+                if pi.n_nodes else None,
+                "idx": _view(pi.out_idx_dev, (pi.rows, K), torch.int32),
+                "dist": _view(pi.out_dist_dev, (pi.rows, K), torch.float32),
+                "forest": pi.forest})
+        self.entries = []
+        for i in range(c):
+            e = PlanEntry()
+            _check(load().rpf_plan_entry_of(h, i, ctypes.byref(e)))
+            self.entries.append({k: getattr(e, k) for k, _ in PlanEntry._fields_})
+
+    def set_inputs(self, xs, directions):
+        """xs[i]: [n_i][d_i] points of data set i, directions[i]: [n_trees][H_i][n_try][d_i]
+        (numpy arrays or tensors); copied into the plan's buffers."""
+        for e, x, r in zip(self.entries, xs, directions):
+            pt = self.parts[e["part"]]
+            pt["X"][e["row"]:e["row"] + e["n"]].copy_(torch.as_tensor(x))
+            if e["n_nodes"]:
+                pt["directions"][:, e["heap_base"]:e["heap_base"] + e["n_nodes"]].copy_(torch.as_tensor(r))
 
     def launch(self, stream=None):
         _check(load().rpf_plan_launch(self._h, _stream(stream)))
@@ -378,13 +415,19 @@ class Plan:
     def check(self, stream=None):
         _check(load().rpf_plan_check(self._h, _stream(stream)))
 
-    def split(self):
-        """(idx, dist) per data set, views of the plan's outputs."""
-        out, o = [], 0
-        for m in self.sizes:
-            out.append((self.idx[o:o + m], self.dist[o:o + m]))
-            o += m
-        return out
+    def tune(self, stream=None) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(load().rpf_plan_tune(self._h, _stream(stream), ctypes.byref(ms)))
+        for k, pt in enumerate(self.parts):
+            pi = PlanPartInfo()
+            _check(load().rpf_plan_part(self._h, k, ctypes.byref(pi)))
+            pt["first_trees"] = pi.first_trees
+        return ms.value
+
+    def result(self, i: int):
+        e = self.entries[i]
+        pt = self.parts[e["part"]]
+        return pt["idx"][e["row"]:e["row"] + e["n"]], pt["dist"][e["row"]:e["row"] + e["n"]]
 
     def close(self):
         if self._h is not None:

@@ -165,16 +165,33 @@ def make_config(c: int, n: int | None = None) -> Workload:
                     meta=dict(config=c, n=nn, d=cfg["d"]))
 
 
-def batched_datasets(seed: int = SEED_BASE + 5, count: int = 512, n_lo: int = 2000,
-                     n_hi: int = 200_000, dims=(8, 32, 64, 256)):
-    """Many uneven data sets: n log-uniform in [n_lo, n_hi], d from `dims`, 5..50 isotropic
-    unit-variance clusters with means ~ N(0, 25 I).  Returns a list of float32 arrays."""
+def batched_shapes(seed: int = SEED_BASE + 5, count: int = 512, n_lo: int = 2000, n_hi: int = 200_000,
+                   dims=(8, 32, 64, 256)):
+    """(n_i, d_i, clusters_i) of the uneven data sets: n log-uniform in [n_lo, n_hi], d from
+    `dims`, 5..50 clusters."""
     rng = _rng(seed, 9)
     ns = np.round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count))).astype(np.int64)
     ds = rng.choice(np.asarray(dims), size=count)
     cs = rng.integers(5, 51, size=count)
-    return [gaussian_mixture(seed * 1000 + i, int(ns[i]), int(ds[i]), int(cs[i]))
-            for i in range(count)]
+    return [(int(ns[i]), int(ds[i]), int(cs[i])) for i in range(count)]
+
+
+def batched_datasets(seed: int = SEED_BASE + 5, count: int = 512, n_lo: int = 2000,
+                     n_hi: int = 200_000, dims=(8, 32, 64, 256), workers: int = 1):
+    """Many uneven data sets (batched_shapes), each an isotropic unit-variance mixture with
+    means ~ N(0, 25 I) from its own seed, so the result does not depend on `workers` (threads
+    generating data sets side by side).  Returns a list of float32 arrays."""
+    shapes = batched_shapes(seed, count, n_lo, n_hi, dims)
+
+    def one(i):
+        n, d, c = shapes[i]
+        return gaussian_mixture(seed * 1000 + i, n, d, c)
+
+    if workers <= 1:
+        return [one(i) for i in range(count)]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(one, range(count)))
 
 
 def serving_requests(seed: int, n_requests: int, rate_per_s: float, b_median: int = 64,

@@ -98,15 +98,21 @@ def test_plan_arguments_rejected_without_device():
                    directions_dev=None, mem_budget_bytes=0)
     h = ctypes.c_void_p(1234)
     ns = (ctypes.c_int64 * 2)(100, 200)
-    assert lib.rpf_plan_create(None, 2, 4, ctypes.byref(p), 5, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    ds = (ctypes.c_int32 * 2)(4, 4)
+    assert lib.rpf_plan_create(None, ds, 2, ctypes.byref(p), 5, 1, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
     assert h.value is None
-    assert lib.rpf_plan_create(ns, 0, 4, ctypes.byref(p), 5, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
-    assert lib.rpf_plan_create(ns, 2, 4, ctypes.byref(p), 0, 1, None, ctypes.byref(h)) == rpf.RPF_EINVAL
-    assert lib.rpf_plan_create(ns, 2, 4, ctypes.byref(p), 5, 2, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, None, 2, ctypes.byref(p), 5, 1, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, ds, 0, ctypes.byref(p), 5, 1, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, ds, 2, ctypes.byref(p), 0, 1, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_create(ns, ds, 2, ctypes.byref(p), 5, 2, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    bad = (ctypes.c_int32 * 2)(4, 0)
+    assert lib.rpf_plan_create(ns, bad, 2, ctypes.byref(p), 5, 1, 0, None, ctypes.byref(h)) == rpf.RPF_EINVAL
     assert lib.rpf_plan_launch(None, None) == rpf.RPF_EINVAL
     assert lib.rpf_plan_check(None, None) == rpf.RPF_EINVAL
-    assert lib.rpf_plan_buffers(None, None, None, None, None) == rpf.RPF_EINVAL
-    assert lib.rpf_plan_forest(None) is None
+    assert lib.rpf_plan_tune(None, None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_info(None, None, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_part(None, 0, None) == rpf.RPF_EINVAL
+    assert lib.rpf_plan_entry_of(None, 0, None) == rpf.RPF_EINVAL
     assert lib.rpf_plan_destroy(None) == rpf.RPF_OK
     assert lib.rpf_build_batched(ctypes.c_void_p(0x1000), None, 2, 4, ctypes.byref(p), None,
                                  ctypes.byref(h)) == rpf.RPF_EINVAL

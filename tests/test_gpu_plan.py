@@ -1,6 +1,7 @@
-"""GPU tests of the recorded build + search (rpf_plan_*): every replay of the graph, with
-eager work and synchronisations between replays and new data between some of them, equals
-the eager build and search over the same inputs."""
+"""GPU tests of the recorded build + search of many data sets (rpf_plan_*): every replay of
+the graph -- with eager work and synchronisations between replays, new data between some of
+them, and a re-recording by the tuner -- gives every data set the same trees and all-points
+kNN as a forest grown over it alone."""
 
 import numpy as np
 import pytest
@@ -12,65 +13,65 @@ from tests.helpers import heap_count
 pytestmark = pytest.mark.gpu
 
 
-def _inputs(seed, sizes, d, T, n0):
-    xs = [W.gaussian_mixture(seed + i, n, d, 5) for i, n in enumerate(sizes)]
-    Rs = [W.directions(seed + 50 + i, T, heap_count(n, n0), 1, d) for i, n in enumerate(sizes)]
+def _inputs(seed, sizes, dims, T, n0):
+    xs = [W.gaussian_mixture(seed + i, n, d, 5) for i, (n, d) in enumerate(zip(sizes, dims))]
+    Rs = [W.directions(seed + 50 + i, T, heap_count(n, n0), 1, d) for i, (n, d) in enumerate(zip(sizes, dims))]
     return xs, Rs
 
 
-def _eager(xs, Rs, T, n0, K, prec):
+def _alone(x, R, T, n0, K, prec):
     from paper_1812_11689_amd import rpf
-    Xs = [torch.from_numpy(x).cuda() for x in xs]
-    R = torch.from_numpy(np.concatenate(Rs, axis=1)).cuda()
-    if len(xs) == 1:
-        f = rpf.build(Xs[0], T, n0, R, dist_prec=prec)
-    else:
-        f = rpf.build_batched(Xs, T, n0, R, dist_prec=prec)
-    i, dd = f.all_knn(K)
+    f = rpf.build(torch.from_numpy(x).cuda(), T, n0, torch.from_numpy(R).cuda(), dist_prec=prec)
+    i, d = f.all_knn(K)
+    dump = f.tree_dump(0)
     torch.cuda.synchronize()
     f.free()
-    return i, dd
+    return i, d, dump
 
 
-@pytest.mark.parametrize("prec,d,sizes", [("fp16", 16, [900, 3000, 150, 5000, 64]), ("fp32", 40, [7000])])
-def test_plan_replays_equal_eager(prec, d, sizes):
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_plan_replays_equal_each_alone(prec):
     from paper_1812_11689_amd import rpf
+    sizes = [900, 3000, 150, 5000, 64, 2200, 700]
+    dims = [16, 16, 8, 16, 8, 40, 16]
     T, n0, K = 3, 32, 7
-    print(f"[plan] {prec} d={d} sizes={sizes}", flush=True)
-    plan = rpf.Plan(sizes, d, T, n0, K, dist_prec=prec)
+    print(f"[plan] {prec} sizes={sizes} dims={dims}", flush=True)
+    plan = rpf.Plan(sizes, dims, T, n0, K, dist_prec=prec, max_part_points=4000)
+    assert len(plan.parts) >= 4  # d 16 is cut into several parts
     for rep, seed in enumerate([1000, 1000, 2000, 1000]):
-        xs, Rs = _inputs(seed, sizes, d, T, n0)
-        plan.X.copy_(torch.from_numpy(np.concatenate(xs)).cuda())
-        plan.directions.copy_(torch.from_numpy(np.concatenate(Rs, axis=1)).cuda())
+        xs, Rs = _inputs(seed, sizes, dims, T, n0)
+        plan.set_inputs(xs, Rs)
+        if rep == 2:
+            plan.tune()  # re-records the graph
         plan.launch()
         plan.check()
-        gi, gd = plan.idx.clone(), plan.dist.clone()
+        torch.cuda.synchronize()
+        for i in range(len(sizes)):
+            gi, gd = plan.result(i)
+            ai, ad, dump = _alone(xs[i], Rs[i], T, n0, K, prec)
+            assert torch.equal(gi, ai) and torch.equal(gd, ad), f"replay {rep} data set {i}"
         # eager work of the program between replays
-        ei, ed = _eager(xs, Rs, T, n0, K, prec)
-        assert torch.equal(gi, ei) and torch.equal(gd, ed), f"replay {rep}"
-        dump = plan.forest.tree_dump(0)
-        assert int(dump["leaf_of"].min()) >= 1
         torch.cuda.synchronize()
     plan.close()
 
 
 def test_plan_reports_nonfinite_input():
     from paper_1812_11689_amd import rpf
-    sizes, d, T, n0 = [500, 800], 8, 2, 30
+    sizes, dims, T, n0 = [500, 800], [8, 8], 2, 30
     print("[plan] non-finite input", flush=True)
-    plan = rpf.Plan(sizes, d, T, n0, 5)
-    xs, Rs = _inputs(3000, sizes, d, T, n0)
-    X = np.concatenate(xs)
-    X[123, 4] = np.nan
-    plan.X.copy_(torch.from_numpy(X).cuda())
-    plan.directions.copy_(torch.from_numpy(np.concatenate(Rs, axis=1)).cuda())
+    plan = rpf.Plan(sizes, dims, T, n0, 5)
+    xs, Rs = _inputs(3000, sizes, dims, T, n0)
+    xs[1][123, 4] = np.nan
+    plan.set_inputs(xs, Rs)
     plan.launch()
     with pytest.raises(rpf.RpfError) as e:
         plan.check()
     assert e.value.status == rpf.RPF_EINVAL
-    # the same plan with finite data afterwards
-    X[123, 4] = 0.5
-    plan.X.copy_(torch.from_numpy(X).cuda())
+    xs[1][123, 4] = 0.5  # the same plan with finite data afterwards
+    plan.set_inputs(xs, Rs)
     plan.launch()
     plan.check()
+    ai, ad, _ = _alone(xs[1], Rs[1], T, n0, 5, "fp32")
+    gi, gd = plan.result(1)
+    assert torch.equal(gi, ai) and torch.equal(gd, ad)
     plan.close()
