@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--only-serve", action="store_true", help="run the serving leg alone (profiling)")
     ap.add_argument("--serve-n", type=int, default=None, help="points of the served forest (default: 4M)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-data-sets leg")
+    ap.add_argument("--only-batched", action="store_true", help="run the many-data-sets leg alone (profiling)")
+    ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
     ap.add_argument("--cpu-trees", type=int, default=1,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
@@ -227,6 +230,9 @@ def main():
     if args.only_serve:
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
         return
+    if args.only_batched:
+        print(json.dumps({"batched": batched_leg(args)}), flush=True)
+        return
     t0 = time.time()
     w = W.make_config(2, n=args.n)
     n, d = w.x.shape
@@ -310,7 +316,14 @@ def main():
     if not args.no_serve:
         del X, Rd
         torch.cuda.empty_cache()
+        rpf.release_cached_memory()
         serving = serving_leg(args)
+
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        rpf.release_cached_memory()
+        batched = batched_leg(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -342,6 +355,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 
@@ -440,6 +454,112 @@ def serving_leg(args):
     torch.cuda.empty_cache()
     f32, res["fp32"] = run("fp32")
     f32.free()
+    return res
+
+
+def batched_leg(args):
+    """Many uneven data sets (default 512: n log-uniform in [2000, 200000], d in {8, 32, 64,
+    256}, 5..50 clusters), T 16, n0 64, K 16, fp16 tiles: one recorded plan (build + all-points
+    kNN of every data set in one graph launch), tuned once, timed over replays; beside it the
+    eager batched path over the same parts and a one-forest-per-data-set loop on a sample."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from paper_1812_11689_amd import rpf
+    from paper_1812_11689_amd import workloads as W
+
+    T, n0, K, prec = 16, 64, 16, "fp16"
+    count = args.batch_count
+    t0 = time.time()
+    shapes = W.batched_shapes(count=count)
+    xs = W.batched_datasets(count=count, workers=16)
+
+    def dirs(i):
+        n, d, _ = shapes[i]
+        return W.directions((W.SEED_BASE + 105) * 1000 + i, T, (1 << rpf.depth(n, n0)) - 1, 1, d)
+
+    with ThreadPoolExecutor(16) as ex:
+        Rs = list(ex.map(dirs, range(count)))
+    sizes = [s_[0] for s_ in shapes]
+    dims = [s_[1] for s_ in shapes]
+    N = sum(sizes)
+    print(f"# many-data-sets workload: {count} sets, {N} points, d in {sorted(set(dims))} "
+          f"(generated in {time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    res = {"workload": f"batched_{count}_sets_T16_fp16", "data_sets": count, "points": N, "K": K, "n_trees": T,
+           "leaf_size": n0}
+    t0 = time.time()
+    plan = rpf.Plan(sizes, dims, T, n0, K, dist_prec=prec)
+    plan.set_inputs(xs, Rs)
+    torch.cuda.synchronize()
+    res["plan_create_s"] = round(time.time() - t0, 2)
+    res["parts"] = len(plan.parts)
+    plan.launch()
+    plan.check()
+    res["tuned_candidate_ms"] = round(plan.tune(), 3)
+    res["first_trees"] = [pt.get("first_trees") for pt in plan.parts]
+    plan.launch()
+    plan.check()
+    times = []
+    for _ in range(max(args.steps, 3)):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        plan.launch()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    plan.check()
+    ms = float(np.median(times)) * 1e3
+    res["graph_ms_per_job"] = round(ms, 3)
+    res["graph_points_per_s"] = round(N / (ms / 1e3), 1)
+    # recall of a sample of data sets against exact brute force (binary64 on the device)
+    rng = np.random.default_rng(W.SEED_BASE + 305)
+    hit = tot = 0
+    for i in rng.choice(count, size=min(8, count), replace=False):
+        X = torch.from_numpy(xs[i]).cuda().double()
+        pts = torch.from_numpy(rng.choice(sizes[i], size=min(300, sizes[i]), replace=False)).cuda()
+        D = (X * X).sum(1)[None, :] - 2.0 * (X[pts] @ X.T)
+        D[torch.arange(len(pts)), pts] = float("inf")
+        truth = torch.topk(D, K, dim=1, largest=False).indices.cpu().numpy()
+        got = plan.result(int(i))[0][pts].cpu().numpy()
+        for a, b in zip(got, truth):
+            hit += len(set(a.tolist()) & set(b.tolist()))
+        tot += truth.size
+    res["recall"] = round(hit / max(tot, 1), 5)
+    parts = [[e_i for e_i, e in enumerate(plan.entries) if e["part"] == k] for k in range(len(plan.parts))]
+    plan.close()
+    torch.cuda.empty_cache()
+    # the eager batched path over the same parts (one warm-up pass, then timed per part,
+    # uploads excluded)
+    eager = []
+    for rep in range(2):
+        eager = []
+        for ids in parts:
+            dev = [torch.from_numpy(xs[i]).cuda() for i in ids]
+            R = torch.from_numpy(np.concatenate([Rs[i] for i in ids], axis=1)).cuda()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            f = rpf.build_batched(dev, T, n0, R, dist_prec=prec)
+            f.all_knn(K)
+            f.free()
+            torch.cuda.synchronize()
+            eager.append(time.perf_counter() - t1)
+            del dev, R
+    res["eager_batched_ms_per_job"] = round(sum(eager) * 1e3, 3)
+    # one forest per data set, on a sample of data sets
+    sample = list(range(min(64, count)))
+    pts_s = sum(sizes[i] for i in sample)
+    dev = [torch.from_numpy(xs[i]).cuda() for i in sample]
+    Rd = [torch.from_numpy(Rs[i]).cuda() for i in sample]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for x, r in zip(dev, Rd):
+        f = rpf.build(x, T, n0, r, dist_prec=prec)
+        f.all_knn(K)
+        f.free()
+    torch.cuda.synchronize()
+    per = time.perf_counter() - t1
+    res["per_data_set_points_per_s"] = round(pts_s / per, 1)
+    res["per_data_set_sample"] = f"first {len(sample)} data sets, {pts_s} points, {per * 1e3:.1f} ms"
+    print(f"# many data sets: {res}", file=sys.stderr, flush=True)
     return res
 
 
