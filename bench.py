@@ -38,7 +38,7 @@ RECORD_KERNEL = {
     "level_small": "k_level_small<true>",
     "leaf_finalize": "k_leaf_finalize<float>",
     "merge_first": "k_merge_first<16>",
-    "final_rerank": "k_final<true>",
+    "final_rerank": "k_final<true, 12>",
 }
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3

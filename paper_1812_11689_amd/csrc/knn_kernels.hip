@@ -853,10 +853,8 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 // ---------------------------------------------------------------- final merge and rerank
 
 constexpr int kListCap = 256;              // Phase I list records per row
-constexpr int kFinalQ = 12;                // entries per lane
+constexpr int kFinalQ = 12;                // most entries per lane (k_final is instantiated for 4, 8, 12)
 constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
-constexpr int kHT = 1024;                  // per-row hash table (indices) for the dedup
-constexpr int kRCap = kHT / 2;             // rerank set per row (its doubles reuse the hash table)
 constexpr int kWCap = 256;                 // binary64 window per row
 
 struct FinalArgs {
@@ -893,8 +891,13 @@ __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
 
 // One wave per result row, four rows per block.  Entries stay in registers; an LDS hash
 // of indices marks the first copy of every index (any copy's interval is valid for it).
-template <bool VEC>
+template <bool VEC, int Q>
 __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
+    // hash table twice the records a row can hold (at most 64 Q), re-rank set half of it
+    constexpr int kHT = Q <= 4 ? 512 : 1024;
+    constexpr int kHBits = Q <= 4 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
+    static_assert((1 << kHBits) == kHT, "hash range must equal the table");
+    constexpr int kRCap = kHT / 2;
     __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
     __shared__ int32_t s_r[4][kRCap];
     __shared__ uint32_t s_d[4][kRCap];
@@ -912,26 +915,26 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         stat_add(A, 5, (unsigned long long)max(c1, 0));
         stat_add(A, 6, (unsigned long long)max(c2, 0));
     }
-    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kFinalCap) {
+    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > 64 * Q) {
         if (lane == 0) push_fallback(A, a);
         return;
     }
     for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
     for (int j = lane; j < A.d; j += 64) s_q[j] = A.Qr[a * A.d + j];
     wave_sync();
-    int32_t eidx[kFinalQ];
-    uint32_t elb[kFinalQ], eub[kFinalQ];
-    bool first[kFinalQ];
+    int32_t eidx[Q];
+    uint32_t elb[Q], eub[Q];
+    bool first[Q];
     int nd = 0;
     bool bad = false;  // an index outside [0, npts) is an internal error, never dereferenced
-    Ent ev[kFinalQ];   // every record of the row is loaded first: the wave waits on memory once
+    Ent ev[Q];   // every record of the row is loaded first: the wave waits on memory once
 #pragma unroll
-    for (int q = 0; q < kFinalQ; q++) {
+    for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
         ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
     }
 #pragma unroll
-    for (int q = 0; q < kFinalQ; q++) {
+    for (int q = 0; q < Q; q++) {
         first[q] = false;
         eidx[q] = -1;
         elb[q] = eub[q] = 0;
@@ -941,7 +944,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
             eidx[q] = e.idx;
             elb[q] = fkey(e.lb);
             eub[q] = fkey(e.ub);
-            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> 22;
+            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kHBits);
             while (true) {
                 const int old = atomicCAS(&s_key[w][h], -1, e.idx);
                 if (old == -1) {
@@ -963,11 +966,11 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         return;
     }
     float tv = INFINITY;
-    if (nd >= K) tv = __uint_as_float(wave_kth_upper<kFinalQ>(eub, first, K - 1));
+    if (nd >= K) tv = __uint_as_float(wave_kth_upper<Q>(eub, first, K - 1));
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
     int nr = 0;  // rerank set R = {first copies with lb <= tau'}
 #pragma unroll
-    for (int q = 0; q < kFinalQ; q++) {
+    for (int q = 0; q < Q; q++) {
         const bool in = first[q] && elb[q] <= tp;
         const uint64_t mk = __ballot(in);
         const int pos = nr + mask_rank(mk);
@@ -1604,12 +1607,20 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     }
     {
         ProfScope ps(s, "merge_first", 0, 0);
-        if (cap1 <= 1024)
-            hipLaunchKernelGGL(k_merge_first<16>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, K, cs.B,
-                               v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
+        // the smallest per-lane slot count that holds the row's B x max_leaf slots
+        const dim3 mg((unsigned)((rows + 3) / 4));
+        if (cap1 <= 256)
+            hipLaunchKernelGGL(k_merge_first<4>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
+                               cap1, tau, list, lcnt, lcap, cnt);
+        else if (cap1 <= 512)
+            hipLaunchKernelGGL(k_merge_first<8>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
+                               cap1, tau, list, lcnt, lcap, cnt);
+        else if (cap1 <= 1024)
+            hipLaunchKernelGGL(k_merge_first<16>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
+                               cap1, tau, list, lcnt, lcap, cnt);
         else
-            hipLaunchKernelGGL(k_merge_first<kMergeCap / 64>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows,
-                               K, cs.B, v.max_leaf, pidx, plb, pub, cap1, tau, list, lcnt, lcap, cnt);
+            hipLaunchKernelGGL(k_merge_first<kMergeCap / 64>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx,
+                               plb, pub, cap1, tau, list, lcnt, lcap, cnt);
         launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0 || cs.nsjobs1 > 0) {
@@ -1637,10 +1648,18 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         ProfScope ps(s, "final_rerank", 0, 0);
         const size_t lds = 4 * sizeof(float) * (size_t)((v.d + 3) & ~3);
         const dim3 grid((unsigned)((rows + 3) / 4));
-        if (vec)
-            hipLaunchKernelGGL(k_final<true>, grid, dim3(256), lds, s, fa, rows);
-        else
-            hipLaunchKernelGGL(k_final<false>, grid, dim3(256), lds, s, fa, rows);
+        // the smallest per-lane record count that holds the list and the Phase II records
+        const int need = lcap + cap2;
+        if (need <= 256) {
+            if (vec) hipLaunchKernelGGL((k_final<true, 4>), grid, dim3(256), lds, s, fa, rows);
+            else hipLaunchKernelGGL((k_final<false, 4>), grid, dim3(256), lds, s, fa, rows);
+        } else if (need <= 512) {
+            if (vec) hipLaunchKernelGGL((k_final<true, 8>), grid, dim3(256), lds, s, fa, rows);
+            else hipLaunchKernelGGL((k_final<false, 8>), grid, dim3(256), lds, s, fa, rows);
+        } else {
+            if (vec) hipLaunchKernelGGL((k_final<true, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
+            else hipLaunchKernelGGL((k_final<false, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
+        }
         launch_check(s, "k_final");
     }
     FallbackArgs fb;

@@ -44,6 +44,9 @@ ALL = [
     ("single_leaf", 300, 5, 2, 300, 9, "bf16", "mixture", 0, 1),
     ("tiny", 40, 3, 2, 4, 3, "fp32", "mixture", 0, 1),
     ("k1", 5000, 10, 5, 20, 1, "fp16", "mixture", 0, 1),
+    # list + Phase II capacity above 512 records per row, and more than 1024 Phase I slots
+    ("many_trees", 8000, 16, 24, 40, 20, "fp32", "mixture", 0, 1),
+    ("big_leaves", 6000, 12, 4, 300, 8, "bf16", "mixture", 0, 1),
 ]
 
 
