@@ -150,7 +150,8 @@ typedef struct {
     int32_t *out_idx_dev;            /* [rows][K]                                            */
     float *out_dist_dev;             /* [rows][K]                                            */
     const rpf_forest *forest;        /* not to be freed                                      */
-    int32_t first_trees, reserved;
+    int32_t first_trees;             /* first-phase trees of its candidate stage             */
+    int32_t reserved;
 } rpf_plan_part_info;
 
 rpf_status rpf_plan_create(const int64_t *n_host, const int32_t *d_host, int32_t count, const rpf_params *params,

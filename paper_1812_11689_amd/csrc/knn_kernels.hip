@@ -1484,12 +1484,11 @@ static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const 
                        const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
     constexpr int NT = NB >= 2 ? 64 * NB : 64;
+    const dim3 g((unsigned)njobs);
     if (out.mode == 0)
-        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm,
-                           pt, bc, excl, out);
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt, bc, excl, out);
     else
-        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), dim3((unsigned)njobs), dim3(NT), 0, s, jobs, A, dp, stride, nrm,
-                           pt, bc, excl, out);
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), g, dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt, bc, excl, out);
     launch_check(s, "k_tile_sym");
 }
 
