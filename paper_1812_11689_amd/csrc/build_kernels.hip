@@ -47,21 +47,27 @@ __device__ inline void project_segment(const float *__restrict__ X, int d, const
 }
 
 // LDS layout: perm[m] int32 | key[m] u64 | dir[d] | hist[256] | misc ; nTry>1 adds p[m], tree[P2]
-template <bool VEC>
+template <bool VEC, bool LEAD>
 __global__ __launch_bounds__(256) void k_level_small(
     const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
     const SegDesc *__restrict__ segs, const int32_t *__restrict__ perm_in,
     int32_t *__restrict__ perm_out, int64_t n, double *__restrict__ split,
-    int32_t *__restrict__ split_idx, int32_t *__restrict__ chosen, int32_t *__restrict__ err) {
+    int32_t *__restrict__ split_idx, int32_t *__restrict__ chosen, int32_t *__restrict__ err,
+    const LookDesc *__restrict__ look, double2 *__restrict__ ahead, uint64_t *__restrict__ keys_next,
+    const uint64_t *__restrict__ keys_in) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int t = blockIdx.y;
     const SegDesc sg = segs[blockIdx.x];
     const int m = sg.size;
     const int tid = threadIdx.x;
+    const int ds = (d + 3) & ~3;
     int32_t *s_perm = reinterpret_cast<int32_t *>(smem);
     uint64_t *s_key = reinterpret_cast<uint64_t *>(smem + ((4 * m + 15) & ~15));
-    float *s_r = reinterpret_cast<float *>(s_key + m);
-    uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_r + ((d + 3) & ~3));
+    // the node's direction (binary32); on a lead level it and its children's, as binary64
+    uint8_t *s_dir = smem + ((((4 * m + 15) & ~15) + 8 * m + 15) & ~15);  // 16-byte aligned
+    float *s_r = reinterpret_cast<float *>(s_dir);
+    double *s_rd = reinterpret_cast<double *>(s_dir);
+    uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_rd + 3 * ds);
     uint32_t *s_misc = s_hist + 256;  // 16 words
     double *s_p = reinterpret_cast<double *>(s_misc + 16);
     int P2 = 1;
@@ -95,9 +101,36 @@ __global__ __launch_bounds__(256) void k_level_small(
         ch = best_i < 0 ? 0 : best_i;
     }
     __syncthreads();
-    for (int j = tid; j < d; j += blockDim.x) s_r[j] = Rn[(int64_t)ch * d + j];
-    __syncthreads();
-    {
+    if (keys_in) {  // fed level: the keys were made by the partition of the level above
+        for (int i = tid; i < m; i += blockDim.x) s_key[i] = keys_in[(int64_t)t * n + sg.off + i];
+    } else if (LEAD) {  // lead level: the children's projections from the same read of X
+        const LookDesc lk = look[blockIdx.x];
+        for (int j = tid; j < d; j += blockDim.x) {
+            s_rd[j] = Rn[j];
+#pragma unroll
+            for (int b = 0; b < 2; b++)  // a leaf child has no direction: project onto zero
+                s_rd[ds * (b + 1) + j] =
+                    lk.child_heap[b] > 0 ? R[((int64_t)t * H + (lk.child_heap[b] - 1)) * (int64_t)d + j] : 0.f;
+        }
+        __syncthreads();
+        const int g = tid & 7, pt = tid >> 3;
+        for (int base = 0; base < m; base += 64) {  // rows base + pt and base + 32 + pt
+            const int ia = base + pt, ib = ia + 32;
+            double p[6];
+            group8_dot64x3r2<VEC>(X + (int64_t)s_perm[ia < m ? ia : 0] * d, X + (int64_t)s_perm[ib < m ? ib : 0] * d,
+                                  s_rd, ds, d, g, p);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int i = h ? ib : ia;
+                if (g == 0 && i < m) {
+                    s_key[i] = key_of(p[3 * h]);
+                    ahead[(int64_t)t * n + sg.off + i] = make_double2(p[3 * h + 1], p[3 * h + 2]);
+                }
+            }
+        }
+    } else {
+        for (int j = tid; j < d; j += blockDim.x) s_r[j] = Rn[(int64_t)ch * d + j];
+        __syncthreads();
         const int g = tid & 7, pt = tid >> 3;
         for (int base = 0; base < m; base += 32) {
             int i = base + pt;
@@ -169,7 +202,13 @@ __global__ __launch_bounds__(256) void k_level_small(
         if (valid) {
             uint32_t lb = lefts + excl;
             int pos = left ? (int)lb : half + (i - (int)lb);
-            if (pos >= 0 && pos < m) pout[pos] = s_perm[i];  // always true when the select is consistent
+            if (pos >= 0 && pos < m) {  // always true when the select is consistent
+                pout[pos] = s_perm[i];
+                if (LEAD) {  // the row's key at the next level: its projection onto its child
+                    const double2 a = ahead[(int64_t)t * n + sg.off + i];
+                    keys_next[(int64_t)t * n + sg.off + pos] = key_of(left ? a.x : a.y);
+                }
+            }
         }
         lefts += total;
     }
@@ -184,14 +223,17 @@ __global__ __launch_bounds__(256) void k_level_small(
 
 // ================================================================ large segments
 
-template <bool VEC>
+template <bool VEC, bool LEAD>
 __global__ __launch_bounds__(256) void k_proj_chunks(
     const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
     const SegDesc *__restrict__ segs, const ChunkDesc *__restrict__ chunks,
     const int32_t *__restrict__ perm, int64_t n, SelState *__restrict__ state, int nseg,
     int mode,  // 0: final projection -> keys + digit-0 histogram; 1: raw projection of try `tr`
-    int tr, uint64_t *__restrict__ keys, double *__restrict__ praw, uint32_t *__restrict__ hist) {
-    __shared__ __align__(16) float s_r[1024];
+    int tr, uint64_t *__restrict__ keys, double *__restrict__ praw, uint32_t *__restrict__ hist,
+    const LookDesc *__restrict__ look, double2 *__restrict__ ahead) {
+    // the node's direction (binary32); on a lead level it and its children's, as binary64
+    extern __shared__ __align__(16) uint8_t s_dir[];
+    float *s_r = reinterpret_cast<float *>(s_dir);
     __shared__ uint32_t s_hist[kDigitBins];
     const int t = blockIdx.y;
     const ChunkDesc c = chunks[blockIdx.x];
@@ -204,7 +246,36 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
     if (mode == 0)
         for (int b = tid; b < kDigitBins; b += 256) s_hist[b] = 0;
     const int g = tid & 7, pt = tid >> 3;
-    if (d <= 1024) {  // longer directions are read from global memory by the scalar loop below
+    if (LEAD && d <= 1024) {  // lead level: the children's projections from the same read of X
+        const LookDesc lk = look[c.seg];
+        const int ds = (d + 3) & ~3;
+        double *s_rd = reinterpret_cast<double *>(s_dir);
+        for (int j = tid; j < d; j += 256) {
+            s_rd[j] = Rn[j];
+#pragma unroll
+            for (int b = 0; b < 2; b++)  // a leaf child has no direction: project onto zero
+                s_rd[ds * (b + 1) + j] =
+                    lk.child_heap[b] > 0 ? R[((int64_t)t * H + (lk.child_heap[b] - 1)) * (int64_t)d + j] : 0.f;
+        }
+        __syncthreads();
+        for (int base = 0; base < c.len; base += 64) {  // rows base + pt and base + 32 + pt
+            const int ia = base + pt, ib = ia + 32;
+            const int64_t sa = c.start + (ia < c.len ? ia : 0), sb = c.start + (ib < c.len ? ib : 0);
+            double p[6];
+            group8_dot64x3r2<VEC>(X + (int64_t)pp[sa] * d, X + (int64_t)pp[sb] * d, s_rd, ds, d, g, p);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int i = h ? ib : ia;
+                const int64_t s = h ? sb : sa;
+                if (g == 0 && i < c.len) {
+                    uint64_t u = key_of(p[3 * h]);
+                    keys[(int64_t)t * n + s] = u;
+                    ahead[(int64_t)t * n + s] = make_double2(p[3 * h + 1], p[3 * h + 2]);
+                    atomicAdd(&s_hist[(uint32_t)(u >> 53)], 1u);
+                }
+            }
+        }
+    } else if (d <= 1024) {  // longer directions are read from global memory by the scalar loop below
         for (int j = tid; j < d; j += 256) s_r[j] = Rn[j];
         __syncthreads();
         for (int base = 0; base < c.len; base += 32) {
@@ -498,8 +569,13 @@ __global__ __launch_bounds__(256) void k_part_scatter(const SegDesc *__restrict_
                                                       const int32_t *__restrict__ perm_in,
                                                       int32_t *__restrict__ perm_out, int64_t n,
                                                       const SelState *__restrict__ state, int nseg,
-                                                      const uint32_t *__restrict__ lbase) {
+                                                      const uint32_t *__restrict__ lbase,
+                                                      const LookDesc *__restrict__ look,
+                                                      const double2 *__restrict__ ahead,
+                                                      uint64_t *__restrict__ keys_next,
+                                                      uint32_t *__restrict__ hist_next, int nseg_next) {
     __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_hn[2][kDigitBins];  // lead level: digit-0 histograms of the two children
     const int t = blockIdx.y, tid = threadIdx.x;
     const ChunkDesc c = chunks[blockIdx.x];
     const SegDesc sg = segs[c.seg];
@@ -508,6 +584,13 @@ __global__ __launch_bounds__(256) void k_part_scatter(const SegDesc *__restrict_
     uint32_t lefts = lbase[(int64_t)t * nchunk + blockIdx.x];
     const int64_t rel0 = c.start - sg.off;  // chunk position within the segment
     int32_t *pout = perm_out + (int64_t)t * n + sg.off;
+    const bool lead = look != nullptr, hn = lead && hist_next != nullptr;
+    LookDesc lk{{-1, -1}, {0, 0}};
+    if (lead) lk = look[c.seg];
+    if (hn) {
+        for (int b = tid; b < 2 * kDigitBins; b += 256) (&s_hn[0][0])[b] = 0;
+        __syncthreads();
+    }
     for (int base = 0; base < c.len; base += 256) {
         const int i = base + tid;
         const bool valid = i < c.len;
@@ -520,9 +603,26 @@ __global__ __launch_bounds__(256) void k_part_scatter(const SegDesc *__restrict_
             const int64_t lb = (int64_t)lefts + excl;
             const int64_t rel = rel0 + i;
             const int64_t pos = left ? lb : half + (rel - lb);
-            if (pos >= 0 && pos < sg.size) pout[pos] = id;  // always true when the select is consistent
+            if (pos >= 0 && pos < sg.size) {  // always true when the select is consistent
+                pout[pos] = id;
+                if (lead) {  // the row's key at the next level: its projection onto its child
+                    const double2 a = ahead[(int64_t)t * n + s];
+                    const uint64_t u = key_of(left ? a.x : a.y);
+                    keys_next[(int64_t)t * n + sg.off + pos] = u;
+                    if (hn && lk.child_seg[left ? 0 : 1] >= 0) atomicAdd(&s_hn[left ? 0 : 1][(uint32_t)(u >> 53)], 1u);
+                }
+            }
         }
         lefts += total;
+    }
+    if (hn) {
+        __syncthreads();
+        for (int b = 0; b < 2; b++) {
+            if (lk.child_seg[b] < 0) continue;
+            uint32_t *gh = hist_next + ((int64_t)t * nseg_next + lk.child_seg[b]) * kDigitBins;
+            for (int q = tid; q < kDigitBins; q += 256)
+                if (s_hn[b][q]) atomicAdd(&gh[q], s_hn[b][q]);
+        }
     }
 }
 
@@ -728,8 +828,8 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
 // ================================================================ launchers
 
 size_t level_small_lds(int max_m, int d, int n_try) {
-    size_t lds = ((4 * (size_t)max_m + 15) & ~(size_t)15) + 8 * (size_t)max_m + 4 * (size_t)((d + 3) & ~3) +
-                 4 * (256 + 16);
+    size_t lds = ((((4 * (size_t)max_m + 15) & ~(size_t)15) + 8 * (size_t)max_m + 15) & ~(size_t)15) +
+                 3 * 8 * (size_t)((d + 3) & ~3) + 4 * (256 + 16);
     lds = (lds + 7) & ~(size_t)7;
     if (n_try > 1) {
         int P2 = 1;
@@ -742,17 +842,20 @@ size_t level_small_lds(int max_m, int d, int n_try) {
 void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H,
                         int n_try, const SegDesc *segs, int nseg, int max_m, int T,
                         const int32_t *pin, int32_t *pout, int64_t n, double *split,
-                        int32_t *split_idx, int32_t *chosen, int32_t *err) {
+                        int32_t *split_idx, int32_t *chosen, int32_t *err, const LevelLink &lk) {
     const size_t lds = level_small_lds(max_m, d, n_try);
     dim3 grid(nseg, T);
-    if (vec) {
-        hipFuncSetAttribute((const void *)k_level_small<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_level_small<true>, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n,
-                           split, split_idx, chosen, err);
+    auto go = [&](auto kern) {
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n, split, split_idx,
+                           chosen, err, lk.look, lk.ahead, lk.keys_next, lk.keys_in);
+    };
+    if (lk.look) {
+        if (vec) go(k_level_small<true, true>);
+        else go(k_level_small<false, true>);
     } else {
-        hipFuncSetAttribute((const void *)k_level_small<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_level_small<false>, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n,
-                           split, split_idx, chosen, err);
+        if (vec) go(k_level_small<true, false>);
+        else go(k_level_small<false, false>);
     }
     launch_check(s, "k_level_small");
 }
@@ -762,30 +865,42 @@ size_t cand_bytes() { return sizeof(Cand); }
 template <bool VEC>
 static void proj_chunks(hipStream_t s, dim3 gc, const float *X, int d, const float *R, int64_t H, int n_try,
                         const SegDesc *segs, const ChunkDesc *chunks, const int32_t *pin, int64_t n,
-                        const LargeBufs &b, int nseg, int mode, int tr) {
-    hipLaunchKernelGGL(k_proj_chunks<VEC>, gc, dim3(256), 0, s, X, d, R, H, n_try, segs, chunks, pin, n, b.state,
-                       nseg, mode, tr, b.keys, b.praw, b.hist);
+                        const LargeBufs &b, int nseg, int mode, int tr, const LevelLink &lk) {
+    const size_t ds = (size_t)((d + 3) & ~3);
+    const size_t lds = d > 1024 ? 0 : lk.look ? 3 * ds * sizeof(double) : ds * sizeof(float);
+    if (lk.look)
+        hipLaunchKernelGGL((k_proj_chunks<VEC, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,
+                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead);
+    else
+        hipLaunchKernelGGL((k_proj_chunks<VEC, false>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,
+                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead);
     launch_check(s, "k_proj_chunks");
 }
 
 void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H,
                         int n_try, const SegDesc *segs, int nseg, const ChunkDesc *chunks, int nchunk,
                         int T, const int32_t *pin, int32_t *pout, int64_t n, double *split,
-                        int32_t *split_idx, int32_t *chosen, int32_t *err, const LargeBufs &b,
-                        double proj_bytes) {
+                        int32_t *split_idx, int32_t *chosen, int32_t *err, const LargeBufs &b0,
+                        double proj_bytes, const LevelLink &lk) {
     dim3 gs(nseg, T), gc(nchunk, T);
+    LargeBufs b = b0;
+    if (lk.keys_in) {  // fed level: keys and digit-0 histograms come from the level above
+        b.keys = const_cast<uint64_t *>(lk.keys_in);
+        b.hist = lk.hist_in;
+    }
     hipLaunchKernelGGL(k_sel_init, dim3((nseg * T + 255) / 256), dim3(256), 0, s, segs, nseg, T, b.state);
     launch_check(s, "k_sel_init");
     // fill kernels, not memsets: the level may be recorded in a graph
-    fill_u32(b.hist, (int64_t)kDigitBins * nseg * T, 0, s);
+    if (!lk.keys_in) fill_u32(b.hist, (int64_t)kDigitBins * nseg * T, 0, s);
+    if (lk.hist_next) fill_u32(lk.hist_next, (int64_t)kDigitBins * lk.nseg_next * T, 0, s);
     fill_u32(b.cand_cnt, (int64_t)nseg * T, 0, s);
     launch_check(s, "select memsets");
     if (n_try > 1) {
         for (int tr = 0; tr < n_try; tr++) {
             {
                 ProfScope ps(s, "proj_try", proj_bytes, 0);
-                if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr);
-                else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr);
+                if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr, LevelLink{});
+                else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 1, tr, LevelLink{});
             }
             for (int what = 0; what < 2; what++) {
                 hipLaunchKernelGGL(k_chunk_sum, gc, dim3(256), 0, s, chunks, nchunk, segs, b.praw, n, b.state,
@@ -797,10 +912,10 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
             }
         }
     }
-    {
-        ProfScope ps(s, "proj_chunks", proj_bytes, 0);
-        if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0);
-        else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0);
+    if (!lk.keys_in) {
+        ProfScope ps(s, lk.look ? "proj_chunks_x3" : "proj_chunks", proj_bytes, 0);
+        if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0, lk);
+        else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0, lk);
     }
     {
         ProfScope ps(s, "select_passes", 0, 0);
@@ -826,7 +941,7 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
                            b.lcount, err);
         launch_check(s, "k_part_scan");
         hipLaunchKernelGGL(k_part_scatter, gc, dim3(256), 0, s, segs, chunks, nchunk, b.keys, pin, pout, n, b.state,
-                           nseg, b.lcount);
+                           nseg, b.lcount, lk.look, lk.ahead, lk.keys_next, lk.hist_next, lk.nseg_next);
         launch_check(s, "k_part_scatter");
     }
 }
@@ -843,6 +958,171 @@ void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T) {
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_iota, dim3(blocks, T), dim3(256), 0, s, perm, n);
     launch_check(s, "k_iota");
+}
+
+// The same leaf pass with the leaf's rows staged in LDS: X is read once (the two-pass
+// kernel reads it once for the mean and again to centre).  One block per (leaf, tree); the
+// leaf (up to ~130 KB) is loaded with every load of a thread in flight at once, since one
+// block holds the CU's LDS.  The centroid is a fixed-order sum (R row classes per column,
+// then the classes in order), so it is reproducible.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(512) void k_leaf_staged(
+    const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
+    const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
+    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
+    extern __shared__ __align__(16) float s_rows[];  // m rows of ds floats, centroid (ds), member ids (m)
+    __shared__ float s_part[512];
+    const int t = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NT = 512, NW = NT / 64, KV = 16;
+    const LeafDesc lf = leaves[blockIdx.x];
+    const int m = lf.size;
+    const int ds = (d + 3) & ~3;
+    float *s_mu = s_rows + (size_t)m * ds;
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + ds);
+    const int32_t *pp = perm + (int64_t)t * n + lf.off;
+    for (int i = tid; i < m; i += NT) {
+        const int id = pp[i];
+        s_id[i] = id;
+        leaf_of[(int64_t)t * n + id] = lf.heap;
+    }
+    __syncthreads();
+    if constexpr (VEC) {  // 16-byte loads, KV of them in flight per thread
+        const int q = d >> 2, tot = m * q;
+        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
+            float4 r[KV];
+#pragma unroll
+            for (int k = 0; k < KV; k++) {  // past the end: reload the last element, not stored
+                const int v = min(v0 + k * NT + tid, tot - 1);
+                const int i = v / q, c = v - i * q;
+                r[k] = reinterpret_cast<const float4 *>(X + (int64_t)s_id[i] * d)[c];
+            }
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = v0 + k * NT + tid;
+                const int i = v / q, c = v - i * q;
+                if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * ds)[c] = r[k];
+            }
+        }
+    } else {
+        const int tot = m * d;
+        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
+            float r[KV];
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = min(v0 + k * NT + tid, tot - 1);
+                const int i = v / d, j = v - i * d;
+                r[k] = X[(int64_t)s_id[i] * d + j];
+            }
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = v0 + k * NT + tid;
+                const int i = v / d, j = v - i * d;
+                if (v < tot) s_rows[(size_t)i * ds + j] = r[k];
+            }
+        }
+    }
+    __syncthreads();
+    if (ds <= NT) {  // R row classes per column: class g sums rows g, g+R, ... (two chains)
+        const int R = NT / ds, g = tid / ds, j = tid - g * ds;
+        if (g < R) {
+            float a0 = 0.f, a1 = 0.f;
+            if (j < d) {
+                int i = g;
+                for (; i + R < m; i += 2 * R) {
+                    a0 += s_rows[(size_t)i * ds + j];
+                    a1 += s_rows[(size_t)(i + R) * ds + j];
+                }
+                if (i < m) a0 += s_rows[(size_t)i * ds + j];
+            }
+            s_part[tid] = a0 + a1;
+        }
+        __syncthreads();
+        if (tid < ds) {
+            float sum = 0.f;
+            for (int c = 0; c < R; c++) sum += s_part[c * ds + tid];
+            const float mu = tid < d ? sum / (float)m : 0.f;
+            s_mu[tid] = mu;
+            if (tid < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + tid] = mu;
+        }
+    } else {
+        for (int j = tid; j < ds; j += NT) {
+            float acc = 0.f;
+            if (j < d)
+                for (int i = 0; i < m; i++) acc += s_rows[(size_t)i * ds + j];
+            const float mu = j < d ? acc / (float)m : 0.f;
+            s_mu[j] = mu;
+            if (j < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + j] = mu;
+        }
+    }
+    __syncthreads();
+    // centred copy and norms: eight lanes per row, each lane four consecutive columns at a
+    // time, so a wave has eight rows in flight and reduces each over three shuffle steps
+    const int sub = lane & 7, grp = lane >> 3;
+    for (int i0 = wv * 8; i0 < m; i0 += NW * 8) {
+        const int i = i0 + grp;
+        const bool live = i < m;
+        const int ir = live ? i : m - 1;
+        T *out = Xc + ((int64_t)t * n + lf.off + ir) * dp;
+        float na = 0.f, ra = 0.f;
+        bool over = false;
+        for (int c = 4 * sub; c < dp; c += 32) {
+            float a[4];
+            if (c < ds) {
+                const float4 x = *reinterpret_cast<const float4 *>(s_rows + (size_t)ir * ds + c);
+                const float4 u = *reinterpret_cast<const float4 *>(s_mu + c);
+                a[0] = c + 0 < d ? x.x - u.x : 0.f;
+                a[1] = c + 1 < d ? x.y - u.y : 0.f;
+                a[2] = c + 2 < d ? x.z - u.z : 0.f;
+                a[3] = c + 3 < d ? x.w - u.w : 0.f;
+            } else {
+                a[0] = a[1] = a[2] = a[3] = 0.f;
+            }
+            T qv[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                over |= fabsf(a[e]) > range_max;
+                qv[e] = to_tile<T>(a[e]);
+                const float qf = (float)qv[e];
+                na = __builtin_fmaf(qf, qf, na);
+                ra = __builtin_fmaf(a[e], a[e], ra);
+            }
+            if (live) {
+                if constexpr (sizeof(T) == 4) {
+                    *reinterpret_cast<float4 *>(out + c) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+                } else {
+                    uint2 w;
+                    __builtin_memcpy(&w, qv, sizeof(w));
+                    *reinterpret_cast<uint2 *>(out + c) = w;
+                }
+            }
+        }
+        for (int o = 4; o > 0; o >>= 1) {
+            na += __shfl_xor(na, o, 64);
+            ra += __shfl_xor(ra, o, 64);
+        }
+        const uint64_t ov = (__ballot(over) >> (8 * grp)) & 0xffu;
+        if (live && sub == 0) nrm[(int64_t)t * n + lf.off + i] = make_float2(na, ov ? INFINITY : sqrtf(ra));
+    }
+}
+
+size_t leaf_staged_lds(int d, int max_leaf) {  // dynamic part; 2 KB of static LDS come on top
+    return sizeof(float) * (size_t)((d + 3) & ~3) * ((size_t)max_leaf + 1) + sizeof(int32_t) * (size_t)max_leaf;
+}
+
+template <typename T>
+static void leaf_staged(hipStream_t s, dim3 grid, size_t lds, bool vec, const float *X, int d, int dp,
+                        const LeafDesc *leaves, int nleaf, const int32_t *perm, int64_t n, int32_t *leaf_of,
+                        float *centroid, void *Xc, float2 *nrm, float range_max) {
+    if (vec) {
+        hipFuncSetAttribute((const void *)k_leaf_staged<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_leaf_staged<T, true>), grid, dim3(512), lds, s, X, d, dp, leaves, nleaf, perm, n, leaf_of,
+                           centroid, (T *)Xc, nrm, range_max);
+    } else {
+        hipFuncSetAttribute((const void *)k_leaf_staged<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_leaf_staged<T, false>), grid, dim3(512), lds, s, X, d, dp, leaves, nleaf, perm, n,
+                           leaf_of, centroid, (T *)Xc, nrm, range_max);
+    }
+    launch_check(s, "k_leaf_staged");
 }
 
 template <typename T>
@@ -863,6 +1143,18 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit) {
     dim3 grid(nleaf, T);
+    const size_t staged = leaf_staged_lds(d, max_leaf);
+    if (staged + 2048 <= (size_t)lds_limit) {  // the leaf's rows fit in LDS: read X once
+        const bool vec = (d % 4) == 0;
+        if (prec == RPF_DIST_BF16)
+            leaf_staged<__bf16>(s, grid, staged, vec, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+        else if (prec == RPF_DIST_FP16)
+            leaf_staged<_Float16>(s, grid, staged, vec, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm,
+                                  60000.f);
+        else
+            leaf_staged<float>(s, grid, staged, vec, X, d, dp, leaves, nleaf, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f);
+        return;
+    }
     const int ids = leaf_finalize_lds(dp, max_leaf, true) <= (size_t)lds_limit ? 1 : 0;
     const size_t lds = leaf_finalize_lds(dp, max_leaf, ids != 0);
     if (prec == RPF_DIST_BF16)

@@ -20,11 +20,13 @@ size_t cand_bytes();
 size_t level_small_lds(int max_m, int d, int n_try);
 void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, int n_try,
                         const SegDesc *segs, int nseg, int max_m, int T, const int32_t *pin, int32_t *pout,
-                        int64_t n, double *split, int32_t *split_idx, int32_t *chosen, int32_t *err);
+                        int64_t n, double *split, int32_t *split_idx, int32_t *chosen, int32_t *err,
+                        const LevelLink &lk);
 void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, int n_try,
                         const SegDesc *segs, int nseg, const ChunkDesc *chunks, int nchunk, int T,
                         const int32_t *pin, int32_t *pout, int64_t n, double *split, int32_t *split_idx,
-                        int32_t *chosen, int32_t *err, const LargeBufs &b, double proj_bytes);
+                        int32_t *chosen, int32_t *err, const LargeBufs &b, double proj_bytes,
+                        const LevelLink &lk);
 void launch_copy_segments(hipStream_t s, const LeafDesc *segs, int nseg, int T, const int32_t *in, int32_t *out,
                           int64_t n);
 void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T);
@@ -162,8 +164,10 @@ struct LevelPlan {
     std::vector<SegDesc> segs;     // internal nodes
     std::vector<ChunkDesc> chunks; // multi-block path
     std::vector<LeafDesc> copy;    // leaves formed at or before this level (carried over)
+    std::vector<LookDesc> look;    // per internal node: its children at the next level
     int max_m = 0;
     bool large = false;
+    bool lead = false, fed = false;  // linked pair: the lead also makes the fed level's keys
     int64_t seg_off = 0, chunk_off = 0, copy_off = 0;  // offsets into the device descriptor arrays
 };
 }  // namespace rpf
@@ -192,6 +196,7 @@ struct rpf_forest {
     ChunkDesc *d_chunks = nullptr;
     LeafDesc *d_leaves = nullptr;
     LeafDesc *d_copy = nullptr;
+    LookDesc *d_look = nullptr;  // per internal node of every level, indexed like d_segs
     TileJob *d_jobs = nullptr;   // all-points tile jobs
     int64_t n_jobs_tree = 0;     // jobs per tree
     int job_mb = 8;
@@ -277,7 +282,7 @@ rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
-                    f->d_copy, f->d_jobs, f->stats, f->d_batch_off};
+                    f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off};
     for (void *p : ptrs) cache_free(p, nullptr);
     for (void *p : f->tmps) cache_free(p, nullptr);
     f->tmps.clear();
@@ -354,9 +359,12 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         std::vector<LeafDesc> formed;
         for (int l = 0; l <= L; l++) {
             std::vector<Node> next;
-            for (auto &nd : cur) {
+            std::vector<int32_t> node_seg(cur.size(), -1);  // internal node index of each node of `cur`
+            for (size_t q = 0; q < cur.size(); q++) {
+                const Node &nd = cur[q];
                 const rpf_batch_entry &r = roots[nd.root];
                 if (nd.size > n0 && l < r.depth) {
+                    node_seg[q] = (int32_t)levels[l].segs.size();
                     levels[l].segs.push_back(SegDesc{nd.off, (int32_t)nd.size, (int32_t)(r.heap_base + nd.heap), 0, 0});
                     levels[l].max_m = std::max<int>(levels[l].max_m, (int)nd.size);
                     next.push_back({2 * nd.heap, nd.off, nd.size / 2, nd.root});
@@ -364,6 +372,16 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
                 } else {
                     formed.push_back(LeafDesc{nd.off, (int32_t)nd.size, (int32_t)(r.leaf_heap_base + nd.heap)});
                 }
+            }
+            if (l > 0 && l <= L) {  // children of level l - 1's nodes: pushed in pairs, in node order
+                auto &up = levels[l - 1];
+                up.look.resize(up.segs.size());
+                for (size_t k = 0; k < up.segs.size(); k++)
+                    for (int b = 0; b < 2; b++) {
+                        const int32_t cs = l < L ? node_seg[2 * k + b] : -1;
+                        up.look[k].child_seg[b] = cs;
+                        up.look[k].child_heap[b] = cs >= 0 ? levels[l].segs[cs].heap : 0;
+                    }
             }
             if (l < L) levels[l].copy = formed;  // leaves carried into this level's output
             cur.swap(next);
@@ -399,6 +417,18 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         ncopy_tot += lv.copy.size();
     }
 
+    // ---- level links: with one direction per node, pair each level with the next (the lead
+    // projects onto the children too); a multi-block level is never fed by a one-block one
+    bool any_link = false, any_large_fed = false;
+    if (n_try == 1 && d <= 1024)
+        for (int l = 0; l + 1 < L; l++) {
+            LevelPlan &a = levels[l], &b = levels[l + 1];
+            if (a.fed || a.segs.empty() || b.segs.empty() || (b.large && !a.large)) continue;
+            a.lead = b.fed = true;
+            any_link = true;
+            any_large_fed |= b.large;
+        }
+
     // ---- memory plan
     const int prec = p->dist_prec;
     const int dp = (d + 7) & ~7;
@@ -422,6 +452,8 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         tmp_bytes += (uint64_t)T * max_seg_large * (sizeof(SelState) + 4 * kDigitBins + cand_bytes() * kCandCap + 4);
         tmp_bytes += (uint64_t)T * max_chunk_large * (4 + 8);
     }
+    if (any_link) tmp_bytes += (uint64_t)T * n * (16 + 8);                    // ahead, keys2
+    if (any_large_fed) tmp_bytes += (uint64_t)T * max_seg_large * 4 * kDigitBins;  // hist2
     if (p->mem_budget_bytes && bytes + tmp_bytes > p->mem_budget_bytes)
         return fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(bytes + tmp_bytes) +
                                     " bytes, over mem_budget_bytes");
@@ -469,13 +501,17 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (nchunk_tot) RPF_ALLOC(f->d_chunks, nchunk_tot * sizeof(ChunkDesc));
     RPF_ALLOC(f->d_leaves, nleaf * sizeof(LeafDesc));
     if (ncopy_tot) RPF_ALLOC(f->d_copy, ncopy_tot * sizeof(LeafDesc));
+    if (nseg_tot && any_link) RPF_ALLOC(f->d_look, nseg_tot * sizeof(LookDesc));
 
     // ---- descriptors (host copies stay alive until the synchronisation below)
     std::vector<SegDesc> all_segs;
     std::vector<ChunkDesc> all_chunks;
     std::vector<LeafDesc> all_copy;
+    std::vector<LookDesc> all_look;
     for (auto &lv : levels) {
         all_segs.insert(all_segs.end(), lv.segs.begin(), lv.segs.end());
+        lv.look.resize(lv.segs.size(), LookDesc{{-1, -1}, {0, 0}});
+        all_look.insert(all_look.end(), lv.look.begin(), lv.look.end());
         all_chunks.insert(all_chunks.end(), lv.chunks.begin(), lv.chunks.end());
         all_copy.insert(all_copy.end(), lv.copy.begin(), lv.copy.end());
     }
@@ -490,6 +526,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (nchunk_tot)
         hipMemcpyAsync(f->d_chunks, all_chunks.data(), nchunk_tot * sizeof(ChunkDesc), hipMemcpyHostToDevice, s);
     if (ncopy_tot) hipMemcpyAsync(f->d_copy, all_copy.data(), ncopy_tot * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
+    if (f->d_look) hipMemcpyAsync(f->d_look, all_look.data(), nseg_tot * sizeof(LookDesc), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
     if (H) hipMemcpyAsync(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice, s);
@@ -517,6 +554,11 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         ok &= talloc((void **)&lb.lcount, (size_t)T * max_chunk_large * 4);
         ok &= talloc((void **)&lb.part, (size_t)T * max_chunk_large * 8);
     }
+    if (any_link) {
+        ok &= talloc((void **)&lb.ahead, (size_t)T * n * 16);
+        ok &= talloc((void **)&lb.keys2, (size_t)T * n * 8);
+    }
+    if (any_large_fed) ok &= talloc((void **)&lb.hist2, (size_t)T * max_seg_large * 4 * kDigitBins);
     if (!ok) {
         fail(RPF_ENOMEM, "rpf_build: temporary allocation failed");
         return bail(RPF_ENOMEM);
@@ -581,16 +623,33 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
         launch_check(s, "copy_segments");
         int64_t members = 0;
         for (auto &sg : lv.segs) members += sg.size;
-        const double proj_bytes = (double)T * members * (4.0 * d + 4 + 8);
+        LevelLink lk;
+        if (lv.lead) {
+            lk.look = f->d_look + lv.seg_off;
+            lk.ahead = f->lb.ahead;
+            lk.keys_next = f->lb.keys2;
+            if (f->levels[l + 1].large) {
+                lk.hist_next = f->lb.hist2;
+                lk.nseg_next = (int)f->levels[l + 1].segs.size();
+            }
+        }
+        if (lv.fed) {
+            lk.keys_in = f->lb.keys2;
+            if (lv.large) lk.hist_in = f->lb.hist2;
+        }
+        // algorithmic bytes: X rows (none on a fed level), ids and keys, the children's
+        // projections out and back on a lead level
+        const double row_bytes = (lv.fed ? 8.0 : 4.0 * d + 8) + 4 + (lv.lead ? 16.0 : 0.0);
+        const double proj_bytes = (double)T * members * (4.0 * d + 4 + 8 + (lv.lead ? 16.0 : 0.0));
         if (!lv.large) {
-            ProfScope ps(s, "level_small", (double)T * members * (4.0 * d + 8), 0);
+            ProfScope ps(s, "level_small", (double)T * members * row_bytes, 0);
             launch_level_small(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
-                               lv.max_m, T, pin, pout, n, f->split, f->split_idx, f->chosen, f->err);
+                               lv.max_m, T, pin, pout, n, f->split, f->split_idx, f->chosen, f->err, lk);
             launch_check(s, "level_small");
         } else {
             launch_level_large(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),
                                f->d_chunks + lv.chunk_off, (int)lv.chunks.size(), T, pin, pout, n, f->split,
-                               f->split_idx, f->chosen, f->err, f->lb, proj_bytes);
+                               f->split_idx, f->chosen, f->err, f->lb, proj_bytes, lk);
             launch_check(s, "level_large");
         }
         cur ^= 1;

@@ -81,8 +81,30 @@ struct Cand {          // a key gathered for the in-block median select
     uint32_t pad;
 };
 
-struct LargeBufs {     // temporaries of the multi-block level path
+struct LookDesc {     // the children of one internal node, for projections made a level ahead
+    int32_t child_seg[2];   // index among the next level's internal nodes, -1 for a leaf
+    int32_t child_heap[2];  // heap ids of the children that are internal nodes, else 0
+};
+
+// Two levels from one read of X (one direction per node): the lead level projects every row
+// onto its node's direction and onto both children's, and its partition hands each row the
+// projection onto the child it moves into, as that level's key at its new position; the fed
+// level below starts from those keys and never reads X.
+struct LevelLink {
+    const LookDesc *look = nullptr;   // lead: per internal node of the level (null: not a lead)
+    double2 *ahead = nullptr;         // lead: [T][n] projections onto the two children, by position
+    uint64_t *keys_next = nullptr;    // lead: [T][n] keys of the fed level, by its positions
+    uint32_t *hist_next = nullptr;    // lead above a multi-block level: its digit-0 histograms
+    int nseg_next = 0;
+    const uint64_t *keys_in = nullptr;  // fed: keys made by the lead (null: project)
+    uint32_t *hist_in = nullptr;        // fed multi-block level: histograms made by the lead
+};
+
+struct LargeBufs {     // temporaries of the multi-block level path (and of the level links)
     uint64_t *keys;
+    uint64_t *keys2;      // keys made one level ahead
+    uint32_t *hist2;      // their digit-0 histograms
+    double2 *ahead;       // projections onto the children, by position
     double *praw;
     SelState *state;
     uint32_t *hist;
@@ -224,22 +246,24 @@ __device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &e
 template <bool VEC>
 __device__ inline double group8_dot64(const float *__restrict__ x, const float *__restrict__ r,
                                       int d, int g) {
+    // the product of two binary32 values is exact in binary64, so fma(x, r, s) rounds once,
+    // exactly as s + x * r does
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (VEC) {
         for (int j = 4 * g; j < d; j += 32) {
             float4 xv = *reinterpret_cast<const float4 *>(x + j);
             float4 rv = *reinterpret_cast<const float4 *>(r + j);
-            s0 = s0 + (double)xv.x * (double)rv.x;
-            s1 = s1 + (double)xv.y * (double)rv.y;
-            s2 = s2 + (double)xv.z * (double)rv.z;
-            s3 = s3 + (double)xv.w * (double)rv.w;
+            s0 = __builtin_fma((double)xv.x, (double)rv.x, s0);
+            s1 = __builtin_fma((double)xv.y, (double)rv.y, s1);
+            s2 = __builtin_fma((double)xv.z, (double)rv.z, s2);
+            s3 = __builtin_fma((double)xv.w, (double)rv.w, s3);
         }
     } else {
         for (int j = 4 * g; j < d; j += 32) {
-            s0 = s0 + (double)x[j] * (double)r[j];
-            if (j + 1 < d) s1 = s1 + (double)x[j + 1] * (double)r[j + 1];
-            if (j + 2 < d) s2 = s2 + (double)x[j + 2] * (double)r[j + 2];
-            if (j + 3 < d) s3 = s3 + (double)x[j + 3] * (double)r[j + 3];
+            s0 = __builtin_fma((double)x[j], (double)r[j], s0);
+            if (j + 1 < d) s1 = __builtin_fma((double)x[j + 1], (double)r[j + 1], s1);
+            if (j + 2 < d) s2 = __builtin_fma((double)x[j + 2], (double)r[j + 2], s2);
+            if (j + 3 < d) s3 = __builtin_fma((double)x[j + 3], (double)r[j + 3], s3);
         }
     }
     double v = (s0 + s1) + (s2 + s3);
@@ -247,6 +271,62 @@ __device__ inline double group8_dot64(const float *__restrict__ x, const float *
     v = v + shfl_xor_d(v, 2);
     v = v + shfl_xor_d(v, 4);
     return v + 0.0;
+}
+
+// Projections of two rows xa, xb onto three directions r, r + rs, r + 2 rs (binary32 values
+// held as binary64, converted once per block rather than once per row) from one read of each
+// row, every direction value read once for both rows; each projection is computed exactly as
+// group8_dot64 computes it.  p[0..2]: row xa, p[3..5]: row xb.
+template <bool VEC>
+__device__ inline void group8_dot64x3r2(const float *__restrict__ xa, const float *__restrict__ xb,
+                                        const double *__restrict__ r, int rs, int d, int g, double p[6]) {
+    double s[6][4];
+#pragma unroll
+    for (int k = 0; k < 6; k++) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0.0;
+    if (VEC) {
+        for (int j = 4 * g; j < d; j += 32) {
+            const float4 va = *reinterpret_cast<const float4 *>(xa + j);
+            const float4 vb = *reinterpret_cast<const float4 *>(xb + j);
+            const double a0 = va.x, a1 = va.y, a2 = va.z, a3 = va.w;
+            const double b0 = vb.x, b1 = vb.y, b2 = vb.z, b3 = vb.w;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double2 ra = *reinterpret_cast<const double2 *>(r + k * rs + j);
+                const double2 rb = *reinterpret_cast<const double2 *>(r + k * rs + j + 2);
+                s[k][0] = __builtin_fma(a0, ra.x, s[k][0]);
+                s[k][1] = __builtin_fma(a1, ra.y, s[k][1]);
+                s[k][2] = __builtin_fma(a2, rb.x, s[k][2]);
+                s[k][3] = __builtin_fma(a3, rb.y, s[k][3]);
+                s[k + 3][0] = __builtin_fma(b0, ra.x, s[k + 3][0]);
+                s[k + 3][1] = __builtin_fma(b1, ra.y, s[k + 3][1]);
+                s[k + 3][2] = __builtin_fma(b2, rb.x, s[k + 3][2]);
+                s[k + 3][3] = __builtin_fma(b3, rb.y, s[k + 3][3]);
+            }
+        }
+    } else {
+        for (int j = 4 * g; j < d; j += 32) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (e == 0 || j + e < d) {
+                    const double ae = (double)xa[j + e], be = (double)xb[j + e];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const double rv = r[k * rs + j + e];
+                        s[k][e] = __builtin_fma(ae, rv, s[k][e]);
+                        s[k + 3][e] = __builtin_fma(be, rv, s[k + 3][e]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double w = (s[k][0] + s[k][1]) + (s[k][2] + s[k][3]);
+        w = w + shfl_xor_d(w, 1);
+        w = w + shfl_xor_d(w, 2);
+        w = w + shfl_xor_d(w, 4);
+        p[k] = w + 0.0;
+    }
 }
 
 template <bool VEC>
