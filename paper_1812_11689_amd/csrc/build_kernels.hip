@@ -960,68 +960,17 @@ void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T) {
     launch_check(s, "k_iota");
 }
 
-// The same leaf pass with the leaf's rows staged in LDS: X is read once (the two-pass
-// kernel reads it once for the mean and again to centre).  One block per (leaf, tree); the
-// leaf (up to ~130 KB) is loaded with every load of a thread in flight at once, since one
-// block holds the CU's LDS.  The centroid is a fixed-order sum (R row classes per column,
-// then the classes in order), so it is reproducible.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(512) void k_leaf_staged(
-    const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
-    const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
-    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
-    extern __shared__ __align__(16) float s_rows[];  // m rows of ds floats, centroid (ds), member ids (m)
-    __shared__ float s_part[512];
-    const int t = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    constexpr int NT = 512, NW = NT / 64, KV = 16;
-    const LeafDesc lf = leaves[blockIdx.x];
-    const int m = lf.size;
-    const int ds = (d + 3) & ~3;
-    float *s_mu = s_rows + (size_t)m * ds;
-    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + ds);
-    const int32_t *pp = perm + (int64_t)t * n + lf.off;
-    for (int i = tid; i < m; i += NT) {
-        const int id = pp[i];
-        s_id[i] = id;
-        leaf_of[(int64_t)t * n + id] = lf.heap;
-    }
-    __syncthreads();
-    if constexpr (VEC) {  // 16-byte loads, KV of them in flight per thread
-        const int q = d >> 2, tot = m * q;
-        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
-            float4 r[KV];
-#pragma unroll
-            for (int k = 0; k < KV; k++) {  // past the end: reload the last element, not stored
-                const int v = min(v0 + k * NT + tid, tot - 1);
-                const int i = v / q, c = v - i * q;
-                r[k] = reinterpret_cast<const float4 *>(X + (int64_t)s_id[i] * d)[c];
-            }
-#pragma unroll
-            for (int k = 0; k < KV; k++) {
-                const int v = v0 + k * NT + tid;
-                const int i = v / q, c = v - i * q;
-                if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * ds)[c] = r[k];
-            }
-        }
-    } else {
-        const int tot = m * d;
-        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
-            float r[KV];
-#pragma unroll
-            for (int k = 0; k < KV; k++) {
-                const int v = min(v0 + k * NT + tid, tot - 1);
-                const int i = v / d, j = v - i * d;
-                r[k] = X[(int64_t)s_id[i] * d + j];
-            }
-#pragma unroll
-            for (int k = 0; k < KV; k++) {
-                const int v = v0 + k * NT + tid;
-                const int i = v / d, j = v - i * d;
-                if (v < tot) s_rows[(size_t)i * ds + j] = r[k];
-            }
-        }
-    }
-    __syncthreads();
+// Mean and centred copy of one leaf whose m rows (stride ds floats) are in LDS, by a block of
+// 512 threads: the centroid is a fixed-order sum (R row classes per column, then the classes
+// in order), so it is reproducible; then eight lanes per row write the centred row, four
+// consecutive columns at a time, and its two norms.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void leaf_centre_staged(const float *s_rows, float *s_mu, float *s_part, int m, int d, int ds,
+                                          int dp, int t, int leaf, int nleaf, const LeafDesc &lf, int64_t n,
+                                          float *__restrict__ centroid, T *__restrict__ Xc,
+                                          float2 *__restrict__ nrm, float range_max) {
+    constexpr int NT = 512, NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (ds <= NT) {  // R row classes per column: class g sums rows g, g+R, ... (two chains)
         const int R = NT / ds, g = tid / ds, j = tid - g * ds;
         if (g < R) {
@@ -1042,7 +991,7 @@ __global__ __launch_bounds__(512) void k_leaf_staged(
             for (int c = 0; c < R; c++) sum += s_part[c * ds + tid];
             const float mu = tid < d ? sum / (float)m : 0.f;
             s_mu[tid] = mu;
-            if (tid < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + tid] = mu;
+            if (tid < d) centroid[((int64_t)t * nleaf + leaf) * d + tid] = mu;
         }
     } else {
         for (int j = tid; j < ds; j += NT) {
@@ -1051,7 +1000,7 @@ __global__ __launch_bounds__(512) void k_leaf_staged(
                 for (int i = 0; i < m; i++) acc += s_rows[(size_t)i * ds + j];
             const float mu = j < d ? acc / (float)m : 0.f;
             s_mu[j] = mu;
-            if (j < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + j] = mu;
+            if (j < d) centroid[((int64_t)t * nleaf + leaf) * d + j] = mu;
         }
     }
     __syncthreads();
@@ -1105,6 +1054,147 @@ __global__ __launch_bounds__(512) void k_leaf_staged(
     }
 }
 
+// The same leaf pass with the leaf's rows staged in LDS: X is read once (the two-pass
+// kernel reads it once for the mean and again to centre).  One block per (leaf, tree); the
+// leaf (up to ~130 KB) is loaded with every load of a thread in flight at once, since one
+// block holds the CU's LDS.  The centroid is a fixed-order sum (R row classes per column,
+// then the classes in order), so it is reproducible.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(512) void k_leaf_staged(
+    const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf,
+    const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
+    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max) {
+    extern __shared__ __align__(16) float s_rows[];  // m rows of ds floats, centroid (ds), member ids (m)
+    __shared__ float s_part[512];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    constexpr int NT = 512, KV = 16;
+    const LeafDesc lf = leaves[blockIdx.x];
+    const int m = lf.size;
+    const int ds = (d + 3) & ~3;
+    float *s_mu = s_rows + (size_t)m * ds;
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + ds);
+    const int32_t *pp = perm + (int64_t)t * n + lf.off;
+    for (int i = tid; i < m; i += NT) {
+        const int id = pp[i];
+        s_id[i] = id;
+        leaf_of[(int64_t)t * n + id] = lf.heap;
+    }
+    __syncthreads();
+    if constexpr (VEC) {  // 16-byte loads, KV of them in flight per thread
+        const int q = d >> 2, tot = m * q;
+        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
+            float4 r[KV];
+#pragma unroll
+            for (int k = 0; k < KV; k++) {  // past the end: reload the last element, not stored
+                const int v = min(v0 + k * NT + tid, tot - 1);
+                const int i = v / q, c = v - i * q;
+                r[k] = reinterpret_cast<const float4 *>(X + (int64_t)s_id[i] * d)[c];
+            }
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = v0 + k * NT + tid;
+                const int i = v / q, c = v - i * q;
+                if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * ds)[c] = r[k];
+            }
+        }
+    } else {
+        const int tot = m * d;
+        for (int v0 = 0; v0 < tot; v0 += NT * KV) {
+            float r[KV];
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = min(v0 + k * NT + tid, tot - 1);
+                const int i = v / d, j = v - i * d;
+                r[k] = X[(int64_t)s_id[i] * d + j];
+            }
+#pragma unroll
+            for (int k = 0; k < KV; k++) {
+                const int v = v0 + k * NT + tid;
+                const int i = v / d, j = v - i * d;
+                if (v < tot) s_rows[(size_t)i * ds + j] = r[k];
+            }
+        }
+    }
+    __syncthreads();
+    leaf_centre_staged<T>(s_rows, s_mu, s_part, m, d, ds, dp, t, blockIdx.x, nleaf, lf, n, centroid, Xc, nrm,
+                          range_max);
+}
+
+// The staged leaf pass as a software pipeline: each block (one per CU: a leaf fills its LDS)
+// walks the (tree, leaf) items w = blockIdx.x, + gridDim.x, ...; while it centres and writes
+// item w from LDS, the rows of the next item are in flight into registers and the member ids
+// of the one after are in flight too.  Needs d % 4 == 0, every leaf at most 512 members and
+// at most 512 * 16 row quarters.
+template <typename T>
+__global__ __launch_bounds__(512) void k_leaf_pipe(
+    const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf, int ntree,
+    const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
+    float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max, int max_leaf) {
+    extern __shared__ __align__(16) float s_rows[];  // max_leaf rows of d floats, centroid (d), ids (max_leaf)
+    __shared__ float s_part[512];
+    constexpr int NT = 512, KV = 16;
+    const int tid = threadIdx.x, q = d >> 2, G = gridDim.x;
+    const int items = nleaf * ntree;
+    float *s_mu = s_rows + (size_t)max_leaf * d;
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + d);
+    float r0[KV], r1[KV], r2[KV], r3[KV];  // the next item's row quarters (scalars stay in registers)
+    // item w -> tree w / nleaf, leaf w % nleaf: neighbouring blocks take neighbouring leaves
+    auto id_of = [&](int w) -> int32_t {  // member tid of item w (0 past its end)
+        if (w >= items) return 0;
+        const int t = w / nleaf;
+        const LeafDesc lf = leaves[w - t * nleaf];
+        return tid < lf.size ? perm[(int64_t)t * n + lf.off + tid] : 0;
+    };
+    auto stage_ids = [&](int w, int32_t id) {  // ids of item w into LDS, and its leaf_of entries
+        if (w >= items) return;
+        const int t = w / nleaf;
+        const LeafDesc lf = leaves[w - t * nleaf];
+        if (tid < lf.size) {
+            s_id[tid] = id;
+            leaf_of[(int64_t)t * n + id] = lf.heap;
+        }
+    };
+    // rows of item w into registers (its ids in LDS); past the end of the leaf the last element
+    // is loaded again and not stored
+#define RPF_ISSUE_ROWS(W)                                                                       \
+    {                                                                                           \
+        const bool ok_ = (W) < items;  /* past the last item: row 0, never stored */            \
+        const int tw_ = ok_ ? (W) / nleaf : 0;                                                  \
+        const int tot_ = ok_ ? leaves[(W) - tw_ * nleaf].size * q : 1;                          \
+        _Pragma("unroll") for (int k = 0; k < KV; k++) {                                        \
+            const int v = min(k * NT + tid, tot_ - 1);                                          \
+            const int i = v / q, c = v - i * q;                                                 \
+            const int64_t row = ok_ ? s_id[i] : 0;                                              \
+            const float4 x_ = reinterpret_cast<const float4 *>(X + row * d)[c];                 \
+            r0[k] = x_.x; r1[k] = x_.y; r2[k] = x_.z; r3[k] = x_.w;                             \
+        }                                                                                       \
+    }
+    int w = blockIdx.x;
+    stage_ids(w, id_of(w));
+    __syncthreads();
+    RPF_ISSUE_ROWS(w)
+    int32_t idn = id_of(w + G);
+    for (; w < items; w += G) {
+        const int t = w / nleaf, leaf = w - t * nleaf;
+        const LeafDesc lf = leaves[leaf];
+        const int m = lf.size, tot = m * q;
+        __syncthreads();  // the previous item is done with s_rows and s_id
+#pragma unroll
+        for (int k = 0; k < KV; k++) {
+            const int v = k * NT + tid;
+            const int i = v / q, c = v - i * q;
+            if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * d)[c] = make_float4(r0[k], r1[k], r2[k], r3[k]);
+        }
+        stage_ids(w + G, idn);
+        __syncthreads();
+        RPF_ISSUE_ROWS(w + G)  // in flight while item w is centred
+        idn = id_of(w + 2 * G);
+        leaf_centre_staged<T>(s_rows, s_mu, s_part, m, d, d, dp, t, leaf, nleaf, lf, n, centroid, Xc, nrm,
+                              range_max);
+    }
+#undef RPF_ISSUE_ROWS
+}
+
 size_t leaf_staged_lds(int d, int max_leaf) {  // dynamic part; 2 KB of static LDS come on top
     return sizeof(float) * (size_t)((d + 3) & ~3) * ((size_t)max_leaf + 1) + sizeof(int32_t) * (size_t)max_leaf;
 }
@@ -1126,6 +1216,22 @@ static void leaf_staged(hipStream_t s, dim3 grid, size_t lds, bool vec, const fl
 }
 
 template <typename T>
+static void leaf_pipe(hipStream_t s, size_t lds, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                      int ntree, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid, void *Xc,
+                      float2 *nrm, float range_max, int max_leaf) {
+    hipFuncSetAttribute((const void *)k_leaf_pipe<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_leaf_pipe<T>, 512, lds);
+    const int64_t items = (int64_t)nleaf * ntree;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)std::max(cus, 1) * std::max(per, 1)));
+    hipLaunchKernelGGL(k_leaf_pipe<T>, dim3(grid), dim3(512), lds, s, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of,
+                       centroid, (T *)Xc, nrm, range_max, max_leaf);
+    launch_check(s, "k_leaf_pipe");
+}
+
+template <typename T>
 static void leaf_finalize(hipStream_t s, dim3 grid, size_t lds, const float *X, int d, int dp,
                           const LeafDesc *leaves, int nleaf, const int32_t *perm, int64_t n, int32_t *leaf_of,
                           float *centroid, void *Xc, float2 *nrm, float range_max, int ids_in_lds) {
@@ -1143,6 +1249,20 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit) {
     dim3 grid(nleaf, T);
+    const size_t piped = sizeof(float) * ((size_t)max_leaf * d + d) + sizeof(int32_t) * (size_t)max_leaf;
+    if (d % 4 == 0 && max_leaf <= 512 && max_leaf * (d / 4) <= 512 * 16 && piped + 2048 <= (size_t)lds_limit &&
+        (int64_t)nleaf * T < (1ll << 31)) {  // a leaf fits a block's registers and LDS: pipelined
+        if (prec == RPF_DIST_BF16)
+            leaf_pipe<__bf16>(s, piped, X, d, dp, leaves, nleaf, T, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f,
+                              max_leaf);
+        else if (prec == RPF_DIST_FP16)
+            leaf_pipe<_Float16>(s, piped, X, d, dp, leaves, nleaf, T, perm, n, leaf_of, centroid, Xc, nrm, 60000.f,
+                                max_leaf);
+        else
+            leaf_pipe<float>(s, piped, X, d, dp, leaves, nleaf, T, perm, n, leaf_of, centroid, Xc, nrm, 3.0e38f,
+                             max_leaf);
+        return;
+    }
     const size_t staged = leaf_staged_lds(d, max_leaf);
     if (staged + 2048 <= (size_t)lds_limit) {  // the leaf's rows fit in LDS: read X once
         const bool vec = (d % 4) == 0;
