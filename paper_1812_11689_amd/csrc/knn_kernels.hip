@@ -388,7 +388,10 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
     constexpr int PAIR = NB + 1;
     constexpr int SLOTS = NB >= 2 ? (PAIR + 1) / 2 : 1;
     __shared__ __align__(16) T s_a[M * C::LDW];
-    __shared__ float s_n[M], s_r[M], s_phi[M], s_tau[M];
+    __shared__ __align__(16) float s_n[M];
+    __shared__ __align__(16) float s_r[M];
+    __shared__ __align__(16) float s_phi[M];
+    __shared__ float s_tau[M];
     __shared__ int32_t s_pt[M];
     __shared__ float s_max[2];
     __shared__ uint2 s_que[MODE == 1 ? NW : 1][MODE == 1 ? kQueue : 1];
@@ -495,24 +498,52 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
     }
 
     if constexpr (MODE == 0) {
+        // (row -> col) slots: lanes hold consecutive columns, so each store covers 128-byte
+        // runs of a row.  (col -> row) slots go through a per-wave 32 x 33 LDS transpose in
+        // the operand tile, which every wave has finished reading: then each store covers a
+        // 128-byte run of a column's row as well.
+        static_assert(sizeof(s_a) >= (size_t)NW * 32 * 33 * sizeof(float), "transpose space");
+        __syncthreads();
+        float *tr = reinterpret_cast<float *>(s_a) + wu * (32 * 33);
 #pragma unroll
         for (int sl = 0; sl < SLOTS; sl++) {
             if (!act[sl]) continue;
             const int bi = sbi[sl], bj = sbj[sl];
             const bool diag = bi == bj;
-            const int col = 32 * bj + (lane & 31);
-            if (col < m) {
-                const float ncol = s_n[col], rcol = s_r[col];
-                const int pcol = s_pt[col];
-                const int64_t ecol = (int64_t)pcol * out.cap + (int64_t)tb * out.ML;
+            const int cl = lane & 31, col = 32 * bj + cl;
+            const bool colok = col < m;
+            const float ncol = s_n[colok ? col : 0], rcol = s_r[colok ? col : 0];
+            const int pcol = s_pt[colok ? col : 0];
+            float lbv[16], ubv[16];
 #pragma unroll
-                for (int v = 0; v < 16; v++) {
-                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    if (row >= m || (diag && (row > col || (row == col && exclude_self)))) continue;
-                    float lb, ub;
-                    pair_bounds(s_n[row], ncol, s_r[row], rcol, acc[sl][v], bc, lb, ub);
-                    put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, pcol, lb, ub);
-                    if (row != col) put_first(out, ecol + row, s_pt[row], lb, ub);
+            for (int v = 0; v < 16; v++) {
+                const int rl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), row = 32 * bi + rl;
+                const bool rowok = row < m;
+                pair_bounds(s_n[rowok ? row : 0], ncol, s_r[rowok ? row : 0], rcol, acc[sl][v], bc, lbv[v], ubv[v]);
+                if (colok && rowok && !(diag && (row > col || (row == col && exclude_self))))
+                    put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, pcol, lbv[v], ubv[v]);
+            }
+            // transposed: output row = column c of the block, positions 32 bi + r
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                float *src = h ? ubv : lbv;
+                wave_sync();
+#pragma unroll
+                for (int v = 0; v < 16; v++) tr[cl * 33 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)] = src[v];
+                wave_sync();
+                for (int c0 = 0; c0 < 32; c0 += 2) {
+                    const int c = c0 + (lane >> 5), r = lane & 31;
+                    const int cg = 32 * bj + c, rg = 32 * bi + r;
+                    if (cg < m && rg < m && rg != cg && !(diag && rg > cg)) {
+                        const int64_t slot = (int64_t)s_pt[cg] * out.cap + (int64_t)tb * out.ML + rg;
+                        const float val = tr[c * 33 + r];
+                        if (h) {
+                            out.pub[slot] = val;
+                        } else {
+                            out.plb[slot] = val;
+                            out.pidx[slot] = s_pt[rg];
+                        }
+                    }
                 }
             }
         }
@@ -541,10 +572,21 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             if (!act[sl]) continue;
             const int bi = sbi[sl], bj = sbj[sl];
             const bool diag = bi == bj;
-            const int col = 32 * bj + (lane & 31);
+            const int col = 32 * bj + (lane & 31);  // < M: rows past the leaf hold n = 0, phi = -inf
             const bool colok = col < m;
             const float ncol = s_n[col];
             const float phicol = s_phi[col];
+            // the lane's 16 rows come in four runs of four: their norms and thresholds are
+            // read up front, four at a time, so the tests below are branch-free register work
+            float nr[16], pr[16];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int r0 = 32 * bi + 8 * j + 4 * (lane >> 5);
+                const float4 n4 = *reinterpret_cast<const float4 *>(s_n + r0);
+                const float4 p4 = *reinterpret_cast<const float4 *>(s_phi + r0);
+                nr[4 * j] = n4.x; nr[4 * j + 1] = n4.y; nr[4 * j + 2] = n4.z; nr[4 * j + 3] = n4.w;
+                pr[4 * j] = p4.x; pr[4 * j + 1] = p4.y; pr[4 * j + 2] = p4.z; pr[4 * j + 3] = p4.w;
+            }
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 uint32_t bits = 0;  // (p1, p2) of the 8 values of this half, two bits each
@@ -555,9 +597,12 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
                     const int v = 8 * h + v8;
                     const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                     const float g = acc[sl][v];
-                    const bool p1 = colok && __builtin_fmaf(-2.f, g, ncol) <= s_phi[row] &&
-                                    !(diag && (row > col || (row == col && exclude_self)));
-                    const bool p2 = (!diag || row < col) && row < m && __builtin_fmaf(-2.f, g, s_n[row]) <= phicol;
+                    // row -> col needs a real column and, on the diagonal block, row <= col
+                    // (row < col when the point itself is excluded); col -> row needs a real
+                    // row and, on the diagonal block, row < col
+                    const bool p1 = colok & (__builtin_fmaf(-2.f, g, ncol) <= pr[v]) &
+                                    !(diag & ((row > col) | ((row == col) & (exclude_self != 0))));
+                    const bool p2 = (!diag | (row < col)) & (row < m) & (__builtin_fmaf(-2.f, g, nr[v]) <= phicol);
                     bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
                     mk[v8] = __ballot(p1 || p2);
                     tot += (uint32_t)__popcll(mk[v8]);
@@ -703,22 +748,23 @@ __device__ inline uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// An upper bound of the k-th smallest (0-based) of the flagged keys held Q per lane (the
-// wave holds more than k of them), within 2^13 key units of it: 2^-10 relative for the
-// bit patterns of normal non-negative floats.  The bits the smallest and largest key share
-// are fixed; each lower bit down to bit 13 is then set, from the top, exactly when at most
-// k keys lie below the candidate, counted by ballots: no LDS and no atomics.  Every use
+// An upper bound of the k-th smallest (0-based) of the keys held Q per lane (the wave holds
+// more than k of them), within 2^13 key units of it: 2^-10 relative for the bit patterns of
+// normal non-negative floats.  An entry that does not take part holds 0xffffffff, which is
+// never below a candidate (every candidate is at most the largest valid key).  The bits the
+// smallest and largest key share are fixed; each lower bit down to bit 13 is then set, from
+// the top, exactly when at most k keys lie below the candidate, counted by ballots (one
+// compare and one population count per entry and bit): no LDS and no atomics.  Every use
 // below is a threshold whose correctness only needs a value at or above the exact one.
 template <int Q>
-__device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], const bool (&ok)[Q], int k) {
+__device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], int k) {
     constexpr int kLow = 13;
     uint32_t lo = 0xffffffffu, hi = 0;
 #pragma unroll
-    for (int q = 0; q < Q; q++)
-        if (ok[q]) {
-            lo = min(lo, v[q]);
-            hi = max(hi, v[q]);
-        }
+    for (int q = 0; q < Q; q++) {
+        lo = min(lo, v[q]);
+        hi = max(hi, v[q] == 0xffffffffu ? 0u : v[q]);
+    }
     lo = wave_min_u32(lo);
     hi = wave_max_u32(hi);
     if (lo >= hi) return lo;
@@ -729,7 +775,7 @@ __device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], const bool (&o
         const uint32_t t = ans | (1u << b);
         int c = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++) c += __popcll(__ballot(ok[q] && v[q] < t));
+        for (int q = 0; q < Q; q++) c += __popcll(__ballot(v[q] < t));
         if (c <= k) ans = t;
     }
     return min(ans | ((1u << kLow) - 1u), hi);
@@ -746,14 +792,18 @@ constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
 constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
 constexpr int kSetCap = 512;
 
-template <int Q>
+template <int Q, int HT>
 __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int ML,
                                                      const int32_t *__restrict__ pidx, const float *__restrict__ plb,
                                                      const float *__restrict__ pub, int cap, float *__restrict__ tau,
                                                      Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap,
                                                      int32_t *__restrict__ cnt) {
-    __shared__ int32_t s_si[4][kSetCap];
-    __shared__ uint32_t s_su[4][kSetCap];
+    // per-wave open-addressing hash of the small set: index -> smallest (ub, slot) packed as
+    // ub bits << 32 | slot (the order the representatives are defined by)
+    constexpr int kHBits = HT == 512 ? 9 : HT == 1024 ? 10 : 11;
+    static_assert((1 << kHBits) == HT, "hash range must equal the table");
+    __shared__ int32_t s_hid[4][HT];
+    __shared__ unsigned long long s_hkey[4][HT];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
@@ -767,80 +817,76 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
         }
         return;
     }
-    uint32_t u[Q];
+    uint32_t u[Q];  // ub bits of the finite slots, 0xffffffff for the others
     float l[Q];
-    bool fin[Q];
+    int32_t id[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
         const bool in = i < c;
-        u[q] = in ? fkey(pub[base_slot + i]) : 0xffffffffu;
+        const uint32_t ub = in ? fkey(pub[base_slot + i]) : 0xffffffffu;
+        u[q] = ub < 0x7f800000u ? ub : 0xffffffffu;
         l[q] = in ? plb[base_slot + i] : INFINITY;
+        id[q] = in ? pidx[base_slot + i] : -1;
+    }
+    for (int i = lane; i < HT; i += 64) {
+        s_hid[w][i] = -1;
+        s_hkey[w][i] = ~0ull;
     }
     int nv = 0;  // finite-ub slots (empty slots hold +inf bounds)
 #pragma unroll
-    for (int q = 0; q < Q; q++) {
-        fin[q] = u[q] < 0x7f800000u;
-        nv += __popcll(__ballot(fin[q]));
-    }
+    for (int q = 0; q < Q; q++) nv += __popcll(__ballot(u[q] != 0xffffffffu));
     const int kb = K * B;
-    const uint32_t theta = nv >= kb ? wave_kth_upper<Q>(u, fin, kb - 1) : 0x7f800000u;
-    // the small set S = {finite slots with ub <= theta}
+    const uint32_t theta = nv >= kb ? wave_kth_upper<Q>(u, kb - 1) : 0x7f800000u;
+    // the small set S = {finite slots with ub <= theta}, each entry hashed by its index
     int ns = 0;
 #pragma unroll
-    for (int q = 0; q < Q; q++) {
-        const bool in = fin[q] && u[q] <= theta;
-        const uint64_t mk = __ballot(in);
-        const int pos = ns + mask_rank(mk);
-        if (in && pos < kSetCap) {
-            s_si[w][pos] = pidx[base_slot + lane + 64 * q];
-            s_su[w][pos] = u[q];
-        }
-        ns += __popcll(mk);
-    }
-    wave_sync();
-    const bool over = ns > kSetCap;
+    for (int q = 0; q < Q; q++) ns += __popcll(__ballot(u[q] <= theta));
+    const bool over = ns > HT / 2;
     float tv = INFINITY;
     if (!over) {
-        // representatives: the entry of smallest (ub, position) among equal indices
-        uint32_t repv[kSetCap / 64];
-        bool rep[kSetCap / 64];
+        wave_sync();  // the cleared table is visible
+        int hq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            hq[q] = -1;
+            if (u[q] <= theta) {
+                const unsigned long long key = ((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q);
+                int h = (int)(((uint32_t)id[q] * 2654435761u) >> (32 - kHBits));
+                while (true) {  // at most half full: a free or matching entry is always found
+                    const int prev = atomicCAS(&s_hid[w][h], -1, id[q]);
+                    if (prev == -1 || prev == id[q]) break;
+                    h = (h + 1) & (HT - 1);
+                }
+                atomicMin(&s_hkey[w][h], key);
+                hq[q] = h;
+            }
+        }
+        wave_sync();
+        // representatives: the entry of smallest (ub, slot) among equal indices
+        uint32_t rv[Q];
         int nrep = 0;
 #pragma unroll
-        for (int q = 0; q < kSetCap / 64; q++) {
-            const int i = lane + 64 * q;
-            rep[q] = i < ns;
-            repv[q] = 0;
-            if (rep[q]) {
-                const int id = s_si[w][i];
-                const uint32_t uu = s_su[w][i];
-                repv[q] = uu;
-                for (int j = 0; j < ns; j++)
-                    if (s_si[w][j] == id && (s_su[w][j] < uu || (s_su[w][j] == uu && j < i))) {
-                        rep[q] = false;
-                        break;
-                    }
-            }
-            nrep += __popcll(__ballot(rep[q]));
+        for (int q = 0; q < Q; q++) {
+            const bool rep = hq[q] >= 0 &&
+                             s_hkey[w][hq[q]] == (((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q));
+            rv[q] = rep ? u[q] : 0xffffffffu;
+            nrep += __popcll(__ballot(rep));
         }
-        if (nrep >= K) tv = __uint_as_float(wave_kth_upper<kSetCap / 64>(repv, rep, K - 1));
+        if (nrep >= K) tv = __uint_as_float(wave_kth_upper<Q>(rv, K - 1));
     }
     const float tp = tv * (1.f + 1e-6f);
     uint32_t kept = 0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
-        // lanes past the row's c slots read nothing: with tau = +inf (fewer distinct
-        // candidates than K) their lb = +inf would pass lb <= tau and the read would land in
-        // the next row's slots, or past the index array for the last row.  Validity of a
-        // slot comes from its index (-1 marks an empty one), never from its bounds: a pair
-        // outside the copy's range carries lb = 0, ub = +inf and is kept.
-        const bool cand = !over && i < c && l[q] <= tp;
-        const int id = cand ? pidx[base_slot + i] : -1;
-        const bool keep = id >= 0;
+        // validity of a slot comes from its index (-1 marks an empty one), never from its
+        // bounds: a pair outside the copy's range carries lb = 0, ub = +inf and is kept
+        const bool keep = !over && i < c && l[q] <= tp && id[q] >= 0;
         const uint64_t mk = __ballot(keep);
         const uint32_t pos = kept + mask_rank(mk);
-        if (keep && pos < (uint32_t)lcap) list[a * lcap + pos] = make_ent(id, l[q], __uint_as_float(u[q]));
+        if (keep && pos < (uint32_t)lcap)
+            list[a * lcap + pos] = make_ent(id[q], l[q], __uint_as_float(u[q] == 0xffffffffu ? 0x7f800000u : u[q]));
         kept += __popcll(mk);
     }
     if (lane == 0) {
@@ -966,7 +1012,12 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         return;
     }
     float tv = INFINITY;
-    if (nd >= K) tv = __uint_as_float(wave_kth_upper<Q>(eub, first, K - 1));
+    if (nd >= K) {
+        uint32_t fu[Q];  // ub keys of first copies, the others masked out
+#pragma unroll
+        for (int q = 0; q < Q; q++) fu[q] = first[q] ? eub[q] : 0xffffffffu;
+        tv = __uint_as_float(wave_kth_upper<Q>(fu, K - 1));
+    }
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
     int nr = 0;  // rerank set R = {first copies with lb <= tau'}
 #pragma unroll
@@ -1000,15 +1051,13 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     wave_sync();
     float d32k = INFINITY;
     if (nr >= K) {
-        uint32_t dv[kRCap / 64];
-        bool dok[kRCap / 64];
+        uint32_t dv[kRCap / 64];  // binary32 distance keys of R, the rest masked out
 #pragma unroll
         for (int q = 0; q < kRCap / 64; q++) {
             const int i = lane + 64 * q;
-            dok[q] = i < nr;
-            dv[q] = dok[q] ? s_d[w][i] : 0u;
+            dv[q] = i < nr ? s_d[w][i] : 0xffffffffu;
         }
-        d32k = __uint_as_float(wave_kth_upper<kRCap / 64>(dv, dok, K - 1));
+        d32k = __uint_as_float(wave_kth_upper<kRCap / 64>(dv, K - 1));
     }
     const float wcut = d32k * (1.f + A.win);
     int nw = 0;  // the window: binary32 distance within w of the K-th; ordered in binary64
@@ -1608,18 +1657,17 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         ProfScope ps(s, "merge_first", 0, 0);
         // the smallest per-lane slot count that holds the row's B x max_leaf slots
         const dim3 mg((unsigned)((rows + 3) / 4));
-        if (cap1 <= 256)
-            hipLaunchKernelGGL(k_merge_first<4>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
-                               cap1, tau, list, lcnt, lcap, cnt);
-        else if (cap1 <= 512)
-            hipLaunchKernelGGL(k_merge_first<8>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
-                               cap1, tau, list, lcnt, lcap, cnt);
-        else if (cap1 <= 1024)
-            hipLaunchKernelGGL(k_merge_first<16>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub,
-                               cap1, tau, list, lcnt, lcap, cnt);
-        else
-            hipLaunchKernelGGL(k_merge_first<kMergeCap / 64>, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx,
-                               plb, pub, cap1, tau, list, lcnt, lcap, cnt);
+        // hash table of the small set: room for twice its largest regular size (K B entries
+        // plus ties)
+        const bool big = K * cs.B > 128;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub, cap1, tau, list,
+                               lcnt, lcap, cnt);
+        };
+        if (cap1 <= 256) big ? go(k_merge_first<4, 1024>) : go(k_merge_first<4, 512>);
+        else if (cap1 <= 512) big ? go(k_merge_first<8, 1024>) : go(k_merge_first<8, 512>);
+        else if (cap1 <= 1024) big ? go(k_merge_first<16, 1024>) : go(k_merge_first<16, 512>);
+        else big ? go(k_merge_first<kMergeCap / 64, 1024>) : go(k_merge_first<kMergeCap / 64, 512>);
         launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0 || cs.nsjobs1 > 0) {
