@@ -1037,15 +1037,33 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     // dead by now and holds the binary64 values
     double *s_dd = reinterpret_cast<double *>(s_key[w]);  // kHT int32 = kRCap doubles
     const int g = lane & 7, grp = lane >> 3;
-    for (int base = 0; base < nr; base += 8) {
-        const int i = base + grp;
-        const int b = s_r[w][i < nr ? i : 0];
-        float D32;
-        double D64;
-        group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
-        if (g == 0 && i < nr) {
-            s_d[w][i] = fkey(D32);
-            s_dd[i] = D64;
+    if constexpr (VEC) {  // two candidates per group of eight lanes at a time
+        for (int base = 0; base < nr; base += 16) {
+            const int i0 = base + grp, i1 = i0 + 8;
+            const int b0 = s_r[w][i0 < nr ? i0 : 0], b1 = s_r[w][i1 < nr ? i1 : 0];
+            float D32[2];
+            double D64[2];
+            group8_dist32_64x2(s_q, A.X + (int64_t)b0 * A.d, A.X + (int64_t)b1 * A.d, A.d, g, D32, D64);
+            if (g == 0 && i0 < nr) {
+                s_d[w][i0] = fkey(D32[0]);
+                s_dd[i0] = D64[0];
+            }
+            if (g == 0 && i1 < nr) {
+                s_d[w][i1] = fkey(D32[1]);
+                s_dd[i1] = D64[1];
+            }
+        }
+    } else {
+        for (int base = 0; base < nr; base += 8) {
+            const int i = base + grp;
+            const int b = s_r[w][i < nr ? i : 0];
+            float D32;
+            double D64;
+            group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
+            if (g == 0 && i < nr) {
+                s_d[w][i] = fkey(D32);
+                s_dd[i] = D64;
+            }
         }
     }
     wave_sync();

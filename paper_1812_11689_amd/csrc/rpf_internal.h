@@ -431,6 +431,65 @@ __device__ inline void group8_dist32_64(const float *__restrict__ a, const float
     D64 = u;
 }
 
+// The same two distances from a to two rows b0, b1 (d % 4 == 0, 16-byte aligned), with the
+// row loads of four steps issued before their arithmetic: the eight lanes of a group then
+// wait on memory once per 256 columns of both rows, not once per 32.  Each distance is
+// computed exactly as group8_dist32_64 computes it.
+__device__ inline void group8_dist32_64x2(const float *__restrict__ a, const float *__restrict__ b0,
+                                          const float *__restrict__ b1, int d, int g, float (&D32)[2],
+                                          double (&D64)[2]) {
+    float f[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    double s[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    auto step = [&](const float4 av, const float4 bv, int r) {
+        const float e0 = av.x - bv.x, e1 = av.y - bv.y, e2 = av.z - bv.z, e3 = av.w - bv.w;
+        f[r][0] = __builtin_fmaf(e0, e0, f[r][0]);
+        f[r][1] = __builtin_fmaf(e1, e1, f[r][1]);
+        f[r][2] = __builtin_fmaf(e2, e2, f[r][2]);
+        f[r][3] = __builtin_fmaf(e3, e3, f[r][3]);
+        const double d0 = (double)av.x - (double)bv.x, d1 = (double)av.y - (double)bv.y;
+        const double d2 = (double)av.z - (double)bv.z, d3 = (double)av.w - (double)bv.w;
+        s[r][0] = __builtin_fma(d0, d0, s[r][0]);
+        s[r][1] = __builtin_fma(d1, d1, s[r][1]);
+        s[r][2] = __builtin_fma(d2, d2, s[r][2]);
+        s[r][3] = __builtin_fma(d3, d3, s[r][3]);
+    };
+    int j = 4 * g;
+    for (; j + 96 < d; j += 128) {  // four steps of both rows in flight
+        float4 x0[4], x1[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            x0[k] = *reinterpret_cast<const float4 *>(b0 + j + 32 * k);
+            x1[k] = *reinterpret_cast<const float4 *>(b1 + j + 32 * k);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float4 av = *reinterpret_cast<const float4 *>(a + j + 32 * k);
+            step(av, x0[k], 0);
+            step(av, x1[k], 1);
+        }
+    }
+    for (; j < d; j += 32) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(b0 + j);
+        const float4 x1 = *reinterpret_cast<const float4 *>(b1 + j);
+        const float4 av = *reinterpret_cast<const float4 *>(a + j);
+        step(av, x0, 0);
+        step(av, x1, 1);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        float v = (f[r][0] + f[r][1]) + (f[r][2] + f[r][3]);
+        v = v + shfl_xor_f(v, 1);
+        v = v + shfl_xor_f(v, 2);
+        v = v + shfl_xor_f(v, 4);
+        D32[r] = v;
+        double u = (s[r][0] + s[r][1]) + (s[r][2] + s[r][3]);
+        u = u + shfl_xor_d(u, 1);
+        u = u + shfl_xor_d(u, 2);
+        u = u + shfl_xor_d(u, 4);
+        D64[r] = u;
+    }
+}
+
 // ---------------------------------------------------------------- host-side launch helpers
 
 struct Prof;  // per-kernel event timing (rpf_api.hip)
