@@ -208,10 +208,10 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     constexpr int NT = 64 * MB;
     __shared__ __align__(16) T s_a[M * C::LDW];
     __shared__ __align__(16) T s_b[M * C::LDW];
-    __shared__ float s_na[M], s_ra[M], s_nb[M], s_rb[M], s_phi[M], s_tau[M];
+    __shared__ float s_na[M], s_ra[M], s_nb[M], s_rb[M], s_tau[M];
+    __shared__ __align__(16) float s_phi[M];
     __shared__ int32_t s_dst[M], s_bpt[M];
     __shared__ float s_bmax[2];
-    __shared__ uint32_t s_qn[MB];
     __shared__ uint2 s_que[MB][kQueue];
 
     const TileJob job = jobs[blockIdx.x];
@@ -252,7 +252,6 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
             s_bpt[r] = -1;
         }
     }
-    if (tid < MB) s_qn[tid] = 0;
     __syncthreads();
     if (tid < 64) {
         float mn = 0.f, mr = 0.f;
@@ -334,41 +333,67 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
         }
         return;
     }
-    // Phase II: cheap test over every pair, exact bounds only for the few that pass
-    uint32_t *qn = &s_qn[wu];
+    // Phase II: a cheap test over every pair; the pairs that pass are compacted by ballot
+    // into a per-wave LDS queue, whose exact bounds and emissions run when it would overflow
+    // and at the end (wave-uniform decisions throughout)
     uint2 *que = s_que[wu];
+    uint32_t qc = 0;
+    auto flush = [&](uint32_t nq) {
+        wave_sync();
+        for (uint32_t i = lane; i < nq; i += 64) {
+            const uint2 e = que[i];
+            const int row = e.x & 255, col = (e.x >> 8) & 255;
+            float lb, ub;
+            pair_bounds(s_na[row], s_nb[col], s_ra[row], s_rb[col], __uint_as_float(e.y), bc, lb, ub);
+            if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
+        }
+        wave_sync();
+    };
+    // the lane's 16 rows come in four runs of four: their thresholds are read up front
+    // (rows past the block hold -inf), so the tests below are branch-free register work
+    float pr[16];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const float4 p4 = *reinterpret_cast<const float4 *>(s_phi + 32 * wu + 8 * j + 4 * (lane >> 5));
+        pr[4 * j] = p4.x; pr[4 * j + 1] = p4.y; pr[4 * j + 2] = p4.z; pr[4 * j + 3] = p4.w;
+    }
 #pragma unroll
     for (int cb = 0; cb < MB; cb++) {
         if (cb >= nbb) continue;
-        const int col = 32 * cb + (lane & 31);
+        const int col = 32 * cb + (lane & 31);  // < M: columns past the block hold n = 0
         const bool colok = col < job.b_rows;
         const float nb = s_nb[col];
 #pragma unroll
-        for (int v = 0; v < 16; v++) {
-            const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            const bool p = colok && __builtin_fmaf(-2.f, acc[cb][v], nb) <= s_phi[row] &&
-                           !(same && exclude_self && row == col);
-            if (p) {
-                const uint32_t pos = atomicAdd(qn, 1u);
-                if (pos < (uint32_t)kQueue) {
-                    que[pos] = make_uint2((uint32_t)row | ((uint32_t)col << 8), __float_as_uint(acc[cb][v]));
-                } else {  // queue full (rare): bounds and emission right here
-                    float lb, ub;
-                    pair_bounds(s_na[row], nb, s_ra[row], s_rb[col], acc[cb][v], bc, lb, ub);
-                    if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
+        for (int h = 0; h < 2; h++) {
+            uint32_t bits = 0;
+            uint64_t mk[8];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int v8 = 0; v8 < 8; v8++) {
+                const int v = 8 * h + v8;
+                const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const bool p = colok & (__builtin_fmaf(-2.f, acc[cb][v], nb) <= pr[v]) &
+                               !(same & (exclude_self != 0) & (row == col));
+                bits |= (p ? 1u : 0u) << v8;
+                mk[v8] = __ballot(p);
+                tot += (uint32_t)__popcll(mk[v8]);
+            }
+            if (qc + tot > (uint32_t)kQueue) {
+                flush(qc);
+                qc = 0;
+            }
+#pragma unroll
+            for (int v8 = 0; v8 < 8; v8++) {
+                const int v = 8 * h + v8;
+                if ((bits >> v8) & 1u) {
+                    const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    que[qc + mask_rank(mk[v8])] = make_uint2((uint32_t)row | ((uint32_t)col << 8), __float_as_uint(acc[cb][v]));
                 }
+                qc += (uint32_t)__popcll(mk[v8]);
             }
         }
     }
-    wave_sync();
-    const uint32_t nq = min(*qn, (uint32_t)kQueue);
-    for (uint32_t i = lane; i < nq; i += 64) {
-        const uint2 e = que[i];
-        const int row = e.x & 255, col = (e.x >> 8) & 255;
-        float lb, ub;
-        pair_bounds(s_na[row], s_nb[col], s_ra[row], s_rb[col], __uint_as_float(e.y), bc, lb, ub);
-        if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
-    }
+    flush(qc);
 }
 
 // All-points tile of one leaf whose rows all fit (m <= 32 NB): the Gram matrix is symmetric,
