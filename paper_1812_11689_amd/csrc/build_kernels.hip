@@ -626,6 +626,100 @@ __global__ __launch_bounds__(256) void k_part_scatter(const SegDesc *__restrict_
     }
 }
 
+// Lead projections of the first level for every tree from one read of X.  At the roots the
+// permutation is the identity in every tree, so the rows of a chunk are the same rows for
+// all trees: a block keeps 64 of them in registers (eight lanes per row, two rows per group,
+// d <= 128 and d % 4 == 0) and walks the trees, staging each tree's three directions (node
+// and children, as binary64) in LDS, double-buffered.  Each projection is computed exactly
+// as group8_dot64 computes it.  Writes the keys and the children's projections; the
+// first-digit histograms come from a selection pass over the keys.
+__global__ __launch_bounds__(256) void k_proj_root(const float *__restrict__ X, int d, const float *__restrict__ R,
+                                                   int64_t H, int ntree, const SegDesc *__restrict__ segs,
+                                                   const ChunkDesc *__restrict__ chunks,
+                                                   const LookDesc *__restrict__ look, int64_t n,
+                                                   uint64_t *__restrict__ keys, double2 *__restrict__ ahead) {
+    constexpr int NJ = 4;                   // float4 steps per lane: d <= 128
+    __shared__ __align__(16) double s_rd[2][3 * 128];
+    const ChunkDesc c = chunks[blockIdx.x];
+    const int sub0 = 64 * blockIdx.y;
+    if (sub0 >= c.len) return;
+    const SegDesc sg = segs[c.seg];
+    const LookDesc lk = look[c.seg];
+    const int tid = threadIdx.x, g = tid & 7, pt = tid >> 3;
+    const int ia = sub0 + pt, ib = ia + 32;  // rows within the chunk
+    const bool oka = ia < c.len, okb = ib < c.len;
+    const float *xa = X + (c.start + (oka ? ia : 0)) * (int64_t)d;
+    const float *xb = X + (c.start + (okb ? ib : 0)) * (int64_t)d;
+    float4 ra[NJ], rb[NJ];
+#pragma unroll
+    for (int k = 0; k < NJ; k++) {
+        const int j = 4 * g + 32 * k;
+        ra[k] = j < d ? *reinterpret_cast<const float4 *>(xa + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        rb[k] = j < d ? *reinterpret_cast<const float4 *>(xb + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    auto stage = [&](int t, double *dst) {  // node, left child, right child (zero for a leaf child)
+        for (int j = tid; j < 3 * 128; j += 256) {
+            const int k = j >> 7, jj = j & 127;
+            float v = 0.f;
+            if (jj < d) {
+                const int heap = k == 0 ? sg.heap : k == 1 ? lk.child_heap[0] : lk.child_heap[1];
+                if (heap > 0) v = R[((int64_t)t * H + (heap - 1)) * (int64_t)d + jj];
+            }
+            dst[j] = v;
+        }
+    };
+    stage(0, s_rd[0]);
+    for (int t = 0; t < ntree; t++) {
+        __syncthreads();  // s_rd[t & 1] is staged; everyone is done with s_rd[(t + 1) & 1]
+        if (t + 1 < ntree) stage(t + 1, s_rd[(t + 1) & 1]);
+        const double *r = s_rd[t & 1];
+        double s[6][4];
+#pragma unroll
+        for (int q = 0; q < 6; q++) s[q][0] = s[q][1] = s[q][2] = s[q][3] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NJ; k++) {
+            const int j = 4 * g + 32 * k;
+            if (j < d) {
+                const double a0 = ra[k].x, a1 = ra[k].y, a2 = ra[k].z, a3 = ra[k].w;
+                const double b0 = rb[k].x, b1 = rb[k].y, b2 = rb[k].z, b3 = rb[k].w;
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const double2 u = *reinterpret_cast<const double2 *>(r + 128 * q + j);
+                    const double2 v = *reinterpret_cast<const double2 *>(r + 128 * q + j + 2);
+                    s[q][0] = __builtin_fma(a0, u.x, s[q][0]);
+                    s[q][1] = __builtin_fma(a1, u.y, s[q][1]);
+                    s[q][2] = __builtin_fma(a2, v.x, s[q][2]);
+                    s[q][3] = __builtin_fma(a3, v.y, s[q][3]);
+                    s[q + 3][0] = __builtin_fma(b0, u.x, s[q + 3][0]);
+                    s[q + 3][1] = __builtin_fma(b1, u.y, s[q + 3][1]);
+                    s[q + 3][2] = __builtin_fma(b2, v.x, s[q + 3][2]);
+                    s[q + 3][3] = __builtin_fma(b3, v.y, s[q + 3][3]);
+                }
+            }
+        }
+        double p[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            double w = (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]);
+            w = w + shfl_xor_d(w, 1);
+            w = w + shfl_xor_d(w, 2);
+            w = w + shfl_xor_d(w, 4);
+            p[q] = w + 0.0;
+        }
+        if (g == 0) {
+            const int64_t base = (int64_t)t * n + c.start;
+            if (oka) {
+                keys[base + ia] = key_of(p[0]);
+                ahead[base + ia] = make_double2(p[1], p[2]);
+            }
+            if (okb) {
+                keys[base + ib] = key_of(p[3]);
+                ahead[base + ib] = make_double2(p[4], p[5]);
+            }
+        }
+    }
+}
+
 // ---- Alg. 2 on large segments: canonical sums over aligned power-of-two chunks
 
 // partial canon_sum of one chunk: of p (what = 0) or of (p - mu)^2 (what = 1)
@@ -912,7 +1006,15 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
             }
         }
     }
-    if (!lk.keys_in) {
+    if (lk.roots) {  // every tree's root projections from one read of X, then the first digit
+        ProfScope ps(s, "proj_roots", proj_bytes, 0);
+        hipLaunchKernelGGL(k_proj_root, dim3(nchunk, kChunk / 64), dim3(256), 0, s, X, d, R, H, T, segs, chunks,
+                           lk.look, n, b.keys, lk.ahead);
+        launch_check(s, "k_proj_root");
+        hipLaunchKernelGGL(k_sel_pass, gc, dim3(256), 0, s, chunks, b.keys, pin, n, b.state, nseg, b.hist, b.cand,
+                           b.cand_cnt);
+        launch_check(s, "k_sel_pass");
+    } else if (!lk.keys_in) {
         ProfScope ps(s, lk.look ? "proj_chunks_x3" : "proj_chunks", proj_bytes, 0);
         if (vec) proj_chunks<true>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0, lk);
         else proj_chunks<false>(s, gc, X, d, R, H, n_try, segs, chunks, pin, n, b, nseg, 0, 0, lk);

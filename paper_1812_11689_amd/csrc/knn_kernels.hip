@@ -1186,6 +1186,8 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
     __shared__ double s_td[256];
     __shared__ int32_t s_ti[256];
     __shared__ int s_tn;
+    __shared__ uint32_t s_scan[8];
+    __shared__ int32_t s_mid[256];
     extern __shared__ __align__(16) float s_q[];
     const int tid = threadIdx.x, g = tid & 7, grp = tid >> 3;
     const int nfb = *F.fb_cnt;
@@ -1200,16 +1202,38 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
             const int heap = F.row_leaf[(int64_t)t * F.nrows + a];
             const LeafDesc lf = F.leaves[F.heap_leaf[heap]];
             for (int base = 0; base < lf.size; base += 256) {
-                // distances of up to 256 members, 8 lanes per member
-                for (int sub = 0; sub < 256; sub += 32) {
-                    const int i = base + sub + grp;
-                    const int ii = i < lf.size ? i : 0;
-                    const int b = F.perm[(int64_t)t * F.n + lf.off + ii];
-                    const double D = group8_dist64<VEC>(s_q, F.X + (int64_t)b * F.d, F.d, g);
-                    if (g == 0) {
-                        const bool ok = i < lf.size && !(F.exclude_self && b == a);
-                        s_cd[sub + grp] = ok ? D : INFINITY;
-                        s_ci[sub + grp] = ok ? b : 0x7fffffff;
+                // distances of up to 256 members, 8 lanes per member; the member ids come
+                // from LDS, read in one pass
+                __syncthreads();
+                s_mid[tid] = base + tid < lf.size ? F.perm[(int64_t)t * F.n + lf.off + base + tid] : -1;
+                __syncthreads();
+                if constexpr (VEC) {  // two members per group of eight lanes at a time
+                    for (int sub = 0; sub < 256; sub += 64) {
+                        const int l0 = sub + grp, l1 = l0 + 32;
+                        const int b0 = s_mid[l0], b1 = s_mid[l1];
+                        float D32[2];
+                        double D64[2];
+                        group8_dist32_64x2(s_q, F.X + (int64_t)(b0 < 0 ? 0 : b0) * F.d,
+                                           F.X + (int64_t)(b1 < 0 ? 0 : b1) * F.d, F.d, g, D32, D64);
+                        if (g == 0) {
+#pragma unroll
+                            for (int h = 0; h < 2; h++) {
+                                const int l = h ? l1 : l0, b = h ? b1 : b0;
+                                const bool ok = b >= 0 && !(F.exclude_self && b == a);
+                                s_cd[l] = ok ? D64[h] : INFINITY;
+                                s_ci[l] = ok ? b : 0x7fffffff;
+                            }
+                        }
+                    }
+                } else {
+                    for (int sub = 0; sub < 256; sub += 32) {
+                        const int l = sub + grp, b = s_mid[l];
+                        const double D = group8_dist64<VEC>(s_q, F.X + (int64_t)(b < 0 ? 0 : b) * F.d, F.d, g);
+                        if (g == 0) {
+                            const bool ok = b >= 0 && !(F.exclude_self && b == a);
+                            s_cd[l] = ok ? D : INFINITY;
+                            s_ci[l] = ok ? b : 0x7fffffff;
+                        }
                     }
                 }
                 for (int i = 256 + tid; i < 512; i += 256) {
@@ -1217,8 +1241,20 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                     s_ci[i] = 0x7fffffff;
                 }
                 __syncthreads();
+                // with a full list, a member at or past its last entry in (D, idx) order cannot
+                // enter it (a repeated index repeats its distance): skip the merge when none is
+                // before it
+                const int tn = s_tn;
+                if (tn == K) {
+                    const double lastd = s_td[K - 1];
+                    const int lasti = s_ti[K - 1];
+                    const double dc = s_cd[tid];
+                    const int ic = s_ci[tid];
+                    const bool better = dc < lastd || (dc == lastd && ic < lasti);
+                    if (__syncthreads_count(better) == 0) continue;
+                }
                 // append the current top list, then sort 512 by (D, idx)
-                for (int i = tid; i < s_tn; i += 256) {
+                for (int i = tid; i < tn; i += 256) {
                     s_cd[256 + i] = s_td[i];
                     s_ci[256 + i] = s_ti[i];
                 }
@@ -1240,16 +1276,35 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                         }
                         __syncthreads();
                     }
-                if (tid == 0) {  // K smallest distinct (equal index implies equal distance)
-                    int nt = 0;
-                    for (int i = 0; i < 512 && nt < K; i++) {
-                        if (s_ci[i] == 0x7fffffff) break;
-                        if (nt > 0 && s_ti[nt - 1] == s_ci[i]) continue;
-                        s_td[nt] = s_cd[i];
-                        s_ti[nt] = s_ci[i];
-                        nt++;
+                {  // K smallest distinct: copies of an index are equal and adjacent after the sort
+                    bool keep[2];
+                    uint32_t cnt = 0;
+#pragma unroll
+                    for (int e = 0; e < 2; e++) {
+                        const int i = 2 * tid + e;
+                        keep[e] = s_ci[i] != 0x7fffffff && (i == 0 || s_ci[i] != s_ci[i - 1]);
+                        cnt += keep[e] ? 1u : 0u;
                     }
-                    s_tn = nt;
+                    uint32_t excl, total;
+                    block_excl_scan256(cnt, reinterpret_cast<uint32_t *>(s_scan), excl, total);
+                    double kd[2];
+                    int ki[2];
+#pragma unroll
+                    for (int e = 0; e < 2; e++) {
+                        kd[e] = s_cd[2 * tid + e];
+                        ki[e] = s_ci[2 * tid + e];
+                    }
+                    __syncthreads();  // every read of the sorted list is done before s_td changes
+#pragma unroll
+                    for (int e = 0; e < 2; e++)
+                        if (keep[e]) {
+                            if (excl < (uint32_t)K) {
+                                s_td[excl] = kd[e];
+                                s_ti[excl] = ki[e];
+                            }
+                            excl++;
+                        }
+                    if (tid == 0) s_tn = (int)min(total, (uint32_t)K);
                 }
                 __syncthreads();
             }

@@ -98,6 +98,7 @@ struct LevelLink {
     int nseg_next = 0;
     const uint64_t *keys_in = nullptr;  // fed: keys made by the lead (null: project)
     uint32_t *hist_in = nullptr;        // fed multi-block level: histograms made by the lead
+    bool roots = false;  // lead at the roots (identity permutation): one read of X for all trees
 };
 
 struct LargeBufs {     // temporaries of the multi-block level path (and of the level links)

@@ -47,6 +47,9 @@ ALL = [
     # list + Phase II capacity above 512 records per row, and more than 1024 Phase I slots
     ("many_trees", 8000, 16, 24, 40, 20, "fp32", "mixture", 0, 1),
     ("big_leaves", 6000, 12, 4, 300, 8, "bf16", "mixture", 0, 1),
+    # half the points are one point: the copies' rows overflow their buffers with zero
+    # distances and take the exhaustive path (asserted below)
+    ("mass_ties", 4000, 8, 4, 200, 5, "fp32", "mixture", 2, 1),
 ]
 
 
@@ -77,6 +80,8 @@ def test_all_knn_matches_oracle(case):
     _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
     st = f.knn_stats()
     print(f"    stats {st}", flush=True)
+    if name == "mass_ties":
+        assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
     f.free()
 
 
