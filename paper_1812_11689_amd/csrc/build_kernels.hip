@@ -484,6 +484,9 @@ __global__ __launch_bounds__(256) void k_sel_finish(const SegDesc *__restrict__ 
                                                     int32_t *__restrict__ err) {
     __shared__ uint64_t s_hi[kCandCap];
     __shared__ uint32_t s_lo[kCandCap];
+    __shared__ uint32_t s_h[256];
+    __shared__ uint32_t s_w[8];
+    __shared__ uint32_t s_sel[3];
     const int t = blockIdx.y, k = blockIdx.x, tid = threadIdx.x;
     SelState *stp = state + (int64_t)t * nseg + k;
     const SelState st = *stp;
@@ -500,10 +503,40 @@ __global__ __launch_bounds__(256) void k_sel_finish(const SegDesc *__restrict__ 
             s_lo[i] = cc[i].lo;
         }
         __syncthreads();
-        for (uint32_t i = tid; i < cnt; i += 256) {
-            uint32_t below = 0;
-            for (uint32_t q = 0; q < cnt; q++) below += key_less(s_hi[q], s_lo[q], s_hi[i], s_lo[i]) ? 1u : 0u;
-            if (below == (uint32_t)st.rank) {
+        // in-block radix select over the candidates, which share the top st.nbits bits:
+        // 8-bit digits of the 96-bit key until one candidate matches the prefix
+        unsigned __int128 P = key96(st.pfx_hi, st.pfx_lo);
+        int nbits = st.nbits;
+        uint32_t rank = (uint32_t)st.rank, c = cnt;
+        while (c > 1 && nbits < 96) {
+            const int w = 96 - nbits < 8 ? 96 - nbits : 8;
+            const int lo_bit = 96 - nbits - w;
+            s_h[tid] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < cnt; i += 256) {
+                const unsigned __int128 Kc = key96(s_hi[i], s_lo[i]);
+                if ((Kc >> (96 - nbits)) == (P >> (96 - nbits)))
+                    atomicAdd(&s_h[(uint32_t)(Kc >> lo_bit) & ((1u << w) - 1u)], 1u);
+            }
+            __syncthreads();
+            const uint32_t v = s_h[tid];
+            uint32_t excl, total;
+            block_excl_scan256(v, s_w, excl, total);
+            if (excl <= rank && rank < excl + v) {
+                s_sel[0] = tid;
+                s_sel[1] = excl;
+                s_sel[2] = v;
+            }
+            __syncthreads();
+            P |= (unsigned __int128)s_sel[0] << lo_bit;
+            rank -= s_sel[1];
+            c = s_sel[2];
+            nbits += w;
+            __syncthreads();
+        }
+        for (uint32_t i = tid; i < cnt; i += 256) {  // the one candidate with the full prefix
+            const unsigned __int128 Kc = key96(s_hi[i], s_lo[i]);
+            if ((Kc >> (96 - nbits)) == (P >> (96 - nbits))) {
                 stp->pfx_hi = s_hi[i];
                 stp->pfx_lo = s_lo[i];
                 stp->nbits = 96;
