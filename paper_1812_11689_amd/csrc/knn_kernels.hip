@@ -491,7 +491,9 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             }
         }
         act[sl] = bj >= 0 && 32 * bj < m;
-        sbi[sl] = bi < 0 ? 0 : bi;
+        // a slot past the pair repeats the block row before it, so that a wave's slots name
+        // at most two block rows, in order (the K loop loads one A fragment per row)
+        sbi[sl] = bi >= 0 ? bi : sl > 0 ? sbi[sl - 1] : 0;
         sbj[sl] = bj < 0 ? 0 : bj;
     }
     f32x16 acc[SLOTS];
@@ -510,15 +512,16 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
         const T *base = s_a + fr * C::LDW + fk;
         using Frag = typename MfmaOperand<PREC>::type;
         for (int kk = 0; kk < kmax; kk += C::KSTEP) {
-            Frag fa[SLOTS], fb[SLOTS];  // all fragment loads of the step first, then the MFMAs
+            // all fragment loads of the step first, then the MFMAs; a wave's slots lie in at
+            // most two block rows (bi0 for the first ones, bi1 after), so two A fragments
+            Frag fa0, fa1, fb[SLOTS];
+            fa0 = *reinterpret_cast<const Frag *>(base + 32 * sbi[0] * C::LDW + kk);
+            fa1 = *reinterpret_cast<const Frag *>(base + 32 * sbi[SLOTS - 1] * C::LDW + kk);
 #pragma unroll
-            for (int sl = 0; sl < SLOTS; sl++) {
-                fa[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbi[sl] * C::LDW + kk);
-                fb[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbj[sl] * C::LDW + kk);
-            }
+            for (int sl = 0; sl < SLOTS; sl++) fb[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbj[sl] * C::LDW + kk);
 #pragma unroll
             for (int sl = 0; sl < SLOTS; sl++)
-                if (act[sl]) acc[sl] = mfma_op<PREC>(fa[sl], fb[sl], acc[sl]);
+                if (act[sl]) acc[sl] = mfma_op<PREC>(sbi[sl] == sbi[0] ? fa0 : fa1, fb[sl], acc[sl]);
         }
     }
 
@@ -601,19 +604,19 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             const bool colok = col < m;
             const float ncol = s_n[col];
             const float phicol = s_phi[col];
-            // the lane's 16 rows come in four runs of four: their norms and thresholds are
-            // read up front, four at a time, so the tests below are branch-free register work
-            float nr[16], pr[16];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int r0 = 32 * bi + 8 * j + 4 * (lane >> 5);
-                const float4 n4 = *reinterpret_cast<const float4 *>(s_n + r0);
-                const float4 p4 = *reinterpret_cast<const float4 *>(s_phi + r0);
-                nr[4 * j] = n4.x; nr[4 * j + 1] = n4.y; nr[4 * j + 2] = n4.z; nr[4 * j + 3] = n4.w;
-                pr[4 * j] = p4.x; pr[4 * j + 1] = p4.y; pr[4 * j + 2] = p4.z; pr[4 * j + 3] = p4.w;
-            }
 #pragma unroll
             for (int h = 0; h < 2; h++) {
+                // the half's 8 rows of this lane come in two runs of four: their norms and
+                // thresholds are read up front, so the tests below are branch-free register work
+                float nr[8], pr[8];
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const int r0 = 32 * bi + 8 * (2 * h + j) + 4 * (lane >> 5);
+                    const float4 n4 = *reinterpret_cast<const float4 *>(s_n + r0);
+                    const float4 p4 = *reinterpret_cast<const float4 *>(s_phi + r0);
+                    nr[4 * j] = n4.x; nr[4 * j + 1] = n4.y; nr[4 * j + 2] = n4.z; nr[4 * j + 3] = n4.w;
+                    pr[4 * j] = p4.x; pr[4 * j + 1] = p4.y; pr[4 * j + 2] = p4.z; pr[4 * j + 3] = p4.w;
+                }
                 uint32_t bits = 0;  // (p1, p2) of the 8 values of this half, two bits each
                 uint64_t mk[8];
                 uint32_t tot = 0;
@@ -625,9 +628,9 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
                     // row -> col needs a real column and, on the diagonal block, row <= col
                     // (row < col when the point itself is excluded); col -> row needs a real
                     // row and, on the diagonal block, row < col
-                    const bool p1 = colok & (__builtin_fmaf(-2.f, g, ncol) <= pr[v]) &
+                    const bool p1 = colok & (__builtin_fmaf(-2.f, g, ncol) <= pr[v8]) &
                                     !(diag & ((row > col) | ((row == col) & (exclude_self != 0))));
-                    const bool p2 = (!diag | (row < col)) & (row < m) & (__builtin_fmaf(-2.f, g, nr[v]) <= phicol);
+                    const bool p2 = (!diag | (row < col)) & (row < m) & (__builtin_fmaf(-2.f, g, nr[v8]) <= phicol);
                     bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
                     mk[v8] = __ballot(p1 || p2);
                     tot += (uint32_t)__popcll(mk[v8]);
