@@ -136,11 +136,14 @@ __device__ inline void pair_bounds(float na, float nb, float ra, float rb, float
         lb = 0.f;
         ub = INFINITY;
     }
+    lb = fminf(lb, 3.40282347e38f);  // +inf marks a Phase I slot that no pair fills, never a pair
 }
 
 // Where a tile's pairs go.
-//  mode 0 (Phase I, the first trees): every pair of the leaf, at the fixed slot
-//          row * cap + (tree - t0) * ML + (position of the column in its leaf);
+//  mode 0 (Phase I, the first trees): every pair of the leaf, as (lb, ub) at the fixed slot
+//          row * cap + (tree - t0) * ML + (position of the column in its leaf); the slot
+//          names the column (the leaf's permutation segment holds its index) and lb = +inf
+//          marks a slot that no pair fills;
 //  mode 1 (Phase II): pairs with lb <= tau(row), appended at row * cap + atomic count.
 struct TileOut {
     int mode;
@@ -150,9 +153,9 @@ struct TileOut {
     Ent *ent;          // mode 1 records
     int32_t *cnt;      // mode 1 counters
     const float *tau;  // mode 1 thresholds
-    int32_t *pidx;     // mode 0: index / lb / ub arrays (-1, +inf, +inf where empty)
-    float *plb;
-    float *pub;
+    float2 *plub;      // mode 0: (lb, ub) per slot, (+inf, +inf) where empty
+    int32_t *roff;     // mode 0: [tree - t0][nrows] start of the row's leaf in the permutation
+    int64_t nrows;
 };
 
 constexpr int kQueue = 512;  // per-wave queue of Phase II pairs that pass the cheap test
@@ -168,13 +171,11 @@ __device__ inline Ent make_ent(int idx, float lb, float ub) {
 
 __device__ inline Ent invalid_rec() { return make_ent(-1, INFINITY, INFINITY); }
 
-__device__ inline void put_first(const TileOut &o, int64_t slot, int idx, float lb, float ub) {
-    o.pidx[slot] = idx;
-    o.plb[slot] = lb;
-    o.pub[slot] = ub;
+__device__ inline void put_first(const TileOut &o, int64_t slot, float lb, float ub) {
+    o.plub[slot] = make_float2(lb, ub);
 }
 
-__device__ inline void put_first_empty(const TileOut &o, int64_t slot) { put_first(o, slot, -1, INFINITY, INFINITY); }
+__device__ inline void put_first_empty(const TileOut &o, int64_t slot) { put_first(o, slot, INFINITY, INFINITY); }
 
 __device__ inline void emit_filtered(const TileOut &o, int a_pt, int b_pt, float lb, float ub) {
     const int slot = atomicAdd(&o.cnt[a_pt], 1);
@@ -274,8 +275,10 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
         const bool last = job.b_pos + job.b_rows == job.leaf_m;
         for (int r = tid; r < job.a_rows; r += NT) {
             const int64_t er = (int64_t)s_dst[r] * out.cap + (int64_t)tb * out.ML;
-            if (last)
+            if (last) {
                 for (int c = job.leaf_m; c < out.ML; c++) put_first_empty(out, er + c);
+                out.roff[(int64_t)tb * out.nrows + s_dst[r]] = (int32_t)(job.b_off - job.b_pos);
+            }
             if (same && exclude_self) put_first_empty(out, er + job.b_pos + r);
         }
     }
@@ -321,14 +324,13 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
             const int col = 32 * cb + (lane & 31);
             if (col >= job.b_rows) continue;
             const float nb = s_nb[col], rb = s_rb[col];
-            const int bpt = s_bpt[col];
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 if (row >= job.a_rows || (same && exclude_self && row == col)) continue;
                 float lb, ub;
                 pair_bounds(s_na[row], nb, s_ra[row], rb, acc[cb][v], bc, lb, ub);
-                put_first(out, (int64_t)s_dst[row] * out.cap + (int64_t)tb * out.ML + job.b_pos + col, bpt, lb, ub);
+                put_first(out, (int64_t)s_dst[row] * out.cap + (int64_t)tb * out.ML + job.b_pos + col, lb, ub);
             }
         }
         return;
@@ -468,6 +470,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             const int64_t er = (int64_t)s_pt[r] * out.cap + (int64_t)tb * out.ML;
             for (int c = m; c < out.ML; c++) put_first_empty(out, er + c);
             if (exclude_self) put_first_empty(out, er + r);
+            out.roff[(int64_t)tb * out.nrows + s_pt[r]] = (int32_t)job.a_off;
         }
     }
 
@@ -541,7 +544,6 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
             const int cl = lane & 31, col = 32 * bj + cl;
             const bool colok = col < m;
             const float ncol = s_n[colok ? col : 0], rcol = s_r[colok ? col : 0];
-            const int pcol = s_pt[colok ? col : 0];
             float lbv[16], ubv[16];
 #pragma unroll
             for (int v = 0; v < 16; v++) {
@@ -549,9 +551,11 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
                 const bool rowok = row < m;
                 pair_bounds(s_n[rowok ? row : 0], ncol, s_r[rowok ? row : 0], rcol, acc[sl][v], bc, lbv[v], ubv[v]);
                 if (colok && rowok && !(diag && (row > col || (row == col && exclude_self))))
-                    put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, pcol, lbv[v], ubv[v]);
+                    put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, lbv[v], ubv[v]);
             }
-            // transposed: output row = column c of the block, positions 32 bi + r
+            // transposed: output row = column c of the block, positions 32 bi + r; lb goes
+            // through the transpose first (kept in registers), then ub, then both are stored
+            float lbt[16];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 float *src = h ? ubv : lbv;
@@ -559,18 +563,17 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
 #pragma unroll
                 for (int v = 0; v < 16; v++) tr[cl * 33 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)] = src[v];
                 wave_sync();
+#pragma unroll
                 for (int c0 = 0; c0 < 32; c0 += 2) {
                     const int c = c0 + (lane >> 5), r = lane & 31;
-                    const int cg = 32 * bj + c, rg = 32 * bi + r;
-                    if (cg < m && rg < m && rg != cg && !(diag && rg > cg)) {
-                        const int64_t slot = (int64_t)s_pt[cg] * out.cap + (int64_t)tb * out.ML + rg;
-                        const float val = tr[c * 33 + r];
-                        if (h) {
-                            out.pub[slot] = val;
-                        } else {
-                            out.plb[slot] = val;
-                            out.pidx[slot] = s_pt[rg];
-                        }
+                    const float val = tr[c * 33 + r];
+                    if (h == 0) {
+                        lbt[c0 >> 1] = val;
+                    } else {
+                        const int cg = 32 * bj + c, rg = 32 * bi + r;
+                        if (cg < m && rg < m && rg != cg && !(diag && rg > cg))
+                            out.plub[(int64_t)s_pt[cg] * out.cap + (int64_t)tb * out.ML + rg] =
+                                make_float2(lbt[c0 >> 1], val);
                     }
                 }
             }
@@ -715,6 +718,7 @@ __global__ __launch_bounds__(256) void k_qtile(const TileJob *__restrict__ jobs,
             const int dq = a_dest[t * a_stride_tree + job.a_off + qi];
             const int64_t er = (int64_t)dq * out.cap + (int64_t)tb * out.ML;
             for (int c = job.leaf_m + lane; c < out.ML; c += 64) put_first_empty(out, er + c);
+            if (lane == 0) out.roff[(int64_t)tb * out.nrows + dq] = (int32_t)(job.b_off - job.b_pos);
         }
     }
     for (int r0 = 0; r0 < job.b_rows; r0 += 8) {
@@ -753,7 +757,7 @@ __global__ __launch_bounds__(256) void k_qtile(const TileJob *__restrict__ jobs,
             float lb, ub;
             pair_bounds(aq.x, nb.x, aq.y, nb.y, gq, bc, lb, ub);
             if (out.mode == 0)
-                put_first(out, (int64_t)dst * out.cap + (int64_t)tb * out.ML + job.b_pos + r, bpt, lb, ub);
+                put_first(out, (int64_t)dst * out.cap + (int64_t)tb * out.ML + job.b_pos + r, lb, ub);
             else if (lb <= tq)
                 emit_filtered(out, dst, bpt, lb, ub);
         }
@@ -820,11 +824,17 @@ constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
 constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
 constexpr int kSetCap = 512;
 
+struct SlotIndex {  // where the index of a Phase I slot comes from: the row's leaf in the tree
+    const int32_t *roff;  // [B][nrows] start of the row's leaf in the permutation
+    const int32_t *perm;  // [T][n] leaf-ordered permutation
+    int64_t n;
+};
+
 template <int Q, int HT>
 __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int ML,
-                                                     const int32_t *__restrict__ pidx, const float *__restrict__ plb,
-                                                     const float *__restrict__ pub, int cap, float *__restrict__ tau,
-                                                     Ent *__restrict__ list, int32_t *__restrict__ lcnt, int lcap,
+                                                     const float2 *__restrict__ plub, SlotIndex si, int cap,
+                                                     float *__restrict__ tau, Ent *__restrict__ list,
+                                                     int32_t *__restrict__ lcnt, int lcap,
                                                      int32_t *__restrict__ cnt) {
     // per-wave open-addressing hash of the small set: index -> smallest (ub, slot) packed as
     // ub bits << 32 | slot (the order the representatives are defined by)
@@ -845,17 +855,29 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
         }
         return;
     }
+    // the row's leaf in each of the B trees: lane t holds its start in the permutation
+    const int32_t loff = lane < B ? si.roff[(int64_t)lane * nrows + a] : 0;
+    const float inv_ml = 1.f / (float)ML;
     uint32_t u[Q];  // ub bits of the finite slots, 0xffffffff for the others
     float l[Q];
-    int32_t id[Q];
+    int32_t id[Q];  // -1 for a slot that no pair fills (lb = +inf)
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
         const bool in = i < c;
-        const uint32_t ub = in ? fkey(pub[base_slot + i]) : 0xffffffffu;
+        const float2 e = in ? plub[base_slot + i] : make_float2(INFINITY, INFINITY);
+        const uint32_t ub = fkey(e.y);
         u[q] = ub < 0x7f800000u ? ub : 0xffffffffu;
-        l[q] = in ? plb[base_slot + i] : INFINITY;
-        id[q] = in ? pidx[base_slot + i] : -1;
+        l[q] = e.x;
+        // the slot's tree: (i + 1/2) / ML in binary32 stays at least 1/(2 ML) away from
+        // the integers, well above its rounding, so the floor is exact (i, ML < 2^12)
+        const int tb = (int)(((float)i + 0.5f) * inv_ml);
+        // the permutation entry is read whatever the slot holds (clamped into the tree), so
+        // that it does not wait for the slot's bounds; an empty slot drops it
+        const int32_t off = __shfl(loff, in ? tb : 0, 64);
+        const int64_t pos = min((int64_t)off + (i - tb * ML), si.n - 1);
+        const int32_t pv = in ? si.perm[(int64_t)tb * si.n + pos] : -1;
+        id[q] = e.x < INFINITY ? pv : -1;
     }
     for (int i = lane; i < HT; i += 64) {
         s_hid[w][i] = -1;
@@ -1690,7 +1712,7 @@ static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get g
     cand_caps(K, v.T, cs.B, w.lcap, w.cap2);
     w.cap1 = v.max_leaf * cs.B;      // Phase I slots per row (index / lb / ub arrays)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
-    const size_t first_bytes = (size_t)rows * w.cap1 * 12;
+    const size_t first_bytes = (size_t)rows * w.cap1 * 8 + (size_t)rows * cs.B * 4;  // slots, leaf starts
     const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
     w.region = static_cast<uint8_t *>(get(std::max(first_bytes, second_bytes) + 256));
     w.tau = static_cast<float *>(get(rows * 4));
@@ -1725,9 +1747,8 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     int32_t *cnt = w.cnt, *lcnt = w.lcnt, *fb_list = w.fb_list, *fb_cnt = w.fb_cnt;
     Ent *list = w.list;
     Ent *ent = reinterpret_cast<Ent *>(region);
-    int32_t *pidx = reinterpret_cast<int32_t *>(region);
-    float *plb = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 4);
-    float *pub = reinterpret_cast<float *>(region + (size_t)rows * cap1 * 8);
+    float2 *plub = reinterpret_cast<float2 *>(region);
+    int32_t *roff = reinterpret_cast<int32_t *>(region + (size_t)rows * cap1 * 8);
     fill_u32(cnt, rows, 0, s);
     fill_u32(fb_cnt, 4, 0, s);
     fill_u32(v.stats, kStatSlots * 8 * 2, 0, s);
@@ -1741,9 +1762,9 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     o1.ent = nullptr;
     o1.cnt = cnt;
     o1.tau = nullptr;
-    o1.pidx = pidx;
-    o1.plb = plb;
-    o1.pub = pub;
+    o1.plub = plub;
+    o1.roff = roff;
+    o1.nrows = rows;
     {
         ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
         if (cs.sym)
@@ -1761,8 +1782,9 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         // hash table of the small set: room for twice its largest regular size (K B entries
         // plus ties)
         const bool big = K * cs.B > 128;
+        const SlotIndex si{roff, v.perm, v.n};
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, pidx, plb, pub, cap1, tau, list,
+            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, plub, si, cap1, tau, list,
                                lcnt, lcap, cnt);
         };
         if (cap1 <= 256) big ? go(k_merge_first<4, 1024>) : go(k_merge_first<4, 512>);
@@ -1895,7 +1917,8 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
         for (int B = 1; B <= cs.B; B++) {
             cand_caps(K, v.T, B, lcap, cap2);
             const size_t cap1 = (size_t)v.max_leaf * B;
-            b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 12, (size_t)v.n * cap2 * sizeof(Ent)) + 256);
+            b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 8 + (size_t)v.n * B * 4,
+                                                   (size_t)v.n * cap2 * sizeof(Ent)) + 256);
             b_list = std::max(b_list, (size_t)v.n * lcap * sizeof(Ent));
         }
         b_rows = std::max(b_rows, (size_t)v.n * 4);
@@ -2076,7 +2099,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     int lcap = 0, cap2 = 0;
     cand_caps(K, v.T, B, lcap, cap2);
     const uint64_t cap1 = (uint64_t)v.max_leaf * B;
-    b += std::max(m * cap1 * 12, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
+    b += std::max(m * cap1 * 8 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
 }
