@@ -995,10 +995,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
     __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
-    __shared__ int32_t s_r[4][kRCap];
+    __shared__ int32_t s_r[4][kRCap];   // the rerank set R; then, compacted in place, the window
     __shared__ uint32_t s_d[4][kRCap];
-    __shared__ int32_t s_wi[4][kWCap];
-    __shared__ double s_wd[4][kWCap];
     extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
@@ -1128,19 +1126,27 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         d32k = __uint_as_float(wave_kth_upper<kRCap / 64>(dv, K - 1));
     }
     const float wcut = d32k * (1.f + A.win);
-    int nw = 0;  // the window: binary32 distance within w of the K-th; ordered in binary64
+    // the window: binary32 distance within w of the K-th; ordered in binary64.  It is
+    // compacted in place over R (a member's new position is at most its old one, and each
+    // round reads its 64 entries before any of them is written)
+    int32_t *s_wi = s_r[w];
+    double *s_wd = s_dd;
+    int nw = 0;
     for (int base = 0; base < nr; base += 64) {
         const int i = base + lane;
         const bool in = i < nr && __uint_as_float(s_d[w][i]) <= wcut;
+        const int32_t ri = i < nr ? s_r[w][i] : 0;
+        const double rd = i < nr ? s_dd[i] : 0.0;
         const uint64_t mk = __ballot(in);
         const int pos = nw + mask_rank(mk);
+        wave_sync();
         if (in && pos < kWCap) {
-            s_wi[w][pos] = s_r[w][i];
-            s_wd[w][pos] = s_dd[i];
+            s_wi[pos] = ri;
+            s_wd[pos] = rd;
         }
         nw += __popcll(mk);
+        wave_sync();
     }
-    wave_sync();
     if (nw > kWCap) {  // pathological window (massive distance ties): exhaustive path
         if (lane == 0) push_fallback(A, a);
         return;
@@ -1148,8 +1154,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     int P2 = 1;
     while (P2 < nw) P2 <<= 1;
     for (int i = nw + lane; i < P2; i += 64) {
-        s_wd[w][i] = INFINITY;
-        s_wi[w][i] = 0x7fffffff;
+        s_wd[i] = INFINITY;
+        s_wi[i] = 0x7fffffff;
     }
     wave_sync();
     for (int size = 2; size <= P2; size <<= 1) {  // bitonic sort by (D64, index)
@@ -1158,14 +1164,14 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
-                const double dl = s_wd[w][lo], dh = s_wd[w][hi];
-                const int il = s_wi[w][lo], ih = s_wi[w][hi];
+                const double dl = s_wd[lo], dh = s_wd[hi];
+                const int il = s_wi[lo], ih = s_wi[hi];
                 const bool gt = dl > dh || (dl == dh && il > ih);
                 if (gt == up) {
-                    s_wd[w][lo] = dh;
-                    s_wd[w][hi] = dl;
-                    s_wi[w][lo] = ih;
-                    s_wi[w][hi] = il;
+                    s_wd[lo] = dh;
+                    s_wd[hi] = dl;
+                    s_wi[lo] = ih;
+                    s_wi[hi] = il;
                 }
             }
             wave_sync();
@@ -1173,8 +1179,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     }
     for (int k = lane; k < K; k += 64) {
         const bool ok = k < nw;
-        A.out_idx[a * K + k] = ok ? s_wi[w][k] : -1;
-        A.out_dist[a * K + k] = ok ? (float)sqrt(s_wd[w][k]) : INFINITY;
+        A.out_idx[a * K + k] = ok ? s_wi[k] : -1;
+        A.out_dist[a * K + k] = ok ? (float)sqrt(s_wd[k]) : INFINITY;
     }
     if (lane == 0) {
         stat_add(A, 0, 1ull);
