@@ -403,17 +403,24 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
 // (row -> col) and (col -> row).  Block rows p and NB-1-p form a pair of NB + 1 blocks,
 // split between two waves (ceil and floor of half), so NB waves share the triangle evenly;
 // both operands come from the same LDS tile.  Blocks wholly past the leaf are skipped.
+//
+// Phase II at NB = 8 runs 12 waves: three per pair of block rows, three blocks each, so the
+// accumulators take 48 registers rather than 80 and six waves share a SIMD instead of four.
+constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE == 1 && NB == 8 ? 12 : NB) : 1; }
+
 template <int NB, int PREC, int MODE>
-__global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
+__global__ __launch_bounds__(64 * sym_waves(NB, MODE)) void k_tile_sym(
     const TileJob *__restrict__ jobs, const void *__restrict__ A_, int dp, int64_t stride_tree,
     const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, int exclude_self, TileOut out) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
-    constexpr int NW = NB >= 2 ? NB : 1;
+    constexpr int NW = sym_waves(NB, MODE);
     constexpr int NT = 64 * NW;
     constexpr int PAIR = NB + 1;
-    constexpr int SLOTS = NB >= 2 ? (PAIR + 1) / 2 : 1;
+    constexpr int WPP = NB >= 2 ? NW / (NB / 2) : 1;  // waves per pair of block rows
+    constexpr int SLOTS = NB >= 2 ? (PAIR + WPP - 1) / WPP : 1;
+    constexpr int QL = NW > 8 ? 384 : kQueue;         // queue entries per wave (LDS for two blocks)
     __shared__ __align__(16) T s_a[M * C::LDW];
     __shared__ __align__(16) float s_n[M];
     __shared__ __align__(16) float s_r[M];
@@ -421,7 +428,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
     __shared__ float s_tau[M];
     __shared__ int32_t s_pt[M];
     __shared__ float s_max[2];
-    __shared__ uint2 s_que[MODE == 1 ? NW : 1][MODE == 1 ? kQueue : 1];
+    __shared__ uint2 s_que[MODE == 1 ? NW : 1][MODE == 1 ? QL : 1];
 
     const TileJob job = jobs[blockIdx.x];
     const int t = job.tree;
@@ -483,7 +490,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
         if (NB == 1) {
             bi = bj = 0;
         } else {
-            const int p = wu >> 1, q = (wu & 1) * SLOTS + sl;
+            const int p = wu / WPP, q = (wu % WPP) * SLOTS + sl;
             const int r1 = p, r2 = NB - 1 - p, len1 = NB - r1;
             if (q < len1) {
                 bi = r1;
@@ -638,7 +645,7 @@ __global__ __launch_bounds__(NB >= 2 ? 64 * NB : 64) void k_tile_sym(
                     mk[v8] = __ballot(p1 || p2);
                     tot += (uint32_t)__popcll(mk[v8]);
                 }
-                if (qc + tot > (uint32_t)kQueue) {
+                if (qc + tot > (uint32_t)QL) {
                     flush(qc);
                     qc = 0;
                 }
@@ -1661,7 +1668,7 @@ template <int NB, int PREC>
 static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
                        const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
-    constexpr int NT = NB >= 2 ? 64 * NB : 64;
+    const int NT = 64 * sym_waves(NB, out.mode);
     const dim3 g((unsigned)njobs);
     if (out.mode == 0)
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt, bc, excl, out);
