@@ -1197,6 +1197,262 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     }
 }
 
+// ---------------------------------------------------------------- final merge, one block per row
+
+// For rows whose list plus Phase II records exceed one wave's 64 Q (large K against many
+// trees): the same steps as k_final with the 256 threads of a block on one row, up to 4096
+// records (16 per thread).  Selections are the same ballot bisection, with each bit's count
+// summed over the four waves.
+constexpr int kBigQ = 16;
+constexpr int kBigCap = 256 * kBigQ;   // list + Phase II records per row
+constexpr int kBigHT = 2 * kBigCap;    // index hash (twice the records); later R's binary64 distances
+constexpr int kBigHBits = 13;          // log2(kBigHT)
+constexpr int kBigRCap = 1024;         // rerank set R
+constexpr int kBigWCap = 512;          // binary64 window
+static_assert((1 << kBigHBits) == kBigHT, "hash range must equal the table");
+static_assert(kBigHT / 2 >= kBigRCap, "the dead hash table holds R's binary64 distances");
+
+// block-wide (256 threads) reductions through 4 LDS words; every thread gets the result
+__device__ inline uint32_t block_sum4(uint32_t v, uint32_t *s4) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
+__device__ inline uint32_t block_min4(uint32_t v, uint32_t *s4) {
+    v = wave_min_u32(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return min(min(s4[0], s4[1]), min(s4[2], s4[3]));
+}
+
+__device__ inline uint32_t block_max4(uint32_t v, uint32_t *s4) {
+    v = wave_max_u32(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return max(max(s4[0], s4[1]), max(s4[2], s4[3]));
+}
+
+// wave_kth_upper over the keys a block holds Q per thread (0xffffffff: not taking part)
+template <int Q>
+__device__ inline uint32_t block_kth_upper(const uint32_t (&v)[Q], int k, uint32_t *s4) {
+    constexpr int kLow = 13;
+    uint32_t lo = 0xffffffffu, hi = 0;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        lo = min(lo, v[q]);
+        hi = max(hi, v[q] == 0xffffffffu ? 0u : v[q]);
+    }
+    lo = block_min4(lo, s4);
+    hi = block_max4(hi, s4);
+    if (lo >= hi) return lo;
+    const int hb = 31 - __builtin_clz(lo ^ hi);
+    if (hb < kLow) return hi;
+    uint32_t ans = hb >= 31 ? 0u : (lo & ~((2u << hb) - 1u));
+    for (int b = hb; b >= kLow; b--) {
+        const uint32_t t = ans | (1u << b);
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < Q; q++) c += (uint32_t)__popcll(__ballot(v[q] < t));
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if ((s4[0] + s4[1]) + (s4[2] + s4[3]) <= (uint32_t)k) ans = t;
+    }
+    return min(ans | ((1u << kLow) - 1u), hi);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
+    __shared__ __align__(16) int32_t s_key[kBigHT];  // index hash; then R's binary64 distances
+    __shared__ int32_t s_r[kBigRCap];                // R; then, compacted, the window
+    __shared__ uint32_t s_d[kBigRCap];
+    __shared__ uint32_t s4[4];    // reductions and selection counts
+    __shared__ uint32_t s_sc[4];  // block scans
+    extern __shared__ __align__(16) float s_q[];      // the query row (d floats)
+    const int tid = threadIdx.x, lane = tid & 63, g = lane & 7, grp = tid >> 3;
+    const int64_t a = blockIdx.x;
+    const int K = A.K;
+    const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    if (tid == 0) {
+        stat_add(A, 5, (unsigned long long)max(c1, 0));
+        stat_add(A, 6, (unsigned long long)max(c2, 0));
+    }
+    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kBigCap) {
+        if (tid == 0) push_fallback(A, a);
+        return;
+    }
+    for (int i = tid; i < kBigHT; i += 256) s_key[i] = -1;
+    for (int j = tid; j < A.d; j += 256) s_q[j] = A.Qr[a * A.d + j];
+    __syncthreads();
+    Ent ev[kBigQ];  // every record of the row is loaded first
+#pragma unroll
+    for (int q = 0; q < kBigQ; q++) {
+        const int i = tid + 256 * q;
+        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+    }
+    int32_t eidx[kBigQ];
+    uint32_t elb[kBigQ], fu[kBigQ];  // lb keys; ub keys of first copies (others masked out)
+    bool bad = false;
+    uint32_t nd_mine = 0;
+#pragma unroll
+    for (int q = 0; q < kBigQ; q++) {
+        const Ent e = ev[q];
+        eidx[q] = -1;
+        elb[q] = 0xffffffffu;
+        fu[q] = 0xffffffffu;
+        bad |= e.idx < -1 || (int64_t)e.idx >= A.npts;
+        if (e.idx >= 0 && (int64_t)e.idx < A.npts) {
+            eidx[q] = e.idx;
+            elb[q] = fkey(e.lb);
+            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kBigHBits);
+            while (true) {  // at most half full: a free or matching entry is always found
+                const int old = atomicCAS(&s_key[h], -1, e.idx);
+                if (old == -1) {
+                    fu[q] = fkey(e.ub);
+                    nd_mine++;
+                    break;
+                }
+                if (old == e.idx) break;
+                h = (h + 1) & (kBigHT - 1);
+            }
+        }
+    }
+    if (__syncthreads_or(bad)) {  // counted for the host to report; the row is recomputed exhaustively
+        if (tid == 0) {
+            stat_add(A, 4, 1ull);
+            push_fallback(A, a);
+        }
+        return;
+    }
+    const uint32_t nd = block_sum4(nd_mine, s4);
+    float tv = INFINITY;
+    if (nd >= (uint32_t)K) tv = __uint_as_float(block_kth_upper<kBigQ>(fu, K - 1, s4));
+    const uint32_t tp = fkey(tv * (1.f + 1e-6f));
+    // R = {first copies with lb <= tau'}: per-thread counts, one block scan, then the writes
+    uint32_t rc = 0;
+#pragma unroll
+    for (int q = 0; q < kBigQ; q++) rc += (fu[q] != 0xffffffffu && elb[q] <= tp) ? 1u : 0u;
+    uint32_t rbase, nr;
+    block_excl_scan256(rc, s_sc, rbase, nr);
+    if (nr > (uint32_t)kBigRCap) {
+        if (tid == 0) push_fallback(A, a);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kBigQ; q++)
+        if (fu[q] != 0xffffffffu && elb[q] <= tp) s_r[rbase++] = eidx[q];
+    __syncthreads();  // R is complete and the hash is dead: it holds the binary64 distances now
+    double *s_dd = reinterpret_cast<double *>(s_key);
+    if constexpr (VEC) {  // 32 groups of eight lanes, two candidates each at a time
+        for (int base = 0; base < (int)nr; base += 64) {
+            const int i0 = base + grp, i1 = i0 + 32;
+            const int b0 = s_r[i0 < (int)nr ? i0 : 0], b1 = s_r[i1 < (int)nr ? i1 : 0];
+            float D32[2];
+            double D64[2];
+            group8_dist32_64x2(s_q, A.X + (int64_t)b0 * A.d, A.X + (int64_t)b1 * A.d, A.d, g, D32, D64);
+            if (g == 0 && i0 < (int)nr) {
+                s_d[i0] = fkey(D32[0]);
+                s_dd[i0] = D64[0];
+            }
+            if (g == 0 && i1 < (int)nr) {
+                s_d[i1] = fkey(D32[1]);
+                s_dd[i1] = D64[1];
+            }
+        }
+    } else {
+        for (int base = 0; base < (int)nr; base += 32) {
+            const int i = base + grp;
+            const int b = s_r[i < (int)nr ? i : 0];
+            float D32;
+            double D64;
+            group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
+            if (g == 0 && i < (int)nr) {
+                s_d[i] = fkey(D32);
+                s_dd[i] = D64;
+            }
+        }
+    }
+    __syncthreads();
+    constexpr int RQ = kBigRCap / 256;
+    float d32k = INFINITY;
+    if (nr >= (uint32_t)K) {
+        uint32_t dv[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const int i = tid + 256 * q;
+            dv[q] = i < (int)nr ? s_d[i] : 0xffffffffu;
+        }
+        d32k = __uint_as_float(block_kth_upper<RQ>(dv, K - 1, s4));
+    }
+    const float wcut = d32k * (1.f + A.win);
+    // the window, compacted in place over R: everything is read before anything is written
+    int32_t wi[RQ];
+    double wd[RQ];
+    uint32_t wc = 0;
+#pragma unroll
+    for (int q = 0; q < RQ; q++) {
+        const int i = tid + 256 * q;
+        const bool in = i < (int)nr && __uint_as_float(s_d[i]) <= wcut;
+        wi[q] = in ? s_r[i] : -1;
+        wd[q] = in ? s_dd[i] : 0.0;
+        wc += in ? 1u : 0u;
+    }
+    uint32_t wbase, nw;
+    block_excl_scan256(wc, s_sc, wbase, nw);  // its barriers also order the reads above before the writes
+    if (nw > (uint32_t)kBigWCap) {  // pathological window (massive distance ties): exhaustive path
+        if (tid == 0) push_fallback(A, a);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; q++)
+        if (wi[q] >= 0) {
+            s_r[wbase] = wi[q];
+            s_dd[wbase] = wd[q];
+            wbase++;
+        }
+    int P2 = 1;
+    while (P2 < (int)nw) P2 <<= 1;
+    for (int i = (int)nw + tid; i < P2; i += 256) {
+        s_dd[i] = INFINITY;
+        s_r[i] = 0x7fffffff;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {  // bitonic sort by (D64, index)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < P2 / 2; i += 256) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double dl = s_dd[lo], dh = s_dd[hi];
+                const int il = s_r[lo], ih = s_r[hi];
+                const bool gt = dl > dh || (dl == dh && il > ih);
+                if (gt == up) {
+                    s_dd[lo] = dh;
+                    s_dd[hi] = dl;
+                    s_r[lo] = ih;
+                    s_r[hi] = il;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = tid; k < K; k += 256) {
+        const bool ok = k < (int)nw;
+        A.out_idx[a * K + k] = ok ? s_r[k] : -1;
+        A.out_dist[a * K + k] = ok ? (float)sqrt(s_dd[k]) : INFINITY;
+    }
+    if (tid == 0) {
+        stat_add(A, 0, 1ull);
+        stat_add(A, 2, (unsigned long long)nr);
+        stat_add(A, 3, (unsigned long long)nw);
+    }
+}
+
 // ---------------------------------------------------------------- exhaustive fallback
 
 struct FallbackArgs {
@@ -1713,9 +1969,19 @@ struct CandWs {
 // Per-row capacities of the merged list and of the Phase II records, from K and the number
 // of Phase II trees (about K (T - B) / 2 records per row were measured on mixtures; twice that
 // plus a margin keeps overflow, which sends a row to the exhaustive path, rare).
-static void cand_caps(int K, int T, int B, int &lcap, int &cap2) {
+//
+// When that would exceed one wave's records (large K against many trees), rows go to the
+// block-per-row merge, with up to kBigCap records, as long as the Phase II buffers of all
+// rows stay within kBigBudget bytes.
+constexpr uint64_t kBigBudget = (uint64_t)2 << 30;
+static void cand_caps(int K, int T, int B, int64_t rows, int &lcap, int &cap2) {
     lcap = std::min(kListCap, std::max(64, 8 * K));
-    cap2 = std::min(kFinalCap - lcap, std::max(128, K * std::max(T - B, 0) + 64));
+    const int want = std::max(128, K * std::max(T - B, 0) + 64);
+    cap2 = std::min(kFinalCap - lcap, want);
+    if (want > kFinalCap - lcap) {
+        const int big = std::min(kBigCap - lcap, want);
+        if ((uint64_t)std::max<int64_t>(rows, 1) * big * sizeof(Ent) <= kBigBudget) cap2 = big;
+    }
 }
 
 // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
@@ -1723,7 +1989,7 @@ static void cand_caps(int K, int T, int B, int &lcap, int &cap2) {
 template <typename Get>
 static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
-    cand_caps(K, v.T, cs.B, w.lcap, w.cap2);
+    cand_caps(K, v.T, cs.B, rows, w.lcap, w.cap2);
     w.cap1 = v.max_leaf * cs.B;      // Phase I slots per row (index / lb / ub arrays)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
     const size_t first_bytes = (size_t)rows * w.cap1 * 8 + (size_t)rows * cs.B * 4;  // slots, leaf starts
@@ -1834,7 +2100,10 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         const dim3 grid((unsigned)((rows + 3) / 4));
         // the smallest per-lane record count that holds the list and the Phase II records
         const int need = lcap + cap2;
-        if (need <= 256) {
+        if (need > kFinalCap) {  // one block per row
+            if (vec) hipLaunchKernelGGL(k_final_blk<true>, dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
+            else hipLaunchKernelGGL(k_final_blk<false>, dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
+        } else if (need <= 256) {
             if (vec) hipLaunchKernelGGL((k_final<true, 4>), grid, dim3(256), lds, s, fa, rows);
             else hipLaunchKernelGGL((k_final<false, 4>), grid, dim3(256), lds, s, fa, rows);
         } else if (need <= 512) {
@@ -1926,10 +2195,10 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
         const ForestView v = view(parts[i]);
         const CandStage cs = all_points_stage(v, K, exclude_self, maxB[i]);
         int lcap = 0, cap2 = 0;
-        cand_caps(K, v.T, cs.B, lcap, cap2);
+        cand_caps(K, v.T, cs.B, v.n, lcap, cap2);
         // capacities grow with B for cap1 and shrink for cap2: take each over 1..B
         for (int B = 1; B <= cs.B; B++) {
-            cand_caps(K, v.T, B, lcap, cap2);
+            cand_caps(K, v.T, B, v.n, lcap, cap2);
             const size_t cap1 = (size_t)v.max_leaf * B;
             b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 8 + (size_t)v.n * B * 4,
                                                    (size_t)v.n * cap2 * sizeof(Ent)) + 256);
@@ -1967,7 +2236,7 @@ void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *ou
     const ForestView v = view(f);
     const CandStage cs = all_points_stage(v, p->K, p->excl, B);
     CandWs w = p->w;
-    cand_caps(p->K, v.T, cs.B, w.lcap, w.cap2);
+    cand_caps(p->K, v.T, cs.B, v.n, w.lcap, w.cap2);
     w.cap1 = v.max_leaf * cs.B;
     cand_launches(v, cs, p->K, w, out_idx, out_dist, s);
 }
@@ -2111,7 +2380,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     b += (uint64_t)T * m * v.dp * esz + (uint64_t)T * m * 8;  // centred queries and norms
     b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob) * (qtile_qs(v.prec, v.dp) ? 2 : 1);
     int lcap = 0, cap2 = 0;
-    cand_caps(K, v.T, B, lcap, cap2);
+    cand_caps(K, v.T, B, m, lcap, cap2);
     const uint64_t cap1 = (uint64_t)v.max_leaf * B;
     b += std::max(m * cap1 * 8 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;

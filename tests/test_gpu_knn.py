@@ -50,6 +50,9 @@ ALL = [
     # half the points are one point: the copies' rows overflow their buffers with zero
     # distances and take the exhaustive path (asserted below)
     ("mass_ties", 4000, 8, 4, 200, 5, "fp32", "mixture", 2, 1),
+    # K 100 against 12 trees: list + Phase II capacity above one wave's records, so the rows
+    # take the block-per-row final merge
+    ("big_k_block_merge", 12000, 16, 12, 200, 100, "fp32", "mixture", 0, 1),
 ]
 
 
@@ -82,6 +85,8 @@ def test_all_knn_matches_oracle(case):
     print(f"    stats {st}", flush=True)
     if name == "mass_ties":
         assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
+    if name == "big_k_block_merge":
+        assert st["fallback_rows"] < n // 10, "the block merge sent most rows to the exhaustive path"
     f.free()
 
 
@@ -97,6 +102,8 @@ QUERY = [
     ("q_sparse_bf16_d200", 8000, 200, 3, 40, 8, "bf16", 150),
     ("q_sparse_fp32_d360", 6000, 360, 3, 40, 6, "fp32", 100),
     ("q_sparse_fp16_d600", 5000, 600, 3, 40, 6, "fp16", 60),
+    # K 100: the block-per-row final merge
+    ("q_big_k_fp16", 20000, 24, 10, 256, 100, "fp16", 500),
 ]
 
 
