@@ -1095,6 +1095,13 @@ void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T) {
     launch_check(s, "k_iota");
 }
 
+// Row stride of a leaf staged in LDS: an odd number of 16-byte chunks, so that the eight rows
+// a wave centres at once (one per group of eight lanes) fall in different bank groups.
+__host__ __device__ inline int leaf_row_stride(int d) {
+    const int s = (d + 3) & ~3;
+    return ((s >> 2) & 1) ? s : s + 4;
+}
+
 // Mean and centred copy of one leaf whose m rows (stride ds floats) are in LDS, by a block of
 // 512 threads: the centroid is a fixed-order sum (R row classes per column, then the classes
 // in order), so it is reproducible; then eight lanes per row write the centred row, four
@@ -1205,7 +1212,7 @@ __global__ __launch_bounds__(512) void k_leaf_staged(
     constexpr int NT = 512, KV = 16;
     const LeafDesc lf = leaves[blockIdx.x];
     const int m = lf.size;
-    const int ds = (d + 3) & ~3;
+    const int ds = leaf_row_stride(d);
     float *s_mu = s_rows + (size_t)m * ds;
     int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + ds);
     const int32_t *pp = perm + (int64_t)t * n + lf.off;
@@ -1265,13 +1272,14 @@ __global__ __launch_bounds__(512) void k_leaf_pipe(
     const float *__restrict__ X, int d, int dp, const LeafDesc *__restrict__ leaves, int nleaf, int ntree,
     const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ leaf_of,
     float *__restrict__ centroid, T *__restrict__ Xc, float2 *__restrict__ nrm, float range_max, int max_leaf) {
-    extern __shared__ __align__(16) float s_rows[];  // max_leaf rows of d floats, centroid (d), ids (max_leaf)
+    extern __shared__ __align__(16) float s_rows[];  // max_leaf rows of S floats, centroid (S), ids (max_leaf)
     __shared__ float s_part[512];
     constexpr int NT = 512, KV = 16;
     const int tid = threadIdx.x, q = d >> 2, G = gridDim.x;
     const int items = nleaf * ntree;
-    float *s_mu = s_rows + (size_t)max_leaf * d;
-    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + d);
+    const int S = leaf_row_stride(d);
+    float *s_mu = s_rows + (size_t)max_leaf * S;
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_mu + S);
     float r0[KV], r1[KV], r2[KV], r3[KV];  // the next item's row quarters (scalars stay in registers)
     // item w -> tree w / nleaf, leaf w % nleaf: neighbouring blocks take neighbouring leaves
     auto id_of = [&](int w) -> int32_t {  // member tid of item w (0 past its end)
@@ -1318,20 +1326,20 @@ __global__ __launch_bounds__(512) void k_leaf_pipe(
         for (int k = 0; k < KV; k++) {
             const int v = k * NT + tid;
             const int i = v / q, c = v - i * q;
-            if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * d)[c] = make_float4(r0[k], r1[k], r2[k], r3[k]);
+            if (v < tot) reinterpret_cast<float4 *>(s_rows + (size_t)i * S)[c] = make_float4(r0[k], r1[k], r2[k], r3[k]);
         }
         stage_ids(w + G, idn);
         __syncthreads();
         RPF_ISSUE_ROWS(w + G)  // in flight while item w is centred
         idn = id_of(w + 2 * G);
-        leaf_centre_staged<T>(s_rows, s_mu, s_part, m, d, d, dp, t, leaf, nleaf, lf, n, centroid, Xc, nrm,
+        leaf_centre_staged<T>(s_rows, s_mu, s_part, m, d, S, dp, t, leaf, nleaf, lf, n, centroid, Xc, nrm,
                               range_max);
     }
 #undef RPF_ISSUE_ROWS
 }
 
 size_t leaf_staged_lds(int d, int max_leaf) {  // dynamic part; 2 KB of static LDS come on top
-    return sizeof(float) * (size_t)((d + 3) & ~3) * ((size_t)max_leaf + 1) + sizeof(int32_t) * (size_t)max_leaf;
+    return sizeof(float) * (size_t)leaf_row_stride(d) * ((size_t)max_leaf + 1) + sizeof(int32_t) * (size_t)max_leaf;
 }
 
 template <typename T>
@@ -1384,7 +1392,8 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit) {
     dim3 grid(nleaf, T);
-    const size_t piped = sizeof(float) * ((size_t)max_leaf * d + d) + sizeof(int32_t) * (size_t)max_leaf;
+    const size_t piped = sizeof(float) * (size_t)leaf_row_stride(d) * ((size_t)max_leaf + 1) +
+                         sizeof(int32_t) * (size_t)max_leaf;
     if (d % 4 == 0 && max_leaf <= 512 && max_leaf * (d / 4) <= 512 * 16 && piped + 2048 <= (size_t)lds_limit &&
         (int64_t)nleaf * T < (1ll << 31)) {  // a leaf fits a block's registers and LDS: pipelined
         if (prec == RPF_DIST_BF16)
