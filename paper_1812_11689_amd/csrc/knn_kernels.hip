@@ -615,6 +615,7 @@ void k_tile_sym(
             const bool colok = col < m;
             const float ncol = s_n[col];
             const float phicol = s_phi[col];
+            const bool inner = !diag && 32 * bi + 32 <= m && 32 * bj + 32 <= m;  // wave-uniform
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 // the half's 8 rows of this lane come in two runs of four: their norms and
@@ -631,20 +632,33 @@ void k_tile_sym(
                 uint32_t bits = 0;  // (p1, p2) of the 8 values of this half, two bits each
                 uint64_t mk[8];
                 uint32_t tot = 0;
+                if (inner) {  // off the diagonal, every row and column real: the two tests alone
 #pragma unroll
-                for (int v8 = 0; v8 < 8; v8++) {
-                    const int v = 8 * h + v8;
-                    const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    const float g = acc[sl][v];
-                    // row -> col needs a real column and, on the diagonal block, row <= col
-                    // (row < col when the point itself is excluded); col -> row needs a real
-                    // row and, on the diagonal block, row < col
-                    const bool p1 = colok & (__builtin_fmaf(-2.f, g, ncol) <= pr[v8]) &
-                                    !(diag & ((row > col) | ((row == col) & (exclude_self != 0))));
-                    const bool p2 = (!diag | (row < col)) & (row < m) & (__builtin_fmaf(-2.f, g, nr[v8]) <= phicol);
-                    bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
-                    mk[v8] = __ballot(p1 || p2);
-                    tot += (uint32_t)__popcll(mk[v8]);
+                    for (int v8 = 0; v8 < 8; v8++) {
+                        const float g = acc[sl][8 * h + v8];
+                        const bool p1 = __builtin_fmaf(-2.f, g, ncol) <= pr[v8];
+                        const bool p2 = __builtin_fmaf(-2.f, g, nr[v8]) <= phicol;
+                        bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
+                        mk[v8] = __ballot(p1 || p2);
+                        tot += (uint32_t)__popcll(mk[v8]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v8 = 0; v8 < 8; v8++) {
+                        const int v = 8 * h + v8;
+                        const int row = 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        const float g = acc[sl][v];
+                        // row -> col needs a real column and, on the diagonal block, row <= col
+                        // (row < col when the point itself is excluded); col -> row needs a real
+                        // row and, on the diagonal block, row < col
+                        const bool p1 = colok & (__builtin_fmaf(-2.f, g, ncol) <= pr[v8]) &
+                                        !(diag & ((row > col) | ((row == col) & (exclude_self != 0))));
+                        const bool p2 =
+                            (!diag | (row < col)) & (row < m) & (__builtin_fmaf(-2.f, g, nr[v8]) <= phicol);
+                        bits |= ((p1 ? 1u : 0u) | (p2 ? 2u : 0u)) << (2 * v8);
+                        mk[v8] = __ballot(p1 || p2);
+                        tot += (uint32_t)__popcll(mk[v8]);
+                    }
                 }
                 if (qc + tot > (uint32_t)QL) {
                     flush(qc);
