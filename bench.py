@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--recall-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the recorded-plan (HIP graph) leg")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--copy-probe into per-kernel HBM traffic (markdown on stdout) and exit")
@@ -292,6 +293,38 @@ def main():
                         breakdown_ms_per_step={k: round(v["total_ms"] / args.steps, 3) for k, v in
                                                sorted(prof16.items(), key=lambda kv: -kv[1]["total_ms"])})
 
+    # the same job as one recorded HIP graph (rpf_plan_*: build and candidate stage, tuned
+    # first-phase tree count), inputs set once before the timed launches
+    def plan_leg(prec, ref_idx):
+        plan = rpf.Plan([n], [d], T, n0, K, dist_prec=prec)
+        try:
+            plan.set_inputs([X], [Rd])
+            plan.launch()
+            plan.check()
+            plan.tune()
+            for _ in range(max(args.warmup, 1)):
+                plan.launch()
+            plan.check()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                plan.launch()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            plan.check()
+            same = bool(torch.equal(plan.result(0)[0], ref_idx))
+            return dict(value=round(n * args.steps / el, 1), ms_per_step=round(el / args.steps * 1e3, 3),
+                        first_trees=plan.parts[0].get("first_trees"), identical_to_plain=same)
+        finally:
+            plan.close()
+
+    graph = None
+    if not args.no_graph:
+        graph = {"fp32": plan_leg("fp32", idx32)}
+        if res_bf16 is not None:
+            graph["bf16"] = plan_leg("bf16", idx16)
+        print(f"# recorded plan: {graph}", file=sys.stderr, flush=True)
+
     # recall against exact brute force on a seeded sample of points
     rng = np.random.default_rng(W.SEED_BASE + 300 + 2)
     pts = np.sort(rng.choice(n, size=min(args.recall_sample, n), replace=False))
@@ -303,8 +336,9 @@ def main():
     dom, roof = roofline(prof32)
     if roof is not None and dom is not None:
         tr = traffic_for(dom)
-        roof["traffic"] = None if tr is None else {"bytes_per_launch": tr, "unit": "B",
-                                                   "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+        roof["traffic"] = tr  # HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE), or None
+        if tr is not None:
+            roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
     breakdown = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(prof32.items(), key=lambda kv: -kv[1]["total_ms"])}
 
     f = rpf.build(X, T, n0, Rd, dist_prec="fp32")
@@ -349,6 +383,7 @@ def main():
         "step_ms_p50": round(float(np.percentile(times32, 50)) * 1e3, 3),
         "step_ms_p99": round(float(np.percentile(times32, 99)) * 1e3, 3),
         "bf16_rerank": res_bf16,
+        "recorded_plan": graph,
         "knn_stats": st,
         "breakdown_ms_per_step": breakdown,
         "roofline_kernel": dom,
