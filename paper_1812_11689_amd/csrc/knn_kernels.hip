@@ -810,9 +810,8 @@ __device__ inline uint32_t wave_max_u32(uint32_t x) {
 // the top, exactly when at most k keys lie below the candidate, counted by ballots (one
 // compare and one population count per entry and bit): no LDS and no atomics.  Every use
 // below is a threshold whose correctness only needs a value at or above the exact one.
-template <int Q>
+template <int Q, int kLow = 13>
 __device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], int k) {
-    constexpr int kLow = 13;
     uint32_t lo = 0xffffffffu, hi = 0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -909,7 +908,8 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 #pragma unroll
     for (int q = 0; q < Q; q++) nv += __popcll(__ballot(u[q] != 0xffffffffu));
     const int kb = K * B;
-    const uint32_t theta = nv >= kb ? wave_kth_upper<Q>(u, kb - 1) : 0x7f800000u;
+    // theta only bounds the small set from above: 2^-5 relative is close enough
+    const uint32_t theta = nv >= kb ? wave_kth_upper<Q, 18>(u, kb - 1) : 0x7f800000u;
     // the small set S = {finite slots with ub <= theta}, each entry hashed by its index
     int ns = 0;
 #pragma unroll
@@ -935,17 +935,32 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
             }
         }
         wave_sync();
-        // representatives: the entry of smallest (ub, slot) among equal indices
-        uint32_t rv[Q];
+        // representatives: the entry of smallest (ub, slot) among equal indices; their ub keys
+        // are compacted into the (now free) id column of the table, HT / 2 at most, and read
+        // back HT / 128 per lane for the selection
+        bool rep[Q];
+#pragma unroll
+        for (int q = 0; q < Q; q++)
+            rep[q] = hq[q] >= 0 &&
+                     s_hkey[w][hq[q]] == (((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q));
+        wave_sync();  // every lookup is done before the id column is overwritten
+        uint32_t *s_rv = reinterpret_cast<uint32_t *>(s_hid[w]);
         int nrep = 0;
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-            const bool rep = hq[q] >= 0 &&
-                             s_hkey[w][hq[q]] == (((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q));
-            rv[q] = rep ? u[q] : 0xffffffffu;
-            nrep += __popcll(__ballot(rep));
+            const uint64_t mk = __ballot(rep[q]);
+            if (rep[q]) s_rv[nrep + mask_rank(mk)] = u[q];
+            nrep += __popcll(mk);
         }
-        if (nrep >= K) tv = __uint_as_float(wave_kth_upper<Q>(rv, K - 1));
+        wave_sync();
+        constexpr int RQ = HT / 128;
+        uint32_t rv[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const int i = lane + 64 * q;
+            rv[q] = i < nrep ? s_rv[i] : 0xffffffffu;
+        }
+        if (nrep >= K) tv = __uint_as_float(wave_kth_upper<RQ>(rv, K - 1));
     }
     const float tp = tv * (1.f + 1e-6f);
     uint32_t kept = 0;
