@@ -1097,7 +1097,21 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         return;
     }
     float tv = INFINITY;
-    if (nd >= K) {
+    int nf = 0;
+    if (nd >= K && nd <= 256) {  // the usual case: first copies' ub keys compacted, 4 per lane
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const uint64_t mk = __ballot(first[q]);
+            if (first[q]) s_d[w][nf + mask_rank(mk)] = eub[q];
+            nf += __popcll(mk);
+        }
+        wave_sync();
+        uint32_t fu[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) fu[q] = lane + 64 * q < nd ? s_d[w][lane + 64 * q] : 0xffffffffu;
+        tv = __uint_as_float(wave_kth_upper<4>(fu, K - 1));
+        wave_sync();
+    } else if (nd >= K) {
         uint32_t fu[Q];  // ub keys of first copies, the others masked out
 #pragma unroll
         for (int q = 0; q < Q; q++) fu[q] = first[q] ? eub[q] : 0xffffffffu;
@@ -1153,7 +1167,10 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     }
     wave_sync();
     float d32k = INFINITY;
-    if (nr >= K) {
+    if (nr >= K && nr <= 64) {  // the usual case: one key per lane
+        uint32_t dv[1] = {lane < nr ? s_d[w][lane] : 0xffffffffu};
+        d32k = __uint_as_float(wave_kth_upper<1>(dv, K - 1));
+    } else if (nr >= K) {
         uint32_t dv[kRCap / 64];  // binary32 distance keys of R, the rest masked out
 #pragma unroll
         for (int q = 0; q < kRCap / 64; q++) {
