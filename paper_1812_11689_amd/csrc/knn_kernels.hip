@@ -1205,6 +1205,37 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         if (lane == 0) push_fallback(A, a);
         return;
     }
+    if (nw <= 64) {  // the usual case: a bitonic network across the wave's lanes, in registers
+        double dk = lane < nw ? s_wd[lane] : INFINITY;
+        int ik = lane < nw ? s_wi[lane] : 0x7fffffff;
+        for (int size = 2; size <= 64; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const double dp = __shfl_xor(dk, stride, 64);
+                const int ip = __shfl_xor(ik, stride, 64);
+                const bool mine_first = dk < dp || (dk == dp && ik <= ip);  // in (D64, index) order
+                const bool want_first = ((lane & stride) == 0) == ((lane & size) == 0);
+                if (mine_first != want_first) {
+                    dk = dp;
+                    ik = ip;
+                }
+            }
+        }
+        if (lane < K) {
+            const bool ok = lane < nw;
+            A.out_idx[a * K + lane] = ok ? ik : -1;
+            A.out_dist[a * K + lane] = ok ? (float)sqrt(dk) : INFINITY;
+        }
+        for (int k = 64 + lane; k < K; k += 64) {  // K above 64: nothing past the window
+            A.out_idx[a * K + k] = -1;
+            A.out_dist[a * K + k] = INFINITY;
+        }
+        if (lane == 0) {
+            stat_add(A, 0, 1ull);
+            stat_add(A, 2, (unsigned long long)nr);
+            stat_add(A, 3, (unsigned long long)nw);
+        }
+        return;
+    }
     int P2 = 1;
     while (P2 < nw) P2 <<= 1;
     for (int i = nw + lane; i < P2; i += 64) {
