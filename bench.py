@@ -69,7 +69,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the many-data-sets leg")
     ap.add_argument("--only-batched", action="store_true", help="run the many-data-sets leg alone (profiling)")
     ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
-    ap.add_argument("--cpu-trees", type=int, default=1,
+    ap.add_argument("--cpu-sample", type=int, default=20000,
+                    help="points whose all-points kNN the CPU baseline times (extrapolated to n)")
+    ap.add_argument("--cpu-trees", type=int, default=0,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
 
@@ -361,7 +363,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, R, pts[:500], K, args.cpu_trees)
+        crng = np.random.default_rng(W.SEED_BASE + 300 + 3)
+        cpts = np.sort(crng.choice(n, size=min(args.cpu_sample, n), replace=False))
+        cpu = cpu_baseline(w, R, cpts, K, args.cpu_trees)
 
     ms = el32 / args.steps * 1e3
     line = {
