@@ -118,6 +118,18 @@ void cache_free(void *p, hipStream_t s) {
     c.idle[b->dev].emplace(b->size, b);
 }
 
+void cache_free_idle(void *p) {
+    if (!p) return;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    Block *b = it->second;
+    c.live.erase(it);
+    b->pending = false;  // nothing queued uses it: no event to wait for
+    c.idle[b->dev].emplace(b->size, b);
+}
+
 uint64_t cache_held_bytes(int dev) {
     if (dev < 0 || dev >= 64) return 0;
     Cache &c = cache();

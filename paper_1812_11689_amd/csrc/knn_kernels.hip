@@ -2094,6 +2094,37 @@ void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s) {
     launch_check(s, "k_fill_u32");
 }
 
+__global__ void k_fill_u64(uint64_t *__restrict__ p, int64_t count, uint64_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+void fill_u64(void *p, int64_t count, uint64_t value, hipStream_t s) {
+    if (count <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, static_cast<uint64_t *>(p), count, value);
+    launch_check(s, "k_fill_u64");
+}
+
+// Every tree has the same leaf shapes, so the all-points tile list of tree 0 (jobs[0, njt))
+// is copied to trees 1 .. T - 1 with only the tree field changed.
+__global__ void k_replicate_jobs(TileJob *__restrict__ jobs, int64_t njt, int T) {
+    const int64_t total = njt * (T - 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / njt + 1, j = i - (t - 1) * njt;
+        TileJob jb = jobs[j];
+        jb.tree = (int32_t)t;
+        jobs[t * njt + j] = jb;
+    }
+}
+
+void replicate_jobs(TileJob *jobs, int64_t njt, int T, hipStream_t s) {
+    if (njt <= 0 || T <= 1) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((njt * (T - 1) + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_replicate_jobs, dim3(blocks), dim3(256), 0, s, jobs, njt, T);
+    launch_check(s, "k_replicate_jobs");
+}
+
 // the candidate stage as launches only (no allocation, no synchronisation)
 static void cand_launches(const ForestView &v, const CandStage &cs, int K, const CandWs &w, int32_t *out_idx,
                           float *out_dist, hipStream_t s) {

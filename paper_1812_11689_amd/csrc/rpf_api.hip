@@ -139,18 +139,80 @@ static void prof_drain() {
 
 // ---------------------------------------------------------------- validation kernels
 
+// *flag |= 1 when x holds a NaN or an infinity.  VEC: x 16-byte aligned, four values per access.
+template <bool VEC>
 __global__ void k_nonfinite(const float *__restrict__ x, int64_t count, int32_t *flag) {
     int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        bad |= !isfinite(x[i]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (VEC) {
+        const int64_t c4 = count >> 2;
+        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+        for (int64_t j = i; j < c4; j += stride) {
+            const float4 v = x4[j];
+            bad |= (int)!isfinite(v.x) | (int)!isfinite(v.y) | (int)!isfinite(v.z) | (int)!isfinite(v.w);
+        }
+        i += c4 << 2;  // the last count % 4 values
+        if (i < count) bad |= !isfinite(x[i]);
+    } else {
+        for (; i < count; i += stride) bad |= !isfinite(x[i]);
+    }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
 }
 
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag) {
     if (count <= 0) return;
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, x, count, flag);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    const int64_t per = vec ? 1024 : 256;
+    const int64_t blocks = std::min<int64_t>((count + per - 1) / per, 16384);
+    if (vec)
+        hipLaunchKernelGGL(k_nonfinite<true>, dim3((unsigned)blocks), dim3(256), 0, s, x, count, flag);
+    else
+        hipLaunchKernelGGL(k_nonfinite<false>, dim3((unsigned)blocks), dim3(256), 0, s, x, count, flag);
+}
+
+// The input copy and its check in one pass: dst = src, and *flag |= 1 when src holds a NaN or
+// an infinity.  VEC: both pointers 16-byte aligned, four values per access.
+template <bool VEC>
+__global__ void k_copy_nonfinite(const float *__restrict__ src, float *__restrict__ dst, int64_t count,
+                                 int32_t *flag) {
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (VEC) {
+        const int64_t c4 = count >> 2;
+        const float4 *s4 = reinterpret_cast<const float4 *>(src);
+        float4 *d4 = reinterpret_cast<float4 *>(dst);
+        for (int64_t j = i; j < c4; j += stride) {
+            const float4 v = s4[j];
+            bad |= (int)!isfinite(v.x) | (int)!isfinite(v.y) | (int)!isfinite(v.z) | (int)!isfinite(v.w);
+            d4[j] = v;
+        }
+        i += c4 << 2;  // the last count % 4 values, one per thread of the first threads
+        if (i < count) {
+            const float v = src[i];
+            bad |= !isfinite(v);
+            dst[i] = v;
+        }
+    } else {
+        for (; i < count; i += stride) {
+            const float v = src[i];
+            bad |= !isfinite(v);
+            dst[i] = v;
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+void launch_copy_nonfinite(hipStream_t s, const float *src, float *dst, int64_t count, int32_t *flag) {
+    if (count <= 0) return;
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+    const int64_t per = vec ? 1024 : 256;  // values one 256-thread block covers per sweep
+    const int64_t blocks = std::min<int64_t>((count + per - 1) / per, 16384);
+    if (vec)
+        hipLaunchKernelGGL(k_copy_nonfinite<true>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count, flag);
+    else
+        hipLaunchKernelGGL(k_copy_nonfinite<false>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count, flag);
 }
 
 }  // namespace rpf
@@ -283,8 +345,8 @@ static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
                     f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off};
-    for (void *p : ptrs) cache_free(p, nullptr);
-    for (void *p : f->tmps) cache_free(p, nullptr);
+    for (void *p : ptrs) cache_free_idle(p);
+    for (void *p : f->tmps) cache_free_idle(p);
     f->tmps.clear();
 }
 
@@ -521,7 +583,6 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     for (int i = 0; i < count; i++) boff[i] = roots[i].offset;
     boff[count] = n;
     hipMemcpyAsync(f->d_batch_off, boff.data(), boff.size() * 8, hipMemcpyHostToDevice, s);
-    std::vector<double> nan_row((size_t)T * H, NAN);
     if (nseg_tot) hipMemcpyAsync(f->d_segs, all_segs.data(), nseg_tot * sizeof(SegDesc), hipMemcpyHostToDevice, s);
     if (nchunk_tot)
         hipMemcpyAsync(f->d_chunks, all_chunks.data(), nchunk_tot * sizeof(ChunkDesc), hipMemcpyHostToDevice, s);
@@ -529,7 +590,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (f->d_look) hipMemcpyAsync(f->d_look, all_look.data(), nseg_tot * sizeof(LookDesc), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(f->d_leaves, leaves.data(), nleaf * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(f->heap_leaf, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
-    if (H) hipMemcpyAsync(f->split, nan_row.data(), (size_t)T * H * 8, hipMemcpyHostToDevice, s);
+    fill_u64(f->split, (int64_t)T * H, 0x7ff8000000000000ull, s);  // binary64 quiet NaN
     fill_u32(f->split_idx, (int64_t)T * H, 0xffffffffu, s);
     fill_u32(f->chosen, (int64_t)T * H, 0xffffffffu, s);
     launch_check(s, "descriptor upload");
@@ -573,31 +634,31 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         else if (max_leaf <= 64) MB = 2;
         else if (max_leaf <= 128) MB = 4;
         const int TR = 32 * MB;
-        std::vector<TileJob> jobs;
-        for (int t = 0; t < T; t++)
-            for (auto &lf : leaves) {
-                const int nt = (lf.size + TR - 1) / TR;
-                for (int I = 0; I < nt; I++)
-                    for (int J = 0; J < nt; J++) {
-                        TileJob j;
-                        j.a_off = lf.off + (int64_t)I * TR;
-                        j.b_off = lf.off + (int64_t)J * TR;
-                        j.a_rows = std::min(TR, lf.size - I * TR);
-                        j.b_rows = std::min(TR, lf.size - J * TR);
-                        j.tree = t;
-                        j.same = I == J;
-                        j.b_pos = J * TR;
-                        j.leaf_m = lf.size;
-                        jobs.push_back(j);
-                    }
-            }
-        f->n_jobs_tree = (int64_t)jobs.size() / T;
+        std::vector<TileJob> jobs;  // tree 0; the device copies them to the other trees
+        for (auto &lf : leaves) {
+            const int nt = (lf.size + TR - 1) / TR;
+            for (int I = 0; I < nt; I++)
+                for (int J = 0; J < nt; J++) {
+                    TileJob j;
+                    j.a_off = lf.off + (int64_t)I * TR;
+                    j.b_off = lf.off + (int64_t)J * TR;
+                    j.a_rows = std::min(TR, lf.size - I * TR);
+                    j.b_rows = std::min(TR, lf.size - J * TR);
+                    j.tree = 0;
+                    j.same = I == J;
+                    j.b_pos = J * TR;
+                    j.leaf_m = lf.size;
+                    jobs.push_back(j);
+                }
+        }
+        f->n_jobs_tree = (int64_t)jobs.size();
         for (auto &lf : leaves) f->tile_flops_tree += 2.0 * d * (double)lf.size * (double)lf.size;
         f->job_mb = MB;
-        RPF_ALLOC(f->d_jobs, jobs.size() * sizeof(TileJob));
+        RPF_ALLOC(f->d_jobs, (size_t)T * jobs.size() * sizeof(TileJob));
         hipMemcpyAsync(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s);
-        hipStreamSynchronize(s);  // the host job list dies with this scope
-        f->bytes += jobs.size() * sizeof(TileJob);
+        replicate_jobs(f->d_jobs, f->n_jobs_tree, T, s);
+        hipStreamSynchronize(s);  // the host job list and descriptors die with this scope
+        f->bytes += (size_t)T * jobs.size() * sizeof(TileJob);
     }
 #undef RPF_ALLOC
     *out = f;
@@ -687,17 +748,11 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
     const int64_t n = f->n, H = f->H;
     const int T = f->T, n_try = f->n_try;
     // ---- inputs: copy, then reject non-finite values (one synchronisation)
-    if ((st = check_hip(hipMemcpyAsync(f->X, X, (size_t)n * d * 4, hipMemcpyDeviceToDevice, s), "copy X")) != RPF_OK)
-        return bail(st);
-    if (H > 0 &&
-        (st = check_hip(hipMemcpyAsync(f->R, p->directions_dev, (size_t)T * H * n_try * d * 4, hipMemcpyDeviceToDevice, s),
-                        "copy directions")) != RPF_OK)
-        return bail(st);
     fill_u32(f->err, 16, 0, s);
     fill_u32(f->stats, kStatSlots * 8 * 2, 0, s);
-    launch_nonfinite(s, f->X, n * d, f->err);
-    launch_nonfinite(s, f->R, T * H * n_try * d, f->err + 1);
-    launch_check(s, "nonfinite check");
+    launch_copy_nonfinite(s, X, f->X, n * d, f->err);
+    if (H > 0) launch_copy_nonfinite(s, p->directions_dev, f->R, T * H * n_try * d, f->err + 1);
+    launch_check(s, "input copy and check");
     int32_t flags[2] = {0, 0};
     if ((st = check_hip(hipMemcpyAsync(flags, f->err, 8, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
     if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);

@@ -159,6 +159,9 @@ int knn_part_first_trees(const rpf_forest *f, int K, int B);
 void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *out_idx, float *out_dist, hipStream_t s);
 void knn_shared_destroy(KnnShared *p, hipStream_t s);
 void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
+void fill_u64(void *p, int64_t count, uint64_t value, hipStream_t s);
+// copies tree 0's all-points tiles (jobs[0, njt)) to trees 1 .. T - 1
+void replicate_jobs(TileJob *jobs, int64_t njt, int T, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);
 int32_t forest_dim(const rpf_forest *f);
 
@@ -174,6 +177,7 @@ void launch_check(hipStream_t s, const char *name);
 constexpr int kStatSlots = 64;  // kNN counters: [kStatSlots][8] unsigned 64-bit, summed on the host
 void *cache_alloc(size_t bytes, hipStream_t s);  // nullptr when the device is out of memory
 void cache_free(void *p, hipStream_t s);          // p's last use is the work queued on s
+void cache_free_idle(void *p);                    // p has no work queued or running (after a synchronisation)
 uint64_t cache_held_bytes(int dev);
 void cache_release(int dev);                      // hipFree idle blocks (dev < 0: every device)
 std::string take_launch_error();

@@ -85,3 +85,38 @@ def test_nonfinite_input_rejected():
     with pytest.raises(rpf.RpfError) as e:
         _gpu_forest(x, R, 2, 20, 1)
     assert e.value.status == rpf.RPF_EINVAL
+
+
+@pytest.mark.parametrize("shift", [0, 1], ids=["aligned", "unaligned"])
+def test_input_copy_check_edges(shift):
+    """The input copy and its non-finite check, on 16-byte aligned and unaligned inputs whose
+    length is not a multiple of four: a NaN or an infinity anywhere (first value, middle, the
+    last value) is rejected, and a finite input grows the same forest as the oracle."""
+    from paper_1812_11689_amd import rpf
+    n, d, T, n0 = 333, 3, 2, 20
+    x, R = problem(n, d, T, n0, 1, seed=11)
+    print(f"[build] input copy check shift={shift} n={n} d={d}", flush=True)
+    Rd = torch.from_numpy(np.ascontiguousarray(R[:T])).cuda()
+
+    def as_dev(a):
+        buf = torch.zeros(n * d + 4, dtype=torch.float32, device="cuda")
+        buf[shift:shift + n * d] = torch.from_numpy(a.reshape(-1)).cuda()
+        return buf[shift:shift + n * d].view(n, d)
+
+    for pos, bad in [(0, np.nan), (n * d // 2, np.inf), (n * d - 1, np.nan), (n * d - 2, -np.inf)]:
+        xb = x.copy().reshape(-1)
+        xb[pos] = bad
+        with pytest.raises(rpf.RpfError) as e:
+            rpf.build(as_dev(xb.reshape(n, d)), T, n0, Rd)
+        assert e.value.status == rpf.RPF_EINVAL
+    ref = oracle.build_forest(x, R, T, n0, 1)
+    f = rpf.build(as_dev(x), T, n0, Rd)
+    try:
+        for t in range(T):
+            g = {k: v.cpu().numpy() for k, v in f.tree_dump(t).items()}
+            np.testing.assert_array_equal(g["perm"], ref.perm[t])
+            np.testing.assert_array_equal(g["leaf_of"], ref.leaf_of[t])
+            assert np.array_equal(g["split"].view(np.uint64), ref.split[t].view(np.uint64)) or \
+                np.array_equal(g["split"], ref.split[t], equal_nan=True)
+    finally:
+        f.free()
