@@ -120,6 +120,34 @@ def roofline(prof):
                   "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
 
+BUILD_LEVEL_RECORDS = ("proj_roots", "proj_chunks_x3", "level_small", "select_passes", "partition")
+KNN_RECORDS = ("tile_phase1", "merge_first", "tile_phase2", "final_rerank", "fallback")
+
+
+def stage_summary(prof, steps, n, d, T, L, K):
+    """Kernel time of the two halves of a step and their bounds: the build levels against the
+    algorithmic bytes of the method (n (4d + 36) bytes per tree and level: row, id, key write,
+    one select read, partition read of key and id, id write), the leaf pass apart, and the
+    search (queries/s of rpf_all_knn alone) with the MFMA fraction of its distance tiles."""
+    def ms(names):
+        return sum(prof[k]["total_ms"] for k in names if k in prof) / steps
+    lv_ms, leaf_ms, knn_ms = ms(BUILD_LEVEL_RECORDS), ms(("leaf_finalize",)), ms(KNN_RECORDS)
+    lv_bytes = float(n) * (4 * d + 36) * L * T
+    tiles = [prof[k] for k in ("tile_phase1", "tile_phase2") if k in prof]
+    t_flops = sum(r["algo_flops"] for r in tiles) / steps
+    t_ms = sum(r["total_ms"] for r in tiles) / steps
+    peak = FP32_MFMA_PEAK_TFLOPS if not tiles or tiles[0].get("prec") != "bf16" else BF16_MFMA_PEAK_TFLOPS
+    return {
+        "build_levels_ms": round(lv_ms, 3),
+        "build_levels_algorithmic_bytes": lv_bytes,
+        "build_levels_effective_hbm_frac": round(lv_bytes / (lv_ms / 1e3) / (HBM_PEAK_GBS * 1e9), 3) if lv_ms else None,
+        "leaf_pass_ms": round(leaf_ms, 3),
+        "all_knn_ms": round(knn_ms, 3),
+        "all_knn_queries_per_s": round(n / (knn_ms / 1e3), 1) if knn_ms else None,
+        "tiles_mfma_frac": round(t_flops / (t_ms / 1e3) / (peak * 1e12), 4) if t_ms else None,
+    }
+
+
 def source_hash():
     """Hash of the HIP sources: traffic figures are valid only for the kernels they measured."""
     import hashlib
@@ -342,6 +370,7 @@ def main():
         if tr is not None:
             roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
     breakdown = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(prof32.items(), key=lambda kv: -kv[1]["total_ms"])}
+    stages = stage_summary(prof32, args.steps, n, d, T, L, K)
 
     f = rpf.build(X, T, n0, Rd, dist_prec="fp32")
     f.all_knn(K)
@@ -390,6 +419,7 @@ def main():
         "recorded_plan": graph,
         "knn_stats": st,
         "breakdown_ms_per_step": breakdown,
+        "stages": stages,
         "roofline_kernel": dom,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -923,7 +923,7 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
             for (int r = 0; r < 2; r++) {
                 const int i = i0 + 4 * r;
                 if (i >= m) continue;
-                T *out = Xc + ((int64_t)t * n + lf.off + i) * dp;
+                T *out = Xc ? Xc + ((int64_t)t * n + lf.off + i) * dp : nullptr;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int j = j0 + 64 * q + lane;
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
                     const float a = j < d ? xv[r][q] - s_mu[j] : 0.f;
                     over[r] |= fabsf(a) > range_max;
                     const T qv = to_tile<T>(a);
-                    out[j] = qv;
+                    if (out) out[j] = qv;
                     const float qf = (float)qv;
                     na[r] = __builtin_fmaf(qf, qf, na[r]);
                     ra[r] = __builtin_fmaf(a, a, ra[r]);
@@ -952,7 +952,75 @@ __global__ __launch_bounds__(256) void k_leaf_finalize(
     }
 }
 
+// The leaf-ordered, centred copy alone, for a forest whose leaf pass did not write it: each
+// element is x - mu rounded to the tile type (zero past d), from the centroid the leaf pass
+// stored, so it holds exactly the values the leaf pass would have written.  One block per
+// (leaf, tree); four columns per thread.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_leaf_copy(const float *__restrict__ X, int d, int dp,
+                                                   const LeafDesc *__restrict__ leaves, int nleaf,
+                                                   const int32_t *__restrict__ perm, int64_t n,
+                                                   const float *__restrict__ centroid, T *__restrict__ Xc) {
+    const int t = blockIdx.y;
+    const LeafDesc lf = leaves[blockIdx.x];
+    const float *mu = centroid + ((int64_t)t * nleaf + blockIdx.x) * d;
+    const int32_t *pp = perm + (int64_t)t * n + lf.off;
+    const int q = dp >> 2;  // four-column groups per row (dp is a multiple of 8)
+    for (int v = threadIdx.x; v < lf.size * q; v += 256) {
+        const int i = v / q, c = 4 * (v - i * q);
+        const float *x = X + (int64_t)pp[i] * d;
+        float a[4];
+        if (VEC && c < d) {  // d % 4 == 0: the four columns are all below d
+            const float4 xv = *reinterpret_cast<const float4 *>(x + c);
+            const float4 u = *reinterpret_cast<const float4 *>(mu + c);
+            a[0] = xv.x - u.x;
+            a[1] = xv.y - u.y;
+            a[2] = xv.z - u.z;
+            a[3] = xv.w - u.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) a[e] = c + e < d ? x[c + e] - mu[c + e] : 0.f;
+        }
+        T qv[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) qv[e] = to_tile<T>(a[e]);
+        T *out = Xc + ((int64_t)t * n + lf.off + i) * dp + c;
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4 *>(out) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+        } else {
+            uint2 w;
+            __builtin_memcpy(&w, qv, sizeof(w));
+            *reinterpret_cast<uint2 *>(out) = w;
+        }
+    }
+}
+
 // ================================================================ launchers
+
+template <typename T>
+static void leaf_copy(hipStream_t s, bool vec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                      int ntree, const int32_t *perm, int64_t n, const float *centroid, void *Xc) {
+    const dim3 grid(nleaf, ntree);
+    if (vec)
+        hipLaunchKernelGGL((k_leaf_copy<T, true>), grid, dim3(256), 0, s, X, d, dp, leaves, nleaf, perm, n, centroid,
+                           (T *)Xc);
+    else
+        hipLaunchKernelGGL((k_leaf_copy<T, false>), grid, dim3(256), 0, s, X, d, dp, leaves, nleaf, perm, n, centroid,
+                           (T *)Xc);
+    launch_check(s, "k_leaf_copy");
+}
+
+void launch_leaf_copy(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                      int ntree, const int32_t *perm, int64_t n, const float *centroid, void *Xc) {
+    if (nleaf <= 0 || ntree <= 0) return;
+    const bool vec = (d % 4) == 0;
+    if (prec == RPF_DIST_BF16)
+        leaf_copy<__bf16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, centroid, Xc);
+    else if (prec == RPF_DIST_FP16)
+        leaf_copy<_Float16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, centroid, Xc);
+    else
+        leaf_copy<float>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, centroid, Xc);
+}
 
 size_t level_small_lds(int max_m, int d, int n_try) {
     size_t lds = ((((4 * (size_t)max_m + 15) & ~(size_t)15) + 8 * (size_t)max_m + 15) & ~(size_t)15) +
@@ -1153,7 +1221,7 @@ __device__ __attribute__((always_inline)) inline void leaf_centre_staged(const f
         const int i = i0 + grp;
         const bool live = i < m;
         const int ir = live ? i : m - 1;
-        T *out = Xc + ((int64_t)t * n + lf.off + ir) * dp;
+        T *out = Xc ? Xc + ((int64_t)t * n + lf.off + ir) * dp : nullptr;
         float na = 0.f, ra = 0.f;
         bool over = false;
         for (int c = 4 * sub; c < dp; c += 32) {
@@ -1177,7 +1245,7 @@ __device__ __attribute__((always_inline)) inline void leaf_centre_staged(const f
                 na = __builtin_fmaf(qf, qf, na);
                 ra = __builtin_fmaf(a[e], a[e], ra);
             }
-            if (live) {
+            if (live && out) {
                 if constexpr (sizeof(T) == 4) {
                     *reinterpret_cast<float4 *>(out + c) = make_float4(qv[0], qv[1], qv[2], qv[3]);
                 } else {

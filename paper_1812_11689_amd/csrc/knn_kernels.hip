@@ -116,6 +116,59 @@ __device__ inline void stage_rows(typename TileCfg<PREC>::T *s, const typename T
     }
 }
 
+// Rows 0 .. rows-1 of a leaf staged straight from X: row r is point pt[r], centred on the
+// leaf's centroid mu and rounded to the tile type (zero past d), columns [k0, k0 + KC), rows
+// up to rows_pad zero-filled.  These are exactly the values of the leaf-ordered centred copy
+// (x - mu in binary32, then one rounding to the tile type), so a tile staged this way equals
+// one staged from that copy.  VEC: d % 4 == 0 (four-column groups never straddle d).
+template <int PREC, bool VEC>
+__device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *__restrict__ X, int d,
+                                    const int32_t *s_pt, const float *__restrict__ mu, int rows, int rows_pad,
+                                    int k0, int nthreads) {
+    using C = TileCfg<PREC>;
+    using T = typename C::T;
+    constexpr int EV = PREC == RPF_DIST_FP32 ? 4 : 8;  // elements per LDS vector
+    constexpr int VPR = C::KC / EV;
+    for (int v = threadIdx.x; v < rows_pad * VPR; v += nthreads) {
+        const int r = v / VPR, c = (v % VPR) * EV, j = k0 + c;
+        float a[EV];
+#pragma unroll
+        for (int e = 0; e < EV; e++) a[e] = 0.f;
+        if (r < rows) {
+            const float *x = X + (int64_t)s_pt[r] * d;
+#pragma unroll
+            for (int h = 0; h < EV; h += 4) {
+                if (VEC) {
+                    if (j + h < d) {
+                        const float4 xv = *reinterpret_cast<const float4 *>(x + j + h);
+                        const float4 u = *reinterpret_cast<const float4 *>(mu + j + h);
+                        a[h] = xv.x - u.x;
+                        a[h + 1] = xv.y - u.y;
+                        a[h + 2] = xv.z - u.z;
+                        a[h + 3] = xv.w - u.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = h; e < h + 4; e++)
+                        if (j + e < d) a[e] = x[j + e] - mu[j + e];
+                }
+            }
+        }
+        T *dst = s + r * C::LDW + c;
+        if constexpr (PREC == RPF_DIST_FP32) {
+#pragma unroll
+            for (int e = 0; e < EV; e++) dst[e] = a[e];
+        } else {
+            T q[EV];
+#pragma unroll
+            for (int e = 0; e < EV; e++) q[e] = (T)a[e];
+            uint4 w;
+            __builtin_memcpy(&w, q, sizeof(w));
+            *reinterpret_cast<uint4 *>(dst) = w;
+        }
+    }
+}
+
 struct BoundCoef {
     float e;      // E: accumulation error per unit of |a|^2 + |b|^2
     float c;      // C: centred-copy rounding per unit of |a'| + |b'|
@@ -411,8 +464,9 @@ constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE == 1 && NB ==
 template <int NB, int PREC, int MODE>
 __global__ __launch_bounds__(64 * sym_waves(NB, MODE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE) > 8 ? 6 : 1)))
 void k_tile_sym(
-    const TileJob *__restrict__ jobs, const void *__restrict__ A_, int dp, int64_t stride_tree,
-    const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc, int exclude_self, TileOut out) {
+    const TileJob *__restrict__ jobs, const float *__restrict__ X, int d, int dp, const float *__restrict__ centroid,
+    int nleaf, int64_t stride_tree, const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc,
+    int exclude_self, TileOut out) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
@@ -436,7 +490,7 @@ void k_tile_sym(
     const int m = job.a_rows;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = __builtin_amdgcn_readfirstlane(w);  // wave-uniform (scalar) wave index
-    const T *A = reinterpret_cast<const T *>(A_) + (t * stride_tree + job.a_off) * dp;
+    const float *mu = centroid + ((int64_t)t * nleaf + job.leaf) * d;
     const float2 *an = nrm + t * stride_tree + job.a_off;
     const int32_t *ap = pt + t * stride_tree + job.a_off;
     const int tb = t - out.t0;
@@ -516,7 +570,8 @@ void k_tile_sym(
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
     for (int k0 = 0; k0 < dp; k0 += C::KC) {
         __syncthreads();
-        stage_rows<PREC>(s_a, A, m, M, dp, k0, NT);
+        if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT);
+        else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT);
         __syncthreads();
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
@@ -1812,6 +1867,8 @@ __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *_
                 j.same = 0;
                 j.b_pos = J * TR;
                 j.leaf_m = lf.size;
+                j.leaf = (int32_t)li;
+                j.pad = 0;
                 const bool first = t < nfirst;
                 const bool small = c <= qs;  // a few queries: the GEMV-shaped kernel
                 const int slot = atomicAdd(&njobs[(first ? 0 : 1) + (small ? 2 : 0)], 1);
@@ -1998,40 +2055,51 @@ static void qtile_dispatch(int prec, int qs, hipStream_t s, int64_t njobs, const
         qtile_dispatch_p<RPF_DIST_FP32>(qs, s, njobs, jobs, A, B, dp, as, bs, an, bn, ad, bp, bc, out);
 }
 
+// the all-points tiles of one leaf each, staged from X and the leaf centroids
+struct SymSrc {
+    const float *X;
+    int d, dp;
+    const float *centroid;
+    int nleaf;
+    int64_t stride;  // points per tree (n)
+};
+
+static SymSrc sym_src(const ForestView &v) { return SymSrc{v.X, v.d, v.dp, v.centroid, (int)v.nleaf, v.n}; }
+
 template <int NB, int PREC>
-static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp, int64_t stride,
-                       const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
+static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const SymSrc &src, const float2 *nrm,
+                       const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
     const int NT = 64 * sym_waves(NB, out.mode);
     const dim3 g((unsigned)njobs);
     if (out.mode == 0)
-        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt, bc, excl, out);
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
+                           src.nleaf, src.stride, nrm, pt, bc, excl, out);
     else
-        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), g, dim3(NT), 0, s, jobs, A, dp, stride, nrm, pt, bc, excl, out);
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
+                           src.nleaf, src.stride, nrm, pt, bc, excl, out);
     launch_check(s, "k_tile_sym");
 }
 
 template <int PREC>
-static void sym_dispatch_nb(int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
-                            int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl,
-                            const TileOut &out) {
+static void sym_dispatch_nb(int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const SymSrc &src,
+                            const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     switch (NB) {
-    case 1: sym_launch<1, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
-    case 2: sym_launch<2, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
-    case 4: sym_launch<4, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
-    default: sym_launch<8, PREC>(s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out); break;
+    case 1: sym_launch<1, PREC>(s, njobs, jobs, src, nrm, pt, bc, excl, out); break;
+    case 2: sym_launch<2, PREC>(s, njobs, jobs, src, nrm, pt, bc, excl, out); break;
+    case 4: sym_launch<4, PREC>(s, njobs, jobs, src, nrm, pt, bc, excl, out); break;
+    default: sym_launch<8, PREC>(s, njobs, jobs, src, nrm, pt, bc, excl, out); break;
     }
 }
 
-static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const void *A, int dp,
-                         int64_t stride, const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl,
-                         const TileOut &out) {
+static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const SymSrc &src,
+                         const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (prec == RPF_DIST_BF16)
-        sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
+        sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
     else if (prec == RPF_DIST_FP16)
-        sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
+        sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
     else
-        sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, A, dp, stride, nrm, pt, bc, excl, out);
+        sym_dispatch_nb<RPF_DIST_FP32>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
 }
 
 // device buffers of the candidate stage (one call)
@@ -2156,7 +2224,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     {
         ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, cs.excl, o1);
+            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, sym_src(v), v.nrm, v.perm, bc, cs.excl, o1);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o1);
@@ -2189,7 +2257,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         o2.ent = ent;
         ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, v.Xc, v.dp, v.n, v.nrm, v.perm, bc, cs.excl, o2);
+            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, sym_src(v), v.nrm, v.perm, bc, cs.excl, o2);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o2);
@@ -2280,8 +2348,15 @@ static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, 
 }
 
 rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s) {
-    const ForestView v = view(f);
-    return run_cand_stage(v, all_points_stage(v, K, exclude_self), K, out_idx, out_dist, s);
+    ForestView v = view(f);
+    const CandStage cs = all_points_stage(v, K, exclude_self);
+    if (!cs.sym && !v.Xc) {  // leaves of more than one tile read the centred copy
+        const rpf_status st = ensure_leaf_copies(f, s);
+        if (st != RPF_OK) return st;
+        v = view(f);
+        return run_cand_stage(v, all_points_stage(v, K, exclude_self), K, out_idx, out_dist, s);
+    }
+    return run_cand_stage(v, cs, K, out_idx, out_dist, s);
 }
 
 // All-points search of several forests (parts) run one after the other with one workspace,
@@ -2374,6 +2449,10 @@ rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_le
 
 rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
                      hipStream_t s) {
+    {
+        const rpf_status st = ensure_leaf_copies(f, s);  // query tiles read the leaf-ordered copy
+        if (st != RPF_OK) return st;
+    }
     const ForestView v = view(f);
     int dev = 0;
     hipGetDevice(&dev);

@@ -33,6 +33,8 @@ void launch_iota(hipStream_t s, int32_t *perm, int64_t n, int T);
 void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves,
                           int nleaf, int T, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid,
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit);
+void launch_leaf_copy(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                      int ntree, const int32_t *perm, int64_t n, const float *centroid, void *Xc);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
 void launch_localize(int32_t *idx, int64_t rows, int K, const int64_t *off, int count, hipStream_t s);
 
@@ -277,6 +279,9 @@ struct rpf_forest {
     // stats of the last kNN call
     unsigned long long *stats = nullptr;  // [kStatSlots][8]
     mutable std::mutex mu;
+    // the leaf copies (Xc) when made after the build, on a query's first use
+    std::mutex xc_mu;
+    hipEvent_t xc_ev = nullptr;  // recorded after the copy kernel
 };
 
 namespace rpf {
@@ -348,6 +353,8 @@ static void free_forest_memory(rpf_forest *f) {
     for (void *p : ptrs) cache_free_idle(p);
     for (void *p : f->tmps) cache_free_idle(p);
     f->tmps.clear();
+    if (f->xc_ev) hipEventDestroy(f->xc_ev);
+    f->xc_ev = nullptr;
 }
 
 rpf_status rpf_free(rpf_forest *f) {
@@ -498,6 +505,10 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     const int64_t nleaf = (int64_t)leaves.size();
     int max_leaf = 0;
     for (auto &lf : leaves) max_leaf = std::max(max_leaf, (int)lf.size);
+    // the all-points search stages leaves of one tile (at most 256 points) straight from X;
+    // larger leaves read the leaf-ordered centred copy, made here; queries make it on first use
+    const bool xc_eager = max_leaf > 256;
+    const uint64_t xc_bytes = (uint64_t)T * n * dp * esz;
     uint64_t bytes = 0;
     bytes += (uint64_t)n * d * 4;                        // X
     bytes += (uint64_t)T * H * n_try * d * 4;            // R
@@ -523,7 +534,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     rpf_forest *f = new rpf_forest();
     f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
     f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
-    f->bytes = bytes;
+    f->bytes = bytes - (xc_eager ? 0 : xc_bytes);
     f->batch = roots;
 
     auto bail = [&](rpf_status st) {
@@ -553,7 +564,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     RPF_ALLOC(f->perm[1], (size_t)T * n * 4);
     RPF_ALLOC(f->leaf_of, (size_t)T * n * 4);
     RPF_ALLOC(f->centroid, (size_t)T * nleaf * d * 4);
-    RPF_ALLOC(f->Xc, (size_t)T * n * dp * esz);
+    if (xc_eager) RPF_ALLOC(f->Xc, (size_t)xc_bytes);
     RPF_ALLOC(f->nrm, (size_t)T * n * 8);
     RPF_ALLOC(f->err, 64);
     RPF_ALLOC(f->stats, kStatSlots * 8 * 8);
@@ -635,7 +646,8 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         else if (max_leaf <= 128) MB = 4;
         const int TR = 32 * MB;
         std::vector<TileJob> jobs;  // tree 0; the device copies them to the other trees
-        for (auto &lf : leaves) {
+        for (size_t li = 0; li < leaves.size(); li++) {
+            const LeafDesc &lf = leaves[li];
             const int nt = (lf.size + TR - 1) / TR;
             for (int I = 0; I < nt; I++)
                 for (int J = 0; J < nt; J++) {
@@ -648,6 +660,8 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
                     j.same = I == J;
                     j.b_pos = J * TR;
                     j.leaf_m = lf.size;
+                    j.leaf = (int32_t)li;
+                    j.pad = 0;
                     jobs.push_back(j);
                 }
         }
@@ -723,6 +737,41 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
     launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of, f->centroid,
                          f->Xc, f->nrm, f->max_leaf, f->lds_max);
     launch_check(s, "leaf_finalize");
+}
+
+// The leaf-ordered centred copy for queries, made once, on the first call that needs it:
+// later callers on other streams wait for the event recorded after the copy kernel.
+rpf_status rpf::ensure_leaf_copies(const rpf_forest *cf, hipStream_t s) {
+    rpf_forest *f = const_cast<rpf_forest *>(cf);
+    std::lock_guard<std::mutex> lk(f->xc_mu);
+    if (f->Xc) return f->xc_ev ? check_hip(hipStreamWaitEvent(s, f->xc_ev, 0), "leaf copies: wait") : RPF_OK;
+    if (capturing(s))
+        return fail(RPF_EINVAL, "the forest's query copies are made on its first query, which cannot be recorded: "
+                                "run one query before the capture");
+    const size_t bytes = (size_t)f->T * f->n * f->dp * (f->prec == RPF_DIST_FP32 ? 4 : 2);
+    void *p = cache_alloc(bytes, s);
+    if (!p) return fail(RPF_ENOMEM, "device allocation of the forest's query copies failed");
+    launch_leaf_copy(s, f->prec, f->X, f->d, f->dp, f->d_leaves, (int)f->leaves.size(), f->T, f->perm[f->final_buf],
+                     f->n, f->centroid, p);
+    const std::string le = take_launch_error();
+    if (!le.empty()) {
+        cache_free(p, s);
+        return fail(RPF_EDEVICE, "leaf copies: " + le);
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
+        if (ev) hipEventDestroy(ev);
+        ev = nullptr;
+        const rpf_status st = check_hip(hipStreamSynchronize(s), "leaf copies");  // no event: finish them here
+        if (st != RPF_OK) {
+            cache_free_idle(p);
+            return st;
+        }
+    }
+    f->xc_ev = ev;
+    f->Xc = p;
+    f->bytes += bytes;
+    return RPF_OK;
 }
 
 static void release_temporaries(rpf_forest *f, hipStream_t s) {

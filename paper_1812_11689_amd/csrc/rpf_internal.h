@@ -124,6 +124,8 @@ struct TileJob {       // one MFMA tile: A rows x B rows (<= 32*MB each) of one 
     int32_t same;      // 1: A and B are the same positions (all-points diagonal tile)
     int32_t b_pos;     // offset of the first B row inside its leaf
     int32_t leaf_m;    // size of the leaf the B rows belong to
+    int32_t leaf;      // index of that leaf (its centroid row)
+    int32_t pad;
 };
 
 // read-only view of a forest for the kNN launchers
@@ -160,6 +162,9 @@ void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *ou
 void knn_shared_destroy(KnnShared *p, hipStream_t s);
 void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
 void fill_u64(void *p, int64_t count, uint64_t value, hipStream_t s);
+// the leaf-ordered, centred copy in the tile precision, made on a query's first use (the
+// all-points search of leaves that fit one tile stages its rows from X instead)
+rpf_status ensure_leaf_copies(const rpf_forest *f, hipStream_t s);
 // copies tree 0's all-points tiles (jobs[0, njt)) to trees 1 .. T - 1
 void replicate_jobs(TileJob *jobs, int64_t njt, int T, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);

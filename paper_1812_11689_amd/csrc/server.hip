@@ -216,6 +216,14 @@ rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, 
         }
         sv->streams.push_back(s);
     }
+    // the forest's query copies are made now, on the first slot's stream, not by the first batch
+    rpf_status st = ensure_leaf_copies(f, sv->streams[0]);
+    if (st == RPF_OK) st = check_hip(hipStreamSynchronize(sv->streams[0]), "rpf_server_create");
+    if (st != RPF_OK) {
+        for (hipStream_t t : sv->streams) hipStreamDestroy(t);
+        delete sv;
+        return st;
+    }
     for (int i = 0; i < cfg->slots; i++) sv->threads.emplace_back(slot_main, sv, i);
     *out = sv;
     return RPF_OK;
