@@ -995,7 +995,136 @@ __global__ __launch_bounds__(256) void k_leaf_copy(const float *__restrict__ X, 
     }
 }
 
+// The leaf statistics without the copy, for forests whose all-points search centres the rows
+// itself as it stages them (leaves of at most 256 points): leaf_of, the centroid mu (binary32
+// mean, a fixed order: each of 32 row groups sums its rows in order, then the groups in
+// order) and per position |tile(x - mu)|^2 of the tile-type values and |x - mu| (+inf past
+// the tile type's range).  A copy made later from this centroid holds exactly the values
+// these norms describe.  One block of 1024 threads per (leaf, tree): 32 lanes per row, four
+// columns each per step of 128 columns, and the block's 32 row groups hold all of the leaf's
+// rows of a step in registers, so X is read once.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_leaf_stats(const float *__restrict__ X, int d, int dp,
+                                                     const LeafDesc *__restrict__ leaves, int nleaf,
+                                                     const int32_t *__restrict__ perm, int64_t n,
+                                                     int32_t *__restrict__ leaf_of, float *__restrict__ centroid,
+                                                     float2 *__restrict__ nrm, float range_max) {
+    constexpr int NT = 1024, RG = NT / 32, RK = 256 / RG;  // row groups, rows per group
+    __shared__ __align__(16) float s_part[RG][128];
+    __shared__ __align__(16) float s_mu[128];
+    __shared__ int32_t s_id[256];
+    __shared__ float s_na[256], s_ra[256];  // the rows' norms, summed over the steps in order
+    const int t = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    const LeafDesc lf = leaves[blockIdx.x];
+    const int m = lf.size;
+    const int32_t *pp = perm + (int64_t)t * n + lf.off;
+    for (int i = tid; i < m; i += NT) {
+        const int id = pp[i];
+        s_id[i] = id;
+        leaf_of[(int64_t)t * n + id] = lf.heap;
+        s_na[i] = 0.f;
+        s_ra[i] = 0.f;
+    }
+    __syncthreads();
+    const int l32 = lane & 31, g = tid >> 5;  // rows g, g + RG, ...
+    for (int cb = 0; cb < dp; cb += 128) {
+        const int j = cb + 4 * l32;
+        float4 x[RK];
+#pragma unroll
+        for (int k = 0; k < RK; k++) {  // every row of the step in flight at once
+            const int r = g + RG * k;
+            x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < m) {
+                const float *xr = X + (int64_t)s_id[r] * d;
+                if (VEC) {
+                    if (j < d) x[k] = *reinterpret_cast<const float4 *>(xr + j);
+                } else {
+                    x[k].x = j < d ? xr[j] : 0.f;
+                    x[k].y = j + 1 < d ? xr[j + 1] : 0.f;
+                    x[k].z = j + 2 < d ? xr[j + 2] : 0.f;
+                    x[k].w = j + 3 < d ? xr[j + 3] : 0.f;
+                }
+            }
+        }
+        float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < RK; k++) {
+            if (g + RG * k < m) {
+                cs.x += x[k].x;
+                cs.y += x[k].y;
+                cs.z += x[k].z;
+                cs.w += x[k].w;
+            }
+        }
+        *reinterpret_cast<float4 *>(&s_part[g][4 * l32]) = cs;
+        __syncthreads();
+        if (tid < 128) {
+            float v = 0.f;
+            for (int q = 0; q < RG; q++) v += s_part[q][tid];
+            const int jj = cb + tid;
+            const float mu = jj < d ? v / (float)m : 0.f;
+            s_mu[tid] = mu;
+            if (jj < d) centroid[((int64_t)t * nleaf + blockIdx.x) * d + jj] = mu;
+        }
+        __syncthreads();
+        const float4 u = *reinterpret_cast<const float4 *>(&s_mu[4 * l32]);
+#pragma unroll
+        for (int k = 0; k < RK; k++) {  // the step's share of each row's norms (past dp: zero)
+            const float a[4] = {j < d ? x[k].x - u.x : 0.f, j + 1 < d ? x[k].y - u.y : 0.f,
+                                j + 2 < d ? x[k].z - u.z : 0.f, j + 3 < d ? x[k].w - u.w : 0.f};
+            float na = 0.f, ra = 0.f;
+            bool over = false;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                over |= fabsf(a[e]) > range_max;
+                const float qf = (float)to_tile<T>(a[e]);
+                na = __builtin_fmaf(qf, qf, na);
+                ra = __builtin_fmaf(a[e], a[e], ra);
+            }
+            for (int o = 1; o < 32; o <<= 1) {
+                na += __shfl_xor(na, o, 64);
+                ra += __shfl_xor(ra, o, 64);
+            }
+            const bool ov = ((__ballot(over) >> (lane & 32)) & 0xffffffffull) != 0;
+            const int r = g + RG * k;
+            if (l32 == 0 && r < m) {
+                s_na[r] += na;
+                s_ra[r] = ov ? INFINITY : s_ra[r] + ra;
+            }
+        }
+        __syncthreads();  // s_part and s_mu are rewritten by the next step
+    }
+    for (int r = tid; r < m; r += NT) nrm[(int64_t)t * n + lf.off + r] = make_float2(s_na[r], sqrtf(s_ra[r]));
+}
+
+template <typename T>
+static void leaf_stats(hipStream_t s, bool vec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                       int ntree, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid, float2 *nrm,
+                       float range_max) {
+    const dim3 grid(nleaf, ntree);
+    if (vec)
+        hipLaunchKernelGGL((k_leaf_stats<T, true>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n, leaf_of,
+                           centroid, nrm, range_max);
+    else
+        hipLaunchKernelGGL((k_leaf_stats<T, false>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n,
+                           leaf_of, centroid, nrm, range_max);
+    launch_check(s, "k_leaf_stats");
+}
+
 // ================================================================ launchers
+
+void launch_leaf_stats(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                       int ntree, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid, float2 *nrm,
+                       int max_leaf) {
+    if (nleaf <= 0 || ntree <= 0 || max_leaf > 256) return;  // the caller runs the full leaf pass instead
+    const bool vec = (d % 4) == 0;
+    if (prec == RPF_DIST_BF16)
+        leaf_stats<__bf16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f);
+    else if (prec == RPF_DIST_FP16)
+        leaf_stats<_Float16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 60000.f);
+    else
+        leaf_stats<float>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f);
+}
 
 template <typename T>
 static void leaf_copy(hipStream_t s, bool vec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,

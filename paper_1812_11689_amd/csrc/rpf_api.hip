@@ -35,6 +35,9 @@ void launch_leaf_finalize(hipStream_t s, int prec, const float *X, int d, int dp
                           void *Xc, float2 *nrm, int max_leaf, int lds_limit);
 void launch_leaf_copy(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
                       int ntree, const int32_t *perm, int64_t n, const float *centroid, void *Xc);
+void launch_leaf_stats(hipStream_t s, int prec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
+                       int ntree, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid, float2 *nrm,
+                       int max_leaf);
 void launch_nonfinite(hipStream_t s, const float *x, int64_t count, int32_t *flag);
 void launch_localize(int32_t *idx, int64_t rows, int K, const int64_t *off, int count, hipStream_t s);
 
@@ -733,10 +736,17 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
         cur ^= 1;
     }
     f->final_buf = cur;
-    ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * esz + 16), 0);
-    launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of, f->centroid,
-                         f->Xc, f->nrm, f->max_leaf, f->lds_max);
-    launch_check(s, "leaf_finalize");
+    if (f->Xc) {  // leaves above one tile: the all-points search reads the centred copy
+        ProfScope ps(s, "leaf_finalize", (double)T * n * (8.0 * d + dp * esz + 16), 0);
+        launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of,
+                             f->centroid, f->Xc, f->nrm, f->max_leaf, f->lds_max);
+        launch_check(s, "leaf_finalize");
+    } else {  // centroids and norms only: the tiles centre the rows as they stage them
+        ProfScope ps(s, "leaf_finalize", (double)T * n * (4.0 * d + 16), 0);
+        launch_leaf_stats(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of, f->centroid,
+                          f->nrm, f->max_leaf);
+        launch_check(s, "leaf_stats");
+    }
 }
 
 // The leaf-ordered centred copy for queries, made once, on the first call that needs it:
