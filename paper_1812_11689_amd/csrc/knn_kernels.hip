@@ -1043,7 +1043,6 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 constexpr int kListCap = 256;              // Phase I list records per row
 constexpr int kFinalQ = 12;                // most entries per lane (k_final is instantiated for 4, 8, 12)
 constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
-constexpr int kWCap = 256;                 // binary64 window per row
 
 struct FinalArgs {
     const Ent *list;
@@ -1187,25 +1186,19 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         if (lane == 0) push_fallback(A, a);
         return;
     }
-    // one gather of every candidate row gives both canonical distances; the hash table is
-    // dead by now and holds the binary64 values
+    // the canonical binary64 distance of every member of R (R is small: about K rows), so
+    // the K best by (D64, index) come straight from R; the hash table is dead by now and
+    // holds the binary64 values
     double *s_dd = reinterpret_cast<double *>(s_key[w]);  // kHT int32 = kRCap doubles
     const int g = lane & 7, grp = lane >> 3;
     if constexpr (VEC) {  // two candidates per group of eight lanes at a time
         for (int base = 0; base < nr; base += 16) {
             const int i0 = base + grp, i1 = i0 + 8;
             const int b0 = s_r[w][i0 < nr ? i0 : 0], b1 = s_r[w][i1 < nr ? i1 : 0];
-            float D32[2];
             double D64[2];
-            group8_dist32_64x2(s_q, A.X + (int64_t)b0 * A.d, A.X + (int64_t)b1 * A.d, A.d, g, D32, D64);
-            if (g == 0 && i0 < nr) {
-                s_d[w][i0] = fkey(D32[0]);
-                s_dd[i0] = D64[0];
-            }
-            if (g == 0 && i1 < nr) {
-                s_d[w][i1] = fkey(D32[1]);
-                s_dd[i1] = D64[1];
-            }
+            group8_dist64x2(s_q, A.X + (int64_t)b0 * A.d, A.X + (int64_t)b1 * A.d, A.d, g, D64);
+            if (g == 0 && i0 < nr) s_dd[i0] = D64[0];
+            if (g == 0 && i1 < nr) s_dd[i1] = D64[1];
         }
     } else {
         for (int base = 0; base < nr; base += 8) {
@@ -1214,52 +1207,15 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
             float D32;
             double D64;
             group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
-            if (g == 0 && i < nr) {
-                s_d[w][i] = fkey(D32);
-                s_dd[i] = D64;
-            }
+            if (g == 0 && i < nr) s_dd[i] = D64;
         }
     }
     wave_sync();
-    float d32k = INFINITY;
-    if (nr >= K && nr <= 64) {  // the usual case: one key per lane
-        uint32_t dv[1] = {lane < nr ? s_d[w][lane] : 0xffffffffu};
-        d32k = __uint_as_float(wave_kth_upper<1>(dv, K - 1));
-    } else if (nr >= K) {
-        uint32_t dv[kRCap / 64];  // binary32 distance keys of R, the rest masked out
-#pragma unroll
-        for (int q = 0; q < kRCap / 64; q++) {
-            const int i = lane + 64 * q;
-            dv[q] = i < nr ? s_d[w][i] : 0xffffffffu;
-        }
-        d32k = __uint_as_float(wave_kth_upper<kRCap / 64>(dv, K - 1));
-    }
-    const float wcut = d32k * (1.f + A.win);
-    // the window: binary32 distance within w of the K-th; ordered in binary64.  It is
-    // compacted in place over R (a member's new position is at most its old one, and each
-    // round reads its 64 entries before any of them is written)
+    // R is sorted whole by (D64, index): it holds the true top K (every candidate with
+    // lb <= tau'), so its first K are the answer
     int32_t *s_wi = s_r[w];
     double *s_wd = s_dd;
-    int nw = 0;
-    for (int base = 0; base < nr; base += 64) {
-        const int i = base + lane;
-        const bool in = i < nr && __uint_as_float(s_d[w][i]) <= wcut;
-        const int32_t ri = i < nr ? s_r[w][i] : 0;
-        const double rd = i < nr ? s_dd[i] : 0.0;
-        const uint64_t mk = __ballot(in);
-        const int pos = nw + mask_rank(mk);
-        wave_sync();
-        if (in && pos < kWCap) {
-            s_wi[pos] = ri;
-            s_wd[pos] = rd;
-        }
-        nw += __popcll(mk);
-        wave_sync();
-    }
-    if (nw > kWCap) {  // pathological window (massive distance ties): exhaustive path
-        if (lane == 0) push_fallback(A, a);
-        return;
-    }
+    const int nw = nr;
     if (nw <= 64) {  // the usual case: a bitonic network across the wave's lanes, in registers
         double dk = lane < nw ? s_wd[lane] : INFINITY;
         int ik = lane < nw ? s_wi[lane] : 0x7fffffff;

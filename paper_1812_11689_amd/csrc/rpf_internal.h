@@ -500,6 +500,50 @@ __device__ inline void group8_dist32_64x2(const float *__restrict__ a, const flo
     }
 }
 
+// The binary64 distances alone of group8_dist32_64x2 (the same operations, in the same order).
+__device__ inline void group8_dist64x2(const float *__restrict__ a, const float *__restrict__ b0,
+                                       const float *__restrict__ b1, int d, int g, double (&D64)[2]) {
+    double s[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    auto step = [&](const float4 av, const float4 bv, int r) {
+        const double d0 = (double)av.x - (double)bv.x, d1 = (double)av.y - (double)bv.y;
+        const double d2 = (double)av.z - (double)bv.z, d3 = (double)av.w - (double)bv.w;
+        s[r][0] = __builtin_fma(d0, d0, s[r][0]);
+        s[r][1] = __builtin_fma(d1, d1, s[r][1]);
+        s[r][2] = __builtin_fma(d2, d2, s[r][2]);
+        s[r][3] = __builtin_fma(d3, d3, s[r][3]);
+    };
+    int j = 4 * g;
+    for (; j + 96 < d; j += 128) {  // four steps of both rows in flight
+        float4 x0[4], x1[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            x0[k] = *reinterpret_cast<const float4 *>(b0 + j + 32 * k);
+            x1[k] = *reinterpret_cast<const float4 *>(b1 + j + 32 * k);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float4 av = *reinterpret_cast<const float4 *>(a + j + 32 * k);
+            step(av, x0[k], 0);
+            step(av, x1[k], 1);
+        }
+    }
+    for (; j < d; j += 32) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(b0 + j);
+        const float4 x1 = *reinterpret_cast<const float4 *>(b1 + j);
+        const float4 av = *reinterpret_cast<const float4 *>(a + j);
+        step(av, x0, 0);
+        step(av, x1, 1);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        double u = (s[r][0] + s[r][1]) + (s[r][2] + s[r][3]);
+        u = u + shfl_xor_d(u, 1);
+        u = u + shfl_xor_d(u, 2);
+        u = u + shfl_xor_d(u, 4);
+        D64[r] = u;
+    }
+}
+
 // ---------------------------------------------------------------- host-side launch helpers
 
 struct Prof;  // per-kernel event timing (rpf_api.hip)
