@@ -1076,37 +1076,18 @@ __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
     stat_add(A, 1, 1ull);
 }
 
-// One wave per result row, four rows per block.  Entries stay in registers; an LDS hash
-// of indices marks the first copy of every index (any copy's interval is valid for it).
-template <bool VEC, int Q>
-__global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
-    // hash table twice the records a row can hold (at most 64 Q), re-rank set half of it
-    constexpr int kHT = Q <= 4 ? 512 : 1024;
-    constexpr int kHBits = Q <= 4 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
+// The steps of k_final for one row once its records are counted: Q records per lane in
+// registers, an index hash of HT entries in LDS (s_key), R and the selection keys in s_r and
+// s_d (HT / 2 each), the query row in s_q.
+template <bool VEC, int Q, int HT>
+__device__ __attribute__((always_inline)) inline void final_row(const FinalArgs &A, int64_t a, int lane,
+                                                                int32_t *s_key, int32_t *s_r, uint32_t *s_d,
+                                                                const float *s_q, int c1, int c2) {
+    constexpr int kHT = HT;
+    constexpr int kHBits = HT == 512 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
-    __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
-    __shared__ int32_t s_r[4][kRCap];   // the rerank set R; then, compacted in place, the window
-    __shared__ uint32_t s_d[4][kRCap];
-    extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t a = (int64_t)blockIdx.x * 4 + w;
-    if (a >= nrows) return;
-    const int dq = (A.d + 3) & ~3;
-    float *s_q = s_qall + w * dq;
     const int K = A.K;
-    const int c1 = A.lcnt[a], c2 = A.cnt[a];
-    if (lane == 0) {
-        stat_add(A, 5, (unsigned long long)max(c1, 0));
-        stat_add(A, 6, (unsigned long long)max(c2, 0));
-    }
-    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > 64 * Q) {
-        if (lane == 0) push_fallback(A, a);
-        return;
-    }
-    for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
-    for (int j = lane; j < A.d; j += 64) s_q[j] = A.Qr[a * A.d + j];
-    wave_sync();
     int32_t eidx[Q];
     uint32_t elb[Q], eub[Q];
     bool first[Q];
@@ -1131,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
             eub[q] = fkey(e.ub);
             uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kHBits);
             while (true) {
-                const int old = atomicCAS(&s_key[w][h], -1, e.idx);
+                const int old = atomicCAS(&s_key[h], -1, e.idx);
                 if (old == -1) {
                     first[q] = true;
                     break;
@@ -1156,13 +1137,13 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
 #pragma unroll
         for (int q = 0; q < Q; q++) {
             const uint64_t mk = __ballot(first[q]);
-            if (first[q]) s_d[w][nf + mask_rank(mk)] = eub[q];
+            if (first[q]) s_d[nf + mask_rank(mk)] = eub[q];
             nf += __popcll(mk);
         }
         wave_sync();
         uint32_t fu[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) fu[q] = lane + 64 * q < nd ? s_d[w][lane + 64 * q] : 0xffffffffu;
+        for (int q = 0; q < 4; q++) fu[q] = lane + 64 * q < nd ? s_d[lane + 64 * q] : 0xffffffffu;
         tv = __uint_as_float(wave_kth_upper<4>(fu, K - 1));
         wave_sync();
     } else if (nd >= K) {
@@ -1178,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         const bool in = first[q] && elb[q] <= tp;
         const uint64_t mk = __ballot(in);
         const int pos = nr + mask_rank(mk);
-        if (in && pos < kRCap) s_r[w][pos] = eidx[q];
+        if (in && pos < kRCap) s_r[pos] = eidx[q];
         nr += __popcll(mk);
     }
     wave_sync();
@@ -1189,12 +1170,12 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     // the canonical binary64 distance of every member of R (R is small: about K rows), so
     // the K best by (D64, index) come straight from R; the hash table is dead by now and
     // holds the binary64 values
-    double *s_dd = reinterpret_cast<double *>(s_key[w]);  // kHT int32 = kRCap doubles
+    double *s_dd = reinterpret_cast<double *>(s_key);  // kHT int32 = kRCap doubles
     const int g = lane & 7, grp = lane >> 3;
     if constexpr (VEC) {  // two candidates per group of eight lanes at a time
         for (int base = 0; base < nr; base += 16) {
             const int i0 = base + grp, i1 = i0 + 8;
-            const int b0 = s_r[w][i0 < nr ? i0 : 0], b1 = s_r[w][i1 < nr ? i1 : 0];
+            const int b0 = s_r[i0 < nr ? i0 : 0], b1 = s_r[i1 < nr ? i1 : 0];
             double D64[2];
             group8_dist64x2(s_q, A.X + (int64_t)b0 * A.d, A.X + (int64_t)b1 * A.d, A.d, g, D64);
             if (g == 0 && i0 < nr) s_dd[i0] = D64[0];
@@ -1203,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     } else {
         for (int base = 0; base < nr; base += 8) {
             const int i = base + grp;
-            const int b = s_r[w][i < nr ? i : 0];
+            const int b = s_r[i < nr ? i : 0];
             float D32;
             double D64;
             group8_dist32_64<VEC>(s_q, A.X + (int64_t)b * A.d, A.d, g, D32, D64);
@@ -1213,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     wave_sync();
     // R is sorted whole by (D64, index): it holds the true top K (every candidate with
     // lb <= tau'), so its first K are the answer
-    int32_t *s_wi = s_r[w];
+    int32_t *s_wi = s_r;
     double *s_wd = s_dd;
     const int nw = nr;
     if (nw <= 64) {  // the usual case: a bitonic network across the wave's lanes, in registers
@@ -1283,6 +1264,45 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         stat_add(A, 2, (unsigned long long)nr);
         stat_add(A, 3, (unsigned long long)nw);
     }
+}
+
+// One wave per result row, four rows per block.  Entries stay in registers; an LDS hash
+// of indices marks the first copy of every index (any copy's interval is valid for it).
+template <bool VEC, int Q>
+__global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
+    // hash table twice the records a row can hold (at most 64 Q), re-rank set half of it
+    constexpr int kHT = Q <= 4 ? 512 : 1024;
+    constexpr int kHBits = Q <= 4 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
+    static_assert((1 << kHBits) == kHT, "hash range must equal the table");
+    constexpr int kRCap = kHT / 2;
+    __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
+    __shared__ int32_t s_r[4][kRCap];   // the rerank set R; then, compacted in place, the window
+    __shared__ uint32_t s_d[4][kRCap];
+    extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t a = (int64_t)blockIdx.x * 4 + w;
+    if (a >= nrows) return;
+    const int dq = (A.d + 3) & ~3;
+    float *s_q = s_qall + w * dq;
+    const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    if (lane == 0) {
+        stat_add(A, 5, (unsigned long long)max(c1, 0));
+        stat_add(A, 6, (unsigned long long)max(c2, 0));
+    }
+    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > 64 * Q) {
+        if (lane == 0) push_fallback(A, a);
+        return;
+    }
+    for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
+    for (int j = lane; j < A.d; j += 64) s_q[j] = A.Qr[a * A.d + j];
+    wave_sync();
+    // most rows fill a few records per lane: they take the four-per-lane steps
+    if (Q > 4 && c1 + c2 <= 256)
+        final_row<VEC, 4, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+    else if (Q > 8 && c1 + c2 <= 512)
+        final_row<VEC, 8, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+    else
+        final_row<VEC, Q, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
 }
 
 // ---------------------------------------------------------------- final merge, one block per row
