@@ -1591,6 +1591,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
     __shared__ int s_tn;
     __shared__ uint32_t s_scan[8];
     __shared__ int32_t s_mid[256];
+    __shared__ LeafDesc s_lf[64];
     extern __shared__ __align__(16) float s_q[];
     const int tid = threadIdx.x, g = tid & 7, grp = tid >> 3;
     const int nfb = *F.fb_cnt;
@@ -1601,27 +1602,44 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
         for (int j = tid; j < F.d; j += 256) s_q[j] = F.Qr[a * F.d + j];
         if (tid == 0) s_tn = 0;
         __syncthreads();
-        for (int t = 0; t < F.T; t++) {
-            const int heap = F.row_leaf[(int64_t)t * F.nrows + a];
-            const LeafDesc lf = F.leaves[F.heap_leaf[heap]];
-            for (int base = 0; base < lf.size; base += 256) {
-                // distances of up to 256 members, 8 lanes per member; the member ids come
-                // from LDS, read in one pass
+        for (int t0 = 0; t0 < F.T; t0 += 64) {  // the row's leaves, 64 trees at a time
+            const int nt = min(64, F.T - t0);
+            __syncthreads();
+            if (tid < nt) s_lf[tid] = F.leaves[F.heap_leaf[F.row_leaf[(int64_t)(t0 + tid) * F.nrows + a]]];
+            __syncthreads();
+            // pieces of up to 256 members, tree after tree; the ids of the next piece are
+            // loaded while the current one is processed
+            auto ids_of = [&](int tt, int base) {
+                const LeafDesc &l = s_lf[tt];
+                return base + tid < l.size ? F.perm[(int64_t)(t0 + tt) * F.n + l.off + base + tid] : -1;
+            };
+            int ct = 0, cb = 0;
+            int nid = ids_of(0, 0);
+            while (ct < nt) {
                 __syncthreads();
-                s_mid[tid] = base + tid < lf.size ? F.perm[(int64_t)t * F.n + lf.off + base + tid] : -1;
+                s_mid[tid] = nid;
                 __syncthreads();
-                if constexpr (VEC) {  // two members per group of eight lanes at a time
-                    for (int sub = 0; sub < 256; sub += 64) {
-                        const int l0 = sub + grp, l1 = l0 + 32;
-                        const int b0 = s_mid[l0], b1 = s_mid[l1];
-                        float D32[2];
-                        double D64[2];
-                        group8_dist32_64x2(s_q, F.X + (int64_t)(b0 < 0 ? 0 : b0) * F.d,
-                                           F.X + (int64_t)(b1 < 0 ? 0 : b1) * F.d, F.d, g, D32, D64);
+                cb += 256;
+                if (cb >= s_lf[ct].size) {
+                    cb = 0;
+                    ct++;
+                }
+                if (ct < nt) nid = ids_of(ct, cb);
+                if constexpr (VEC) {  // four members per group of eight lanes at a time
+                    for (int sub = 0; sub < 256; sub += 128) {
+                        int bm[4];
+                        const float *rows[4];
+#pragma unroll
+                        for (int h = 0; h < 4; h++) {
+                            bm[h] = s_mid[sub + grp + 32 * h];
+                            rows[h] = F.X + (int64_t)(bm[h] < 0 ? 0 : bm[h]) * F.d;
+                        }
+                        double D64[4];
+                        group8_dist64x4(s_q, rows, F.d, g, D64);
                         if (g == 0) {
 #pragma unroll
-                            for (int h = 0; h < 2; h++) {
-                                const int l = h ? l1 : l0, b = h ? b1 : b0;
+                            for (int h = 0; h < 4; h++) {
+                                const int l = sub + grp + 32 * h, b = bm[h];
                                 const bool ok = b >= 0 && !(F.exclude_self && b == a);
                                 s_cd[l] = ok ? D64[h] : INFINITY;
                                 s_ci[l] = ok ? b : 0x7fffffff;
@@ -1644,22 +1662,63 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                     s_ci[i] = 0x7fffffff;
                 }
                 __syncthreads();
-                // with a full list, a member at or past its last entry in (D, idx) order cannot
-                // enter it (a repeated index repeats its distance): skip the merge when none is
-                // before it
+                // only members before the list's last entry in (D, idx) order can enter a full
+                // list (a repeated index repeats its distance): they are compacted to the front
+                // and the list appended behind them
                 const int tn = s_tn;
+                const double dc = s_cd[tid];
+                const int ic = s_ci[tid];
+                bool take = ic != 0x7fffffff;
                 if (tn == K) {
                     const double lastd = s_td[K - 1];
                     const int lasti = s_ti[K - 1];
-                    const double dc = s_cd[tid];
-                    const int ic = s_ci[tid];
-                    const bool better = dc < lastd || (dc == lastd && ic < lasti);
-                    if (__syncthreads_count(better) == 0) continue;
+                    take = take && (dc < lastd || (dc == lastd && ic < lasti));
                 }
-                // append the current top list, then sort 512 by (D, idx)
+                uint32_t pos, ncand;
+                block_excl_scan256(take ? 1u : 0u, reinterpret_cast<uint32_t *>(s_scan), pos, ncand);
+                if (ncand == 0) continue;
+                if (take) {
+                    s_cd[pos] = dc;
+                    s_ci[pos] = ic;
+                }
                 for (int i = tid; i < tn; i += 256) {
-                    s_cd[256 + i] = s_td[i];
-                    s_ci[256 + i] = s_ti[i];
+                    s_cd[ncand + i] = s_td[i];
+                    s_ci[ncand + i] = s_ti[i];
+                }
+                const int tot = (int)ncand + tn;
+                __syncthreads();
+                if (tot <= 64) {  // the usual case: one wave sorts in registers and keeps K distinct
+                    if (tid < 64) {
+                        double dk = tid < tot ? s_cd[tid] : INFINITY;
+                        int ik = tid < tot ? s_ci[tid] : 0x7fffffff;
+                        for (int size = 2; size <= 64; size <<= 1) {
+                            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                                const double dp = __shfl_xor(dk, stride, 64);
+                                const int ip = __shfl_xor(ik, stride, 64);
+                                const bool mine_first = dk < dp || (dk == dp && ik <= ip);
+                                const bool want_first = ((tid & stride) == 0) == ((tid & size) == 0);
+                                if (mine_first != want_first) {
+                                    dk = dp;
+                                    ik = ip;
+                                }
+                            }
+                        }
+                        const int iprev = __shfl_up(ik, 1, 64);
+                        const bool keep = ik != 0x7fffffff && (tid == 0 || ik != iprev);
+                        const uint64_t mk = __ballot(keep);
+                        const int r = mask_rank(mk);
+                        if (keep && r < K) {
+                            s_td[r] = dk;
+                            s_ti[r] = ik;
+                        }
+                        if (tid == 0) s_tn = min(__popcll(mk), K);
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                for (int i = tot + tid; i < 512; i += 256) {
+                    s_cd[i] = INFINITY;
+                    s_ci[i] = 0x7fffffff;
                 }
                 __syncthreads();
                 for (int size = 2; size <= 512; size <<= 1)

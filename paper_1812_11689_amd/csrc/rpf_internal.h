@@ -544,6 +544,50 @@ __device__ inline void group8_dist64x2(const float *__restrict__ a, const float 
     }
 }
 
+// The binary64 distances of four rows at once (the same operations, in the same order, as
+// group8_dist32_64 computes D64): sixteen 16-byte loads in flight per lane for d = 128.
+__device__ inline void group8_dist64x4(const float *__restrict__ a, const float *const (&b)[4], int d, int g,
+                                       double (&D64)[4]) {
+    double s[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) s[r][0] = s[r][1] = s[r][2] = s[r][3] = 0.0;
+    auto step = [&](const float4 av, const float4 bv, int r) {
+        const double d0 = (double)av.x - (double)bv.x, d1 = (double)av.y - (double)bv.y;
+        const double d2 = (double)av.z - (double)bv.z, d3 = (double)av.w - (double)bv.w;
+        s[r][0] = __builtin_fma(d0, d0, s[r][0]);
+        s[r][1] = __builtin_fma(d1, d1, s[r][1]);
+        s[r][2] = __builtin_fma(d2, d2, s[r][2]);
+        s[r][3] = __builtin_fma(d3, d3, s[r][3]);
+    };
+    int j = 4 * g;
+    for (; j + 96 < d; j += 128) {  // four steps of all four rows in flight
+        float4 x[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[r][k] = *reinterpret_cast<const float4 *>(b[r] + j + 32 * k);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float4 av = *reinterpret_cast<const float4 *>(a + j + 32 * k);
+#pragma unroll
+            for (int r = 0; r < 4; r++) step(av, x[r][k], r);
+        }
+    }
+    for (; j < d; j += 32) {
+        const float4 av = *reinterpret_cast<const float4 *>(a + j);
+#pragma unroll
+        for (int r = 0; r < 4; r++) step(av, *reinterpret_cast<const float4 *>(b[r] + j), r);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        double u = (s[r][0] + s[r][1]) + (s[r][2] + s[r][3]);
+        u = u + shfl_xor_d(u, 1);
+        u = u + shfl_xor_d(u, 2);
+        u = u + shfl_xor_d(u, 4);
+        D64[r] = u;
+    }
+}
+
 // ---------------------------------------------------------------- host-side launch helpers
 
 struct Prof;  // per-kernel event timing (rpf_api.hip)
