@@ -690,21 +690,32 @@ __global__ __launch_bounds__(256) void k_proj_root(const float *__restrict__ X, 
         ra[k] = j < d ? *reinterpret_cast<const float4 *>(xa + j) : make_float4(0.f, 0.f, 0.f, 0.f);
         rb[k] = j < d ? *reinterpret_cast<const float4 *>(xb + j) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    auto stage = [&](int t, double *dst) {  // node, left child, right child (zero for a leaf child)
-        for (int j = tid; j < 3 * 128; j += 256) {
-            const int k = j >> 7, jj = j & 127;
+    // a tree's three directions (node, left child, right child; zero for a leaf child): thread
+    // tid holds elements tid and tid + 256.  The loads for tree t + 2 are issued while tree t
+    // is projected, and stored to LDS after it, so their latency is hidden.
+    float nv[2];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const int j = tid + 256 * e, k = j >> 7, jj = j & 127;
             float v = 0.f;
-            if (jj < d) {
+            if (j < 3 * 128 && jj < d) {
                 const int heap = k == 0 ? sg.heap : k == 1 ? lk.child_heap[0] : lk.child_heap[1];
                 if (heap > 0) v = R[((int64_t)t * H + (heap - 1)) * (int64_t)d + jj];
             }
-            dst[j] = v;
+            nv[e] = v;
         }
     };
-    stage(0, s_rd[0]);
+    auto put = [&](double *dst) {
+#pragma unroll
+        for (int e = 0; e < 2; e++)
+            if (tid + 256 * e < 3 * 128) dst[tid + 256 * e] = nv[e];
+    };
+    fetch(0);
+    put(s_rd[0]);
+    if (ntree > 1) fetch(1);
     for (int t = 0; t < ntree; t++) {
         __syncthreads();  // s_rd[t & 1] is staged; everyone is done with s_rd[(t + 1) & 1]
-        if (t + 1 < ntree) stage(t + 1, s_rd[(t + 1) & 1]);
         const double *r = s_rd[t & 1];
         double s[6][4];
 #pragma unroll
@@ -749,6 +760,10 @@ __global__ __launch_bounds__(256) void k_proj_root(const float *__restrict__ X, 
                 keys[base + ib] = key_of(p[3]);
                 ahead[base + ib] = make_double2(p[4], p[5]);
             }
+        }
+        if (t + 1 < ntree) {  // tree t + 1's directions (loaded during this tree), then t + 2's loads
+            put(s_rd[(t + 1) & 1]);
+            if (t + 2 < ntree) fetch(t + 2);
         }
     }
 }
