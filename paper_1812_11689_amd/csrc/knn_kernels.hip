@@ -933,27 +933,32 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     }
     // the row's leaf in each of the B trees: lane t holds its start in the permutation
     const int32_t loff = lane < B ? si.roff[(int64_t)lane * nrows + a] : 0;
-    const float inv_ml = 1.f / (float)ML;
+    // ML is a multiple of 64, so the slots of wave-wide column q all lie in tree q / (ML / 64):
+    // the tree, its leaf start and the column offset are the same for every lane
+    const int ncol = B * (ML >> 6);  // wave-wide slot columns of the row
     uint32_t u[Q];  // ub bits of the finite slots, 0xffffffff for the others
     float l[Q];
     int32_t id[Q];  // -1 for a slot that no pair fills (lb = +inf)
+    int tb = 0, col0 = 0;  // tree of column q, and its first slot's position in the tree
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
-        const bool in = i < c;
+        const bool in = q < ncol;  // i < c for every lane
         const float2 e = in ? plub[base_slot + i] : make_float2(INFINITY, INFINITY);
         const uint32_t ub = fkey(e.y);
         u[q] = ub < 0x7f800000u ? ub : 0xffffffffu;
         l[q] = e.x;
-        // the slot's tree: (i + 1/2) / ML in binary32 stays at least 1/(2 ML) away from
-        // the integers, well above its rounding, so the floor is exact (i, ML < 2^12)
-        const int tb = (int)(((float)i + 0.5f) * inv_ml);
+        const int32_t off = __builtin_amdgcn_readlane(loff, in ? tb : 0);
         // the permutation entry is read whatever the slot holds (clamped into the tree), so
         // that it does not wait for the slot's bounds; an empty slot drops it
-        const int32_t off = __shfl(loff, in ? tb : 0, 64);
-        const int64_t pos = min((int64_t)off + (i - tb * ML), si.n - 1);
+        const int32_t pos = min(off + col0 + lane, (int32_t)(si.n - 1));
         const int32_t pv = in ? si.perm[(int64_t)tb * si.n + pos] : -1;
         id[q] = e.x < INFINITY ? pv : -1;
+        col0 += 64;
+        if (col0 == ML) {
+            col0 = 0;
+            tb++;
+        }
     }
     for (int i = lane; i < HT; i += 64) {
         s_hid[w][i] = -1;
@@ -1950,8 +1955,12 @@ __global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q,
 // Phase I trees: at most kFirstTrees, and K * B must leave room in the merge's small set
 // trees of Phase I: at most kFirstTrees, and few enough that the K B smallest bounds fit the
 // representative set and the B ML slots of a row fit one wave's registers
+// Phase I slots per (row, tree): the largest leaf rounded up to a wave, so that the slots of a
+// row's wave-wide column q all belong to one tree
+static inline int slot_stride(int max_leaf) { return (std::max(max_leaf, 1) + 63) & ~63; }
+
 static int first_trees(int T, int K, int max_leaf) {
-    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K, kMergeCap / std::max(max_leaf, 1)}));
+    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K, kMergeCap / slot_stride(max_leaf)}));
 }
 
 static BoundCoef bound_coef(int prec, int d) {
@@ -2170,7 +2179,7 @@ template <typename Get>
 static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
     cand_caps(K, v.T, cs.B, rows, w.lcap, w.cap2);
-    w.cap1 = v.max_leaf * cs.B;      // Phase I slots per row (index / lb / ub arrays)
+    w.cap1 = slot_stride(v.max_leaf) * cs.B;  // Phase I slots per row (bounds)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
     const size_t first_bytes = (size_t)rows * w.cap1 * 8 + (size_t)rows * cs.B * 4;  // slots, leaf starts
     const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
@@ -2248,7 +2257,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     TileOut o1;
     o1.mode = 0;
     o1.t0 = 0;
-    o1.ML = v.max_leaf;
+    o1.ML = slot_stride(v.max_leaf);
     o1.cap = cap1;
     o1.ent = nullptr;
     o1.cnt = cnt;
@@ -2275,7 +2284,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         const bool big = K * cs.B > 128;
         const SlotIndex si{roff, v.perm, v.n};
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, v.max_leaf, plub, si, cap1, tau, list,
+            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, slot_stride(v.max_leaf), plub, si, cap1, tau, list,
                                lcnt, lcap, cnt);
         };
         if (cap1 <= 256) big ? go(k_merge_first<4, 1024>) : go(k_merge_first<4, 512>);
@@ -2355,7 +2364,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
 
 // largest first-phase tree count the merge supports for this forest and K
 static int max_first_trees(const ForestView &v, int K) {
-    return std::max(1, std::min({v.T, (kSetCap - 64) / K, kMergeCap / std::max(v.max_leaf, 1)}));
+    return std::max(1, std::min({v.T, (kSetCap - 64) / K, kMergeCap / slot_stride(v.max_leaf)}));
 }
 
 static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, int B = 0) {
@@ -2417,7 +2426,7 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
         // capacities grow with B for cap1 and shrink for cap2: take each over 1..B
         for (int B = 1; B <= cs.B; B++) {
             cand_caps(K, v.T, B, v.n, lcap, cap2);
-            const size_t cap1 = (size_t)v.max_leaf * B;
+            const size_t cap1 = (size_t)slot_stride(v.max_leaf) * B;
             b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 8 + (size_t)v.n * B * 4,
                                                    (size_t)v.n * cap2 * sizeof(Ent)) + 256);
             b_list = std::max(b_list, (size_t)v.n * lcap * sizeof(Ent));
@@ -2455,7 +2464,7 @@ void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *ou
     const CandStage cs = all_points_stage(v, p->K, p->excl, B);
     CandWs w = p->w;
     cand_caps(p->K, v.T, cs.B, v.n, w.lcap, w.cap2);
-    w.cap1 = v.max_leaf * cs.B;
+    w.cap1 = slot_stride(v.max_leaf) * cs.B;
     cand_launches(v, cs, p->K, w, out_idx, out_dist, s);
 }
 
@@ -2603,7 +2612,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob) * (qtile_qs(v.prec, v.dp) ? 2 : 1);
     int lcap = 0, cap2 = 0;
     cand_caps(K, v.T, B, m, lcap, cap2);
-    const uint64_t cap1 = (uint64_t)v.max_leaf * B;
+    const uint64_t cap1 = (uint64_t)slot_stride(v.max_leaf) * B;
     b += std::max(m * cap1 * 8 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
