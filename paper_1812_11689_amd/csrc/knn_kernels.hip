@@ -462,7 +462,7 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
 constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE == 1 && NB == 8 ? 12 : NB) : 1; }
 
 template <int NB, int PREC, int MODE>
-__global__ __launch_bounds__(64 * sym_waves(NB, MODE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE) > 8 ? 6 : 1)))
+__global__ __launch_bounds__(64 * sym_waves(NB, MODE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE) > 8 ? 6 : NB == 8 ? 4 : 1)))
 void k_tile_sym(
     const TileJob *__restrict__ jobs, const float *__restrict__ X, int d, int dp, const float *__restrict__ centroid,
     int nleaf, int64_t stride_tree, const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc,
