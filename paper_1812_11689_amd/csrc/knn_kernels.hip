@@ -206,7 +206,7 @@ struct TileOut {
     Ent *ent;          // mode 1 records
     int32_t *cnt;      // mode 1 counters
     const float *tau;  // mode 1 thresholds
-    float2 *plub;      // mode 0: (lb, ub) per slot, (+inf, +inf) where empty
+    uint32_t *plub;    // mode 0: packed bounds per slot (pack_bounds), (+inf, +inf) where empty
     int32_t *roff;     // mode 0: [tree - t0][nrows] start of the row's leaf in the permutation
     int64_t nrows;
 };
@@ -224,8 +224,18 @@ __device__ inline Ent make_ent(int idx, float lb, float ub) {
 
 __device__ inline Ent invalid_rec() { return make_ent(-1, INFINITY, INFINITY); }
 
+// A Phase I slot: the pair's bounds in four bytes, each kept to the top 16 bits of its
+// binary32 pattern (the bfloat16 range) rounded outward -- lb toward zero (truncation of a
+// non-negative value), ub away from it -- so they stay bounds on the squared distance.  The
+// low half holds lb, the high half ub; +inf in both marks an empty slot.
+__device__ inline uint32_t pack_bounds(float lb, float ub) {
+    const uint32_t l = __float_as_uint(lb) >> 16;
+    const uint32_t u = (__float_as_uint(ub) + 0xffffu) >> 16;  // +inf stays +inf
+    return (u << 16) | l;
+}
+
 __device__ inline void put_first(const TileOut &o, int64_t slot, float lb, float ub) {
-    o.plub[slot] = make_float2(lb, ub);
+    o.plub[slot] = pack_bounds(lb, ub);
 }
 
 __device__ inline void put_first_empty(const TileOut &o, int64_t slot) { put_first(o, slot, INFINITY, INFINITY); }
@@ -616,29 +626,20 @@ void k_tile_sym(
                 if (colok && rowok && !(diag && (row > col || (row == col && exclude_self))))
                     put_first(out, (int64_t)s_pt[row] * out.cap + (int64_t)tb * out.ML + col, lbv[v], ubv[v]);
             }
-            // transposed: output row = column c of the block, positions 32 bi + r; lb goes
-            // through the transpose first (kept in registers), then ub, then both are stored
-            float lbt[16];
+            // transposed: output row = column c of the block, positions 32 bi + r; the packed
+            // bounds go through the transpose and are stored
+            uint32_t *tru = reinterpret_cast<uint32_t *>(tr);
+            wave_sync();
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                float *src = h ? ubv : lbv;
-                wave_sync();
+            for (int v = 0; v < 16; v++)
+                tru[cl * 33 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)] = pack_bounds(lbv[v], ubv[v]);
+            wave_sync();
 #pragma unroll
-                for (int v = 0; v < 16; v++) tr[cl * 33 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)] = src[v];
-                wave_sync();
-#pragma unroll
-                for (int c0 = 0; c0 < 32; c0 += 2) {
-                    const int c = c0 + (lane >> 5), r = lane & 31;
-                    const float val = tr[c * 33 + r];
-                    if (h == 0) {
-                        lbt[c0 >> 1] = val;
-                    } else {
-                        const int cg = 32 * bj + c, rg = 32 * bi + r;
-                        if (cg < m && rg < m && rg != cg && !(diag && rg > cg))
-                            out.plub[(int64_t)s_pt[cg] * out.cap + (int64_t)tb * out.ML + rg] =
-                                make_float2(lbt[c0 >> 1], val);
-                    }
-                }
+            for (int c0 = 0; c0 < 32; c0 += 2) {
+                const int c = c0 + (lane >> 5), r = lane & 31;
+                const int cg = 32 * bj + c, rg = 32 * bi + r;
+                if (cg < m && rg < m && rg != cg && !(diag && rg > cg))
+                    out.plub[(int64_t)s_pt[cg] * out.cap + (int64_t)tb * out.ML + rg] = tru[c * 33 + r];
             }
         }
         return;
@@ -908,7 +909,7 @@ struct SlotIndex {  // where the index of a Phase I slot comes from: the row's l
 
 template <int Q, int HT>
 __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B, int ML,
-                                                     const float2 *__restrict__ plub, SlotIndex si, int cap,
+                                                     const uint32_t *__restrict__ plub, SlotIndex si, int cap,
                                                      float *__restrict__ tau, Ent *__restrict__ list,
                                                      int32_t *__restrict__ lcnt, int lcap,
                                                      int32_t *__restrict__ cnt) {
@@ -944,16 +945,17 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
         const bool in = q < ncol;  // i < c for every lane
-        const float2 e = in ? plub[base_slot + i] : make_float2(INFINITY, INFINITY);
-        const uint32_t ub = fkey(e.y);
+        const uint32_t e = in ? plub[base_slot + i] : 0x7f807f80u;  // packed bounds (pack_bounds)
+        const uint32_t ub = e & 0xffff0000u;                        // fkey of the ub kept
+        const float lb = __uint_as_float(e << 16);
         u[q] = ub < 0x7f800000u ? ub : 0xffffffffu;
-        l[q] = e.x;
+        l[q] = lb;
         const int32_t off = __builtin_amdgcn_readlane(loff, in ? tb : 0);
         // the permutation entry is read whatever the slot holds (clamped into the tree), so
         // that it does not wait for the slot's bounds; an empty slot drops it
         const int32_t pos = min(off + col0 + lane, (int32_t)(si.n - 1));
         const int32_t pv = in ? si.perm[(int64_t)tb * si.n + pos] : -1;
-        id[q] = e.x < INFINITY ? pv : -1;
+        id[q] = lb < INFINITY ? pv : -1;
         col0 += 64;
         if (col0 == ML) {
             col0 = 0;
@@ -2181,7 +2183,7 @@ static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get g
     cand_caps(K, v.T, cs.B, rows, w.lcap, w.cap2);
     w.cap1 = slot_stride(v.max_leaf) * cs.B;  // Phase I slots per row (bounds)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
-    const size_t first_bytes = (size_t)rows * w.cap1 * 8 + (size_t)rows * cs.B * 4;  // slots, leaf starts
+    const size_t first_bytes = (size_t)rows * w.cap1 * 4 + (size_t)rows * cs.B * 4;  // slots, leaf starts
     const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
     w.region = static_cast<uint8_t *>(get(std::max(first_bytes, second_bytes) + 256));
     w.tau = static_cast<float *>(get(rows * 4));
@@ -2247,8 +2249,8 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     int32_t *cnt = w.cnt, *lcnt = w.lcnt, *fb_list = w.fb_list, *fb_cnt = w.fb_cnt;
     Ent *list = w.list;
     Ent *ent = reinterpret_cast<Ent *>(region);
-    float2 *plub = reinterpret_cast<float2 *>(region);
-    int32_t *roff = reinterpret_cast<int32_t *>(region + (size_t)rows * cap1 * 8);
+    uint32_t *plub = reinterpret_cast<uint32_t *>(region);
+    int32_t *roff = reinterpret_cast<int32_t *>(region + (size_t)rows * cap1 * 4);
     fill_u32(cnt, rows, 0, s);
     fill_u32(fb_cnt, 4, 0, s);
     fill_u32(v.stats, kStatSlots * 8 * 2, 0, s);
@@ -2427,7 +2429,7 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
         for (int B = 1; B <= cs.B; B++) {
             cand_caps(K, v.T, B, v.n, lcap, cap2);
             const size_t cap1 = (size_t)slot_stride(v.max_leaf) * B;
-            b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 8 + (size_t)v.n * B * 4,
+            b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 4 + (size_t)v.n * B * 4,
                                                    (size_t)v.n * cap2 * sizeof(Ent)) + 256);
             b_list = std::max(b_list, (size_t)v.n * lcap * sizeof(Ent));
         }
@@ -2613,7 +2615,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     int lcap = 0, cap2 = 0;
     cand_caps(K, v.T, B, m, lcap, cap2);
     const uint64_t cap1 = (uint64_t)slot_stride(v.max_leaf) * B;
-    b += std::max(m * cap1 * 8 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
+    b += std::max(m * cap1 * 4 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
 }
