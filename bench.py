@@ -71,6 +71,10 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
     ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="points whose all-points kNN the CPU baseline times (extrapolated to n)")
+    ap.add_argument("--target-recall", type=float, default=0.99,
+                    help="recall the at-target leg looks for by growing more trees (0 = skip the leg)")
+    ap.add_argument("--target-trees", default="48,64,80,96,128",
+                    help="tree counts the at-target leg tries, in order (the first T trees are the bench's)")
     ap.add_argument("--cpu-trees", type=int, default=0,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
@@ -361,6 +365,57 @@ def main():
     truth = exact_knn_sample(X, torch.from_numpy(pts).cuda(), K)
     recall = recall_of(idx32.cpu().numpy()[pts], truth)
 
+    # queries/s at the target recall: the same points and the same first T trees, plus more
+    # trees of the same direction streams (tree t always uses stream (seed, t)), until the
+    # sampled recall reaches the target; then the fp32 and bf16 steps are timed at that T
+    target = None
+    if args.target_recall > 0:
+        sweep, Rt, hit = [], R, None
+        for Tt in [int(v) for v in args.target_trees.split(",") if int(v) > T]:
+            extra = W.directions(w.dir_seed, Tt - Rt.shape[0], (1 << L) - 1, 1, d, first_tree=Rt.shape[0])
+            Rt = np.concatenate([Rt, extra])
+            Rtd = torch.from_numpy(Rt).cuda()
+            f = rpf.build(X, Tt, n0, Rtd, dist_prec="fp32")
+            it, _ = f.all_knn(K)
+            st_t = f.knn_stats()
+            f.free()
+            r_t = recall_of(it.cpu().numpy()[pts], truth)
+            sweep.append({"n_trees": Tt, "recall": round(r_t, 5), "fallback_rows": st_t.get("fallback_rows")})
+            print(f"# target leg: T={Tt} recall {r_t:.4f}", file=sys.stderr, flush=True)
+            if r_t >= args.target_recall:
+                hit = (Tt, Rtd, r_t, it)
+                break
+            del Rtd
+        target = {"target": args.target_recall, "sweep": sweep, "n_trees": None}
+        if hit is not None:
+            Tt, Rtd, r_t, it = hit
+
+            def step_t(prec):
+                f = rpf.build(X, Tt, n0, Rtd, dist_prec=prec)
+                out = f.all_knn(K)
+                f.free()
+                return out
+
+            def time_t(prec, steps=3):
+                step_t(prec)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(steps):
+                    ib, _ = step_t(prec)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t) / steps
+                return ib, {"value": round(n / el, 1), "ms_per_step": round(el * 1e3, 3)}
+
+            i32, t32 = time_t("fp32")
+            t32["identical_to_sweep"] = bool(torch.equal(i32, it))
+            target.update(n_trees=Tt, recall=round(r_t, 5), fp32=t32)
+            if not args.no_bf16:
+                i16, t16 = time_t("bf16")
+                t16["identical_to_fp32"] = bool(torch.equal(i16, i32))
+                target["bf16"] = t16
+            print(f"# target leg: {target}", file=sys.stderr, flush=True)
+            del Rtd, it
+
     for name, r in prof32.items():
         r["prec"] = "fp32"
     dom, roof = roofline(prof32)
@@ -417,6 +472,7 @@ def main():
         "step_ms_p99": round(float(np.percentile(times32, 99)) * 1e3, 3),
         "bf16_rerank": res_bf16,
         "recorded_plan": graph,
+        "at_target_recall": target,
         "knn_stats": st,
         "breakdown_ms_per_step": breakdown,
         "stages": stages,

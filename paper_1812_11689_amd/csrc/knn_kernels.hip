@@ -2161,15 +2161,16 @@ struct CandWs {
 // of Phase II trees (about K (T - B) / 2 records per row were measured on mixtures; twice that
 // plus a margin keeps overflow, which sends a row to the exhaustive path, rare).
 //
-// When that would exceed one wave's records (large K against many trees), rows go to the
-// block-per-row merge, with up to kBigCap records, as long as the Phase II buffers of all
-// rows stay within kBigBudget bytes.
-constexpr uint64_t kBigBudget = (uint64_t)2 << 30;
+// When one wave's records hold less than half of that (large K against many trees), rows go
+// to the block-per-row merge, with up to kBigCap records, as long as the Phase II buffers of
+// all rows stay within kBigBudget bytes.  Between the two, the wave merge's capacity still
+// holds well over the measured mean, and the wave merge is the faster of the two.
+constexpr uint64_t kBigBudget = (uint64_t)32 << 30;
 static void cand_caps(int K, int T, int B, int64_t rows, int &lcap, int &cap2) {
     lcap = std::min(kListCap, std::max(64, 8 * K));
     const int want = std::max(128, K * std::max(T - B, 0) + 64);
     cap2 = std::min(kFinalCap - lcap, want);
-    if (want > kFinalCap - lcap) {
+    if (want > 2 * (kFinalCap - lcap)) {
         const int big = std::min(kBigCap - lcap, want);
         if ((uint64_t)std::max<int64_t>(rows, 1) * big * sizeof(Ent) <= kBigBudget) cap2 = big;
     }

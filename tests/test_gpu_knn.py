@@ -53,6 +53,9 @@ ALL = [
     # K 100 against 12 trees: list + Phase II capacity above one wave's records, so the rows
     # take the block-per-row final merge
     ("big_k_block_merge", 12000, 16, 12, 200, 100, "fp32", "mixture", 0, 1),
+    # K 20 against 64 trees (the tree count that reaches 0.99 recall at scale is of this
+    # order): the wave merge would hold under half the wanted capacity, so the block merge runs
+    ("many_trees_block_merge", 12000, 16, 64, 50, 20, "bf16", "mixture", 0, 1),
 ]
 
 
@@ -85,7 +88,7 @@ def test_all_knn_matches_oracle(case):
     print(f"    stats {st}", flush=True)
     if name == "mass_ties":
         assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
-    if name == "big_k_block_merge":
+    if name in ("big_k_block_merge", "many_trees_block_merge"):
         assert st["fallback_rows"] < n // 10, "the block merge sent most rows to the exhaustive path"
     f.free()
 
