@@ -399,12 +399,17 @@ def main():
             def time_t(prec, steps=3):
                 step_t(prec)
                 torch.cuda.synchronize()
+                rpf.profile_reset()
+                rpf.profile_enable(True)
                 t = time.perf_counter()
                 for _ in range(steps):
                     ib, _ = step_t(prec)
                 torch.cuda.synchronize()
                 el = (time.perf_counter() - t) / steps
-                return ib, {"value": round(n / el, 1), "ms_per_step": round(el * 1e3, 3)}
+                rpf.profile_enable(False)
+                pr = rpf.profile_read()
+                bd = {k: round(v["total_ms"] / steps, 3) for k, v in sorted(pr.items(), key=lambda kv: -kv[1]["total_ms"])}
+                return ib, {"value": round(n / el, 1), "ms_per_step": round(el * 1e3, 3), "breakdown_ms_per_step": bd}
 
             i32, t32 = time_t("fp32")
             t32["identical_to_sweep"] = bool(torch.equal(i32, it))

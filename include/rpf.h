@@ -210,13 +210,15 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);
  * overflowed, the total number of candidates re-ranked in binary32 / binary64, and the
  * candidate records that reached the final merge (kept from the first trees' leaves, and
  * emitted by the remaining trees below the row's threshold; rows that overflowed count
- * what they attempted).
+ * what they attempted), and the rows whose records outgrew the one-wave final merge and were
+ * merged by a whole block instead (their results are exact either way).
  * Returns RPF_EINTERNAL when the last call met a candidate index outside [0, n) in its
  * pruning buffers (an internal error: such rows are recomputed by the exhaustive scan,
  * never dereferenced, so the outputs stay correct). */
 typedef struct {
     int64_t rows, fallback_rows, reranked32, reranked64;
     int64_t first_phase_kept, second_phase_emitted;
+    int64_t block_merged_rows;
 } rpf_knn_stats;
 
 rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out_host, void *stream);

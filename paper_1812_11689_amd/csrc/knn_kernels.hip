@@ -1048,8 +1048,10 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
 // ---------------------------------------------------------------- final merge and rerank
 
 constexpr int kListCap = 256;              // Phase I list records per row
-constexpr int kFinalQ = 12;                // most entries per lane (k_final is instantiated for 4, 8, 12)
+constexpr int kFinalQ = 12;                // entries per lane of the widest k_final in common use
 constexpr int kFinalCap = 64 * kFinalQ;    // list + emissions per row handled by k_final
+constexpr int kBigQ = 16;                  // records per thread of the block-per-row merge
+constexpr int kBigCap = 256 * kBigQ;       // list + Phase II records per row it handles
 
 struct FinalArgs {
     const Ent *list;
@@ -1067,9 +1069,11 @@ struct FinalArgs {
     float *out_dist;
     int32_t *fb_list;   // rows for the exhaustive fallback
     int32_t *fb_cnt;
+    int32_t *big_list;  // rows past the wave merge's records for the block merge (nullptr: none)
+    int32_t *big_cnt;
     int64_t npts;       // rows of X: every candidate index lies in [0, npts)
     unsigned long long *stats;  // [kStatSlots][8]: rows, fallback, reranked32, reranked64, bad_index,
-                                //                 kept1, emitted2 (summed over slots by the host)
+                                //                 kept1, emitted2, block-merged (summed over slots by the host)
 };
 
 // counters are spread over slots by block so that a million rows do not meet on one address
@@ -1083,6 +1087,18 @@ __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
     stat_add(A, 1, 1ull);
 }
 
+// A row the wave merge cannot hold goes to the block merge when its records fit the buffers
+// and the block's kBigCap, else to the exhaustive fallback.
+__device__ inline void push_overflow(const FinalArgs &A, int64_t a, int c1, int c2) {
+    if (A.big_list && c1 <= A.lcap && c2 <= A.cap && c1 + c2 <= kBigCap) {
+        const int slot = atomicAdd(A.big_cnt, 1);
+        A.big_list[slot] = (int32_t)a;
+        stat_add(A, 7, 1ull);
+    } else {
+        push_fallback(A, a);
+    }
+}
+
 // The steps of k_final for one row once its records are counted: Q records per lane in
 // registers, an index hash of HT entries in LDS (s_key), R and the selection keys in s_r and
 // s_d (HT / 2 each), the query row in s_q.
@@ -1091,7 +1107,7 @@ __device__ __attribute__((always_inline)) inline void final_row(const FinalArgs 
                                                                 int32_t *s_key, int32_t *s_r, uint32_t *s_d,
                                                                 const float *s_q, int c1, int c2) {
     constexpr int kHT = HT;
-    constexpr int kHBits = HT == 512 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
+    constexpr int kHBits = HT == 512 ? 9 : HT == 1024 ? 10 : 11;  // log2(kHT): the hash keeps that many top bits
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
     const int K = A.K;
@@ -1278,8 +1294,8 @@ __device__ __attribute__((always_inline)) inline void final_row(const FinalArgs 
 template <bool VEC, int Q>
 __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     // hash table twice the records a row can hold (at most 64 Q), re-rank set half of it
-    constexpr int kHT = Q <= 4 ? 512 : 1024;
-    constexpr int kHBits = Q <= 4 ? 9 : 10;  // log2(kHT): the hash keeps that many top bits
+    constexpr int kHT = Q <= 4 ? 512 : Q <= 12 ? 1024 : 2048;
+    constexpr int kHBits = Q <= 4 ? 9 : Q <= 12 ? 10 : 11;  // log2(kHT): the hash keeps that many top bits
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
     __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
@@ -1297,7 +1313,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         stat_add(A, 6, (unsigned long long)max(c2, 0));
     }
     if (c1 > A.lcap || c2 > A.cap || c1 + c2 > 64 * Q) {
-        if (lane == 0) push_fallback(A, a);
+        if (lane == 0) push_overflow(A, a, c1, c2);
         return;
     }
     for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
@@ -1308,6 +1324,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
         final_row<VEC, 4, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
     else if (Q > 8 && c1 + c2 <= 512)
         final_row<VEC, 8, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+    else if (Q > 12 && c1 + c2 <= 768)
+        final_row<VEC, 12, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
     else
         final_row<VEC, Q, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
 }
@@ -1318,8 +1336,6 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
 // trees): the same steps as k_final with the 256 threads of a block on one row, up to 4096
 // records (16 per thread).  Selections are the same ballot bisection, with each bit's count
 // summed over the four waves.
-constexpr int kBigQ = 16;
-constexpr int kBigCap = 256 * kBigQ;   // list + Phase II records per row
 constexpr int kBigHT = 2 * kBigCap;    // index hash (twice the records); later R's binary64 distances
 constexpr int kBigHBits = 13;          // log2(kBigHT)
 constexpr int kBigRCap = 1024;         // rerank set R
@@ -1381,19 +1397,16 @@ __device__ inline uint32_t block_kth_upper(const uint32_t (&v)[Q], int k, uint32
     return min(ans | ((1u << kLow) - 1u), hi);
 }
 
+// One row of the block merge.  `counted`: the row's record counts are not yet in the stats
+// (a row handed over by the wave merge was counted there).
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
-    __shared__ __align__(16) int32_t s_key[kBigHT];  // index hash; then R's binary64 distances
-    __shared__ int32_t s_r[kBigRCap];                // R; then, compacted, the window
-    __shared__ uint32_t s_d[kBigRCap];
-    __shared__ uint32_t s4[4];    // reductions and selection counts
-    __shared__ uint32_t s_sc[4];  // block scans
-    extern __shared__ __align__(16) float s_q[];      // the query row (d floats)
+__device__ __attribute__((always_inline)) inline void final_blk_row(const FinalArgs &A, int64_t a, bool counted,
+                                                                    int32_t *s_key, int32_t *s_r, uint32_t *s_d,
+                                                                    uint32_t *s4, uint32_t *s_sc, float *s_q) {
     const int tid = threadIdx.x, lane = tid & 63, g = lane & 7, grp = tid >> 3;
-    const int64_t a = blockIdx.x;
     const int K = A.K;
     const int c1 = A.lcnt[a], c2 = A.cnt[a];
-    if (tid == 0) {
+    if (tid == 0 && !counted) {
         stat_add(A, 5, (unsigned long long)max(c1, 0));
         stat_add(A, 6, (unsigned long long)max(c2, 0));
     }
@@ -1565,6 +1578,27 @@ __global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
         stat_add(A, 0, 1ull);
         stat_add(A, 2, (unsigned long long)nr);
         stat_add(A, 3, (unsigned long long)nw);
+    }
+}
+
+// LIST = false: one block per row.  LIST = true: the blocks walk the rows the wave merge
+// handed over (their count is final: the wave merge ran before on the same stream).
+template <bool VEC, bool LIST>
+__global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
+    __shared__ __align__(16) int32_t s_key[kBigHT];  // index hash; then R's binary64 distances
+    __shared__ int32_t s_r[kBigRCap];                // R; then, compacted, the window
+    __shared__ uint32_t s_d[kBigRCap];
+    __shared__ uint32_t s4[4];    // reductions and selection counts
+    __shared__ uint32_t s_sc[4];  // block scans
+    extern __shared__ __align__(16) float s_q[];      // the query row (d floats)
+    if constexpr (LIST) {
+        const int nb = *A.big_cnt;
+        for (int i = blockIdx.x; i < nb; i += gridDim.x) {
+            __syncthreads();  // the previous row's LDS reads are done
+            final_blk_row<VEC>(A, A.big_list[i], true, s_key, s_r, s_d, s4, s_sc, s_q);
+        }
+    } else {
+        final_blk_row<VEC>(A, blockIdx.x, false, s_key, s_r, s_d, s4, s_sc, s_q);
     }
 }
 
@@ -2161,16 +2195,16 @@ struct CandWs {
 // of Phase II trees (about K (T - B) / 2 records per row were measured on mixtures; twice that
 // plus a margin keeps overflow, which sends a row to the exhaustive path, rare).
 //
-// When one wave's records hold less than half of that (large K against many trees), rows go
-// to the block-per-row merge, with up to kBigCap records, as long as the Phase II buffers of
-// all rows stay within kBigBudget bytes.  Between the two, the wave merge's capacity still
-// holds well over the measured mean, and the wave merge is the faster of the two.
+// When that exceeds one wave's records (many trees, or a large K), the buffers take up to
+// kBigCap records per row as long as the Phase II buffers of all rows stay within kBigBudget
+// bytes: rows that outgrow the wave merge then go to the block-per-row merge rather than to
+// the exhaustive path.
 constexpr uint64_t kBigBudget = (uint64_t)32 << 30;
 static void cand_caps(int K, int T, int B, int64_t rows, int &lcap, int &cap2) {
     lcap = std::min(kListCap, std::max(64, 8 * K));
     const int want = std::max(128, K * std::max(T - B, 0) + 64);
     cap2 = std::min(kFinalCap - lcap, want);
-    if (want > 2 * (kFinalCap - lcap)) {
+    if (want > kFinalCap - lcap) {
         const int big = std::min(kBigCap - lcap, want);
         if ((uint64_t)std::max<int64_t>(rows, 1) * big * sizeof(Ent) <= kBigBudget) cap2 = big;
     }
@@ -2191,7 +2225,7 @@ static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get g
     w.cnt = static_cast<int32_t *>(get(rows * 4));
     w.list = static_cast<Ent *>(get((size_t)rows * w.lcap * sizeof(Ent)));
     w.lcnt = static_cast<int32_t *>(get(rows * 4));
-    w.fb_list = static_cast<int32_t *>(get(rows * 4));
+    w.fb_list = static_cast<int32_t *>(get(rows * 8));  // fallback rows, then block-merge rows
     w.fb_cnt = static_cast<int32_t *>(get(16));
     return w.region && w.tau && w.cnt && w.list && w.lcnt && w.fb_list && w.fb_cnt;
 }
@@ -2323,9 +2357,15 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         const dim3 grid((unsigned)((rows + 3) / 4));
         // the smallest per-lane record count that holds the list and the Phase II records
         const int need = lcap + cap2;
-        if (need > kFinalCap) {  // one block per row
-            if (vec) hipLaunchKernelGGL(k_final_blk<true>, dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
-            else hipLaunchKernelGGL(k_final_blk<false>, dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
+        // records per lane of the wave merge: the smallest that holds the capacity, at most 12;
+        // 16 for bf16 / fp16 tiles when the capacity passes 1024 (their looser bounds emit more
+        // records per row, which would otherwise send many rows to the slower block merge)
+        const int wq = need <= 256 ? 4 : need <= 512 ? 8 : (need > 1024 && v.prec != RPF_DIST_FP32) ? 16 : 12;
+        fa.big_list = need > 64 * wq ? fb_list + rows : nullptr;  // second half of the row lists
+        fa.big_cnt = fb_cnt + 1;
+        if (need > kFinalCap && K > 64) {  // one block per row
+            if (vec) hipLaunchKernelGGL((k_final_blk<true, false>), dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
+            else hipLaunchKernelGGL((k_final_blk<false, false>), dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
         } else if (need <= 256) {
             if (vec) hipLaunchKernelGGL((k_final<true, 4>), grid, dim3(256), lds, s, fa, rows);
             else hipLaunchKernelGGL((k_final<false, 4>), grid, dim3(256), lds, s, fa, rows);
@@ -2333,8 +2373,18 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
             if (vec) hipLaunchKernelGGL((k_final<true, 8>), grid, dim3(256), lds, s, fa, rows);
             else hipLaunchKernelGGL((k_final<false, 8>), grid, dim3(256), lds, s, fa, rows);
         } else {
-            if (vec) hipLaunchKernelGGL((k_final<true, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
-            else hipLaunchKernelGGL((k_final<false, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
+            if (wq == 16) {
+                if (vec) hipLaunchKernelGGL((k_final<true, 16>), grid, dim3(256), lds, s, fa, rows);
+                else hipLaunchKernelGGL((k_final<false, 16>), grid, dim3(256), lds, s, fa, rows);
+            } else {
+                if (vec) hipLaunchKernelGGL((k_final<true, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
+                else hipLaunchKernelGGL((k_final<false, kFinalQ>), grid, dim3(256), lds, s, fa, rows);
+            }
+            if (fa.big_list) {  // the rows the wave merge handed over
+                const dim3 gb((unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, 2048)));
+                if (vec) hipLaunchKernelGGL((k_final_blk<true, true>), gb, dim3(256), lds / 4, s, fa);
+                else hipLaunchKernelGGL((k_final_blk<false, true>), gb, dim3(256), lds / 4, s, fa);
+            }
         }
         launch_check(s, "k_final");
     }
@@ -2447,7 +2497,7 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
     w.cnt = static_cast<int32_t *>(get(b_rows));
     w.list = static_cast<Ent *>(get(b_list));
     w.lcnt = static_cast<int32_t *>(get(b_rows));
-    w.fb_list = static_cast<int32_t *>(get(b_rows));
+    w.fb_list = static_cast<int32_t *>(get(2 * b_rows));  // fallback rows, then block-merge rows
     w.fb_cnt = static_cast<int32_t *>(get(16));
     if (!w.region || !w.tau || !w.cnt || !w.list || !w.lcnt || !w.fb_list || !w.fb_cnt) {
         knn_shared_destroy(p, s);
@@ -2617,7 +2667,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     cand_caps(K, v.T, B, m, lcap, cap2);
     const uint64_t cap1 = (uint64_t)slot_stride(v.max_leaf) * B;
     b += std::max(m * cap1 * 4 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
-    b += (uint64_t)m * 4 * 4 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
+    b += (uint64_t)m * 4 * 5 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
 }
 

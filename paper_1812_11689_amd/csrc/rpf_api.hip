@@ -1204,6 +1204,7 @@ rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *str
     out->reranked64 = (int64_t)v[3];
     out->first_phase_kept = (int64_t)v[5];
     out->second_phase_emitted = (int64_t)v[6];
+    out->block_merged_rows = (int64_t)v[7];
     return RPF_OK;
 }
 

@@ -56,7 +56,7 @@ class BatchEntry(ctypes.Structure):
 class KnnStats(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int64), ("fallback_rows", ctypes.c_int64), ("reranked32", ctypes.c_int64),
                 ("reranked64", ctypes.c_int64), ("first_phase_kept", ctypes.c_int64),
-                ("second_phase_emitted", ctypes.c_int64)]
+                ("second_phase_emitted", ctypes.c_int64), ("block_merged_rows", ctypes.c_int64)]
 
 
 class ProfileRecord(ctypes.Structure):

@@ -56,6 +56,9 @@ ALL = [
     # K 20 against 64 trees (the tree count that reaches 0.99 recall at scale is of this
     # order): the wave merge would hold under half the wanted capacity, so the block merge runs
     ("many_trees_block_merge", 12000, 16, 64, 50, 20, "bf16", "mixture", 0, 1),
+    # K 60 against 24 trees of ~200-point leaves: rows whose records outgrow the one-wave
+    # merge are handed to the block merge (asserted below), the others stay on the wave merge
+    ("wave_to_block_handover", 8000, 8, 24, 200, 60, "fp32", "mixture", 0, 1),
 ]
 
 
@@ -88,8 +91,10 @@ def test_all_knn_matches_oracle(case):
     print(f"    stats {st}", flush=True)
     if name == "mass_ties":
         assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
-    if name in ("big_k_block_merge", "many_trees_block_merge"):
+    if name in ("big_k_block_merge", "many_trees_block_merge", "wave_to_block_handover"):
         assert st["fallback_rows"] < n // 10, "the block merge sent most rows to the exhaustive path"
+    if name == "wave_to_block_handover":
+        assert 0 < st["block_merged_rows"] < n, "the hand-over from the wave merge was not exercised"
     f.free()
 
 
