@@ -167,7 +167,12 @@ rpf_status rpf_plan_destroy(rpf_plan *plan);
 
 /* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
  * exclude_self = 1 drops each point from its own candidate set.  1 <= K <= n - exclude_self.
- * Rows shorter than K (|N_q| < K) are padded with (-1, +inf). */
+ * Rows shorter than K (|N_q| < K) are padded with (-1, +inf).
+ * Device workspace is taken from the library's cache for the call: about n x (16 B x the
+ * per-row record capacity), where the capacity grows with K x n_trees.  Once that passes
+ * one wave's 768 records, the buffers take up to 4096 records per row while all rows fit
+ * 32 GiB (for example about 25 GB at n = 10^6, K 20, 80 trees).  A failed allocation
+ * returns RPF_ENOMEM. */
 rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self,
                        int32_t *out_idx_dev, float *out_dist_dev, void *stream);
 
