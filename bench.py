@@ -329,10 +329,10 @@ def main():
 
     # the same job as one recorded HIP graph (rpf_plan_*: build and candidate stage, tuned
     # first-phase tree count), inputs set once before the timed launches
-    def plan_leg(prec, ref_idx):
-        plan = rpf.Plan([n], [d], T, n0, K, dist_prec=prec)
+    def plan_leg(prec, ref_idx, n_trees=None, dirs=None):
+        plan = rpf.Plan([n], [d], n_trees or T, n0, K, dist_prec=prec)
         try:
-            plan.set_inputs([X], [Rd])
+            plan.set_inputs([X], [Rd if dirs is None else dirs])
             plan.launch()
             plan.check()
             plan.tune()
@@ -418,6 +418,10 @@ def main():
                 i16, t16 = time_t("bf16")
                 t16["identical_to_fp32"] = bool(torch.equal(i16, i32))
                 target["bf16"] = t16
+            if not args.no_graph:  # the same step as a tuned, recorded plan (first-phase trees picked)
+                target["recorded_plan"] = {"fp32": plan_leg("fp32", i32, Tt, Rtd)}
+                if not args.no_bf16:
+                    target["recorded_plan"]["bf16"] = plan_leg("bf16", i32, Tt, Rtd)
             print(f"# target leg: {target}", file=sys.stderr, flush=True)
             del Rtd, it
 
