@@ -2420,10 +2420,19 @@ static int max_first_trees(const ForestView &v, int K) {
     return std::max(1, std::min({v.T, (kSetCap - 64) / K, kMergeCap / slot_stride(v.max_leaf)}));
 }
 
+// Default first-phase trees of the all-points search: kFirstTrees, or twice that for bf16 /
+// fp16 tiles over 64 trees or more.  Their looser bounds emit more Phase II records per row,
+// and the tighter threshold of more first-phase trees pays for itself there (the plan tuner
+// picks 8 at 10^6 points, K 20, T 80 in bf16, and 4 in fp32 or at T 32).
+static int all_points_first_trees(const ForestView &v, int K) {
+    const int want = (v.prec != RPF_DIST_FP32 && v.T >= 64) ? 2 * kFirstTrees : kFirstTrees;
+    return std::min(want, max_first_trees(v, K));
+}
+
 static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, int B = 0) {
     CandStage cs;
     cs.rows = v.n;
-    cs.B = B > 0 ? std::min(B, max_first_trees(v, K)) : first_trees(v.T, K, v.max_leaf);
+    cs.B = B > 0 ? std::min(B, max_first_trees(v, K)) : all_points_first_trees(v, K);
     cs.jobs0 = v.jobs;
     cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
     cs.njobs0 = v.n_jobs_tree * cs.B;
