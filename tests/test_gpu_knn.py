@@ -59,6 +59,9 @@ ALL = [
     # K 60 against 24 trees of ~200-point leaves: rows whose records outgrow the one-wave
     # merge are handed to the block merge (asserted below), the others stay on the wave merge
     ("wave_to_block_handover", 8000, 8, 24, 200, 60, "fp32", "mixture", 0, 1),
+    # bf16, K 40 against 40 trees: capacity above 1024 records, so the wave merge holds 16
+    # records per lane and rows past that are handed to the block merge
+    ("bf16_wide_wave_handover", 8000, 8, 40, 200, 40, "bf16", "mixture", 0, 1),
 ]
 
 
@@ -91,9 +94,9 @@ def test_all_knn_matches_oracle(case):
     print(f"    stats {st}", flush=True)
     if name == "mass_ties":
         assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
-    if name in ("big_k_block_merge", "many_trees_block_merge", "wave_to_block_handover"):
+    if name in ("big_k_block_merge", "many_trees_block_merge", "wave_to_block_handover", "bf16_wide_wave_handover"):
         assert st["fallback_rows"] < n // 10, "the block merge sent most rows to the exhaustive path"
-    if name == "wave_to_block_handover":
+    if name in ("wave_to_block_handover", "bf16_wide_wave_handover"):
         assert 0 < st["block_merged_rows"] < n, "the hand-over from the wave merge was not exercised"
     f.free()
 
