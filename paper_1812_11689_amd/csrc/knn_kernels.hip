@@ -897,9 +897,7 @@ __device__ inline uint32_t wave_kth_upper(const uint32_t (&v)[Q], int k) {
 // matters.  tau is bounded from above on that small set; the list keeps every entry with
 // lb <= tau (duplicates included: the final merge removes them).  Every slot of the row is
 // loaded at the start (Q per lane), so a wave waits on memory once.
-constexpr int kFirstTrees = 4;   // trees whose leaves are kept whole (Phase I)
-constexpr int kMergeCap = 2048;  // Phase I entries per row handled here
-constexpr int kSetCap = 512;
+// (kFirstTrees, kMergeCap, kSetCap and the slot geometry live in merge_index.h)
 
 struct SlotIndex {  // where the index of a Phase I slot comes from: the row's leaf in the tree
     const int32_t *roff;  // [B][nrows] start of the row's leaf in the permutation
@@ -922,7 +920,6 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
-    const int64_t base_slot = a * cap;
     const int c = B * ML;  // fixed slots of the first B trees
     if (c > 64 * Q) {      // leaves above kMergeCap points: the row takes the exhaustive path
         if (lane == 0) {
@@ -935,32 +932,28 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     // the row's leaf in each of the B trees: lane t holds its start in the permutation
     const int32_t loff = lane < B ? si.roff[(int64_t)lane * nrows + a] : 0;
     // ML is a multiple of 64, so the slots of wave-wide column q all lie in tree q / (ML / 64):
-    // the tree, its leaf start and the column offset are the same for every lane
-    const int ncol = B * (ML >> 6);  // wave-wide slot columns of the row
+    // the tree, its leaf start and the column offset are the same for every lane.  The index
+    // arithmetic is that of merge_index.h, which a host-only test replays.
+    const int ncol = first_slot_cols(B, ML);  // wave-wide slot columns of the row
     uint32_t u[Q];  // ub bits of the finite slots, 0xffffffff for the others
     float l[Q];
     int32_t id[Q];  // -1 for a slot that no pair fills (lb = +inf)
-    int tb = 0, col0 = 0;  // tree of column q, and its first slot's position in the tree
+    FirstSlotCursor cur;  // tree of column q, and its first slot's position in the leaf
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        const int i = lane + 64 * q;
-        const bool in = q < ncol;  // i < c for every lane
-        const uint32_t e = in ? plub[base_slot + i] : 0x7f807f80u;  // packed bounds (pack_bounds)
-        const uint32_t ub = e & 0xffff0000u;                        // fkey of the ub kept
+        const bool in = q < ncol;  // lane + 64 q < c for every lane
+        const uint32_t e = in ? plub[first_slot_addr(a, cap, lane, q)] : 0x7f807f80u;  // packed bounds
+        const uint32_t ub = e & 0xffff0000u;                                             // fkey of the ub kept
         const float lb = __uint_as_float(e << 16);
         u[q] = ub < 0x7f800000u ? ub : 0xffffffffu;
         l[q] = lb;
-        const int32_t off = __builtin_amdgcn_readlane(loff, in ? tb : 0);
+        const int32_t off = __builtin_amdgcn_readlane(loff, in ? cur.tree : 0);
         // the permutation entry is read whatever the slot holds (clamped into the tree), so
         // that it does not wait for the slot's bounds; an empty slot drops it
-        const int32_t pos = min(off + col0 + lane, (int32_t)(si.n - 1));
-        const int32_t pv = in ? si.perm[(int64_t)tb * si.n + pos] : -1;
+        const int32_t pos = first_slot_perm_pos(off, cur.col0, lane, si.n);
+        const int32_t pv = in ? si.perm[(int64_t)cur.tree * si.n + pos] : -1;
         id[q] = lb < INFINITY ? pv : -1;
-        col0 += 64;
-        if (col0 == ML) {
-            col0 = 0;
-            tb++;
-        }
+        first_slot_next(cur, ML);
     }
     for (int i = lane; i < HT; i += 64) {
         s_hid[w][i] = -1;
@@ -1074,6 +1067,7 @@ struct FinalArgs {
     int64_t npts;       // rows of X: every candidate index lies in [0, npts)
     unsigned long long *stats;  // [kStatSlots][8]: rows, fallback, reranked32, reranked64, bad_index,
                                 //                 kept1, emitted2, block-merged (summed over slots by the host)
+    unsigned long long *fault;  // the forest's sticky count of rows that met a bad index
 };
 
 // counters are spread over slots by block so that a million rows do not meet on one address
@@ -1150,6 +1144,7 @@ __device__ __attribute__((always_inline)) inline void final_row(const FinalArgs 
     if (__ballot(bad)) {  // counted for the host to report; the row is recomputed exhaustively
         if (lane == 0) {
             stat_add(A, 4, 1ull);
+            atomicAdd(A.fault, 1ull);
             push_fallback(A, a);
         }
         return;
@@ -1453,6 +1448,7 @@ __device__ __attribute__((always_inline)) inline void final_blk_row(const FinalA
     if (__syncthreads_or(bad)) {  // counted for the host to report; the row is recomputed exhaustively
         if (tid == 0) {
             stat_add(A, 4, 1ull);
+            atomicAdd(A.fault, 1ull);
             push_fallback(A, a);
         }
         return;
@@ -1993,11 +1989,6 @@ __global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q,
 // representative set and the B ML slots of a row fit one wave's registers
 // Phase I slots per (row, tree): the largest leaf rounded up to a wave, so that the slots of a
 // row's wave-wide column q all belong to one tree
-static inline int slot_stride(int max_leaf) { return (std::max(max_leaf, 1) + 63) & ~63; }
-
-static int first_trees(int T, int K, int max_leaf) {
-    return std::max(1, std::min({kFirstTrees, T, (kSetCap - 64) / K, kMergeCap / slot_stride(max_leaf)}));
-}
 
 static BoundCoef bound_coef(int prec, int d) {
     const double u32 = ldexp(1.0, -24);
@@ -2324,10 +2315,12 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
             hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, slot_stride(v.max_leaf), plub, si, cap1, tau, list,
                                lcnt, lcap, cnt);
         };
-        if (cap1 <= 256) big ? go(k_merge_first<4, 1024>) : go(k_merge_first<4, 512>);
-        else if (cap1 <= 512) big ? go(k_merge_first<8, 1024>) : go(k_merge_first<8, 512>);
-        else if (cap1 <= 1024) big ? go(k_merge_first<16, 1024>) : go(k_merge_first<16, 512>);
-        else big ? go(k_merge_first<kMergeCap / 64, 1024>) : go(k_merge_first<kMergeCap / 64, 512>);
+        switch (merge_first_q(cap1)) {
+            case 4: big ? go(k_merge_first<4, 1024>) : go(k_merge_first<4, 512>); break;
+            case 8: big ? go(k_merge_first<8, 1024>) : go(k_merge_first<8, 512>); break;
+            case 16: big ? go(k_merge_first<16, 1024>) : go(k_merge_first<16, 512>); break;
+            default: big ? go(k_merge_first<kMergeCap / 64, 1024>) : go(k_merge_first<kMergeCap / 64, 512>); break;
+        }
         launch_check(s, "k_merge_first");
     }
     if (cs.njobs1 > 0 || cs.nsjobs1 > 0) {
@@ -2350,6 +2343,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     fa.X = v.X; fa.Qr = cs.Qr; fa.d = v.d; fa.win = rerank_window(v.d); fa.out_idx = out_idx;
     fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.npts = v.n;
     fa.stats = v.stats;
+    fa.fault = v.fault;
     const bool vec = (v.d % 4) == 0;
     {
         ProfScope ps(s, "final_rerank", 0, 0);
@@ -2416,9 +2410,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
 }
 
 // largest first-phase tree count the merge supports for this forest and K
-static int max_first_trees(const ForestView &v, int K) {
-    return std::max(1, std::min({v.T, (kSetCap - 64) / K, kMergeCap / slot_stride(v.max_leaf)}));
-}
+static int max_first_trees(const ForestView &v, int K) { return max_first_trees_for(v.T, K, v.max_leaf); }
 
 // Default first-phase trees of the all-points search: kFirstTrees, or twice that for bf16 /
 // fp16 tiles over 64 trees or more.  Their looser bounds emit more Phase II records per row,

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/rpf.h"
+#include "merge_index.h"
 
 namespace rpf {
 
@@ -143,8 +144,18 @@ struct ForestView {
     int64_t n_jobs_tree;
     double tile_flops_tree;  // useful Gram flops of one tree's all-points tiles
     unsigned long long *stats;
+    unsigned long long *fault;  // sticky count of rows that met an out-of-range candidate index
 };
 ForestView view(const rpf_forest *f);
+// internal-fault counter of a forest: the host mirror (no synchronisation; it lags the device
+// by the work still queued), its refresh (an asynchronous copy enqueued on s), and a read of
+// the device counter itself (synchronises s)
+uint64_t forest_fault_seen(const rpf_forest *f);
+void forest_fault_mirror(const rpf_forest *f, hipStream_t s);
+uint64_t forest_fault_read(const rpf_forest *f, hipStream_t s);
+rpf_status fault_error(const rpf_forest *f, const char *who);
+rpf_status search_tail(const rpf_forest *f, hipStream_t s, const char *who);
+bool sync_check_on();  // RPF_SYNC_CHECK=1: every launch is followed by a synchronisation
 
 // entry points of the search (knn_kernels.hip), shared by the C ABI and the server
 rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s);
