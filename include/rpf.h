@@ -165,7 +165,17 @@ rpf_status rpf_plan_check(rpf_plan *plan, void *stream);
 rpf_status rpf_plan_tune(rpf_plan *plan, void *stream, double *tuned_ms_host);
 rpf_status rpf_plan_destroy(rpf_plan *plan);
 
-/* All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
+/* Internal faults of the search.  The final merge checks every candidate index it takes
+ * from its pruning buffers against [0, n); a row that meets one outside is recomputed by
+ * the exhaustive scan (its output stays correct) and counted on the forest, for good (the
+ * count is never cleared).  Once the count is nonzero, rpf_all_knn, rpf_query and
+ * rpf_server_submit on that forest return RPF_EINTERNAL, and so do the serving batches,
+ * rpf_last_knn_stats, rpf_forest_info and rpf_plan_check.  Since searches are asynchronous,
+ * the count reaches the host by a copy enqueued behind each search: a fault is reported by
+ * the first of those calls made after that copy has run (with RPF_SYNC_CHECK=1 in the
+ * environment every launch is synchronised and the faulting call reports it itself).
+ *
+ * All-points kNN (Alg. 3 with Q = U): out_idx_dev int32 [n][K], out_dist_dev float [n][K].
  * exclude_self = 1 drops each point from its own candidate set.  1 <= K <= n - exclude_self.
  * Rows shorter than K (|N_q| < K) are padded with (-1, +inf).
  * Device workspace is taken from the library's cache for the call: about n x (16 B x the
@@ -278,6 +288,9 @@ typedef struct {
     double mean_batch_rows;
     double p50_s, p99_s, max_s;         /* request latency percentiles (seconds)      */
     double rows_per_s;                  /* rows completed / (last completion - first submit) */
+    int64_t failed_requests;            /* requests that ended with an error status   */
+    int64_t bad_index_rows;             /* the forest's internal-fault count (see
+                                           rpf_all_knn); 0 unless the library is wrong   */
 } rpf_server_report;
 
 rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, rpf_server **out);
@@ -291,6 +304,19 @@ rpf_status rpf_server_poll(rpf_server *srv, uint64_t ticket, int32_t *done_host,
 /* Blocks until the request is done; returns its status and releases the ticket. */
 rpf_status rpf_server_wait(rpf_server *srv, uint64_t ticket, double *latency_s_host);
 rpf_status rpf_server_stats(rpf_server *srv, rpf_server_report *out_host);
+/* Device-side span of each batch since creation or the last reset (at most the first 65536):
+ * HIP events recorded on the slot's stream before the batch's first launch and after its
+ * last, in milliseconds after an event completed when the server was created.  Spans of
+ * batches on different slots that intersect show their work in flight on the device at the
+ * same time.  Copies up to `cap` records; *count_host = records held.  A span the events
+ * could not time holds -1. */
+typedef struct {
+    int32_t slot, requests;
+    int64_t rows;
+    double start_ms, end_ms;
+} rpf_server_batch;
+
+rpf_status rpf_server_batch_log(rpf_server *srv, rpf_server_batch *out_host, int32_t cap, int32_t *count_host);
 rpf_status rpf_server_reset_stats(rpf_server *srv);
 /* Serves every waiting request, stops the workers and frees the server (NULL: no-op).
  * Requests not collected are released with it. */

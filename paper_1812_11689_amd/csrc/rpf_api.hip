@@ -64,11 +64,16 @@ rpf_status check_hip(hipError_t e, const char *what) {
 
 static thread_local std::string g_launch_err;
 
-void launch_check(hipStream_t s, const char *name) {
+bool sync_check_on() {
     static const bool sync = [] {
         const char *e = getenv("RPF_SYNC_CHECK");
         return e && e[0] == '1';
     }();
+    return sync;
+}
+
+void launch_check(hipStream_t s, const char *name) {
+    const bool sync = sync_check_on();
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && sync && !capturing(s)) e = hipStreamSynchronize(s);
     if (e != hipSuccess && g_launch_err.empty()) g_launch_err = std::string(name) + ": " + hipGetErrorString(e);
@@ -281,6 +286,11 @@ struct rpf_forest {
     int64_t *d_batch_off = nullptr;       // [count + 1] first point of every data set, then n
     // stats of the last kNN call
     unsigned long long *stats = nullptr;  // [kStatSlots][8]
+    // rows whose pruning buffers met an index outside [0, n) since the build (an internal
+    // error; never cleared): device counter (the word after the stats), and its host mirror
+    // in pinned memory, refreshed by an asynchronous copy at the end of every search call
+    unsigned long long *fault = nullptr;
+    int pin_slot = -1;
     mutable std::mutex mu;
     // the leaf copies (Xc) when made after the build, on a query's first use
     std::mutex xc_mu;
@@ -347,6 +357,38 @@ rpf_status rpf_profile_read(rpf_profile_record *out, int32_t cap, int32_t *count
     return RPF_OK;
 }
 
+// Host mirrors of the forests' internal-fault counters: one pinned page for the process
+// (allocated once, never freed), a word per live forest.  A forest that finds no free word
+// reports its faults at synchronising calls only.
+constexpr int kPinSlots = 4096;
+static std::mutex g_pin_mu;
+static unsigned long long *g_pin = nullptr;
+static std::vector<int> g_pin_free;
+
+static int pin_take() {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, kPinSlots * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess || !p) {
+            hipGetLastError();
+            return -1;
+        }
+        g_pin = static_cast<unsigned long long *>(p);
+        for (int i = kPinSlots - 1; i >= 0; i--) g_pin_free.push_back(i);
+    }
+    if (g_pin_free.empty()) return -1;
+    const int k = g_pin_free.back();
+    g_pin_free.pop_back();
+    __atomic_store_n(&g_pin[k], 0ull, __ATOMIC_RELAXED);
+    return k;
+}
+
+static void pin_give(int k) {
+    if (k < 0) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(k);
+}
+
 // forest arrays come from the library's caching allocator, so repeated build / free
 // cycles reuse device blocks instead of mapping fresh pages; callers synchronise first
 static void free_forest_memory(rpf_forest *f) {
@@ -354,6 +396,8 @@ static void free_forest_memory(rpf_forest *f) {
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
                     f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off};
     for (void *p : ptrs) cache_free_idle(p);
+    pin_give(f->pin_slot);
+    f->pin_slot = -1;
     for (void *p : f->tmps) cache_free_idle(p);
     f->tmps.clear();
     if (f->xc_ev) hipEventDestroy(f->xc_ev);
@@ -570,7 +614,10 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (xc_eager) RPF_ALLOC(f->Xc, (size_t)xc_bytes);
     RPF_ALLOC(f->nrm, (size_t)T * n * 8);
     RPF_ALLOC(f->err, 64);
-    RPF_ALLOC(f->stats, kStatSlots * 8 * 8);
+    RPF_ALLOC(f->stats, kStatSlots * 8 * 8 + 256);
+    f->fault = f->stats + kStatSlots * 8;
+    fill_u64(f->fault, 1, 0, s);
+    f->pin_slot = pin_take();
     RPF_ALLOC(f->heap_leaf, ((size_t)LB + 1) * sizeof(int32_t));  // leaf ids < lbase + 2^(L+1)
     RPF_ALLOC(f->d_batch_off, ((size_t)count + 1) * sizeof(int64_t));
     if (nseg_tot) RPF_ALLOC(f->d_segs, nseg_tot * sizeof(SegDesc));
@@ -1052,6 +1099,9 @@ rpf_status rpf_plan_check(rpf_plan *pl, void *stream) {
         if (flags[4 * k + 3])
             return fail(RPF_EINVAL, "rpf_plan_check: directions hold NaN or Inf (part " + std::to_string(k) + ")");
         if (flags[4 * k]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[4 * k]));
+        if (const uint64_t flt = forest_fault_read(pl->parts[k].f, (hipStream_t)stream))
+            return fail(RPF_EINTERNAL, "rpf_plan_check: " + std::to_string(flt) + " rows of part " + std::to_string(k) +
+                                           " met a candidate index outside the data set");
     }
     return RPF_OK;
 }
@@ -1104,6 +1154,28 @@ rpf_status rpf_plan_destroy(rpf_plan *pl) {
     return RPF_OK;
 }
 
+}  // extern "C"
+
+namespace rpf {
+rpf_status fault_error(const rpf_forest *f, const char *who) {
+    return fail(RPF_EINTERNAL, std::string(who) + ": " + std::to_string(forest_fault_seen(f)) +
+                                   " rows of an earlier search on this forest met a candidate index outside the "
+                                   "data set (recomputed exhaustively; an internal error)");
+}
+
+// end of a search call: the fault counter's host mirror is refreshed behind the call's work;
+// when every launch is synchronised (RPF_SYNC_CHECK=1) the call itself reports a fault
+rpf_status search_tail(const rpf_forest *f, hipStream_t s, const char *who) {
+    forest_fault_mirror(f, s);
+    if (!sync_check_on()) return RPF_OK;
+    const rpf_status st = check_hip(hipStreamSynchronize(s), who);
+    if (st != RPF_OK) return st;
+    return forest_fault_seen(f) ? fault_error(f, who) : RPF_OK;
+}
+}  // namespace rpf
+
+extern "C" {
+
 rpf_status rpf_batch_info(const rpf_forest *f, int32_t i, rpf_batch_entry *out) {
     if (!f || !out) return fail(RPF_EINVAL, "rpf_batch_info: NULL pointer");
     if (i < 0 || i >= (int32_t)f->batch.size()) return fail(RPF_EINVAL, "rpf_batch_info: data set out of range");
@@ -1118,11 +1190,16 @@ rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self, int
     if (exclude_self != 0 && exclude_self != 1) return fail(RPF_EINVAL, "rpf_all_knn: exclude_self must be 0 or 1");
     if (K < 1 || K > f->n - exclude_self) return fail(RPF_EINVAL, "rpf_all_knn: K must be in [1, n - exclude_self]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_all_knn: K above 256 is not supported");
-    const rpf_status st = knn_all(f, K, exclude_self, out_idx, out_dist, (hipStream_t)stream);
-    if (st != RPF_OK || f->batch.size() < 2) return st;
-    launch_localize(out_idx, f->n, K, f->d_batch_off, (int)f->batch.size(), (hipStream_t)stream);
-    const std::string le = take_launch_error();
-    return le.empty() ? RPF_OK : fail(RPF_EDEVICE, "rpf_all_knn: " + le);
+    if (forest_fault_seen(f)) return fault_error(f, "rpf_all_knn");
+    hipStream_t s = (hipStream_t)stream;
+    rpf_status st = knn_all(f, K, exclude_self, out_idx, out_dist, s);
+    if (st != RPF_OK) return st;
+    if (f->batch.size() >= 2) {
+        launch_localize(out_idx, f->n, K, f->d_batch_off, (int)f->batch.size(), s);
+        const std::string le = take_launch_error();
+        if (!le.empty()) return fail(RPF_EDEVICE, "rpf_all_knn: " + le);
+    }
+    return search_tail(f, s, "rpf_all_knn");
 }
 
 rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, int32_t *out_idx, float *out_dist,
@@ -1134,7 +1211,9 @@ rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, 
     if (K < 1 || K > f->n) return fail(RPF_EINVAL, "rpf_query: K must be in [1, n]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_query: K above 256 is not supported");
     if (f->batch.size() > 1) return fail(RPF_EINVAL, "rpf_query: the forest holds several data sets");
-    return knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
+    if (forest_fault_seen(f)) return fault_error(f, "rpf_query");
+    const rpf_status st = knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
+    return st != RPF_OK ? st : search_tail(f, (hipStream_t)stream, "rpf_query");
 }
 
 rpf_status rpf_query_workspace_bytes(const rpf_forest *f, int64_t m, int32_t K, uint64_t *bytes) {
@@ -1184,6 +1263,11 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
     hipDeviceSynchronize();
     hipMemcpy(&err, f->err, 4, hipMemcpyDeviceToHost);
     if (err) return fail(RPF_EINTERNAL, "rpf_forest_info: build kernels flagged error " + std::to_string(err));
+    unsigned long long flt = 0;
+    hipMemcpy(&flt, f->fault, sizeof(flt), hipMemcpyDeviceToHost);
+    if (flt)
+        return fail(RPF_EINTERNAL, "rpf_forest_info: " + std::to_string(flt) +
+                                       " rows of a search met a candidate index outside the data set");
     return RPF_OK;
 }
 
@@ -1198,6 +1282,9 @@ rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *str
     if (v[4] != 0)
         return fail(RPF_EINTERNAL, "rpf_last_knn_stats: " + std::to_string(v[4]) +
                                        " rows met a candidate index outside the data set (recomputed exhaustively)");
+    if (const uint64_t flt = forest_fault_read(f, (hipStream_t)stream))
+        return fail(RPF_EINTERNAL, "rpf_last_knn_stats: " + std::to_string(flt) +
+                                       " rows of an earlier search met a candidate index outside the data set");
     out->rows = (int64_t)v[0] + (int64_t)v[1];
     out->fallback_rows = (int64_t)v[1];
     out->reranked32 = (int64_t)v[2];
@@ -1223,6 +1310,26 @@ ForestView view(const rpf_forest *f) {
     v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
     v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;
     v.n_jobs_tree = f->n_jobs_tree; v.tile_flops_tree = f->tile_flops_tree; v.stats = f->stats;
+    v.fault = f->fault;
+    return v;
+}
+
+uint64_t forest_fault_seen(const rpf_forest *f) {
+    return f->pin_slot < 0 ? 0 : __atomic_load_n(&g_pin[f->pin_slot], __ATOMIC_RELAXED);
+}
+
+void forest_fault_mirror(const rpf_forest *f, hipStream_t s) {
+    if (f->pin_slot >= 0)
+        hipMemcpyAsync(&g_pin[f->pin_slot], f->fault, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+}
+
+// the device counter read after a synchronisation of s (a failed read counts as no fault:
+// the failure itself surfaces as a device error)
+uint64_t forest_fault_read(const rpf_forest *f, hipStream_t s) {
+    unsigned long long v = 0;
+    if (hipMemcpyAsync(&v, f->fault, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return 0;
     return v;
 }
 }  // namespace rpf

@@ -68,7 +68,11 @@ struct rpf_server {
     bool stop = false;
     // statistics since creation or the last reset
     std::vector<double> lat;
-    int64_t rows_done = 0, requests_done = 0, batches = 0, batch_rows = 0;
+    int64_t rows_done = 0, requests_done = 0, batches = 0, batch_rows = 0, failed = 0;
+    // device-side span of every batch (HIP events on the slot's stream, in ms after `ref`,
+    // an event completed at creation), the last kLogCap batches
+    hipEvent_t ref = nullptr;
+    std::vector<rpf_server_batch> log;
     rpf::Clock::time_point t_first, t_last;
     bool have_first = false;
 };
@@ -76,9 +80,13 @@ struct rpf_server {
 namespace rpf {
 namespace {
 
-void finish(rpf_server *sv, std::vector<Request *> &batch, rpf_status st, const std::string &err, uint64_t bytes) {
+constexpr size_t kLogCap = 1 << 16;
+
+void finish(rpf_server *sv, std::vector<Request *> &batch, rpf_status st, const std::string &err, uint64_t bytes,
+            const rpf_server_batch &span) {
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->log.size() < kLogCap) sv->log.push_back(span);
     sv->inflight_bytes -= bytes;
     sv->running_batches--;
     int64_t rows = 0;
@@ -92,6 +100,8 @@ void finish(rpf_server *sv, std::vector<Request *> &batch, rpf_status st, const 
             sv->lat.push_back(std::chrono::duration<double>(now - r->t_submit).count());
             sv->rows_done += r->m;
             sv->requests_done++;
+        } else {
+            sv->failed++;
         }
     }
     sv->batches++;
@@ -105,6 +115,16 @@ void slot_main(rpf_server *sv, int slot) {
     hipSetDevice(sv->device);
     hipStream_t s = sv->streams[slot];
     const int d = forest_dim(sv->f);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // batch start / end on this slot's stream
+    hipEventCreate(&ev0);
+    hipEventCreate(&ev1);
+    struct Drop {
+        hipEvent_t a, b;
+        ~Drop() {
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+        }
+    } drop{ev0, ev1};
     for (;;) {
         std::vector<Request *> batch;
         uint64_t bytes = 0;
@@ -147,6 +167,7 @@ void slot_main(rpf_server *sv, int slot) {
         }
         // run the batch on this slot's stream
         for (Request *q : batch) hipStreamWaitEvent(s, q->ready, 0);
+        hipEventRecord(ev0, s);
         rpf_status st = RPF_OK;
         std::string err;
         const int K = batch[0]->K;
@@ -180,12 +201,31 @@ void slot_main(rpf_server *sv, int slot) {
             cache_free(db, s);
         }
         if (st != RPF_OK) err = rpf_last_error();
+        forest_fault_mirror(sv->f, s);
+        hipEventRecord(ev1, s);
         const rpf_status sync = check_hip(hipStreamSynchronize(s), "rpf_server batch");
+        rpf_server_batch span{};
+        span.slot = slot;
+        span.requests = (int32_t)batch.size();
+        span.rows = rows;
+        float t0 = -1.f, t1 = -1.f;
+        if (sync == RPF_OK && hipEventElapsedTime(&t0, sv->ref, ev0) == hipSuccess &&
+            hipEventElapsedTime(&t1, sv->ref, ev1) == hipSuccess) {
+            span.start_ms = t0;
+            span.end_ms = t1;
+        } else {
+            span.start_ms = span.end_ms = -1.0;
+        }
         if (st == RPF_OK && sync != RPF_OK) {
             st = sync;
             err = rpf_last_error();
         }
-        finish(sv, batch, st, err, bytes);
+        // an out-of-range candidate index met by this batch or an earlier one fails the batch
+        if (st == RPF_OK && forest_fault_seen(sv->f)) {
+            st = fault_error(sv->f, "rpf_server batch");
+            err = rpf_last_error();
+        }
+        finish(sv, batch, st, err, bytes, span);
     }
 }
 
@@ -218,9 +258,12 @@ rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, 
     }
     // the forest's query copies are made now, on the first slot's stream, not by the first batch
     rpf_status st = ensure_leaf_copies(f, sv->streams[0]);
+    if (st == RPF_OK) st = check_hip(hipEventCreate(&sv->ref), "rpf_server_create event");
+    if (st == RPF_OK) st = check_hip(hipEventRecord(sv->ref, sv->streams[0]), "rpf_server_create event");
     if (st == RPF_OK) st = check_hip(hipStreamSynchronize(sv->streams[0]), "rpf_server_create");
     if (st != RPF_OK) {
         for (hipStream_t t : sv->streams) hipStreamDestroy(t);
+        if (sv->ref) hipEventDestroy(sv->ref);
         delete sv;
         return st;
     }
@@ -237,6 +280,7 @@ rpf_status rpf_server_submit(rpf_server *sv, const float *Q, int64_t m, int32_t 
     if (!Q || !out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_server_submit: NULL array");
     if (K < 1 || K > forest_points(sv->f) || K > 256)
         return fail(RPF_EINVAL, "rpf_server_submit: K must be in [1, min(n, 256)]");
+    if (forest_fault_seen(sv->f)) return fault_error(sv->f, "rpf_server_submit");
     Request *r = new Request();
     if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(r->ready, (hipStream_t)stream) != hipSuccess) {
@@ -317,6 +361,8 @@ rpf_status rpf_server_stats(rpf_server *sv, rpf_server_report *out) {
     out->rows = sv->rows_done;
     out->batches = sv->batches;
     out->mean_batch_rows = sv->batches ? (double)sv->batch_rows / (double)sv->batches : 0.0;
+    out->failed_requests = sv->failed;
+    out->bad_index_rows = (int64_t)forest_fault_seen(sv->f);
     if (!sv->lat.empty()) {
         std::vector<double> v = sv->lat;
         std::sort(v.begin(), v.end());
@@ -335,11 +381,21 @@ rpf_status rpf_server_stats(rpf_server *sv, rpf_server_report *out) {
     return RPF_OK;
 }
 
+rpf_status rpf_server_batch_log(rpf_server *sv, rpf_server_batch *out, int32_t cap, int32_t *count) {
+    if (!sv || !count || (cap > 0 && !out)) return fail(RPF_EINVAL, "rpf_server_batch_log: NULL pointer");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const int32_t k = (int32_t)sv->log.size();
+    for (int32_t i = 0; i < std::min(k, cap); i++) out[i] = sv->log[i];
+    *count = k;
+    return RPF_OK;
+}
+
 rpf_status rpf_server_reset_stats(rpf_server *sv) {
     if (!sv) return fail(RPF_EINVAL, "rpf_server_reset_stats: NULL pointer");
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->lat.clear();
-    sv->rows_done = sv->requests_done = sv->batches = sv->batch_rows = 0;
+    sv->log.clear();
+    sv->rows_done = sv->requests_done = sv->batches = sv->batch_rows = sv->failed = 0;
     sv->have_first = false;
     return RPF_OK;
 }
@@ -353,6 +409,7 @@ rpf_status rpf_server_destroy(rpf_server *sv) {
     sv->cv_work.notify_all();
     for (auto &t : sv->threads) t.join();  // the slots drain every waiting request first
     for (hipStream_t s : sv->streams) hipStreamDestroy(s);
+    if (sv->ref) hipEventDestroy(sv->ref);
     for (auto &kv : sv->live) {
         hipEventDestroy(kv.second->ready);
         delete kv.second;

@@ -24,7 +24,7 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
+           "rpf_server_batch_log", "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
            "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
            "rpf_plan_destroy", "rpf_last_error"]
 
@@ -72,7 +72,13 @@ class ServerConfig(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("rows", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("mean_batch_rows", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
-                ("max_s", ctypes.c_double), ("rows_per_s", ctypes.c_double)]
+                ("max_s", ctypes.c_double), ("rows_per_s", ctypes.c_double),
+                ("failed_requests", ctypes.c_int64), ("bad_index_rows", ctypes.c_int64)]
+
+
+class ServerBatch(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_int32), ("requests", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
 
 
 class PlanEntry(ctypes.Structure):
@@ -140,6 +146,8 @@ def load(path: str = LIB_PATH):
     lib.rpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.rpf_server_reset_stats.restype = i32
     lib.rpf_server_reset_stats.argtypes = [vp]
+    lib.rpf_server_batch_log.restype = i32
+    lib.rpf_server_batch_log.argtypes = [vp, ctypes.POINTER(ServerBatch), i32, ctypes.POINTER(i32)]
     lib.rpf_server_destroy.restype = i32
     lib.rpf_server_destroy.argtypes = [vp]
     lib.rpf_build_batched.restype = i32
@@ -515,6 +523,14 @@ class Server:
         s = ServerStats()
         _check(load().rpf_server_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def batch_log(self) -> list:
+        """Device-side spans of the batches: dicts of slot, requests, rows, start_ms, end_ms."""
+        cnt = ctypes.c_int32(0)
+        _check(load().rpf_server_batch_log(self._h, None, 0, ctypes.byref(cnt)))
+        buf = (ServerBatch * max(cnt.value, 1))()
+        _check(load().rpf_server_batch_log(self._h, buf, cnt.value, ctypes.byref(cnt)))
+        return [{k: getattr(buf[i], k) for k, _ in ServerBatch._fields_} for i in range(cnt.value)]
 
     def reset_stats(self):
         _check(load().rpf_server_reset_stats(self._h))

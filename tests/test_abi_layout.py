@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PAIRS = [(rpf.Params, "rpf_params"), (rpf.Info, "rpf_info"), (rpf.BatchEntry, "rpf_batch_entry"),
          (rpf.KnnStats, "rpf_knn_stats"), (rpf.ProfileRecord, "rpf_profile_record"),
          (rpf.ServerConfig, "rpf_server_config"), (rpf.ServerStats, "rpf_server_report"),
-         (rpf.PlanEntry, "rpf_plan_entry"), (rpf.PlanPartInfo, "rpf_plan_part_info")]
+         (rpf.PlanEntry, "rpf_plan_entry"), (rpf.PlanPartInfo, "rpf_plan_part_info"),
+         (rpf.ServerBatch, "rpf_server_batch")]
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")

@@ -32,6 +32,7 @@ def test_batched_equals_each_alone(prec, d, sizes):
     Xs = [torch.from_numpy(x).cuda() for x in xs]
     bf = rpf.build_batched(Xs, T, n0, R, dist_prec=prec)
     parts = bf.all_knn_split(K)
+    bf.knn_stats()  # raises on an out-of-range candidate index (internal error)
     ents = bf.entries()
     dumps = [bf.tree_dump(t) for t in range(T)]
     torch.cuda.synchronize()

@@ -62,16 +62,25 @@ ALL = [
     # bf16, K 40 against 40 trees: capacity above 1024 records, so the wave merge holds 16
     # records per lane and rows past that are handed to the block merge
     ("bf16_wide_wave_handover", 8000, 8, 40, 200, 40, "bf16", "mixture", 0, 1),
+    # leaves of 243/244 points (the 1M x 128, n0 256 leaf shape): every block row of the
+    # 8 x 8 symmetric tile and all twelve Phase II waves run; 4 first-phase trees, 4 more
+    ("leaves244_fp32", 7800, 128, 8, 256, 20, "fp32", "aniso", 0, 1),
+    ("leaves244_bf16", 7800, 128, 8, 256, 20, "bf16", "aniso", 0, 1),
+    ("leaves244_fp16", 7800, 128, 8, 256, 20, "fp16", "aniso", 0, 1),
+    ("leaves244_fp32_self", 7800, 128, 8, 256, 20, "fp32", "aniso", 0, 0),
+    ("leaves244_bf16_self", 7800, 128, 8, 256, 20, "bf16", "aniso", 0, 0),
+    # leaves of exactly 256 points, the largest the symmetric tile takes
+    ("leaves256_fp32", 8192, 64, 9, 256, 12, "fp32", "mixture", 0, 1),
+    ("leaves256_fp16_self", 8192, 64, 9, 256, 12, "fp16", "mixture", 0, 0),
 ]
 
 
-# K above the distinct candidates of the first-phase leaves: every row's threshold is +inf.
-# It faulted the GPU twice (an out-of-range slot read in the first merge, past the index
-# array for the last row, whose float bits then reached the re-rank gather as indices); the
-# cause is fixed and the re-rank now rejects out-of-range indices, but this case stays off
-# the GPU until a later session re-runs it.  `tiny` covers the same +inf-threshold path.
-_SKIP = {"k_above_leaf": "faulted the GPU twice before its cause (out-of-range slot read in "
-                         "the first merge at tau=+inf) was found; fixed, not re-run this session"}
+# `k_above_leaf`: K above the distinct candidates of the first-phase leaves, so every row's
+# threshold is +inf.  It once faulted the GPU: lanes past the row's slot columns read the
+# next row's slots (past the slot array for the last row).  Slot columns past the row are
+# now masked; tests/test_merge_index.py replays the merge's index arithmetic on the host for
+# this shape and shows every read in range (and that the old arithmetic was not).
+_SKIP = {}
 
 
 def _params(cases):
@@ -90,7 +99,7 @@ def test_all_knn_matches_oracle(case):
     gi, gd = f.all_knn(K, exclude_self=bool(excl))
     torch.cuda.synchronize()
     _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
-    st = f.knn_stats()
+    st = f.knn_stats()  # raises on an out-of-range candidate index (internal error)
     print(f"    stats {st}", flush=True)
     if name == "mass_ties":
         assert st["fallback_rows"] > 0, "the exhaustive path was not exercised"
@@ -115,6 +124,9 @@ QUERY = [
     ("q_sparse_fp16_d600", 5000, 600, 3, 40, 6, "fp16", 60),
     # K 100: the block-per-row final merge
     ("q_big_k_fp16", 20000, 24, 10, 256, 100, "fp16", 500),
+    # leaves of 243/244 points, as in the 4M x 96 served forest
+    ("q_leaves244_fp16", 7800, 96, 8, 256, 10, "fp16", 3000),
+    ("q_leaves244_bf16", 7800, 96, 8, 256, 100, "bf16", 800),
 ]
 
 
@@ -131,6 +143,8 @@ def test_query_matches_oracle(case):
     gi, gd = f.query(torch.from_numpy(q).cuda(), K)
     torch.cuda.synchronize()
     _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
+    st = f.knn_stats()  # raises on an out-of-range candidate index (internal error)
+    print(f"    stats {st}", flush=True)
     f.free()
 
 

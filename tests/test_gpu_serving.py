@@ -39,6 +39,7 @@ def test_mix_equals_alone(prec, slots):
     res = [srv.wait(t) for t in tickets]
     st = srv.stats()
     print(f"    stats {st}", flush=True)
+    assert st["failed_requests"] == 0 and st["bad_index_rows"] == 0
     assert st["requests"] == len(qs)
     assert st["rows"] == sum(q.shape[0] for q in qs)
     assert st["batches"] < len(qs), "no request was batched with another"
@@ -78,7 +79,11 @@ def test_memory_budget_serialises_batches_and_poll():
         ai, ad = f.query(q, k)
         torch.cuda.synchronize()
         assert torch.equal(out[t][0], ai) and torch.equal(out[t][1], ad)
-    assert srv.stats()["requests"] == len(qs)
+    st = srv.stats()
+    assert st["requests"] == len(qs) and st["failed_requests"] == 0 and st["bad_index_rows"] == 0
+    # one batch at a time: no two device spans intersect
+    spans = sorted((b["start_ms"], b["end_ms"]) for b in srv.batch_log())
+    assert len(spans) == st["batches"] and all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
     srv.close()
     f.free()
 
