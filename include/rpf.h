@@ -191,6 +191,26 @@ rpf_status rpf_all_knn(const rpf_forest *f, int32_t K, int32_t exclude_self,
 rpf_status rpf_query(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t K,
                      int32_t *out_idx_dev, float *out_dist_dev, void *stream);
 
+/* rpf_query for callers that cannot allocate device memory: code in a serving loop that
+ * must not call hipMalloc / hipFree, or a harness that forbids them.  Same arguments,
+ * results and errors as rpf_query; the call allocates nothing.  Its workspace is carved
+ * from a fixed scratch area of 256 MiB that the library holds on each device it runs on
+ * until the process ends.
+ *   - RPF_EINVAL when m queries at this K need more workspace than the scratch area
+ *     (rpf_query_workspace_bytes gives the need; about 1 000 to 2 000 queries of K 100 over
+ *     64 trees of 256-point leaves fit, many more at small K): split the batch.
+ *   - RPF_ENOTREADY when the forest's leaf-ordered query copies do not exist yet: they are
+ *     made (allocated) by the forest's first rpf_query call or by rpf_server_create, or at
+ *     build time when leaves exceed 256 points.
+ *   - Every call on a device shares that device's scratch area and leaves its contents
+ *     behind: calls whose work overlaps on one device (other threads, other streams with
+ *     no ordering between them) race and corrupt each other's results.  Order them, e.g. on
+ *     one stream, or synchronise between them.  Like rpf_query, the call synchronises
+ *     `stream` twice (input check, tile counts); its last kernels are still queued when it
+ *     returns. */
+rpf_status rpf_query_noalloc(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t K,
+                             int32_t *out_idx_dev, float *out_dist_dev, void *stream);
+
 /* Route queries only (Alg. 3 descent): out_leaf_dev int32 [T][m] = heap id of the leaf
  * each query reaches in each tree (right child iff projection >= split value). */
 rpf_status rpf_route(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t *out_leaf_dev,

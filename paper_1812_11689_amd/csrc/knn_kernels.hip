@@ -21,6 +21,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -2397,16 +2399,22 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     }
 }
 
-static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
-                                 float *out_dist, hipStream_t s) {
-    Workspace ws(s);
+// the candidate stage with its buffers from `get` (device bytes, nullptr = failure)
+template <typename Get>
+static rpf_status run_cand_stage_get(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
+                                     float *out_dist, hipStream_t s, Get get) {
     CandWs w;
-    if (!cand_ws_alloc(v, cs, K, [&](size_t b) { return ws.get<void>(b); }, w) || !ws.ok)
-        return fail(RPF_ENOMEM, "kNN workspace allocation failed");
+    if (!cand_ws_alloc(v, cs, K, get, w)) return fail(RPF_ENOMEM, "kNN workspace allocation failed");
     cand_launches(v, cs, K, w, out_idx, out_dist, s);
     const std::string le = take_launch_error();
     if (!le.empty()) return fail(RPF_EDEVICE, "kNN: " + le);
     return RPF_OK;
+}
+
+static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K, int32_t *out_idx,
+                                 float *out_dist, hipStream_t s) {
+    Workspace ws(s);
+    return run_cand_stage_get(v, cs, K, out_idx, out_dist, s, [&](size_t b) { return ws.get<void>(b); });
 }
 
 // largest first-phase tree count the merge supports for this forest and K
@@ -2545,52 +2553,58 @@ rpf_status route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_le
     return RPF_OK;
 }
 
-rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
-                     hipStream_t s) {
+// The query search with every device buffer taken from `get` (device bytes, nullptr =
+// failure): the library's cache (knn_query) or a fixed scratch area (rpf_query_noalloc).
+// may_copy: the forest's leaf copies may be made (allocated) here on its first query.
+template <typename Get>
+static rpf_status knn_query_get(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx,
+                                float *out_dist, hipStream_t s, Get get, bool may_copy) {
     {
-        const rpf_status st = ensure_leaf_copies(f, s);  // query tiles read the leaf-ordered copy
+        const rpf_status st = ensure_leaf_copies(f, s, may_copy);  // query tiles read the leaf-ordered copy
         if (st != RPF_OK) return st;
     }
     const ForestView v = view(f);
-    int dev = 0;
-    hipGetDevice(&dev);
     {   // queries must be finite (one synchronisation)
-        int32_t *flag = static_cast<int32_t *>(cache_alloc(16, s));
+        int32_t *flag = static_cast<int32_t *>(get(16));
         if (!flag) return fail(RPF_ENOMEM, "rpf_query: allocation");
         fill_u32(flag, 4, 0, s);
         launch_nonfinite(s, Q, m * v.d, flag);
         int32_t h = 0;
         hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
-        cache_free(flag, s);
         rpf_status st = check_hip(hipStreamSynchronize(s), "rpf_query input check");
         if (st != RPF_OK) return st;
         if (h) return fail(RPF_EINVAL, "rpf_query: Q holds NaN or Inf");
     }
-    Workspace ws(s);
+    bool ok = true;
+    auto take = [&](size_t bytes) {
+        void *p = get(bytes ? bytes : 16);
+        ok = ok && p;
+        return p;
+    };
     const int T = v.T;
     const int64_t nleaf = v.nleaf;
     const int TR = 32 * v.job_mb;
     const size_t esz = v.prec == RPF_DIST_FP32 ? 4 : 2;
-    int32_t *qleaf = ws.get<int32_t>((size_t)T * m * 4);
-    int32_t *gcount = ws.get<int32_t>((size_t)T * nleaf * 4);
-    int32_t *goff = ws.get<int32_t>((size_t)T * nleaf * 4);
-    int32_t *gfill = ws.get<int32_t>((size_t)T * nleaf * 4);
-    int32_t *qorder = ws.get<int32_t>((size_t)T * m * 4);
-    int32_t *qgleaf = ws.get<int32_t>((size_t)T * m * 4);
-    void *Qc = ws.get<void>((size_t)T * m * v.dp * esz);
-    float2 *qnrm = ws.get<float2>((size_t)T * m * 8);
+    int32_t *qleaf = static_cast<int32_t *>(take((size_t)T * m * 4));
+    int32_t *gcount = static_cast<int32_t *>(take((size_t)T * nleaf * 4));
+    int32_t *goff = static_cast<int32_t *>(take((size_t)T * nleaf * 4));
+    int32_t *gfill = static_cast<int32_t *>(take((size_t)T * nleaf * 4));
+    int32_t *qorder = static_cast<int32_t *>(take((size_t)T * m * 4));
+    int32_t *qgleaf = static_cast<int32_t *>(take((size_t)T * m * 4));
+    void *Qc = take((size_t)T * m * v.dp * esz);
+    float2 *qnrm = static_cast<float2 *>(take((size_t)T * m * 8));
     const int nbt = (v.max_leaf + TR - 1) / TR;
     const int nfirst = first_trees(T, K, v.max_leaf);
     const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
     const int64_t jcap0 = jcap_tree * nfirst;
     const int64_t jcap1 = jcap_tree * (T > nfirst ? T - nfirst : 1);
-    TileJob *jobs0 = ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob));
-    TileJob *jobs1 = ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob));
+    TileJob *jobs0 = static_cast<TileJob *>(take((size_t)jcap0 * sizeof(TileJob)));
+    TileJob *jobs1 = static_cast<TileJob *>(take((size_t)jcap1 * sizeof(TileJob)));
     const int qs = qtile_qs(v.prec, v.dp);
-    TileJob *sjobs0 = qs ? ws.get<TileJob>((size_t)jcap0 * sizeof(TileJob)) : nullptr;
-    TileJob *sjobs1 = qs ? ws.get<TileJob>((size_t)jcap1 * sizeof(TileJob)) : nullptr;
-    int32_t *njobs = ws.get<int32_t>(16);
-    if (!ws.ok) return fail(RPF_ENOMEM, "rpf_query: workspace allocation failed");
+    TileJob *sjobs0 = qs ? static_cast<TileJob *>(take((size_t)jcap0 * sizeof(TileJob))) : nullptr;
+    TileJob *sjobs1 = qs ? static_cast<TileJob *>(take((size_t)jcap1 * sizeof(TileJob))) : nullptr;
+    int32_t *njobs = static_cast<int32_t *>(take(16));
+    if (!ok) return fail(RPF_ENOMEM, "rpf_query: workspace allocation failed");
     rpf_status st = route(f, Q, m, qleaf, s);
     if (st != RPF_OK) return st;
     fill_u32(gcount, (int64_t)T * nleaf, 0, s);
@@ -2647,7 +2661,13 @@ rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int3
     cs.excl = 0;
     cs.flops0 = cs.flops1 = cs.bytes0 = cs.bytes1 = 0;
     cs.sym = false;
-    return run_cand_stage(v, cs, K, out_idx, out_dist, s);
+    return run_cand_stage_get(v, cs, K, out_idx, out_dist, s, get);
+}
+
+rpf_status knn_query(const rpf_forest *f, const float *Q, int64_t m, int K, int32_t *out_idx, float *out_dist,
+                     hipStream_t s) {
+    Workspace ws(s);
+    return knn_query_get(f, Q, m, K, out_idx, out_dist, s, [&](size_t b) { return ws.get<void>(b); }, true);
 }
 
 // device bytes one knn_query call of m queries takes from the allocator (its workspace)
@@ -2673,3 +2693,77 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
 }
 
 }  // namespace rpf
+
+// ---------------------------------------------------------------- allocation-free queries
+
+// A fixed scratch area per device for callers that cannot allocate device memory: the
+// workspace of rpf_query_noalloc is carved from it.  The name `scratch` is a host-side
+// stand-in for the device array; host code uses only the device address obtained for it
+// with hipGetSymbolAddress, per device, on the first call made on that device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace rpf {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// the device address of this device's scratch array (nullptr on failure, with the error)
+void *scratch_of(int dev, hipError_t &err) {
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[dev] = e;
+        g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    });
+    err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+
+// bump allocation from the scratch area, 256-byte aligned
+struct Arena {
+    uint8_t *base;
+    size_t cap, used = 0;
+    void *get(size_t bytes) {
+        const size_t at = (used + 255) & ~(size_t)255;
+        if (at + bytes > cap) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+};
+
+}  // namespace
+}  // namespace rpf
+
+extern "C" rpf_status rpf_query_noalloc(const rpf_forest *f, const float *Q, int64_t m, int32_t K, int32_t *out_idx,
+                                        float *out_dist, void *stream) {
+    using namespace rpf;
+    if (!f) return fail(RPF_EINVAL, "rpf_query_noalloc: forest is NULL");
+    if (m < 0) return fail(RPF_EINVAL, "rpf_query_noalloc: m must be >= 0");
+    if (m == 0) return RPF_OK;
+    if (!Q || !out_idx || !out_dist) return fail(RPF_EINVAL, "rpf_query_noalloc: NULL pointer");
+    if (K < 1 || K > forest_points(f)) return fail(RPF_EINVAL, "rpf_query_noalloc: K must be in [1, n]");
+    if (K > 256) return fail(RPF_EINVAL, "rpf_query_noalloc: K above 256 is not supported");
+    if (forest_batch_count(f) > 1) return fail(RPF_EINVAL, "rpf_query_noalloc: the forest holds several data sets");
+    if (forest_fault_seen(f)) return fault_error(f, "rpf_query_noalloc");
+    const uint64_t need = query_workspace_bytes(f, m, K);  // an upper bound of the carve below
+    if (need > kScratchBytes)
+        return fail(RPF_EINVAL, "rpf_query_noalloc: m = " + std::to_string(m) + " queries at K = " + std::to_string(K) +
+                                    " need " + std::to_string(need) + " bytes of workspace, above the " +
+                                    std::to_string(kScratchBytes) + "-byte scratch area: use fewer queries per call");
+    int dev = 0;
+    rpf_status st = check_hip(hipGetDevice(&dev), "rpf_query_noalloc");
+    if (st != RPF_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) return fail(RPF_EINVAL, "rpf_query_noalloc: device index out of range");
+    hipError_t err = hipSuccess;
+    void *base = scratch_of(dev, err);
+    if (!base) return check_hip(err == hipSuccess ? hipErrorInvalidSymbol : err, "rpf_query_noalloc: scratch address");
+    Arena ar{static_cast<uint8_t *>(base), kScratchBytes};
+    hipStream_t s = (hipStream_t)stream;
+    st = knn_query_get(f, Q, m, K, out_idx, out_dist, s, [&](size_t b) { return ar.get(b); }, false);
+    if (st == RPF_ENOMEM) return fail(RPF_EINTERNAL, "rpf_query_noalloc: the scratch carve exceeded its bound");
+    return st != RPF_OK ? st : search_tail(f, s, "rpf_query_noalloc");
+}

@@ -798,10 +798,13 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
 
 // The leaf-ordered centred copy for queries, made once, on the first call that needs it:
 // later callers on other streams wait for the event recorded after the copy kernel.
-rpf_status rpf::ensure_leaf_copies(const rpf_forest *cf, hipStream_t s) {
+rpf_status rpf::ensure_leaf_copies(const rpf_forest *cf, hipStream_t s, bool may_make) {
     rpf_forest *f = const_cast<rpf_forest *>(cf);
     std::lock_guard<std::mutex> lk(f->xc_mu);
     if (f->Xc) return f->xc_ev ? check_hip(hipStreamWaitEvent(s, f->xc_ev, 0), "leaf copies: wait") : RPF_OK;
+    if (!may_make)
+        return fail(RPF_ENOTREADY, "the forest's query copies do not exist yet: they are made (allocated) by its "
+                                   "first rpf_query call or by rpf_server_create");
     if (capturing(s))
         return fail(RPF_EINVAL, "the forest's query copies are made on its first query, which cannot be recorded: "
                                 "run one query before the capture");
@@ -1301,6 +1304,7 @@ rpf_status rpf_last_knn_stats(const rpf_forest *f, rpf_knn_stats *out, void *str
 namespace rpf {
 int64_t forest_points(const rpf_forest *f) { return f->n; }
 int32_t forest_dim(const rpf_forest *f) { return f->d; }
+int32_t forest_batch_count(const rpf_forest *f) { return (int32_t)f->batch.size(); }
 
 ForestView view(const rpf_forest *f) {
     ForestView v;

@@ -175,11 +175,13 @@ void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
 void fill_u64(void *p, int64_t count, uint64_t value, hipStream_t s);
 // the leaf-ordered, centred copy in the tile precision, made on a query's first use (the
 // all-points search of leaves that fit one tile stages its rows from X instead)
-rpf_status ensure_leaf_copies(const rpf_forest *f, hipStream_t s);
+// (may_make = false: RPF_ENOTREADY instead of allocating them when they do not exist yet)
+rpf_status ensure_leaf_copies(const rpf_forest *f, hipStream_t s, bool may_make = true);
 // copies tree 0's all-points tiles (jobs[0, njt)) to trees 1 .. T - 1
 void replicate_jobs(TileJob *jobs, int64_t njt, int T, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);
 int32_t forest_dim(const rpf_forest *f);
+int32_t forest_batch_count(const rpf_forest *f);
 
 bool capturing(hipStream_t s);  // a stream capture (graph recording) is active on s
 rpf_status fail(rpf_status st, const std::string &msg);

@@ -24,7 +24,7 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_batch_log", "rpf_server_destroy", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
+           "rpf_server_batch_log", "rpf_server_destroy", "rpf_query_noalloc", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
            "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
            "rpf_plan_destroy", "rpf_last_error"]
 
@@ -146,6 +146,8 @@ def load(path: str = LIB_PATH):
     lib.rpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.rpf_server_reset_stats.restype = i32
     lib.rpf_server_reset_stats.argtypes = [vp]
+    lib.rpf_query_noalloc.restype = i32
+    lib.rpf_query_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     lib.rpf_server_batch_log.restype = i32
     lib.rpf_server_batch_log.argtypes = [vp, ctypes.POINTER(ServerBatch), i32, ctypes.POINTER(i32)]
     lib.rpf_server_destroy.restype = i32
@@ -230,6 +232,21 @@ class Forest:
         else:
             idx, dist = out
         _check(load().rpf_query(self.handle, Q.data_ptr(), m, K, idx.data_ptr(), dist.data_ptr(), _stream(stream)))
+        return idx, dist
+
+    def query_noalloc(self, Q: torch.Tensor, K: int, out, stream=None):
+        """rpf_query_noalloc: like query(), into the caller's outputs `out` = (idx int32 [m][K],
+        dist float32 [m][K]); the library allocates nothing."""
+        Q = _dev(Q, torch.float32)
+        idx, dist = out
+        m = Q.shape[0]
+        if tuple(idx.shape) != (m, K) or tuple(dist.shape) != (m, K):
+            raise ValueError("out must be ([m][K] int32, [m][K] float32)")
+        for t, dt in ((idx, torch.int32), (dist, torch.float32)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError("out tensors must be contiguous device tensors of int32 / float32")
+        _check(load().rpf_query_noalloc(self.handle, Q.data_ptr(), m, K, idx.data_ptr(), dist.data_ptr(),
+                                        _stream(stream)))
         return idx, dist
 
     def route(self, Q: torch.Tensor, stream=None):
