@@ -211,6 +211,19 @@ rpf_status rpf_query(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t
 rpf_status rpf_query_noalloc(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t K,
                              int32_t *out_idx_dev, float *out_dist_dev, void *stream);
 
+/* Exact kNN by brute force (the problem the forest approximates; the ground truth of the
+ * accuracy measures of Sec. 5.1): for each query row of Q_dev (binary32 [m][d]) the K points
+ * of X_dev (binary32 [n][d], finite) of smallest key (D, index), D the canonical binary64
+ * squared distance (the library's ranking), written as out_idx_dev int32 [m][K] and
+ * out_dist_dev float [m][K] = (float)sqrt(D), ascending.  self_dev (optional, int64 [m]):
+ * point index to leave out of query i's candidates (its own row in X), or -1; rows with
+ * fewer than K candidates are padded with (-1, +inf).  1 <= K <= 256, 1 <= d <= 2048,
+ * 1 <= n < 2^31.  Device workspace: one binary64 distance row per query of a chunk, at
+ * most 4 GiB.  Synchronises `stream` once (input check). */
+rpf_status rpf_exact_knn(const float *X_dev, int64_t n, int32_t d, const float *Q_dev, int64_t m,
+                         const int64_t *self_dev, int32_t K, int32_t *out_idx_dev, float *out_dist_dev,
+                         void *stream);
+
 /* Route queries only (Alg. 3 descent): out_leaf_dev int32 [T][m] = heap id of the leaf
  * each query reaches in each tree (right child iff projection >= split value). */
 rpf_status rpf_route(const rpf_forest *f, const float *Q_dev, int64_t m, int32_t *out_leaf_dev,

@@ -24,7 +24,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",
 ]
-SOURCES = ["rpf_api.hip", "build_kernels.hip", "knn_kernels.hip", "device_cache.hip", "server.hip"]
+SOURCES = ["rpf_api.hip", "build_kernels.hip", "knn_kernels.hip", "device_cache.hip", "server.hip",
+           "exact_kernels.hip"]
 
 
 def _compile(src: str) -> str:

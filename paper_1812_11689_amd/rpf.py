@@ -24,7 +24,7 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",
            "rpf_profile_read", "rpf_release_cached_memory", "rpf_query_workspace_bytes", "rpf_server_create",
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
-           "rpf_server_batch_log", "rpf_server_destroy", "rpf_query_noalloc", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
+           "rpf_server_batch_log", "rpf_server_destroy", "rpf_query_noalloc", "rpf_exact_knn", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
            "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
            "rpf_plan_destroy", "rpf_last_error"]
 
@@ -146,6 +146,8 @@ def load(path: str = LIB_PATH):
     lib.rpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.rpf_server_reset_stats.restype = i32
     lib.rpf_server_reset_stats.argtypes = [vp]
+    lib.rpf_exact_knn.restype = i32
+    lib.rpf_exact_knn.argtypes = [vp, i64, i32, vp, i64, vp, i32, vp, vp, vp]
     lib.rpf_query_noalloc.restype = i32
     lib.rpf_query_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     lib.rpf_server_batch_log.restype = i32
@@ -294,6 +296,28 @@ class Forest:
             self.free()
         except Exception:
             pass
+
+
+def exact_knn(X: torch.Tensor, Q: torch.Tensor, K: int, self_idx: torch.Tensor | None = None, stream=None):
+    """rpf_exact_knn: the exact K nearest points of X to each row of Q by (binary64 distance,
+    index); self_idx (int64 [m], optional) leaves out one point per query."""
+    X = _dev(X, torch.float32)
+    Q = _dev(Q, torch.float32)
+    n, d = X.shape
+    m = Q.shape[0]
+    if Q.shape[1] != d:
+        raise ValueError("X and Q need the same number of columns")
+    sp = None
+    if self_idx is not None:
+        self_idx = _dev(self_idx, torch.int64)
+        if self_idx.shape != (m,):
+            raise ValueError("self_idx must be int64 [m]")
+        sp = self_idx.data_ptr()
+    idx = torch.empty((m, K), dtype=torch.int32, device="cuda")
+    dist = torch.empty((m, K), dtype=torch.float32, device="cuda")
+    _check(load().rpf_exact_knn(X.data_ptr(), n, d, Q.data_ptr(), m, sp, K, idx.data_ptr(), dist.data_ptr(),
+                                _stream(stream)))
+    return idx, dist
 
 
 def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
