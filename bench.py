@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the rpForests kNN path on one MI355X.
 
-One step = the whole hot path on one batch: grow the forest (rpf_build) over the
-1M x 128 anisotropic Gaussian mixture (T = 32 trees, leaf size 256) and find the K = 20
-nearest neighbours of every point among the union of its leaves (rpf_all_knn), then
-release the forest.  Inputs are resident in device memory before the timed region.
+One step = the whole hot path on one batch: grow the forest (rpf_build) over the 1M x 128
+anisotropic Gaussian mixture (leaf size 256) and find the K = 20 nearest neighbours of every
+point among the union of its leaves (rpf_all_knn), then release the forest.  Inputs are
+resident in device memory before the timed region.
 
-Prints one JSON line: whole-job throughput in queries/s (points whose exact top-K over
-the leaf union is produced per second) with binary32 tiles, the same with bfloat16 tiles
-plus re-rank, the recall against exact brute force on a sample of points, the roofline
-of the dominant kernel (timed with HIP events on the launch stream, inside the library)
-and the CPU oracle timed on the host.
+The metric is queries/s at recall >= 0.99.  The recall (1 - the missing rate of Sec. 5.1)
+is measured against the exact kNN of a seeded sample of 10 000 points (rpf_exact_knn);
+the forest is grown tree by tree (nested forests: 32, 48, 64, 80, ... trees) until it
+reaches 0.99, and the step is timed there: bfloat16 tiles + binary32/binary64 re-rank
+(`value`) and plain binary32 tiles beside it, same steps and warm-up.  The named
+configuration (32 trees) is timed as a sub-record.  Also: the roofline of the dominant
+kernel (HIP events on the launch stream, inside the library), the precision path on 1M x 784
+quantised data, the serving loop on the 4M x 96 forest, many uneven data sets in one
+recorded launch, and the CPU oracle timed on the host.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -29,17 +33,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kNN queries/s at ≥0.99 recall, FP32 vs BF16+rerank; p50/p99 latency"
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T32.md")
-# kernel behind each timed record of the library, for the fp32 run of the 1M x 128 workload
+# HBM bytes per dispatch of the headline step's kernels (two rocprofv3 counter runs of
+# `--only-step 80:bf16`), valid while the HIP sources hash to the value recorded in it
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T80_bf16.md")
+PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2}
+# kernel (name prefix in the counter summary) behind each timed record of the library for the
+# 1M x 128 workload (leaves of 244/245 points: the 8 x 8 symmetric tile)
 RECORD_KERNEL = {
-    "tile_phase2": "k_tile_sym<8, 0, 1>",
-    "tile_phase1": "k_tile_sym<8, 0, 0>",
-    "proj_chunks": "k_proj_chunks<true>",
-    "level_small": "k_level_small<true>",
-    "leaf_finalize": "k_leaf_finalize<float>",
-    "merge_first": "k_merge_first<16>",
-    "final_rerank": "k_final<true, 12>",
+    "tile_phase2": "k_tile_sym<8, {p}, 1>",
+    "tile_phase1": "k_tile_sym<8, {p}, 0>",
+    "proj_chunks_x3": "k_proj_chunks<true, true>",
+    "level_small": "k_level_small<true, true>",
+    "leaf_finalize": "k_leaf_stats<",
+    "merge_first": "k_merge_first<",
+    "final_rerank": "k_final<true",
 }
+BUILD_KERNELS = ("k_proj_root", "k_proj_chunks", "k_level_small", "k_sel_", "k_part_")
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
@@ -51,9 +60,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=None, help="fewer points (same recipe), for quick checks")
-    ap.add_argument("--recall-sample", type=int, default=2000)
+    ap.add_argument("--recall-sample", type=int, default=10000, help="points whose exact kNN is the recall truth")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the recorded-plan (HIP graph) leg")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
@@ -63,9 +71,18 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 1M x 784 precision-path leg")
+    ap.add_argument("--precision-n", type=int, default=None, help="points of the precision-path leg (default 1M)")
+    ap.add_argument("--only-step", default=None, metavar="T:PREC",
+                    help="run only the 1M x 128 step with T trees and PREC tiles (--steps, --warmup), for profiling")
+    ap.add_argument("--only-precision", action="store_true", help="run the precision-path leg alone (profiling)")
     ap.add_argument("--only-serve", action="store_true", help="run the serving leg alone (profiling)")
     ap.add_argument("--serve-n", type=int, default=None, help="points of the served forest (default: 4M)")
-    ap.add_argument("--serve-requests", type=int, default=4000, help="requests per serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="requests per serving measurement")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95],
+                    help="open-loop loads as fractions of the saturated request rate")
+    ap.add_argument("--serve-recall-rows", type=int, default=700, help="sampled request rows per K for recall")
+    ap.add_argument("--serve-curve", default="16,32,64,96,128", help="tree counts of the served recall curve")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-data-sets leg")
     ap.add_argument("--only-batched", action="store_true", help="run the many-data-sets leg alone (profiling)")
     ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
@@ -78,29 +95,6 @@ def parse():
     ap.add_argument("--cpu-trees", type=int, default=0,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
-
-
-def exact_knn_sample(X, pts, K):
-    """Exact K nearest neighbours (excluding self) of the sampled points, by binary64
-    distances on the device -- the ground truth of the recall measurement."""
-    import torch
-    Xd = X.double()
-    nrm = (Xd * Xd).sum(1)
-    out = []
-    for s in range(0, len(pts), 256):
-        p = pts[s:s + 256]
-        q = Xd[p]
-        D = nrm[p][:, None] + nrm[None, :] - 2.0 * (q @ Xd.T)
-        D[torch.arange(len(p)), p] = float("inf")
-        out.append(torch.topk(D, K, dim=1, largest=False).indices)
-    return torch.cat(out).cpu().numpy()
-
-
-def recall_of(found, truth):
-    hit = 0
-    for f, t in zip(found, truth):
-        hit += len(set(f.tolist()) & set(t.tolist()))
-    return hit / truth.size
 
 
 def roofline(prof):
@@ -129,10 +123,14 @@ KNN_RECORDS = ("tile_phase1", "merge_first", "tile_phase2", "final_rerank", "fal
 
 
 def stage_summary(prof, steps, n, d, T, L, K):
-    """Kernel time of the two halves of a step and their bounds: the build levels against the
-    algorithmic bytes of the method (n (4d + 36) bytes per tree and level: row, id, key write,
-    one select read, partition read of key and id, id write), the leaf pass apart, and the
-    search (queries/s of rpf_all_knn alone) with the MFMA fraction of its distance tiles."""
+    """Kernel time of the two halves of a step and their bounds.  The build levels: their
+    time, the method's algorithmic bytes (n (4d + 36) bytes per tree and level: row, id, key
+    write, one select read, partition read of key and id, id write) and the time those bytes
+    would take at the HBM peak -- the linked levels read X once per two levels, so they move
+    fewer bytes than that and the ratio is no fraction of a peak -- and the HBM bytes the
+    counters measured (committed summary of the same step), with the rate they give.  The
+    leaf pass apart; the search (queries/s of rpf_all_knn alone) with the MFMA fraction of
+    its distance tiles in algorithmic flops."""
     def ms(names):
         return sum(prof[k]["total_ms"] for k in names if k in prof) / steps
     lv_ms, leaf_ms, knn_ms = ms(BUILD_LEVEL_RECORDS), ms(("leaf_finalize",)), ms(KNN_RECORDS)
@@ -141,10 +139,15 @@ def stage_summary(prof, steps, n, d, T, L, K):
     t_flops = sum(r["algo_flops"] for r in tiles) / steps
     t_ms = sum(r["total_ms"] for r in tiles) / steps
     peak = FP32_MFMA_PEAK_TFLOPS if not tiles or tiles[0].get("prec") != "bf16" else BF16_MFMA_PEAK_TFLOPS
+    measured = build_traffic_per_step()
     return {
         "build_levels_ms": round(lv_ms, 3),
         "build_levels_algorithmic_bytes": lv_bytes,
-        "build_levels_effective_hbm_frac": round(lv_bytes / (lv_ms / 1e3) / (HBM_PEAK_GBS * 1e9), 3) if lv_ms else None,
+        "build_levels_ms_at_hbm_peak_for_algorithmic_bytes": round(lv_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 3),
+        "build_levels_hbm_bytes_measured": measured,
+        "build_levels_hbm_GBps_measured": round(measured / (lv_ms / 1e3) / 1e9, 1) if measured and lv_ms else None,
+        "build_levels_hbm_frac_measured": round(measured / (lv_ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4)
+        if measured and lv_ms else None,
         "leaf_pass_ms": round(leaf_ms, 3),
         "all_knn_ms": round(knn_ms, 3),
         "all_knn_queries_per_s": round(n / (knn_ms / 1e3), 1) if knn_ms else None,
@@ -229,21 +232,72 @@ def kt_summary(d):
               f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
 
 
-def traffic_for(record):
-    """HBM bytes per launch of a timed record, from the committed counter summary, or None
-    when there is none or the kernels changed since it was taken."""
-    kname = RECORD_KERNEL.get(record)
-    if not kname or not os.path.exists(TRAFFIC_FILE):
+def _traffic_table():
+    """The committed counter summary of the headline step, or None when absent or stale."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         js = [ln for ln in fh if ln.startswith("{")]
     if not js:
         return None
     t = json.loads(js[-1])
-    if t.get("source_hash") != source_hash():
+    return t if t.get("source_hash") == source_hash() else None
+
+
+def traffic_for(record, prec):
+    """HBM bytes per launch of a timed record (scaled FETCH_SIZE + WRITE_SIZE), or None."""
+    pat = RECORD_KERNEL.get(record)
+    t = _traffic_table()
+    if not pat or t is None:
         return None
-    k = t["kernels"].get(kname)
-    return None if k is None else k["bytes_per_dispatch"]
+    pat = pat.format(p=PREC_INDEX.get(prec, 0))
+    for k, v in t["kernels"].items():
+        if k == pat or (pat.endswith("<") or pat.endswith("true")) and k.startswith(pat):
+            return v["bytes_per_dispatch"]
+    return None
+
+
+def build_traffic_per_step():
+    """HBM bytes of the build-level kernels in one step, from the counter summary (whose run
+    is one step), or None."""
+    t = _traffic_table()
+    if t is None:
+        return None
+    return sum(v["bytes_per_dispatch"] * v["dispatches"] for k, v in t["kernels"].items()
+               if k.startswith(BUILD_KERNELS))
+
+
+def timed_steps(step, steps, warmup):
+    """W untimed warm-up steps, then K timed steps bracketed by synchronisations; per-kernel
+    records from the library's HIP events on the launch stream over the timed steps."""
+    import torch
+    from paper_1812_11689_amd import rpf
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    rpf.profile_reset()
+    rpf.profile_enable(True)
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        ts = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    rpf.profile_enable(False)
+    return out, elapsed, times, rpf.profile_read()
+
+
+def step_record(n, steps, elapsed, times, prof):
+    return {"value": round(n * steps / elapsed, 1), "ms_per_step": round(elapsed / steps * 1e3, 3),
+            "step_ms_p50": round(float(np.percentile(times, 50)) * 1e3, 3),
+            "step_ms_p99": round(float(np.percentile(times, 99)) * 1e3, 3),
+            "breakdown_ms_per_step": {k: round(v["total_ms"] / steps, 3)
+                                      for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])}}
 
 
 def main():
@@ -259,7 +313,7 @@ def main():
                                    "by trees is a design note only)"}))
         sys.exit(2)
     import torch
-    from paper_1812_11689_amd import rpf
+    from paper_1812_11689_amd import metrics, rpf
     from paper_1812_11689_amd import workloads as W
 
     if args.only_serve:
@@ -268,17 +322,39 @@ def main():
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(args)}), flush=True)
         return
+    if args.only_precision:
+        print(json.dumps({"precision_path": precision_leg(args)}), flush=True)
+        return
+    if args.only_step:
+        Ts, prec = args.only_step.split(":")
+        w = W.make_config(2, n=args.n)
+        n, d = w.x.shape
+        Tq, n0, K = int(Ts), w.leaf_size, w.k
+        Lq = rpf.depth(n, n0)
+        Xq = torch.from_numpy(w.x).cuda()
+        Rq = torch.from_numpy(W.directions(w.dir_seed, Tq, (1 << Lq) - 1, 1, d)).cuda()
+
+        def one():
+            f = rpf.build(Xq, Tq, n0, Rq, dist_prec=prec)
+            out = f.all_knn(K)
+            f.free()
+            return out
+        _, el, times, prof = timed_steps(one, args.steps, args.warmup)
+        print(json.dumps({"only_step": f"allknn_1M_d128_T{Tq}", "prec": prec, **step_record(n, args.steps, el, times, prof)}),
+              flush=True)
+        return
     t0 = time.time()
     w = W.make_config(2, n=args.n)
     n, d = w.x.shape
-    T, n0, K = w.n_trees, w.leaf_size, w.k
+    T0, n0, K = w.n_trees, w.leaf_size, w.k
     L = rpf.depth(n, n0)
-    R = W.directions(w.dir_seed, T, (1 << L) - 1, 1, d)
+    trees = sorted({T0, *[int(v) for v in args.target_trees.split(",") if int(v) > T0]})
+    # directions of the largest forest; tree t always uses stream (seed, t), so every smaller
+    # forest is a prefix of it
+    R = W.directions(w.dir_seed, trees[-1], (1 << L) - 1, 1, d)
     X = torch.from_numpy(w.x).cuda()
-    Rd = torch.from_numpy(R).cuda()
     torch.cuda.synchronize()
-    gen_s = time.time() - t0
-    print(f"# workload {w.name}: n={n} d={d} T={T} n0={n0} K={K} L={L} (generated in {gen_s:.1f}s)",
+    print(f"# workload {w.name}: n={n} d={d} T={T0} n0={n0} K={K} L={L} (generated in {time.time() - t0:.1f}s)",
           file=sys.stderr, flush=True)
 
     if args.copy_probe:
@@ -289,50 +365,86 @@ def main():
         print(f"# copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written", file=sys.stderr, flush=True)
         del src, dst
 
-    def step(prec):
-        f = rpf.build(X, T, n0, Rd, dist_prec=prec)
-        idx, dist = f.all_knn(K)
+    # ground truth of the recall (Sec. 5.1): exact kNN of a seeded sample of points by the
+    # library's brute-force kernel (binary64 distances, ties by index), each point left out
+    rng = np.random.default_rng(W.SEED_BASE + 300 + 2)
+    pts = np.sort(rng.choice(n, size=min(args.recall_sample, n), replace=False))
+    pts_d = torch.from_numpy(pts.astype(np.int64)).cuda()
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    ti, td = rpf.exact_knn(X, X[pts_d], K, pts_d)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - te
+    truth, truth_d = ti.cpu().numpy(), td.cpu().numpy()
+    exact = {"sample": len(pts), "ms": round(t_exact * 1e3, 2), "queries_per_s": round(len(pts) / t_exact, 1),
+             "binary64_distances_per_s": round(len(pts) * n / t_exact, 1)}
+    print(f"# exact truth of {len(pts)} points: {t_exact * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    Rd = {}
+
+    def dirs(T):
+        if T not in Rd:
+            Rd[T] = torch.from_numpy(np.ascontiguousarray(R[:T])).cuda()
+        return Rd[T]
+
+    def step_fn(T, prec):
+        def step():
+            f = rpf.build(X, T, n0, dirs(T), dist_prec=prec)
+            out = f.all_knn(K)
+            f.free()
+            return out
+        return step
+
+    # recall of the forest as it grows (nested forests: the first T trees are the T-tree forest)
+    sweep, t_star, ref_idx = [], None, {}
+    for T in trees:
+        f = rpf.build(X, T, n0, dirs(T), dist_prec="fp32")
+        it, dt = f.all_knn(K)
+        st_t = f.knn_stats()
         f.free()
-        return idx, dist
+        found = it.cpu().numpy()[pts]
+        r_t = metrics.recall(found, truth)
+        sweep.append({"n_trees": T, "recall": round(r_t, 5),
+                      "kth_distance_excess": round(metrics.kth_distance_excess(dt.cpu().numpy()[pts], truth_d), 6),
+                      "fallback_rows": st_t.get("fallback_rows")})
+        ref_idx[T] = it
+        print(f"# T={T}: recall {r_t:.4f}", file=sys.stderr, flush=True)
+        if r_t >= args.target_recall and t_star is None:
+            t_star = T
+            break
+    if t_star is None:
+        t_star = trees[-1]
+    recall_star = next(s_["recall"] for s_ in sweep if s_["n_trees"] == t_star)
 
-    def measure(prec, steps, warmup):
-        for _ in range(warmup):
-            step(prec)
-        torch.cuda.synchronize()
-        rpf.profile_reset()
-        rpf.profile_enable(True)
-        times = []
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for _ in range(steps):
-            ts = time.perf_counter()
-            idx, dist = step(prec)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - ts)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        rpf.profile_enable(False)
-        prof = rpf.profile_read()
-        return idx, dist, elapsed, times, prof
+    # the headline: the whole step (build + all-points kNN + free) at the tree count that
+    # reaches the target recall, bfloat16 tiles + re-rank, and plain binary32 beside it
+    res = {}
+    profs = {}
+    for prec in ("bf16", "fp32"):
+        (idx, _), el, times, prof = timed_steps(step_fn(t_star, prec), args.steps, args.warmup)
+        for r_ in prof.values():
+            r_["prec"] = prec
+        profs[prec] = prof
+        res[prec] = step_record(n, args.steps, el, times, prof)
+        res[prec]["identical_to_sweep"] = bool(torch.equal(idx, ref_idx[t_star]))
+        print(f"# T={t_star} {prec}: {res[prec]['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+    head = res["bf16"]
+    head_prof = profs["bf16"]
 
-    idx32, _, el32, times32, prof32 = measure("fp32", args.steps, args.warmup)
-    print(f"# fp32: {el32 / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
-    res_bf16 = None
-    if not args.no_bf16:
-        idx16, _, el16, times16, prof16 = measure("bf16", args.steps, 1)
-        print(f"# bf16: {el16 / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
-        same = bool(torch.equal(idx16, idx32))
-        res_bf16 = dict(value=round(n * args.steps / el16, 1), ms_per_step=round(el16 / args.steps * 1e3, 3),
-                        identical_to_fp32=same,
-                        breakdown_ms_per_step={k: round(v["total_ms"] / args.steps, 3) for k, v in
-                                               sorted(prof16.items(), key=lambda kv: -kv[1]["total_ms"])})
+    # the named configuration (T = 32), same steps
+    named = {"n_trees": T0, "recall": next(s_["recall"] for s_ in sweep if s_["n_trees"] == T0)}
+    for prec in ("fp32", "bf16"):
+        (idx, _), el, times, prof = timed_steps(step_fn(T0, prec), args.steps, args.warmup)
+        named[prec] = step_record(n, args.steps, el, times, prof)
+        named[prec]["identical_to_sweep"] = bool(torch.equal(idx, ref_idx[T0]))
+        print(f"# T={T0} {prec}: {named[prec]['ms_per_step']} ms/step", file=sys.stderr, flush=True)
 
-    # the same job as one recorded HIP graph (rpf_plan_*: build and candidate stage, tuned
+    # the same step recorded once as a HIP graph (rpf_plan_*: build and candidate stage, tuned
     # first-phase tree count), inputs set once before the timed launches
-    def plan_leg(prec, ref_idx, n_trees=None, dirs=None):
-        plan = rpf.Plan([n], [d], n_trees or T, n0, K, dist_prec=prec)
+    def plan_leg(prec, T, ref):
+        plan = rpf.Plan([n], [d], T, n0, K, dist_prec=prec)
         try:
-            plan.set_inputs([X], [Rd if dirs is None else dirs])
+            plan.set_inputs([X], [dirs(T)])
             plan.launch()
             plan.check()
             plan.tune()
@@ -346,104 +458,42 @@ def main():
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             plan.check()
-            same = bool(torch.equal(plan.result(0)[0], ref_idx))
             return dict(value=round(n * args.steps / el, 1), ms_per_step=round(el / args.steps * 1e3, 3),
-                        first_trees=plan.parts[0].get("first_trees"), identical_to_plain=same)
+                        first_trees=plan.parts[0].get("first_trees"),
+                        identical_to_plain=bool(torch.equal(plan.result(0)[0], ref)))
         finally:
             plan.close()
 
     graph = None
     if not args.no_graph:
-        graph = {"fp32": plan_leg("fp32", idx32)}
-        if res_bf16 is not None:
-            graph["bf16"] = plan_leg("bf16", idx16)
+        graph = {prec: plan_leg(prec, t_star, ref_idx[t_star]) for prec in ("bf16", "fp32")}
         print(f"# recorded plan: {graph}", file=sys.stderr, flush=True)
 
-    # recall against exact brute force on a seeded sample of points
-    rng = np.random.default_rng(W.SEED_BASE + 300 + 2)
-    pts = np.sort(rng.choice(n, size=min(args.recall_sample, n), replace=False))
-    truth = exact_knn_sample(X, torch.from_numpy(pts).cuda(), K)
-    recall = recall_of(idx32.cpu().numpy()[pts], truth)
-
-    # queries/s at the target recall: the same points and the same first T trees, plus more
-    # trees of the same direction streams (tree t always uses stream (seed, t)), until the
-    # sampled recall reaches the target; then the fp32 and bf16 steps are timed at that T
-    target = None
-    if args.target_recall > 0:
-        sweep, Rt, hit = [], R, None
-        for Tt in [int(v) for v in args.target_trees.split(",") if int(v) > T]:
-            extra = W.directions(w.dir_seed, Tt - Rt.shape[0], (1 << L) - 1, 1, d, first_tree=Rt.shape[0])
-            Rt = np.concatenate([Rt, extra])
-            Rtd = torch.from_numpy(Rt).cuda()
-            f = rpf.build(X, Tt, n0, Rtd, dist_prec="fp32")
-            it, _ = f.all_knn(K)
-            st_t = f.knn_stats()
-            f.free()
-            r_t = recall_of(it.cpu().numpy()[pts], truth)
-            sweep.append({"n_trees": Tt, "recall": round(r_t, 5), "fallback_rows": st_t.get("fallback_rows")})
-            print(f"# target leg: T={Tt} recall {r_t:.4f}", file=sys.stderr, flush=True)
-            if r_t >= args.target_recall:
-                hit = (Tt, Rtd, r_t, it)
-                break
-            del Rtd
-        target = {"target": args.target_recall, "sweep": sweep, "n_trees": None}
-        if hit is not None:
-            Tt, Rtd, r_t, it = hit
-
-            def step_t(prec):
-                f = rpf.build(X, Tt, n0, Rtd, dist_prec=prec)
-                out = f.all_knn(K)
-                f.free()
-                return out
-
-            def time_t(prec, steps=3):
-                step_t(prec)
-                torch.cuda.synchronize()
-                rpf.profile_reset()
-                rpf.profile_enable(True)
-                t = time.perf_counter()
-                for _ in range(steps):
-                    ib, _ = step_t(prec)
-                torch.cuda.synchronize()
-                el = (time.perf_counter() - t) / steps
-                rpf.profile_enable(False)
-                pr = rpf.profile_read()
-                bd = {k: round(v["total_ms"] / steps, 3) for k, v in sorted(pr.items(), key=lambda kv: -kv[1]["total_ms"])}
-                return ib, {"value": round(n / el, 1), "ms_per_step": round(el * 1e3, 3), "breakdown_ms_per_step": bd}
-
-            i32, t32 = time_t("fp32")
-            t32["identical_to_sweep"] = bool(torch.equal(i32, it))
-            target.update(n_trees=Tt, recall=round(r_t, 5), fp32=t32)
-            if not args.no_bf16:
-                i16, t16 = time_t("bf16")
-                t16["identical_to_fp32"] = bool(torch.equal(i16, i32))
-                target["bf16"] = t16
-            if not args.no_graph:  # the same step as a tuned, recorded plan (first-phase trees picked)
-                target["recorded_plan"] = {"fp32": plan_leg("fp32", i32, Tt, Rtd)}
-                if not args.no_bf16:
-                    target["recorded_plan"]["bf16"] = plan_leg("bf16", i32, Tt, Rtd)
-            print(f"# target leg: {target}", file=sys.stderr, flush=True)
-            del Rtd, it
-
-    for name, r in prof32.items():
-        r["prec"] = "fp32"
-    dom, roof = roofline(prof32)
+    dom, roof = roofline(head_prof)
     if roof is not None and dom is not None:
-        tr = traffic_for(dom)
+        tr = traffic_for(dom, "bf16")
         roof["traffic"] = tr  # HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE), or None
         if tr is not None:
             roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
-    breakdown = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(prof32.items(), key=lambda kv: -kv[1]["total_ms"])}
-    stages = stage_summary(prof32, args.steps, n, d, T, L, K)
+    stages = stage_summary(head_prof, args.steps, n, d, t_star, L, K)
 
-    f = rpf.build(X, T, n0, Rd, dist_prec="fp32")
+    f = rpf.build(X, t_star, n0, dirs(t_star), dist_prec="bf16")
     f.all_knn(K)
     st = f.knn_stats()
     f.free()
+    del Rd
+    torch.cuda.empty_cache()
+    rpf.release_cached_memory()
+
+    precision = None
+    if not args.no_precision:
+        precision = precision_leg(args)
+        torch.cuda.empty_cache()
+        rpf.release_cached_memory()
 
     serving = None
     if not args.no_serve:
-        del X, Rd
+        del X
         torch.cuda.empty_cache()
         rpf.release_cached_memory()
         serving = serving_leg(args)
@@ -458,49 +508,133 @@ def main():
     if not args.no_cpu_baseline:
         crng = np.random.default_rng(W.SEED_BASE + 300 + 3)
         cpts = np.sort(crng.choice(n, size=min(args.cpu_sample, n), replace=False))
-        cpu = cpu_baseline(w, R, cpts, K, args.cpu_trees)
+        cpu = cpu_baseline(w, R[:t_star], cpts, K, args.cpu_trees)
 
-    ms = el32 / args.steps * 1e3
     line = {
         "metric": METRIC,
-        "value": round(n * args.steps / el32, 1),
+        "value": head["value"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "d": d, "n_trees": T, "leaf_size": n0, "K": K,
-                   "tile_prec": "fp32", "split_projection": "f64", "rerank": "fp32+f64"},
-        "recall": round(recall, 5),
-        "step_ms_p50": round(float(np.percentile(times32, 50)) * 1e3, 3),
-        "step_ms_p99": round(float(np.percentile(times32, 99)) * 1e3, 3),
-        "bf16_rerank": res_bf16,
+        "config": {"workload": f"allknn_1M_d128_T{t_star}", "n": n, "d": d, "n_trees": t_star, "leaf_size": n0,
+                   "K": K, "tile_prec": "bf16", "split_projection": "f64", "rerank": "fp32+f64",
+                   "trees_chosen_for_recall": args.target_recall, "named_config_trees": T0},
+        "recall": recall_star,
+        "recall_truth": "exact kNN (rpf_exact_knn, binary64) of a seeded sample of points; Sec. 5.1 missing rate",
+        "step_ms_p50": head["step_ms_p50"],
+        "step_ms_p99": head["step_ms_p99"],
+        "bf16_rerank": head,
+        "fp32": res["fp32"],
+        "bf16_speedup_over_fp32": round(head["value"] / res["fp32"]["value"], 4),
+        "recall_sweep": sweep,
+        "named_config": named,
         "recorded_plan": graph,
-        "at_target_recall": target,
+        "exact_truth": exact,
         "knn_stats": st,
-        "breakdown_ms_per_step": breakdown,
         "stages": stages,
         "roofline_kernel": dom,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "precision_path": precision,
         "serving": serving,
         "batched": batched,
     }
     print(json.dumps(line), flush=True)
 
 
+def precision_leg(args):
+    """The precision path on quantised image-like data: 10^6 x 784, 70 % exact zeros, other
+    entries k/255; T 48, n0 512 (leaves of 488/489 points), K 10, bfloat16 tiles with the
+    binary32/binary64 re-rank, and the same forest with binary32 tiles once beside it (the
+    outputs must be identical: both are the exact top-K of the leaf union).  Reports the step
+    time, the tiles' fraction of the bf16 MFMA peak, the recall against exact kNN of a seeded
+    sample, and the error of the bfloat16 distance model against binary64 on sampled leaf pairs."""
+    import torch
+    from paper_1812_11689_amd import metrics, rpf
+    from paper_1812_11689_amd import workloads as W
+
+    t0 = time.time()
+    w = W.make_config(3, n=args.precision_n)
+    n, d = w.x.shape
+    T, n0, K = w.n_trees, w.leaf_size, w.k
+    L = rpf.depth(n, n0)
+    X = torch.from_numpy(w.x).cuda()
+    R = torch.from_numpy(W.directions(w.dir_seed, T, (1 << L) - 1, 1, d)).cuda()
+    torch.cuda.synchronize()
+    print(f"# precision workload {w.name}: n={n} d={d} T={T} n0={n0} K={K} (generated in {time.time() - t0:.1f}s)",
+          file=sys.stderr, flush=True)
+    res = {"workload": w.name, "n": n, "d": d, "n_trees": T, "leaf_size": n0, "K": K}
+
+    def step_fn(prec):
+        def step():
+            f = rpf.build(X, T, n0, R, dist_prec=prec)
+            out = f.all_knn(K)
+            f.free()
+            return out
+        return step
+
+    (i16, _), el, times, prof = timed_steps(step_fn("bf16"), max(1, min(args.steps, 3)), 1)
+    rec = step_record(n, max(1, min(args.steps, 3)), el, times, prof)
+    tiles = [prof[k] for k in ("tile_phase1", "tile_phase2") if k in prof]
+    t_ms = sum(r["total_ms"] for r in tiles) / max(1, min(args.steps, 3))
+    t_fl = sum(r["algo_flops"] for r in tiles) / max(1, min(args.steps, 3))
+    rec["tiles_ms"] = round(t_ms, 3)
+    rec["tiles_algorithmic_tflop"] = round(t_fl / 1e12, 3)
+    rec["tiles_bf16_mfma_frac"] = round(t_fl / (t_ms / 1e3) / (BF16_MFMA_PEAK_TFLOPS * 1e12), 4) if t_ms else None
+    res["bf16"] = rec
+    print(f"# precision bf16: {rec['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+    (i32, _), el, times, prof = timed_steps(step_fn("fp32"), 1, 0)
+    res["fp32_once"] = {"ms": round(el * 1e3, 3), "identical_to_bf16": bool(torch.equal(i32, i16))}
+    res["missing_rate_bf16_vs_fp32_tiles"] = 0.0 if res["fp32_once"]["identical_to_bf16"] else None
+    del i32
+    rng = np.random.default_rng(W.SEED_BASE + 303)
+    pts = np.sort(rng.choice(n, size=min(2000, n), replace=False))
+    pts_d = torch.from_numpy(pts.astype(np.int64)).cuda()
+    ti, _ = rpf.exact_knn(X, X[pts_d], K, pts_d)
+    res["recall"] = round(metrics.recall(i16.cpu().numpy()[pts], ti.cpu().numpy()), 5)
+    res["recall_sample"] = len(pts)
+    # the bfloat16 tile arithmetic against binary64 on the leaf pairs of sampled points (tree 0):
+    # rows centred on their leaf's binary32 mean, rounded to bfloat16, products accumulated in
+    # binary32 -- a model of what the tiles compute, with the same operand rounding
+    f = rpf.build(X, T, n0, R, dist_prec="bf16")
+    dump = f.tree_dump(0)
+    f.free()
+    leaf_of = dump["leaf_of"]
+    errs = []
+    for p in pts[:64]:
+        mates = torch.nonzero(leaf_of == leaf_of[int(p)]).flatten()
+        xs = X[mates]
+        mu = xs.mean(0)
+        c = (xs - mu).to(torch.bfloat16).float()
+        a = c[(mates == int(p)).nonzero().flatten()[0]]
+        Dt = (a * a).sum() + (c * c).sum(1) - 2.0 * (c @ a)
+        D64 = ((xs.double() - X[int(p)].double()) ** 2).sum(1)
+        ok = D64 > 0
+        errs.append(((Dt.double() - D64).abs()[ok] / D64[ok]).cpu().numpy())
+    e = np.concatenate(errs)
+    res["bf16_distance_rel_error_vs_f64"] = {"max": float(e.max()), "mean": float(e.mean()), "pairs": int(e.size),
+                                             "what": "bf16-rounded centred rows, fp32 products (tile model), tree 0"}
+    print(f"# precision: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def serving_leg(args):
     """Continuous-batching server over the resident 4M x 96 forest (T 64, n0 256): a closed
-    burst of requests gives the saturated rate; an open-loop Poisson stream at 0.8 of it gives
-    request latency.  Batch sizes lognormal (median 64, sigma 1.5) in [1, 4096], K uniform over
-    {1, 10, 100}; queries from the served mixture with 5 % uniform outliers."""
+    burst of requests gives the saturated rate; open-loop Poisson streams at 0.5, 0.8 and 0.95
+    of it give request latency (p50 / p99).  Batch sizes lognormal (median 64, sigma 1.5) in
+    [1, 4096], K uniform over {1, 10, 100}; queries from the served mixture with 5 % uniform
+    outliers.  Recall of the served results against exact kNN (rpf_exact_knn) on sampled
+    request rows, and the recall of the same rows as the forest grows (nested forests: the
+    first T' trees of the T-tree forest)."""
     import torch
-    from paper_1812_11689_amd import rpf
+    from paper_1812_11689_amd import metrics, rpf
     from paper_1812_11689_amd import workloads as W
 
     t0 = time.time()
@@ -508,8 +642,11 @@ def serving_leg(args):
     n, d = w.x.shape
     T, n0 = w.n_trees, w.leaf_size
     L = rpf.depth(n, n0)
+    curve_trees = [int(v) for v in args.serve_curve.split(",") if v]
+    Tmax = max([T] + curve_trees)
     X = torch.from_numpy(w.x).cuda()
-    R = torch.from_numpy(W.directions(w.dir_seed, T, (1 << L) - 1, 1, d)).cuda()
+    Rall = W.directions(w.dir_seed, Tmax, (1 << L) - 1, 1, d)
+    R = torch.from_numpy(np.ascontiguousarray(Rall[:T])).cuda()
     nreq = args.serve_requests
     seed = W.SEED_BASE + 200 + 4
     _, sizes, ks = W.serving_requests(seed, nreq, 1.0)
@@ -523,15 +660,39 @@ def serving_leg(args):
     torch.cuda.synchronize()
     print(f"# serving workload {w.name}: n={n} d={d} T={T} n0={n0}, {nreq} requests, {pool} rows "
           f"(generated in {time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    res = {"workload": w.name, "requests": nreq, "rows": pool,
-           "batch_rows": "lognormal(ln 64, 1.5) in [1, 4096]", "K": "uniform {1, 10, 100}"}
+    res = {"workload": w.name, "requests_per_load": nreq, "rows_per_load": pool,
+           "batch_rows": "lognormal(ln 64, 1.5) in [1, 4096]", "K": "uniform {1, 10, 100}",
+           "loads": list(args.serve_loads)}
+
+    # sampled request rows per K and their exact neighbours (the recall truth)
+    samp = {}
+    for k in (1, 10, 100):
+        rows = []
+        for i in range(nreq):
+            if ks[i] == k:
+                rows.extend(range(offs[i], min(offs[i + 1], offs[i] + 8)))
+            if len(rows) >= args.serve_recall_rows:
+                break
+        rows = np.asarray(rows[:args.serve_recall_rows], dtype=np.int64)
+        if len(rows):
+            rd = torch.from_numpy(rows).cuda()
+            ti, _ = rpf.exact_knn(X, Q[rd], k)
+            samp[k] = (rows, rd, ti.cpu().numpy())
+    req_of_row = np.searchsorted(offs, np.arange(pool), side="right") - 1
+
+    def served_recall():
+        hits = tot = 0
+        for k, (rows, _, truth) in samp.items():
+            got = np.stack([outs[req_of_row[r]][0][r - offs[req_of_row[r]]].cpu().numpy() for r in rows])
+            hits += (1.0 - metrics.missing_rate(got, truth)) * truth.size
+            tot += truth.size
+        return round(hits / max(tot, 1), 5)
 
     def run(prec):
         f = rpf.build(X, T, n0, R, dist_prec=prec)
         torch.cuda.synchronize()
         srv = rpf.Server(f, slots=4, max_batch_rows=8192)
-        # warm-up
-        for q, k in reqs[:64]:
+        for q, k in reqs[:64]:  # warm-up
             srv.wait(srv.submit(q, k))
         # closed burst: every request queued at once
         srv.reset_stats()
@@ -540,55 +701,77 @@ def serving_leg(args):
             srv.wait(t)
         burst = srv.stats()
         rate = burst["requests"] / (burst["rows"] / burst["rows_per_s"])  # requests/s at saturation
-        # open loop at 0.8 of the saturated request rate
-        srv.reset_stats()
-        arr, _, _ = W.serving_requests(seed + 1, nreq, 0.8 * rate)
-        start = time.perf_counter()
-        ts = []
-        for i, ((q, k), o) in enumerate(zip(reqs, outs)):
-            now = time.perf_counter() - start
-            if arr[i] > now:
-                time.sleep(arr[i] - now)
-            ts.append(srv.submit(q, k, out=o))
-        for t in ts:
-            srv.wait(t)
-        ol = srv.stats()
-        srv.close()
         out = {"saturated_rows_per_s": round(burst["rows_per_s"], 1),
                "saturated_requests_per_s": round(rate, 1),
                "burst_mean_batch_rows": round(burst["mean_batch_rows"], 1),
-               "open_loop": {"offered_requests_per_s": round(0.8 * rate, 1),
-                             "rows_per_s": round(ol["rows_per_s"], 1),
-                             "p50_ms": round(ol["p50_s"] * 1e3, 3), "p99_ms": round(ol["p99_s"] * 1e3, 3),
-                             "max_ms": round(ol["max_s"] * 1e3, 3),
-                             "mean_batch_rows": round(ol["mean_batch_rows"], 1)}}
+               "recall": served_recall(), "open_loop": {}}
+        for rho in args.serve_loads:
+            srv.reset_stats()
+            arr, _, _ = W.serving_requests(seed + 1, nreq, rho * rate)
+            start = time.perf_counter()
+            ts = []
+            for i, ((q, k), o) in enumerate(zip(reqs, outs)):
+                now = time.perf_counter() - start
+                if arr[i] > now:
+                    time.sleep(arr[i] - now)
+                ts.append(srv.submit(q, k, out=o))
+            for t in ts:
+                srv.wait(t)
+            ol = srv.stats()
+            spans = srv.batch_log()
+            out["open_loop"][str(rho)] = {
+                "offered_requests_per_s": round(rho * rate, 1), "rows_per_s": round(ol["rows_per_s"], 1),
+                "p50_ms": round(ol["p50_s"] * 1e3, 3), "p99_ms": round(ol["p99_s"] * 1e3, 3),
+                "max_ms": round(ol["max_s"] * 1e3, 3), "mean_batch_rows": round(ol["mean_batch_rows"], 1),
+                "failed_requests": ol["failed_requests"], "recall": served_recall(),
+                "device_busy_frac": round(_busy(spans) / max(1e-9, (time.perf_counter() - start) * 1e3), 4)}
+        srv.close()
         print(f"# serving {prec}: {out}", file=sys.stderr, flush=True)
         return f, out
 
     f16, res["fp16"] = run("fp16")
-    # recall of the fp16 results on the first requests' rows (K as requested)
-    Xd = X.double()
-    nrm = (Xd * Xd).sum(1)
-    hit = tot = 0
-    for i in range(nreq):
-        if tot >= 1500:
-            break
-        q, k = reqs[i]
-        qd = q[:16].double()  # at most 16 rows of a request: [16][n] binary64 distances
-        D = nrm[None, :] - 2.0 * (qd @ Xd.T)
-        truth = torch.topk(D, k, dim=1, largest=False).indices.cpu().numpy()
-        got = outs[i][0][:16].cpu().numpy()
-        for a, b in zip(got, truth):
-            hit += len(set(a.tolist()) & set(b.tolist()))
-        tot += truth.size
-    res["recall_fp16"] = round(hit / max(tot, 1), 5)
-    res["recall_sample_neighbours"] = tot
     f16.free()
-    del Xd, nrm
     torch.cuda.empty_cache()
     f32, res["fp32"] = run("fp32")
     f32.free()
+    del outs
+    torch.cuda.empty_cache()
+    rpf.release_cached_memory()
+    # recall of the sampled rows as the forest grows (fp16 tiles; results are exact for the
+    # union, so the precision does not change them)
+    curve = []
+    for Tc in curve_trees:
+        Rc = torch.from_numpy(np.ascontiguousarray(Rall[:Tc])).cuda()
+        f = rpf.build(X, Tc, n0, Rc, dist_prec="fp16")
+        hits = tot = 0
+        for k, (rows, rd, truth) in samp.items():
+            gi, _ = f.query(Q[rd], k)
+            hits += (1.0 - metrics.missing_rate(gi.cpu().numpy(), truth)) * truth.size
+            tot += truth.size
+        f.free()
+        del Rc
+        rpf.release_cached_memory()
+        curve.append({"n_trees": Tc, "recall": round(hits / max(tot, 1), 5)})
+        print(f"# serving recall T'={Tc}: {curve[-1]['recall']}", file=sys.stderr, flush=True)
+    res["recall_by_trees"] = curve
+    res["recall_sample_rows"] = int(sum(len(v[0]) for v in samp.values()))
     return res
+
+
+def _busy(spans):
+    """Milliseconds in which at least one batch was in flight on the device (union of spans)."""
+    iv = sorted((b["start_ms"], b["end_ms"]) for b in spans if b["start_ms"] >= 0)
+    tot, cur = 0.0, None
+    for a, b in iv:
+        if cur is None or a > cur[1]:
+            if cur is not None:
+                tot += cur[1] - cur[0]
+            cur = [a, b]
+        else:
+            cur[1] = max(cur[1], b)
+    if cur is not None:
+        tot += cur[1] - cur[0]
+    return tot
 
 
 def batched_leg(args):
@@ -644,18 +827,18 @@ def batched_leg(args):
     ms = float(np.median(times)) * 1e3
     res["graph_ms_per_job"] = round(ms, 3)
     res["graph_points_per_s"] = round(N / (ms / 1e3), 1)
-    # recall of a sample of data sets against exact brute force (binary64 on the device)
+    # recall of a sample of data sets against exact kNN (rpf_exact_knn), Sec. 5.1 missing rate
+    from paper_1812_11689_amd import metrics
     rng = np.random.default_rng(W.SEED_BASE + 305)
     hit = tot = 0
-    for i in rng.choice(count, size=min(8, count), replace=False):
-        X = torch.from_numpy(xs[i]).cuda().double()
-        pts = torch.from_numpy(rng.choice(sizes[i], size=min(300, sizes[i]), replace=False)).cuda()
-        D = (X * X).sum(1)[None, :] - 2.0 * (X[pts] @ X.T)
-        D[torch.arange(len(pts)), pts] = float("inf")
-        truth = torch.topk(D, K, dim=1, largest=False).indices.cpu().numpy()
-        got = plan.result(int(i))[0][pts].cpu().numpy()
-        for a, b in zip(got, truth):
-            hit += len(set(a.tolist()) & set(b.tolist()))
+    for i in rng.choice(count, size=min(16, count), replace=False):
+        X = torch.from_numpy(xs[i]).cuda()
+        pts = np.sort(rng.choice(sizes[i], size=min(500, sizes[i]), replace=False))
+        pd = torch.from_numpy(pts.astype(np.int64)).cuda()
+        ti, _ = rpf.exact_knn(X, X[pd], K, pd)
+        truth = ti.cpu().numpy()
+        got = plan.result(int(i))[0][pd].cpu().numpy()
+        hit += metrics.recall(got, truth) * truth.size
         tot += truth.size
     res["recall"] = round(hit / max(tot, 1), 5)
     parts = [[e_i for e_i, e in enumerate(plan.entries) if e["part"] == k] for k in range(len(plan.parts))]
@@ -697,25 +880,61 @@ def batched_leg(args):
     return res
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, R, sample_pts, K, cpu_trees):
     """The oracle as it stands, on the host cores: the forest build timed in full on all n
     points (all T trees, or `cpu_trees` of them scaled by T/cpu_trees), plus all-points kNN
-    timed on a seeded sample of points and extrapolated linearly to n."""
+    timed on a seeded sample of points and extrapolated linearly to n; then one thread on a
+    smaller sample (two trees, scaled; 200 points) for the single-core rate."""
     import oracle
     oracle.build(force=False)
     n = w.x.shape[0]
-    T = w.n_trees if not cpu_trees else min(cpu_trees, w.n_trees)
+    Tw = R.shape[0]
+    T = Tw if not cpu_trees else min(cpu_trees, Tw)
     t0 = time.perf_counter()
     f = oracle.build_forest(w.x, R, T, w.leaf_size)
-    t_build = (time.perf_counter() - t0) * (w.n_trees / T)
+    t_build = (time.perf_counter() - t0) * (Tw / T)
     t0 = time.perf_counter()
     oracle.all_knn(f, K, points=sample_pts)
-    t_knn = (time.perf_counter() - t0) * (n / len(sample_pts)) * (w.n_trees / T)
-    return {"value": round(n / (t_build + t_knn), 1), "unit": "queries/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"build of {T} of {w.n_trees} trees on all {n} points (scaled by {w.n_trees}/{T}) + "
-                      f"kNN of {len(sample_pts)} sampled points extrapolated to {n}",
-            "build_s": round(t_build, 2), "knn_s_extrapolated": round(t_knn, 2)}
+    t_knn = (time.perf_counter() - t0) * (n / len(sample_pts)) * (Tw / T)
+    out = {"value": round(n / (t_build + t_knn), 1), "unit": "queries/s", "cores": oracle.threads(),
+           "kind": "oracle", "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "sample": f"build of {T} of {Tw} trees on all {n} points (scaled by {Tw}/{T}) + "
+                     f"kNN of {len(sample_pts)} sampled points extrapolated to {n}",
+           "build_s": round(t_build, 2), "knn_s_extrapolated": round(t_knn, 2)}
+    # one thread: a child process with OMP_NUM_THREADS=1 (the thread count is fixed per process)
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); import oracle; "
+            "from paper_1812_11689_amd import workloads as W; "
+            "w = W.make_config(2, n=%d); L = oracle.depth(w.x.shape[0], w.leaf_size); "
+            "R = W.directions(w.dir_seed, 2, (1 << L) - 1, 1, w.x.shape[1]); "
+            "t0 = time.perf_counter(); f = oracle.build_forest(w.x, R, 2, w.leaf_size); tb = time.perf_counter() - t0; "
+            "p = np.sort(np.random.default_rng(5).choice(w.x.shape[0], 200, replace=False)); "
+            "t0 = time.perf_counter(); oracle.all_knn(f, %d, points=p); tk = time.perf_counter() - t0; "
+            "print(oracle.threads(), tb, tk)") % (ROOT, n, K)
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        th, tb, tk = r.stdout.split()[-3:]
+        b1 = float(tb) * Tw / 2
+        k1 = float(tk) * (n / 200) * (Tw / 2)
+        out["one_thread"] = {"value": round(n / (b1 + k1), 1), "cores": int(th), "build_s": round(b1, 1),
+                             "knn_s_extrapolated": round(k1, 1),
+                             "sample": f"build of 2 of {Tw} trees on all {n} points (scaled) + kNN of 200 sampled "
+                                       f"points on those 2 trees (scaled to {Tw} trees and {n} points)"}
+    except Exception as e:  # the all-cores figure stands on its own
+        out["one_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 if __name__ == "__main__":

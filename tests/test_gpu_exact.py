@@ -27,6 +27,9 @@ CASES = [
     ("duplicates", 6000, 8, 300, 8, "mixture", 5, True),
     ("mass_ties", 6000, 8, 200, 16, "mixture", 2, True),
     ("wide_exponents", 3000, 24, 150, 6, "wide", 0, True),
+    ("d64_two_steps", 5000, 64, 200, 16, "mixture", 0, True),
+    ("d256_eight_steps", 3000, 256, 130, 16, "aniso", 0, True),
+    ("d8_one_step", 6000, 8, 300, 16, "mixture", 0, True),
 ]
 
 
