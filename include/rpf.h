@@ -54,7 +54,13 @@ typedef enum { RPF_SPLIT_MEDIAN = 0 } rpf_split;
  * precision, the returned neighbours are the exact top-K of the leaf union under the
  * binary64 ranking: tile distances only prune, with rigorous error bounds, and the
  * surviving candidates are re-ranked in binary32 and, near the K-th distance, binary64. */
-typedef enum { RPF_DIST_FP32 = 0, RPF_DIST_BF16 = 1, RPF_DIST_FP16 = 2 } rpf_dist_prec;
+typedef enum { RPF_DIST_FP32 = 0, RPF_DIST_BF16 = 1, RPF_DIST_FP16 = 2, RPF_DIST_BF16X3 = 3 } rpf_dist_prec;
+/* RPF_DIST_BF16X3: the forest holds binary32 copies and norms (as RPF_DIST_FP32, and
+ * rpf_query runs the binary32 tiles), but the all-points tiles split every centred binary32
+ * value a into hi = bf16(a) and lo = bf16(a - hi) and form the Gram product on bfloat16
+ * MFMA as hi.hi + hi.lo + lo.hi with binary32 accumulation; the omitted and rounded parts
+ * (|a - hi - lo| <= 2^-16 |a|, |lo.lo| <= 2^-16 |a||b|) enter the pruning bounds, which stay
+ * close to the binary32 ones. */
 
 typedef struct rpf_forest rpf_forest; /* opaque; owns all of its device memory */
 

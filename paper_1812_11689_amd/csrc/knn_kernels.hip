@@ -51,6 +51,13 @@ struct TileCfg<RPF_DIST_FP16> {
     using T = _Float16;
     static constexpr int KC = 64, LDW = 72, KSTEP = 16;
 };
+// split bfloat16: every staged binary32 value a is held as hi = bf16(a) and lo = bf16(a - hi)
+// in two LDS tiles of this shape (hi tile, then lo tile)
+template <>
+struct TileCfg<RPF_DIST_BF16X3> {
+    using T = __bf16;
+    static constexpr int KC = 32, LDW = 40, KSTEP = 16;
+};
 
 template <int PREC>
 __device__ inline f32x16 mfma_step(const typename TileCfg<PREC>::T *sa, const typename TileCfg<PREC>::T *sb,
@@ -79,12 +86,16 @@ template <>
 struct MfmaOperand<RPF_DIST_FP16> {
     using type = f16x8;
 };
+template <>
+struct MfmaOperand<RPF_DIST_BF16X3> {
+    using type = bf16x8;
+};
 
 template <int PREC>
 __device__ inline f32x16 mfma_op(typename MfmaOperand<PREC>::type a, typename MfmaOperand<PREC>::type b, f32x16 acc) {
     if constexpr (PREC == RPF_DIST_FP32)
         return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    else if constexpr (PREC == RPF_DIST_BF16)
+    else if constexpr (PREC == RPF_DIST_BF16 || PREC == RPF_DIST_BF16X3)
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     else
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
@@ -126,7 +137,7 @@ __device__ inline void stage_rows(typename TileCfg<PREC>::T *s, const typename T
 template <int PREC, bool VEC>
 __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *__restrict__ X, int d,
                                     const int32_t *s_pt, const float *__restrict__ mu, int rows, int rows_pad,
-                                    int k0, int nthreads) {
+                                    int k0, int nthreads, typename TileCfg<PREC>::T *s_lo = nullptr) {
     using C = TileCfg<PREC>;
     using T = typename C::T;
     constexpr int EV = PREC == RPF_DIST_FP32 ? 4 : 8;  // elements per LDS vector
@@ -157,7 +168,20 @@ __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *_
             }
         }
         T *dst = s + r * C::LDW + c;
-        if constexpr (PREC == RPF_DIST_FP32) {
+        if constexpr (PREC == RPF_DIST_BF16X3) {
+            // hi = RN_bf16(a); a - hi is exact in binary32; lo = RN_bf16(a - hi)
+            T hq[EV], lq[EV];
+#pragma unroll
+            for (int e = 0; e < EV; e++) {
+                hq[e] = (T)a[e];
+                lq[e] = (T)(a[e] - (float)hq[e]);
+            }
+            uint4 wh, wl;
+            __builtin_memcpy(&wh, hq, sizeof(wh));
+            __builtin_memcpy(&wl, lq, sizeof(wl));
+            *reinterpret_cast<uint4 *>(dst) = wh;
+            *reinterpret_cast<uint4 *>(s_lo + r * C::LDW + c) = wl;
+        } else if constexpr (PREC == RPF_DIST_FP32) {
 #pragma unroll
             for (int e = 0; e < EV; e++) dst[e] = a[e];
         } else {
@@ -487,8 +511,9 @@ void k_tile_sym(
     constexpr int PAIR = NB + 1;
     constexpr int WPP = NB >= 2 ? NW / (NB / 2) : 1;  // waves per pair of block rows
     constexpr int SLOTS = NB >= 2 ? (PAIR + WPP - 1) / WPP : 1;
-    constexpr int QL = NW > 8 ? 384 : kQueue;         // queue entries per wave (LDS for two blocks)
-    __shared__ __align__(16) T s_a[M * C::LDW];
+    constexpr bool SPLIT = PREC == RPF_DIST_BF16X3;   // hi and lo tiles, three products per step
+    constexpr int QL = NW > 8 ? (SPLIT ? 352 : 384) : kQueue;  // queue entries per wave (LDS for two blocks)
+    __shared__ __align__(16) T s_a[(SPLIT ? 2 : 1) * M * C::LDW];
     __shared__ __align__(16) float s_n[M];
     __shared__ __align__(16) float s_r[M];
     __shared__ __align__(16) float s_phi[M];
@@ -582,8 +607,8 @@ void k_tile_sym(
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
     for (int k0 = 0; k0 < dp; k0 += C::KC) {
         __syncthreads();
-        if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT);
-        else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT);
+        if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+        else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
         __syncthreads();
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
@@ -597,9 +622,31 @@ void k_tile_sym(
             fa1 = *reinterpret_cast<const Frag *>(base + 32 * sbi[SLOTS - 1] * C::LDW + kk);
 #pragma unroll
             for (int sl = 0; sl < SLOTS; sl++) fb[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbj[sl] * C::LDW + kk);
+            // (split: every slot's MFMA runs -- an inactive slot's accumulator is never read --
+            // so that the three passes stay one basic block and the accumulators in registers)
 #pragma unroll
             for (int sl = 0; sl < SLOTS; sl++)
-                if (act[sl]) acc[sl] = mfma_op<PREC>(sbi[sl] == sbi[0] ? fa0 : fa1, fb[sl], acc[sl]);
+                if (SPLIT || act[sl]) acc[sl] = mfma_op<PREC>(sbi[sl] == sbi[0] ? fa0 : fa1, fb[sl], acc[sl]);
+            if constexpr (SPLIT) {
+                // hi_a . lo_b, then lo_a . hi_b: at most five fragments live at a time (the
+                // scheduling barriers keep the next pass's loads behind this pass's MFMAs)
+                const T *lo = base + M * C::LDW;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; sl++) fb[sl] = *reinterpret_cast<const Frag *>(lo + 32 * sbj[sl] * C::LDW + kk);
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; sl++)
+                    acc[sl] = mfma_op<PREC>(sbi[sl] == sbi[0] ? fa0 : fa1, fb[sl], acc[sl]);
+                __builtin_amdgcn_sched_barrier(0);
+                fa0 = *reinterpret_cast<const Frag *>(lo + 32 * sbi[0] * C::LDW + kk);
+                fa1 = *reinterpret_cast<const Frag *>(lo + 32 * sbi[SLOTS - 1] * C::LDW + kk);
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; sl++) fb[sl] = *reinterpret_cast<const Frag *>(base + 32 * sbj[sl] * C::LDW + kk);
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; sl++)
+                    acc[sl] = mfma_op<PREC>(sbi[sl] == sbi[0] ? fa0 : fa1, fb[sl], acc[sl]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
 
@@ -1992,12 +2039,28 @@ __global__ __launch_bounds__(256) void k_query_prep(const float *__restrict__ Q,
 // Phase I slots per (row, tree): the largest leaf rounded up to a wave, so that the slots of a
 // row's wave-wide column q all belong to one tree
 
+// Bound coefficients of a tile precision (see pair_bounds).  Split bfloat16: the tiles hold
+// the binary32 values a (norms and copy rounding as binary32), and the Gram product is
+// sum(hi_a hi_b + hi_a lo_b + lo_a hi_b) over 3d exact products accumulated in binary32.
+// With |lo| <= 2^-8 |a|, |a - hi - lo| <= 2^-16 |a|, the omitted lo.lo and residual terms
+// are at most 3.0001 2^-16 |a||b| per column, the accumulation at most 1.0235 gamma_{3d+1}
+// |a||b|; twice that (D = |a|^2 + |b|^2 - 2G) is at most (1.0235 gamma_{3d+1} + 3.0001
+// 2^-16)(|a|^2 + |b|^2), beside 2 gamma_{d+2} for the two norms.  An input a flushed to zero
+// by the MFMA moves each row by at most 2^-126 per column: eta covers it.
 static BoundCoef bound_coef(int prec, int d) {
     const double u32 = ldexp(1.0, -24);
     const double ulp = prec == RPF_DIST_BF16 ? ldexp(1.0, -8) : prec == RPF_DIST_FP16 ? ldexp(1.0, -11) : 0.0;
     const double k = d + 2;
     const double gam = k * u32 / (1.0 - k * u32);
     BoundCoef bc;
+    if (prec == RPF_DIST_BF16X3) {
+        const double k3 = 3.0 * d + 2;
+        const double gam3 = k3 * u32 / (1.0 - k3 * u32);
+        bc.e = (float)((2.0 * gam + 1.0235 * gam3 + 3.0001 * ldexp(1.0, -16)) * 1.02);
+        bc.c = (float)(u32 * (1.0 + (d + 4) * u32) * 1.01);
+        bc.eta = (float)(2.0 * ldexp(1.0, -125) * sqrt((double)d) * 1.01);
+        return bc;
+    }
     bc.e = (float)(2.0 * 2.0 * gam * 1.01);
     bc.c = (float)((ulp + u32 + ulp * u32) * (1.0 + (d + 4) * u32) * 1.01);
     bc.eta = prec == RPF_DIST_FP16 ? (float)(2.0 * ldexp(1.0, -25) * sqrt((double)d) * 1.01) : 0.f;
@@ -2167,7 +2230,9 @@ static void sym_dispatch_nb(int NB, hipStream_t s, int64_t njobs, const TileJob 
 
 static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const TileJob *jobs, const SymSrc &src,
                          const float2 *nrm, const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
-    if (prec == RPF_DIST_BF16)
+    if (prec == RPF_DIST_BF16X3)
+        sym_dispatch_nb<RPF_DIST_BF16X3>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
+    else if (prec == RPF_DIST_BF16)
         sym_dispatch_nb<RPF_DIST_BF16>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
     else if (prec == RPF_DIST_FP16)
         sym_dispatch_nb<RPF_DIST_FP16>(NB, s, njobs, jobs, src, nrm, pt, bc, excl, out);
@@ -2283,6 +2348,8 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     fill_u32(fb_cnt, 4, 0, s);
     fill_u32(v.stats, kStatSlots * 8 * 2, 0, s);
     const BoundCoef bc = bound_coef(v.prec, v.d);
+    // the all-points symmetric tiles may run split bfloat16 over a binary32 forest
+    const BoundCoef bc_sym = v.sym_prec == v.prec ? bc : bound_coef(v.sym_prec, v.d);
     const int MB = v.job_mb;
     TileOut o1;
     o1.mode = 0;
@@ -2298,7 +2365,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     {
         ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, sym_src(v), v.nrm, v.perm, bc, cs.excl, o1);
+            sym_dispatch(v.sym_prec, MB, s, cs.njobs0, cs.jobs0, sym_src(v), v.nrm, v.perm, bc_sym, cs.excl, o1);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o1);
@@ -2333,7 +2400,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         o2.ent = ent;
         ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
         if (cs.sym)
-            sym_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, sym_src(v), v.nrm, v.perm, bc, cs.excl, o2);
+            sym_dispatch(v.sym_prec, MB, s, cs.njobs1, cs.jobs1, sym_src(v), v.nrm, v.perm, bc_sym, cs.excl, o2);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
                           cs.a_dest, v.perm, bc, cs.excl, o2);

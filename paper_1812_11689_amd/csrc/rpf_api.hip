@@ -247,6 +247,7 @@ struct LevelPlan {
 struct rpf_forest {
     int64_t n = 0;
     int32_t d = 0, T = 0, n0 = 0, n_try = 0, L = 0, prec = 0, dp = 0;
+    int32_t tile_prec = 0;  // as asked (rpf_dist_prec); prec is that of the copies and norms
     int64_t H = 0;
     int device = 0;
     // persistent device arrays
@@ -438,7 +439,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
     if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
     if (p->split_rule != RPF_SPLIT_MEDIAN) return fail(RPF_EINVAL, "rpf_build: only the median split rule is implemented");
-    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_FP16)
+    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_BF16X3)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
     if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
     std::vector<rpf_batch_entry> roots(count);
@@ -546,7 +547,8 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         }
 
     // ---- memory plan
-    const int prec = p->dist_prec;
+    // split bfloat16 tiles run over binary32 copies and norms: the forest is a binary32 one
+    const int prec = p->dist_prec == RPF_DIST_BF16X3 ? RPF_DIST_FP32 : p->dist_prec;
     const int dp = (d + 7) & ~7;
     const size_t esz = prec == RPF_DIST_FP32 ? 4 : 2;
     const int64_t nleaf = (int64_t)leaves.size();
@@ -580,7 +582,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
 
     rpf_forest *f = new rpf_forest();
     f->n = n; f->d = d; f->T = T; f->n0 = n0; f->n_try = n_try; f->L = L; f->H = H;
-    f->prec = prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
+    f->prec = prec; f->tile_prec = p->dist_prec; f->dp = dp; f->device = dev; f->leaves = leaves; f->max_leaf = max_leaf;
     f->bytes = bytes - (xc_eager ? 0 : xc_bytes);
     f->batch = roots;
 
@@ -1257,7 +1259,7 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
     out->leaf_size = f->n0;
     out->n_try = f->n_try;
     out->depth = f->L;
-    out->dist_prec = f->prec;
+    out->dist_prec = f->tile_prec;
     out->n_leaves = (int64_t)f->leaves.size();
     out->device_bytes = f->bytes;
     out->batch_count = (int32_t)f->batch.size();
@@ -1310,6 +1312,7 @@ ForestView view(const rpf_forest *f) {
     ForestView v;
     v.n = f->n; v.H = f->H; v.d = f->d; v.T = f->T; v.n0 = f->n0; v.n_try = f->n_try; v.L = f->L;
     v.prec = f->prec; v.dp = f->dp; v.max_leaf = f->max_leaf; v.job_mb = f->job_mb;
+    v.sym_prec = f->tile_prec;
     v.X = f->X; v.R = f->R; v.centroid = f->centroid; v.split = f->split; v.chosen = f->chosen;
     v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
     v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;

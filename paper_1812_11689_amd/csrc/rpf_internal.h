@@ -133,6 +133,7 @@ struct TileJob {       // one MFMA tile: A rows x B rows (<= 32*MB each) of one 
 struct ForestView {
     int64_t n, H;
     int d, T, n0, n_try, L, prec, dp, max_leaf, job_mb;
+    int sym_prec;  // precision of the all-points symmetric tiles (prec, or split bfloat16 over binary32)
     const float *X, *R, *centroid;
     const double *split;
     const int32_t *chosen, *perm, *leaf_of, *heap_leaf;

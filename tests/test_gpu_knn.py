@@ -72,6 +72,16 @@ ALL = [
     # leaves of exactly 256 points, the largest the symmetric tile takes
     ("leaves256_fp32", 8192, 64, 9, 256, 12, "fp32", "mixture", 0, 1),
     ("leaves256_fp16_self", 8192, 64, 9, 256, 12, "fp16", "mixture", 0, 0),
+    # split bfloat16 tiles (hi/lo bf16 MFMA over binary32 copies), at every tile shape
+    ("split_leaves244", 7800, 128, 8, 256, 20, "bf16x3", "aniso", 0, 1),
+    ("split_leaves244_self", 7800, 128, 8, 256, 20, "bf16x3", "aniso", 0, 0),
+    ("split_leaves256", 8192, 64, 9, 256, 12, "bf16x3", "mixture", 0, 1),
+    ("split_mixture_10k", 10_000, 16, 6, 50, 10, "bf16x3", "mixture", 0, 1),
+    ("split_d33", 4000, 33, 5, 40, 7, "bf16x3", "mixture", 0, 1),
+    ("split_wide_exponents", 3000, 24, 5, 50, 6, "bf16x3", "wide", 0, 1),
+    ("split_duplicates", 6000, 8, 5, 30, 8, "bf16x3", "mixture", 5, 1),
+    ("split_big_k", 12000, 16, 12, 200, 100, "bf16x3", "mixture", 0, 1),
+    ("split_big_leaves", 6000, 12, 6, 300, 8, "bf16x3", "mixture", 0, 1),
 ]
 
 
@@ -127,6 +137,7 @@ QUERY = [
     # leaves of 243/244 points, as in the 4M x 96 served forest
     ("q_leaves244_fp16", 7800, 96, 8, 256, 10, "fp16", 3000),
     ("q_leaves244_bf16", 7800, 96, 8, 256, 100, "bf16", 800),
+    ("q_split_forest", 12_000, 96, 5, 256, 20, "bf16x3", 1000),
 ]
 
 
