@@ -54,7 +54,21 @@ typedef enum { RPF_SPLIT_MEDIAN = 0 } rpf_split;
  * precision, the returned neighbours are the exact top-K of the leaf union under the
  * binary64 ranking: tile distances only prune, with rigorous error bounds, and the
  * surviving candidates are re-ranked in binary32 and, near the K-th distance, binary64. */
-typedef enum { RPF_DIST_FP32 = 0, RPF_DIST_BF16 = 1, RPF_DIST_FP16 = 2, RPF_DIST_BF16X3 = 3 } rpf_dist_prec;
+typedef enum {
+    RPF_DIST_FP32 = 0,
+    RPF_DIST_BF16 = 1,
+    RPF_DIST_FP16 = 2,
+    RPF_DIST_BF16X3 = 3,
+    RPF_DIST_U8GRID = 4
+} rpf_dist_prec;
+/* RPF_DIST_U8GRID: for points on the 1/255 grid (every coordinate is float(k) / 255.0f for
+ * an integer k in [0, 255], as 8-bit image data scaled to [0, 1]); rpf_build returns
+ * RPF_EINVAL otherwise.  The build keeps an int8 copy k - 128 of the points, and the
+ * all-points tiles form the exact integer Gram product on the int8 MFMA: the grid distance
+ * sum (k_a - k_b)^2 is exact, and the pruning bounds differ from it only by the binary32
+ * rounding of k / 255, so almost every candidate is decided before the re-rank.  Like
+ * RPF_DIST_BF16X3 the forest otherwise holds binary32 copies and norms, and rpf_query runs
+ * the binary32 tiles (queries need not lie on the grid). */
 /* RPF_DIST_BF16X3: the forest holds binary32 copies and norms (as RPF_DIST_FP32, and
  * rpf_query runs the binary32 tiles), but the all-points tiles split every centred binary32
  * value a into hi = bf16(a) and lo = bf16(a - hi) and form the Gram product on bfloat16

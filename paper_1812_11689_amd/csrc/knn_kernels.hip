@@ -487,6 +487,240 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     flush(qc);
 }
 
+// ---------------------------------------------------------------- tiles on the 1/255 grid
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+constexpr int kQ8KC = 64;   // int8 columns staged per chunk
+constexpr int kQ8LDW = 80;  // LDS row stride in bytes (16-byte aligned, padded against bank conflicts)
+
+// Bounds on the binary64 squared distance of two grid points from their exact grid distance
+// dint = sum (k_a - k_b)^2.  With q = k / 255 and each coordinate x = q (1 + e), |e| <= 2^-24
+// (one correctly rounded division), the real distance of the binary32 points is within
+// 2^-24 (|q_a| + |q_b|) of sqrt(dint) / 255; dint / 255^2 in binary32 is off by at most 3
+// roundings (2^-24 each); the 1e-6 widening covers the square roots' roundings and the
+// binary64 canonical sum.
+__device__ inline void lattice_bounds(int32_t dint, float ra, float rb, float &lb, float &ub) {
+    constexpr float u = 5.9604645e-8f;  // 2^-24
+    const float dt = (float)dint * (1.f / 65025.f);
+    const float delta = u * 1.01f * (ra + rb);
+    const float lo = fmaxf(sqrtf(dt * (1.f - 4.f * u)) - delta, 0.f);
+    const float hi = sqrtf(dt * (1.f + 4.f * u)) + delta;
+    lb = fminf(lo * lo * (1.f - 1e-6f), 3.40282347e38f);
+    ub = hi * hi * (1.f + 1e-6f);
+}
+
+// Integer threshold of the cheap test of a row: lb <= tau(row) implies
+// dint <= phi_d = (sqrt(tau / (1 - 1e-6)) + delta_max)^2 * 255^2 / ((1 - 4u)(1 - 3u)), taken with
+// slack upward; returned as phi_d - |k_row - 128|^2 so that the test reads |k_col - 128|^2 - 2G <= phi.
+__device__ inline int32_t lattice_phi(float tv, int32_t na, float ra, float rbmax) {
+    if (!(tv < INFINITY)) return INT32_MAX;
+    if (tv < 0.f) return INT32_MIN;
+    constexpr float u = 5.9604645e-8f;
+    const float st = sqrtf(tv / (1.f - 1e-6f)) + u * 1.01f * (ra + rbmax);
+    const double pd = (double)st * (double)st * 65025.0 * (1.0 + 1e-5) + 2.0;
+    const double ph = pd - (double)na;
+    return ph >= 2.0e9 ? INT32_MAX : (int32_t)ph;
+}
+
+// All-points tile of grid points (one job: A rows x B rows of one leaf, MB waves; wave w owns
+// A rows [32w, 32w + 32)): rows are gathered from the int8 copy through the permutation, the
+// integer Gram product runs on v_mfma_i32_32x32x32_i8, and the grid distance
+// |k_a - 128|^2 + |k_b - 128|^2 - 2G is exact.  Outputs as the other tiles (Phase I slots,
+// Phase II records below the row's threshold).
+template <int MB>
+__global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__ jobs, const int8_t *__restrict__ Xq,
+                                                    int dq, const LatNorm *__restrict__ qn,
+                                                    const int32_t *__restrict__ perm, int64_t n, int exclude_self,
+                                                    TileOut out) {
+    constexpr int M = 32 * MB;
+    constexpr int NT = 64 * MB;
+    __shared__ __align__(16) int8_t s_a[M * kQ8LDW];
+    __shared__ __align__(16) int8_t s_b[M * kQ8LDW];
+    __shared__ int32_t s_na[M], s_nb[M], s_phi[M];
+    __shared__ float s_ra[M], s_rb[M], s_tau[M];
+    __shared__ int32_t s_dst[M], s_bpt[M];
+    __shared__ float s_rbmax;
+    __shared__ uint2 s_que[MB][kQueue];
+
+    const TileJob job = jobs[blockIdx.x];
+    const int t = job.tree;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const bool same = job.same != 0;
+    const int32_t *ap = perm + (int64_t)t * n + job.a_off;
+    const int32_t *bp = perm + (int64_t)t * n + job.b_off;
+    const int tb = t - out.t0;
+    for (int r = tid; r < M; r += NT) {
+        if (r < job.a_rows) {
+            const int p = ap[r];
+            const LatNorm q = qn[p];
+            s_dst[r] = p;
+            s_na[r] = q.na;
+            s_ra[r] = q.ra;
+            s_tau[r] = out.mode == 1 ? out.tau[p] : INFINITY;
+        } else {
+            s_dst[r] = -1;
+            s_na[r] = 0;
+            s_ra[r] = 0.f;
+            s_tau[r] = -1.f;
+        }
+        if (r < job.b_rows) {
+            const int p = bp[r];
+            const LatNorm q = qn[p];
+            s_bpt[r] = p;
+            s_nb[r] = q.na;
+            s_rb[r] = q.ra;
+        } else {
+            s_bpt[r] = -1;
+            s_nb[r] = 0;
+            s_rb[r] = 0.f;
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        float mr = 0.f;
+        for (int r = lane; r < job.b_rows; r += 64) mr = fmaxf(mr, s_rb[r]);
+        for (int o = 32; o > 0; o >>= 1) mr = fmaxf(mr, __shfl_xor(mr, o, 64));
+        if (lane == 0) s_rbmax = mr;
+    }
+    __syncthreads();
+    for (int r = tid; r < M; r += NT) s_phi[r] = lattice_phi(s_tau[r], s_na[r], s_ra[r], s_rbmax);
+    if (out.mode == 0) {  // Phase I: the slots no pair of this tile fills (past the leaf, self)
+        const bool last = job.b_pos + job.b_rows == job.leaf_m;
+        for (int r = tid; r < job.a_rows; r += NT) {
+            const int64_t er = (int64_t)s_dst[r] * out.cap + (int64_t)tb * out.ML;
+            if (last) {
+                for (int c = job.leaf_m; c < out.ML; c++) put_first_empty(out, er + c);
+                out.roff[(int64_t)tb * out.nrows + s_dst[r]] = (int32_t)(job.b_off - job.b_pos);
+            }
+            if (same && exclude_self) put_first_empty(out, er + job.b_pos + r);
+        }
+    }
+
+    i32x16 acc[MB];
+#pragma unroll
+    for (int cb = 0; cb < MB; cb++)
+#pragma unroll
+        for (int v = 0; v < 16; v++) acc[cb][v] = 0;
+    const int nbb = (job.b_rows + 31) >> 5;
+    const bool active = 32 * wu < job.a_rows;
+    const int fr = lane & 31;
+    const int fk = 16 * (lane >> 5);  // the lane's 16 consecutive int8 of the 32-column step
+    const int a_pad = ((job.a_rows + 31) >> 5) << 5;
+    const int b_pad = nbb << 5;
+    constexpr int VPR = kQ8KC / 16;  // 16-byte vectors per staged row chunk
+    for (int k0 = 0; k0 < dq; k0 += kQ8KC) {
+        __syncthreads();
+        for (int v = tid; v < a_pad * VPR; v += NT) {
+            const int r = v / VPR, c = (v % VPR) * 16;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (r < job.a_rows) val = *reinterpret_cast<const uint4 *>(Xq + (int64_t)s_dst[r] * dq + k0 + c);
+            *reinterpret_cast<uint4 *>(s_a + r * kQ8LDW + c) = val;
+        }
+        if (!same)
+            for (int v = tid; v < b_pad * VPR; v += NT) {
+                const int r = v / VPR, c = (v % VPR) * 16;
+                uint4 val = make_uint4(0, 0, 0, 0);
+                if (r < job.b_rows) val = *reinterpret_cast<const uint4 *>(Xq + (int64_t)s_bpt[r] * dq + k0 + c);
+                *reinterpret_cast<uint4 *>(s_b + r * kQ8LDW + c) = val;
+            }
+        __syncthreads();
+        const int8_t *sb_base = same ? s_a : s_b;
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < kQ8KC; kk += 32) {
+                const i32x4 fa = *reinterpret_cast<const i32x4 *>(s_a + (32 * wu + fr) * kQ8LDW + kk + fk);
+#pragma unroll
+                for (int cb = 0; cb < MB; cb++) {
+                    if (cb < nbb) {
+                        const i32x4 fb = *reinterpret_cast<const i32x4 *>(sb_base + (32 * cb + fr) * kQ8LDW + kk + fk);
+                        acc[cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fb, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    if (!active) return;
+
+    if (out.mode == 0) {
+#pragma unroll
+        for (int cb = 0; cb < MB; cb++) {
+            if (cb >= nbb) continue;
+            const int col = 32 * cb + (lane & 31);
+            if (col >= job.b_rows) continue;
+            const int32_t nb = s_nb[col];
+            const float rb = s_rb[col];
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (row >= job.a_rows || (same && exclude_self && row == col)) continue;
+                float lb, ub;
+                lattice_bounds(s_na[row] + nb - 2 * acc[cb][v], s_ra[row], rb, lb, ub);
+                put_first(out, (int64_t)s_dst[row] * out.cap + (int64_t)tb * out.ML + job.b_pos + col, lb, ub);
+            }
+        }
+        return;
+    }
+    // Phase II: the integer cheap test over every pair; passing pairs are compacted into a
+    // per-wave LDS queue and get their exact bounds when it would overflow and at the end
+    uint2 *que = s_que[wu];
+    uint32_t qc = 0;
+    auto flush = [&](uint32_t nq) {
+        wave_sync();
+        for (uint32_t i = lane; i < nq; i += 64) {
+            const uint2 e = que[i];
+            const int row = e.x & 255, col = (e.x >> 8) & 255;
+            float lb, ub;
+            lattice_bounds(s_na[row] + s_nb[col] - 2 * (int32_t)e.y, s_ra[row], s_rb[col], lb, ub);
+            if (lb <= s_tau[row]) emit_filtered(out, s_dst[row], s_bpt[col], lb, ub);
+        }
+        wave_sync();
+    };
+    int32_t pr[16];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int4 p4 = *reinterpret_cast<const int4 *>(s_phi + 32 * wu + 8 * j + 4 * (lane >> 5));
+        pr[4 * j] = p4.x; pr[4 * j + 1] = p4.y; pr[4 * j + 2] = p4.z; pr[4 * j + 3] = p4.w;
+    }
+#pragma unroll
+    for (int cb = 0; cb < MB; cb++) {
+        if (cb >= nbb) continue;
+        const int col = 32 * cb + (lane & 31);
+        const bool colok = col < job.b_rows;
+        const int32_t nb = s_nb[col];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            uint32_t bits = 0;
+            uint64_t mk[8];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int v8 = 0; v8 < 8; v8++) {
+                const int v = 8 * h + v8;
+                const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const bool p = colok & (nb - 2 * acc[cb][v] <= pr[v]) & !(same & (exclude_self != 0) & (row == col));
+                bits |= (p ? 1u : 0u) << v8;
+                mk[v8] = __ballot(p);
+                tot += (uint32_t)__popcll(mk[v8]);
+            }
+            if (qc + tot > (uint32_t)kQueue) {
+                flush(qc);
+                qc = 0;
+            }
+#pragma unroll
+            for (int v8 = 0; v8 < 8; v8++) {
+                const int v = 8 * h + v8;
+                if ((bits >> v8) & 1u) {
+                    const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    que[qc + mask_rank(mk[v8])] = make_uint2((uint32_t)row | ((uint32_t)col << 8), (uint32_t)acc[cb][v]);
+                }
+                qc += (uint32_t)__popcll(mk[v8]);
+            }
+        }
+    }
+    flush(qc);
+}
+
 // All-points tile of one leaf whose rows all fit (m <= 32 NB): the Gram matrix is symmetric,
 // so only blocks (i, j) with i <= j run on MFMA and an off-diagonal block serves both
 // (row -> col) and (col -> row).  Block rows p and NB-1-p form a pair of NB + 1 blocks,
@@ -2129,6 +2363,7 @@ struct Workspace {
 
 // common candidate stage once the tile jobs, A rows and per-row metadata are known
 struct CandStage {
+    bool all_points = false;  // rows are the forest's points (Q = U)
     int64_t rows;          // number of result rows (n or m)
     const TileJob *jobs0;  // Phase I jobs (first tree)
     const TileJob *jobs1;  // Phase II jobs (other trees)
@@ -2362,9 +2597,22 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     o1.plub = plub;
     o1.roff = roff;
     o1.nrows = rows;
+    const bool grid = v.sym_prec == RPF_DIST_U8GRID && cs.all_points;
+    auto grid_launch = [&](const TileJob *jobs, int64_t njobs, const TileOut &o) {
+        if (njobs <= 0) return;
+        switch (v.job_mb) {
+            case 1: hipLaunchKernelGGL(k_tile_q8<1>, dim3((unsigned)njobs), dim3(64), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            case 2: hipLaunchKernelGGL(k_tile_q8<2>, dim3((unsigned)njobs), dim3(128), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            case 4: hipLaunchKernelGGL(k_tile_q8<4>, dim3((unsigned)njobs), dim3(256), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            default: hipLaunchKernelGGL(k_tile_q8<8>, dim3((unsigned)njobs), dim3(512), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+        }
+        launch_check(s, "k_tile_q8");
+    };
     {
         ProfScope ps(s, "tile_phase1", cs.bytes0, cs.flops0);
-        if (cs.sym)
+        if (grid)
+            grid_launch(cs.jobs0, cs.njobs0, o1);
+        else if (cs.sym)
             sym_dispatch(v.sym_prec, MB, s, cs.njobs0, cs.jobs0, sym_src(v), v.nrm, v.perm, bc_sym, cs.excl, o1);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs0, cs.jobs0, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
@@ -2399,7 +2647,9 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         o2.tau = tau;
         o2.ent = ent;
         ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
-        if (cs.sym)
+        if (grid)
+            grid_launch(cs.jobs1, cs.njobs1, o2);
+        else if (cs.sym)
             sym_dispatch(v.sym_prec, MB, s, cs.njobs1, cs.jobs1, sym_src(v), v.nrm, v.perm, bc_sym, cs.excl, o2);
         else
             tile_dispatch(v.prec, MB, s, cs.njobs1, cs.jobs1, cs.A, v.Xc, v.dp, cs.a_stride, v.n, cs.a_nrm, v.nrm,
@@ -2517,13 +2767,18 @@ static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, 
     cs.bytes0 = (double)v.n * v.dp * esz * cs.B;
     cs.bytes1 = (double)v.n * v.dp * esz * (v.T - cs.B);
     cs.sym = v.max_leaf <= 32 * v.job_mb;  // every leaf is a single diagonal tile
+    cs.all_points = true;
+    if (v.sym_prec == RPF_DIST_U8GRID) {  // int8 rows
+        cs.bytes0 = (double)v.n * v.dq * cs.B;
+        cs.bytes1 = (double)v.n * v.dq * (v.T - cs.B);
+    }
     return cs;
 }
 
 rpf_status knn_all(const rpf_forest *f, int K, int exclude_self, int32_t *out_idx, float *out_dist, hipStream_t s) {
     ForestView v = view(f);
     const CandStage cs = all_points_stage(v, K, exclude_self);
-    if (!cs.sym && !v.Xc) {  // leaves of more than one tile read the centred copy
+    if (!cs.sym && !v.Xc && v.sym_prec != RPF_DIST_U8GRID) {  // leaves of more than one tile read the centred copy
         const rpf_status st = ensure_leaf_copies(f, s);
         if (st != RPF_OK) return st;
         v = view(f);

@@ -225,6 +225,61 @@ void launch_copy_nonfinite(hipStream_t s, const float *src, float *dst, int64_t 
         hipLaunchKernelGGL(k_copy_nonfinite<false>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count, flag);
 }
 
+// Points on the 1/255 grid: for each coordinate x, k = rint(255 x) must lie in [0, 255] with
+// float(k) / 255.0f == x (so -0 counts as k = 0); the row is stored as int8 k - 128 (zero from
+// d to dq) with |k - 128|^2 (exact) and |k| / 255.  One wave per row; any coordinate off the
+// grid sets *flag.
+__global__ __launch_bounds__(256) void k_grid_quantise(const float *__restrict__ X, int64_t n, int d, int dq,
+                                                       int8_t *__restrict__ Xq, LatNorm *__restrict__ qn,
+                                                       int32_t *__restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    int32_t na = 0, kk = 0;
+    bool ok = true;
+    for (int c = lane; c < dq; c += 64) {
+        int v = 0;
+        if (c < d) {
+            const float x = X[row * d + c];
+            const int k = (int)rintf(x * 255.f);
+            ok &= k >= 0 && k <= 255 && (float)k / 255.f == x;
+            const int kc = k < 0 ? 0 : k > 255 ? 255 : k;
+            v = kc - 128;
+            na += v * v;
+            kk += kc * kc;
+        }
+        Xq[row * dq + c] = (int8_t)v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        na += __shfl_xor(na, o, 64);
+        kk += __shfl_xor(kk, o, 64);
+    }
+    if (lane == 0) qn[row] = LatNorm{na, sqrtf((float)kk) / 255.f};
+    if (__ballot(!ok) && lane == 0) atomicOr(flag, 1);
+}
+
+// leaf_of alone: the heap id of every point's leaf, from the leaf table and the final order
+__global__ __launch_bounds__(256) void k_leaf_ids(const LeafDesc *__restrict__ leaves, const int32_t *__restrict__ perm,
+                                                  int64_t n, int32_t *__restrict__ leaf_of) {
+    const LeafDesc lf = leaves[blockIdx.x];
+    const int64_t t = blockIdx.y;
+    for (int i = threadIdx.x; i < lf.size; i += blockDim.x)
+        leaf_of[t * n + perm[t * n + lf.off + i]] = lf.heap;
+}
+
+void launch_leaf_ids(hipStream_t s, const LeafDesc *leaves, int nleaf, int T, const int32_t *perm, int64_t n,
+                     int32_t *leaf_of) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_leaf_ids, dim3((unsigned)nleaf, (unsigned)T), dim3(256), 0, s, leaves, perm, n, leaf_of);
+}
+
+void launch_grid_quantise(hipStream_t s, const float *X, int64_t n, int d, int dq, int8_t *Xq, LatNorm *qn,
+                          int32_t *flag) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_grid_quantise, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, dq, Xq, qn, flag);
+    launch_check(s, "k_grid_quantise");
+}
+
 }  // namespace rpf
 
 using namespace rpf;
@@ -248,6 +303,9 @@ struct rpf_forest {
     int64_t n = 0;
     int32_t d = 0, T = 0, n0 = 0, n_try = 0, L = 0, prec = 0, dp = 0;
     int32_t tile_prec = 0;  // as asked (rpf_dist_prec); prec is that of the copies and norms
+    int8_t *Xq = nullptr;       // grid forests: [n][dq] int8 k - 128
+    rpf::LatNorm *qn = nullptr; // grid forests: [n]
+    int32_t dq = 0;
     int64_t H = 0;
     int device = 0;
     // persistent device arrays
@@ -395,7 +453,7 @@ static void pin_give(int k) {
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
-                    f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off};
+                    f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off, f->Xq, f->qn};
     for (void *p : ptrs) cache_free_idle(p);
     pin_give(f->pin_slot);
     f->pin_slot = -1;
@@ -439,7 +497,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
     if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
     if (p->split_rule != RPF_SPLIT_MEDIAN) return fail(RPF_EINVAL, "rpf_build: only the median split rule is implemented");
-    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_BF16X3)
+    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_U8GRID)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
     if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
     std::vector<rpf_batch_entry> roots(count);
@@ -547,8 +605,11 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
         }
 
     // ---- memory plan
-    // split bfloat16 tiles run over binary32 copies and norms: the forest is a binary32 one
-    const int prec = p->dist_prec == RPF_DIST_BF16X3 ? RPF_DIST_FP32 : p->dist_prec;
+    // split bfloat16 and int8 grid tiles run beside binary32 copies and norms: the forest is a
+    // binary32 one
+    const bool grid = p->dist_prec == RPF_DIST_U8GRID;
+    const int prec = (p->dist_prec == RPF_DIST_BF16X3 || grid) ? RPF_DIST_FP32 : p->dist_prec;
+    const int dq = grid ? (d + 63) & ~63 : 0;
     const int dp = (d + 7) & ~7;
     const size_t esz = prec == RPF_DIST_FP32 ? 4 : 2;
     const int64_t nleaf = (int64_t)leaves.size();
@@ -556,7 +617,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     for (auto &lf : leaves) max_leaf = std::max(max_leaf, (int)lf.size);
     // the all-points search stages leaves of one tile (at most 256 points) straight from X;
     // larger leaves read the leaf-ordered centred copy, made here; queries make it on first use
-    const bool xc_eager = max_leaf > 256;
+    const bool xc_eager = max_leaf > 256 && !grid;  // grid tiles read the int8 copy
     const uint64_t xc_bytes = (uint64_t)T * n * dp * esz;
     uint64_t bytes = 0;
     bytes += (uint64_t)n * d * 4;                        // X
@@ -615,6 +676,12 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     RPF_ALLOC(f->centroid, (size_t)T * nleaf * d * 4);
     if (xc_eager) RPF_ALLOC(f->Xc, (size_t)xc_bytes);
     RPF_ALLOC(f->nrm, (size_t)T * n * 8);
+    if (grid) {
+        RPF_ALLOC(f->Xq, (size_t)n * dq);
+        RPF_ALLOC(f->qn, (size_t)n * sizeof(LatNorm));
+        f->dq = dq;
+        f->bytes += (size_t)n * dq + (size_t)n * sizeof(LatNorm);
+    }
     RPF_ALLOC(f->err, 64);
     RPF_ALLOC(f->stats, kStatSlots * 8 * 8 + 256);
     f->fault = f->stats + kStatSlots * 8;
@@ -790,6 +857,13 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
         launch_leaf_finalize(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of,
                              f->centroid, f->Xc, f->nrm, f->max_leaf, f->lds_max);
         launch_check(s, "leaf_finalize");
+    } else if (f->Xq && f->max_leaf > 256) {
+        // grid forest with leaves above one tile: the all-points tiles read the int8 copy and
+        // its norms; leaf_of is all they need.  Centroids, norms and the query copies are made
+        // together by the first query (rpf::ensure_leaf_copies)
+        ProfScope ps(s, "leaf_finalize", (double)T * n * 12.0, 0);
+        launch_leaf_ids(s, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of);
+        launch_check(s, "leaf_ids");
     } else {  // centroids and norms only: the tiles centre the rows as they stage them
         ProfScope ps(s, "leaf_finalize", (double)T * n * (4.0 * d + 16), 0);
         launch_leaf_stats(s, prec, f->X, d, dp, f->d_leaves, (int)nleaf, T, f->perm[cur], n, f->leaf_of, f->centroid,
@@ -813,8 +887,12 @@ rpf_status rpf::ensure_leaf_copies(const rpf_forest *cf, hipStream_t s, bool may
     const size_t bytes = (size_t)f->T * f->n * f->dp * (f->prec == RPF_DIST_FP32 ? 4 : 2);
     void *p = cache_alloc(bytes, s);
     if (!p) return fail(RPF_ENOMEM, "device allocation of the forest's query copies failed");
-    launch_leaf_copy(s, f->prec, f->X, f->d, f->dp, f->d_leaves, (int)f->leaves.size(), f->T, f->perm[f->final_buf],
-                     f->n, f->centroid, p);
+    if (f->Xq && f->max_leaf > 256)  // grid forest: centroids and norms were left to this call
+        launch_leaf_finalize(s, f->prec, f->X, f->d, f->dp, f->d_leaves, (int)f->leaves.size(), f->T,
+                             f->perm[f->final_buf], f->n, f->leaf_of, f->centroid, p, f->nrm, f->max_leaf, f->lds_max);
+    else
+        launch_leaf_copy(s, f->prec, f->X, f->d, f->dp, f->d_leaves, (int)f->leaves.size(), f->T,
+                         f->perm[f->final_buf], f->n, f->centroid, p);
     const std::string le = take_launch_error();
     if (!le.empty()) {
         cache_free(p, s);
@@ -863,12 +941,18 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
     fill_u32(f->stats, kStatSlots * 8 * 2, 0, s);
     launch_copy_nonfinite(s, X, f->X, n * d, f->err);
     if (H > 0) launch_copy_nonfinite(s, p->directions_dev, f->R, T * H * n_try * d, f->err + 1);
+    if (f->Xq) launch_grid_quantise(s, f->X, n, d, f->dq, f->Xq, f->qn, f->err + 4);
     launch_check(s, "input copy and check");
-    int32_t flags[2] = {0, 0};
-    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 8, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
+    int32_t flags[5] = {0, 0, 0, 0, 0};
+    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 20, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
     if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);
     if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
     if (flags[1]) { fail(RPF_EINVAL, "rpf_build: directions hold NaN or Inf"); return bail(RPF_EINVAL); }
+    if (flags[4]) {
+        fail(RPF_EINVAL, "rpf_build: RPF_DIST_U8GRID needs every coordinate of X to be float(k) / 255 for an integer "
+                         "k in [0, 255]");
+        return bail(RPF_EINVAL);
+    }
     fill_u32(f->err, 16, 0, s);
     build_launches(f, s);
     release_temporaries(f, s);
@@ -954,6 +1038,7 @@ static rpf_status plan_record(rpf_plan *pl) {
         fill_u32(f->err, 16, 0, c);
         launch_nonfinite(c, f->X, f->n * f->d, f->err + 2);
         launch_nonfinite(c, f->R, (int64_t)f->T * f->H * f->n_try * f->d, f->err + 3);
+        if (f->Xq) launch_grid_quantise(c, f->X, f->n, f->d, f->dq, f->Xq, f->qn, f->err + 4);
         build_launches(f, c);
         knn_part_launch(pl->knn, f, pt.B, pt.out_idx, pt.out_dist, c);
         if (pt.sets.size() > 1) launch_localize(pt.out_idx, f->n, pl->K, f->d_batch_off, (int)pt.sets.size(), c);
@@ -1094,16 +1179,18 @@ rpf_status rpf_plan_launch(rpf_plan *pl, void *stream) {
 
 rpf_status rpf_plan_check(rpf_plan *pl, void *stream) {
     if (!pl) return fail(RPF_EINVAL, "rpf_plan_check: NULL plan");
-    std::vector<int32_t> flags(4 * pl->parts.size(), 0);
+    std::vector<int32_t> flags(5 * pl->parts.size(), 0);
     for (size_t k = 0; k < pl->parts.size(); k++)
-        hipMemcpyAsync(&flags[4 * k], pl->parts[k].f->err, 16, hipMemcpyDeviceToHost, (hipStream_t)stream);
+        hipMemcpyAsync(&flags[5 * k], pl->parts[k].f->err, 20, hipMemcpyDeviceToHost, (hipStream_t)stream);
     const rpf_status st = check_hip(hipStreamSynchronize((hipStream_t)stream), "rpf_plan_check");
     if (st != RPF_OK) return st;
     for (size_t k = 0; k < pl->parts.size(); k++) {
-        if (flags[4 * k + 2]) return fail(RPF_EINVAL, "rpf_plan_check: X holds NaN or Inf (part " + std::to_string(k) + ")");
-        if (flags[4 * k + 3])
+        if (flags[5 * k + 2]) return fail(RPF_EINVAL, "rpf_plan_check: X holds NaN or Inf (part " + std::to_string(k) + ")");
+        if (flags[5 * k + 3])
             return fail(RPF_EINVAL, "rpf_plan_check: directions hold NaN or Inf (part " + std::to_string(k) + ")");
-        if (flags[4 * k]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[4 * k]));
+        if (flags[5 * k + 4])
+            return fail(RPF_EINVAL, "rpf_plan_check: X is off the 1/255 grid (part " + std::to_string(k) + ")");
+        if (flags[5 * k]) return fail(RPF_EINTERNAL, "rpf_plan_check: build kernels flagged error " + std::to_string(flags[5 * k]));
         if (const uint64_t flt = forest_fault_read(pl->parts[k].f, (hipStream_t)stream))
             return fail(RPF_EINTERNAL, "rpf_plan_check: " + std::to_string(flt) + " rows of part " + std::to_string(k) +
                                            " met a candidate index outside the data set");
@@ -1313,6 +1400,7 @@ ForestView view(const rpf_forest *f) {
     v.n = f->n; v.H = f->H; v.d = f->d; v.T = f->T; v.n0 = f->n0; v.n_try = f->n_try; v.L = f->L;
     v.prec = f->prec; v.dp = f->dp; v.max_leaf = f->max_leaf; v.job_mb = f->job_mb;
     v.sym_prec = f->tile_prec;
+    v.Xq = f->Xq; v.qn = f->qn; v.dq = f->dq;
     v.X = f->X; v.R = f->R; v.centroid = f->centroid; v.split = f->split; v.chosen = f->chosen;
     v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
     v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;

@@ -76,6 +76,11 @@ struct Ent {           // one pruning candidate: point index and bounds on its s
 };
 
 
+struct LatNorm {       // a point on the 1/255 grid: |k - 128|^2 (exact) and |k| / 255
+    int32_t na;
+    float ra;
+};
+
 struct Cand {          // a key gathered for the in-block median select
     uint64_t hi;
     uint32_t lo;
@@ -133,7 +138,10 @@ struct TileJob {       // one MFMA tile: A rows x B rows (<= 32*MB each) of one 
 struct ForestView {
     int64_t n, H;
     int d, T, n0, n_try, L, prec, dp, max_leaf, job_mb;
-    int sym_prec;  // precision of the all-points symmetric tiles (prec, or split bfloat16 over binary32)
+    int sym_prec;  // precision of the all-points tiles (prec, split bfloat16 or the int8 grid over binary32)
+    const int8_t *Xq;     // grid forests: [n][dq] k - 128 (zero past d)
+    const LatNorm *qn;    // grid forests: [n]
+    int dq;
     const float *X, *R, *centroid;
     const double *split;
     const int32_t *chosen, *perm, *leaf_of, *heap_leaf;

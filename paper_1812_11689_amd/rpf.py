@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librpf.so")
 RPF_OK, RPF_EINVAL, RPF_ENOMEM, RPF_EDEVICE, RPF_EBUSY, RPF_ENOTREADY, RPF_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {0: "RPF_OK", -1: "RPF_EINVAL", -2: "RPF_ENOMEM", -3: "RPF_EDEVICE", -4: "RPF_EBUSY",
            -5: "RPF_ENOTREADY", -6: "RPF_EINTERNAL"}
-PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "u8grid": 4}
 
 EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "rpf_free", "rpf_tree_dump",
            "rpf_forest_info", "rpf_last_knn_stats", "rpf_profile_enable", "rpf_profile_reset",

@@ -6,8 +6,9 @@
     distances within 1e-5 relative;
   - the served forest, 4 * 10^6 x 96, T 64, n0 256, float16 tiles: 5 000 mixture queries (5 %
     uniform outliers) at K 1, 10 and 100;
-  - 10^5 x 784 quantised (70 % zeros, 1/255 grid), T 48, n0 512, bfloat16 tiles: leaves of
-    390/391 points take the copied-leaf tiles; the whole build and kNN on 5 000 sampled rows.
+  - 10^5 x 784 quantised (70 % zeros, 1/255 grid), T 48, n0 512, bfloat16 tiles (leaves of
+    390/391 points take the copied-leaf tiles) and int8 grid tiles: the whole build and kNN on
+    5 000 sampled rows.
 
 The oracle runs on the host cores (OpenMP); these cases take about a minute each."""
 
@@ -107,14 +108,15 @@ def test_4M_d96_T64_served_queries():
     f.free()
 
 
-def test_100k_d784_T48_quantised_bf16():
+@pytest.mark.parametrize("prec", ["bf16", "u8grid"])
+def test_100k_d784_T48_quantised(prec):
     n, d, T, n0, K = 100_000, 784, 48, 512, 10
     x = W.sparse_quantized(W.SEED_BASE + 3, n, d)
     L = oracle.depth(n, n0)
-    print(f"[fullsize] quantised n={n} d={d} T={T} n0={n0} K={K} L={L} bf16", flush=True)
+    print(f"[fullsize] quantised n={n} d={d} T={T} n0={n0} K={K} L={L} {prec}", flush=True)
     R = W.directions(W.SEED_BASE + 103, T, (1 << L) - 1, 1, d)
     ref = oracle.build_forest(x, R, T, n0)
-    f = _build(x, R, T, n0, "bf16")
+    f = _build(x, R, T, n0, prec)
     _check_trees(f, ref, T)
     print(f"    {T} trees bit-exact", flush=True)
     pts = _sample(W.SEED_BASE + 303, n, 5000)
@@ -124,6 +126,6 @@ def test_100k_d784_T48_quantised_bf16():
     st = f.knn_stats()
     print(f"    stats {st}", flush=True)
     sel = torch.from_numpy(pts).cuda().long()
-    _compare(gi[sel].cpu().numpy(), gd[sel].cpu().numpy(), ri, rd, "all_knn bf16 quantised")
+    _compare(gi[sel].cpu().numpy(), gd[sel].cpu().numpy(), ri, rd, f"all_knn {prec} quantised")
     print("    all_knn sample matches", flush=True)
     f.free()
