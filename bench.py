@@ -52,6 +52,7 @@ BUILD_KERNELS = ("k_proj_root", "k_proj_chunks", "k_level_small", "k_sel_", "k_p
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+INT8_MFMA_PEAK_TOPS = 5000.0
 
 
 def parse():
@@ -88,6 +89,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
     ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="points whose all-points kNN the CPU baseline times (extrapolated to n)")
+    ap.add_argument("--headline-prec", default="bf16x3", choices=["bf16x3", "bf16", "fp16"],
+                    help="tile precision of the headline (low-precision + re-rank) path")
     ap.add_argument("--target-recall", type=float, default=0.99,
                     help="recall the at-target leg looks for by growing more trees (0 = skip the leg)")
     ap.add_argument("--target-trees", default="48,64,80,96,128",
@@ -95,6 +98,16 @@ def parse():
     ap.add_argument("--cpu-trees", type=int, default=0,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
     return ap.parse_args()
+
+
+def mfma_peak(prec):
+    """Dense MFMA peak of the tile arithmetic: bf16 for bfloat16 and split bfloat16 tiles (the
+    algorithmic flops count the plain product once), int8 for grid tiles, else fp32."""
+    if prec in ("bf16", "bf16x3", "fp16"):
+        return BF16_MFMA_PEAK_TFLOPS
+    if prec == "u8grid":
+        return INT8_MFMA_PEAK_TOPS
+    return FP32_MFMA_PEAK_TFLOPS
 
 
 def roofline(prof):
@@ -109,7 +122,7 @@ def roofline(prof):
     r = prof[best]
     avg_s = r["total_ms"] / r["launches"] / 1e3
     if r["algo_flops"] > 0:
-        peak = BF16_MFMA_PEAK_TFLOPS if r.get("prec") == "bf16" else FP32_MFMA_PEAK_TFLOPS
+        peak = mfma_peak(r.get("prec"))
         ach = r["algo_flops"] / r["launches"] / avg_s / 1e12
         return best, {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                       "frac": round(ach / peak, 4), "traffic": None}
@@ -138,7 +151,7 @@ def stage_summary(prof, steps, n, d, T, L, K):
     tiles = [prof[k] for k in ("tile_phase1", "tile_phase2") if k in prof]
     t_flops = sum(r["algo_flops"] for r in tiles) / steps
     t_ms = sum(r["total_ms"] for r in tiles) / steps
-    peak = FP32_MFMA_PEAK_TFLOPS if not tiles or tiles[0].get("prec") != "bf16" else BF16_MFMA_PEAK_TFLOPS
+    peak = mfma_peak(tiles[0].get("prec") if tiles else None)
     measured = build_traffic_per_step()
     return {
         "build_levels_ms": round(lv_ms, 3),
@@ -420,7 +433,7 @@ def main():
     # reaches the target recall, bfloat16 tiles + re-rank, and plain binary32 beside it
     res = {}
     profs = {}
-    for prec in ("bf16", "fp32"):
+    for prec in (args.headline_prec, "bf16", "fp32") if args.headline_prec != "bf16" else ("bf16", "fp32"):
         (idx, _), el, times, prof = timed_steps(step_fn(t_star, prec), args.steps, args.warmup)
         for r_ in prof.values():
             r_["prec"] = prec
@@ -428,8 +441,8 @@ def main():
         res[prec] = step_record(n, args.steps, el, times, prof)
         res[prec]["identical_to_sweep"] = bool(torch.equal(idx, ref_idx[t_star]))
         print(f"# T={t_star} {prec}: {res[prec]['ms_per_step']} ms/step", file=sys.stderr, flush=True)
-    head = res["bf16"]
-    head_prof = profs["bf16"]
+    head = res[args.headline_prec]
+    head_prof = profs[args.headline_prec]
 
     # the named configuration (T = 32), same steps
     named = {"n_trees": T0, "recall": next(s_["recall"] for s_ in sweep if s_["n_trees"] == T0)}
@@ -466,18 +479,18 @@ def main():
 
     graph = None
     if not args.no_graph:
-        graph = {prec: plan_leg(prec, t_star, ref_idx[t_star]) for prec in ("bf16", "fp32")}
+        graph = {prec: plan_leg(prec, t_star, ref_idx[t_star]) for prec in res}
         print(f"# recorded plan: {graph}", file=sys.stderr, flush=True)
 
     dom, roof = roofline(head_prof)
     if roof is not None and dom is not None:
-        tr = traffic_for(dom, "bf16")
+        tr = traffic_for(dom, args.headline_prec)
         roof["traffic"] = tr  # HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE), or None
         if tr is not None:
             roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
     stages = stage_summary(head_prof, args.steps, n, d, t_star, L, K)
 
-    f = rpf.build(X, t_star, n0, dirs(t_star), dist_prec="bf16")
+    f = rpf.build(X, t_star, n0, dirs(t_star), dist_prec=args.headline_prec)
     f.all_knn(K)
     st = f.knn_stats()
     f.free()
@@ -521,18 +534,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": args.headline_prec,
         "data": "synthetic",
         "config": {"workload": f"allknn_1M_d128_T{t_star}", "n": n, "d": d, "n_trees": t_star, "leaf_size": n0,
-                   "K": K, "tile_prec": "bf16", "split_projection": "f64", "rerank": "fp32+f64",
+                   "K": K, "tile_prec": args.headline_prec, "split_projection": "f64", "rerank": "fp32+f64",
                    "trees_chosen_for_recall": args.target_recall, "named_config_trees": T0},
         "recall": recall_star,
         "recall_truth": "exact kNN (rpf_exact_knn, binary64) of a seeded sample of points; Sec. 5.1 missing rate",
         "step_ms_p50": head["step_ms_p50"],
         "step_ms_p99": head["step_ms_p99"],
-        "bf16_rerank": head,
+        "headline_path": f"{args.headline_prec} tiles + fp32/f64 re-rank",
+        "bf16_rerank": res["bf16"],
+        "bf16x3_rerank": res.get("bf16x3"),
         "fp32": res["fp32"],
-        "bf16_speedup_over_fp32": round(head["value"] / res["fp32"]["value"], 4),
+        "speedup_over_fp32": round(head["value"] / res["fp32"]["value"], 4),
         "recall_sweep": sweep,
         "named_config": named,
         "recorded_plan": graph,
@@ -551,11 +566,13 @@ def main():
 
 def precision_leg(args):
     """The precision path on quantised image-like data: 10^6 x 784, 70 % exact zeros, other
-    entries k/255; T 48, n0 512 (leaves of 488/489 points), K 10, bfloat16 tiles with the
-    binary32/binary64 re-rank, and the same forest with binary32 tiles once beside it (the
-    outputs must be identical: both are the exact top-K of the leaf union).  Reports the step
-    time, the tiles' fraction of the bf16 MFMA peak, the recall against exact kNN of a seeded
-    sample, and the error of the bfloat16 distance model against binary64 on sampled leaf pairs."""
+    entries k/255; T 48, n0 512 (leaves of 488/489 points), K 10.  Tile precisions: int8 grid
+    tiles (exact integer grid distances, the data lying on the 1/255 grid) timed over steps;
+    bfloat16 (the loose bf16 bounds send rows to the exhaustive scan on these concentrated
+    distances), binary32 and split bfloat16 once each.  Every output must be identical (each is
+    the exact top-K of the leaf union).  Reports step times, tile throughput, recall against
+    exact kNN of a seeded sample, and the error of the bfloat16 distance model against
+    binary64 on sampled leaf pairs."""
     import torch
     from paper_1812_11689_amd import metrics, rpf
     from paper_1812_11689_amd import workloads as W
@@ -580,29 +597,37 @@ def precision_leg(args):
             return out
         return step
 
-    (i16, _), el, times, prof = timed_steps(step_fn("bf16"), max(1, min(args.steps, 3)), 1)
-    rec = step_record(n, max(1, min(args.steps, 3)), el, times, prof)
-    tiles = [prof[k] for k in ("tile_phase1", "tile_phase2") if k in prof]
-    t_ms = sum(r["total_ms"] for r in tiles) / max(1, min(args.steps, 3))
-    t_fl = sum(r["algo_flops"] for r in tiles) / max(1, min(args.steps, 3))
-    rec["tiles_ms"] = round(t_ms, 3)
-    rec["tiles_algorithmic_tflop"] = round(t_fl / 1e12, 3)
-    rec["tiles_bf16_mfma_frac"] = round(t_fl / (t_ms / 1e3) / (BF16_MFMA_PEAK_TFLOPS * 1e12), 4) if t_ms else None
-    res["bf16"] = rec
-    print(f"# precision bf16: {rec['ms_per_step']} ms/step", file=sys.stderr, flush=True)
-    (i32, _), el, times, prof = timed_steps(step_fn("fp32"), 1, 0)
-    res["fp32_once"] = {"ms": round(el * 1e3, 3), "identical_to_bf16": bool(torch.equal(i32, i16))}
-    res["missing_rate_bf16_vs_fp32_tiles"] = 0.0 if res["fp32_once"]["identical_to_bf16"] else None
-    del i32
+    def tiles(prof, steps, peak):
+        tl = [prof[k] for k in ("tile_phase1", "tile_phase2") if k in prof]
+        t_ms = sum(r["total_ms"] for r in tl) / steps
+        t_fl = sum(r["algo_flops"] for r in tl) / steps
+        return {"tiles_ms": round(t_ms, 3), "tiles_algorithmic_tera_ops": round(t_fl / 1e12, 3),
+                "tiles_frac_of_peak": round(t_fl / (t_ms / 1e3) / (peak * 1e12), 4) if t_ms else None,
+                "peak_tera_ops": peak}
+
+    steps = max(1, min(args.steps, 3))
+    (ig, _), el, times, prof = timed_steps(step_fn("u8grid"), steps, 1)
+    res["u8grid"] = {**step_record(n, steps, el, times, prof), **tiles(prof, steps, INT8_MFMA_PEAK_TOPS)}
+    print(f"# precision u8grid: {res['u8grid']['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+    for prec, peak in (("bf16", BF16_MFMA_PEAK_TFLOPS), ("fp32", FP32_MFMA_PEAK_TFLOPS),
+                       ("bf16x3", BF16_MFMA_PEAK_TFLOPS)):
+        (ip, _), el, times, prof = timed_steps(step_fn(prec), 1, 0)
+        res[prec + "_once"] = {"ms": round(el * 1e3, 3), "identical_to_u8grid": bool(torch.equal(ip, ig)),
+                               "breakdown_ms": step_record(n, 1, el, times, prof)["breakdown_ms_per_step"],
+                               **tiles(prof, 1, peak)}
+        print(f"# precision {prec}: {el * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        del ip
+    res["missing_rate_vs_each_other"] = 0.0 if all(res[p + "_once"]["identical_to_u8grid"]
+                                                   for p in ("bf16", "fp32", "bf16x3")) else None
     rng = np.random.default_rng(W.SEED_BASE + 303)
     pts = np.sort(rng.choice(n, size=min(2000, n), replace=False))
     pts_d = torch.from_numpy(pts.astype(np.int64)).cuda()
     ti, _ = rpf.exact_knn(X, X[pts_d], K, pts_d)
-    res["recall"] = round(metrics.recall(i16.cpu().numpy()[pts], ti.cpu().numpy()), 5)
+    res["recall"] = round(metrics.recall(ig.cpu().numpy()[pts], ti.cpu().numpy()), 5)
     res["recall_sample"] = len(pts)
     # the bfloat16 tile arithmetic against binary64 on the leaf pairs of sampled points (tree 0):
     # rows centred on their leaf's binary32 mean, rounded to bfloat16, products accumulated in
-    # binary32 -- a model of what the tiles compute, with the same operand rounding
+    # binary32 -- a model of what the bf16 tiles compute, with the same operand rounding
     f = rpf.build(X, T, n0, R, dist_prec="bf16")
     dump = f.tree_dump(0)
     f.free()
