@@ -73,6 +73,8 @@ def parse():
                     help="first run one plain device copy of MIB MiB (reference kernel for HBM counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the 1M x 784 precision-path leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy sweep of Sec. 5 (Table 1 shapes)")
+    ap.add_argument("--accuracy-runs", type=int, default=5, help="independent runs averaged per accuracy point")
     ap.add_argument("--precision-n", type=int, default=None, help="points of the precision-path leg (default 1M)")
     ap.add_argument("--only-step", default=None, metavar="T:PREC",
                     help="run only the 1M x 128 step with T trees and PREC tiles (--steps, --warmup), for profiling")
@@ -111,6 +113,11 @@ def mfma_peak(prec):
 
 
 def roofline(prof):
+    """Roofline of the dominant timed record (most time per step among records with
+    algorithmic bytes or flops): its bound is the MFMA peak of its arithmetic when its
+    algorithmic intensity (flops per algorithmic byte) is above that peak's ridge point
+    (peak / 8 TB/s), HBM otherwise; achieved = algorithmic flops or bytes per launch over the
+    launch's average duration (HIP events on the launch stream)."""
     best = None
     for name, r in prof.items():
         if r["algo_bytes"] <= 0 and r["algo_flops"] <= 0:
@@ -121,14 +128,21 @@ def roofline(prof):
         return None, None
     r = prof[best]
     avg_s = r["total_ms"] / r["launches"] / 1e3
-    if r["algo_flops"] > 0:
-        peak = mfma_peak(r.get("prec"))
+    peak = mfma_peak(r.get("prec"))
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ai = r["algo_flops"] / r["algo_bytes"] if r["algo_bytes"] > 0 else float("inf")
+    if r["algo_flops"] > 0 and ai >= ridge:
         ach = r["algo_flops"] / r["launches"] / avg_s / 1e12
         return best, {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
-                      "frac": round(ach / peak, 4), "traffic": None}
+                      "frac": round(ach / peak, 4), "traffic": None,
+                      "arithmetic_intensity": round(ai, 1), "ridge": round(ridge, 1)}
     ach = r["algo_bytes"] / r["launches"] / avg_s / 1e9
-    return best, {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    if r["algo_flops"] > 0:
+        out.update(arithmetic_intensity=round(ai, 1), ridge=round(ridge, 1),
+                   mfma_achieved_tflops=round(r["algo_flops"] / r["launches"] / avg_s / 1e12, 2), mfma_peak=peak)
+    return best, out
 
 
 BUILD_LEVEL_RECORDS = ("proj_roots", "proj_chunks_x3", "level_small", "select_passes", "partition")
@@ -498,6 +512,16 @@ def main():
     torch.cuda.empty_cache()
     rpf.release_cached_memory()
 
+    accuracy_sweep = None
+    if not args.no_accuracy:
+        from paper_1812_11689_amd import accuracy
+        ta = time.time()
+        accuracy_sweep = accuracy.run(runs=args.accuracy_runs,
+                                      progress=lambda m: print(f"# accuracy: {m}", file=sys.stderr, flush=True))
+        accuracy_sweep["seconds"] = round(time.time() - ta, 1)
+        torch.cuda.empty_cache()
+        rpf.release_cached_memory()
+
     precision = None
     if not args.no_precision:
         precision = precision_leg(args)
@@ -558,6 +582,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "precision_path": precision,
+        "accuracy_sweep": accuracy_sweep,
         "serving": serving,
         "batched": batched,
     }
