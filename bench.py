@@ -34,9 +34,9 @@ sys.path.insert(0, ROOT)
 METRIC = "kNN queries/s at ≥0.99 recall, FP32 vs BF16+rerank; p50/p99 latency"
 PROFILES = os.path.join(ROOT, "profiles")
 # HBM bytes per dispatch of the headline step's kernels (two rocprofv3 counter runs of
-# `--only-step 80:bf16`), valid while the HIP sources hash to the value recorded in it
-TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T80_bf16.md")
-PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2}
+# `--only-step 80:bf16x3`), valid while the HIP sources hash to the value recorded in it
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T80_bf16x3.md")
+PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "u8grid": 4}
 # kernel (name prefix in the counter summary) behind each timed record of the library for the
 # 1M x 128 workload (leaves of 244/245 points: the 8 x 8 symmetric tile)
 RECORD_KERNEL = {
@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--copy-probe into per-kernel HBM traffic (markdown on stdout) and exit")
+    ap.add_argument("--mfma-summary", metavar="DIR", help="summarise a rocprofv3 --pmc run of MFMA counters")
     ap.add_argument("--kt-summary", metavar="DIR", help="summarise a rocprofv3 --kernel-trace --stats run "
                                                         "(markdown on stdout) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -250,6 +251,33 @@ def pmc_summary(fetch_dir, write_dir):
     print(json.dumps(out))
 
 
+def mfma_summary(d):
+    """Per-kernel MFMA counters per dispatch from one rocprofv3 --pmc run: executed MFMA ops
+    (SQ_INSTS_VALU_MFMA_MOPS_* x 512), MFMA-busy cycles over GUI-active cycles x SIMDs."""
+    rows = _csv_rows(d, "counter_collection.csv")
+    agg = {}
+    for r in rows:
+        k = _short(r["Kernel_Name"])
+        if not k.startswith("k_"):
+            continue
+        a = agg.setdefault(k, {})
+        a.setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
+    simds = 256 * 4
+    print("| kernel | dispatches | MFMA Tops/dispatch (bf16, f32, i8) | MFMA busy / (GUI active x SIMDs) |")
+    print("|---|---|---|---|")
+    out = {}
+    for k, a in sorted(agg.items(), key=lambda kv: -sum(kv[1].get("GRBM_GUI_ACTIVE", {}).values())):
+        disp = len(a.get("GRBM_GUI_ACTIVE", {})) or 1
+        ops = [sum(a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{t}", {}).values()) * 512 / disp / 1e12 for t in ("BF16", "F32", "I8")]
+        busy = sum(a.get("SQ_VALU_MFMA_BUSY_CYCLES", {}).values())
+        gui = sum(a.get("GRBM_GUI_ACTIVE", {}).values())
+        frac = busy / (gui * simds) if gui else 0.0
+        out[k] = {"mfma_tops": [round(v, 4) for v in ops], "mfma_busy_frac": round(frac, 4)}
+        if sum(ops) > 0 or frac > 0:
+            print(f"| {k} | {disp} | {ops[0]:.3f}, {ops[1]:.3f}, {ops[2]:.3f} | {frac:.4f} |")
+    print("\n" + json.dumps(out))
+
+
 def kt_summary(d):
     rows = _csv_rows(d, "kernel_stats.csv")
     print("| kernel | calls | total ms | average us | share |")
@@ -335,6 +363,9 @@ def main():
     if args.kt_summary:
         kt_summary(args.kt_summary)
         return
+    if args.mfma_summary:
+        mfma_summary(args.mfma_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "by trees is a design note only)"}))
@@ -360,6 +391,12 @@ def main():
         Lq = rpf.depth(n, n0)
         Xq = torch.from_numpy(w.x).cuda()
         Rq = torch.from_numpy(W.directions(w.dir_seed, Tq, (1 << Lq) - 1, 1, d)).cuda()
+        if args.copy_probe:  # a plain device copy of known size, whose counters give their scale
+            src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
 
         def one():
             f = rpf.build(Xq, Tq, n0, Rq, dist_prec=prec)
