@@ -1018,17 +1018,19 @@ __global__ __launch_bounds__(256) void k_leaf_copy(const float *__restrict__ X, 
 // these norms describe.  One block of 1024 threads per (leaf, tree): 32 lanes per row, four
 // columns each per step of 128 columns, and the block's 32 row groups hold all of the leaf's
 // rows of a step in registers, so X is read once.
-template <typename T, bool VEC>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_leaf_stats(const float *__restrict__ X, int d, int dp,
+// NT threads hold leaves of up to NT / 4 points (1024 threads for 256-point leaves, 256 for
+// leaves of at most 64, where a larger block would leave most of its rows empty).
+template <typename T, bool VEC, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_leaf_stats(const float *__restrict__ X, int d, int dp,
                                                      const LeafDesc *__restrict__ leaves, int nleaf,
                                                      const int32_t *__restrict__ perm, int64_t n,
                                                      int32_t *__restrict__ leaf_of, float *__restrict__ centroid,
                                                      float2 *__restrict__ nrm, float range_max) {
-    constexpr int NT = 1024, RG = NT / 32, RK = 256 / RG;  // row groups, rows per group
+    constexpr int ML = NT / 4, RG = NT / 32, RK = ML / RG;  // rows, row groups, rows per group
     __shared__ __align__(16) float s_part[RG][128];
     __shared__ __align__(16) float s_mu[128];
-    __shared__ int32_t s_id[256];
-    __shared__ float s_na[256], s_ra[256];  // the rows' norms, summed over the steps in order
+    __shared__ int32_t s_id[ML];
+    __shared__ float s_na[ML], s_ra[ML];  // the rows' norms, summed over the steps in order
     const int t = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
     const LeafDesc lf = leaves[blockIdx.x];
     const int m = lf.size;
@@ -1115,14 +1117,23 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 template <typename T>
 static void leaf_stats(hipStream_t s, bool vec, const float *X, int d, int dp, const LeafDesc *leaves, int nleaf,
                        int ntree, const int32_t *perm, int64_t n, int32_t *leaf_of, float *centroid, float2 *nrm,
-                       float range_max) {
+                       float range_max, int max_leaf) {
     const dim3 grid(nleaf, ntree);
-    if (vec)
-        hipLaunchKernelGGL((k_leaf_stats<T, true>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n, leaf_of,
-                           centroid, nrm, range_max);
-    else
-        hipLaunchKernelGGL((k_leaf_stats<T, false>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n,
-                           leaf_of, centroid, nrm, range_max);
+    if (max_leaf <= 64) {
+        if (vec)
+            hipLaunchKernelGGL((k_leaf_stats<T, true, 256>), grid, dim3(256), 0, s, X, d, dp, leaves, nleaf, perm, n,
+                               leaf_of, centroid, nrm, range_max);
+        else
+            hipLaunchKernelGGL((k_leaf_stats<T, false, 256>), grid, dim3(256), 0, s, X, d, dp, leaves, nleaf, perm, n,
+                               leaf_of, centroid, nrm, range_max);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_leaf_stats<T, true, 1024>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n,
+                               leaf_of, centroid, nrm, range_max);
+        else
+            hipLaunchKernelGGL((k_leaf_stats<T, false, 1024>), grid, dim3(1024), 0, s, X, d, dp, leaves, nleaf, perm, n,
+                               leaf_of, centroid, nrm, range_max);
+    }
     launch_check(s, "k_leaf_stats");
 }
 
@@ -1134,11 +1145,11 @@ void launch_leaf_stats(hipStream_t s, int prec, const float *X, int d, int dp, c
     if (nleaf <= 0 || ntree <= 0 || max_leaf > 256) return;  // the caller runs the full leaf pass instead
     const bool vec = (d % 4) == 0;
     if (prec == RPF_DIST_BF16)
-        leaf_stats<__bf16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f);
+        leaf_stats<__bf16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f, max_leaf);
     else if (prec == RPF_DIST_FP16)
-        leaf_stats<_Float16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 60000.f);
+        leaf_stats<_Float16>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 60000.f, max_leaf);
     else
-        leaf_stats<float>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f);
+        leaf_stats<float>(s, vec, X, d, dp, leaves, nleaf, ntree, perm, n, leaf_of, centroid, nrm, 3.0e38f, max_leaf);
 }
 
 template <typename T>

@@ -2205,30 +2205,53 @@ __global__ void k_make_jobs(const int32_t *__restrict__ gcount, const int32_t *_
                             const LeafDesc *__restrict__ leaves, int TR, int nfirst, int qs, TileJob *__restrict__ jobs0,
                             TileJob *__restrict__ jobs1, TileJob *__restrict__ sjobs0, TileJob *__restrict__ sjobs1,
                             int32_t *__restrict__ njobs) {
+    // one (leaf, tree) group per lane; the jobs of a wave are reserved with one atomic per
+    // list (MFMA tiles or the GEMV-shaped kernel) instead of one per job
     const int t = blockIdx.y;
-    for (int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; li < nleaf; li += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = gcount[(int64_t)t * nleaf + li];
-        if (c == 0) continue;
-        const LeafDesc lf = leaves[li];
-        const int na = (c + TR - 1) / TR, nb = (lf.size + TR - 1) / TR;
-        for (int I = 0; I < na; I++)
-            for (int J = 0; J < nb; J++) {
-                TileJob j;
-                j.a_off = goff[(int64_t)t * nleaf + li] + (int64_t)I * TR;
-                j.b_off = lf.off + (int64_t)J * TR;
-                j.a_rows = min(TR, c - I * TR);
-                j.b_rows = min(TR, lf.size - J * TR);
-                j.tree = t;
-                j.same = 0;
-                j.b_pos = J * TR;
-                j.leaf_m = lf.size;
-                j.leaf = (int32_t)li;
-                j.pad = 0;
-                const bool first = t < nfirst;
-                const bool small = c <= qs;  // a few queries: the GEMV-shaped kernel
-                const int slot = atomicAdd(&njobs[(first ? 0 : 1) + (small ? 2 : 0)], 1);
-                (small ? (first ? sjobs0 : sjobs1) : (first ? jobs0 : jobs1))[slot] = j;
+    const int lane = threadIdx.x & 63;
+    const bool first = t < nfirst;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nleaf; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t li = base + threadIdx.x;
+        const int32_t c = li < nleaf ? gcount[(int64_t)t * nleaf + li] : 0;
+        LeafDesc lf{};
+        int na = 0, nb = 0;
+        if (c > 0) {
+            lf = leaves[li];
+            na = (c + TR - 1) / TR;
+            nb = (lf.size + TR - 1) / TR;
+        }
+        const bool small = c <= qs;  // a few queries: the GEMV-shaped kernel
+#pragma unroll
+        for (int ls = 0; ls < 2; ls++) {  // ls = 1: the small-group list
+            const int v = (c > 0 && small == (ls == 1)) ? na * nb : 0;
+            int incl = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
             }
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) continue;
+            int slot0 = 0;
+            if (lane == 63) slot0 = atomicAdd(&njobs[(first ? 0 : 1) + (ls ? 2 : 0)], total);
+            slot0 = __shfl(slot0, 63, 64) + incl - v;
+            if (v == 0) continue;
+            TileJob *dst = ls ? (first ? sjobs0 : sjobs1) : (first ? jobs0 : jobs1);
+            for (int I = 0; I < na; I++)
+                for (int J = 0; J < nb; J++) {
+                    TileJob j;
+                    j.a_off = goff[(int64_t)t * nleaf + li] + (int64_t)I * TR;
+                    j.b_off = lf.off + (int64_t)J * TR;
+                    j.a_rows = min(TR, c - I * TR);
+                    j.b_rows = min(TR, lf.size - J * TR);
+                    j.tree = t;
+                    j.same = 0;
+                    j.b_pos = J * TR;
+                    j.leaf_m = lf.size;
+                    j.leaf = (int32_t)li;
+                    j.pad = 0;
+                    dst[slot0++] = j;
+                }
+        }
     }
 }
 

@@ -82,6 +82,41 @@ namespace {
 
 constexpr size_t kLogCap = 1 << 16;
 
+// The requests of a batch, up to kGroup at a time, as kernel arguments: their query rows are
+// gathered into the batch's contiguous block, and the batch's outputs scattered back to each
+// request's own arrays, by one launch each (rather than three copies per request).
+constexpr int kGroup = 48;
+struct GroupTable {
+    const float *q[kGroup];
+    int32_t *oi[kGroup];
+    float *od[kGroup];
+    int64_t row0[kGroup + 1];  // first row of each request in the batch block; row0[count] = end
+    int count;
+};
+
+__global__ __launch_bounds__(256) void k_gather_rows(GroupTable g, float *__restrict__ dst, int d) {
+    const int64_t total = (g.row0[g.count] - g.row0[0]) * d;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = g.row0[0] + i / d;
+        int k = 0;
+        while (row >= g.row0[k + 1]) k++;
+        dst[g.row0[0] * d + i] = g.q[k][(row - g.row0[k]) * d + i % d];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_rows(GroupTable g, const int32_t *__restrict__ si,
+                                                      const float *__restrict__ sd, int K) {
+    const int64_t total = (g.row0[g.count] - g.row0[0]) * K;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = g.row0[0] + i / K;
+        int k = 0;
+        while (row >= g.row0[k + 1]) k++;
+        const int64_t at = (row - g.row0[k]) * K + i % K;
+        g.oi[k][at] = si[g.row0[0] * K + i];
+        g.od[k][at] = sd[g.row0[0] * K + i];
+    }
+}
+
 void finish(rpf_server *sv, std::vector<Request *> &batch, rpf_status st, const std::string &err, uint64_t bytes,
             const rpf_server_batch &span) {
     const auto now = Clock::now();
@@ -181,19 +216,38 @@ void slot_main(rpf_server *sv, int slot) {
             if (!Qb || !ib || !db) {
                 st = fail(RPF_ENOMEM, "rpf_server: batch staging allocation failed");
             } else {
+                // the batch's requests in groups of kGroup: one gather launch per group
+                std::vector<GroupTable> groups;
                 int64_t off = 0;
-                for (Request *q : batch) {
-                    hipMemcpyAsync(Qb + off * d, q->Q, (size_t)q->m * d * 4, hipMemcpyDeviceToDevice, s);
-                    off += q->m;
-                }
-                st = knn_query(sv->f, Qb, rows, K, ib, db, s);
-                if (st == RPF_OK) {
-                    off = 0;
-                    for (Request *q : batch) {
-                        hipMemcpyAsync(q->out_idx, ib + off * K, (size_t)q->m * K * 4, hipMemcpyDeviceToDevice, s);
-                        hipMemcpyAsync(q->out_dist, db + off * K, (size_t)q->m * K * 4, hipMemcpyDeviceToDevice, s);
+                for (size_t b = 0; b < batch.size(); b += kGroup) {
+                    GroupTable g{};
+                    g.count = (int)std::min<size_t>(kGroup, batch.size() - b);
+                    for (int k = 0; k < g.count; k++) {
+                        Request *q = batch[b + k];
+                        g.q[k] = q->Q;
+                        g.oi[k] = q->out_idx;
+                        g.od[k] = q->out_dist;
+                        g.row0[k] = off;
                         off += q->m;
                     }
+                    g.row0[g.count] = off;
+                    groups.push_back(g);
+                }
+                auto blocks = [](int64_t elems) {
+                    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((elems + 255) / 256, 4096)));
+                };
+                for (const GroupTable &g : groups)
+                    hipLaunchKernelGGL(k_gather_rows, blocks((g.row0[g.count] - g.row0[0]) * d), dim3(256), 0, s, g,
+                                       Qb, d);
+                launch_check(s, "k_gather_rows");
+                st = knn_query(sv->f, Qb, rows, K, ib, db, s);
+                if (st == RPF_OK) {
+                    for (const GroupTable &g : groups)
+                        hipLaunchKernelGGL(k_scatter_rows, blocks((g.row0[g.count] - g.row0[0]) * K), dim3(256), 0, s,
+                                           g, ib, db, K);
+                    launch_check(s, "k_scatter_rows");
+                    const std::string le = take_launch_error();
+                    if (!le.empty()) st = fail(RPF_EDEVICE, "rpf_server: " + le);
                 }
             }
             cache_free(Qb, s);
