@@ -4,7 +4,8 @@ Written separately from `rpf_oracle.c` (recursive rather than work-list driven, 
 floats rather than C doubles, exact integer arithmetic for fused multiply-add) so that the
 two can pin each other bit for bit on small problems.  It follows the same canonical
 reading of the paper (Sec. 2 projections, Alg. 1 median split on the key (p, index),
-Alg. 2 direction choice by the largest S2, Alg. 3 union of leaves and exact distances):
+Alg. 2 direction choice by the largest S2, Alg. 3 union of leaves and exact distances; the
+uniform split point of Alg. 1 with the SplitMix64 generator keyed by (seed, tree, node)):
 
   canon_sum: +0.0-padding to a power of two, then adjacent pairs summed level by level;
   projection: 32 partial sums by j mod 32 of exact binary64 products, canon_sum, + 0.0;
@@ -149,3 +150,84 @@ def all_knn(x, trees, K: int, exclude_self: bool = True):
         idx[i], dist[i] = knn_union(x, trees, [t["leaf_of"][i] for t in trees], x[i], K,
                                     i if exclude_self else None)
     return idx, dist
+
+
+# ---- uniform split rule (Alg. 1 as printed: c uniform in [a, b]) --------------------------
+# SplitMix64 (Steele, Lea and Flood 2014) in Python integers: output i of the stream with
+# seed s is mix64(s + (i + 1) * GAMMA) mod 2^64.
+
+MASK64 = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+UNIFORM_DEPTH = 62
+
+
+def mix64(z: int) -> int:
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def stream(seed: int, i: int) -> int:
+    return mix64(seed + (i + 1) * GAMMA)
+
+
+def node_key(seed: int, t: int, h: int) -> int:
+    return stream(stream(seed, t), h)
+
+
+def node_u(key: int) -> float:
+    return (stream(key, 0) >> 11) * 2.0 ** -53
+
+
+def node_direction(key: int, try_i: int, d: int) -> np.ndarray:
+    out = []
+    for j in range(d):
+        total = 0
+        for q in range(6):
+            w = stream(key, 1 + 6 * (try_i * d + j) + q)
+            total += (w >> 32) + (w & 0xFFFFFFFF)
+        out.append(total * 2.0 ** -32 - 6.0)  # exact: fewer than 53 significant bits
+    return np.asarray(out, dtype=np.float64).astype(np.float32)
+
+
+def build_tree_uniform(x, seed: int, t: int, n0: int, n_try: int = 1):
+    """Tree t by the uniform rule, recursively.  Returns dict(perm, leaf_of (ordinals),
+    nleaf, max_depth, nodes) with the C oracle's conventions; nodes lists (heap, a, b, c,
+    size, left size, try, depth) of every node where a split was attempted, in the order
+    the recursion visits them (pre-order, left first)."""
+    x = np.asarray(x, dtype=np.float32)
+    n, d = x.shape
+    leaf_of = np.zeros(n, np.int32)
+    nodes = []
+    state = {"nleaf": 0, "depth": 0}
+
+    def leaf(members, depth):
+        for i in members:
+            leaf_of[i] = state["nleaf"]
+        state["nleaf"] += 1
+        state["depth"] = max(state["depth"], depth)
+        return list(members)
+
+    def grow(members, h, depth):
+        if len(members) <= n0 or depth >= UNIFORM_DEPTH:
+            return leaf(members, depth)
+        key = node_key(seed, t, h)
+        R = [node_direction(key, i, d) for i in range(n_try)]
+        ch = _which_projection(x, members, R, n_try)
+        p = [canon_dot64(x[i], R[ch]) for i in members]
+        a, b = min(p), max(p)
+        c = a + node_u(key) * (b - a)
+        left = [i for i, v in zip(members, p) if v < c]
+        right = [i for i, v in zip(members, p) if v >= c]
+        nodes.append((h, a, b, c, len(members), len(left), ch, depth))
+        if not left or not right:
+            return leaf(members, depth)
+        return grow(left, 2 * h, depth + 1) + grow(right, 2 * h + 1, depth + 1)
+
+    perm = np.asarray(grow(list(range(n)), 1, 0), dtype=np.int32)
+    return dict(perm=perm, leaf_of=leaf_of, nleaf=state["nleaf"], max_depth=state["depth"], nodes=nodes)
+
+
+def build_forest_uniform(x, n_trees: int, n0: int, seed: int, n_try: int = 1):
+    return [build_tree_uniform(x, seed, t, n0, n_try) for t in range(n_trees)]

@@ -30,6 +30,10 @@
  * and try 0 is used when every S2 is 0.  Random directions are an input:
  * R[t][h-1][try][0..d) for heap id h (root 1, children 2h and 2h+1).
  *
+ * The uniform split point that Alg. 1 prints (c drawn uniformly between the smallest and
+ * the largest projection) is grown as well, with its random numbers from a counter-based
+ * generator; its section below states the rule.
+ *
  * kNN follows Alg. 3: each query falls through every tree to one leaf, the union of the
  * leaves' members is formed, exact distances are computed and the K closest are kept,
  * ordered by (D, index).  Fewer than K candidates leave (-1, +inf) in the tail.
@@ -349,6 +353,222 @@ void rpfo_bruteforce(const float *X, int64_t n, int d, const float *Q, int64_t m
         }
         free(best);
     }
+}
+
+/* ---- uniform split rule: Alg. 1 as printed, c drawn uniformly in [a, b] ----------------
+ *
+ * The trees' shapes depend on the data, so the random numbers of a node cannot be laid out
+ * in advance as the median rule's direction array is.  They come from a counter-based
+ * generator instead, keyed by (seed, tree, heap id of the node): SplitMix64 (Steele, Lea
+ * and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014).  Its stream
+ * with seed s has the outputs  out(s, i) = mix64(s + (i + 1) * GAMMA), i = 0, 1, ...  with
+ * GAMMA = 0x9E3779B97F4A7C15 and mix64 the published finaliser below (all arithmetic mod
+ * 2^64).  The stream of node h of tree t has the seed out(out(seed, t), h), and its draws
+ * are used as follows:
+ *
+ *   draw 0          the split fraction u = (draw >> 11) * 2^-53, a uniform in [0, 1) on
+ *                   the 2^-53 grid;
+ *   draws 1, 2, ..  the nTry random directions (Alg. 1 and Alg. 2): coordinate j of try i
+ *                   takes the six draws 1 + 6 (i d + j) + q, q = 0..5, splits each into its
+ *                   two 32-bit halves, and is (sum of the twelve halves) * 2^-32 - 6, exact in
+ *                   binary64, rounded once to binary32 (an Irwin-Hall approximation of a
+ *                   standard normal coordinate: mean 0, variance 1).
+ *
+ * A node W is split when |W| > n0 and its depth is below RPFO_UNIFORM_DEPTH: the direction
+ * is chosen among the tries as for the median rule (Alg. 2), a = min and b = max of the
+ * projections, c = RN(a + RN(u * RN(b - a))), W_L = {p < c}, W_R = {p >= c}, both kept in
+ * ascending original index.  When one side is empty (a = b, or c rounded onto a) the node
+ * is a leaf, so a leaf larger than n0 holds points that the node's direction does not
+ * separate.  Leaves are ordered left to right; a point's leaf id is the ordinal of its leaf
+ * in that order. */
+
+#define RPFO_GAMMA 0x9E3779B97F4A7C15ull
+#define RPFO_UNIFORM_DEPTH 62
+
+uint64_t rpfo_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t rpfo_stream(uint64_t s, uint64_t i) { return rpfo_mix64(s + (i + 1) * RPFO_GAMMA); }
+
+uint64_t rpfo_node_key(uint64_t seed, int t, int64_t h)
+{
+    return rpfo_stream(rpfo_stream(seed, (uint64_t)t), (uint64_t)h);
+}
+
+double rpfo_node_u(uint64_t key) { return (double)(rpfo_stream(key, 0) >> 11) * 0x1p-53; }
+
+/* Direction `try` of the node with stream seed `key`: r[0..d). */
+void rpfo_node_direction(uint64_t key, int try_i, int d, float *r)
+{
+    for (int j = 0; j < d; j++) {
+        uint64_t sum = 0;
+        for (int q = 0; q < 6; q++) {
+            uint64_t w = rpfo_stream(key, 1 + 6 * ((uint64_t)try_i * (uint64_t)d + (uint64_t)j) + (uint64_t)q);
+            sum += (w >> 32) + (w & 0xffffffffull);
+        }
+        r[j] = (float)((double)sum * 0x1p-32 - 6.0);
+    }
+}
+
+typedef struct { int64_t heap; int depth; int64_t m; int32_t *idx; } unode_t;
+
+/* Grow tree t by the uniform rule.  Outputs perm and leaf_of (leaf ordinals) of the tree;
+ * returns the number of leaves.  *max_depth gets the depth of the deepest leaf.  When
+ * node_heap is not NULL, every node where a split was attempted is listed (at most n of
+ * them): heap id, (a, b, c), (size, left size, chosen try, depth). */
+static int64_t grow_tree_uniform(const float *X, int64_t n, int d, uint64_t seed, int t, int n_try,
+                                 int64_t n0, int32_t *perm, int32_t *leaf_of, int32_t *max_depth,
+                                 int64_t *n_nodes, int64_t *node_heap, double *node_abc,
+                                 int32_t *node_info)
+{
+    /* depth-first, left child first: leaves come off the stack in left-to-right order */
+    unode_t *stack = (unode_t *)malloc(sizeof(unode_t) * (RPFO_UNIFORM_DEPTH + 2));
+    int top = 0;
+    int32_t *root = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    for (int64_t i = 0; i < n; i++) root[i] = (int32_t)i;
+    stack[top++] = (unode_t){1, 0, n, root};
+    float *Rnode = (float *)malloc((size_t)n_try * d * sizeof(float));
+    double *P = (double *)malloc((size_t)n * sizeof(double));
+    int64_t pos = 0, nleaf = 0, nn = 0;
+    *max_depth = 0;
+    while (top > 0) {
+        unode_t W = stack[--top];
+        int is_leaf = W.m <= n0 || W.depth >= RPFO_UNIFORM_DEPTH;
+        int32_t *left = NULL, *right = NULL;
+        int64_t nl = 0, nr = 0;
+        if (!is_leaf) {
+            uint64_t key = rpfo_node_key(seed, t, W.heap);
+            for (int i = 0; i < n_try; i++) rpfo_node_direction(key, i, d, Rnode + (int64_t)i * d);
+            int ch = which_projection(X, d, W.idx, W.m, Rnode, n_try, P);
+            const float *r = Rnode + (int64_t)ch * d;
+            for (int64_t k = 0; k < W.m; k++) P[k] = rpfo_canon_dot64(X + (int64_t)W.idx[k] * d, r, d);
+            double a = P[0], b = P[0];
+            for (int64_t k = 1; k < W.m; k++) {
+                if (P[k] < a) a = P[k];
+                if (P[k] > b) b = P[k];
+            }
+            double u = rpfo_node_u(key);
+            double c = a + u * (b - a); /* three roundings: no contraction in this file */
+            left = (int32_t *)malloc((size_t)W.m * sizeof(int32_t));
+            right = (int32_t *)malloc((size_t)W.m * sizeof(int32_t));
+            for (int64_t k = 0; k < W.m; k++) {
+                if (P[k] < c) left[nl++] = W.idx[k];
+                else right[nr++] = W.idx[k];
+            }
+            if (node_heap) {
+                node_heap[nn] = W.heap;
+                node_abc[3 * nn] = a;
+                node_abc[3 * nn + 1] = b;
+                node_abc[3 * nn + 2] = c;
+                node_info[4 * nn] = (int32_t)W.m;
+                node_info[4 * nn + 1] = (int32_t)nl;
+                node_info[4 * nn + 2] = ch;
+                node_info[4 * nn + 3] = W.depth;
+            }
+            nn++;
+            if (nl == 0 || nr == 0) is_leaf = 1; /* an empty child: W stays whole */
+        }
+        if (is_leaf) {
+            for (int64_t k = 0; k < W.m; k++) {
+                perm[pos++] = W.idx[k];
+                leaf_of[W.idx[k]] = (int32_t)nleaf;
+            }
+            nleaf++;
+            if (W.depth > *max_depth) *max_depth = W.depth;
+            free(left);
+            free(right);
+            free(W.idx);
+            continue;
+        }
+        free(W.idx);
+        stack[top++] = (unode_t){2 * W.heap + 1, W.depth + 1, nr, right};
+        stack[top++] = (unode_t){2 * W.heap, W.depth + 1, nl, left};
+    }
+    if (n_nodes) *n_nodes = nn;
+    free(P);
+    free(Rnode);
+    free(stack);
+    return nleaf;
+}
+
+/* Alg. 3 forest growth with the uniform rule: T independent trees.  perm and leaf_of are
+ * [T][n]; nleaf and max_depth [T]; the optional node lists are [T][n] slabs (node_abc
+ * [T][n][3], node_info [T][n][4]) with n_nodes [T] entries used. */
+void rpfo_build_uniform(const float *X, int64_t n, int d, int T, int n_try, int64_t n0, uint64_t seed,
+                        int32_t *perm, int32_t *leaf_of, int32_t *nleaf, int32_t *max_depth,
+                        int64_t *n_nodes, int64_t *node_heap, double *node_abc, int32_t *node_info)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < T; t++) {
+        int64_t nn = 0;
+        nleaf[t] = (int32_t)grow_tree_uniform(
+            X, n, d, seed, t, n_try, n0, perm + (int64_t)t * n, leaf_of + (int64_t)t * n, max_depth + t, &nn,
+            node_heap ? node_heap + (int64_t)t * n : NULL, node_abc ? node_abc + (int64_t)t * n * 3 : NULL,
+            node_info ? node_info + (int64_t)t * n * 4 : NULL);
+        if (n_nodes) n_nodes[t] = nn;
+    }
+}
+
+/* Alg. 3 union and exact ranking over leaves given as ordinals: leaf_of [T][n] holds the
+ * leaf ordinal of every point (its leaf's members sit together in perm [T][n]); query q
+ * reaches leaf qleaf[t][q] of tree t.  Same outputs and conventions as rpfo_knn. */
+void rpfo_knn_ordinal(const float *X, int64_t n, int d, int T, const int32_t *perm, const int32_t *leaf_of,
+                      const float *Q, int64_t m, const int32_t *qleaf, const int64_t *self, int K,
+                      int32_t *out_idx, double *out_dist)
+{
+    /* leaf ranges of every tree: a leaf's members are consecutive in perm */
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)T * (size_t)(n + 1));
+    for (int t = 0; t < T; t++) {
+        int64_t *st = start + (int64_t)t * (n + 1);
+        int32_t prev = -1;
+        int64_t nl = 0;
+        for (int64_t pos = 0; pos < n; pos++) {
+            int32_t lf = leaf_of[(int64_t)t * n + perm[(int64_t)t * n + pos]];
+            if (lf != prev) {
+                st[nl++] = pos;
+                prev = lf;
+            }
+        }
+        st[nl] = n;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < m; q++) {
+        int64_t cap = 0;
+        for (int t = 0; t < T; t++) {
+            const int64_t *st = start + (int64_t)t * (n + 1);
+            int32_t lf = qleaf[(int64_t)t * m + q];
+            cap += st[lf + 1] - st[lf];
+        }
+        int32_t *u = (int32_t *)malloc((size_t)(cap > 0 ? cap : 1) * sizeof(int32_t));
+        int64_t nu = 0;
+        for (int t = 0; t < T; t++) {
+            const int64_t *st = start + (int64_t)t * (n + 1);
+            int32_t lf = qleaf[(int64_t)t * m + q];
+            for (int64_t pos = st[lf]; pos < st[lf + 1]; pos++) u[nu++] = perm[(int64_t)t * n + pos];
+        }
+        qsort(u, (size_t)nu, sizeof(int32_t), cmp_i32);
+        cand_t *c = (cand_t *)malloc((size_t)(nu > 0 ? nu : 1) * sizeof(cand_t));
+        int64_t nc = 0;
+        for (int64_t k = 0; k < nu; k++) {
+            if (k > 0 && u[k] == u[k - 1]) continue;
+            if (self && self[q] == u[k]) continue;
+            c[nc].idx = u[k];
+            c[nc].D = rpfo_canon_dist64(Q + q * d, X + (int64_t)u[k] * d, d);
+            nc++;
+        }
+        qsort(c, (size_t)nc, sizeof(cand_t), cmp_cand);
+        for (int k = 0; k < K; k++) {
+            out_idx[q * K + k] = k < nc ? c[k].idx : -1;
+            out_dist[q * K + k] = k < nc ? sqrt(c[k].D) : INFINITY;
+        }
+        free(c);
+        free(u);
+    }
+    free(start);
 }
 
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
