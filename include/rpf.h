@@ -3,7 +3,8 @@
  *
  * kNN search by random projection forests (Yan, Wang, Wang, Wang, Li, arXiv 1812.11689):
  *   - rpf_build     grows an ensemble of T random projection trees over the points U
- *                   (Alg. 3, forest growth, with Alg. 1 and Alg. 2; median split, Sec. 2);
+ *                   (Alg. 3, forest growth, with Alg. 1 and Alg. 2; median split of Sec. 2,
+ *                   or the uniform split point that Alg. 1 prints);
  *   - rpf_all_knn   finds the K nearest neighbours of every point of U among the union
  *                   of its leaves (Alg. 3 search with Q = U);
  *   - rpf_query     lets external queries fall through every tree and searches the union
@@ -47,8 +48,25 @@ typedef enum {
     RPF_EINTERNAL = -6  /* an internal invariant failed                                     */
 } rpf_status;
 
-/* Split point rule.  Only the median (Sec. 2, "choose the median") is implemented. */
-typedef enum { RPF_SPLIT_MEDIAN = 0 } rpf_split;
+/* Split point rule.
+ * RPF_SPLIT_MEDIAN (Sec. 2): the member of rank floor(m/2) in (p, index) order splits the
+ *   node; every tree has the same data-independent shape (rpf_depth).
+ * RPF_SPLIT_UNIFORM (Alg. 1 as printed): c is drawn uniformly between a = min and b = max
+ *   of the node's projections, c = RN(a + RN(u RN(b - a))) in binary64 with u in [0, 1);
+ *   W_L = {p < c}, W_R = {p >= c}, both in ascending original index.  A node with an empty
+ *   child (a = b, or c rounded onto a) stays whole as a leaf, so its leaf can hold more than
+ *   leaf_size points; nodes at depth 62 are not split.  The random numbers come from the
+ *   counter-based generator SplitMix64 (Steele, Lea, Flood 2014: output i of the stream with
+ *   seed s is mix64(s + (i + 1) 0x9E3779B97F4A7C15)): node h (heap id, root 1) of tree t uses
+ *   the stream whose seed is out(out(params.seed, t), h); its draw 0 gives
+ *   u = (draw >> 11) 2^-53, and coordinate j of direction try i is the sum of the 32-bit
+ *   halves of draws 1 + 6 (i d + j) + q, q = 0..5, times 2^-32, minus 6, rounded once to
+ *   binary32.  directions_dev is not used.  Tree shapes depend on the data, so leaves are
+ *   numbered per tree (ordinal in left-to-right order).  Uniform forests support rpf_all_knn,
+ *   rpf_tree_dump (perm and leaf ordinals), rpf_tree_nodes, rpf_forest_info, rpf_free and
+ *   rpf_last_knn_stats; rpf_build_batched, rpf_plan_create, rpf_query, rpf_route and the
+ *   server return RPF_EINVAL for them. */
+typedef enum { RPF_SPLIT_MEDIAN = 0, RPF_SPLIT_UNIFORM = 1 } rpf_split;
 
 /* Precision of the candidate distance tiles (the MFMA Gram products).  Whatever the tile
  * precision, the returned neighbours are the exact top-K of the leaf union under the
@@ -84,15 +102,18 @@ typedef struct {
                             every leaf holds at most n0 (Alg. 1, n_s = n0 + 1)              */
     int32_t n_try;       /* nTry >= 1 random directions per node, the one with the largest
                             spread of projections is used (Alg. 2); 1 = basic rpTree        */
-    int32_t split_rule;  /* rpf_split; must be RPF_SPLIT_MEDIAN                             */
+    int32_t split_rule;  /* rpf_split                                                       */
     int32_t dist_prec;   /* rpf_dist_prec for the candidate tiles                           */
     int32_t reserved;    /* must be 0                                                       */
     const float *directions_dev; /* random directions (Alg. 1 and Alg. 2), binary32
                             [n_trees][2^L - 1][n_try][d], row h-1 for heap node h (root 1,
-                            children 2h, 2h+1), L = rpf_depth(n, leaf_size).  Required; it is
-                            copied, so the caller may free it once the build's work ends.   */
+                            children 2h, 2h+1), L = rpf_depth(n, leaf_size).  Required by the
+                            median rule (ignored by the uniform rule); it is copied, so the
+                            caller may free it once the build's work ends.                  */
     uint64_t mem_budget_bytes; /* 0 = unlimited; otherwise rpf_build fails with RPF_ENOMEM
                             when the forest's device memory would exceed it                 */
+    uint64_t seed;       /* RPF_SPLIT_UNIFORM: key of the counter-based generator (any value);
+                            ignored by the median rule                                      */
 } rpf_params;
 
 /* Tree depth L = number of split levels for n points and leaf size n0 (host only). */
@@ -257,18 +278,36 @@ rpf_status rpf_free(rpf_forest *f);
  *   split_dev double [2^L-1], split_idx_dev int32 [2^L-1], chosen_dev int32 [2^L-1]
  *   (NaN / -1 / -1 where the heap slot is not an internal node), perm_dev int32 [n] (the
  *   leaves left to right, members ascending), leaf_of_dev int32 [n] (heap id of the leaf
- *   holding each point).  Any output pointer may be NULL. */
+ *   holding each point; for a uniform-rule forest, the leaf's ordinal in left-to-right
+ *   order).  Any output pointer may be NULL; a uniform-rule forest has no split arrays
+ *   (RPF_EINVAL unless split_dev, split_idx_dev and chosen_dev are NULL). */
 rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split_dev,
                          int32_t *split_idx_dev, int32_t *chosen_dev, int32_t *perm_dev,
                          int32_t *leaf_of_dev, void *stream);
 
+/* The nodes of a uniform-rule tree where a split was attempted (host output, at most n of
+ * them per tree, listed level by level): heap id, split value c, size, left size (0 or
+ * size: the node stayed whole as a leaf), the direction try chosen by Alg. 2, and depth.
+ * count_host gets the number of nodes; at most cap records are written.  RPF_EINVAL for a
+ * median-rule forest (its split arrays come from rpf_tree_dump).  Host only. */
+typedef struct {
+    int64_t heap;
+    double split;
+    int32_t size, left, chosen, depth;
+} rpf_node;
+
+rpf_status rpf_tree_nodes(const rpf_forest *f, int32_t tree, rpf_node *out_host, int64_t cap,
+                          int64_t *count_host);
+
 typedef struct {
     int64_t n;               /* points (all data sets of a batched forest)                  */
-    int32_t d, n_trees, leaf_size, n_try, depth, dist_prec;
-    int64_t n_leaves;
+    int32_t d, n_trees, leaf_size, n_try;
+    int32_t depth;           /* split levels (uniform rule: depth of the deepest leaf)       */
+    int32_t dist_prec;
+    int64_t n_leaves;        /* leaves per tree (uniform rule: of the tree with the most)    */
     uint64_t device_bytes;   /* device memory owned by the forest                           */
     int32_t batch_count;     /* data sets (1 unless built by rpf_build_batched)             */
-    int32_t reserved;
+    int32_t split_rule;      /* rpf_split the forest was grown with                         */
 } rpf_info;
 
 rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out_host);

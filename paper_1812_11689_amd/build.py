@@ -25,7 +25,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",
 ]
 SOURCES = ["rpf_api.hip", "build_kernels.hip", "knn_kernels.hip", "device_cache.hip", "server.hip",
-           "exact_kernels.hip"]
+           "exact_kernels.hip", "uniform_kernels.hip"]
 
 
 def _compile(src: str) -> str:

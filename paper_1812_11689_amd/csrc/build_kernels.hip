@@ -18,21 +18,6 @@ namespace rpf {
 
 // ================================================================ small segments: fused level
 
-// canon_sum over s[0..m) in place (s has room for the power-of-two padding P2 >= m)
-__device__ inline double block_canon_sum(double *s, int m) {
-    int P2 = 1;
-    while (P2 < m) P2 <<= 1;
-    for (int i = m + threadIdx.x; i < P2; i += blockDim.x) s[i] = 0.0;
-    __syncthreads();
-    for (int h = 1; h < P2; h <<= 1) {
-        for (int i = 2 * h * threadIdx.x; i < P2; i += 2 * h * blockDim.x) s[i] = s[i] + s[i + h];
-        __syncthreads();
-    }
-    double r = s[0];
-    __syncthreads();
-    return r;
-}
-
 template <bool VEC>
 __device__ inline void project_segment(const float *__restrict__ X, int d, const float *s_r,
                                        const int32_t *s_perm, int m, double *s_p) {

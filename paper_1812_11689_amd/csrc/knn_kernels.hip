@@ -1897,6 +1897,7 @@ struct FallbackArgs {
     int64_t nrows;
     const int32_t *heap_leaf;   // heap id -> leaf index
     const LeafDesc *leaves;
+    int64_t leaf_stride;        // leaves of tree t start at t * leaf_stride (0: one shared table)
     int32_t exclude_self;       // all-points: row a is point a
     int32_t *out_idx;
     float *out_dist;
@@ -1925,7 +1926,8 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
         for (int t0 = 0; t0 < F.T; t0 += 64) {  // the row's leaves, 64 trees at a time
             const int nt = min(64, F.T - t0);
             __syncthreads();
-            if (tid < nt) s_lf[tid] = F.leaves[F.heap_leaf[F.row_leaf[(int64_t)(t0 + tid) * F.nrows + a]]];
+            if (tid < nt)
+                s_lf[tid] = F.leaves[(t0 + tid) * F.leaf_stride + F.heap_leaf[F.row_leaf[(int64_t)(t0 + tid) * F.nrows + a]]];
             __syncthreads();
             // pieces of up to 256 members, tree after tree; the ids of the next piece are
             // loaded while the current one is processed
@@ -2727,7 +2729,8 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     FallbackArgs fb;
     fb.fb_list = fb_list; fb.fb_cnt = fb_cnt; fb.X = v.X; fb.Qr = cs.Qr; fb.d = v.d; fb.K = K; fb.T = v.T;
     fb.n = v.n; fb.perm = v.perm; fb.row_leaf = cs.row_leaf; fb.nrows = rows; fb.heap_leaf = v.heap_leaf;
-    fb.leaves = v.leaves; fb.exclude_self = cs.excl; fb.out_idx = out_idx; fb.out_dist = out_dist;
+    fb.leaves = v.leaves; fb.leaf_stride = v.leaf_stride; fb.exclude_self = cs.excl; fb.out_idx = out_idx;
+    fb.out_dist = out_dist;
     {
         ProfScope ps(s, "fallback", 0, 0);
         const unsigned nb = (unsigned)std::min<int64_t>(rows, 1024);
@@ -2774,9 +2777,15 @@ static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, 
     cs.rows = v.n;
     cs.B = B > 0 ? std::min(B, max_first_trees(v, K)) : all_points_first_trees(v, K);
     cs.jobs0 = v.jobs;
-    cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
-    cs.njobs0 = v.n_jobs_tree * cs.B;
-    cs.njobs1 = v.n_jobs_tree * (v.T - cs.B);
+    if (v.job_off) {  // trees with leaves of their own: tree t's tiles are jobs[job_off[t], job_off[t + 1])
+        cs.jobs1 = v.jobs + v.job_off[cs.B];
+        cs.njobs0 = v.job_off[cs.B];
+        cs.njobs1 = v.job_off[v.T] - v.job_off[cs.B];
+    } else {
+        cs.jobs1 = v.jobs + v.n_jobs_tree * cs.B;
+        cs.njobs0 = v.n_jobs_tree * cs.B;
+        cs.njobs1 = v.n_jobs_tree * (v.T - cs.B);
+    }
     cs.A = v.Xc;
     cs.a_stride = v.n;
     cs.a_nrm = v.nrm;
@@ -2785,8 +2794,8 @@ static CandStage all_points_stage(const ForestView &v, int K, int exclude_self, 
     cs.row_leaf = v.leaf_of;
     cs.excl = exclude_self;
     const double esz = v.prec == RPF_DIST_FP32 ? 4.0 : 2.0;
-    cs.flops0 = v.tile_flops_tree * cs.B;
-    cs.flops1 = v.tile_flops_tree * (v.T - cs.B);
+    cs.flops0 = v.flops_off ? v.flops_off[cs.B] : v.tile_flops_tree * cs.B;
+    cs.flops1 = v.flops_off ? v.flops_off[v.T] - v.flops_off[cs.B] : v.tile_flops_tree * (v.T - cs.B);
     cs.bytes0 = (double)v.n * v.dp * esz * cs.B;
     cs.bytes1 = (double)v.n * v.dp * esz * (v.T - cs.B);
     cs.sym = v.max_leaf <= 32 * v.job_mb;  // every leaf is a single diagonal tile
@@ -3093,6 +3102,7 @@ extern "C" rpf_status rpf_query_noalloc(const rpf_forest *f, const float *Q, int
     if (K < 1 || K > forest_points(f)) return fail(RPF_EINVAL, "rpf_query_noalloc: K must be in [1, n]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_query_noalloc: K above 256 is not supported");
     if (forest_batch_count(f) > 1) return fail(RPF_EINVAL, "rpf_query_noalloc: the forest holds several data sets");
+    if (forest_uniform(f)) return fail(RPF_EINVAL, "rpf_query_noalloc: queries need a median-rule forest");
     if (forest_fault_seen(f)) return fault_error(f, "rpf_query_noalloc");
     const uint64_t need = query_workspace_bytes(f, m, K);  // an upper bound of the carve below
     if (need > kScratchBytes)

@@ -354,6 +354,15 @@ struct rpf_forest {
     // the leaf copies (Xc) when made after the build, on a query's first use
     std::mutex xc_mu;
     hipEvent_t xc_ev = nullptr;  // recorded after the copy kernel
+    // uniform split rule: every tree has its own leaves (table [T][leaf_stride], leaf_of holds
+    // ordinals within the tree), its own tile jobs and its own node list
+    int32_t split_rule = RPF_SPLIT_MEDIAN;
+    uint64_t seed = 0;
+    int64_t leaf_stride = 0;
+    std::vector<int32_t> tree_nleaf;       // leaves of each tree
+    std::vector<int64_t> job_off;          // [T + 1]
+    std::vector<double> flops_off;         // [T + 1]
+    std::vector<std::vector<rpf_node>> nodes;
 };
 
 namespace rpf {
@@ -496,7 +505,10 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     if (p->n_trees < 1 || p->n_trees > 65535) return fail(RPF_EINVAL, "rpf_build: n_trees must be in [1, 65535]");
     if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
     if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
-    if (p->split_rule != RPF_SPLIT_MEDIAN) return fail(RPF_EINVAL, "rpf_build: only the median split rule is implemented");
+    if (p->split_rule != RPF_SPLIT_MEDIAN)
+        return fail(RPF_EINVAL, p->split_rule == RPF_SPLIT_UNIFORM
+                                    ? "the uniform split rule grows one data set per forest (rpf_build), not batches or plans"
+                                    : "rpf_build: unknown split_rule");
     if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_U8GRID)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
     if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
@@ -876,6 +888,8 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
 // later callers on other streams wait for the event recorded after the copy kernel.
 rpf_status rpf::ensure_leaf_copies(const rpf_forest *cf, hipStream_t s, bool may_make) {
     rpf_forest *f = const_cast<rpf_forest *>(cf);
+    if (f->split_rule == RPF_SPLIT_UNIFORM)
+        return fail(RPF_EINVAL, "queries need a median-rule forest (a uniform-rule forest has no query copies)");
     std::lock_guard<std::mutex> lk(f->xc_mu);
     if (f->Xc) return f->xc_ev ? check_hip(hipStreamWaitEvent(s, f->xc_ev, 0), "leaf copies: wait") : RPF_OK;
     if (!may_make)
@@ -966,9 +980,367 @@ static rpf_status build_impl(const float *X, const int64_t *sizes, int count, in
     return RPF_OK;
 }
 
+// ---------------------------------------------------------------- uniform split rule
+
+// Leaf pass of a uniform-rule forest: each tree has its own leaf table (row t of the
+// [T][leaf_stride] table), so the leaf kernels run once per tree on that tree's slices.
+static void uniform_leaf_pass(rpf_forest *f, hipStream_t s) {
+    const int64_t n = f->n, ls = f->leaf_stride;
+    const int d = f->d, dp = f->dp, prec = f->prec;
+    const size_t esz = prec == RPF_DIST_FP32 ? 4 : 2;
+    const int32_t *perm = f->perm[f->final_buf];
+    for (int t = 0; t < f->T; t++) {
+        const LeafDesc *lv = f->d_leaves + (int64_t)t * ls;
+        const int nl = f->tree_nleaf[t];
+        const int32_t *pt = perm + (int64_t)t * n;
+        int32_t *lo = f->leaf_of + (int64_t)t * n;
+        float *cen = f->centroid + (int64_t)t * ls * d;
+        float2 *nr = f->nrm + (int64_t)t * n;
+        if (f->Xc)
+            launch_leaf_finalize(s, prec, f->X, d, dp, lv, nl, 1, pt, n, lo, cen,
+                                 static_cast<uint8_t *>(f->Xc) + (size_t)t * n * dp * esz, nr, f->max_leaf, f->lds_max);
+        else if (f->Xq && f->max_leaf > 256)
+            launch_leaf_ids(s, lv, nl, 1, pt, n, lo);
+        else
+            launch_leaf_stats(s, prec, f->X, d, dp, lv, nl, 1, pt, n, lo, cen, nr, f->max_leaf);
+    }
+    launch_check(s, "uniform leaf pass");
+}
+
+// Grow a forest by the uniform split rule: a host-driven level loop over the open nodes of
+// every tree (the shapes depend on the data), then the same leaf pass and all-points tile
+// jobs as the median rule, per tree.  Synchronises the stream once per level.
+static rpf_status build_uniform(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream,
+                                rpf_forest **out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(RPF_EINVAL, "rpf_build: out is NULL");
+    if (!X) return fail(RPF_EINVAL, "rpf_build: X is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(RPF_EINVAL, "rpf_build: n must be in [1, 2^31)");
+    if (d < 1) return fail(RPF_EINVAL, "rpf_build: d must be >= 1");
+    if (d > 4096) return fail(RPF_EINVAL, "rpf_build: d above 4096 is not supported (per-block staging)");
+    if (p->n_trees < 1 || p->n_trees > 65535) return fail(RPF_EINVAL, "rpf_build: n_trees must be in [1, 65535]");
+    if (p->leaf_size < 1) return fail(RPF_EINVAL, "rpf_build: leaf_size must be >= 1");
+    if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
+    if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_U8GRID)
+        return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
+    if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
+    const int64_t T = p->n_trees, TN = T * n;
+    if (TN >= ((int64_t)1 << 40)) return fail(RPF_EINVAL, "rpf_build: n_trees * n too large");
+    const int n0 = p->leaf_size, n_try = p->n_try;
+    const uint64_t seed = p->seed;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    hipGetDevice(&dev);
+    const bool grid = p->dist_prec == RPF_DIST_U8GRID;
+    const int prec = (p->dist_prec == RPF_DIST_BF16X3 || grid) ? RPF_DIST_FP32 : p->dist_prec;
+    const int dq = grid ? (d + 63) & ~63 : 0;
+    const int dp = (d + 7) & ~7;
+    const size_t esz = prec == RPF_DIST_FP32 ? 4 : 2;
+    const int lds_max = lds_limit(dev);
+    int small_max = kChunk;
+    while (small_max > 2 && uni_block_lds(small_max, d, n_try) > (size_t)lds_max) small_max /= 2;
+    const bool chunked = n > small_max;  // only nodes above small_max take the chunked path
+    // open nodes are larger than n0, chunked ones larger than small_max
+    const int64_t seg_cap = TN / (n0 + 1) + T + 1;
+    const int64_t lseg_cap = chunked ? TN / (small_max + 1) + T + 1 : 0;
+    const int64_t chunk_cap = chunked ? TN / kChunk + lseg_cap + 1 : 0;
+
+    uint64_t bytes = (uint64_t)n * d * 4 + (uint64_t)TN * (4 + 4 + 8);  // X, perm, leaf_of, nrm
+    if (grid) bytes += (uint64_t)n * dq + (uint64_t)n * sizeof(LatNorm);
+    uint64_t tmp_bytes = (uint64_t)seg_cap * (sizeof(UniSeg) + sizeof(UniSplit));
+    if (chunked)
+        tmp_bytes += (uint64_t)n_try * TN * 8 + (uint64_t)TN * 4 + (uint64_t)chunk_cap * (sizeof(UniChunk) + n_try * 24 + 8) +
+                     (uint64_t)lseg_cap * (sizeof(UniSeg) + sizeof(UniSplit) + n_try * 8);
+    if (p->mem_budget_bytes && bytes + tmp_bytes > p->mem_budget_bytes)
+        return fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(bytes + tmp_bytes) +
+                                    " bytes, over mem_budget_bytes");
+
+    rpf_forest *f = new rpf_forest();
+    f->n = n; f->d = d; f->T = (int32_t)T; f->n0 = n0; f->n_try = n_try; f->L = 0; f->H = 0;
+    f->prec = prec; f->tile_prec = p->dist_prec; f->dp = dp; f->device = dev; f->lds_max = lds_max;
+    f->split_rule = RPF_SPLIT_UNIFORM; f->seed = seed;
+    rpf_batch_entry root{};
+    root.offset = 0; root.n = n;
+    f->batch = {root};
+    f->bytes = bytes;
+    std::vector<void *> temps;
+    auto bail = [&](rpf_status st) {
+        hipStreamSynchronize(s);
+        for (void *q : temps) cache_free_idle(q);
+        free_forest_memory(f);
+        delete f;
+        return st;
+    };
+    auto dalloc = [&](size_t sz) -> void * { return sz ? cache_alloc(sz, s) : nullptr; };
+#define RPF_UALLOC(ptr, sz)                                                                   \
+    do {                                                                                      \
+        const size_t _sz = (size_t)(sz);                                                      \
+        (ptr) = static_cast<std::remove_reference_t<decltype(ptr)>>(dalloc(_sz));            \
+        if (_sz && !(ptr)) {                                                                  \
+            fail(RPF_ENOMEM, "rpf_build: device allocation of " #ptr " failed");             \
+            return bail(RPF_ENOMEM);                                                          \
+        }                                                                                     \
+    } while (0)
+#define RPF_UTEMP(ptr, sz)                                                                    \
+    do {                                                                                      \
+        RPF_UALLOC(ptr, sz);                                                                  \
+        if (ptr) temps.push_back((void *)(ptr));                                              \
+    } while (0)
+
+    RPF_UALLOC(f->X, (size_t)n * d * 4);
+    RPF_UALLOC(f->perm[0], (size_t)TN * 4);
+    RPF_UALLOC(f->leaf_of, (size_t)TN * 4);
+    RPF_UALLOC(f->nrm, (size_t)TN * 8);
+    RPF_UALLOC(f->err, 64);
+    RPF_UALLOC(f->stats, kStatSlots * 8 * 8 + 256);
+    f->fault = f->stats + kStatSlots * 8;
+    fill_u64(f->fault, 1, 0, s);
+    f->pin_slot = pin_take();
+    if (grid) {
+        RPF_UALLOC(f->Xq, (size_t)n * dq);
+        RPF_UALLOC(f->qn, (size_t)n * sizeof(LatNorm));
+        f->dq = dq;
+    }
+    UniSeg *d_seg = nullptr, *d_lseg = nullptr;
+    UniSplit *d_split = nullptr, *d_lsplit = nullptr;
+    UniChunk *d_chunk = nullptr;
+    UniBufs ub;
+    RPF_UTEMP(d_seg, (size_t)seg_cap * sizeof(UniSeg));
+    RPF_UTEMP(d_split, (size_t)seg_cap * sizeof(UniSplit));
+    if (chunked) {
+        RPF_UTEMP(d_lseg, (size_t)lseg_cap * sizeof(UniSeg));
+        RPF_UTEMP(d_lsplit, (size_t)lseg_cap * sizeof(UniSplit));
+        RPF_UTEMP(d_chunk, (size_t)chunk_cap * sizeof(UniChunk));
+        RPF_UTEMP(ub.P, (size_t)n_try * TN * 8);
+        RPF_UTEMP(ub.part, (size_t)chunk_cap * n_try * 8);
+        RPF_UTEMP(ub.mm, (size_t)chunk_cap * n_try * sizeof(double2));
+        RPF_UTEMP(ub.mu, (size_t)lseg_cap * n_try * 8);
+        RPF_UTEMP(ub.lcount, (size_t)chunk_cap * 4);
+        RPF_UTEMP(ub.loff, (size_t)chunk_cap * 4);
+        RPF_UTEMP(ub.tmp, (size_t)TN * 4);
+    }
+
+    // ---- inputs: copy, then reject non-finite values (one synchronisation)
+    fill_u32(f->err, 16, 0, s);
+    fill_u32(f->stats, kStatSlots * 8 * 2, 0, s);
+    launch_copy_nonfinite(s, X, f->X, n * d, f->err);
+    if (f->Xq) launch_grid_quantise(s, f->X, n, d, dq, f->Xq, f->qn, f->err + 4);
+    launch_iota(s, f->perm[0], n, (int)T);
+    launch_check(s, "input copy and check");
+    int32_t flags[5] = {0, 0, 0, 0, 0};
+    rpf_status st;
+    if ((st = check_hip(hipMemcpyAsync(flags, f->err, 20, hipMemcpyDeviceToHost, s), "read flags")) != RPF_OK) return bail(st);
+    if ((st = check_hip(hipStreamSynchronize(s), "rpf_build input check")) != RPF_OK) return bail(st);
+    if (flags[0]) { fail(RPF_EINVAL, "rpf_build: X holds NaN or Inf"); return bail(RPF_EINVAL); }
+    if (flags[4]) {
+        fail(RPF_EINVAL, "rpf_build: RPF_DIST_U8GRID needs every coordinate of X to be float(k) / 255 for an integer "
+                         "k in [0, 255]");
+        return bail(RPF_EINVAL);
+    }
+
+    // ---- growth, level by level
+    struct Open { int64_t pos, heap; int32_t size, tree, depth; };
+    std::vector<Open> open;
+    std::vector<std::vector<LeafDesc>> tleaves(T);
+    f->nodes.assign(T, {});
+    int max_depth = 0;
+    auto close_leaf = [&](const Open &o) {
+        tleaves[o.tree].push_back(LeafDesc{o.pos - (int64_t)o.tree * n, o.size, 0});
+        max_depth = std::max(max_depth, (int)o.depth);
+    };
+    for (int64_t t = 0; t < T; t++) {
+        const Open r{t * n, 1, (int32_t)n, (int32_t)t, 0};
+        if (n > n0) open.push_back(r);
+        else close_leaf(r);
+    }
+    std::vector<UniSeg> hs, hl;
+    std::vector<UniChunk> hc;
+    std::vector<int64_t> is_small, is_large;  // indices into `open`
+    std::vector<UniSplit> rs, rl;
+    while (!open.empty()) {
+        hs.clear(); hl.clear(); hc.clear(); is_small.clear(); is_large.clear();
+        int max_small = 2;
+        for (int64_t k = 0; k < (int64_t)open.size(); k++) {
+            const Open &o = open[k];
+            UniSeg g{o.pos, o.heap, o.size, o.tree, 0, 0};
+            if (o.size <= small_max) {
+                hs.push_back(g);
+                is_small.push_back(k);
+                max_small = std::max(max_small, (int)o.size);
+            } else {
+                g.chunk0 = (int32_t)hc.size();
+                g.nchunk = (int32_t)((o.size + kChunk - 1) / kChunk);
+                for (int q = 0; q < g.nchunk; q++) {
+                    const int64_t st0 = o.pos + (int64_t)q * kChunk;
+                    hc.push_back(UniChunk{st0, (int32_t)std::min<int64_t>(kChunk, o.pos + o.size - st0),
+                                          (int32_t)hl.size()});
+                }
+                hl.push_back(g);
+                is_large.push_back(k);
+            }
+        }
+        if ((int64_t)hs.size() > seg_cap || (int64_t)hl.size() > lseg_cap || (int64_t)hc.size() > chunk_cap) {
+            fail(RPF_EINTERNAL, "rpf_build: uniform growth outgrew its node capacity");
+            return bail(RPF_EINTERNAL);
+        }
+        if (!hs.empty()) {
+            hipMemcpyAsync(d_seg, hs.data(), hs.size() * sizeof(UniSeg), hipMemcpyHostToDevice, s);
+            ProfScope ps(s, "uniform_level_block", 0, 0);
+            launch_uni_block(s, f->X, d, n_try, seed, d_seg, (int)hs.size(), max_small, f->perm[0], d_split);
+        }
+        if (!hl.empty()) {
+            hipMemcpyAsync(d_lseg, hl.data(), hl.size() * sizeof(UniSeg), hipMemcpyHostToDevice, s);
+            hipMemcpyAsync(d_chunk, hc.data(), hc.size() * sizeof(UniChunk), hipMemcpyHostToDevice, s);
+            ProfScope ps(s, "uniform_level_chunked", 0, 0);
+            launch_uni_chunked(s, f->X, d, n_try, seed, d_lseg, (int)hl.size(), d_chunk, (int)hc.size(), f->perm[0], TN,
+                               ub, d_lsplit);
+        }
+        rs.resize(hs.size());
+        rl.resize(hl.size());
+        if (!rs.empty()) hipMemcpyAsync(rs.data(), d_split, rs.size() * sizeof(UniSplit), hipMemcpyDeviceToHost, s);
+        if (!rl.empty()) hipMemcpyAsync(rl.data(), d_lsplit, rl.size() * sizeof(UniSplit), hipMemcpyDeviceToHost, s);
+        if ((st = check_hip(hipStreamSynchronize(s), "rpf_build uniform level")) != RPF_OK) return bail(st);
+        {
+            const std::string le = take_launch_error();
+            if (!le.empty()) {
+                fail(RPF_EDEVICE, "rpf_build: " + le);
+                return bail(RPF_EDEVICE);
+            }
+        }
+        std::vector<Open> next;
+        auto settle = [&](const Open &o, const UniSplit &r) -> bool {
+            if (r.nl < 0 || r.nl > o.size || r.chosen < 0 || r.chosen >= n_try) return false;
+            f->nodes[o.tree].push_back(rpf_node{o.heap, r.c, o.size, r.nl, r.chosen, o.depth});
+            if (r.nl == 0 || r.nl == o.size) {  // an empty child: the node stays whole
+                close_leaf(o);
+                return true;
+            }
+            const Open kids[2] = {{o.pos, 2 * o.heap, r.nl, o.tree, o.depth + 1},
+                                  {o.pos + r.nl, 2 * o.heap + 1, o.size - r.nl, o.tree, o.depth + 1}};
+            for (const Open &c : kids) {
+                if (c.size > n0 && c.depth < kUniformDepth) next.push_back(c);
+                else close_leaf(c);
+            }
+            return true;
+        };
+        bool ok = true;
+        for (size_t k = 0; k < hs.size(); k++) ok &= settle(open[is_small[k]], rs[k]);
+        for (size_t k = 0; k < hl.size(); k++) ok &= settle(open[is_large[k]], rl[k]);
+        if (!ok) {
+            fail(RPF_EINTERNAL, "rpf_build: a uniform split came back out of range");
+            return bail(RPF_EINTERNAL);
+        }
+        open.swap(next);
+    }
+    for (void *q : temps) cache_free(q, s);
+    temps.clear();
+
+    // ---- leaves: left to right within each tree (ordinal = leaf id), one padded table
+    int64_t stride = 0;
+    int max_leaf = 0;
+    f->tree_nleaf.resize(T);
+    for (int64_t t = 0; t < T; t++) {
+        auto &lv = tleaves[t];
+        std::sort(lv.begin(), lv.end(), [](const LeafDesc &a, const LeafDesc &b) { return a.off < b.off; });
+        int64_t at = 0;
+        for (size_t i = 0; i < lv.size(); i++) {
+            if (lv[i].off != at) {
+                fail(RPF_EINTERNAL, "rpf_build: uniform leaves do not tile the permutation");
+                return bail(RPF_EINTERNAL);
+            }
+            at += lv[i].size;
+            lv[i].heap = (int32_t)i;
+            max_leaf = std::max(max_leaf, (int)lv[i].size);
+        }
+        if (at != n) {
+            fail(RPF_EINTERNAL, "rpf_build: uniform leaves do not tile the permutation");
+            return bail(RPF_EINTERNAL);
+        }
+        f->tree_nleaf[t] = (int32_t)lv.size();
+        stride = std::max<int64_t>(stride, (int64_t)lv.size());
+    }
+    f->leaf_stride = stride;
+    f->max_leaf = max_leaf;
+    f->L = max_depth;
+    f->batch[0].depth = max_depth;
+    int MB = 8;
+    if (max_leaf <= 32) MB = 1;
+    else if (max_leaf <= 64) MB = 2;
+    else if (max_leaf <= 128) MB = 4;
+    const int TR = 32 * MB;
+    f->job_mb = MB;
+    std::vector<TileJob> jobs;
+    f->job_off.assign(T + 1, 0);
+    f->flops_off.assign(T + 1, 0.0);
+    for (int64_t t = 0; t < T; t++) {
+        double fl = 0;
+        for (size_t li = 0; li < tleaves[t].size(); li++) {
+            const LeafDesc &lf = tleaves[t][li];
+            const int nt = (lf.size + TR - 1) / TR;
+            for (int I = 0; I < nt; I++)
+                for (int J = 0; J < nt; J++) {
+                    TileJob j;
+                    j.a_off = lf.off + (int64_t)I * TR;
+                    j.b_off = lf.off + (int64_t)J * TR;
+                    j.a_rows = std::min(TR, lf.size - I * TR);
+                    j.b_rows = std::min(TR, lf.size - J * TR);
+                    j.tree = (int32_t)t;
+                    j.same = I == J;
+                    j.b_pos = J * TR;
+                    j.leaf_m = lf.size;
+                    j.leaf = (int32_t)li;
+                    j.pad = 0;
+                    jobs.push_back(j);
+                }
+            fl += 2.0 * d * (double)lf.size * (double)lf.size;
+        }
+        f->job_off[t + 1] = (int64_t)jobs.size();
+        f->flops_off[t + 1] = f->flops_off[t] + fl;
+    }
+    f->n_jobs_tree = 0;
+    f->tile_flops_tree = f->flops_off[T] / (double)T;
+    std::vector<LeafDesc> table((size_t)(T * stride), LeafDesc{0, 0, -1});
+    for (int64_t t = 0; t < T; t++)
+        std::copy(tleaves[t].begin(), tleaves[t].end(), table.begin() + t * stride);
+    const bool xc_eager = max_leaf > 256 && !grid;
+    const uint64_t more = (uint64_t)T * stride * (d * 4 + sizeof(LeafDesc)) + (uint64_t)(stride + 1) * 4 +
+                          (uint64_t)jobs.size() * sizeof(TileJob) + (xc_eager ? (uint64_t)TN * dp * esz : 0);
+    if (p->mem_budget_bytes && f->bytes + more > p->mem_budget_bytes) {
+        fail(RPF_ENOMEM, "rpf_build: forest needs " + std::to_string(f->bytes + more) + " bytes, over mem_budget_bytes");
+        return bail(RPF_ENOMEM);
+    }
+    RPF_UALLOC(f->d_leaves, table.size() * sizeof(LeafDesc));
+    RPF_UALLOC(f->heap_leaf, (size_t)(stride + 1) * 4);
+    RPF_UALLOC(f->centroid, (size_t)T * stride * d * 4);
+    RPF_UALLOC(f->d_jobs, jobs.size() * sizeof(TileJob));
+    if (xc_eager) RPF_UALLOC(f->Xc, (size_t)TN * dp * esz);
+    f->bytes += more;
+    std::vector<int32_t> ident((size_t)stride + 1);
+    for (int64_t i = 0; i <= stride; i++) ident[i] = (int32_t)i;
+    hipMemcpyAsync(f->d_leaves, table.data(), table.size() * sizeof(LeafDesc), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(f->heap_leaf, ident.data(), ident.size() * 4, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(f->d_jobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s);
+    f->final_buf = 0;
+    {
+        ProfScope ps(s, "leaf_finalize", (double)TN * (4.0 * d + 16), 0);
+        uniform_leaf_pass(f, s);
+    }
+    if ((st = check_hip(hipStreamSynchronize(s), "rpf_build uniform leaves")) != RPF_OK) return bail(st);
+    const std::string le = take_launch_error();
+    if (!le.empty()) {
+        fail(RPF_EDEVICE, "rpf_build: " + le);
+        return bail(RPF_EDEVICE);
+    }
+#undef RPF_UTEMP
+#undef RPF_UALLOC
+    *out = f;
+    return RPF_OK;
+}
+
 extern "C" {
 
 rpf_status rpf_build(const float *X, int64_t n, int32_t d, const rpf_params *p, void *stream, rpf_forest **out) {
+    if (p && p->split_rule == RPF_SPLIT_UNIFORM) return build_uniform(X, n, d, p, stream, out);
     return build_impl(X, &n, 1, d, p, stream, out);
 }
 
@@ -1303,6 +1675,7 @@ rpf_status rpf_query(const rpf_forest *f, const float *Q, int64_t m, int32_t K, 
     if (K < 1 || K > f->n) return fail(RPF_EINVAL, "rpf_query: K must be in [1, n]");
     if (K > 256) return fail(RPF_EINVAL, "rpf_query: K above 256 is not supported");
     if (f->batch.size() > 1) return fail(RPF_EINVAL, "rpf_query: the forest holds several data sets");
+    if (f->split_rule == RPF_SPLIT_UNIFORM) return fail(RPF_EINVAL, "rpf_query: queries need a median-rule forest");
     if (forest_fault_seen(f)) return fault_error(f, "rpf_query");
     const rpf_status st = knn_query(f, Q, m, K, out_idx, out_dist, (hipStream_t)stream);
     return st != RPF_OK ? st : search_tail(f, (hipStream_t)stream, "rpf_query");
@@ -1318,6 +1691,7 @@ rpf_status rpf_query_workspace_bytes(const rpf_forest *f, int64_t m, int32_t K, 
 rpf_status rpf_route(const rpf_forest *f, const float *Q, int64_t m, int32_t *out_leaf, void *stream) {
     if (!f) return fail(RPF_EINVAL, "rpf_route: forest is NULL");
     if (f->batch.size() > 1) return fail(RPF_EINVAL, "rpf_route: the forest holds several data sets");
+    if (f->split_rule == RPF_SPLIT_UNIFORM) return fail(RPF_EINVAL, "rpf_route: routing needs a median-rule forest");
     if (m < 0) return fail(RPF_EINVAL, "rpf_route: m must be >= 0");
     if (m == 0) return RPF_OK;
     if (!Q || !out_leaf) return fail(RPF_EINVAL, "rpf_route: NULL pointer");
@@ -1328,6 +1702,8 @@ rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split, int32
                          int32_t *perm, int32_t *leaf_of, void *stream) {
     if (!f) return fail(RPF_EINVAL, "rpf_tree_dump: forest is NULL");
     if (tree < 0 || tree >= f->T) return fail(RPF_EINVAL, "rpf_tree_dump: tree out of range");
+    if (f->split_rule == RPF_SPLIT_UNIFORM && (split || split_idx || chosen))
+        return fail(RPF_EINVAL, "rpf_tree_dump: a uniform-rule forest has no split arrays (rpf_tree_nodes lists its nodes)");
     hipStream_t s = (hipStream_t)stream;
     const int64_t H = f->H, n = f->n;
     if (split && H) hipMemcpyAsync(split, f->split + tree * H, H * 8, hipMemcpyDeviceToDevice, s);
@@ -1336,6 +1712,18 @@ rpf_status rpf_tree_dump(const rpf_forest *f, int32_t tree, double *split, int32
     if (perm) hipMemcpyAsync(perm, f->perm[f->final_buf] + tree * n, n * 4, hipMemcpyDeviceToDevice, s);
     if (leaf_of) hipMemcpyAsync(leaf_of, f->leaf_of + tree * n, n * 4, hipMemcpyDeviceToDevice, s);
     return check_hip(hipGetLastError(), "rpf_tree_dump");
+}
+
+rpf_status rpf_tree_nodes(const rpf_forest *f, int32_t tree, rpf_node *out, int64_t cap, int64_t *count) {
+    if (!f || !count) return fail(RPF_EINVAL, "rpf_tree_nodes: NULL pointer");
+    if (f->split_rule != RPF_SPLIT_UNIFORM) return fail(RPF_EINVAL, "rpf_tree_nodes: not a uniform-rule forest");
+    if (tree < 0 || tree >= f->T) return fail(RPF_EINVAL, "rpf_tree_nodes: tree out of range");
+    if (cap < 0 || (cap > 0 && !out)) return fail(RPF_EINVAL, "rpf_tree_nodes: bad output capacity");
+    const std::vector<rpf_node> &v = f->nodes[tree];
+    const int64_t k = std::min<int64_t>(cap, (int64_t)v.size());
+    if (k > 0) std::copy(v.begin(), v.begin() + k, out);
+    *count = (int64_t)v.size();
+    return RPF_OK;
 }
 
 rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
@@ -1347,10 +1735,10 @@ rpf_status rpf_forest_info(const rpf_forest *f, rpf_info *out) {
     out->n_try = f->n_try;
     out->depth = f->L;
     out->dist_prec = f->tile_prec;
-    out->n_leaves = (int64_t)f->leaves.size();
+    out->n_leaves = f->split_rule == RPF_SPLIT_UNIFORM ? f->leaf_stride : (int64_t)f->leaves.size();
     out->device_bytes = f->bytes;
     out->batch_count = (int32_t)f->batch.size();
-    out->reserved = 0;
+    out->split_rule = f->split_rule;
     int32_t err = 0;
     hipDeviceSynchronize();
     hipMemcpy(&err, f->err, 4, hipMemcpyDeviceToHost);
@@ -1403,11 +1791,17 @@ ForestView view(const rpf_forest *f) {
     v.Xq = f->Xq; v.qn = f->qn; v.dq = f->dq;
     v.X = f->X; v.R = f->R; v.centroid = f->centroid; v.split = f->split; v.chosen = f->chosen;
     v.perm = f->perm[f->final_buf]; v.leaf_of = f->leaf_of; v.heap_leaf = f->heap_leaf; v.Xc = f->Xc;
-    v.nrm = f->nrm; v.leaves = f->d_leaves; v.nleaf = (int64_t)f->leaves.size(); v.jobs = f->d_jobs;
+    v.nrm = f->nrm; v.leaves = f->d_leaves; v.jobs = f->d_jobs;
+    v.nleaf = f->leaf_stride ? f->leaf_stride : (int64_t)f->leaves.size();
     v.n_jobs_tree = f->n_jobs_tree; v.tile_flops_tree = f->tile_flops_tree; v.stats = f->stats;
     v.fault = f->fault;
+    v.leaf_stride = f->leaf_stride;
+    v.job_off = f->job_off.empty() ? nullptr : f->job_off.data();
+    v.flops_off = f->flops_off.empty() ? nullptr : f->flops_off.data();
     return v;
 }
+
+bool forest_uniform(const rpf_forest *f) { return f->split_rule == RPF_SPLIT_UNIFORM; }
 
 uint64_t forest_fault_seen(const rpf_forest *f) {
     return f->pin_slot < 0 ? 0 : __atomic_load_n(&g_pin[f->pin_slot], __ATOMIC_RELAXED);

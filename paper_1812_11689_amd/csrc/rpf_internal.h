@@ -154,6 +154,15 @@ struct ForestView {
     double tile_flops_tree;  // useful Gram flops of one tree's all-points tiles
     unsigned long long *stats;
     unsigned long long *fault;  // sticky count of rows that met an out-of-range candidate index
+    // uniform-rule forests: every tree has its own leaves.  The leaf table is [T][leaf_stride]
+    // (nleaf == leaf_stride, unused entries of a tree have size 0), leaf_of holds ordinals
+    // within the tree and heap_leaf is the identity; tree t's all-points tiles are
+    // jobs[job_off[t], job_off[t + 1]) and flops_off[t] is the useful Gram flops of the trees
+    // before t (host arrays of T + 1 entries).  Median-rule forests: leaf_stride 0 (one table
+    // for every tree), job_off and flops_off null.
+    int64_t leaf_stride;
+    const int64_t *job_off;
+    const double *flops_off;
 };
 ForestView view(const rpf_forest *f);
 // internal-fault counter of a forest: the host mirror (no synchronisation; it lags the device
@@ -191,6 +200,7 @@ void replicate_jobs(TileJob *jobs, int64_t njt, int T, hipStream_t s);
 int64_t forest_points(const rpf_forest *f);
 int32_t forest_dim(const rpf_forest *f);
 int32_t forest_batch_count(const rpf_forest *f);
+bool forest_uniform(const rpf_forest *f);  // grown by the uniform split rule (leaves per tree)
 
 bool capturing(hipStream_t s);  // a stream capture (graph recording) is active on s
 rpf_status fail(rpf_status st, const std::string &msg);
@@ -208,6 +218,48 @@ void cache_free_idle(void *p);                    // p has no work queued or run
 uint64_t cache_held_bytes(int dev);
 void cache_release(int dev);                      // hipFree idle blocks (dev < 0: every device)
 std::string take_launch_error();
+
+// ---------------------------------------------------------------- uniform split rule (uniform_kernels.hip)
+
+constexpr int kUniformDepth = 62;  // nodes this deep are not split (heap ids below 2^63)
+
+struct UniSeg {        // one open node of a level of the uniform-rule growth
+    int64_t pos;       // first position in the [T][n] permutation (tree * n + offset)
+    int64_t heap;      // heap id within its tree (root 1)
+    int32_t size;
+    int32_t tree;
+    int32_t chunk0;    // chunked path: first chunk of the node
+    int32_t nchunk;
+};
+
+struct UniChunk {
+    int64_t pos;       // first position in the [T][n] permutation
+    int32_t len;       // <= kChunk
+    int32_t seg;       // node index within the chunked list
+};
+
+struct UniSplit {      // the split of one node
+    double c;          // split value
+    int32_t nl;        // left size (0 or the node's size: the node stays whole)
+    int32_t chosen;    // direction try (Alg. 2)
+};
+
+struct UniBufs {       // temporaries of the chunked path
+    double *P = nullptr;        // [n_try][T n] projections
+    double *part = nullptr;     // [chunks][n_try] partial canonical sums
+    double2 *mm = nullptr;      // [chunks][n_try] (min, max)
+    double *mu = nullptr;       // [nodes][n_try] means
+    uint32_t *lcount = nullptr; // [chunks] left members
+    uint32_t *loff = nullptr;   // [chunks] left members of the node before the chunk
+    int32_t *tmp = nullptr;     // [T n] scratch permutation
+};
+
+size_t uni_block_lds(int max_m, int d, int n_try);
+void launch_uni_block(hipStream_t s, const float *X, int d, int n_try, uint64_t seed, const UniSeg *segs, int nseg,
+                      int max_m, int32_t *perm, UniSplit *out);
+void launch_uni_chunked(hipStream_t s, const float *X, int d, int n_try, uint64_t seed, const UniSeg *segs, int nseg,
+                        const UniChunk *chunks, int nchunk, int32_t *perm, int64_t TN, const UniBufs &b,
+                        UniSplit *out);
 
 // ---------------------------------------------------------------- order-preserving keys
 
@@ -272,6 +324,22 @@ __device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &e
 }
 
 // ---------------------------------------------------------------- canonical arithmetic
+
+// canon_sum over s[0..m) in place by the whole block (s has room for the power-of-two
+// padding P2 >= m); every thread returns the sum
+__device__ inline double block_canon_sum(double *s, int m) {
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    for (int i = m + threadIdx.x; i < P2; i += blockDim.x) s[i] = 0.0;
+    __syncthreads();
+    for (int h = 1; h < P2; h <<= 1) {
+        for (int i = 2 * h * threadIdx.x; i < P2; i += 2 * h * blockDim.x) s[i] = s[i] + s[i + h];
+        __syncthreads();
+    }
+    double r = s[0];
+    __syncthreads();
+    return r;
+}
 
 // Projection of row x onto r (r usually staged in LDS) by an aligned group of 8 lanes;
 // every lane of the group returns p.  VEC: d % 4 == 0 and x, r 16-byte aligned.

@@ -296,6 +296,7 @@ rpf_status rpf_server_create(const rpf_forest *f, const rpf_server_config *cfg, 
     if (cfg->slots < 1 || cfg->slots > 16) return fail(RPF_EINVAL, "rpf_server_create: slots must be in [1, 16]");
     if (cfg->max_batch_rows < 1) return fail(RPF_EINVAL, "rpf_server_create: max_batch_rows must be >= 1");
     if (cfg->max_queue < 1) return fail(RPF_EINVAL, "rpf_server_create: max_queue must be >= 1");
+    if (forest_uniform(f)) return fail(RPF_EINVAL, "rpf_server_create: queries need a median-rule forest");
     rpf_server *sv = new rpf_server();
     sv->f = f;
     sv->cfg = *cfg;

@@ -26,7 +26,7 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
            "rpf_server_batch_log", "rpf_server_destroy", "rpf_query_noalloc", "rpf_exact_knn", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
            "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
-           "rpf_plan_destroy", "rpf_last_error"]
+           "rpf_plan_destroy", "rpf_last_error", "rpf_tree_nodes"]
 
 
 class RpfError(RuntimeError):
@@ -38,14 +38,20 @@ class RpfError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("n_trees", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32),
                 ("split_rule", ctypes.c_int32), ("dist_prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("directions_dev", ctypes.c_void_p), ("mem_budget_bytes", ctypes.c_uint64)]
+                ("directions_dev", ctypes.c_void_p), ("mem_budget_bytes", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64)]
+
+
+class Node(ctypes.Structure):
+    _fields_ = [("heap", ctypes.c_int64), ("split", ctypes.c_double), ("size", ctypes.c_int32),
+                ("left", ctypes.c_int32), ("chosen", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("n_trees", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("dist_prec", ctypes.c_int32), ("n_leaves", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
-                ("batch_count", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("batch_count", ctypes.c_int32), ("split_rule", ctypes.c_int32)]
 
 
 class BatchEntry(ctypes.Structure):
@@ -121,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.rpf_free.argtypes = [vp]
     lib.rpf_tree_dump.restype = i32
     lib.rpf_tree_dump.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.rpf_tree_nodes.restype = i32
+    lib.rpf_tree_nodes.argtypes = [vp, i32, ctypes.POINTER(Node), i64, ctypes.POINTER(i64)]
     lib.rpf_forest_info.restype = i32
     lib.rpf_forest_info.argtypes = [vp, ctypes.POINTER(Info)]
     lib.rpf_last_knn_stats.restype = i32
@@ -261,6 +269,12 @@ class Forest:
         return (1 << self.depth) - 1
 
     def tree_dump(self, t: int, stream=None):
+        if getattr(self, "split_rule", "median") == "uniform":  # leaves only: perm and leaf ordinals
+            perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+            leaf_of = torch.empty(self.n, dtype=torch.int32, device="cuda")
+            _check(load().rpf_tree_dump(self.handle, t, None, None, None, perm.data_ptr(), leaf_of.data_ptr(),
+                                        _stream(stream)))
+            return dict(perm=perm, leaf_of=leaf_of)
         H = self._nodes()
         split = torch.empty(max(H, 1), dtype=torch.float64, device="cuda")
         sidx = torch.empty(max(H, 1), dtype=torch.int32, device="cuda")
@@ -270,6 +284,15 @@ class Forest:
         _check(load().rpf_tree_dump(self.handle, t, split.data_ptr(), sidx.data_ptr(), chosen.data_ptr(),
                                     perm.data_ptr(), leaf_of.data_ptr(), _stream(stream)))
         return dict(split=split[:H], split_idx=sidx[:H], chosen=chosen[:H], perm=perm, leaf_of=leaf_of)
+
+    def tree_nodes(self, t: int) -> list:
+        """rpf_tree_nodes (uniform rule): the nodes of tree t where a split was attempted, as
+        dicts (heap, split, size, left, chosen, depth)."""
+        cnt = ctypes.c_int64(0)
+        _check(load().rpf_tree_nodes(self.handle, t, None, 0, ctypes.byref(cnt)))
+        buf = (Node * max(cnt.value, 1))()
+        _check(load().rpf_tree_nodes(self.handle, t, buf, cnt.value, ctypes.byref(cnt)))
+        return [{k: getattr(buf[i], k) for k, _ in Node._fields_} for i in range(cnt.value)]
 
     def query_workspace_bytes(self, m: int, K: int) -> int:
         b = ctypes.c_uint64(0)
@@ -320,23 +343,34 @@ def exact_knn(X: torch.Tensor, Q: torch.Tensor, K: int, self_idx: torch.Tensor |
     return idx, dist
 
 
+SPLIT = {"median": 0, "uniform": 1}
+
+
 def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
-          dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None) -> Forest:
-    """Grow a forest over X (float32 [n][d] on the device) with the given directions
-    (float32 [n_trees][2^L-1][n_try][d] on the device, L = depth(n, leaf_size))."""
+          dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None, split_rule: str = "median",
+          seed: int = 0) -> Forest:
+    """Grow a forest over X (float32 [n][d] on the device).  Median rule: with the given
+    directions (float32 [n_trees][2^L-1][n_try][d] on the device, L = depth(n, leaf_size)).
+    Uniform rule (split_rule="uniform"): directions None, the random numbers come from the
+    library's counter-based generator keyed by `seed`."""
     X = _dev(X, torch.float32)
     n, d = X.shape
-    L = depth(n, leaf_size) if n >= 1 and leaf_size >= 1 else 0
+    rule = SPLIT[split_rule]
+    L = depth(n, leaf_size) if n >= 1 and leaf_size >= 1 and rule == 0 else 0
     dptr = None
     if directions is not None:
         directions = _dev(directions, torch.float32)
         dptr = directions.data_ptr()
-    p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
+    p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=rule,
                dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
-               directions_dev=dptr, mem_budget_bytes=mem_budget_bytes)
+               directions_dev=dptr, mem_budget_bytes=mem_budget_bytes, seed=seed & (2**64 - 1))
     h = ctypes.c_void_p()
     _check(load().rpf_build(X.data_ptr(), n, d, ctypes.byref(p), _stream(stream), ctypes.byref(h)))
-    return Forest(h, n, d, n_trees, leaf_size, n_try, L)
+    f = Forest(h, n, d, n_trees, leaf_size, n_try, L)
+    f.split_rule = split_rule
+    if rule:
+        f.depth = f.info()["depth"]
+    return f
 
 
 class BatchedForest(Forest):

@@ -45,12 +45,24 @@ def test_invalid_arguments_rejected_without_device():
     assert b"NULL" in lib.rpf_last_error()
     assert lib.rpf_build(fake, 0, 4, ctypes.byref(p), None, ctypes.byref(h)) == rpf.RPF_EINVAL
     assert lib.rpf_build(fake, 100, 0, ctypes.byref(p), None, ctypes.byref(h)) == rpf.RPF_EINVAL
-    for field, bad in [("n_trees", 0), ("leaf_size", 0), ("n_try", 0), ("split_rule", 1), ("dist_prec", 7),
-                       ("reserved", 1)]:
-        q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, reserved=0,
-                       directions_dev=0x2000, mem_budget_bytes=0)
-        setattr(q, field, bad)
-        assert lib.rpf_build(fake, 100, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_EINVAL, field
+    for rule in (0, 1):
+        for field, bad in [("n_trees", 0), ("leaf_size", 0), ("n_try", 0), ("split_rule", 2), ("dist_prec", 7),
+                           ("reserved", 1)]:
+            q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=rule, dist_prec=0, reserved=0,
+                           directions_dev=0x2000, mem_budget_bytes=0)
+            setattr(q, field, bad)
+            assert lib.rpf_build(fake, 100, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_EINVAL, field
+    # the uniform rule grows one data set per forest: no batches
+    q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=1, dist_prec=0, reserved=0,
+                   directions_dev=None, mem_budget_bytes=0, seed=5)
+    sizes = (ctypes.c_int64 * 2)(50, 50)
+    assert lib.rpf_build_batched(fake, sizes, 2, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_EINVAL
+    assert b"uniform" in lib.rpf_last_error()
+    # a uniform forest over budget is refused before any device work
+    q.mem_budget_bytes = 1000
+    assert lib.rpf_build(fake, 100, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_ENOMEM
+    cnt64 = ctypes.c_int64(0)
+    assert lib.rpf_tree_nodes(None, 0, None, 0, ctypes.byref(cnt64)) == rpf.RPF_EINVAL
     # a tree with splits needs directions
     assert lib.rpf_build(fake, 100, 4, ctypes.byref(p), None, ctypes.byref(h)) == rpf.RPF_EINVAL
     assert b"directions" in lib.rpf_last_error()

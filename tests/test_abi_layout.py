@@ -17,7 +17,7 @@ PAIRS = [(rpf.Params, "rpf_params"), (rpf.Info, "rpf_info"), (rpf.BatchEntry, "r
          (rpf.KnnStats, "rpf_knn_stats"), (rpf.ProfileRecord, "rpf_profile_record"),
          (rpf.ServerConfig, "rpf_server_config"), (rpf.ServerStats, "rpf_server_report"),
          (rpf.PlanEntry, "rpf_plan_entry"), (rpf.PlanPartInfo, "rpf_plan_part_info"),
-         (rpf.ServerBatch, "rpf_server_batch")]
+         (rpf.ServerBatch, "rpf_server_batch"), (rpf.Node, "rpf_node")]
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
