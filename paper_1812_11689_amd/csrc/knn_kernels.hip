@@ -19,6 +19,7 @@
 //     binary32 error) is ordered by the canonical binary64 distance and the index.
 //  5. Rows whose buffers overflowed take k_fallback: the exhaustive union in binary64.
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <mutex>
@@ -57,6 +58,22 @@ template <>
 struct TileCfg<RPF_DIST_BF16X3> {
     using T = __bf16;
     static constexpr int KC = 32, LDW = 40, KSTEP = 16;
+};
+
+// k-chunk of the all-points symmetric tiles.  binary32: 32 columns, whose rows arrive in LDS
+// as gathered (the raw tile, written by direct global-to-LDS loads while the previous chunk
+// is on MFMA) and are then centred into the operand tile.  16-bit tiles: twice the chunk of
+// the other tiles, staged from X directly; their operand tile is the only large LDS array and
+// the Phase II queues and Phase I transposes reuse its space, and fewer chunks mean fewer
+// exposed row gathers.  (The 16-bit kernels hold their registers at the occupancy cap, where
+// spill reloads in the k loop would make the MFMAs wait for the raw tile's loads.)
+template <int PREC>
+struct SymCfg {
+    using T = typename TileCfg<PREC>::T;
+    static constexpr bool DMA = PREC == RPF_DIST_FP32;
+    static constexpr int KC = DMA ? 32 : 2 * TileCfg<PREC>::KC;
+    static constexpr int LDW = PREC == RPF_DIST_FP32 ? KC + 1 : KC + 8;
+    static constexpr int KSTEP = TileCfg<PREC>::KSTEP;
 };
 
 template <int PREC>
@@ -138,7 +155,7 @@ template <int PREC, bool VEC>
 __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *__restrict__ X, int d,
                                     const int32_t *s_pt, const float *__restrict__ mu, int rows, int rows_pad,
                                     int k0, int nthreads, typename TileCfg<PREC>::T *s_lo = nullptr) {
-    using C = TileCfg<PREC>;
+    using C = SymCfg<PREC>;
     using T = typename C::T;
     constexpr int EV = PREC == RPF_DIST_FP32 ? 4 : 8;  // elements per LDS vector
     constexpr int VPR = C::KC / EV;
@@ -195,6 +212,77 @@ __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *_
     }
 }
 
+// Rows 0 .. rows-1 of a leaf, columns [k0, k0 + KC), from the raw tile (binary32 rows as
+// gathered, KC floats each) to the operand tile(s): centred on mu and rounded to the tile
+// type, exactly as stage_rows_x does from X (zero past d and past the leaf's rows).  d % 4 == 0.
+template <int PREC>
+__device__ inline void convert_rows(typename TileCfg<PREC>::T *s, const float *raw, int d,
+                                    const float *__restrict__ mu, int rows, int rows_pad, int k0, int nthreads,
+                                    typename TileCfg<PREC>::T *s_lo = nullptr) {
+    using C = SymCfg<PREC>;
+    using T = typename C::T;
+    constexpr int EV = PREC == RPF_DIST_FP32 ? 4 : 8;
+    constexpr int VPR = C::KC / EV;
+    for (int v = threadIdx.x; v < rows_pad * VPR; v += nthreads) {
+        const int r = v / VPR, c = (v % VPR) * EV, j = k0 + c;
+        float a[EV];
+#pragma unroll
+        for (int e = 0; e < EV; e++) a[e] = 0.f;
+        if (r < rows) {
+#pragma unroll
+            for (int h = 0; h < EV; h += 4) {
+                if (j + h < d) {
+                    const float4 xv = *reinterpret_cast<const float4 *>(raw + r * C::KC + c + h);
+                    const float4 u = *reinterpret_cast<const float4 *>(mu + j + h);
+                    a[h] = xv.x - u.x;
+                    a[h + 1] = xv.y - u.y;
+                    a[h + 2] = xv.z - u.z;
+                    a[h + 3] = xv.w - u.w;
+                }
+            }
+        }
+        T *dst = s + r * C::LDW + c;
+        if constexpr (PREC == RPF_DIST_BF16X3) {
+            T hq[EV], lq[EV];
+#pragma unroll
+            for (int e = 0; e < EV; e++) {
+                hq[e] = (T)a[e];
+                lq[e] = (T)(a[e] - (float)hq[e]);
+            }
+            uint4 wh, wl;
+            __builtin_memcpy(&wh, hq, sizeof(wh));
+            __builtin_memcpy(&wl, lq, sizeof(wl));
+            *reinterpret_cast<uint4 *>(dst) = wh;
+            *reinterpret_cast<uint4 *>(s_lo + r * C::LDW + c) = wl;
+        } else if constexpr (PREC == RPF_DIST_FP32) {
+#pragma unroll
+            for (int e = 0; e < EV; e++) dst[e] = a[e];
+        } else {
+            T q[EV];
+#pragma unroll
+            for (int e = 0; e < EV; e++) q[e] = (T)a[e];
+            uint4 w;
+            __builtin_memcpy(&w, q, sizeof(w));
+            *reinterpret_cast<uint4 *>(dst) = w;
+        }
+    }
+}
+
+// Issue the direct global-to-LDS loads of a chunk's rows: each wave instruction moves eight
+// rows of 32 binary32 columns (16 bytes per lane, lane i to raw + 16 i bytes of its group), a
+// wave takes the groups wu, wu + nw, ...  Lanes past the leaf's rows or past d load nothing
+// (their raw values are never read).  d % 4 == 0 and X 16-byte aligned.
+__device__ inline void issue_rows_dma(float *raw, const float *__restrict__ X, int d, const int32_t *s_pt, int rows,
+                                      int k0, int wu, int nw) {
+    const int lane = lane_id();  // recomputed here rather than kept live across the k loop
+    for (int g = wu; 8 * g < rows; g += nw) {
+        const int r = 8 * g + (lane >> 3), j = k0 + 4 * (lane & 7);
+        if (r < rows && j < d)
+            __builtin_amdgcn_global_load_lds(X + (int64_t)s_pt[r] * d + j,
+                                             (__attribute__((address_space(3))) void *)(raw + 8 * g * 32), 16, 0, 0);
+    }
+}
+
 struct BoundCoef {
     float e;      // E: accumulation error per unit of |a|^2 + |b|^2
     float c;      // C: centred-copy rounding per unit of |a'| + |b'|
@@ -223,18 +311,28 @@ __device__ inline void pair_bounds(float na, float nb, float ra, float rb, float
 //          row * cap + (tree - t0) * ML + (position of the column in its leaf); the slot
 //          names the column (the leaf's permutation segment holds its index) and lb = +inf
 //          marks a slot that no pair fills;
-//  mode 1 (Phase II): pairs with lb <= tau(row), appended at row * cap + atomic count.
+//  mode 1 (Phase II): pairs with lb <= tau(row), appended at row * cap + atomic count; or,
+//          when bcnt is set (all-points symmetric tiles, where one block holds every pair of
+//          a row in its tree), in the row's bucket of S records for its tree, counted in LDS:
+//          row * cap + (tree - t1) * S + rank, the bucket's count stored in bcnt[row][tree - t1]
+//          at the end, and records past S appended to the row's overflow list at
+//          row * cap + nT2 * S + atomic count.
 struct TileOut {
     int mode;
     int t0;
     int ML;
     int cap;
     Ent *ent;          // mode 1 records
-    int32_t *cnt;      // mode 1 counters
+    int32_t *cnt;      // mode 1 counters (bucket mode: of the overflow list)
     const float *tau;  // mode 1 thresholds
     uint32_t *plub;    // mode 0: packed bounds per slot (pack_bounds), (+inf, +inf) where empty
     int32_t *roff;     // mode 0: [tree - t0][nrows] start of the row's leaf in the permutation
     int64_t nrows;
+    uint8_t *bcnt;     // mode 1 bucket counts [nrows][nT2], or nullptr (counted lists)
+    int t1;            // bucket mode: first Phase II tree
+    int S;             // bucket mode: records per bucket
+    int nT2;           // bucket mode: Phase II trees
+    int capO;          // bucket mode: overflow records per row
 };
 
 constexpr int kQueue = 512;  // per-wave queue of Phase II pairs that pass the cheap test
@@ -269,6 +367,20 @@ __device__ inline void put_first_empty(const TileOut &o, int64_t slot) { put_fir
 __device__ inline void emit_filtered(const TileOut &o, int a_pt, int b_pt, float lb, float ub) {
     const int slot = atomicAdd(&o.cnt[a_pt], 1);
     if (slot < o.cap) o.ent[(int64_t)a_pt * o.cap + slot] = make_ent(b_pt, lb, ub);
+}
+
+// bucket mode: the record's rank among its row's records of this tree comes from the block's
+// LDS counter of that row; only a record past the bucket takes a device-scope atomic
+__device__ inline void emit_bucket(const TileOut &o, int32_t *s_cnt, int r, int tb2, int a_pt, int b_pt, float lb,
+                                   float ub) {
+    const int slot = atomicAdd(&s_cnt[r], 1);
+    const int64_t base = (int64_t)a_pt * o.cap;
+    if (slot < o.S) {
+        o.ent[base + (int64_t)tb2 * o.S + slot] = make_ent(b_pt, lb, ub);
+    } else {
+        const int q = atomicAdd(&o.cnt[a_pt], 1);
+        if (q < o.capO) o.ent[base + (int64_t)o.nT2 * o.S + q] = make_ent(b_pt, lb, ub);
+    }
 }
 
 // per-row threshold of the cheap test  |b|^2 - 2 a.b <= phi(row),  a necessary condition for
@@ -729,7 +841,7 @@ __global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__
 //
 // Phase II at NB = 8 runs 12 waves: three per pair of block rows, three blocks each, so the
 // accumulators take 48 registers rather than 80 and six waves share a SIMD instead of four.
-constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE == 1 && NB == 8 ? 12 : NB) : 1; }
+constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE >= 1 && NB == 8 ? 12 : NB) : 1; }
 
 template <int NB, int PREC, int MODE>
 __global__ __launch_bounds__(64 * sym_waves(NB, MODE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE) > 8 ? 6 : NB == 8 ? 4 : 1)))
@@ -737,7 +849,7 @@ void k_tile_sym(
     const TileJob *__restrict__ jobs, const float *__restrict__ X, int d, int dp, const float *__restrict__ centroid,
     int nleaf, int64_t stride_tree, const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc,
     int exclude_self, TileOut out) {
-    using C = TileCfg<PREC>;
+    using C = SymCfg<PREC>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
     constexpr int NW = sym_waves(NB, MODE);
@@ -747,14 +859,27 @@ void k_tile_sym(
     constexpr int SLOTS = NB >= 2 ? (PAIR + WPP - 1) / WPP : 1;
     constexpr bool SPLIT = PREC == RPF_DIST_BF16X3;   // hi and lo tiles, three products per step
     constexpr int QL = NW > 8 ? (SPLIT ? 352 : 384) : kQueue;  // queue entries per wave (LDS for two blocks)
-    __shared__ __align__(16) T s_a[(SPLIT ? 2 : 1) * M * C::LDW];
+    // one LDS area: the operand tile(s) during the k loop, then the Phase II queues or the
+    // Phase I transposes
+    // LDS: the operand tile(s) during the k loop, whose space then holds the Phase II queues
+    // or the Phase I transposes; and the raw tile, a separate array so that the operand
+    // tile's reads need not wait for the next chunk's loads into it
+    static_assert(!C::DMA || C::KC == 32, "the raw tile's row groups are 32 binary32 columns");
+    constexpr size_t kTileBytes = (size_t)(SPLIT ? 2 : 1) * M * C::LDW * sizeof(T);
+    constexpr size_t kQueBytes = MODE >= 1 ? (size_t)NW * QL * sizeof(uint2) : 0;
+    constexpr size_t kTrBytes = MODE == 0 ? (size_t)NW * 32 * 33 * sizeof(float) : 0;
+    constexpr size_t kBuf = kTileBytes > kQueBytes ? (kTileBytes > kTrBytes ? kTileBytes : kTrBytes)
+                                                   : (kQueBytes > kTrBytes ? kQueBytes : kTrBytes);
+    __shared__ __align__(16) uint8_t s_buf[kBuf];
+    __shared__ __align__(16) float s_raw[C::DMA ? M * C::KC : 1];
+    T *s_a = reinterpret_cast<T *>(s_buf);
     __shared__ __align__(16) float s_n[M];
     __shared__ __align__(16) float s_r[M];
     __shared__ __align__(16) float s_phi[M];
     __shared__ float s_tau[M];
     __shared__ int32_t s_pt[M];
     __shared__ float s_max[2];
-    __shared__ uint2 s_que[MODE == 1 ? NW : 1][MODE == 1 ? QL : 1];
+    __shared__ int32_t s_cnt[MODE == 2 ? M : 1];  // bucket mode: records of each row so far
 
     const TileJob job = jobs[blockIdx.x];
     const int t = job.tree;
@@ -772,15 +897,20 @@ void k_tile_sym(
             s_r[r] = q.y;
             const int p = ap[r];
             s_pt[r] = p;
-            s_tau[r] = MODE == 1 ? out.tau[p] : INFINITY;
+            s_tau[r] = MODE >= 1 ? out.tau[p] : INFINITY;
         } else {
             s_n[r] = 0.f;
             s_r[r] = 0.f;
             s_pt[r] = -1;
             s_tau[r] = -1.f;
         }
+        if constexpr (MODE == 2) s_cnt[r] = 0;
     }
     __syncthreads();
+    // rows of 16-byte multiples: the first chunk's rows go straight to LDS while the rest of
+    // the set-up runs
+    const bool dma = C::DMA && (d % 4) == 0;
+    if (dma) issue_rows_dma(s_raw, X, d, s_pt, m, 0, wu, NW);
     if (tid < 64) {
         float mn = 0.f, mr = 0.f;
         for (int r = lane; r < m; r += 64) {
@@ -840,10 +970,18 @@ void k_tile_sym(
     const int fr = lane & 31;
     const int fk = PREC == RPF_DIST_FP32 ? (lane >> 5) : 8 * (lane >> 5);
     for (int k0 = 0; k0 < dp; k0 += C::KC) {
-        __syncthreads();
-        if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
-        else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
-        __syncthreads();
+        if (dma) {
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the chunk are in LDS
+            __syncthreads();                 // and every wave's; the last chunk's MFMA reads are done
+            convert_rows<PREC>(s_a, s_raw, d, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+            __syncthreads();  // operand tile complete, raw tile free: the next chunk's loads fly
+            if (k0 + C::KC < dp) issue_rows_dma(s_raw, X, d, s_pt, m, k0 + C::KC, wu, NW);
+        } else {
+            __syncthreads();
+            if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+            else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+            __syncthreads();
+        }
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
         kmax = (kmax + C::KSTEP - 1) / C::KSTEP * C::KSTEP;
         const T *base = s_a + fr * C::LDW + fk;
@@ -889,9 +1027,8 @@ void k_tile_sym(
         // runs of a row.  (col -> row) slots go through a per-wave 32 x 33 LDS transpose in
         // the operand tile, which every wave has finished reading: then each store covers a
         // 128-byte run of a column's row as well.
-        static_assert(sizeof(s_a) >= (size_t)NW * 32 * 33 * sizeof(float), "transpose space");
-        __syncthreads();
-        float *tr = reinterpret_cast<float *>(s_a) + wu * (32 * 33);
+        __syncthreads();  // every wave is done with the operand tile: its space holds the transposes
+        float *tr = reinterpret_cast<float *>(s_buf) + wu * (32 * 33);
 #pragma unroll
         for (int sl = 0; sl < SLOTS; sl++) {
             if (!act[sl]) continue;
@@ -927,12 +1064,15 @@ void k_tile_sym(
         }
         return;
     }
-    if constexpr (MODE == 1) {
+    if constexpr (MODE >= 1) {
         // Phase II: a cheap test over every pair (both directions); the pairs that pass are
         // compacted by ballot into a per-wave LDS queue, whose exact bounds and emissions
         // run when it would overflow and at the end (wave-uniform decisions throughout)
-        uint2 *que = s_que[wu];
+        __syncthreads();  // every wave is done with the operand tile: its space holds the queues
+        uint2 *que = reinterpret_cast<uint2 *>(s_buf) + (size_t)wu * QL;
         uint32_t qc = 0;
+        constexpr bool bucket = MODE == 2;
+        const int tb2 = t - out.t1;
         auto flush = [&](uint32_t nq) {
             wave_sync();
             for (uint32_t i = lane; i < nq; i += 64) {
@@ -940,8 +1080,13 @@ void k_tile_sym(
                 const int row = e.x & 255, col = (e.x >> 8) & 255;
                 float lb, ub;
                 pair_bounds(s_n[row], s_n[col], s_r[row], s_r[col], __uint_as_float(e.y), bc, lb, ub);
-                if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
-                if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
+                if constexpr (bucket) {
+                    if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_bucket(out, s_cnt, row, tb2, s_pt[row], s_pt[col], lb, ub);
+                    if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_bucket(out, s_cnt, col, tb2, s_pt[col], s_pt[row], lb, ub);
+                } else {
+                    if (((e.x >> 16) & 1) && lb <= s_tau[row]) emit_filtered(out, s_pt[row], s_pt[col], lb, ub);
+                    if (((e.x >> 17) & 1) && lb <= s_tau[col]) emit_filtered(out, s_pt[col], s_pt[row], lb, ub);
+                }
             }
             wave_sync();
         };
@@ -1017,6 +1162,11 @@ void k_tile_sym(
             }
         }
         flush(qc);
+        if constexpr (bucket) {  // every wave has emitted: the bucket counts of the block's rows
+            __syncthreads();
+            for (int r = tid; r < m; r += NT)
+                out.bcnt[(int64_t)s_pt[r] * out.nT2 + tb2] = (uint8_t)min(s_cnt[r], out.S);
+        }
     }
 }
 
@@ -1348,6 +1498,10 @@ struct FinalArgs {
     int32_t *big_list;  // rows past the wave merge's records for the block merge (nullptr: none)
     int32_t *big_cnt;
     int64_t npts;       // rows of X: every candidate index lies in [0, npts)
+    const uint8_t *bcnt;  // bucket mode (see TileOut): bucket counts [rows][nT2]; nullptr = one counted list
+    int S;              // bucket mode: records per bucket
+    int nT2;            // bucket mode: buckets (Phase II trees) per row, at most 128
+    int capO;           // bucket mode: overflow records per row (cnt counts them)
     unsigned long long *stats;  // [kStatSlots][8]: rows, fallback, reranked32, reranked64, bad_index,
                                 //                 kept1, emitted2, block-merged (summed over slots by the host)
     unsigned long long *fault;  // the forest's sticky count of rows that met a bad index
@@ -1365,9 +1519,10 @@ __device__ inline void push_fallback(const FinalArgs &A, int64_t a) {
 }
 
 // A row the wave merge cannot hold goes to the block merge when its records fit the buffers
-// and the block's kBigCap, else to the exhaustive fallback.
-__device__ inline void push_overflow(const FinalArgs &A, int64_t a, int c1, int c2) {
-    if (A.big_list && c1 <= A.lcap && c2 <= A.cap && c1 + c2 <= kBigCap) {
+// (ovf: the Phase II records overflowed) and the block's kBigCap, else to the exhaustive
+// fallback.
+__device__ inline void push_overflow(const FinalArgs &A, int64_t a, int c1, int c2, bool ovf) {
+    if (A.big_list && c1 <= A.lcap && !ovf && c1 + c2 <= kBigCap) {
         const int slot = atomicAdd(A.big_cnt, 1);
         A.big_list[slot] = (int32_t)a;
         stat_add(A, 7, 1ull);
@@ -1376,52 +1531,112 @@ __device__ inline void push_overflow(const FinalArgs &A, int64_t a, int c1, int 
     }
 }
 
+// Bucket mode: the Phase II records of row a are bucket b = 0 .. nT2 - 1 (bcnt[a][b] records
+// at a * cap + b * S), then the overflow list.  The wave's lanes read the counts of buckets
+// lane and lane + 64 and scan them: s_pre[b] = the number of bucket b's first record in the
+// row's sequence; s_own[j] = the bucket of record j, for j < room.  Returns the bucket
+// records' total.
+__device__ inline int bucket_tables_wave(const FinalArgs &A, int64_t a, int lane, int32_t *s_pre, uint8_t *s_own,
+                                         int room) {
+    const uint8_t *bc = A.bcnt + a * A.nT2;
+    const int n0 = lane < A.nT2 ? bc[lane] : 0;
+    const int n1 = lane + 64 < A.nT2 ? bc[lane + 64] : 0;
+    int x0 = n0, x1 = n1;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y0 = __shfl_up(x0, o, 64), y1 = __shfl_up(x1, o, 64);
+        if (lane >= o) {
+            x0 += y0;
+            x1 += y1;
+        }
+    }
+    const int t0 = __shfl(x0, 63, 64);
+    const int P = t0 + __shfl(x1, 63, 64);
+    const int e0 = x0 - n0, e1 = t0 + x1 - n1;
+    if (lane < A.nT2) s_pre[lane] = e0;
+    if (lane + 64 < A.nT2) s_pre[lane + 64] = e1;
+    for (int k = 0; k < n0 && e0 + k < room; k++) s_own[e0 + k] = (uint8_t)lane;
+    for (int k = 0; k < n1 && e1 + k < room; k++) s_own[e1 + k] = (uint8_t)(lane + 64);
+    wave_sync();
+    return P;
+}
+
+// Phase II record j of row a (j below the row's count; P = the bucket records' total)
+__device__ inline Ent phase2_rec(const FinalArgs &A, int64_t a, int j, int P, const int32_t *s_pre,
+                                 const uint8_t *s_own) {
+    if (!A.bcnt) return A.ent[a * A.cap + j];
+    if (j < P) {
+        const int b = s_own[j];
+        return A.ent[a * A.cap + (int64_t)b * A.S + (j - s_pre[b])];
+    }
+    return A.ent[a * A.cap + (int64_t)A.nT2 * A.S + (j - P)];
+}
+
+// The Phase II record count of row a and whether its buffers overflowed.
+__device__ inline void phase2_count(const FinalArgs &A, int64_t a, int P, int &c2, bool &ovf) {
+    const int c = A.cnt[a];
+    if (A.bcnt) {
+        ovf = c > A.capO;
+        c2 = P + min(c, A.capO);
+    } else {
+        ovf = c > A.cap;
+        c2 = c;
+    }
+}
+
 // The steps of k_final for one row once its records are counted: Q records per lane in
-// registers, an index hash of HT entries in LDS (s_key), R and the selection keys in s_r and
-// s_d (HT / 2 each), the query row in s_q.
+// registers, an index hash of HT entries in LDS (s_key), the per-slot ub minima and then R in
+// s_r and s_d (HT / 2 each, contiguous), the compacted selection keys in s_c (256), the query
+// row in s_q.
 template <bool VEC, int Q, int HT>
 __device__ __attribute__((always_inline)) inline void final_row(const FinalArgs &A, int64_t a, int lane,
                                                                 int32_t *s_key, int32_t *s_r, uint32_t *s_d,
-                                                                const float *s_q, int c1, int c2) {
+                                                                const float *s_q, int c1, int c2, int P,
+                                                                const int32_t *s_pre, const uint8_t *s_own,
+                                                                uint32_t *s_c) {
     constexpr int kHT = HT;
     constexpr int kHBits = HT == 512 ? 9 : HT == 1024 ? 10 : 11;  // log2(kHT): the hash keeps that many top bits
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
     const int K = A.K;
-    int32_t eidx[Q];
-    uint32_t elb[Q], eub[Q];
-    bool first[Q];
     int nd = 0;
     bool bad = false;  // an index outside [0, npts) is an internal error, never dereferenced
     Ent ev[Q];   // every record of the row is loaded first: the wave waits on memory once
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int i = lane + 64 * q;
-        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : phase2_rec(A, a, i - c1, P, s_pre, s_own))
+                            : invalid_rec();
     }
+    // the bucket tables are read: R's area (s_r, s_d) holds the per-slot ub minima during the
+    // dedup
+    uint32_t *s_ubn = reinterpret_cast<uint32_t *>(s_r);
+    wave_sync();
+    for (int k = lane; k < kHT; k += 64) s_ubn[k] = 0xffffffffu;
+    wave_sync();
+    // Dedup by index: the first copy of an index claims a hash slot; the slot keeps the
+    // smallest ub of the index's copies (every copy's interval holds the index's distance).
+    // tau' = the K-th smallest of those, and R = the indices with a copy whose lb <= tau':
+    // both are functions of the set of copies, so they do not depend on which copy of an
+    // index came first.
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        first[q] = false;
-        eidx[q] = -1;
-        elb[q] = eub[q] = 0;
         const Ent e = ev[q];
         bad |= e.idx < -1 || (int64_t)e.idx >= A.npts;
+        bool fst = false;
         if (e.idx >= 0 && (int64_t)e.idx < A.npts) {
-            eidx[q] = e.idx;
-            elb[q] = fkey(e.lb);
-            eub[q] = fkey(e.ub);
             uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kHBits);
             while (true) {
                 const int old = atomicCAS(&s_key[h], -1, e.idx);
                 if (old == -1) {
-                    first[q] = true;
+                    fst = true;
                     break;
                 }
                 if (old == e.idx) break;
                 h = (h + 1) & (kHT - 1);
             }
+            atomicMin(&s_ubn[h], fkey(e.ub));
         }
-        nd += __popcll(__ballot(first[q]));
+        nd += __popcll(__ballot(fst));
     }
     wave_sync();
     if (__ballot(bad)) {  // counted for the host to report; the row is recomputed exhaustively
@@ -1432,35 +1647,63 @@ __device__ __attribute__((always_inline)) inline void final_row(const FinalArgs 
         }
         return;
     }
+    // The distinct indices are the occupied slots.  tau' = the K-th smallest of their ub: in
+    // the usual case (at most 256 indices) over their ub keys compacted four per lane (s_c),
+    // else over the NS slots per lane (an empty slot reads as the largest key).
+    constexpr int NS = kHT / 64;
     float tv = INFINITY;
-    int nf = 0;
-    if (nd >= K && nd <= 256) {  // the usual case: first copies' ub keys compacted, 4 per lane
+    if (nd >= K && nd <= 256) {
+        int nf = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-            const uint64_t mk = __ballot(first[q]);
-            if (first[q]) s_d[nf + mask_rank(mk)] = eub[q];
+        for (int k = 0; k < NS; k++) {
+            const int slot = lane + 64 * k;
+            const bool occ = s_key[slot] != -1;
+            const uint64_t mk = __ballot(occ);
+            if (occ) s_c[nf + mask_rank(mk)] = s_ubn[slot];
             nf += __popcll(mk);
         }
         wave_sync();
         uint32_t fu[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) fu[q] = lane + 64 * q < nd ? s_d[lane + 64 * q] : 0xffffffffu;
+        for (int q = 0; q < 4; q++) fu[q] = lane + 64 * q < nd ? s_c[lane + 64 * q] : 0xffffffffu;
         tv = __uint_as_float(wave_kth_upper<4>(fu, K - 1));
-        wave_sync();
     } else if (nd >= K) {
-        uint32_t fu[Q];  // ub keys of first copies, the others masked out
+        uint32_t fu[NS];
 #pragma unroll
-        for (int q = 0; q < Q; q++) fu[q] = first[q] ? eub[q] : 0xffffffffu;
-        tv = __uint_as_float(wave_kth_upper<Q>(fu, K - 1));
+        for (int k = 0; k < NS; k++) {
+            const int slot = lane + 64 * k;
+            fu[k] = s_key[slot] != -1 ? s_ubn[slot] : 0xffffffffu;
+        }
+        tv = __uint_as_float(wave_kth_upper<NS>(fu, K - 1));
     }
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
-    int nr = 0;  // rerank set R = {first copies with lb <= tau'}
+    // a copy with lb <= tau' (a few per row) marks its index for R, in the top bit of the
+    // slot's ub key, which a non-negative float's key never sets
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        const bool in = first[q] && elb[q] <= tp;
+        const Ent e = ev[q];
+        if (e.idx >= 0 && fkey(e.lb) <= tp) {
+            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kHBits);
+            while (s_key[h] != e.idx) h = (h + 1) & (kHT - 1);
+            atomicOr(&s_ubn[h], 0x80000000u);
+        }
+    }
+    wave_sync();
+    int32_t sid[NS];  // the slots' indices, -1 where empty or not in R
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        const int slot = lane + 64 * k;
+        const int32_t id = s_key[slot];
+        sid[k] = (id != -1 && (s_ubn[slot] >> 31)) ? id : -1;
+    }
+    wave_sync();  // the ub keys are read: R takes their area
+    int nr = 0;   // rerank set R
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        const bool in = sid[k] != -1;
         const uint64_t mk = __ballot(in);
         const int pos = nr + mask_rank(mk);
-        if (in && pos < kRCap) s_r[pos] = eidx[q];
+        if (in && pos < kRCap) s_r[pos] = sid[k];
         nr += __popcll(mk);
     }
     wave_sync();
@@ -1576,22 +1819,33 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     constexpr int kHBits = Q <= 4 ? 9 : Q <= 12 ? 10 : 11;  // log2(kHT): the hash keeps that many top bits
     static_assert((1 << kHBits) == kHT, "hash range must equal the table");
     constexpr int kRCap = kHT / 2;
-    __shared__ __align__(16) int32_t s_key[4][kHT];  // also read as doubles once the dedup is done
-    __shared__ int32_t s_r[4][kRCap];   // the rerank set R; then, compacted in place, the window
-    __shared__ uint32_t s_d[4][kRCap];
+    __shared__ __align__(16) int32_t s_key[4][kHT];  // index hash; read as doubles once the dedup is done
+    // the rerank set R (first half; then, compacted in place, the window) and the selection
+    // keys (second half); before the records are loaded, the bucket tables
+    __shared__ int32_t s_rd[4][kHT];
+    __shared__ uint32_t s_c[4][256];  // the distinct indices' ub keys, compacted
     extern __shared__ __align__(16) float s_qall[];  // 4 rows x dq floats
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
     const int dq = (A.d + 3) & ~3;
     float *s_q = s_qall + w * dq;
-    const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    int32_t *s_r = s_rd[w];
+    uint32_t *s_d = reinterpret_cast<uint32_t *>(s_rd[w] + kRCap);
+    int32_t *s_pre = s_rd[w];  // 128 buckets at most
+    uint8_t *s_own = reinterpret_cast<uint8_t *>(s_rd[w] + 128);
+    static_assert((kHT - 128) * 4 >= 64 * Q, "bucket owner table");
+    const int c1 = A.lcnt[a];
+    const int P = A.bcnt ? bucket_tables_wave(A, a, lane, s_pre, s_own, 64 * Q) : 0;
+    int c2;
+    bool ovf;
+    phase2_count(A, a, P, c2, ovf);
     if (lane == 0) {
         stat_add(A, 5, (unsigned long long)max(c1, 0));
         stat_add(A, 6, (unsigned long long)max(c2, 0));
     }
-    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > 64 * Q) {
-        if (lane == 0) push_overflow(A, a, c1, c2);
+    if (c1 > A.lcap || ovf || c1 + c2 > 64 * Q) {
+        if (lane == 0) push_overflow(A, a, c1, c2, ovf);
         return;
     }
     for (int i = lane; i < kHT; i += 64) s_key[w][i] = -1;
@@ -1599,13 +1853,13 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs A, int64_t nrows) {
     wave_sync();
     // most rows fill a few records per lane: they take the four-per-lane steps
     if (Q > 4 && c1 + c2 <= 256)
-        final_row<VEC, 4, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+        final_row<VEC, 4, kHT>(A, a, lane, s_key[w], s_r, s_d, s_q, c1, c2, P, s_pre, s_own, s_c[w]);
     else if (Q > 8 && c1 + c2 <= 512)
-        final_row<VEC, 8, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+        final_row<VEC, 8, kHT>(A, a, lane, s_key[w], s_r, s_d, s_q, c1, c2, P, s_pre, s_own, s_c[w]);
     else if (Q > 12 && c1 + c2 <= 768)
-        final_row<VEC, 12, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+        final_row<VEC, 12, kHT>(A, a, lane, s_key[w], s_r, s_d, s_q, c1, c2, P, s_pre, s_own, s_c[w]);
     else
-        final_row<VEC, Q, kHT>(A, a, lane, s_key[w], s_r[w], s_d[w], s_q, c1, c2);
+        final_row<VEC, Q, kHT>(A, a, lane, s_key[w], s_r, s_d, s_q, c1, c2, P, s_pre, s_own, s_c[w]);
 }
 
 // ---------------------------------------------------------------- final merge, one block per row
@@ -1679,53 +1933,68 @@ __device__ inline uint32_t block_kth_upper(const uint32_t (&v)[Q], int k, uint32
 // (a row handed over by the wave merge was counted there).
 template <bool VEC>
 __device__ __attribute__((always_inline)) inline void final_blk_row(const FinalArgs &A, int64_t a, bool counted,
-                                                                    int32_t *s_key, int32_t *s_r, uint32_t *s_d,
-                                                                    uint32_t *s4, uint32_t *s_sc, float *s_q) {
+                                                                    int32_t *s_key, uint32_t *s_ubn, int32_t *s_r,
+                                                                    uint32_t *s_d, uint32_t *s4, uint32_t *s_sc,
+                                                                    float *s_q) {
     const int tid = threadIdx.x, lane = tid & 63, g = lane & 7, grp = tid >> 3;
     const int K = A.K;
-    const int c1 = A.lcnt[a], c2 = A.cnt[a];
+    const int c1 = A.lcnt[a];
+    // bucket mode: the first wave builds the row's bucket tables in s_r (first records) and
+    // s_d (owner of each record), both dead until R is formed
+    int32_t *s_pre = s_r;
+    uint8_t *s_own = reinterpret_cast<uint8_t *>(s_d);
+    static_assert(kBigRCap * 4 >= kBigCap && kBigRCap >= 128, "bucket tables");
+    if (A.bcnt && tid < 64) {
+        const int P = bucket_tables_wave(A, a, lane, s_pre, s_own, kBigCap);
+        if (lane == 0) s4[0] = (uint32_t)P;
+    }
+    __syncthreads();
+    const int P = A.bcnt ? (int)s4[0] : 0;
+    int c2;
+    bool ovf;
+    phase2_count(A, a, P, c2, ovf);
     if (tid == 0 && !counted) {
         stat_add(A, 5, (unsigned long long)max(c1, 0));
         stat_add(A, 6, (unsigned long long)max(c2, 0));
     }
-    if (c1 > A.lcap || c2 > A.cap || c1 + c2 > kBigCap) {
+    if (c1 > A.lcap || ovf || c1 + c2 > kBigCap) {
         if (tid == 0) push_fallback(A, a);
         return;
     }
-    for (int i = tid; i < kBigHT; i += 256) s_key[i] = -1;
+    for (int i = tid; i < kBigHT; i += 256) {
+        s_key[i] = -1;
+        s_ubn[i] = 0xffffffffu;
+    }
     for (int j = tid; j < A.d; j += 256) s_q[j] = A.Qr[a * A.d + j];
     __syncthreads();
     Ent ev[kBigQ];  // every record of the row is loaded first
 #pragma unroll
     for (int q = 0; q < kBigQ; q++) {
         const int i = tid + 256 * q;
-        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : A.ent[a * A.cap + (i - c1)]) : invalid_rec();
+        ev[q] = i < c1 + c2 ? (i < c1 ? A.list[a * A.lcap + i] : phase2_rec(A, a, i - c1, P, s_pre, s_own))
+                            : invalid_rec();
     }
-    int32_t eidx[kBigQ];
-    uint32_t elb[kBigQ], fu[kBigQ];  // lb keys; ub keys of first copies (others masked out)
+    // Dedup by index, as in final_row: the first copy of an index claims a hash slot, the slot
+    // keeps the smallest ub of the copies (s_ubn), and a copy with lb <= tau' marks its index
+    // for R.
     bool bad = false;
     uint32_t nd_mine = 0;
 #pragma unroll
     for (int q = 0; q < kBigQ; q++) {
         const Ent e = ev[q];
-        eidx[q] = -1;
-        elb[q] = 0xffffffffu;
-        fu[q] = 0xffffffffu;
         bad |= e.idx < -1 || (int64_t)e.idx >= A.npts;
         if (e.idx >= 0 && (int64_t)e.idx < A.npts) {
-            eidx[q] = e.idx;
-            elb[q] = fkey(e.lb);
             uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kBigHBits);
             while (true) {  // at most half full: a free or matching entry is always found
                 const int old = atomicCAS(&s_key[h], -1, e.idx);
                 if (old == -1) {
-                    fu[q] = fkey(e.ub);
                     nd_mine++;
                     break;
                 }
                 if (old == e.idx) break;
                 h = (h + 1) & (kBigHT - 1);
             }
+            atomicMin(&s_ubn[h], fkey(e.ub));
         }
     }
     if (__syncthreads_or(bad)) {  // counted for the host to report; the row is recomputed exhaustively
@@ -1736,14 +2005,36 @@ __device__ __attribute__((always_inline)) inline void final_blk_row(const FinalA
         }
         return;
     }
+    constexpr int NS = kBigHT / 256;  // hash slots per thread
     const uint32_t nd = block_sum4(nd_mine, s4);
     float tv = INFINITY;
-    if (nd >= (uint32_t)K) tv = __uint_as_float(block_kth_upper<kBigQ>(fu, K - 1, s4));
+    if (nd >= (uint32_t)K) {
+        uint32_t fu[NS];  // ub minima of the occupied slots, empty slots as the largest key
+#pragma unroll
+        for (int k = 0; k < NS; k++) {
+            const int slot = tid + 256 * k;
+            fu[k] = s_key[slot] != -1 ? s_ubn[slot] : 0xffffffffu;
+        }
+        tv = __uint_as_float(block_kth_upper<NS>(fu, K - 1, s4));
+    }
     const uint32_t tp = fkey(tv * (1.f + 1e-6f));
-    // R = {first copies with lb <= tau'}: per-thread counts, one block scan, then the writes
+#pragma unroll
+    for (int q = 0; q < kBigQ; q++) {
+        const Ent e = ev[q];
+        if (e.idx >= 0 && fkey(e.lb) <= tp) {
+            uint32_t h = ((uint32_t)e.idx * 2654435761u) >> (32 - kBigHBits);
+            while (s_key[h] != e.idx) h = (h + 1) & (kBigHT - 1);
+            atomicOr(&s_ubn[h], 0x80000000u);
+        }
+    }
+    __syncthreads();
+    // R = the marked indices: per-thread counts, one block scan, then the writes
     uint32_t rc = 0;
 #pragma unroll
-    for (int q = 0; q < kBigQ; q++) rc += (fu[q] != 0xffffffffu && elb[q] <= tp) ? 1u : 0u;
+    for (int k = 0; k < NS; k++) {
+        const int slot = tid + 256 * k;
+        rc += (s_key[slot] != -1 && (s_ubn[slot] >> 31)) ? 1u : 0u;
+    }
     uint32_t rbase, nr;
     block_excl_scan256(rc, s_sc, rbase, nr);
     if (nr > (uint32_t)kBigRCap) {
@@ -1751,8 +2042,11 @@ __device__ __attribute__((always_inline)) inline void final_blk_row(const FinalA
         return;
     }
 #pragma unroll
-    for (int q = 0; q < kBigQ; q++)
-        if (fu[q] != 0xffffffffu && elb[q] <= tp) s_r[rbase++] = eidx[q];
+    for (int k = 0; k < NS; k++) {
+        const int slot = tid + 256 * k;
+        const int32_t id = s_key[slot];
+        if (id != -1 && (s_ubn[slot] >> 31)) s_r[rbase++] = id;
+    }
     __syncthreads();  // R is complete and the hash is dead: it holds the binary64 distances now
     double *s_dd = reinterpret_cast<double *>(s_key);
     if constexpr (VEC) {  // 32 groups of eight lanes, two candidates each at a time
@@ -1865,6 +2159,7 @@ __device__ __attribute__((always_inline)) inline void final_blk_row(const FinalA
 template <bool VEC, bool LIST>
 __global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
     __shared__ __align__(16) int32_t s_key[kBigHT];  // index hash; then R's binary64 distances
+    __shared__ uint32_t s_ubn[kBigHT];                // per hash slot: smallest ub, top bit = out of R
     __shared__ int32_t s_r[kBigRCap];                // R; then, compacted, the window
     __shared__ uint32_t s_d[kBigRCap];
     __shared__ uint32_t s4[4];    // reductions and selection counts
@@ -1874,10 +2169,10 @@ __global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
         const int nb = *A.big_cnt;
         for (int i = blockIdx.x; i < nb; i += gridDim.x) {
             __syncthreads();  // the previous row's LDS reads are done
-            final_blk_row<VEC>(A, A.big_list[i], true, s_key, s_r, s_d, s4, s_sc, s_q);
+            final_blk_row<VEC>(A, A.big_list[i], true, s_key, s_ubn, s_r, s_d, s4, s_sc, s_q);
         }
     } else {
-        final_blk_row<VEC>(A, blockIdx.x, false, s_key, s_r, s_d, s4, s_sc, s_q);
+        final_blk_row<VEC>(A, blockIdx.x, false, s_key, s_ubn, s_r, s_d, s4, s_sc, s_q);
     }
 }
 
@@ -2471,6 +2766,9 @@ static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const 
     if (out.mode == 0)
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
                            src.nleaf, src.stride, nrm, pt, bc, excl, out);
+    else if (out.bcnt)  // Phase II into per-tree buckets
+        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 2>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
+                           src.nleaf, src.stride, nrm, pt, bc, excl, out);
     else
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
                            src.nleaf, src.stride, nrm, pt, bc, excl, out);
@@ -2501,12 +2799,23 @@ static void sym_dispatch(int prec, int NB, hipStream_t s, int64_t njobs, const T
 }
 
 // device buffers of the candidate stage (one call)
+// Per-row record capacities of a candidate stage.  want2 sizes the wave merge (the Phase II
+// records a row is expected to hold at most); cap2 is the row's Phase II record area.  In
+// bucket mode (S > 0) the area is nT2 buckets of S records, one per Phase II tree, then an
+// overflow list of capO records.
+struct RecLayout {
+    int lcap = 0, want2 = 0, cap2 = 0;
+    int S = 0, nT2 = 0, capO = 0;
+};
+
 struct CandWs {
     int lcap = 0, cap1 = 0, cap2 = 0;
+    RecLayout lay;
     uint8_t *region = nullptr;  // Phase I index / lb / ub arrays, then the Phase II records
     float *tau = nullptr;
     int32_t *cnt = nullptr, *lcnt = nullptr, *fb_list = nullptr, *fb_cnt = nullptr;
     Ent *list = nullptr;
+    uint8_t *bcnt = nullptr;    // bucket mode: per-(row, Phase II tree) record counts
 };
 
 // Per-row capacities of the merged list and of the Phase II records, from K and the number
@@ -2528,12 +2837,69 @@ static void cand_caps(int K, int T, int B, int64_t rows, int &lcap, int &cap2) {
     }
 }
 
+// Bucket mode: the all-points symmetric tiles, where one block holds every pair of a row in
+// its tree, so a row's records of one tree are ranked in LDS and need no device-scope atomic.
+// A row's records in one tree are about its neighbours among the leaf's rows, so they grow
+// with K: S = the power of two at or above K within [16, 64], halved (to 4 at least) until
+// the area fits kBucketBudget; the overflow list holds max(128, 2K).  Each bucket's count is
+// a byte.
+constexpr int kMaxBucketTrees = 128;   // buckets per row (two per lane of the merge's wave)
+constexpr int kBucketOverflow = 128;   // overflow records per row, at least
+constexpr uint64_t kBucketBudget = (uint64_t)40 << 30;
+
+// RPF_BUCKET_S (1 .. 16) fixes the bucket size instead, so that tests can drive most records
+// through the overflow list and its hand-over to the block merge and the exhaustive path.
+static int bucket_size_override() {
+    const char *e = getenv("RPF_BUCKET_S");
+    const int v = e ? atoi(e) : 0;
+    return v >= 1 && v <= 16 ? v : 0;
+}
+
+static RecLayout rec_layout(int K, int T, int B, int64_t rows, bool buckets) {
+    RecLayout r;
+    cand_caps(K, T, B, rows, r.lcap, r.cap2);
+    r.want2 = r.cap2;
+    const int nT2 = T - B;
+    if (buckets && nT2 >= 1 && nT2 <= kMaxBucketTrees) {
+        const int forced = bucket_size_override();
+        const int capO = std::max(kBucketOverflow, 2 * K);
+        int S0 = 16;
+        while (S0 < K && S0 < 64) S0 *= 2;
+        for (int S = forced ? forced : S0; S >= (forced ? forced : 4); S /= 2) {
+            const int cap2 = nT2 * S + capO;
+            if ((uint64_t)std::max<int64_t>(rows, 1) * cap2 * sizeof(Ent) <= kBucketBudget) {
+                r.S = S;
+                r.nT2 = nT2;
+                r.capO = capO;
+                r.cap2 = cap2;
+                break;
+            }
+            if (forced) break;
+        }
+    }
+    return r;
+}
+
+static bool phase2_buckets(const ForestView &v, const CandStage &cs) {
+    return cs.all_points && cs.sym && v.sym_prec != RPF_DIST_U8GRID;
+}
+
+static RecLayout stage_layout(const ForestView &v, const CandStage &cs, int K) {
+    return rec_layout(K, v.T, cs.B, cs.rows, phase2_buckets(v, cs));
+}
+
+static void set_layout(CandWs &w, const RecLayout &lay) {
+    w.lay = lay;
+    w.lcap = lay.lcap;
+    w.cap2 = lay.cap2;
+}
+
 // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
 // threshold of the union of those leaves.  `get` hands out device bytes (nullptr = failure).
 template <typename Get>
 static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
-    cand_caps(K, v.T, cs.B, rows, w.lcap, w.cap2);
+    set_layout(w, stage_layout(v, cs, K));
     w.cap1 = slot_stride(v.max_leaf) * cs.B;  // Phase I slots per row (bounds)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
     const size_t first_bytes = (size_t)rows * w.cap1 * 4 + (size_t)rows * cs.B * 4;  // slots, leaf starts
@@ -2545,7 +2911,8 @@ static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get g
     w.lcnt = static_cast<int32_t *>(get(rows * 4));
     w.fb_list = static_cast<int32_t *>(get(rows * 8));  // fallback rows, then block-merge rows
     w.fb_cnt = static_cast<int32_t *>(get(16));
-    return w.region && w.tau && w.cnt && w.list && w.lcnt && w.fb_list && w.fb_cnt;
+    if (w.lay.S) w.bcnt = static_cast<uint8_t *>(get((size_t)rows * w.lay.nT2));
+    return w.region && w.tau && w.cnt && w.list && w.lcnt && w.fb_list && w.fb_cnt && (!w.lay.S || w.bcnt);
 }
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t count, uint32_t value) {
@@ -2622,6 +2989,11 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     o1.plub = plub;
     o1.roff = roff;
     o1.nrows = rows;
+    o1.bcnt = nullptr;
+    o1.t1 = 0;
+    o1.S = 0;
+    o1.nT2 = 0;
+    o1.capO = 0;
     const bool grid = v.sym_prec == RPF_DIST_U8GRID && cs.all_points;
     auto grid_launch = [&](const TileJob *jobs, int64_t njobs, const TileOut &o) {
         if (njobs <= 0) return;
@@ -2671,6 +3043,13 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         o2.cap = cap2;
         o2.tau = tau;
         o2.ent = ent;
+        if (w.lay.S) {  // rows' records in per-tree buckets (k_tile_sym only)
+            o2.bcnt = w.bcnt;
+            o2.t1 = cs.B;
+            o2.S = w.lay.S;
+            o2.nT2 = w.lay.nT2;
+            o2.capO = w.lay.capO;
+        }
         ProfScope ps(s, "tile_phase2", cs.bytes1, cs.flops1);
         if (grid)
             grid_launch(cs.jobs1, cs.njobs1, o2);
@@ -2688,18 +3067,24 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     fa.out_dist = out_dist; fa.fb_list = fb_list; fa.fb_cnt = fb_cnt; fa.npts = v.n;
     fa.stats = v.stats;
     fa.fault = v.fault;
+    fa.bcnt = w.lay.S ? w.bcnt : nullptr;
+    fa.S = w.lay.S;
+    fa.nT2 = w.lay.nT2;
+    fa.capO = w.lay.capO;
     const bool vec = (v.d % 4) == 0;
     {
         ProfScope ps(s, "final_rerank", 0, 0);
         const size_t lds = 4 * sizeof(float) * (size_t)((v.d + 3) & ~3);
         const dim3 grid((unsigned)((rows + 3) / 4));
         // the smallest per-lane record count that holds the list and the Phase II records
-        const int need = lcap + cap2;
+        // a row is expected to have (in bucket mode the record area is larger than that)
+        const int need = lcap + w.lay.want2;
         // records per lane of the wave merge: the smallest that holds the capacity, at most 12;
         // 16 for bf16 / fp16 tiles when the capacity passes 1024 (their looser bounds emit more
         // records per row, which would otherwise send many rows to the slower block merge)
         const int wq = need <= 256 ? 4 : need <= 512 ? 8 : (need > 1024 && v.prec != RPF_DIST_FP32) ? 16 : 12;
-        fa.big_list = need > 64 * wq ? fb_list + rows : nullptr;  // second half of the row lists
+        // second half of the row lists; in bucket mode any row may outgrow the wave merge
+        fa.big_list = (need > 64 * wq || w.lay.S) ? fb_list + rows : nullptr;
         fa.big_cnt = fb_cnt + 1;
         if (need > kFinalCap && K > 64) {  // one block per row
             if (vec) hipLaunchKernelGGL((k_final_blk<true, false>), dim3((unsigned)rows), dim3(256), lds / 4, s, fa);
@@ -2833,19 +3218,20 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
     KnnShared *p = new KnnShared();
     p->K = K;
     p->excl = exclude_self;
-    size_t b_region = 0, b_rows = 0, b_list = 0;
+    size_t b_region = 0, b_rows = 0, b_list = 0, b_bcnt = 0;
     for (size_t i = 0; i < parts.size(); i++) {
         const ForestView v = view(parts[i]);
         const CandStage cs = all_points_stage(v, K, exclude_self, maxB[i]);
-        int lcap = 0, cap2 = 0;
-        cand_caps(K, v.T, cs.B, v.n, lcap, cap2);
         // capacities grow with B for cap1 and shrink for cap2: take each over 1..B
         for (int B = 1; B <= cs.B; B++) {
-            cand_caps(K, v.T, B, v.n, lcap, cap2);
+            CandStage cb = cs;
+            cb.B = B;
+            const RecLayout lay = stage_layout(v, cb, K);
             const size_t cap1 = (size_t)slot_stride(v.max_leaf) * B;
             b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 4 + (size_t)v.n * B * 4,
-                                                   (size_t)v.n * cap2 * sizeof(Ent)) + 256);
-            b_list = std::max(b_list, (size_t)v.n * lcap * sizeof(Ent));
+                                                   (size_t)v.n * lay.cap2 * sizeof(Ent)) + 256);
+            b_list = std::max(b_list, (size_t)v.n * lay.lcap * sizeof(Ent));
+            if (lay.S) b_bcnt = std::max(b_bcnt, (size_t)v.n * lay.nT2);
         }
         b_rows = std::max(b_rows, (size_t)v.n * 4);
     }
@@ -2862,7 +3248,8 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
     w.lcnt = static_cast<int32_t *>(get(b_rows));
     w.fb_list = static_cast<int32_t *>(get(2 * b_rows));  // fallback rows, then block-merge rows
     w.fb_cnt = static_cast<int32_t *>(get(16));
-    if (!w.region || !w.tau || !w.cnt || !w.list || !w.lcnt || !w.fb_list || !w.fb_cnt) {
+    if (b_bcnt) w.bcnt = static_cast<uint8_t *>(get(b_bcnt));
+    if (!w.region || !w.tau || !w.cnt || !w.list || !w.lcnt || !w.fb_list || !w.fb_cnt || (b_bcnt && !w.bcnt)) {
         knn_shared_destroy(p, s);
         return nullptr;
     }
@@ -2879,7 +3266,7 @@ void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *ou
     const ForestView v = view(f);
     const CandStage cs = all_points_stage(v, p->K, p->excl, B);
     CandWs w = p->w;
-    cand_caps(p->K, v.T, cs.B, v.n, w.lcap, w.cap2);
+    set_layout(w, stage_layout(v, cs, p->K));
     w.cap1 = slot_stride(v.max_leaf) * cs.B;
     cand_launches(v, cs, p->K, w, out_idx, out_dist, s);
 }

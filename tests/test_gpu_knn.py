@@ -174,3 +174,51 @@ def test_single_leaf_is_brute_force():
     gi, gd = f.all_knn(10)
     bi, bd = oracle.bruteforce(x, x, 10, np.arange(500))
     _compare(gi.cpu().numpy(), gd.cpu().numpy(), bi, bd)
+
+
+# Phase II records of the all-points symmetric tiles go to one bucket per (row, tree), the
+# excess to a per-row overflow list.  Tiny buckets (RPF_BUCKET_S) send most records through
+# the overflow list, and rows whose overflow list fills up on to the block merge or the
+# exhaustive path; every result must still equal the oracle's.
+BUCKETS = [
+    ("bucket1_leaves244_fp32", 7800, 128, 12, 256, 20, "fp32", "aniso", 0, 1, 1),
+    ("bucket2_leaves244_split", 7800, 128, 12, 256, 20, "bf16x3", "aniso", 0, 1, 2),
+    ("bucket1_duplicates_bf16", 6000, 8, 10, 30, 8, "bf16", "mixture", 5, 1, 1),
+    ("bucket3_big_k", 12000, 16, 12, 200, 100, "fp32", "mixture", 0, 1, 3),
+]
+
+
+@pytest.mark.parametrize("case", BUCKETS, ids=[c[0] for c in BUCKETS])
+def test_small_buckets_match_oracle(case, monkeypatch):
+    name, n, d, T, n0, K, prec, kind, dup, excl, S = case
+    print(f"[buckets] {name} n={n} d={d} T={T} n0={n0} K={K} {prec} S={S}", flush=True)
+    monkeypatch.setenv("RPF_BUCKET_S", str(S))
+    x, R = problem(n, d, T, n0, seed=len(name) + 400, kind=kind, dup_every=dup)
+    ref = oracle.build_forest(x, R, T, n0)
+    ri, rd = oracle.all_knn(ref, K, exclude_self=bool(excl))
+    f = _gpu_forest(x, R, T, n0, prec=prec)
+    gi, gd = f.all_knn(K, exclude_self=bool(excl))
+    torch.cuda.synchronize()
+    _compare(gi.cpu().numpy(), gd.cpu().numpy(), ri, rd)
+    st = f.knn_stats()
+    print(f"    stats {st}", flush=True)
+    f.free()
+
+
+def test_rerank_set_is_reproducible():
+    # the dedup keeps every index's smallest ub and admits an index to the rerank set when any
+    # copy's lb is below the threshold, so neither depends on which copy of an index the hash
+    # saw first: repeated calls rerank exactly the same number of candidates
+    x, R = problem(7800, 128, 10, 256, seed=91, kind="aniso")
+    for prec in ("bf16", "bf16x3"):
+        f = _gpu_forest(x, R, 10, 256, prec=prec)
+        runs = []
+        for _ in range(3):
+            i, _d = f.all_knn(20)
+            torch.cuda.synchronize()
+            st = f.knn_stats()
+            runs.append((st["reranked32"], st["reranked64"], st["second_phase_emitted"], i.cpu().numpy()))
+        for r in runs[1:]:
+            assert r[:3] == runs[0][:3], (prec, [q[:3] for q in runs])
+            np.testing.assert_array_equal(r[3], runs[0][3])
+        f.free()
