@@ -104,7 +104,7 @@ typedef struct {
                             spread of projections is used (Alg. 2); 1 = basic rpTree        */
     int32_t split_rule;  /* rpf_split                                                       */
     int32_t dist_prec;   /* rpf_dist_prec for the candidate tiles                           */
-    int32_t reserved;    /* must be 0                                                       */
+    int32_t build_flags; /* 0, or RPF_BUILD_SUBTREES (see below); the median rule only      */
     const float *directions_dev; /* random directions (Alg. 1 and Alg. 2), binary32
                             [n_trees][2^L - 1][n_try][d], row h-1 for heap node h (root 1,
                             children 2h, 2h+1), L = rpf_depth(n, leaf_size).  Required by the
@@ -115,6 +115,18 @@ typedef struct {
     uint64_t seed;       /* RPF_SPLIT_UNIFORM: key of the counter-based generator (any value);
                             ignored by the median rule                                      */
 } rpf_params;
+
+/* Build schedule (a performance choice only: the forest is bit-identical either way).
+ * 0: level-synchronous, one launch group per level (levels paired so that one read of X
+ *    serves two levels, where the shapes allow).
+ * RPF_BUILD_SUBTREES: the levels from the first one whose nodes all fit one workgroup
+ *    (at most 4096 members) down to the leaves run as ONE persistent launch: a fixed grid of
+ *    resident workgroups takes (tree, node) items from a device counter and grows each
+ *    item's whole subtree inside the workgroup, level by level, its permutation segment held
+ *    in LDS.  Fewer launches and no global step between those levels, at the price of one
+ *    read of X per level there.  Used only with n_try = 1 and at least two such levels;
+ *    otherwise the flag is ignored.  rpf_plan_tune picks the schedule per part. */
+#define RPF_BUILD_SUBTREES 1
 
 /* Tree depth L = number of split levels for n points and leaf size n0 (host only). */
 int32_t rpf_depth(int64_t n, int32_t leaf_size);

@@ -206,6 +206,204 @@ __global__ __launch_bounds__(256) void k_level_small(
     }
 }
 
+// ================================================================ small subtrees: one persistent launch
+
+// One internal node of a subtree, by the whole block (256 threads), nTry = 1: project the
+// members s_perm[0 .. m) onto the node's direction r (binary64, canonical order), select the
+// member of rank floor(m/2) in (p, index) order, and write the stable partition to s_out.
+// The same operations, in the same order, as k_level_small on a one-direction level.
+template <bool VEC>
+__device__ inline void subtree_node(const float *__restrict__ X, int d, const float *__restrict__ r,
+                                    const int32_t *s_perm, int32_t *s_out, int m, uint64_t *s_key, float *s_r,
+                                    uint32_t *s_hist, uint32_t *s_misc, double *split_out, int32_t *split_idx_out,
+                                    int32_t *chosen_out, int32_t *err) {
+    const int tid = threadIdx.x;
+    for (int j = tid; j < d; j += blockDim.x) s_r[j] = r[j];
+    __syncthreads();
+    {
+        const int g = tid & 7, pt = tid >> 3;
+        for (int base = 0; base < m; base += 32) {
+            const int i = base + pt;
+            const double p = group8_dot64<VEC>(X + (int64_t)s_perm[i < m ? i : 0] * d, s_r, d, g);
+            if (g == 0 && i < m) s_key[i] = key_of(p);
+        }
+    }
+    __syncthreads();
+    uint64_t phi = 0;
+    uint32_t plo = 0;
+    int nbits = 0;
+    uint32_t rank = (uint32_t)(m / 2), cnt = (uint32_t)m;
+    while (cnt > 1 && nbits < 96) {
+        const int lo_bit = 88 - nbits;
+        const unsigned __int128 P = key96(phi, plo);
+        s_hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < m; i += blockDim.x) {
+            const unsigned __int128 K = key96(s_key[i], (uint32_t)s_perm[i]);
+            if (nbits == 0 || (K >> (96 - nbits)) == (P >> (96 - nbits)))
+                atomicAdd(&s_hist[(uint32_t)(K >> lo_bit) & 255u], 1u);
+        }
+        __syncthreads();
+        const uint32_t v = s_hist[tid];
+        uint32_t excl, total;
+        block_excl_scan256(v, s_misc, excl, total);
+        if (excl <= rank && rank < excl + v) {
+            s_misc[8] = tid;
+            s_misc[9] = excl;
+            s_misc[10] = v;
+        }
+        __syncthreads();
+        const uint32_t b = s_misc[8];
+        rank -= s_misc[9];
+        cnt = s_misc[10];
+        const unsigned __int128 NP = P | ((unsigned __int128)b << lo_bit);
+        phi = (uint64_t)(NP >> 32);
+        plo = (uint32_t)NP;
+        nbits += 8;
+        __syncthreads();
+    }
+    if (nbits < 96) {  // exactly one key matches the prefix: it is the median
+        const unsigned __int128 P = key96(phi, plo);
+        for (int i = tid; i < m; i += blockDim.x) {
+            const unsigned __int128 K = key96(s_key[i], (uint32_t)s_perm[i]);
+            if ((K >> (96 - nbits)) == (P >> (96 - nbits))) {
+                s_misc[12] = (uint32_t)s_key[i];
+                s_misc[13] = (uint32_t)(s_key[i] >> 32);
+                s_misc[14] = (uint32_t)s_perm[i];
+            }
+        }
+        __syncthreads();
+        phi = ((uint64_t)s_misc[13] << 32) | s_misc[12];
+        plo = s_misc[14];
+    }
+    const int half = m / 2;
+    uint32_t lefts = 0;
+    for (int base = 0; base < m; base += 256) {
+        const int i = base + tid;
+        const bool valid = i < m;
+        const bool left = valid && key_less(s_key[i], (uint32_t)s_perm[i], phi, plo);
+        uint32_t excl, total;
+        block_excl_scan256(left ? 1u : 0u, s_misc, excl, total);
+        if (valid) {
+            const uint32_t lb = lefts + excl;
+            const int pos = left ? (int)lb : half + (i - (int)lb);
+            if (pos >= 0 && pos < m) s_out[pos] = s_perm[i];  // always in range when the select is consistent
+        }
+        lefts += total;
+    }
+    if (tid == 0) {
+        *split_out = val_of(phi);
+        *split_idx_out = (int32_t)plo;
+        *chosen_out = 0;
+        if (lefts != (uint32_t)half) atomicOr(err, 1);
+    }
+    __syncthreads();
+}
+
+// Persistent launch over the small levels: a fixed grid of resident blocks takes items (tree,
+// internal node of the first small level) from a device counter until none is left, and
+// grows each item's whole subtree inside the block, level by level (a node's children only
+// after its partition: the level dependencies stay inside the block).  The item's permutation
+// segment stays in LDS (two buffers, one per level parity) and is written once, in leaf order,
+// to perm_out.  Every block leaves the loop when the counter passes the item count.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_subtree(const float *__restrict__ X, int d, const float *__restrict__ R,
+                                                 int64_t H, const SubItem *__restrict__ items, int nitems, int T,
+                                                 int n0, const int32_t *__restrict__ perm_in,
+                                                 int32_t *__restrict__ perm_out, int64_t n,
+                                                 double *__restrict__ split, int32_t *__restrict__ split_idx,
+                                                 int32_t *__restrict__ chosen, int32_t *__restrict__ err,
+                                                 uint32_t *__restrict__ next, int max_m) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int mp = (max_m + 3) & ~3;
+    int32_t *s_pa = reinterpret_cast<int32_t *>(smem);
+    int32_t *s_pb = s_pa + mp;
+    uint64_t *s_key = reinterpret_cast<uint64_t *>(s_pb + mp);
+    float *s_r = reinterpret_cast<float *>(s_key + mp);
+    uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_r + ((d + 3) & ~3));
+    uint32_t *s_misc = s_hist + 256;  // 16 words; [15] = the block's current item
+    const int tid = threadIdx.x;
+    const uint32_t total = (uint32_t)nitems * (uint32_t)T;
+    while (true) {
+        if (tid == 0) s_misc[15] = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t w = s_misc[15];
+        __syncthreads();
+        if (w >= total) break;
+        const int t = (int)(w / (uint32_t)nitems);
+        const SubItem it = items[w % (uint32_t)nitems];
+        const int m0 = it.size;
+        int32_t *pa = s_pa, *pb = s_pb;
+        const int32_t *pin = perm_in + (int64_t)t * n + it.off;
+        for (int i = tid; i < m0; i += blockDim.x) pa[i] = pin[i];
+        for (int k = 0; k < 31; k++) {  // relative depth k: nodes j = 0 .. 2^k - 1 of the subtree
+            for (int i = tid; i < m0; i += blockDim.x) pb[i] = pa[i];  // leaves stay in place
+            __syncthreads();
+            bool any = false;
+            for (int j = 0; j < (1 << k); j++) {
+                int lo = 0, sz = m0;
+                int64_t hl = it.heap - it.hbase;  // heap id within the data set
+                bool present = true;
+                for (int b = k - 1; b >= 0; b--) {  // walk down from the item: left = floor(m/2)
+                    if (sz <= n0) {
+                        present = false;
+                        break;
+                    }
+                    const int left = sz / 2;
+                    if ((j >> b) & 1) {
+                        lo += left;
+                        sz -= left;
+                        hl = 2 * hl + 1;
+                    } else {
+                        sz = left;
+                        hl = 2 * hl;
+                    }
+                }
+                if (!present || sz <= n0) continue;
+                any = true;
+                const int64_t hs = (int64_t)t * H + (it.hbase + hl - 1);
+                subtree_node<VEC>(X, d, R + hs * d, pa + lo, pb + lo, sz, s_key, s_r, s_hist, s_misc, split + hs,
+                                  split_idx + hs, chosen + hs, err);
+            }
+            if (!any) break;
+            int32_t *tmp = pa;
+            pa = pb;
+            pb = tmp;
+        }
+        __syncthreads();
+        int32_t *pout = perm_out + (int64_t)t * n + it.off;
+        for (int i = tid; i < m0; i += blockDim.x) pout[i] = pa[i];
+        __syncthreads();
+    }
+}
+
+size_t subtree_lds(int max_m, int d) {
+    const size_t mp = (size_t)((max_m + 3) & ~3);
+    return mp * 4 * 2 + mp * 8 + (size_t)((d + 3) & ~3) * 4 + 4 * (256 + 16);
+}
+
+void launch_subtree(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, const SubItem *items,
+                    int nitems, int T, int n0, const int32_t *pin, int32_t *pout, int64_t n, double *split,
+                    int32_t *split_idx, int32_t *chosen, int32_t *err, uint32_t *next, int max_m, int lds_limit) {
+    if (nitems <= 0) return;
+    const size_t lds = subtree_lds(max_m, d);
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = std::max(1, std::min(8, (int)((size_t)lds_limit / std::max<size_t>(lds, 1))));
+    const int64_t total = (int64_t)nitems * T;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)std::max(cus, 1) * per_cu));
+    fill_u32(next, 1, 0, s);
+    auto go = [&](auto kern) {
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, X, d, R, H, items, nitems, T, n0, pin, pout, n, split,
+                           split_idx, chosen, err, next, max_m);
+    };
+    if (vec) go(k_subtree<true>);
+    else go(k_subtree<false>);
+    launch_check(s, "k_subtree");
+}
+
 // ================================================================ large segments
 
 template <bool VEC, bool LEAD>

@@ -292,6 +292,7 @@ struct LevelPlan {
     std::vector<ChunkDesc> chunks; // multi-block path
     std::vector<LeafDesc> copy;    // leaves formed at or before this level (carried over)
     std::vector<LookDesc> look;    // per internal node: its children at the next level
+    std::vector<int32_t> hbase;    // per internal node: its data set's first heap slot
     int max_m = 0;
     bool large = false;
     bool lead = false, fed = false;  // linked pair: the lead also makes the fed level's keys
@@ -340,6 +341,13 @@ struct rpf_forest {
     rpf::LargeBufs lb{};         // temporaries of the multi-block levels
     std::vector<void *> tmps;    // their blocks (released after a one-shot build)
     int lds_max = 0;
+    // persistent subtree schedule (RPF_BUILD_SUBTREES): levels sub_level .. L-1 in one launch
+    int sub_level = -1;          // -1: not available for this forest
+    bool subtree_on = false;     // the schedule build_launches uses
+    int sub_max_m = 0;
+    int64_t n_sub_items = 0;
+    rpf::SubItem *d_sub_items = nullptr;
+    uint32_t *sub_next = nullptr;  // the launch's work counter
     // batched forests: one root per data set (a single data set is the one-root case)
     std::vector<rpf_batch_entry> batch;
     int64_t *d_batch_off = nullptr;       // [count + 1] first point of every data set, then n
@@ -462,7 +470,8 @@ static void pin_give(int k) {
 static void free_forest_memory(rpf_forest *f) {
     void *ptrs[] = {f->X, f->R, f->split, f->split_idx, f->chosen, f->perm[0], f->perm[1], f->leaf_of,
                     f->centroid, f->Xc, f->nrm, f->err, f->heap_leaf, f->d_segs, f->d_chunks, f->d_leaves,
-                    f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off, f->Xq, f->qn};
+                    f->d_copy, f->d_look, f->d_jobs, f->stats, f->d_batch_off, f->Xq, f->qn, f->d_sub_items,
+                    f->sub_next};
     for (void *p : ptrs) cache_free_idle(p);
     pin_give(f->pin_slot);
     f->pin_slot = -1;
@@ -511,7 +520,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
                                     : "rpf_build: unknown split_rule");
     if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_U8GRID)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
-    if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
+    if (p->build_flags & ~RPF_BUILD_SUBTREES) return fail(RPF_EINVAL, "rpf_build: unknown build_flags");
     std::vector<rpf_batch_entry> roots(count);
     int L = 0;
     int64_t H = 0, LB = 0;
@@ -553,6 +562,7 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
                 if (nd.size > n0 && l < r.depth) {
                     node_seg[q] = (int32_t)levels[l].segs.size();
                     levels[l].segs.push_back(SegDesc{nd.off, (int32_t)nd.size, (int32_t)(r.heap_base + nd.heap), 0, 0});
+                    levels[l].hbase.push_back((int32_t)r.heap_base);
                     levels[l].max_m = std::max<int>(levels[l].max_m, (int)nd.size);
                     next.push_back({2 * nd.heap, nd.off, nd.size / 2, nd.root});
                     next.push_back({2 * nd.heap + 1, nd.off + nd.size / 2, nd.size - nd.size / 2, nd.root});
@@ -615,6 +625,21 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
             any_link = true;
             any_large_fed |= b.large;
         }
+
+    // ---- the persistent subtree schedule: from the first level after which every level fits
+    // one workgroup (a fed level stays level-synchronous: its keys come from the level above),
+    // when at least two levels remain
+    int sub_level = -1;
+    if (n_try == 1) {
+        int l0 = L;
+        while (l0 > 0 && !levels[l0 - 1].large) l0--;
+        if (l0 < L && levels[l0].fed) l0++;
+        int mm = 0;
+        for (int l = l0; l < L; l++) mm = std::max(mm, levels[l].max_m);
+        if (l0 + 2 <= L && !levels[l0].segs.empty() && (int64_t)levels[l0].segs.size() * T < ((int64_t)1 << 31) &&
+            subtree_lds(mm, d) <= (size_t)lds_max)
+            sub_level = l0;
+    }
 
     // ---- memory plan
     // split bfloat16 and int8 grid tiles run beside binary32 copies and norms: the forest is a
@@ -706,6 +731,21 @@ static rpf_status prepare_forest(const int64_t *sizes, int count, int32_t d, con
     RPF_ALLOC(f->d_leaves, nleaf * sizeof(LeafDesc));
     if (ncopy_tot) RPF_ALLOC(f->d_copy, ncopy_tot * sizeof(LeafDesc));
     if (nseg_tot && any_link) RPF_ALLOC(f->d_look, nseg_tot * sizeof(LookDesc));
+    std::vector<SubItem> sub_items;
+    if (sub_level >= 0) {
+        const LevelPlan &lv = levels[sub_level];
+        for (size_t k = 0; k < lv.segs.size(); k++)
+            sub_items.push_back(SubItem{lv.segs[k].off, lv.segs[k].size, lv.segs[k].heap, lv.hbase[k], 0});
+        int mm = 0;
+        for (int l = sub_level; l < L; l++) mm = std::max(mm, levels[l].max_m);
+        RPF_ALLOC(f->d_sub_items, sub_items.size() * sizeof(SubItem));
+        RPF_ALLOC(f->sub_next, 16);
+        f->sub_level = sub_level;
+        f->sub_max_m = mm;
+        f->n_sub_items = (int64_t)sub_items.size();
+        f->subtree_on = (p->build_flags & RPF_BUILD_SUBTREES) != 0;
+        hipMemcpyAsync(f->d_sub_items, sub_items.data(), sub_items.size() * sizeof(SubItem), hipMemcpyHostToDevice, s);
+    }
 
     // ---- descriptors (host copies stay alive until the synchronisation below)
     std::vector<SegDesc> all_segs;
@@ -827,6 +867,18 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
         int32_t *pout = f->perm[cur ^ 1];
         launch_copy_segments(s, f->d_copy + lv.copy_off, (int)lv.copy.size(), T, pin, pout, n);
         launch_check(s, "copy_segments");
+        if (f->subtree_on && (int)l == f->sub_level) {
+            // this level and every one below it: one persistent launch, leaf order in pout
+            double bytes = 0;
+            for (size_t k = l; k < f->levels.size(); k++)
+                for (auto &sg : f->levels[k].segs) bytes += (double)T * sg.size * (4.0 * d + 4 + 8);
+            ProfScope ps(s, "subtree_levels", bytes, 0);
+            launch_subtree(s, vec, f->X, d, f->R, H, f->d_sub_items, (int)f->n_sub_items, T, f->n0, pin, pout, n,
+                           f->split, f->split_idx, f->chosen, f->err, f->sub_next, f->sub_max_m, f->lds_max);
+            launch_check(s, "subtree");
+            cur ^= 1;
+            break;
+        }
         int64_t members = 0;
         for (auto &sg : lv.segs) members += sg.size;
         LevelLink lk;
@@ -1023,7 +1075,7 @@ static rpf_status build_uniform(const float *X, int64_t n, int32_t d, const rpf_
     if (p->n_try < 1) return fail(RPF_EINVAL, "rpf_build: n_try must be >= 1");
     if (p->dist_prec < RPF_DIST_FP32 || p->dist_prec > RPF_DIST_U8GRID)
         return fail(RPF_EINVAL, "rpf_build: unknown dist_prec");
-    if (p->reserved != 0) return fail(RPF_EINVAL, "rpf_build: reserved must be 0");
+    if (p->build_flags & ~RPF_BUILD_SUBTREES) return fail(RPF_EINVAL, "rpf_build: unknown build_flags");
     const int64_t T = p->n_trees, TN = T * n;
     if (TN >= ((int64_t)1 << 40)) return fail(RPF_EINVAL, "rpf_build: n_trees * n too large");
     const int n0 = p->leaf_size, n_try = p->n_try;

@@ -107,6 +107,19 @@ struct LevelLink {
     bool roots = false;  // lead at the roots (identity permutation): one read of X for all trees
 };
 
+struct SubItem {       // an internal node at the first level of the persistent subtree launch
+    int64_t off;      // first position in the node-ordered permutation
+    int32_t size;     // members (at most the one-block segment size)
+    int32_t heap;     // heap id, global (hbase + id within its data set)
+    int32_t hbase;    // the data set's first heap slot (0 for a single data set)
+    int32_t pad;
+};
+
+size_t subtree_lds(int max_m, int d);
+void launch_subtree(hipStream_t s, bool vec, const float *X, int d, const float *R, int64_t H, const SubItem *items,
+                    int nitems, int T, int n0, const int32_t *pin, int32_t *pout, int64_t n, double *split,
+                    int32_t *split_idx, int32_t *chosen, int32_t *err, uint32_t *next, int max_m, int lds_limit);
+
 struct LargeBufs {     // temporaries of the multi-block level path (and of the level links)
     uint64_t *keys;
     uint64_t *keys2;      // keys made one level ahead

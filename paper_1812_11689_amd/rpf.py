@@ -37,7 +37,7 @@ class RpfError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("n_trees", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("n_try", ctypes.c_int32),
-                ("split_rule", ctypes.c_int32), ("dist_prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("split_rule", ctypes.c_int32), ("dist_prec", ctypes.c_int32), ("build_flags", ctypes.c_int32),
                 ("directions_dev", ctypes.c_void_p), ("mem_budget_bytes", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64)]
 
@@ -346,13 +346,16 @@ def exact_knn(X: torch.Tensor, Q: torch.Tensor, K: int, self_idx: torch.Tensor |
 SPLIT = {"median": 0, "uniform": 1}
 
 
+BUILD_SUBTREES = 1  # RPF_BUILD_SUBTREES: the small levels in one persistent launch
+
+
 def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
           dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None, split_rule: str = "median",
-          seed: int = 0) -> Forest:
+          seed: int = 0, subtrees: bool = False) -> Forest:
     """Grow a forest over X (float32 [n][d] on the device).  Median rule: with the given
     directions (float32 [n_trees][2^L-1][n_try][d] on the device, L = depth(n, leaf_size)).
     Uniform rule (split_rule="uniform"): directions None, the random numbers come from the
-    library's counter-based generator keyed by `seed`."""
+    library's counter-based generator keyed by `seed`.  subtrees: RPF_BUILD_SUBTREES."""
     X = _dev(X, torch.float32)
     n, d = X.shape
     rule = SPLIT[split_rule]
@@ -362,7 +365,8 @@ def build(X: torch.Tensor, n_trees: int, leaf_size: int, directions: torch.Tenso
         directions = _dev(directions, torch.float32)
         dptr = directions.data_ptr()
     p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=rule,
-               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec),
+               build_flags=BUILD_SUBTREES if subtrees else 0,
                directions_dev=dptr, mem_budget_bytes=mem_budget_bytes, seed=seed & (2**64 - 1))
     h = ctypes.c_void_p()
     _check(load().rpf_build(X.data_ptr(), n, d, ctypes.byref(p), _stream(stream), ctypes.byref(h)))
@@ -404,7 +408,8 @@ def batched_directions_rows(sizes, leaf_size: int):
 
 
 def build_batched(Xs, n_trees: int, leaf_size: int, directions: torch.Tensor | None, n_try: int = 1,
-                  dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None) -> BatchedForest:
+                  dist_prec: str = "fp32", mem_budget_bytes: int = 0, stream=None,
+                  subtrees: bool = False) -> BatchedForest:
     """Grow one forest per data set (same d) in shared launches.  Xs: list of float32 [n_i][d]
     device tensors (or one concatenated tensor with `sizes` given as a list of (X, n) pairs);
     directions: float32 [n_trees][sum H_i][n_try][d] on the device (see batched_directions_rows)."""
@@ -418,7 +423,8 @@ def build_batched(Xs, n_trees: int, leaf_size: int, directions: torch.Tensor | N
         directions = _dev(directions, torch.float32)
         dptr = directions.data_ptr()
     p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
-               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+               dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec),
+               build_flags=BUILD_SUBTREES if subtrees else 0,
                directions_dev=dptr, mem_budget_bytes=mem_budget_bytes)
     ns = (ctypes.c_int64 * len(sizes))(*sizes)
     h = ctypes.c_void_p()
@@ -454,7 +460,7 @@ class Plan:
         self.dims = [int(d) for d in dims] if not isinstance(dims, int) else [int(dims)] * len(self.sizes)
         self.n_trees, self.leaf_size, self.n_try, self.K = n_trees, leaf_size, n_try, K
         p = Params(n_trees=n_trees, leaf_size=leaf_size, n_try=n_try, split_rule=0,
-                   dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), reserved=0,
+                   dist_prec=PREC[dist_prec] if isinstance(dist_prec, str) else int(dist_prec), build_flags=0,
                    directions_dev=None, mem_budget_bytes=0)
         c = len(self.sizes)
         ns = (ctypes.c_int64 * c)(*self.sizes)

@@ -36,7 +36,7 @@ def test_depth_matches_oracle(n, n0):
 
 def test_invalid_arguments_rejected_without_device():
     lib = rpf.load()
-    p = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, reserved=0,
+    p = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, build_flags=0,
                    directions_dev=None, mem_budget_bytes=0)
     h = ctypes.c_void_p(1234)
     fake = ctypes.c_void_p(0x1000)
@@ -47,13 +47,13 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.rpf_build(fake, 100, 0, ctypes.byref(p), None, ctypes.byref(h)) == rpf.RPF_EINVAL
     for rule in (0, 1):
         for field, bad in [("n_trees", 0), ("leaf_size", 0), ("n_try", 0), ("split_rule", 2), ("dist_prec", 7),
-                           ("reserved", 1)]:
-            q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=rule, dist_prec=0, reserved=0,
+                           ("build_flags", 2)]:
+            q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=rule, dist_prec=0, build_flags=0,
                            directions_dev=0x2000, mem_budget_bytes=0)
             setattr(q, field, bad)
             assert lib.rpf_build(fake, 100, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_EINVAL, field
     # the uniform rule grows one data set per forest: no batches
-    q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=1, dist_prec=0, reserved=0,
+    q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=1, dist_prec=0, build_flags=0,
                    directions_dev=None, mem_budget_bytes=0, seed=5)
     sizes = (ctypes.c_int64 * 2)(50, 50)
     assert lib.rpf_build_batched(fake, sizes, 2, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_EINVAL
@@ -67,7 +67,7 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.rpf_build(fake, 100, 4, ctypes.byref(p), None, ctypes.byref(h)) == rpf.RPF_EINVAL
     assert b"directions" in lib.rpf_last_error()
     # budget below the plan
-    q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, reserved=0,
+    q = rpf.Params(n_trees=4, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, build_flags=0,
                    directions_dev=0x2000, mem_budget_bytes=1000)
     assert lib.rpf_build(fake, 100, 4, ctypes.byref(q), None, ctypes.byref(h)) == rpf.RPF_ENOMEM
     assert lib.rpf_free(None) == rpf.RPF_OK
@@ -106,7 +106,7 @@ def test_server_and_workspace_arguments_rejected_without_device():
 
 def test_plan_arguments_rejected_without_device():
     lib = rpf.load()
-    p = rpf.Params(n_trees=2, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, reserved=0,
+    p = rpf.Params(n_trees=2, leaf_size=10, n_try=1, split_rule=0, dist_prec=0, build_flags=0,
                    directions_dev=None, mem_budget_bytes=0)
     h = ctypes.c_void_p(1234)
     ns = (ctypes.c_int64 * 2)(100, 200)

@@ -17,20 +17,23 @@ def _sets(seed, sizes, d, clusters=6):
     return [W.gaussian_mixture(seed + i, n, d, clusters) for i, n in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("prec,d,sizes", [
-    ("fp16", 24, [300, 1500, 4000, 77, 2500, 10_000, 41]),
-    ("fp32", 8, [2000, 130, 6000, 999]),
-    ("bf16", 64, [5000, 800, 3000]),
+@pytest.mark.parametrize("prec,d,sizes,subtrees", [
+    ("fp16", 24, [300, 1500, 4000, 77, 2500, 10_000, 41], False),
+    ("fp32", 8, [2000, 130, 6000, 999], False),
+    ("bf16", 64, [5000, 800, 3000], False),
+    # the one-block levels of every data set in one persistent launch
+    ("fp16", 24, [300, 1500, 4000, 77, 2500, 10_000, 41], True),
+    ("fp32", 33, [9000, 130, 6000, 40, 999], True),
 ])
-def test_batched_equals_each_alone(prec, d, sizes):
+def test_batched_equals_each_alone(prec, d, sizes, subtrees):
     from paper_1812_11689_amd import rpf
     T, n0, K = 3, 40, 9
-    print(f"[batched] {prec} d={d} sizes={sizes}", flush=True)
+    print(f"[batched] {prec} d={d} sizes={sizes} subtrees={subtrees}", flush=True)
     xs = _sets(700 + d, sizes, d)
     Rs = [W.directions(800 + d + i, T, heap_count(n, n0), 1, d) for i, n in enumerate(sizes)]
     R = torch.from_numpy(np.concatenate(Rs, axis=1)).cuda()
     Xs = [torch.from_numpy(x).cuda() for x in xs]
-    bf = rpf.build_batched(Xs, T, n0, R, dist_prec=prec)
+    bf = rpf.build_batched(Xs, T, n0, R, dist_prec=prec, subtrees=subtrees)
     parts = bf.all_knn_split(K)
     bf.knn_stats()  # raises on an out-of-range candidate index (internal error)
     ents = bf.entries()

@@ -55,6 +55,42 @@ def test_build_matches_oracle(case):
     f.free()
 
 
+SUBTREE_CASES = [c for c in CASES if c[5] == 1 and c[0] not in ("single_leaf", "n0_plus_1")] + [
+    # every level one-block from the root; levels of mixed leaf and internal nodes
+    ("all_small_levels", 3000, 6, 3, 10, 1, "mixture", 0),
+    ("n0_3_deep", 4000, 9, 2, 3, 1, "aniso", 0),
+]
+
+
+@pytest.mark.parametrize("case", SUBTREE_CASES, ids=[c[0] for c in SUBTREE_CASES])
+def test_subtree_schedule_matches_oracle(case):
+    # RPF_BUILD_SUBTREES: the one-block levels run as one persistent launch; the forest must be
+    # the same, bit for bit
+    from paper_1812_11689_amd import rpf
+    name, n, d, T, n0, n_try, kind, dup = case
+    print(f"[subtree] {name} n={n} d={d} T={T} n0={n0}", flush=True)
+    x, R = problem(n, d, T, n0, n_try, seed=len(name) + 50, kind=kind, dup_every=dup)
+    ref = oracle.build_forest(x, R, T, n0, n_try)
+    rpf.profile_reset()
+    rpf.profile_enable(True)
+    f = rpf.build(torch.from_numpy(x).cuda(), T, n0, torch.from_numpy(np.ascontiguousarray(R[:T])).cuda(),
+                  n_try=n_try, subtrees=True)
+    info = f.info()
+    rpf.profile_enable(False)
+    prof = rpf.profile_read()
+    if ref.L >= 2:
+        assert "subtree_levels" in prof, "the persistent launch did not run"
+    for t in range(T):
+        g = {k: v.cpu().numpy() for k, v in f.tree_dump(t).items()}
+        np.testing.assert_array_equal(g["perm"], ref.perm[t])
+        np.testing.assert_array_equal(g["leaf_of"], ref.leaf_of[t])
+        assert np.array_equal(g["split"].view(np.uint64), ref.split[t].view(np.uint64)) or \
+            np.array_equal(g["split"], ref.split[t], equal_nan=True)
+        np.testing.assert_array_equal(g["split_idx"], ref.split_idx[t])
+    assert info["depth"] == ref.L
+    f.free()
+
+
 def test_build_twice_bit_identical():
     x, R = problem(8000, 32, 3, 40, seed=5)
     a = _gpu_forest(x, R, 3, 40, 1)
