@@ -899,8 +899,12 @@ def batched_leg(args):
     res["parts"] = len(plan.parts)
     plan.launch()
     plan.check()
-    res["tuned_candidate_ms"] = round(plan.tune(), 3)
-    res["first_trees"] = [pt.get("first_trees") for pt in plan.parts]
+    res["tuned_ms"] = round(plan.tune(), 3)
+    ch = plan.choices()
+    res["first_trees"] = [c["first_trees"] for c in ch]
+    res["tile_shape"] = [c["tile_shape"] for c in ch]
+    res["bucket_size"] = [c["bucket_size"] for c in ch]
+    res["subtree_build"] = [c["subtrees"] for c in ch]
     plan.launch()
     plan.check()
     times = []

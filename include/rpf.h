@@ -180,10 +180,26 @@ rpf_status rpf_batch_info(const rpf_forest *f, int32_t index, rpf_batch_entry *o
  *     must not overlap); every launch rebuilds from the current buffer contents;
  *   rpf_plan_check: synchronises `stream`, reports non-finite inputs (RPF_EINVAL) or an
  *     internal error of the build kernels;
- *   rpf_plan_tune: launches once, then times the candidate stage of every part for several
- *     first-phase tree counts (the trees whose leaves are kept whole and set the pruning
- *     threshold), keeps the fastest per part and records the graph again; the results do
- *     not depend on the choice. */
+ *   rpf_plan_tune: launches once, then, per part, times and keeps the fastest of
+ *     - the first-phase tree count (trees whose leaves are kept whole and set the pruning
+ *       threshold): 2, 3, 4, 6 or 8;
+ *     - the Phase II tile shape of the all-points symmetric tiles, bits of tile_shape:
+ *       1 = the alternative k-chunk (binary32: 64 columns staged from X instead of 32
+ *       loaded straight into LDS behind the previous chunk's MFMAs; 16-bit tiles: 64 (split
+ *       bfloat16 32) columns instead of 128 (64)), 2 = queues of 256 candidate pairs per
+ *       wave instead of 352-512, 4 = eight waves per block instead of twelve (leaves above
+ *       128 points only);
+ *     - the Phase II bucket size: the default (from K) or half of it;
+ *     - the build schedule: level by level, or RPF_BUILD_SUBTREES;
+ *     then records the graph again and enters the choices in the process's tuning table.
+ *     No choice changes the results.
+ *   The tuning table maps a part's shape (d, largest leaf, tile precision, K, T,
+ *   floor(log2 rows)) to its choices; rpf_plan_create applies the entry of every part whose
+ *   shape it holds.  rpf_tune_save writes it to a text file, one JSON object per line
+ *   ({"d": .., "max_leaf": .., "prec": .., "K": .., "T": .., "n_log2": .., "first_trees": ..,
+ *   "tile_shape": .., "bucket_size": .., "subtrees": ..}); rpf_tune_load merges such a file
+ *   into the table (RPF_EINVAL, and the table unchanged, on a malformed line) and gives
+ *   the entry count; rpf_tune_clear empties it.  Host only. */
 typedef struct rpf_plan rpf_plan;
 
 typedef struct {
@@ -204,7 +220,9 @@ typedef struct {
     float *out_dist_dev;             /* [rows][K]                                            */
     const rpf_forest *forest;        /* not to be freed                                      */
     int32_t first_trees;             /* first-phase trees of its candidate stage             */
-    int32_t reserved;
+    int32_t tile_shape;              /* Phase II tile shape of its all-points tiles (below)  */
+    int32_t bucket_size;             /* Phase II records per (row, tree) bucket, 0 = none    */
+    int32_t subtrees;                /* 1: its small levels run as one persistent launch     */
 } rpf_plan_part_info;
 
 rpf_status rpf_plan_create(const int64_t *n_host, const int32_t *d_host, int32_t count, const rpf_params *params,
@@ -216,6 +234,9 @@ rpf_status rpf_plan_entry_of(const rpf_plan *plan, int32_t index, rpf_plan_entry
 rpf_status rpf_plan_launch(rpf_plan *plan, void *stream);
 rpf_status rpf_plan_check(rpf_plan *plan, void *stream);
 rpf_status rpf_plan_tune(rpf_plan *plan, void *stream, double *tuned_ms_host);
+rpf_status rpf_tune_save(const char *path);
+rpf_status rpf_tune_load(const char *path, int32_t *entries_host);
+rpf_status rpf_tune_clear(void);
 rpf_status rpf_plan_destroy(rpf_plan *plan);
 
 /* Internal faults of the search.  The final merge checks every candidate index it takes

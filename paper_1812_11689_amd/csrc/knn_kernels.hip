@@ -67,11 +67,13 @@ struct TileCfg<RPF_DIST_BF16X3> {
 // the Phase II queues and Phase I transposes reuse its space, and fewer chunks mean fewer
 // exposed row gathers.  (The 16-bit kernels hold their registers at the occupancy cap, where
 // spill reloads in the k loop would make the MFMAs wait for the raw tile's loads.)
-template <int PREC>
+// ALT, the tuner's alternative chunk: binary32 64 columns staged from X directly; 16-bit
+// tiles the chunk of the other tiles.
+template <int PREC, bool ALT = false>
 struct SymCfg {
     using T = typename TileCfg<PREC>::T;
-    static constexpr bool DMA = PREC == RPF_DIST_FP32;
-    static constexpr int KC = DMA ? 32 : 2 * TileCfg<PREC>::KC;
+    static constexpr bool DMA = PREC == RPF_DIST_FP32 && !ALT;
+    static constexpr int KC = PREC == RPF_DIST_FP32 ? (ALT ? 64 : 32) : (ALT ? 1 : 2) * TileCfg<PREC>::KC;
     static constexpr int LDW = PREC == RPF_DIST_FP32 ? KC + 1 : KC + 8;
     static constexpr int KSTEP = TileCfg<PREC>::KSTEP;
 };
@@ -151,11 +153,11 @@ __device__ inline void stage_rows(typename TileCfg<PREC>::T *s, const typename T
 // up to rows_pad zero-filled.  These are exactly the values of the leaf-ordered centred copy
 // (x - mu in binary32, then one rounding to the tile type), so a tile staged this way equals
 // one staged from that copy.  VEC: d % 4 == 0 (four-column groups never straddle d).
-template <int PREC, bool VEC>
+template <int PREC, bool VEC, bool ALT = false>
 __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *__restrict__ X, int d,
                                     const int32_t *s_pt, const float *__restrict__ mu, int rows, int rows_pad,
                                     int k0, int nthreads, typename TileCfg<PREC>::T *s_lo = nullptr) {
-    using C = SymCfg<PREC>;
+    using C = SymCfg<PREC, ALT>;
     using T = typename C::T;
     constexpr int EV = PREC == RPF_DIST_FP32 ? 4 : 8;  // elements per LDS vector
     constexpr int VPR = C::KC / EV;
@@ -333,6 +335,7 @@ struct TileOut {
     int S;             // bucket mode: records per bucket
     int nT2;           // bucket mode: Phase II trees
     int capO;          // bucket mode: overflow records per row
+    int shape;         // Phase II symmetric tile shape (k_tile_sym SHAPE)
 };
 
 constexpr int kQueue = 512;  // per-wave queue of Phase II pairs that pass the cheap test
@@ -841,24 +844,32 @@ __global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__
 //
 // Phase II at NB = 8 runs 12 waves: three per pair of block rows, three blocks each, so the
 // accumulators take 48 registers rather than 80 and six waves share a SIMD instead of four.
-constexpr int sym_waves(int NB, int MODE) { return NB >= 2 ? (MODE >= 1 && NB == 8 ? 12 : NB) : 1; }
+//
+// SHAPE (Phase II tile shapes the tuner chooses among; 0 is the default): bit 0 the
+// alternative k-chunk (SymCfg ALT), bit 1 queues of 256 entries per wave, bit 2 (NB = 8) eight
+// waves per block (five blocks each) instead of twelve.
+constexpr int sym_waves(int NB, int MODE, int SHAPE = 0) {
+    return NB >= 2 ? (MODE >= 1 && NB == 8 && !(SHAPE & 4) ? 12 : NB) : 1;
+}
 
-template <int NB, int PREC, int MODE>
-__global__ __launch_bounds__(64 * sym_waves(NB, MODE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE) > 8 ? 6 : NB == 8 ? 4 : 1)))
+template <int NB, int PREC, int MODE, int SHAPE = 0>
+__global__ __launch_bounds__(64 * sym_waves(NB, MODE, SHAPE)) __attribute__((amdgpu_waves_per_eu(sym_waves(NB, MODE, SHAPE) > 8 ? 6 : NB == 8 ? 4 : 1)))
 void k_tile_sym(
     const TileJob *__restrict__ jobs, const float *__restrict__ X, int d, int dp, const float *__restrict__ centroid,
     int nleaf, int64_t stride_tree, const float2 *__restrict__ nrm, const int32_t *__restrict__ pt, BoundCoef bc,
     int exclude_self, TileOut out) {
-    using C = SymCfg<PREC>;
+    constexpr bool ALT = (SHAPE & 1) != 0;
+    using C = SymCfg<PREC, ALT>;
     using T = typename C::T;
     constexpr int M = 32 * NB;
-    constexpr int NW = sym_waves(NB, MODE);
+    constexpr int NW = sym_waves(NB, MODE, SHAPE);
     constexpr int NT = 64 * NW;
     constexpr int PAIR = NB + 1;
     constexpr int WPP = NB >= 2 ? NW / (NB / 2) : 1;  // waves per pair of block rows
     constexpr int SLOTS = NB >= 2 ? (PAIR + WPP - 1) / WPP : 1;
     constexpr bool SPLIT = PREC == RPF_DIST_BF16X3;   // hi and lo tiles, three products per step
-    constexpr int QL = NW > 8 ? (SPLIT ? 352 : 384) : kQueue;  // queue entries per wave (LDS for two blocks)
+    // queue entries per wave (LDS for two blocks)
+    constexpr int QL = (SHAPE & 2) ? 256 : NW > 8 ? (SPLIT ? 352 : 384) : kQueue;
     // one LDS area: the operand tile(s) during the k loop, then the Phase II queues or the
     // Phase I transposes
     // LDS: the operand tile(s) during the k loop, whose space then holds the Phase II queues
@@ -978,8 +989,8 @@ void k_tile_sym(
             if (k0 + C::KC < dp) issue_rows_dma(s_raw, X, d, s_pt, m, k0 + C::KC, wu, NW);
         } else {
             __syncthreads();
-            if (d % 4 == 0) stage_rows_x<PREC, true>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
-            else stage_rows_x<PREC, false>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+            if (d % 4 == 0) stage_rows_x<PREC, true, ALT>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
+            else stage_rows_x<PREC, false, ALT>(s_a, X, d, s_pt, mu, m, M, k0, NT, s_a + (SPLIT ? M * C::LDW : 0));
             __syncthreads();
         }
         int kmax = dp - k0 < C::KC ? dp - k0 : C::KC;
@@ -2684,6 +2695,8 @@ struct Workspace {
 // common candidate stage once the tile jobs, A rows and per-row metadata are known
 struct CandStage {
     bool all_points = false;  // rows are the forest's points (Q = U)
+    int shape = 0;            // Phase II symmetric tile shape (the tuner's; 0 = default)
+    int bucket_S = 0;         // Phase II bucket size (the tuner's; 0 = the default rule)
     int64_t rows;          // number of result rows (n or m)
     const TileJob *jobs0;  // Phase I jobs (first tree)
     const TileJob *jobs1;  // Phase II jobs (other trees)
@@ -2757,19 +2770,39 @@ struct SymSrc {
 
 static SymSrc sym_src(const ForestView &v) { return SymSrc{v.X, v.d, v.dp, v.centroid, (int)v.nleaf, v.n}; }
 
+// Phase II into per-tree buckets with tile shape SH
+template <int NB, int PREC, int SH>
+static void sym_launch_p2(hipStream_t s, const dim3 g, const TileJob *jobs, const SymSrc &src, const float2 *nrm,
+                          const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
+    hipLaunchKernelGGL((k_tile_sym<NB, PREC, 2, SH>), g, dim3(64 * sym_waves(NB, 2, SH)), 0, s, jobs, src.X, src.d,
+                       src.dp, src.centroid, src.nleaf, src.stride, nrm, pt, bc, excl, out);
+}
+
+// the shapes a block-count NB offers: none at NB = 1, the chunk and queue bits at 2 and 4,
+// all three at 8
+constexpr int sym_shape_mask(int NB) { return NB == 1 ? 0 : NB == 8 ? 7 : 3; }
+
 template <int NB, int PREC>
 static void sym_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const SymSrc &src, const float2 *nrm,
                        const int32_t *pt, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
     const int NT = 64 * sym_waves(NB, out.mode);
     const dim3 g((unsigned)njobs);
-    if (out.mode == 0)
+    if (out.mode == 0) {
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 0>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
                            src.nleaf, src.stride, nrm, pt, bc, excl, out);
-    else if (out.bcnt)  // Phase II into per-tree buckets
-        hipLaunchKernelGGL((k_tile_sym<NB, PREC, 2>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
-                           src.nleaf, src.stride, nrm, pt, bc, excl, out);
-    else
+    } else if (out.bcnt) {  // Phase II into per-tree buckets
+        switch (out.shape & sym_shape_mask(NB)) {
+        case 1: sym_launch_p2<NB, PREC, 1 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 2: sym_launch_p2<NB, PREC, 2 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 3: sym_launch_p2<NB, PREC, 3 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 4: sym_launch_p2<NB, PREC, 4 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 5: sym_launch_p2<NB, PREC, 5 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 6: sym_launch_p2<NB, PREC, 6 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        case 7: sym_launch_p2<NB, PREC, 7 & sym_shape_mask(NB)>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        default: sym_launch_p2<NB, PREC, 0>(s, g, jobs, src, nrm, pt, bc, excl, out); break;
+        }
+    } else
         hipLaunchKernelGGL((k_tile_sym<NB, PREC, 1>), g, dim3(NT), 0, s, jobs, src.X, src.d, src.dp, src.centroid,
                            src.nleaf, src.stride, nrm, pt, bc, excl, out);
     launch_check(s, "k_tile_sym");
@@ -2855,13 +2888,13 @@ static int bucket_size_override() {
     return v >= 1 && v <= 16 ? v : 0;
 }
 
-static RecLayout rec_layout(int K, int T, int B, int64_t rows, bool buckets) {
+static RecLayout rec_layout(int K, int T, int B, int64_t rows, bool buckets, int want_S = 0) {
     RecLayout r;
     cand_caps(K, T, B, rows, r.lcap, r.cap2);
     r.want2 = r.cap2;
     const int nT2 = T - B;
     if (buckets && nT2 >= 1 && nT2 <= kMaxBucketTrees) {
-        const int forced = bucket_size_override();
+        const int forced = bucket_size_override() ? bucket_size_override() : std::min(want_S, 64);
         const int capO = std::max(kBucketOverflow, 2 * K);
         int S0 = 16;
         while (S0 < K && S0 < 64) S0 *= 2;
@@ -2885,7 +2918,7 @@ static bool phase2_buckets(const ForestView &v, const CandStage &cs) {
 }
 
 static RecLayout stage_layout(const ForestView &v, const CandStage &cs, int K) {
-    return rec_layout(K, v.T, cs.B, cs.rows, phase2_buckets(v, cs));
+    return rec_layout(K, v.T, cs.B, cs.rows, phase2_buckets(v, cs), cs.bucket_S);
 }
 
 static void set_layout(CandWs &w, const RecLayout &lay) {
@@ -2994,6 +3027,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     o1.S = 0;
     o1.nT2 = 0;
     o1.capO = 0;
+    o1.shape = 0;
     const bool grid = v.sym_prec == RPF_DIST_U8GRID && cs.all_points;
     auto grid_launch = [&](const TileJob *jobs, int64_t njobs, const TileOut &o) {
         if (njobs <= 0) return;
@@ -3044,6 +3078,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         o2.tau = tau;
         o2.ent = ent;
         if (w.lay.S) {  // rows' records in per-tree buckets (k_tile_sym only)
+            o2.shape = cs.shape;
             o2.bcnt = w.bcnt;
             o2.t1 = cs.B;
             o2.S = w.lay.S;
@@ -3262,9 +3297,28 @@ int knn_part_first_trees(const rpf_forest *f, int K, int B) {
     return all_points_stage(v, K, 0, B).B;
 }
 
-void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *out_idx, float *out_dist, hipStream_t s) {
+// the Phase II tile shapes the part's symmetric tiles offer (0: none but the default)
+int knn_part_shape_mask(const rpf_forest *f, int K) {
     const ForestView v = view(f);
-    const CandStage cs = all_points_stage(v, p->K, p->excl, B);
+    const CandStage cs = all_points_stage(v, K, 0);
+    if (!cs.sym || v.sym_prec == RPF_DIST_U8GRID) return 0;
+    return v.job_mb == 1 ? sym_shape_mask(1) : v.job_mb == 2 ? sym_shape_mask(2) : v.job_mb == 4 ? sym_shape_mask(4)
+                                                                                             : sym_shape_mask(8);
+}
+
+// the Phase II bucket size the default rule gives a part (0: no buckets)
+int knn_part_bucket_size(const rpf_forest *f, int K, int B) {
+    const ForestView v = view(f);
+    const CandStage cs = all_points_stage(v, K, 0, B);
+    return stage_layout(v, cs, K).S;
+}
+
+void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int shape, int bucket_S, int32_t *out_idx,
+                     float *out_dist, hipStream_t s) {
+    const ForestView v = view(f);
+    CandStage cs = all_points_stage(v, p->K, p->excl, B);
+    cs.shape = shape;
+    cs.bucket_S = bucket_S;
     CandWs w = p->w;
     set_layout(w, stage_layout(v, cs, p->K));
     w.cap1 = slot_stride(v.max_leaf) * cs.B;

@@ -1,6 +1,7 @@
 // C ABI of the rpForests library: argument checks, the closed-form tree plan, device
 // memory, and the launch sequences of rpf_build / rpf_all_knn / rpf_query.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -9,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "rpf_internal.h"
@@ -1416,6 +1418,8 @@ struct PlanPart {
     int32_t *out_idx = nullptr;
     float *out_dist = nullptr;
     int B = 0;                 // first-phase trees (0: default rule; set by the tuner)
+    int shape = 0;             // Phase II symmetric tile shape (set by the tuner)
+    int S = 0;                 // Phase II bucket size (0: default rule; set by the tuner)
 };
 
 struct rpf_plan {
@@ -1429,6 +1433,28 @@ struct rpf_plan {
 };
 
 constexpr int kTuneB[] = {2, 3, 4, 6, 8};  // first-phase tree counts the tuner tries
+
+// The tuner's choices, per part shape: kept for the process, written to and read from a
+// file (rpf_tune_save / rpf_tune_load), and applied by rpf_plan_create to every part whose
+// shape has an entry.  A part's shape: d, largest leaf, tile precision, K, T and
+// floor(log2 n).
+struct TuneKey {
+    int d, max_leaf, prec, K, T, nlog2;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(d, max_leaf, prec, K, T, nlog2) < std::tie(o.d, o.max_leaf, o.prec, o.K, o.T, o.nlog2);
+    }
+};
+struct TuneVal {
+    int B, shape, S, subtree;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+
+static TuneKey tune_key(const rpf_forest *f, int K) {
+    int lg = 0;
+    while (((int64_t)2 << lg) <= f->n) lg++;
+    return TuneKey{f->d, f->max_leaf, f->tile_prec, K, f->T, lg};
+}
 
 static void plan_free(rpf_plan *pl) {
     if (!pl) return;
@@ -1464,7 +1490,7 @@ static rpf_status plan_record(rpf_plan *pl) {
         launch_nonfinite(c, f->R, (int64_t)f->T * f->H * f->n_try * f->d, f->err + 3);
         if (f->Xq) launch_grid_quantise(c, f->X, f->n, f->d, f->dq, f->Xq, f->qn, f->err + 4);
         build_launches(f, c);
-        knn_part_launch(pl->knn, f, pt.B, pt.out_idx, pt.out_dist, c);
+        knn_part_launch(pl->knn, f, pt.B, pt.shape, pt.S, pt.out_idx, pt.out_dist, c);
         if (pt.sets.size() > 1) launch_localize(pt.out_idx, f->n, pl->K, f->d_batch_off, (int)pt.sets.size(), c);
     }
     const hipError_t ec = hipStreamEndCapture(c, &pl->graph);
@@ -1545,6 +1571,16 @@ rpf_status rpf_plan_create(const int64_t *n_host, const int32_t *d_host, int32_t
             pe.heap_base = e.heap_base;
             pe.n_nodes = ((int64_t)1 << e.depth) - 1;
         }
+        {  // the tuner's earlier choices for a part of this shape, if any
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            const auto it = g_tune.find(tune_key(pt.f, K));
+            if (it != g_tune.end()) {
+                pt.B = it->second.B;
+                pt.shape = it->second.shape & knn_part_shape_mask(pt.f, K);
+                pt.S = it->second.S;
+                pt.f->subtree_on = it->second.subtree && pt.f->sub_level >= 0;
+            }
+        }
         fs.push_back(pt.f);
         maxB.push_back(knn_part_first_trees(pt.f, K, kTuneB[sizeof(kTuneB) / sizeof(kTuneB[0]) - 1]));
     }
@@ -1585,7 +1621,9 @@ rpf_status rpf_plan_part(const rpf_plan *pl, int32_t k, rpf_plan_part_info *out)
     out->out_dist_dev = pt.out_dist;
     out->forest = pt.f;
     out->first_trees = knn_part_first_trees(pt.f, pl->K, pt.B);
-    out->reserved = 0;
+    out->tile_shape = pt.shape;
+    out->bucket_size = pt.S ? pt.S : knn_part_bucket_size(pt.f, pl->K, out->first_trees);
+    out->subtrees = pt.f->subtree_on ? 1 : 0;
     return RPF_OK;
 }
 
@@ -1630,8 +1668,26 @@ rpf_status rpf_plan_tune(rpf_plan *pl, void *stream, double *tuned_ms) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
+    // the best of two timed runs after one warm-up run
+    auto timed = [&](auto &&run) {
+        double ms = 1e300;
+        for (int rep = 0; rep < 3; rep++) {
+            hipEventRecord(e0, s);
+            run();
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float t = 0;
+            hipEventElapsedTime(&t, e0, e1);
+            if (rep) ms = std::min(ms, (double)t);
+        }
+        return ms;
+    };
     double total = 0;
     for (auto &pt : pl->parts) {
+        auto cand = [&](int B, int shape, int S) {
+            return timed([&] { knn_part_launch(pl->knn, pt.f, B, shape, S, pt.out_idx, pt.out_dist, s); });
+        };
+        // 1. first-phase trees, default tile shape and bucket size
         double best = 1e300;
         int bestB = pt.B;
         std::vector<int> tried;
@@ -1639,23 +1695,49 @@ rpf_status rpf_plan_tune(rpf_plan *pl, void *stream, double *tuned_ms) {
             const int B = knn_part_first_trees(pt.f, pl->K, b);
             if (std::find(tried.begin(), tried.end(), B) != tried.end()) continue;
             tried.push_back(B);
-            double ms = 1e300;
-            for (int rep = 0; rep < 3; rep++) {  // first run warms up, the best of the others counts
-                hipEventRecord(e0, s);
-                knn_part_launch(pl->knn, pt.f, B, pt.out_idx, pt.out_dist, s);
-                hipEventRecord(e1, s);
-                hipEventSynchronize(e1);
-                float t = 0;
-                hipEventElapsedTime(&t, e0, e1);
-                if (rep) ms = std::min(ms, (double)t);
-            }
+            const double ms = cand(B, 0, 0);
             if (ms < best) {
                 best = ms;
                 bestB = B;
             }
         }
+        // 2. Phase II tile shape: k-chunk, queue length, waves per block
+        const int mask = knn_part_shape_mask(pt.f, pl->K);
+        int bestShape = 0;
+        for (int sh = 1; sh <= mask; sh++) {
+            if ((sh & mask) != sh) continue;
+            const double ms = cand(bestB, sh, 0);
+            if (ms < best) {
+                best = ms;
+                bestShape = sh;
+            }
+        }
+        // 3. Phase II bucket size: the default rule's, or half of it
+        int bestS = 0;
+        const int S0 = knn_part_bucket_size(pt.f, pl->K, bestB);
+        if (S0 >= 8) {
+            const double ms = cand(bestB, bestShape, S0 / 2);
+            if (ms < best) {
+                best = ms;
+                bestS = S0 / 2;
+            }
+        }
         pt.B = bestB;
+        pt.shape = bestShape;
+        pt.S = bestS;
+        // 4. build schedule: level by level, or the small levels in one persistent launch
+        if (pt.f->sub_level >= 0) {
+            double ms_sched[2];
+            for (int on = 0; on < 2; on++) {
+                pt.f->subtree_on = on != 0;
+                ms_sched[on] = timed([&] { build_launches(pt.f, s); });
+            }
+            pt.f->subtree_on = ms_sched[1] < ms_sched[0];
+            best += std::min(ms_sched[0], ms_sched[1]);
+        }
         total += best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(pt.f, pl->K)] = TuneVal{pt.B, pt.shape, pt.S, pt.f->subtree_on ? 1 : 0};
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1663,6 +1745,65 @@ rpf_status rpf_plan_tune(rpf_plan *pl, void *stream, double *tuned_ms) {
     if (!le.empty()) return fail(RPF_EDEVICE, "rpf_plan_tune: " + le);
     if (tuned_ms) *tuned_ms = total;
     return plan_record(pl);  // the outputs are recomputed by the next launch
+}
+
+rpf_status rpf_tune_save(const char *path) {
+    if (!path) return fail(RPF_EINVAL, "rpf_tune_save: NULL path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *fp = fopen(path, "w");
+    if (!fp) return fail(RPF_EINVAL, std::string("rpf_tune_save: cannot open ") + path);
+    for (const auto &kv : g_tune) {
+        const TuneKey &k = kv.first;
+        const TuneVal &v = kv.second;
+        fprintf(fp,
+                "{\"d\": %d, \"max_leaf\": %d, \"prec\": %d, \"K\": %d, \"T\": %d, \"n_log2\": %d, "
+                "\"first_trees\": %d, \"tile_shape\": %d, \"bucket_size\": %d, \"subtrees\": %d}\n",
+                k.d, k.max_leaf, k.prec, k.K, k.T, k.nlog2, v.B, v.shape, v.S, v.subtree);
+    }
+    const bool ok = fclose(fp) == 0;
+    return ok ? RPF_OK : fail(RPF_EINVAL, std::string("rpf_tune_save: write failed: ") + path);
+}
+
+rpf_status rpf_tune_load(const char *path, int32_t *entries) {
+    if (!path) return fail(RPF_EINVAL, "rpf_tune_load: NULL path");
+    FILE *fp = fopen(path, "r");
+    if (!fp) return fail(RPF_EINVAL, std::string("rpf_tune_load: cannot open ") + path);
+    std::map<TuneKey, TuneVal> got;
+    char line[512];
+    int lineno = 0;
+    bool bad = false;
+    while (fgets(line, sizeof line, fp)) {
+        lineno++;
+        bool blank = true;
+        for (const char *c = line; *c; c++) blank &= (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r');
+        if (blank) continue;
+        TuneKey k;
+        TuneVal v;
+        int used = 0;
+        const int got_n = sscanf(line,
+                                 " {\"d\": %d, \"max_leaf\": %d, \"prec\": %d, \"K\": %d, \"T\": %d, \"n_log2\": %d, "
+                                 "\"first_trees\": %d, \"tile_shape\": %d, \"bucket_size\": %d, \"subtrees\": %d}%n",
+                                 &k.d, &k.max_leaf, &k.prec, &k.K, &k.T, &k.nlog2, &v.B, &v.shape, &v.S, &v.subtree,
+                                 &used);
+        if (got_n != 10 || used == 0 || v.B < 0 || v.shape < 0 || v.shape > 7 || v.S < 0 || v.S > 64 ||
+            (v.subtree != 0 && v.subtree != 1)) {
+            bad = true;
+            break;
+        }
+        got[k] = v;
+    }
+    fclose(fp);
+    if (bad) return fail(RPF_EINVAL, "rpf_tune_load: malformed entry on line " + std::to_string(lineno));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    if (entries) *entries = (int32_t)g_tune.size();
+    return RPF_OK;
+}
+
+rpf_status rpf_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return RPF_OK;
 }
 
 rpf_status rpf_plan_destroy(rpf_plan *pl) {

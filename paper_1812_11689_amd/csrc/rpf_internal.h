@@ -200,7 +200,10 @@ struct KnnShared;
 KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const std::vector<int> &maxB, int K,
                              int exclude_self, hipStream_t s);
 int knn_part_first_trees(const rpf_forest *f, int K, int B);
-void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int32_t *out_idx, float *out_dist, hipStream_t s);
+int knn_part_shape_mask(const rpf_forest *f, int K);
+int knn_part_bucket_size(const rpf_forest *f, int K, int B);
+void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int shape, int bucket_S, int32_t *out_idx,
+                     float *out_dist, hipStream_t s);
 void knn_shared_destroy(KnnShared *p, hipStream_t s);
 void fill_u32(void *p, int64_t count, uint32_t value, hipStream_t s);
 void fill_u64(void *p, int64_t count, uint64_t value, hipStream_t s);

@@ -26,7 +26,8 @@ EXPORTS = ["rpf_depth", "rpf_build", "rpf_all_knn", "rpf_query", "rpf_route", "r
            "rpf_server_submit", "rpf_server_poll", "rpf_server_wait", "rpf_server_stats", "rpf_server_reset_stats",
            "rpf_server_batch_log", "rpf_server_destroy", "rpf_query_noalloc", "rpf_exact_knn", "rpf_build_batched", "rpf_batch_info", "rpf_plan_create", "rpf_plan_info",
            "rpf_plan_part", "rpf_plan_entry_of", "rpf_plan_launch", "rpf_plan_check", "rpf_plan_tune",
-           "rpf_plan_destroy", "rpf_last_error", "rpf_tree_nodes"]
+           "rpf_plan_destroy", "rpf_last_error", "rpf_tree_nodes", "rpf_tune_save", "rpf_tune_load",
+           "rpf_tune_clear"]
 
 
 class RpfError(RuntimeError):
@@ -97,7 +98,8 @@ class PlanPartInfo(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int64), ("d", ctypes.c_int32), ("n_sets", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("X_dev", ctypes.c_void_p), ("directions_dev", ctypes.c_void_p),
                 ("out_idx_dev", ctypes.c_void_p), ("out_dist_dev", ctypes.c_void_p), ("forest", ctypes.c_void_p),
-                ("first_trees", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("first_trees", ctypes.c_int32), ("tile_shape", ctypes.c_int32), ("bucket_size", ctypes.c_int32),
+                ("subtrees", ctypes.c_int32)]
 
 
 _lib = None
@@ -181,6 +183,12 @@ def load(path: str = LIB_PATH):
     lib.rpf_plan_check.argtypes = [vp, vp]
     lib.rpf_plan_tune.restype = i32
     lib.rpf_plan_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.rpf_tune_save.restype = i32
+    lib.rpf_tune_save.argtypes = [ctypes.c_char_p]
+    lib.rpf_tune_load.restype = i32
+    lib.rpf_tune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    lib.rpf_tune_clear.restype = i32
+    lib.rpf_tune_clear.argtypes = []
     lib.rpf_plan_destroy.restype = i32
     lib.rpf_plan_destroy.argtypes = [vp]
     lib.rpf_release_cached_memory.restype = i32
@@ -449,6 +457,22 @@ def _view(ptr: int, shape, dtype) -> torch.Tensor:
     return torch.as_tensor(_DeviceArray(ptr, shape, typestr), device="cuda")
 
 
+def tune_save(path: str):
+    """Write the process's tuning table (rpf_tune_save)."""
+    _check(load().rpf_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> int:
+    """Merge a tuning table file into the process's table (rpf_tune_load); its entry count."""
+    n = ctypes.c_int32(0)
+    _check(load().rpf_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_clear():
+    _check(load().rpf_tune_clear())
+
+
 class Plan:
     """Build + all-points search of many data sets recorded as one HIP graph (rpf_plan_*).
     set_inputs() writes the points and directions into the plan's buffers, launch() runs the
@@ -504,13 +528,23 @@ class Plan:
     def check(self, stream=None):
         _check(load().rpf_plan_check(self._h, _stream(stream)))
 
-    def tune(self, stream=None) -> float:
-        ms = ctypes.c_double(0.0)
-        _check(load().rpf_plan_tune(self._h, _stream(stream), ctypes.byref(ms)))
+    def choices(self):
+        """The tuned choices of every part (first-phase trees, Phase II tile shape, bucket
+        size, persistent subtree build)."""
+        out = []
         for k, pt in enumerate(self.parts):
             pi = PlanPartInfo()
             _check(load().rpf_plan_part(self._h, k, ctypes.byref(pi)))
-            pt["first_trees"] = pi.first_trees
+            pt.update(first_trees=pi.first_trees, tile_shape=pi.tile_shape, bucket_size=pi.bucket_size,
+                      subtrees=pi.subtrees)
+            out.append({"first_trees": pi.first_trees, "tile_shape": pi.tile_shape, "bucket_size": pi.bucket_size,
+                        "subtrees": pi.subtrees})
+        return out
+
+    def tune(self, stream=None) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(load().rpf_plan_tune(self._h, _stream(stream), ctypes.byref(ms)))
+        self.choices()
         return ms.value
 
     def result(self, i: int):

@@ -128,3 +128,34 @@ def test_plan_arguments_rejected_without_device():
     assert lib.rpf_plan_destroy(None) == rpf.RPF_OK
     assert lib.rpf_build_batched(ctypes.c_void_p(0x1000), None, 2, 4, ctypes.byref(p), None,
                                  ctypes.byref(h)) == rpf.RPF_EINVAL
+
+
+def test_tuning_table_round_trip(tmp_path):
+    # host only: the tuner's table is read from and written to a text file, one JSON object
+    # per line; a malformed file is refused and leaves the table as it was
+    import json
+    lib = rpf.load()
+    assert lib.rpf_tune_clear() == rpf.RPF_OK
+    rows = [dict(d=64, max_leaf=64, prec=2, K=16, T=16, n_log2=17, first_trees=4, tile_shape=3, bucket_size=8,
+                 subtrees=1),
+            dict(d=128, max_leaf=245, prec=3, K=20, T=80, n_log2=19, first_trees=4, tile_shape=4, bucket_size=16,
+                 subtrees=0)]
+    src = tmp_path / "tune.jsonl"
+    src.write_text("".join(json.dumps(r) + "\n" for r in rows) + "\n")
+    assert rpf.tune_load(str(src)) == 2
+    out = tmp_path / "again.jsonl"
+    rpf.tune_save(str(out))
+    got = sorted((json.loads(ln) for ln in out.read_text().splitlines() if ln.strip()), key=lambda r: r["d"])
+    assert got == rows
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text(json.dumps(rows[0]) + "\n" + '{"d": 8, "max_leaf": 9}\n')
+    n = ctypes.c_int32(-1)
+    assert lib.rpf_tune_load(os.fsencode(str(bad)), ctypes.byref(n)) == rpf.RPF_EINVAL
+    assert b"line 2" in lib.rpf_last_error()
+    assert n.value == -1
+    assert lib.rpf_tune_load(os.fsencode(str(tmp_path / "missing.jsonl")), None) == rpf.RPF_EINVAL
+    rpf.tune_save(str(out))
+    assert len([ln for ln in out.read_text().splitlines() if ln.strip()]) == 2
+    assert lib.rpf_tune_clear() == rpf.RPF_OK
+    rpf.tune_save(str(out))
+    assert out.read_text() == ""

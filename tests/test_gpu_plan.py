@@ -75,3 +75,74 @@ def test_plan_reports_nonfinite_input():
     gi, gd = plan.result(1)
     assert torch.equal(gi, ai) and torch.equal(gd, ad)
     plan.close()
+
+
+@pytest.mark.parametrize("n,d,n0,K,prec", [(6000, 24, 60, 8, "fp16"),     # leaves <= 64: NB 2
+                                          (7800, 32, 250, 12, "bf16x3"),  # leaves of 244: NB 8
+                                          (7800, 32, 250, 12, "fp32")])
+def test_every_tuned_choice_gives_the_same_result(n, d, n0, K, prec, tmp_path):
+    # each Phase II tile shape, bucket size and build schedule the tuner can pick, entered
+    # through the tuning table, must give the forest grown alone, bit for bit
+    import json
+    import math
+    from paper_1812_11689_amd import rpf
+    T = 6
+    xs, Rs = _inputs(4000 + d, [n], [d], T, n0)
+    ai, ad, _ = _alone(xs[0], Rs[0], T, n0, K, prec)
+    L = rpf.depth(n, n0)
+    key = dict(d=d, max_leaf=-(-n // (1 << L)), prec=rpf.PREC[prec], K=K, T=T, n_log2=int(math.floor(math.log2(n))))
+    mask = 7 if key["max_leaf"] > 128 else 3
+    seen = set()
+    try:
+        for shape in range(mask + 1):
+            for S in (0, 4):
+                print(f"[tuned choice] {prec} n={n} shape={shape} S={S}", flush=True)
+                rpf.tune_clear()
+                path = tmp_path / f"t{shape}_{S}.jsonl"
+                path.write_text(json.dumps(dict(key, first_trees=3, tile_shape=shape, bucket_size=S,
+                                                subtrees=shape & 1)) + "\n")
+                assert rpf.tune_load(str(path)) == 1
+                plan = rpf.Plan([n], [d], T, n0, K, dist_prec=prec)
+                ch = plan.choices()[0]
+                assert ch["tile_shape"] == shape and ch["first_trees"] == 3 and ch["subtrees"] == (shape & 1)
+                if S:
+                    assert ch["bucket_size"] == S
+                seen.add((ch["tile_shape"], ch["bucket_size"]))
+                plan.set_inputs(xs, Rs)
+                plan.launch()
+                plan.check()
+                gi, gd = plan.result(0)
+                assert torch.equal(gi, ai) and torch.equal(gd, ad), (shape, S)
+                plan.close()
+    finally:
+        rpf.tune_clear()
+    assert len(seen) == 2 * (mask + 1)
+
+
+def test_tuner_records_its_choices(tmp_path):
+    from paper_1812_11689_amd import rpf
+    sizes, dims, T, n0, K = [3000, 5000], [16, 16], 5, 40, 9
+    rpf.tune_clear()
+    try:
+        plan = rpf.Plan(sizes, dims, T, n0, K, dist_prec="fp16")
+        xs, Rs = _inputs(5000, sizes, dims, T, n0)
+        plan.set_inputs(xs, Rs)
+        plan.tune()
+        ch = plan.choices()
+        plan.launch()
+        plan.check()
+        for i in range(len(sizes)):
+            gi, gd = plan.result(i)
+            ai, ad, _ = _alone(xs[i], Rs[i], T, n0, K, "fp16")
+            assert torch.equal(gi, ai) and torch.equal(gd, ad)
+        plan.close()
+        path = tmp_path / "tuned.jsonl"
+        rpf.tune_save(str(path))
+        assert len(path.read_text().splitlines()) == 1  # one part
+        rpf.tune_clear()
+        assert rpf.tune_load(str(path)) == 1
+        again = rpf.Plan(sizes, dims, T, n0, K, dist_prec="fp16")  # takes the saved choices
+        assert again.choices() == ch
+        again.close()
+    finally:
+        rpf.tune_clear()
