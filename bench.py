@@ -251,9 +251,13 @@ def pmc_summary(fetch_dir, write_dir):
     print(json.dumps(out))
 
 
+XCDS = 8  # GRBM_GUI_ACTIVE sums the active cycles of the eight XCDs
+
+
 def mfma_summary(d):
     """Per-kernel MFMA counters per dispatch from one rocprofv3 --pmc run: executed MFMA ops
-    (SQ_INSTS_VALU_MFMA_MOPS_* x 512), MFMA-busy cycles over GUI-active cycles x SIMDs."""
+    (SQ_INSTS_VALU_MFMA_MOPS_* x 512), MFMA-busy cycles over (GUI-active cycles of one XCD x
+    SIMDs); GRBM_GUI_ACTIVE counts every XCD, so it is divided by their number."""
     rows = _csv_rows(d, "counter_collection.csv")
     agg = {}
     for r in rows:
@@ -263,7 +267,7 @@ def mfma_summary(d):
         a = agg.setdefault(k, {})
         a.setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
     simds = 256 * 4
-    print("| kernel | dispatches | MFMA Tops/dispatch (bf16, f32, i8) | MFMA busy / (GUI active x SIMDs) |")
+    print("| kernel | dispatches | MFMA Tops/dispatch (bf16, f32, i8) | MFMA busy / (GUI active per XCD x SIMDs) |")
     print("|---|---|---|---|")
     out = {}
     for k, a in sorted(agg.items(), key=lambda kv: -sum(kv[1].get("GRBM_GUI_ACTIVE", {}).values())):
@@ -271,7 +275,7 @@ def mfma_summary(d):
         ops = [sum(a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{t}", {}).values()) * 512 / disp / 1e12 for t in ("BF16", "F32", "I8")]
         busy = sum(a.get("SQ_VALU_MFMA_BUSY_CYCLES", {}).values())
         gui = sum(a.get("GRBM_GUI_ACTIVE", {}).values())
-        frac = busy / (gui * simds) if gui else 0.0
+        frac = busy / (gui / XCDS * simds) if gui else 0.0
         out[k] = {"mfma_tops": [round(v, 4) for v in ops], "mfma_busy_frac": round(frac, 4)}
         if sum(ops) > 0 or frac > 0:
             print(f"| {k} | {disp} | {ops[0]:.3f}, {ops[1]:.3f}, {ops[2]:.3f} | {frac:.4f} |")
