@@ -40,8 +40,8 @@ PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "u8grid": 4}
 # kernel (name prefix in the counter summary) behind each timed record of the library for the
 # 1M x 128 workload (leaves of 244/245 points: the 8 x 8 symmetric tile)
 RECORD_KERNEL = {
-    "tile_phase2": "k_tile_sym<8, {p}, 2>",
-    "tile_phase1": "k_tile_sym<8, {p}, 0>",
+    "tile_phase2": "k_tile_sym<8, {p}, 2, 0>",
+    "tile_phase1": "k_tile_sym<8, {p}, 0, 0>",
     "proj_chunks_x3": "k_proj_chunks<true, true>",
     "level_small": "k_level_small<true, true>",
     "leaf_finalize": "k_leaf_stats<",
