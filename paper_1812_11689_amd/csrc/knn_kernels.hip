@@ -166,25 +166,33 @@ __device__ inline void stage_rows_x(typename TileCfg<PREC>::T *s, const float *_
         float a[EV];
 #pragma unroll
         for (int e = 0; e < EV; e++) a[e] = 0.f;
-        if (r < rows) {
-            const float *x = X + (int64_t)s_pt[r] * d;
+        if (VEC) {
+            // every load of the vector is issued before the first is used (one wait per
+            // vector): addresses past the leaf or past d are clamped to the first four values
+            // of X and of the centroid (present whenever d >= 4), and those lanes keep zero
+            const bool rok = r < rows;
+            const float *x = X + (rok ? (int64_t)s_pt[r] * d : 0);
+            float4 xv[EV / 4], uv[EV / 4];
 #pragma unroll
-            for (int h = 0; h < EV; h += 4) {
-                if (VEC) {
-                    if (j + h < d) {
-                        const float4 xv = *reinterpret_cast<const float4 *>(x + j + h);
-                        const float4 u = *reinterpret_cast<const float4 *>(mu + j + h);
-                        a[h] = xv.x - u.x;
-                        a[h + 1] = xv.y - u.y;
-                        a[h + 2] = xv.z - u.z;
-                        a[h + 3] = xv.w - u.w;
-                    }
-                } else {
+            for (int h = 0; h < EV / 4; h++) {
+                const int o = rok && j + 4 * h < d ? j + 4 * h : 0;
+                xv[h] = *reinterpret_cast<const float4 *>(x + o);
+                uv[h] = *reinterpret_cast<const float4 *>(mu + (j + 4 * h < d ? j + 4 * h : 0));
+            }
 #pragma unroll
-                    for (int e = h; e < h + 4; e++)
-                        if (j + e < d) a[e] = x[j + e] - mu[j + e];
+            for (int h = 0; h < EV / 4; h++) {
+                if (rok && j + 4 * h < d) {
+                    a[4 * h] = xv[h].x - uv[h].x;
+                    a[4 * h + 1] = xv[h].y - uv[h].y;
+                    a[4 * h + 2] = xv[h].z - uv[h].z;
+                    a[4 * h + 3] = xv[h].w - uv[h].w;
                 }
             }
+        } else if (r < rows) {
+            const float *x = X + (int64_t)s_pt[r] * d;
+#pragma unroll
+            for (int e = 0; e < EV; e++)
+                if (j + e < d) a[e] = x[j + e] - mu[j + e];
         }
         T *dst = s + r * C::LDW + c;
         if constexpr (PREC == RPF_DIST_BF16X3) {
