@@ -1373,10 +1373,12 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
     const int c = B * ML;  // fixed slots of the first B trees
+    // A row that takes the exhaustive path gets a negative threshold: no later tile emits a
+    // record for it (lb >= 0), since the exhaustive scan does not read them.
     if (c > 64 * Q) {      // leaves above kMergeCap points: the row takes the exhaustive path
         if (lane == 0) {
             lcnt[a] = lcap + 1;
-            tau[a] = INFINITY;
+            tau[a] = -1.f;
             cnt[a] = 0;
         }
         return;
@@ -1485,7 +1487,7 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     }
     if (lane == 0) {
         lcnt[a] = over ? lcap + 1 : (int32_t)kept;
-        tau[a] = over ? INFINITY : tp;
+        tau[a] = over ? -1.f : tp;
         cnt[a] = 0;
     }
 }
@@ -2197,6 +2199,8 @@ __global__ __launch_bounds__(256) void k_final_blk(FinalArgs A) {
 
 // ---------------------------------------------------------------- exhaustive fallback
 
+constexpr int kFallbackThreads = 512;  // threads per row of the exhaustive path
+
 struct FallbackArgs {
     const int32_t *fb_list;
     const int32_t *fb_cnt;
@@ -2217,16 +2221,27 @@ struct FallbackArgs {
     float *out_dist;
 };
 
-template <bool VEC>
-__global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
-    __shared__ double s_cd[512];
-    __shared__ int32_t s_ci[512];
+// The exhaustive path, one row per block of NTH threads: the union of the row's leaves over
+// all trees in binary64.  The members of up to 64 trees' leaves are taken as one list, NTH at
+// a time (a piece spans trees); the ids of the next piece are read while the current one is
+// measured, and every group of eight lanes measures four members at once.  Only members
+// before the running list's last entry in (D, index) order can enter a full list; they are
+// compacted to the front, the list is appended behind them, and the K smallest distinct
+// indices are kept (a repeated index repeats its distance, so its copies sort together).
+template <bool VEC, int NTH>
+__global__ __launch_bounds__(NTH) void k_fallback(FallbackArgs F) {
+    constexpr int NW = NTH / 64, NG = NTH / 8;
+    constexpr int CAP = 2 * NTH;  // a piece's candidates and the list (K <= 256 <= NTH)
+    static_assert(NTH >= 256 && (NTH & (NTH - 1)) == 0, "a power of two of at least 256 threads");
+    __shared__ double s_cd[CAP];
+    __shared__ int32_t s_ci[CAP];
     __shared__ double s_td[256];
     __shared__ int32_t s_ti[256];
     __shared__ int s_tn;
-    __shared__ uint32_t s_scan[8];
-    __shared__ int32_t s_mid[256];
+    __shared__ uint32_t s_scan[NW];
+    __shared__ int32_t s_mid[NTH];
     __shared__ LeafDesc s_lf[64];
+    __shared__ int32_t s_lo[65];  // first member of each tree's leaf in the list
     extern __shared__ __align__(16) float s_q[];
     const int tid = threadIdx.x, g = tid & 7, grp = tid >> 3;
     const int nfb = *F.fb_cnt;
@@ -2234,7 +2249,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
     for (int q = blockIdx.x; q < nfb; q += gridDim.x) {
         const int64_t a = F.fb_list[q];
         __syncthreads();
-        for (int j = tid; j < F.d; j += 256) s_q[j] = F.Qr[a * F.d + j];
+        for (int j = tid; j < F.d; j += NTH) s_q[j] = F.Qr[a * F.d + j];
         if (tid == 0) s_tn = 0;
         __syncthreads();
         for (int t0 = 0; t0 < F.T; t0 += 64) {  // the row's leaves, 64 trees at a time
@@ -2243,31 +2258,39 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
             if (tid < nt)
                 s_lf[tid] = F.leaves[(t0 + tid) * F.leaf_stride + F.heap_leaf[F.row_leaf[(int64_t)(t0 + tid) * F.nrows + a]]];
             __syncthreads();
-            // pieces of up to 256 members, tree after tree; the ids of the next piece are
-            // loaded while the current one is processed
-            auto ids_of = [&](int tt, int base) {
-                const LeafDesc &l = s_lf[tt];
-                return base + tid < l.size ? F.perm[(int64_t)(t0 + tt) * F.n + l.off + base + tid] : -1;
+            if (tid == 0) {
+                int run = 0;
+                for (int tt = 0; tt < nt; tt++) {
+                    s_lo[tt] = run;
+                    run += s_lf[tt].size;
+                }
+                s_lo[nt] = run;
+            }
+            __syncthreads();
+            const int M = s_lo[nt];
+            auto id_of = [&](int m) -> int32_t {  // member m of the list: its point index
+                if (m >= M) return -1;
+                int lo = 0, hi = nt - 1;  // the last tree whose first member is at most m
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_lo[mid] <= m) lo = mid;
+                    else hi = mid - 1;
+                }
+                return F.perm[(int64_t)(t0 + lo) * F.n + s_lf[lo].off + (m - s_lo[lo])];
             };
-            int ct = 0, cb = 0;
-            int nid = ids_of(0, 0);
-            while (ct < nt) {
+            int32_t nid = id_of(tid);
+            for (int base = 0; base < M; base += NTH) {
                 __syncthreads();
                 s_mid[tid] = nid;
                 __syncthreads();
-                cb += 256;
-                if (cb >= s_lf[ct].size) {
-                    cb = 0;
-                    ct++;
-                }
-                if (ct < nt) nid = ids_of(ct, cb);
+                nid = id_of(base + NTH + tid);
                 if constexpr (VEC) {  // four members per group of eight lanes at a time
-                    for (int sub = 0; sub < 256; sub += 128) {
+                    for (int sub = 0; sub < NTH; sub += 4 * NG) {
                         int bm[4];
                         const float *rows[4];
 #pragma unroll
                         for (int h = 0; h < 4; h++) {
-                            bm[h] = s_mid[sub + grp + 32 * h];
+                            bm[h] = s_mid[sub + grp + NG * h];
                             rows[h] = F.X + (int64_t)(bm[h] < 0 ? 0 : bm[h]) * F.d;
                         }
                         double D64[4];
@@ -2275,7 +2298,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                         if (g == 0) {
 #pragma unroll
                             for (int h = 0; h < 4; h++) {
-                                const int l = sub + grp + 32 * h, b = bm[h];
+                                const int l = sub + grp + NG * h, b = bm[h];
                                 const bool ok = b >= 0 && !(F.exclude_self && b == a);
                                 s_cd[l] = ok ? D64[h] : INFINITY;
                                 s_ci[l] = ok ? b : 0x7fffffff;
@@ -2283,7 +2306,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                         }
                     }
                 } else {
-                    for (int sub = 0; sub < 256; sub += 32) {
+                    for (int sub = 0; sub < NTH; sub += NG) {
                         const int l = sub + grp, b = s_mid[l];
                         const double D = group8_dist64<VEC>(s_q, F.X + (int64_t)(b < 0 ? 0 : b) * F.d, F.d, g);
                         if (g == 0) {
@@ -2293,14 +2316,11 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                         }
                     }
                 }
-                for (int i = 256 + tid; i < 512; i += 256) {
+                for (int i = NTH + tid; i < CAP; i += NTH) {
                     s_cd[i] = INFINITY;
                     s_ci[i] = 0x7fffffff;
                 }
                 __syncthreads();
-                // only members before the list's last entry in (D, idx) order can enter a full
-                // list (a repeated index repeats its distance): they are compacted to the front
-                // and the list appended behind them
                 const int tn = s_tn;
                 const double dc = s_cd[tid];
                 const int ic = s_ci[tid];
@@ -2311,13 +2331,13 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                     take = take && (dc < lastd || (dc == lastd && ic < lasti));
                 }
                 uint32_t pos, ncand;
-                block_excl_scan256(take ? 1u : 0u, reinterpret_cast<uint32_t *>(s_scan), pos, ncand);
+                block_excl_scan_w<NW>(take ? 1u : 0u, s_scan, pos, ncand);  // every read above is done
                 if (ncand == 0) continue;
                 if (take) {
                     s_cd[pos] = dc;
                     s_ci[pos] = ic;
                 }
-                for (int i = tid; i < tn; i += 256) {
+                for (int i = tid; i < tn; i += NTH) {
                     s_cd[ncand + i] = s_td[i];
                     s_ci[ncand + i] = s_ti[i];
                 }
@@ -2352,49 +2372,51 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                     __syncthreads();
                     continue;
                 }
-                for (int i = tot + tid; i < 512; i += 256) {
+                int P2 = 128;  // bitonic sort of the first P2 >= tot entries (block-uniform)
+                while (P2 < tot) P2 <<= 1;
+                for (int i = tot + tid; i < P2; i += NTH) {
                     s_cd[i] = INFINITY;
                     s_ci[i] = 0x7fffffff;
                 }
                 __syncthreads();
-                for (int size = 2; size <= 512; size <<= 1)
+                for (int size = 2; size <= P2; size <<= 1)
                     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                        const int i = tid;
-                        const int lo = 2 * i - (i & (stride - 1));
-                        const int hi = lo + stride;
-                        const bool up = (lo & size) == 0;
-                        const double dl = s_cd[lo], dh = s_cd[hi];
-                        const int il = s_ci[lo], ih = s_ci[hi];
-                        const bool gtr = dl > dh || (dl == dh && il > ih);
-                        if (gtr == up) {
-                            s_cd[lo] = dh;
-                            s_cd[hi] = dl;
-                            s_ci[lo] = ih;
-                            s_ci[hi] = il;
+                        for (int i = tid; i < P2 / 2; i += NTH) {
+                            const int lo = 2 * i - (i & (stride - 1));
+                            const int hi = lo + stride;
+                            const bool up = (lo & size) == 0;
+                            const double dl = s_cd[lo], dh = s_cd[hi];
+                            const int il = s_ci[lo], ih = s_ci[hi];
+                            const bool gtr = dl > dh || (dl == dh && il > ih);
+                            if (gtr == up) {
+                                s_cd[lo] = dh;
+                                s_cd[hi] = dl;
+                                s_ci[lo] = ih;
+                                s_ci[hi] = il;
+                            }
                         }
                         __syncthreads();
                     }
-                {  // K smallest distinct: copies of an index are equal and adjacent after the sort
-                    bool keep[2];
+                {  // K smallest distinct: thread tid holds entries E tid .. E tid + E - 1
+                    constexpr int EMAX = CAP / NTH;
+                    const int E = P2 > NTH ? P2 / NTH : 1;
+                    bool keep[EMAX];
+                    double kd[EMAX];
+                    int ki[EMAX];
                     uint32_t cnt = 0;
 #pragma unroll
-                    for (int e = 0; e < 2; e++) {
-                        const int i = 2 * tid + e;
-                        keep[e] = s_ci[i] != 0x7fffffff && (i == 0 || s_ci[i] != s_ci[i - 1]);
+                    for (int e = 0; e < EMAX; e++) {
+                        const int i = E * tid + e;
+                        const bool in = e < E && i < P2;
+                        keep[e] = in && s_ci[i] != 0x7fffffff && (i == 0 || s_ci[i] != s_ci[i - 1]);
+                        kd[e] = in ? s_cd[i] : INFINITY;
+                        ki[e] = in ? s_ci[i] : 0x7fffffff;
                         cnt += keep[e] ? 1u : 0u;
                     }
                     uint32_t excl, total;
-                    block_excl_scan256(cnt, reinterpret_cast<uint32_t *>(s_scan), excl, total);
-                    double kd[2];
-                    int ki[2];
+                    block_excl_scan_w<NW>(cnt, s_scan, excl, total);  // every read of the sorted list is done
 #pragma unroll
-                    for (int e = 0; e < 2; e++) {
-                        kd[e] = s_cd[2 * tid + e];
-                        ki[e] = s_ci[2 * tid + e];
-                    }
-                    __syncthreads();  // every read of the sorted list is done before s_td changes
-#pragma unroll
-                    for (int e = 0; e < 2; e++)
+                    for (int e = 0; e < EMAX; e++)
                         if (keep[e]) {
                             if (excl < (uint32_t)K) {
                                 s_td[excl] = kd[e];
@@ -2407,7 +2429,7 @@ __global__ __launch_bounds__(256) void k_fallback(FallbackArgs F) {
                 __syncthreads();
             }
         }
-        for (int k = tid; k < K; k += 256) {
+        for (int k = tid; k < K; k += NTH) {
             const bool ok = k < s_tn;
             F.out_idx[a * K + k] = ok ? s_ti[k] : -1;
             F.out_dist[a * K + k] = ok ? (float)sqrt(s_td[k]) : INFINITY;
@@ -3162,10 +3184,11 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     {
         ProfScope ps(s, "fallback", 0, 0);
         const unsigned nb = (unsigned)std::min<int64_t>(rows, 1024);
+        constexpr int NTH = kFallbackThreads;
         if (vec)
-            hipLaunchKernelGGL(k_fallback<true>, dim3(nb), dim3(256), v.d * 4, s, fb);
+            hipLaunchKernelGGL((k_fallback<true, NTH>), dim3(nb), dim3(NTH), v.d * 4, s, fb);
         else
-            hipLaunchKernelGGL(k_fallback<false>, dim3(nb), dim3(256), v.d * 4, s, fb);
+            hipLaunchKernelGGL((k_fallback<false, NTH>), dim3(nb), dim3(NTH), v.d * 4, s, fb);
         launch_check(s, "k_fallback");
     }
 }

@@ -339,6 +339,28 @@ __device__ inline void block_excl_scan256(uint32_t v, uint32_t *s_w, uint32_t &e
     __syncthreads();
 }
 
+// exclusive scan over a block of NW waves; s_w needs NW words
+template <int NW>
+__device__ inline void block_excl_scan_w(uint32_t v, uint32_t *s_w, uint32_t &excl, uint32_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t wb = 0, tot = 0;
+    for (int k = 0; k < NW; k++) {
+        uint32_t c = s_w[k];
+        if (k < w) wb += c;
+        tot += c;
+    }
+    excl = wb + x - v;
+    total = tot;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- canonical arithmetic
 
 // canon_sum over s[0..m) in place by the whole block (s has room for the power-of-two
@@ -584,12 +606,22 @@ __device__ inline void group8_dist32_64x2(const float *__restrict__ a, const flo
             step(av, x1[k], 1);
         }
     }
-    for (; j < d; j += 32) {
-        const float4 x0 = *reinterpret_cast<const float4 *>(b0 + j);
-        const float4 x1 = *reinterpret_cast<const float4 *>(b1 + j);
-        const float4 av = *reinterpret_cast<const float4 *>(a + j);
-        step(av, x0, 0);
-        step(av, x1, 1);
+    if (j < d) {  // the last one to three steps, their loads in flight together: a step past d
+                  // reads a clamped address and adds fma(0, 0, s) = s (the sums are never -0)
+        float4 x0[3], x1[3], av[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int jk = j + 32 * k < d ? j + 32 * k : j;
+            x0[k] = *reinterpret_cast<const float4 *>(b0 + jk);
+            x1[k] = *reinterpret_cast<const float4 *>(b1 + jk);
+            av[k] = *reinterpret_cast<const float4 *>(a + jk);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const bool ok = j + 32 * k < d;
+            step(av[k], ok ? x0[k] : av[k], 0);
+            step(av[k], ok ? x1[k] : av[k], 1);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -633,12 +665,22 @@ __device__ inline void group8_dist64x2(const float *__restrict__ a, const float 
             step(av, x1[k], 1);
         }
     }
-    for (; j < d; j += 32) {
-        const float4 x0 = *reinterpret_cast<const float4 *>(b0 + j);
-        const float4 x1 = *reinterpret_cast<const float4 *>(b1 + j);
-        const float4 av = *reinterpret_cast<const float4 *>(a + j);
-        step(av, x0, 0);
-        step(av, x1, 1);
+    if (j < d) {  // the last one to three steps, their loads in flight together: a step past d
+                  // reads a clamped address and adds fma(0, 0, s) = s (the sums are never -0)
+        float4 x0[3], x1[3], av[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int jk = j + 32 * k < d ? j + 32 * k : j;
+            x0[k] = *reinterpret_cast<const float4 *>(b0 + jk);
+            x1[k] = *reinterpret_cast<const float4 *>(b1 + jk);
+            av[k] = *reinterpret_cast<const float4 *>(a + jk);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const bool ok = j + 32 * k < d;
+            step(av[k], ok ? x0[k] : av[k], 0);
+            step(av[k], ok ? x1[k] : av[k], 1);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -679,10 +721,22 @@ __device__ inline void group8_dist64x4(const float *__restrict__ a, const float 
             for (int r = 0; r < 4; r++) step(av, x[r][k], r);
         }
     }
-    for (; j < d; j += 32) {
-        const float4 av = *reinterpret_cast<const float4 *>(a + j);
+    if (j < d) {  // the last one to three steps, their loads in flight together: a step past d
+                  // reads a clamped address and adds fma(0, 0, s) = s (the sums are never -0)
+        float4 x[4][3], av[3];
 #pragma unroll
-        for (int r = 0; r < 4; r++) step(av, *reinterpret_cast<const float4 *>(b[r] + j), r);
+        for (int k = 0; k < 3; k++) {
+            const int jk = j + 32 * k < d ? j + 32 * k : j;
+#pragma unroll
+            for (int r = 0; r < 4; r++) x[r][k] = *reinterpret_cast<const float4 *>(b[r] + jk);
+            av[k] = *reinterpret_cast<const float4 *>(a + jk);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const bool ok = j + 32 * k < d;
+#pragma unroll
+            for (int r = 0; r < 4; r++) step(av[k], ok ? x[r][k] : av[k], r);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; r++) {
