@@ -1251,45 +1251,60 @@ __global__ __launch_bounds__(256) void k_qtile(const TileJob *__restrict__ jobs,
             if (lane == 0) out.roff[(int64_t)tb * out.nrows + dq] = (int32_t)(job.b_off - job.b_pos);
         }
     }
-    for (int r0 = 0; r0 < job.b_rows; r0 += 8) {
-        const int r = r0 + grp;
-        const bool rok = r < job.b_rows;
-        const T *row = B + (int64_t)(rok ? r : 0) * dp;
-        float acc[QS];
+    // QU groups of eight rows per pass (about eight 16-byte loads per lane): every chunk load
+    // of the pass is issued before the first product (chunk addresses past the row are
+    // clamped to its first chunk and their products skipped), so a wave waits on memory once
+    // per 8 QU rows
+    constexpr int QU = NCH >= 8 ? 1 : 8 / NCH;
+    for (int r0 = 0; r0 < job.b_rows; r0 += 8 * QU) {
+        uint4 v[QU][NCH];
 #pragma unroll
-        for (int qi = 0; qi < QS; qi++) acc[qi] = 0.f;
+        for (int u = 0; u < QU; u++) {
+            const int r = r0 + 8 * u + grp;
+            const T *row = B + (int64_t)(r < job.b_rows ? r : 0) * dp;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ch++) {
-            if (g + 8 * ch >= nchunk) continue;
-            const uint4 v = *reinterpret_cast<const uint4 *>(row + (g + 8 * ch) * EPC);
-            T pv[EPC];
-            __builtin_memcpy(pv, &v, sizeof(v));
+            for (int ch = 0; ch < NCH; ch++)
+                v[u][ch] = *reinterpret_cast<const uint4 *>(row + (g + 8 * ch < nchunk ? g + 8 * ch : g) * EPC);
+        }
 #pragma unroll
-            for (int e = 0; e < EPC; e++) {
-                const float x = (float)pv[e];
+        for (int u = 0; u < QU; u++) {
+            const int r = r0 + 8 * u + grp;
+            const bool rok = r < job.b_rows;
+            float acc[QS];
 #pragma unroll
-                for (int qi = 0; qi < QS; qi++) acc[qi] = __builtin_fmaf(x, qv[ch][e][qi], acc[qi]);
+            for (int qi = 0; qi < QS; qi++) acc[qi] = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ch++) {
+                if (g + 8 * ch >= nchunk) continue;
+                T pv[EPC];
+                __builtin_memcpy(pv, &v[u][ch], sizeof(v[u][ch]));
+#pragma unroll
+                for (int e = 0; e < EPC; e++) {
+                    const float x = (float)pv[e];
+#pragma unroll
+                    for (int qi = 0; qi < QS; qi++) acc[qi] = __builtin_fmaf(x, qv[ch][e][qi], acc[qi]);
+                }
             }
-        }
 #pragma unroll
-        for (int qi = 0; qi < QS; qi++) {
-            acc[qi] += __shfl_xor(acc[qi], 1, 64);
-            acc[qi] += __shfl_xor(acc[qi], 2, 64);
-            acc[qi] += __shfl_xor(acc[qi], 4, 64);
-        }
-        if (rok && g < na_rows) {
-            float gq = acc[0];
+            for (int qi = 0; qi < QS; qi++) {
+                acc[qi] += __shfl_xor(acc[qi], 1, 64);
+                acc[qi] += __shfl_xor(acc[qi], 2, 64);
+                acc[qi] += __shfl_xor(acc[qi], 4, 64);
+            }
+            if (rok && g < na_rows) {
+                float gq = acc[0];
 #pragma unroll
-            for (int qi = 1; qi < QS; qi++)
-                if (g == qi) gq = acc[qi];
-            const float2 nb = b_nrm[t * b_stride_tree + job.b_off + r];
-            const int bpt = b_pt[t * b_stride_tree + job.b_off + r];
-            float lb, ub;
-            pair_bounds(aq.x, nb.x, aq.y, nb.y, gq, bc, lb, ub);
-            if (out.mode == 0)
-                put_first(out, (int64_t)dst * out.cap + (int64_t)tb * out.ML + job.b_pos + r, lb, ub);
-            else if (lb <= tq)
-                emit_filtered(out, dst, bpt, lb, ub);
+                for (int qi = 1; qi < QS; qi++)
+                    if (g == qi) gq = acc[qi];
+                const float2 nb = b_nrm[t * b_stride_tree + job.b_off + r];
+                const int bpt = b_pt[t * b_stride_tree + job.b_off + r];
+                float lb, ub;
+                pair_bounds(aq.x, nb.x, aq.y, nb.y, gq, bc, lb, ub);
+                if (out.mode == 0)
+                    put_first(out, (int64_t)dst * out.cap + (int64_t)tb * out.ML + job.b_pos + r, lb, ub);
+                else if (lb <= tq)
+                    emit_filtered(out, dst, bpt, lb, ub);
+            }
         }
     }
 }
