@@ -1378,12 +1378,16 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
                                                      float *__restrict__ tau, Ent *__restrict__ list,
                                                      int32_t *__restrict__ lcnt, int lcap,
                                                      int32_t *__restrict__ cnt) {
-    // per-wave open-addressing hash of the small set: index -> smallest (ub, slot) packed as
-    // ub bits << 32 | slot (the order the representatives are defined by)
+    // per-wave open-addressing hash of the small set: index -> smallest (ub, slot), packed as
+    // one 32-bit key (the order the representatives are defined by)
     constexpr int kHBits = HT == 512 ? 9 : HT == 1024 ? 10 : 11;
     static_assert((1 << kHBits) == HT, "hash range must equal the table");
+    static_assert(64 * Q <= 65536, "a slot number fits the lower half of the key");
+    // the kept ub is the upper half of a binary32 pattern, so (ub bits | slot) orders entries
+    // by (ub, slot) in one 32-bit key (slots < 2^11)
     __shared__ int32_t s_hid[4][HT];
-    __shared__ unsigned long long s_hkey[4][HT];
+    __shared__ uint32_t s_hkey[4][HT];
+    __shared__ uint32_t s_sm[4][2][HT / 2];  // the compacted small set of each wave: key, index
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t a = (int64_t)blockIdx.x * 4 + w;
     if (a >= nrows) return;
@@ -1426,7 +1430,7 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     }
     for (int i = lane; i < HT; i += 64) {
         s_hid[w][i] = -1;
-        s_hkey[w][i] = ~0ull;
+        s_hkey[w][i] = 0xffffffffu;
     }
     int nv = 0;  // finite-ub slots (empty slots hold +inf bounds)
 #pragma unroll
@@ -1441,39 +1445,61 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     const bool over = ns > HT / 2;
     float tv = INFINITY;
     if (!over) {
-        wave_sync();  // the cleared table is visible
-        int hq[Q];
+        // the small set compacted to the front of per-wave staging arrays ((ub, slot) key,
+        // index), so the hash inserts and the representative tests below run over at most
+        // HT / 128 entries per lane rather than over all Q slots
+        uint32_t *s_sk = s_sm[w][0];
+        int32_t *s_si = reinterpret_cast<int32_t *>(s_sm[w][1]);
+        {
+            int base = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-            hq[q] = -1;
-            if (u[q] <= theta) {
-                const unsigned long long key = ((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q);
-                int h = (int)(((uint32_t)id[q] * 2654435761u) >> (32 - kHBits));
+            for (int q = 0; q < Q; q++) {
+                const bool in = u[q] <= theta;
+                const uint64_t mk = __ballot(in);
+                if (in) {
+                    const int p = base + mask_rank(mk);
+                    s_sk[p] = u[q] | (uint32_t)(lane + 64 * q);
+                    s_si[p] = id[q];
+                }
+                base += __popcll(mk);
+            }
+        }
+        wave_sync();  // the staged set and the cleared table are visible
+        constexpr int KS = HT / 128;  // ns <= HT / 2
+        int hq[KS];
+        uint32_t kq[KS];
+#pragma unroll
+        for (int k = 0; k < KS; k++) {
+            const int i = lane + 64 * k;
+            hq[k] = -1;
+            kq[k] = 0xffffffffu;
+            if (i < ns) {
+                kq[k] = s_sk[i];
+                const int32_t idk = s_si[i];
+                int h = (int)(((uint32_t)idk * 2654435761u) >> (32 - kHBits));
                 while (true) {  // at most half full: a free or matching entry is always found
-                    const int prev = atomicCAS(&s_hid[w][h], -1, id[q]);
-                    if (prev == -1 || prev == id[q]) break;
+                    const int prev = atomicCAS(&s_hid[w][h], -1, idk);
+                    if (prev == -1 || prev == idk) break;
                     h = (h + 1) & (HT - 1);
                 }
-                atomicMin(&s_hkey[w][h], key);
-                hq[q] = h;
+                atomicMin(&s_hkey[w][h], kq[k]);
+                hq[k] = h;
             }
         }
         wave_sync();
         // representatives: the entry of smallest (ub, slot) among equal indices; their ub keys
         // are compacted into the (now free) id column of the table, HT / 2 at most, and read
         // back HT / 128 per lane for the selection
-        bool rep[Q];
+        bool rep[KS];
 #pragma unroll
-        for (int q = 0; q < Q; q++)
-            rep[q] = hq[q] >= 0 &&
-                     s_hkey[w][hq[q]] == (((unsigned long long)u[q] << 32) | (uint32_t)(lane + 64 * q));
+        for (int k = 0; k < KS; k++) rep[k] = hq[k] >= 0 && s_hkey[w][hq[k]] == kq[k];
         wave_sync();  // every lookup is done before the id column is overwritten
         uint32_t *s_rv = reinterpret_cast<uint32_t *>(s_hid[w]);
         int nrep = 0;
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-            const uint64_t mk = __ballot(rep[q]);
-            if (rep[q]) s_rv[nrep + mask_rank(mk)] = u[q];
+        for (int k = 0; k < KS; k++) {
+            const uint64_t mk = __ballot(rep[k]);
+            if (rep[k]) s_rv[nrep + mask_rank(mk)] = kq[k] & 0xffff0000u;
             nrep += __popcll(mk);
         }
         wave_sync();
