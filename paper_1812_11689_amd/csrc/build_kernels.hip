@@ -513,6 +513,8 @@ __global__ void k_sel_init(const SegDesc *__restrict__ segs, int nseg, int T, Se
     s.chosen = 0;
     s.best_s2 = 0.0;
     s.s1 = 0.0;
+    s.counted = 0;
+    s.pad = 0;
     state[i] = s;
 }
 
@@ -593,7 +595,8 @@ __global__ __launch_bounds__(256) void k_sel_pass(const ChunkDesc *__restrict__ 
                                                   SelState *__restrict__ state, int nseg,
                                                   uint32_t *__restrict__ hist,
                                                   Cand *__restrict__ cand,
-                                                  uint32_t *__restrict__ cand_cnt) {
+                                                  uint32_t *__restrict__ cand_cnt,
+                                                  uint32_t *__restrict__ lcount, int nchunk) {
     __shared__ uint32_t s_hist[kDigitBins];
     __shared__ uint32_t s_w[8];
     const int t = blockIdx.y, tid = threadIdx.x;
@@ -621,12 +624,15 @@ __global__ __launch_bounds__(256) void k_sel_pass(const ChunkDesc *__restrict__ 
         for (int b = tid; b < kDigitBins; b += 256)
             if (s_hist[b]) atomicAdd(&gh[b], s_hist[b]);
     } else {
-        // gather the keys matching the prefix (at most kCandCap of them in the segment)
-        uint32_t mine = 0;
+        // gather the keys matching the prefix (at most kCandCap of them in the segment), each
+        // with its chunk; the chunk's keys below the prefix are counted on the way, so that
+        // the median's final step can complete the chunk's left count for the partition
+        uint32_t mine = 0, below = 0;
         for (int i = tid; i < c.len; i += 256) {
             const int64_t s = c.start + i;
             unsigned __int128 K = key96(kk[s], (uint32_t)pp[s]);
             mine += ((K >> sh) == (P >> sh)) ? 1u : 0u;
+            below += ((K >> sh) < (P >> sh)) ? 1u : 0u;
         }
         const int lane = tid & 63, wv = tid >> 6;
         uint32_t x = mine;
@@ -634,14 +640,18 @@ __global__ __launch_bounds__(256) void k_sel_pass(const ChunkDesc *__restrict__ 
             uint32_t y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
+        for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
         if (lane == 63) s_w[wv] = x;
+        if (lane == 0) s_w[4 + wv] = below;
         __syncthreads();
         uint32_t wb = 0, total = 0;
         for (int q = 0; q < 4; q++) {
             if (q < wv) wb += s_w[q];
             total += s_w[q];
         }
+        if (tid == 0) lcount[(int64_t)t * nchunk + blockIdx.x] = s_w[4] + s_w[5] + s_w[6] + s_w[7];
         if (total == 0) return;
+        __syncthreads();  // s_w[4] is read above before it is reused below
         if (tid == 0) s_w[4] = atomicAdd(&cand_cnt[(int64_t)t * nseg + c.seg], total);
         __syncthreads();
         uint32_t pos = s_w[4] + wb + x - mine;
@@ -650,7 +660,7 @@ __global__ __launch_bounds__(256) void k_sel_pass(const ChunkDesc *__restrict__ 
             const int64_t s = c.start + i;
             unsigned __int128 K = key96(kk[s], (uint32_t)pp[s]);
             if ((K >> sh) == (P >> sh)) {
-                if (pos < (uint32_t)kCandCap) cc[pos] = Cand{kk[s], (uint32_t)pp[s], 0u};
+                if (pos < (uint32_t)kCandCap) cc[pos] = Cand{kk[s], (uint32_t)pp[s], (uint32_t)blockIdx.x};
                 pos++;
             }
         }
@@ -664,7 +674,8 @@ __global__ __launch_bounds__(256) void k_sel_finish(const SegDesc *__restrict__ 
                                                     int64_t H, double *__restrict__ split,
                                                     int32_t *__restrict__ split_idx,
                                                     int32_t *__restrict__ chosen,
-                                                    int32_t *__restrict__ err) {
+                                                    int32_t *__restrict__ err,
+                                                    uint32_t *__restrict__ lcount, int nchunk) {
     __shared__ uint64_t s_hi[kCandCap];
     __shared__ uint32_t s_lo[kCandCap];
     __shared__ uint32_t s_h[256];
@@ -727,6 +738,15 @@ __global__ __launch_bounds__(256) void k_sel_finish(const SegDesc *__restrict__ 
             }
         }
         __syncthreads();
+        // the partition's left count of every chunk: its keys below the gathered prefix
+        // (counted by the gathering pass) plus its candidates below the median
+        const SelState fs = *stp;
+        if (fs.mode == SEL_DONE) {
+            const unsigned __int128 S = key96(fs.pfx_hi, fs.pfx_lo);
+            for (uint32_t i = tid; i < cnt; i += 256)
+                if (key96(s_hi[i], s_lo[i]) < S) atomicAdd(&lcount[(int64_t)t * nchunk + cc[i].pad], 1u);
+            if (tid == 0) stp->counted = 1;
+        }
     } else if (st.mode != SEL_DONE) {
         if (tid == 0) atomicOr(err, 4);
         return;
@@ -750,6 +770,7 @@ __global__ __launch_bounds__(256) void k_part_count(const ChunkDesc *__restrict_
     const int t = blockIdx.y, tid = threadIdx.x;
     const ChunkDesc c = chunks[blockIdx.x];
     const SelState st = state[(int64_t)t * nseg + c.seg];
+    if (st.counted) return;  // the median's final step counted this chunk already
     uint32_t mine = 0;
     for (int i = tid; i < c.len; i += 256) {
         const int64_t s = c.start + i;
@@ -1451,7 +1472,7 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
                            lk.look, n, b.keys, lk.ahead);
         launch_check(s, "k_proj_root");
         hipLaunchKernelGGL(k_sel_pass, gc, dim3(256), 0, s, chunks, b.keys, pin, n, b.state, nseg, b.hist, b.cand,
-                           b.cand_cnt);
+                           b.cand_cnt, b.lcount, nchunk);
         launch_check(s, "k_sel_pass");
     } else if (!lk.keys_in) {
         ProfScope ps(s, lk.look ? "proj_chunks_x3" : "proj_chunks", proj_bytes, 0);
@@ -1465,12 +1486,12 @@ void launch_level_large(hipStream_t s, bool vec, const float *X, int d, const fl
             launch_check(s, "k_sel_scan");
             if (j + 1 < kNumDigits) {
                 hipLaunchKernelGGL(k_sel_pass, gc, dim3(256), 0, s, chunks, b.keys, pin, n, b.state, nseg, b.hist,
-                                   b.cand, b.cand_cnt);
+                                   b.cand, b.cand_cnt, b.lcount, nchunk);
                 launch_check(s, "k_sel_pass");
             }
         }
         hipLaunchKernelGGL(k_sel_finish, gs, dim3(256), 0, s, segs, b.state, nseg, b.cand, b.cand_cnt, H, split,
-                           split_idx, chosen, err);
+                           split_idx, chosen, err, b.lcount, nchunk);
         launch_check(s, "k_sel_finish");
     }
     {

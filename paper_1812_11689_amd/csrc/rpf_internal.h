@@ -66,6 +66,8 @@ struct SelState {
     int32_t chosen;    // chosen try (Alg. 2)
     double best_s2;    // Alg. 2 running best spread
     double s1;         // Alg. 2 scratch: sum of projections of the current try
+    int32_t counted;   // 1: the final step filled the partition's left counts of the chunks
+    int32_t pad;
 };
 
 struct Ent {           // one pruning candidate: point index and bounds on its squared distance
