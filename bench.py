@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--serve-recall-rows", type=int, default=700, help="sampled request rows per K for recall")
     ap.add_argument("--serve-curve", default="16,32,64,96,128", help="tree counts of the served recall curve")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-data-sets leg")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-rule leg")
+    ap.add_argument("--only-uniform", default=None, metavar="T:PREC",
+                    help="run only the uniform-rule 1M x 128 step with T trees and PREC tiles, for profiling")
     ap.add_argument("--only-batched", action="store_true", help="run the many-data-sets leg alone (profiling)")
     ap.add_argument("--batch-count", type=int, default=512, help="data sets of the many-data-sets leg")
     ap.add_argument("--cpu-sample", type=int, default=20000,
@@ -411,6 +414,20 @@ def main():
         print(json.dumps({"only_step": f"allknn_1M_d128_T{Tq}", "prec": prec, **step_record(n, args.steps, el, times, prof)}),
               flush=True)
         return
+    if args.only_uniform:
+        Ts, prec = args.only_uniform.split(":")
+        w = W.make_config(2, n=args.n)
+        Xq = torch.from_numpy(w.x).cuda()
+
+        def one():
+            f = rpf.build(Xq, int(Ts), w.leaf_size, None, dist_prec=prec, split_rule="uniform", seed=UNIFORM_SEED)
+            out = f.all_knn(w.k)
+            f.free()
+            return out
+        _, el, times, prof = timed_steps(one, args.steps, args.warmup)
+        print(json.dumps({"only_uniform": f"allknn_1M_d128_T{Ts}_uniform", "prec": prec,
+                          **step_record(len(w.x), args.steps, el, times, prof)}), flush=True)
+        return
     t0 = time.time()
     w = W.make_config(2, n=args.n)
     n, d = w.x.shape
@@ -506,6 +523,14 @@ def main():
         named[prec] = step_record(n, args.steps, el, times, prof)
         named[prec]["identical_to_sweep"] = bool(torch.equal(idx, ref_idx[T0]))
         print(f"# T={T0} {prec}: {named[prec]['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+
+    # the uniform split rule of Alg. 1 (c uniform between the node's extreme projections,
+    # directions and split points from the library's counter-based generator) on the same
+    # data and K, at the headline's tree count and tile precision
+    uniform = None
+    if not args.no_uniform:
+        uniform = uniform_leg(args, X, n0, K, t_star, pts, truth, truth_d, res[args.headline_prec])
+        print(f"# uniform rule: {uniform}", file=sys.stderr, flush=True)
 
     # the same step recorded once as a HIP graph (rpf_plan_*: build and candidate stage, tuned
     # first-phase tree count), inputs set once before the timed launches
@@ -622,12 +647,50 @@ def main():
         "roofline_kernel": dom,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "uniform_rule": uniform,
         "precision_path": precision,
         "accuracy_sweep": accuracy_sweep,
         "serving": serving,
         "batched": batched,
     }
     print(json.dumps(line), flush=True)
+
+
+UNIFORM_SEED = 11689400  # key of the uniform rule's generator in the bench
+
+
+def uniform_leg(args, X, n0, K, T, pts, truth, truth_d, median_rec):
+    """Alg. 1 as printed (RPF_SPLIT_UNIFORM) over the headline's data, K, tree count and tile
+    precision: the whole step (build + all-points kNN + free), its recall against the same
+    exact truth, the forest's shape, and the step time against the median rule's."""
+    import torch
+    from paper_1812_11689_amd import metrics, rpf
+    n = X.shape[0]
+    prec = args.headline_prec
+
+    def step():
+        f = rpf.build(X, T, n0, None, dist_prec=prec, split_rule="uniform", seed=UNIFORM_SEED)
+        out = f.all_knn(K)
+        f.free()
+        return out
+    (idx, dist), el, times, prof = timed_steps(step, args.steps, args.warmup)
+    rec = step_record(n, args.steps, el, times, prof)
+    f = rpf.build(X, T, n0, None, dist_prec=prec, split_rule="uniform", seed=UNIFORM_SEED)
+    info = f.info()
+    i2, _ = f.all_knn(K)
+    st = f.knn_stats()
+    f.free()
+    torch.cuda.synchronize()
+    rec.update({
+        "workload": f"allknn_1M_d128_T{T}_uniform", "n_trees": T, "tile_prec": prec, "seed": UNIFORM_SEED,
+        "recall": round(metrics.recall(idx.cpu().numpy()[pts], truth), 5),
+        "kth_distance_excess": round(metrics.kth_distance_excess(dist.cpu().numpy()[pts], truth_d), 6),
+        "deepest_leaf": info["depth"], "most_leaves_per_tree": info["n_leaves"],
+        "repeatable": bool(torch.equal(idx, i2)), "knn_stats": st,
+        "median_rule_ms_per_step": median_rec["ms_per_step"],
+        "time_vs_median_rule": round(rec["ms_per_step"] / median_rec["ms_per_step"], 4),
+    })
+    return rec
 
 
 def precision_leg(args):

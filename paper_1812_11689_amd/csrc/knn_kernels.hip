@@ -3260,7 +3260,12 @@ static int max_first_trees(const ForestView &v, int K) { return max_first_trees_
 // and the tighter threshold of more first-phase trees pays for itself there (the plan tuner
 // picks 8 at 10^6 points, K 20, T 80 in bf16, and 4 in fp32 or at T 32).
 static int all_points_first_trees(const ForestView &v, int K) {
-    const int want = (v.prec != RPF_DIST_FP32 && v.T >= 64) ? 2 * kFirstTrees : kFirstTrees;
+    int want = (v.prec != RPF_DIST_FP32 && v.T >= 64) ? 2 * kFirstTrees : kFirstTrees;
+    // uniform-rule trees: leaves of every size up to n0 (at 10^6 x 128, n0 256, a median of
+    // about 40 points), so four trees' leaves hold too few candidates for a tight threshold.
+    // (The slot stride follows the largest leaf of any tree, so a deep chain of uneven splits
+    // that ends in a large leaf at the depth cap still limits the count.)
+    if (v.leaf_stride > 0) want = 2 * kFirstTrees;
     return std::min(want, max_first_trees(v, K));
 }
 
