@@ -439,6 +439,13 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     const int32_t *ad = a_dest + t * a_stride_tree + job.a_off;
     const int32_t *bp = b_pt + t * b_stride_tree + job.b_off;
     const int tb = t - out.t0;
+    if (out.mode == 0 && job.leaf_m > out.ML) {
+        // a leaf above the first-phase slot stride (a uniform-rule leaf kept whole at the
+        // depth cap): its rows take the exhaustive path, which a negative leaf start tells
+        // the merge; no slot is written
+        for (int r = tid; r < job.a_rows; r += NT) out.roff[(int64_t)tb * out.nrows + ad[r]] = -1;
+        return;
+    }
 
     for (int r = tid; r < M; r += NT) {
         if (r < job.a_rows) {
@@ -674,6 +681,10 @@ __global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__
     const int32_t *ap = perm + (int64_t)t * n + job.a_off;
     const int32_t *bp = perm + (int64_t)t * n + job.b_off;
     const int tb = t - out.t0;
+    if (out.mode == 0 && job.leaf_m > out.ML) {  // as in k_tile: the rows take the exhaustive path
+        for (int r = tid; r < job.a_rows; r += NT) out.roff[(int64_t)tb * out.nrows + ap[r]] = -1;
+        return;
+    }
     for (int r = tid; r < M; r += NT) {
         if (r < job.a_rows) {
             const int p = ap[r];
@@ -909,6 +920,10 @@ void k_tile_sym(
     const float2 *an = nrm + t * stride_tree + job.a_off;
     const int32_t *ap = pt + t * stride_tree + job.a_off;
     const int tb = t - out.t0;
+    if (MODE == 0 && m > out.ML) {  // as in k_tile: the rows take the exhaustive path
+        for (int r = tid; r < m; r += NT) out.roff[(int64_t)tb * out.nrows + ap[r]] = -1;
+        return;
+    }
     for (int r = tid; r < M; r += NT) {
         if (r < m) {
             const float2 q = an[r];
@@ -1442,7 +1457,9 @@ __global__ __launch_bounds__(256) void k_merge_first(int64_t nrows, int K, int B
     int ns = 0;
 #pragma unroll
     for (int q = 0; q < Q; q++) ns += __popcll(__ballot(u[q] <= theta));
-    const bool over = ns > HT / 2;
+    // a leaf start of -1: the row's leaf in a first-phase tree was above the slot stride, its
+    // slots were not written (the row takes the exhaustive path)
+    const bool over = ns > HT / 2 || __ballot(lane < B && loff < 0) != 0;
     float tv = INFINITY;
     if (!over) {
         // the small set compacted to the front of per-wave staging arrays ((ub, slot) key,
@@ -2998,13 +3015,20 @@ static void set_layout(CandWs &w, const RecLayout &lay) {
     w.cap2 = lay.cap2;
 }
 
+// first-phase slots per (row, tree): the largest leaf, but at most the leaf size n0 (only a
+// uniform-rule leaf kept whole at the depth cap or over duplicates exceeds it; the rows of
+// such a leaf in a first-phase tree take the exhaustive path)
+static int first_slot_leaf(const ForestView &v) { return std::min(v.max_leaf, std::max(v.n0, 1)); }
+static int first_slot_stride(const ForestView &v) { return slot_stride(first_slot_leaf(v)); }
+
+
 // Phase I keeps every pair of a row's first B leaves; Phase II keeps pairs below the
 // threshold of the union of those leaves.  `get` hands out device bytes (nullptr = failure).
 template <typename Get>
 static bool cand_ws_alloc(const ForestView &v, const CandStage &cs, int K, Get get, CandWs &w) {
     const int64_t rows = cs.rows;
     set_layout(w, stage_layout(v, cs, K));
-    w.cap1 = slot_stride(v.max_leaf) * cs.B;  // Phase I slots per row (bounds)
+    w.cap1 = first_slot_stride(v) * cs.B;  // Phase I slots per row (bounds)
     // the Phase II records reuse the Phase I arrays, dead once the first merge has run
     const size_t first_bytes = (size_t)rows * w.cap1 * 4 + (size_t)rows * cs.B * 4;  // slots, leaf starts
     const size_t second_bytes = (size_t)rows * w.cap2 * sizeof(Ent);
@@ -3085,7 +3109,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     TileOut o1;
     o1.mode = 0;
     o1.t0 = 0;
-    o1.ML = slot_stride(v.max_leaf);
+    o1.ML = first_slot_stride(v);
     o1.cap = cap1;
     o1.ent = nullptr;
     o1.cnt = cnt;
@@ -3131,7 +3155,7 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
         const bool big = K * cs.B > 128;
         const SlotIndex si{roff, v.perm, v.n};
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, slot_stride(v.max_leaf), plub, si, cap1, tau, list,
+            hipLaunchKernelGGL(kern, mg, dim3(256), 0, s, rows, K, cs.B, first_slot_stride(v), plub, si, cap1, tau, list,
                                lcnt, lcap, cnt);
         };
         switch (merge_first_q(cap1)) {
@@ -3253,7 +3277,7 @@ static rpf_status run_cand_stage(const ForestView &v, const CandStage &cs, int K
 }
 
 // largest first-phase tree count the merge supports for this forest and K
-static int max_first_trees(const ForestView &v, int K) { return max_first_trees_for(v.T, K, v.max_leaf); }
+static int max_first_trees(const ForestView &v, int K) { return max_first_trees_for(v.T, K, first_slot_leaf(v)); }
 
 // Default first-phase trees of the all-points search: kFirstTrees, or twice that for bf16 /
 // fp16 tiles over 64 trees or more.  Their looser bounds emit more Phase II records per row,
@@ -3339,7 +3363,7 @@ KnnShared *knn_shared_create(const std::vector<const rpf_forest *> &parts, const
             CandStage cb = cs;
             cb.B = B;
             const RecLayout lay = stage_layout(v, cb, K);
-            const size_t cap1 = (size_t)slot_stride(v.max_leaf) * B;
+            const size_t cap1 = (size_t)first_slot_stride(v) * B;
             b_region = std::max(b_region, std::max((size_t)v.n * cap1 * 4 + (size_t)v.n * B * 4,
                                                    (size_t)v.n * lay.cap2 * sizeof(Ent)) + 256);
             b_list = std::max(b_list, (size_t)v.n * lay.lcap * sizeof(Ent));
@@ -3398,7 +3422,7 @@ void knn_part_launch(const KnnShared *p, const rpf_forest *f, int B, int shape, 
     cs.bucket_S = bucket_S;
     CandWs w = p->w;
     set_layout(w, stage_layout(v, cs, p->K));
-    w.cap1 = slot_stride(v.max_leaf) * cs.B;
+    w.cap1 = first_slot_stride(v) * cs.B;
     cand_launches(v, cs, p->K, w, out_idx, out_dist, s);
 }
 
@@ -3466,7 +3490,7 @@ static rpf_status knn_query_get(const rpf_forest *f, const float *Q, int64_t m, 
     void *Qc = take((size_t)T * m * v.dp * esz);
     float2 *qnrm = static_cast<float2 *>(take((size_t)T * m * 8));
     const int nbt = (v.max_leaf + TR - 1) / TR;
-    const int nfirst = first_trees(T, K, v.max_leaf);
+    const int nfirst = first_trees(T, K, first_slot_leaf(v));
     const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
     const int64_t jcap0 = jcap_tree * nfirst;
     const int64_t jcap1 = jcap_tree * (T > nfirst ? T - nfirst : 1);
@@ -3549,7 +3573,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     const int TR = 32 * v.job_mb;
     const uint64_t esz = v.prec == RPF_DIST_FP32 ? 4 : 2;
     const int nbt = (v.max_leaf + TR - 1) / TR;
-    const int B = first_trees(v.T, K, v.max_leaf);
+    const int B = first_trees(v.T, K, first_slot_leaf(v));
     const int64_t jcap_tree = (m / TR + std::min<int64_t>(m, nleaf) + 1) * nbt;
     uint64_t b = 0;
     b += (uint64_t)T * m * 4 * 3;                  // leaf per tree, order, group leaf
@@ -3558,7 +3582,7 @@ uint64_t query_workspace_bytes(const rpf_forest *f, int64_t m, int K) {
     b += (uint64_t)jcap_tree * (B + (T > B ? T - B : 1)) * sizeof(TileJob) * (qtile_qs(v.prec, v.dp) ? 2 : 1);
     int lcap = 0, cap2 = 0;
     cand_caps(K, v.T, B, m, lcap, cap2);
-    const uint64_t cap1 = (uint64_t)slot_stride(v.max_leaf) * B;
+    const uint64_t cap1 = (uint64_t)first_slot_stride(v) * B;
     b += std::max(m * cap1 * 4 + m * (uint64_t)B * 4, m * (uint64_t)cap2 * sizeof(Ent)) + 256;
     b += (uint64_t)m * 4 * 5 + (uint64_t)m * lcap * sizeof(Ent) + 16 * 3;
     return b + (uint64_t)16 * 4096;  // allocator rounding of the ~16 blocks
