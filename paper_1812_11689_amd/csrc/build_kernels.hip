@@ -206,6 +206,138 @@ __global__ __launch_bounds__(256) void k_level_small(
     }
 }
 
+
+// Fed levels of small segments (at most kWaveSeg members, one direction per node): one wave
+// per (segment, tree), four segments per workgroup.  The wave holds the keys the lead
+// level's partition made and the member ids in registers, eight per lane (position
+// i = lane + 64 e), selects the member of rank floor(m/2) in (key, index) order with 8-bit
+// radix passes over a per-wave LDS histogram, and writes the stable partition: the same
+// operations and result as k_level_small on a fed level, without workgroup barriers.
+constexpr int kWaveSeg = 512;
+
+__global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restrict__ segs, int nseg,
+                                                        const int32_t *__restrict__ perm_in,
+                                                        int32_t *__restrict__ perm_out, int64_t n, int64_t H,
+                                                        double *__restrict__ split, int32_t *__restrict__ split_idx,
+                                                        int32_t *__restrict__ chosen, int32_t *__restrict__ err,
+                                                        const uint64_t *__restrict__ keys_in) {
+    __shared__ uint32_t s_hist[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k = blockIdx.x * 4 + w, t = blockIdx.y;
+    if (k >= nseg) return;  // a whole wave; nothing below waits on the workgroup
+    const SegDesc sg = segs[k];
+    const int m = sg.size;
+    const int32_t *pin = perm_in + (int64_t)t * n + sg.off;
+    const uint64_t *kin = keys_in + (int64_t)t * n + sg.off;
+    uint64_t kk[8];
+    uint32_t id[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int i = lane + 64 * e;
+        kk[e] = i < m ? kin[i] : 0;
+        id[e] = i < m ? (uint32_t)pin[i] : 0u;
+    }
+    uint32_t *h = s_hist[w];
+    uint64_t phi = 0;
+    uint32_t plo = 0;
+    int nbits = 0;
+    uint32_t rank = (uint32_t)(m / 2), cnt = (uint32_t)m;
+    while (cnt > 1 && nbits < 96) {
+        const int lo_bit = 88 - nbits;
+        const unsigned __int128 P = key96(phi, plo);
+#pragma unroll
+        for (int j = 0; j < 4; j++) h[lane + 64 * j] = 0;
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int i = lane + 64 * e;
+            const unsigned __int128 K = key96(kk[e], id[e]);
+            if (i < m && (nbits == 0 || (K >> (96 - nbits)) == (P >> (96 - nbits))))
+                atomicAdd(&h[(uint32_t)(K >> lo_bit) & 255u], 1u);
+        }
+        wave_sync();
+        // lane l holds bins 4l .. 4l + 3; an inclusive scan of their sums over the lanes
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            v[j] = h[4 * lane + j];
+            sum += v[j];
+        }
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        uint32_t run = incl - sum;  // members in the bins below this lane's
+        int bsel = -1;
+        uint32_t ex = 0, vc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (bsel < 0 && run <= rank && rank < run + v[j]) {
+                bsel = 4 * lane + j;
+                ex = run;
+                vc = v[j];
+            }
+            run += v[j];
+        }
+        const uint64_t own = __ballot(bsel >= 0);  // exactly one lane holds the rank
+        const int src = own ? __builtin_ctzll(own) : 0;
+        const uint32_t b = (uint32_t)__shfl(bsel, src, 64);
+        rank -= (uint32_t)__shfl((int)ex, src, 64);
+        cnt = (uint32_t)__shfl((int)vc, src, 64);
+        const unsigned __int128 NP = P | ((unsigned __int128)b << lo_bit);
+        phi = (uint64_t)(NP >> 32);
+        plo = (uint32_t)NP;
+        nbits += 8;
+        wave_sync();  // every read of the histogram is done before the next pass clears it
+    }
+    if (nbits < 96) {  // exactly one key matches the prefix: it is the median
+        const unsigned __int128 P = key96(phi, plo);
+        uint64_t mh = 0;
+        uint32_t ml = 0;
+        bool found = false;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int i = lane + 64 * e;
+            const unsigned __int128 K = key96(kk[e], id[e]);
+            if (i < m && (K >> (96 - nbits)) == (P >> (96 - nbits))) {
+                mh = kk[e];
+                ml = id[e];
+                found = true;
+            }
+        }
+        const uint64_t own = __ballot(found);
+        const int src = own ? __builtin_ctzll(own) : 0;
+        phi = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mh >> 32), src, 64) << 32) |
+              (uint32_t)__shfl((int)(uint32_t)mh, src, 64);
+        plo = (uint32_t)__shfl((int)ml, src, 64);
+    }
+    // stable partition: left = keys below (c, c_idx), in position (= index) order
+    const int half = m / 2;
+    int32_t *pout = perm_out + (int64_t)t * n + sg.off;
+    uint32_t lefts = 0;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int i = lane + 64 * e;
+        const bool valid = i < m;
+        const bool left = valid && key_less(kk[e], id[e], phi, plo);
+        const uint64_t mk = __ballot(left);
+        if (valid) {
+            const int lb = (int)lefts + mask_rank(mk);
+            const int pos = left ? lb : half + (i - lb);
+            if (pos >= 0 && pos < m) pout[pos] = (int32_t)id[e];
+        }
+        lefts += (uint32_t)__popcll(mk);
+    }
+    if (lane == 0) {
+        const int64_t hs = (int64_t)t * H + (sg.heap - 1);
+        split[hs] = val_of(phi);
+        split_idx[hs] = (int32_t)plo;
+        chosen[hs] = 0;
+        if (lefts != (uint32_t)half) atomicOr(err, 1);
+    }
+}
+
 // ================================================================ small subtrees: one persistent launch
 
 // One internal node of a subtree, by the whole block (256 threads), nTry = 1: project the
@@ -1397,6 +1529,12 @@ void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const fl
                         int n_try, const SegDesc *segs, int nseg, int max_m, int T,
                         const int32_t *pin, int32_t *pout, int64_t n, double *split,
                         int32_t *split_idx, int32_t *chosen, int32_t *err, const LevelLink &lk) {
+    if (!lk.look && lk.keys_in && n_try == 1 && max_m <= kWaveSeg) {  // fed level of small segments
+        hipLaunchKernelGGL(k_level_fed_wave, dim3((nseg + 3) / 4, T), dim3(256), 0, s, segs, nseg, pin, pout, n, H,
+                           split, split_idx, chosen, err, lk.keys_in);
+        launch_check(s, "k_level_fed_wave");
+        return;
+    }
     const size_t lds = level_small_lds(max_m, d, n_try);
     dim3 grid(nseg, T);
     auto go = [&](auto kern) {
