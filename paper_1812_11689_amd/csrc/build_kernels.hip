@@ -207,14 +207,15 @@ __global__ __launch_bounds__(256) void k_level_small(
 }
 
 
-// Fed levels of small segments (at most kWaveSeg members, one direction per node): one wave
-// per (segment, tree), four segments per workgroup.  The wave holds the keys the lead
-// level's partition made and the member ids in registers, eight per lane (position
-// i = lane + 64 e), selects the member of rank floor(m/2) in (key, index) order with 8-bit
+// Fed levels of small segments (at most 64 E members, one direction per node): one wave per
+// (segment, tree), four segments per workgroup.  The wave holds the keys the lead level's
+// partition made and the member ids in registers, E per lane (position i = lane + 64 e),
+// selects the member of rank floor(m/2) in (key, index) order with 8-bit
 // radix passes over a per-wave LDS histogram, and writes the stable partition: the same
 // operations and result as k_level_small on a fed level, without workgroup barriers.
-constexpr int kWaveSeg = 512;
+constexpr int kWaveSeg = 1024;  // largest segment of the wave-per-segment fed level
 
+template <int E>
 __global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restrict__ segs, int nseg,
                                                         const int32_t *__restrict__ perm_in,
                                                         int32_t *__restrict__ perm_out, int64_t n, int64_t H,
@@ -229,10 +230,10 @@ __global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restric
     const int m = sg.size;
     const int32_t *pin = perm_in + (int64_t)t * n + sg.off;
     const uint64_t *kin = keys_in + (int64_t)t * n + sg.off;
-    uint64_t kk[8];
-    uint32_t id[8];
+    uint64_t kk[E];
+    uint32_t id[E];
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
+    for (int e = 0; e < E; e++) {
         const int i = lane + 64 * e;
         kk[e] = i < m ? kin[i] : 0;
         id[e] = i < m ? (uint32_t)pin[i] : 0u;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restric
         for (int j = 0; j < 4; j++) h[lane + 64 * j] = 0;
         wave_sync();
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
+        for (int e = 0; e < E; e++) {
             const int i = lane + 64 * e;
             const unsigned __int128 K = key96(kk[e], id[e]);
             if (i < m && (nbits == 0 || (K >> (96 - nbits)) == (P >> (96 - nbits))))
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restric
         uint32_t ml = 0;
         bool found = false;
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
+        for (int e = 0; e < E; e++) {
             const int i = lane + 64 * e;
             const unsigned __int128 K = key96(kk[e], id[e]);
             if (i < m && (K >> (96 - nbits)) == (P >> (96 - nbits))) {
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256) void k_level_fed_wave(const SegDesc *__restric
     int32_t *pout = perm_out + (int64_t)t * n + sg.off;
     uint32_t lefts = 0;
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
+    for (int e = 0; e < E; e++) {
         const int i = lane + 64 * e;
         const bool valid = i < m;
         const bool left = valid && key_less(kk[e], id[e], phi, plo);
@@ -1530,8 +1531,12 @@ void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const fl
                         const int32_t *pin, int32_t *pout, int64_t n, double *split,
                         int32_t *split_idx, int32_t *chosen, int32_t *err, const LevelLink &lk) {
     if (!lk.look && lk.keys_in && n_try == 1 && max_m <= kWaveSeg) {  // fed level of small segments
-        hipLaunchKernelGGL(k_level_fed_wave, dim3((nseg + 3) / 4, T), dim3(256), 0, s, segs, nseg, pin, pout, n, H,
-                           split, split_idx, chosen, err, lk.keys_in);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((nseg + 3) / 4, T), dim3(256), 0, s, segs, nseg, pin, pout, n, H, split,
+                               split_idx, chosen, err, lk.keys_in);
+        };
+        if (max_m <= 512) go(k_level_fed_wave<8>);
+        else go(k_level_fed_wave<16>);
         launch_check(s, "k_level_fed_wave");
         return;
     }
