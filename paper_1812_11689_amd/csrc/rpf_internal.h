@@ -413,6 +413,51 @@ __device__ inline double group8_dot64(const float *__restrict__ x, const float *
     return v + 0.0;
 }
 
+// Projections of two rows xa, xb onto one direction r (binary32, usually in LDS) from one
+// pass, the loads of both rows in flight together; each equals group8_dot64's bit for bit.
+template <bool VEC>
+__device__ inline void group8_dot64r2(const float *__restrict__ xa, const float *__restrict__ xb,
+                                      const float *__restrict__ r, int d, int g, double &pa, double &pb) {
+    double s[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    if (VEC) {
+        for (int j = 4 * g; j < d; j += 32) {
+            const float4 va = *reinterpret_cast<const float4 *>(xa + j);
+            const float4 vb = *reinterpret_cast<const float4 *>(xb + j);
+            const float4 rv = *reinterpret_cast<const float4 *>(r + j);
+            s[0][0] = __builtin_fma((double)va.x, (double)rv.x, s[0][0]);
+            s[0][1] = __builtin_fma((double)va.y, (double)rv.y, s[0][1]);
+            s[0][2] = __builtin_fma((double)va.z, (double)rv.z, s[0][2]);
+            s[0][3] = __builtin_fma((double)va.w, (double)rv.w, s[0][3]);
+            s[1][0] = __builtin_fma((double)vb.x, (double)rv.x, s[1][0]);
+            s[1][1] = __builtin_fma((double)vb.y, (double)rv.y, s[1][1]);
+            s[1][2] = __builtin_fma((double)vb.z, (double)rv.z, s[1][2]);
+            s[1][3] = __builtin_fma((double)vb.w, (double)rv.w, s[1][3]);
+        }
+    } else {
+        for (int j = 4 * g; j < d; j += 32) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (e == 0 || j + e < d) {
+                    const double rv = (double)r[j + e];
+                    s[0][e] = __builtin_fma((double)xa[j + e], rv, s[0][e]);
+                    s[1][e] = __builtin_fma((double)xb[j + e], rv, s[1][e]);
+                }
+            }
+        }
+    }
+    double v[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        double w = (s[k][0] + s[k][1]) + (s[k][2] + s[k][3]);
+        w = w + shfl_xor_d(w, 1);
+        w = w + shfl_xor_d(w, 2);
+        w = w + shfl_xor_d(w, 4);
+        v[k] = w + 0.0;
+    }
+    pa = v[0];
+    pb = v[1];
+}
+
 // Projections of two rows xa, xb onto three directions r, r + rs, r + 2 rs (binary32 values
 // held as binary64, converted once per block rather than once per row) from one read of each
 // row, every direction value read once for both rows; each projection is computed exactly as

@@ -169,10 +169,13 @@ __global__ __launch_bounds__(NT) void k_uni_block(const float *__restrict__ X, i
         __syncthreads();  // the previous try is done with the direction
         for (int j = tid; j < ds; j += NT) s_dir[j] = j < d ? uni_coord(key, tr, d, j) : 0.f;
         __syncthreads();
-        for (int base = 0; base < m; base += NT / 8) {
-            const int i = base + pt;
-            const double p = group8_dot64<VEC>(X + (int64_t)s_ids[i < m ? i : 0] * d, s_dir, d, g);
-            if (g == 0 && i < m) s_p[i] = p;
+        for (int base = 0; base < m; base += NT / 4) {  // rows base + pt and base + NT / 8 + pt
+            const int ia = base + pt, ib = ia + NT / 8;
+            double pa, pb;
+            group8_dot64r2<VEC>(X + (int64_t)s_ids[ia < m ? ia : 0] * d, X + (int64_t)s_ids[ib < m ? ib : 0] * d,
+                                s_dir, d, g, pa, pb);
+            if (g == 0 && ia < m) s_p[ia] = pa;
+            if (g == 0 && ib < m) s_p[ib] = pb;
         }
         __syncthreads();
         if (n_try == 1) break;
@@ -232,8 +235,8 @@ __global__ __launch_bounds__(256) void k_uni_proj(const float *__restrict__ X, i
                                                   double *__restrict__ P, double *__restrict__ part,
                                                   double2 *__restrict__ mm) {
     __shared__ __align__(16) float s_dir[4096];
-    __shared__ double s_p[kChunk];
     __shared__ double s_red[8];
+    extern __shared__ double s_p[];  // kChunk projections of the chunk, only for several tries
     const UniChunk c = chunks[blockIdx.x];
     const UniSeg sg = segs[c.seg];
     const int tid = threadIdx.x, g = tid & 7, pt = tid >> 3;
@@ -244,15 +247,22 @@ __global__ __launch_bounds__(256) void k_uni_proj(const float *__restrict__ X, i
         for (int j = tid; j < ds; j += 256) s_dir[j] = j < d ? uni_coord(key, tr, d, j) : 0.f;
         __syncthreads();
         double lo = INFINITY, hi = -INFINITY;
-        for (int base = 0; base < c.len; base += 32) {
-            const int i = base + pt;
-            const int32_t id = perm[c.pos + (i < c.len ? i : 0)];
-            const double p = group8_dot64<VEC>(X + (int64_t)id * d, s_dir, d, g);
-            if (g == 0 && i < c.len) {
-                P[(int64_t)tr * TN + c.pos + i] = p;
-                s_p[i] = p;
-                lo = fmin(lo, p);
-                hi = fmax(hi, p);
+        for (int base = 0; base < c.len; base += 64) {  // rows base + pt and base + 32 + pt
+            const int ia = base + pt, ib = ia + 32;
+            const int32_t ida = perm[c.pos + (ia < c.len ? ia : 0)];
+            const int32_t idb = perm[c.pos + (ib < c.len ? ib : 0)];
+            double p2[2];
+            group8_dot64r2<VEC>(X + (int64_t)ida * d, X + (int64_t)idb * d, s_dir, d, g, p2[0], p2[1]);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int i = h ? ib : ia;
+                const double p = p2[h];
+                if (g == 0 && i < c.len) {
+                    P[(int64_t)tr * TN + c.pos + i] = p;
+                    if (n_try > 1) s_p[i] = p;
+                    lo = fmin(lo, p);
+                    hi = fmax(hi, p);
+                }
             }
         }
         block_minmax<256>(lo, hi, s_red);
@@ -419,11 +429,11 @@ void launch_uni_chunked(hipStream_t s, const float *X, int d, int n_try, uint64_
     if (nseg <= 0) return;
     const bool vec = d % 4 == 0;
     if (vec)
-        hipLaunchKernelGGL(k_uni_proj<true>, dim3(nchunk), dim3(256), 0, s, X, d, n_try, seed, segs, chunks, perm, TN,
-                           b.P, b.part, b.mm);
+        hipLaunchKernelGGL(k_uni_proj<true>, dim3(nchunk), dim3(256), n_try > 1 ? kChunk * sizeof(double) : 0, s, X,
+                           d, n_try, seed, segs, chunks, perm, TN, b.P, b.part, b.mm);
     else
-        hipLaunchKernelGGL(k_uni_proj<false>, dim3(nchunk), dim3(256), 0, s, X, d, n_try, seed, segs, chunks, perm, TN,
-                           b.P, b.part, b.mm);
+        hipLaunchKernelGGL(k_uni_proj<false>, dim3(nchunk), dim3(256), n_try > 1 ? kChunk * sizeof(double) : 0, s, X,
+                           d, n_try, seed, segs, chunks, perm, TN, b.P, b.part, b.mm);
     launch_check(s, "k_uni_proj");
     if (n_try > 1) {
         const int64_t items = (int64_t)nseg * n_try;
