@@ -653,27 +653,39 @@ __device__ inline int32_t lattice_phi(float tv, int32_t na, float ra, float rbma
     return ph >= 2.0e9 ? INT32_MAX : (int32_t)ph;
 }
 
+// Workgroups are dealt to the eight XCDs in turn, so block b runs on XCD b % 8.  Block b takes
+// job (b % 8) * per + b / 8: each XCD walks one contiguous range of the job list front to back,
+// so the tiles of one leaf, which read the same rows, meet in that XCD's L2.  The grid is
+// 8 * per blocks with per = ceil(njobs / 8); blocks past the list return.
+__device__ inline int64_t xcd_job() {
+    const int64_t per = (int64_t)gridDim.x >> 3;
+    return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
 // All-points tile of grid points (one job: A rows x B rows of one leaf, MB waves; wave w owns
 // A rows [32w, 32w + 32)): rows are gathered from the int8 copy through the permutation, the
 // integer Gram product runs on v_mfma_i32_32x32x32_i8, and the grid distance
 // |k_a - 128|^2 + |k_b - 128|^2 - 2G is exact.  Outputs as the other tiles (Phase I slots,
-// Phase II records below the row's threshold).
+// Phase II records below the row's threshold).  Jobs are taken in XCD order (xcd_job).
 template <int MB>
-__global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__ jobs, const int8_t *__restrict__ Xq,
+__global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__ jobs, int64_t njobs,
+                                                    const int8_t *__restrict__ Xq,
                                                     int dq, const LatNorm *__restrict__ qn,
                                                     const int32_t *__restrict__ perm, int64_t n, int exclude_self,
                                                     TileOut out) {
     constexpr int M = 32 * MB;
     constexpr int NT = 64 * MB;
-    __shared__ __align__(16) int8_t s_a[M * kQ8LDW];
-    __shared__ __align__(16) int8_t s_b[M * kQ8LDW];
+    __shared__ __align__(16) int8_t s_a[2][M * kQ8LDW];
+    __shared__ __align__(16) int8_t s_b[2][M * kQ8LDW];
     __shared__ int32_t s_na[M], s_nb[M], s_phi[M];
     __shared__ float s_ra[M], s_rb[M], s_tau[M];
     __shared__ int32_t s_dst[M], s_bpt[M];
     __shared__ float s_rbmax;
     __shared__ uint2 s_que[MB][kQueue];
 
-    const TileJob job = jobs[blockIdx.x];
+    const int64_t ji = xcd_job();
+    if (ji >= njobs) return;
+    const TileJob job = jobs[ji];
     const int t = job.tree;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -743,37 +755,66 @@ __global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__
     const int fk = 16 * (lane >> 5);  // the lane's 16 consecutive int8 of the 32-column step
     const int a_pad = ((job.a_rows + 31) >> 5) << 5;
     const int b_pad = nbb << 5;
+    // Staging: thread tid owns the 16-byte piece (tid % VPR) of rows tid / VPR + SR * i (i < 2)
+    // of each side.  Chunks are double-buffered in LDS and the gathers of chunk c + 1 are issued
+    // before the MFMAs of chunk c, so their latency hides behind the products.  Rows past the
+    // tile load a valid row (the tile's first) and stage zeros.
     constexpr int VPR = kQ8KC / 16;  // 16-byte vectors per staged row chunk
-    for (int k0 = 0; k0 < dq; k0 += kQ8KC) {
-        __syncthreads();
-        for (int v = tid; v < a_pad * VPR; v += NT) {
-            const int r = v / VPR, c = (v % VPR) * 16;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (r < job.a_rows) val = *reinterpret_cast<const uint4 *>(Xq + (int64_t)s_dst[r] * dq + k0 + c);
-            *reinterpret_cast<uint4 *>(s_a + r * kQ8LDW + c) = val;
+    constexpr int SR = NT / VPR;     // rows staged per pass (M = 2 SR)
+    static_assert(M == 2 * SR, "two staged rows per thread and side");
+    const int sc = (tid % VPR) * 16;
+    const int sr0 = tid / VPR, sr1 = sr0 + SR;
+    const bool oka0 = sr0 < job.a_rows, oka1 = sr1 < job.a_rows;
+    const bool okb0 = sr0 < job.b_rows, okb1 = sr1 < job.b_rows;
+    const bool sta0 = sr0 < a_pad, sta1 = sr1 < a_pad;
+    const bool stb0 = !same && sr0 < b_pad, stb1 = !same && sr1 < b_pad;
+    const int8_t *ga0 = Xq + (int64_t)s_dst[oka0 ? sr0 : 0] * dq + sc;
+    const int8_t *ga1 = Xq + (int64_t)s_dst[oka1 ? sr1 : 0] * dq + sc;
+    const int8_t *gb0 = Xq + (int64_t)s_bpt[okb0 ? sr0 : 0] * dq + sc;
+    const int8_t *gb1 = Xq + (int64_t)s_bpt[okb1 ? sr1 : 0] * dq + sc;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
+    u32x4 va0, va1, vb0 = z4, vb1 = z4;
+    auto gather = [&](int k0) {
+        va0 = *reinterpret_cast<const u32x4 *>(ga0 + k0);
+        va1 = *reinterpret_cast<const u32x4 *>(ga1 + k0);
+        if (!same) {
+            vb0 = *reinterpret_cast<const u32x4 *>(gb0 + k0);
+            vb1 = *reinterpret_cast<const u32x4 *>(gb1 + k0);
         }
-        if (!same)
-            for (int v = tid; v < b_pad * VPR; v += NT) {
-                const int r = v / VPR, c = (v % VPR) * 16;
-                uint4 val = make_uint4(0, 0, 0, 0);
-                if (r < job.b_rows) val = *reinterpret_cast<const uint4 *>(Xq + (int64_t)s_bpt[r] * dq + k0 + c);
-                *reinterpret_cast<uint4 *>(s_b + r * kQ8LDW + c) = val;
-            }
-        __syncthreads();
-        const int8_t *sb_base = same ? s_a : s_b;
+    };
+    auto put = [&](int buf) {
+        int8_t *pa = s_a[buf], *pb = s_b[buf];
+        if (sta0) *reinterpret_cast<u32x4 *>(pa + sr0 * kQ8LDW + sc) = oka0 ? va0 : z4;
+        if (sta1) *reinterpret_cast<u32x4 *>(pa + sr1 * kQ8LDW + sc) = oka1 ? va1 : z4;
+        if (stb0) *reinterpret_cast<u32x4 *>(pb + sr0 * kQ8LDW + sc) = okb0 ? vb0 : z4;
+        if (stb1) *reinterpret_cast<u32x4 *>(pb + sr1 * kQ8LDW + sc) = okb1 ? vb1 : z4;
+    };
+    gather(0);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < dq; k0 += kQ8KC) {
+        const bool more = k0 + kQ8KC < dq;
+        if (more) gather(k0 + kQ8KC);
+        const int8_t *sa = s_a[buf];
+        const int8_t *sb = same ? s_a[buf] : s_b[buf];
         if (active) {
 #pragma unroll
             for (int kk = 0; kk < kQ8KC; kk += 32) {
-                const i32x4 fa = *reinterpret_cast<const i32x4 *>(s_a + (32 * wu + fr) * kQ8LDW + kk + fk);
+                const i32x4 fa = *reinterpret_cast<const i32x4 *>(sa + (32 * wu + fr) * kQ8LDW + kk + fk);
+                i32x4 fb[MB];
 #pragma unroll
-                for (int cb = 0; cb < MB; cb++) {
-                    if (cb < nbb) {
-                        const i32x4 fb = *reinterpret_cast<const i32x4 *>(sb_base + (32 * cb + fr) * kQ8LDW + kk + fk);
-                        acc[cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fb, acc[cb], 0, 0, 0);
-                    }
-                }
+                for (int cb = 0; cb < MB; cb++)
+                    fb[cb] = *reinterpret_cast<const i32x4 *>(sb + (32 * (cb < nbb ? cb : 0) + fr) * kQ8LDW + kk + fk);
+#pragma unroll
+                for (int cb = 0; cb < MB; cb++)
+                    if (cb < nbb) acc[cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fb[cb], acc[cb], 0, 0, 0);
             }
         }
+        if (more) put(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
     if (!active) return;
 
@@ -3126,11 +3167,12 @@ static void cand_launches(const ForestView &v, const CandStage &cs, int K, const
     const bool grid = v.sym_prec == RPF_DIST_U8GRID && cs.all_points;
     auto grid_launch = [&](const TileJob *jobs, int64_t njobs, const TileOut &o) {
         if (njobs <= 0) return;
+        const dim3 g((unsigned)(8 * ((njobs + 7) / 8)));
         switch (v.job_mb) {
-            case 1: hipLaunchKernelGGL(k_tile_q8<1>, dim3((unsigned)njobs), dim3(64), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
-            case 2: hipLaunchKernelGGL(k_tile_q8<2>, dim3((unsigned)njobs), dim3(128), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
-            case 4: hipLaunchKernelGGL(k_tile_q8<4>, dim3((unsigned)njobs), dim3(256), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
-            default: hipLaunchKernelGGL(k_tile_q8<8>, dim3((unsigned)njobs), dim3(512), 0, s, jobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            case 1: hipLaunchKernelGGL(k_tile_q8<1>, g, dim3(64), 0, s, jobs, njobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            case 2: hipLaunchKernelGGL(k_tile_q8<2>, g, dim3(128), 0, s, jobs, njobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            case 4: hipLaunchKernelGGL(k_tile_q8<4>, g, dim3(256), 0, s, jobs, njobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
+            default: hipLaunchKernelGGL(k_tile_q8<8>, g, dim3(512), 0, s, jobs, njobs, v.Xq, v.dq, v.qn, v.perm, v.n, cs.excl, o); break;
         }
         launch_check(s, "k_tile_q8");
     };

@@ -3,7 +3,7 @@
 binary32 rounding of k / 255): neighbour indices bit-exact against the oracle (binary64
 ranking, ties by index) and distances within 1e-5 relative, for copied-leaf and one-tile
 leaf shapes, d not a multiple of 64, include/exclude self, exact duplicates (small d on the
-grid), K 100; queries on such a forest (binary32 tiles); data off the grid is rejected."""
+grid), K 100, tile lists several times longer than the resident grid; queries on such a forest (binary32 tiles); data off the grid is rejected."""
 
 import numpy as np
 import pytest
@@ -25,6 +25,10 @@ CASES = [
     ("duplicates_d4", 6000, 4, 5, 60, 8, 1),
     ("big_k", 12_000, 24, 12, 200, 100, 1),
     ("leaves390_d200", 25_000, 200, 6, 400, 16, 0),
+    # many more tiles than resident blocks at 64- and 128-row tiles: each block runs
+    # several jobs, the next one's rows loaded during the current one
+    ("many_tiles_mb2", 60_000, 8, 8, 64, 10, 1),
+    ("many_tiles_mb4", 40_000, 12, 6, 128, 10, 1),
 ]
 
 
