@@ -407,11 +407,20 @@ __device__ inline float cheap_phi(float tv, float na, float ra, float nmax, floa
     return (th - na) + 1e-5f * (th + na + nmax) + 1e-30f;
 }
 
+// Workgroups are dealt to the eight XCDs in turn, so block b runs on XCD b % 8.  Block b takes
+// job (b % 8) * per + b / 8: each XCD walks one contiguous range of the job list front to back,
+// so the tiles of one leaf, which read the same rows, meet in that XCD's L2.  The grid is
+// 8 * per blocks with per = ceil(njobs / 8); blocks past the list return.
+__device__ inline int64_t xcd_job() {
+    const int64_t per = (int64_t)gridDim.x >> 3;
+    return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
 // One tile job per block: A rows x B rows of one leaf (or query group x leaf), MB waves,
-// wave w owns A rows [32w, 32w + 32) against all B rows.
+// wave w owns A rows [32w, 32w + 32) against all B rows.  Jobs are taken in XCD order (xcd_job).
 template <int MB, int PREC>
 __global__ __launch_bounds__(64 * MB) void k_tile(
-    const TileJob *__restrict__ jobs, const void *__restrict__ A_, const void *__restrict__ B_, int dp,
+    const TileJob *__restrict__ jobs, int64_t njobs, const void *__restrict__ A_, const void *__restrict__ B_, int dp,
     int64_t a_stride_tree, int64_t b_stride_tree, const float2 *__restrict__ a_nrm, const float2 *__restrict__ b_nrm,
     const int32_t *__restrict__ a_dest, const int32_t *__restrict__ b_pt, BoundCoef bc, int exclude_self,
     TileOut out) {
@@ -427,7 +436,9 @@ __global__ __launch_bounds__(64 * MB) void k_tile(
     __shared__ float s_bmax[2];
     __shared__ uint2 s_que[MB][kQueue];
 
-    const TileJob job = jobs[blockIdx.x];
+    const int64_t ji = xcd_job();
+    if (ji >= njobs) return;
+    const TileJob job = jobs[ji];
     const int t = job.tree;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -651,15 +662,6 @@ __device__ inline int32_t lattice_phi(float tv, int32_t na, float ra, float rbma
     const double pd = (double)st * (double)st * 65025.0 * (1.0 + 1e-5) + 2.0;
     const double ph = pd - (double)na;
     return ph >= 2.0e9 ? INT32_MAX : (int32_t)ph;
-}
-
-// Workgroups are dealt to the eight XCDs in turn, so block b runs on XCD b % 8.  Block b takes
-// job (b % 8) * per + b / 8: each XCD walks one contiguous range of the job list front to back,
-// so the tiles of one leaf, which read the same rows, meet in that XCD's L2.  The grid is
-// 8 * per blocks with per = ceil(njobs / 8); blocks past the list return.
-__device__ inline int64_t xcd_job() {
-    const int64_t per = (int64_t)gridDim.x >> 3;
-    return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
 // All-points tile of grid points (one job: A rows x B rows of one leaf, MB waves; wave w owns
@@ -2772,8 +2774,8 @@ static void tile_launch(hipStream_t s, int64_t njobs, const TileJob *jobs, const
                         int64_t as, int64_t bs, const float2 *an, const float2 *bn, const int32_t *ad,
                         const int32_t *bp, BoundCoef bc, int excl, const TileOut &out) {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL((k_tile<MB, PREC>), dim3((unsigned)njobs), dim3(64 * MB), 0, s, jobs, A, B, dp, as, bs, an, bn,
-                       ad, bp, bc, excl, out);
+    hipLaunchKernelGGL((k_tile<MB, PREC>), dim3((unsigned)(8 * ((njobs + 7) / 8))), dim3(64 * MB), 0, s, jobs, njobs, A,
+                       B, dp, as, bs, an, bn, ad, bp, bc, excl, out);
     launch_check(s, "k_tile");
 }
 
