@@ -8,8 +8,8 @@ resident in device memory before the timed region.
 
 The metric is queries/s at recall >= 0.99.  The recall (1 - the missing rate of Sec. 5.1)
 is measured against the exact kNN of a seeded sample of 10 000 points (rpf_exact_knn);
-the forest is grown tree by tree (nested forests: 32, 48, 64, 80, ... trees) until it
-reaches 0.99, and the step is timed there: bfloat16 tiles + binary32/binary64 re-rank
+the forest is grown tree by tree (nested forests: 32, 48, 56, 64, 68, 72, ... trees) until
+it reaches 0.99, and the step is timed there: bfloat16 tiles + binary32/binary64 re-rank
 (`value`) and plain binary32 tiles beside it, same steps and warm-up.  The named
 configuration (32 trees) is timed as a sub-record.  Also: the roofline of the dominant
 kernel (HIP events on the launch stream, inside the library), the precision path on 1M x 784
@@ -33,9 +33,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kNN queries/s at ≥0.99 recall, FP32 vs BF16+rerank; p50/p99 latency"
 PROFILES = os.path.join(ROOT, "profiles")
-# HBM bytes per dispatch of the headline step's kernels (two rocprofv3 counter runs of
-# `--only-step 80:bf16x3`), valid while the HIP sources hash to the value recorded in it
-TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_allknn_1M_d128_T80_bf16x3.md")
+# HBM bytes per dispatch of the headline step's kernels at T trees (two rocprofv3 counter runs
+# of `--only-step T:bf16x3`), valid while the HIP sources hash to the value recorded in it
+
+
+def traffic_file(T):
+    return os.path.join(PROFILES, f"hbm_traffic_allknn_1M_d128_T{T}_bf16x3.md")
 PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "u8grid": 4}
 # kernel (name prefix in the counter summary) behind each timed record of the library for the
 # 1M x 128 workload (leaves of 244/245 points: the 8 x 8 symmetric tile)
@@ -99,7 +102,7 @@ def parse():
                     help="tile precision of the headline (low-precision + re-rank) path")
     ap.add_argument("--target-recall", type=float, default=0.99,
                     help="recall the at-target leg looks for by growing more trees (0 = skip the leg)")
-    ap.add_argument("--target-trees", default="48,64,80,96,128",
+    ap.add_argument("--target-trees", default="48,56,64,68,72,76,80,88,96,112,128",
                     help="tree counts the at-target leg tries, in order (the first T trees are the bench's)")
     ap.add_argument("--cpu-trees", type=int, default=0,
                     help="trees the CPU baseline builds (its time is scaled to all trees; 0 = all)")
@@ -170,7 +173,7 @@ def stage_summary(prof, steps, n, d, T, L, K):
     t_flops = sum(r["algo_flops"] for r in tiles) / steps
     t_ms = sum(r["total_ms"] for r in tiles) / steps
     peak = mfma_peak(tiles[0].get("prec") if tiles else None)
-    measured = build_traffic_per_step()
+    measured = build_traffic_per_step(T)
     return {
         "build_levels_ms": round(lv_ms, 3),
         "build_levels_algorithmic_bytes": lv_bytes,
@@ -294,11 +297,12 @@ def kt_summary(d):
               f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
 
 
-def _traffic_table():
-    """The committed counter summary of the headline step, or None when absent or stale."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _traffic_table(T):
+    """The committed counter summary of the headline step at T trees, or None when absent or
+    stale."""
+    if not os.path.exists(traffic_file(T)):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(traffic_file(T)) as fh:
         js = [ln for ln in fh if ln.startswith("{")]
     if not js:
         return None
@@ -306,10 +310,11 @@ def _traffic_table():
     return t if t.get("source_hash") == source_hash() else None
 
 
-def traffic_for(record, prec):
-    """HBM bytes per launch of a timed record (scaled FETCH_SIZE + WRITE_SIZE), or None."""
+def traffic_for(record, prec, T):
+    """HBM bytes per launch of a timed record at T trees (scaled FETCH_SIZE + WRITE_SIZE), or
+    None."""
     pat = RECORD_KERNEL.get(record)
-    t = _traffic_table()
+    t = _traffic_table(T)
     if not pat or t is None:
         return None
     pat = pat.format(p=PREC_INDEX.get(prec, 0))
@@ -319,10 +324,10 @@ def traffic_for(record, prec):
     return None
 
 
-def build_traffic_per_step():
-    """HBM bytes of the build-level kernels in one step, from the counter summary (whose run
-    is one step), or None."""
-    t = _traffic_table()
+def build_traffic_per_step(T):
+    """HBM bytes of the build-level kernels in one step at T trees, from the counter summary
+    (whose run is one step), or None."""
+    t = _traffic_table(T)
     if t is None:
         return None
     return sum(v["bytes_per_dispatch"] * v["dispatches"] for k, v in t["kernels"].items()
@@ -564,10 +569,10 @@ def main():
 
     dom, roof = roofline(head_prof)
     if roof is not None and dom is not None:
-        tr = traffic_for(dom, args.headline_prec)
+        tr = traffic_for(dom, args.headline_prec, t_star)
         roof["traffic"] = tr  # HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE), or None
         if tr is not None:
-            roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
+            roof["traffic_source"] = os.path.relpath(traffic_file(t_star), ROOT)
     stages = stage_summary(head_prof, args.steps, n, d, t_star, L, K)
 
     f = rpf.build(X, t_star, n0, dirs(t_star), dist_prec=args.headline_prec)
