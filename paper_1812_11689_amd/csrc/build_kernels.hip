@@ -32,14 +32,15 @@ __device__ inline void project_segment(const float *__restrict__ X, int d, const
 }
 
 // LDS layout: perm[m] int32 | key[m] u64 | dir[d] | hist[256] | misc ; nTry>1 adds p[m], tree[P2]
-template <bool VEC, bool LEAD>
+// Q8: the node projections read rows from the int8 grid copy Xq (stride dq); the same values
+template <bool VEC, bool LEAD, bool Q8 = false>
 __global__ __launch_bounds__(256) void k_level_small(
     const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
     const SegDesc *__restrict__ segs, const int32_t *__restrict__ perm_in,
     int32_t *__restrict__ perm_out, int64_t n, double *__restrict__ split,
     int32_t *__restrict__ split_idx, int32_t *__restrict__ chosen, int32_t *__restrict__ err,
     const LookDesc *__restrict__ look, double2 *__restrict__ ahead, uint64_t *__restrict__ keys_next,
-    const uint64_t *__restrict__ keys_in) {
+    const uint64_t *__restrict__ keys_in, const int8_t *__restrict__ Xq, int dq) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int t = blockIdx.y;
     const SegDesc sg = segs[blockIdx.x];
@@ -102,8 +103,12 @@ __global__ __launch_bounds__(256) void k_level_small(
         for (int base = 0; base < m; base += 64) {  // rows base + pt and base + 32 + pt
             const int ia = base + pt, ib = ia + 32;
             double p[6];
-            group8_dot64x3r2<VEC>(X + (int64_t)s_perm[ia < m ? ia : 0] * d, X + (int64_t)s_perm[ib < m ? ib : 0] * d,
-                                  s_rd, ds, d, g, p);
+            if constexpr (Q8)
+                group8_dot64x3r2_q8(Xq + (int64_t)s_perm[ia < m ? ia : 0] * dq, Xq + (int64_t)s_perm[ib < m ? ib : 0] * dq,
+                                    s_rd, ds, d, g, p);
+            else
+                group8_dot64x3r2<VEC>(X + (int64_t)s_perm[ia < m ? ia : 0] * d, X + (int64_t)s_perm[ib < m ? ib : 0] * d,
+                                      s_rd, ds, d, g, p);
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const int i = h ? ib : ia;
@@ -120,7 +125,9 @@ __global__ __launch_bounds__(256) void k_level_small(
         for (int base = 0; base < m; base += 32) {
             int i = base + pt;
             int ii = i < m ? i : 0;
-            double p = group8_dot64<VEC>(X + (int64_t)s_perm[ii] * d, s_r, d, g);
+            double p;
+            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)s_perm[ii] * dq, s_r, d, g);
+            else p = group8_dot64<VEC>(X + (int64_t)s_perm[ii] * d, s_r, d, g);
             if (g == 0 && i < m) s_key[i] = key_of(p);
         }
     }
@@ -539,14 +546,15 @@ void launch_subtree(hipStream_t s, bool vec, const float *X, int d, const float 
 
 // ================================================================ large segments
 
-template <bool VEC, bool LEAD>
+// Q8: rows read from the int8 grid copy Xq (stride dq) instead of X; the same values
+template <bool VEC, bool LEAD, bool Q8 = false>
 __global__ __launch_bounds__(256) void k_proj_chunks(
     const float *__restrict__ X, int d, const float *__restrict__ R, int64_t H, int n_try,
     const SegDesc *__restrict__ segs, const ChunkDesc *__restrict__ chunks,
     const int32_t *__restrict__ perm, int64_t n, SelState *__restrict__ state, int nseg,
     int mode,  // 0: final projection -> keys + digit-0 histogram; 1: raw projection of try `tr`
     int tr, uint64_t *__restrict__ keys, double *__restrict__ praw, uint32_t *__restrict__ hist,
-    const LookDesc *__restrict__ look, double2 *__restrict__ ahead) {
+    const LookDesc *__restrict__ look, double2 *__restrict__ ahead, const int8_t *__restrict__ Xq, int dq) {
     // the node's direction (binary32); on a lead level it and its children's, as binary64
     extern __shared__ __align__(16) uint8_t s_dir[];
     float *s_r = reinterpret_cast<float *>(s_dir);
@@ -578,7 +586,8 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
             const int ia = base + pt, ib = ia + 32;
             const int64_t sa = c.start + (ia < c.len ? ia : 0), sb = c.start + (ib < c.len ? ib : 0);
             double p[6];
-            group8_dot64x3r2<VEC>(X + (int64_t)pp[sa] * d, X + (int64_t)pp[sb] * d, s_rd, ds, d, g, p);
+            if constexpr (Q8) group8_dot64x3r2_q8(Xq + (int64_t)pp[sa] * dq, Xq + (int64_t)pp[sb] * dq, s_rd, ds, d, g, p);
+            else group8_dot64x3r2<VEC>(X + (int64_t)pp[sa] * d, X + (int64_t)pp[sb] * d, s_rd, ds, d, g, p);
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const int i = h ? ib : ia;
@@ -597,7 +606,9 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
         for (int base = 0; base < c.len; base += 32) {
             const int i = base + pt;
             const int64_t s = c.start + (i < c.len ? i : 0);
-            double p = group8_dot64<VEC>(X + (int64_t)pp[s] * d, s_r, d, g);
+            double p;
+            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)pp[s] * dq, s_r, d, g);
+            else p = group8_dot64<VEC>(X + (int64_t)pp[s] * d, s_r, d, g);
             if (g == 0 && i < c.len) {
                 if (mode == 0) {
                     uint64_t u = key_of(p);
@@ -612,7 +623,9 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
         for (int base = 0; base < c.len; base += 32) {
             const int i = base + pt;
             const int64_t s = c.start + (i < c.len ? i : 0);
-            double p = group8_dot64<false>(X + (int64_t)pp[s] * d, Rn, d, g);
+            double p;
+            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)pp[s] * dq, Rn, d, g);
+            else p = group8_dot64<false>(X + (int64_t)pp[s] * d, Rn, d, g);
             if (g == 0 && i < c.len) {
                 if (mode == 0) {
                     uint64_t u = key_of(p);
@@ -1545,13 +1558,16 @@ void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const fl
     auto go = [&](auto kern) {
         hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, d, R, H, n_try, segs, pin, pout, n, split, split_idx,
-                           chosen, err, lk.look, lk.ahead, lk.keys_next, lk.keys_in);
+                           chosen, err, lk.look, lk.ahead, lk.keys_next, lk.keys_in, lk.xq, lk.dq);
     };
+    const bool q8 = lk.xq && n_try == 1;  // (several tries project through the binary32 rows)
     if (lk.look) {
-        if (vec) go(k_level_small<true, true>);
+        if (q8) go(k_level_small<false, true, true>);
+        else if (vec) go(k_level_small<true, true>);
         else go(k_level_small<false, true>);
     } else {
-        if (vec) go(k_level_small<true, false>);
+        if (q8) go(k_level_small<false, false, true>);
+        else if (vec) go(k_level_small<true, false>);
         else go(k_level_small<false, false>);
     }
     launch_check(s, "k_level_small");
@@ -1565,12 +1581,19 @@ static void proj_chunks(hipStream_t s, dim3 gc, const float *X, int d, const flo
                         const LargeBufs &b, int nseg, int mode, int tr, const LevelLink &lk) {
     const size_t ds = (size_t)((d + 3) & ~3);
     const size_t lds = d > 1024 ? 0 : lk.look ? 3 * ds * sizeof(double) : ds * sizeof(float);
-    if (lk.look)
+    const bool q8 = lk.xq != nullptr;
+    if (lk.look && q8)
+        hipLaunchKernelGGL((k_proj_chunks<false, true, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
+                           pin, n, b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
+    else if (lk.look)
         hipLaunchKernelGGL((k_proj_chunks<VEC, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,
-                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead);
+                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
+    else if (q8)
+        hipLaunchKernelGGL((k_proj_chunks<false, false, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
+                           pin, n, b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
     else
         hipLaunchKernelGGL((k_proj_chunks<VEC, false>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,
-                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead);
+                           b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
     launch_check(s, "k_proj_chunks");
 }
 

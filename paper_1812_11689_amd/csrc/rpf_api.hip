@@ -899,11 +899,15 @@ static void build_launches(rpf_forest *f, hipStream_t s) {
         }
         // the roots: identity permutation in every tree, so one read of X serves all trees
         lk.roots = l == 0 && lv.lead && lv.large && vec && d <= 128;
+        // grid forests: the rows come from the int8 copy (one byte a coordinate)
+        lk.xq = f->Xq;
+        lk.dq = f->dq;
+        const double xb = f->Xq ? (double)f->dq : 4.0 * d;  // bytes of a row read
         // algorithmic bytes: X rows (none on a fed level), ids and keys, the children's
         // projections out and back on a lead level
-        const double row_bytes = (lv.fed ? 8.0 : 4.0 * d + 8) + 4 + (lv.lead ? 16.0 : 0.0);
+        const double row_bytes = (lv.fed ? 8.0 : xb + 8) + 4 + (lv.lead ? 16.0 : 0.0);
         const double proj_bytes = lk.roots ? members * (4.0 * d) + (double)T * members * (8 + 16)
-                                           : (double)T * members * (4.0 * d + 4 + 8 + (lv.lead ? 16.0 : 0.0));
+                                           : (double)T * members * (xb + 4 + 8 + (lv.lead ? 16.0 : 0.0));
         if (!lv.large) {
             ProfScope ps(s, "level_small", (double)T * members * row_bytes, 0);
             launch_level_small(s, vec, f->X, d, f->R, H, n_try, f->d_segs + lv.seg_off, (int)lv.segs.size(),

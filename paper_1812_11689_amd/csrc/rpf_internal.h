@@ -107,6 +107,10 @@ struct LevelLink {
     const uint64_t *keys_in = nullptr;  // fed: keys made by the lead (null: project)
     uint32_t *hist_in = nullptr;        // fed multi-block level: histograms made by the lead
     bool roots = false;  // lead at the roots (identity permutation): one read of X for all trees
+    // grid forests: the projections read each row from the int8 copy (k - 128, stride dq)
+    // instead of X, a quarter of the bytes for the same binary32 values
+    const int8_t *xq = nullptr;
+    int dq = 0;
 };
 
 struct SubItem {       // an internal node at the first level of the persistent subtree launch
@@ -500,6 +504,61 @@ __device__ inline void group8_dot64x3r2(const float *__restrict__ xa, const floa
                         s[k][e] = __builtin_fma(ae, rv, s[k][e]);
                         s[k + 3][e] = __builtin_fma(be, rv, s[k + 3][e]);
                     }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double w = (s[k][0] + s[k][1]) + (s[k][2] + s[k][3]);
+        w = w + shfl_xor_d(w, 1);
+        w = w + shfl_xor_d(w, 2);
+        w = w + shfl_xor_d(w, 4);
+        p[k] = w + 0.0;
+    }
+}
+
+// Binary32 coordinate of a grid point from its int8 copy (byte k - 128): the binary64 product
+// k * (1/255) rounded to binary32, which equals the correctly rounded quotient k / 255 for
+// every k in [0, 255].  The copy holds only coordinates x with float(k) / 255 == x, so this is
+// x itself (up to the sign of a zero, which no sum below can see), returned as binary64.
+__device__ inline double grid_x(uint32_t k) { return (double)(float)((double)k * (1.0 / 255.0)); }
+
+// group8_dot64 over a row of the int8 grid copy (4-byte aligned, zero-padded past d): the
+// same lanes, elements and order as the binary32 forms, so the value is theirs bit for bit.
+__device__ inline double group8_dot64_q8(const int8_t *__restrict__ x, const float *__restrict__ r, int d, int g) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 4 * g; j < d; j += 32) {
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(x + j) ^ 0x80808080u;
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+            if (e == 0 || j + e < d) s[e] = __builtin_fma(grid_x((w >> (8 * e)) & 255u), (double)r[j + e], s[e]);
+    }
+    double v = (s[0] + s[1]) + (s[2] + s[3]);
+    v = v + shfl_xor_d(v, 1);
+    v = v + shfl_xor_d(v, 2);
+    v = v + shfl_xor_d(v, 4);
+    return v + 0.0;
+}
+
+// group8_dot64x3r2 over two rows of the int8 grid copy; bit for bit the binary32 form's values.
+__device__ inline void group8_dot64x3r2_q8(const int8_t *__restrict__ xa, const int8_t *__restrict__ xb,
+                                           const double *__restrict__ r, int rs, int d, int g, double p[6]) {
+    double s[6][4];
+#pragma unroll
+    for (int k = 0; k < 6; k++) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0.0;
+    for (int j = 4 * g; j < d; j += 32) {
+        const uint32_t wa = *reinterpret_cast<const uint32_t *>(xa + j) ^ 0x80808080u;
+        const uint32_t wb = *reinterpret_cast<const uint32_t *>(xb + j) ^ 0x80808080u;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (e == 0 || j + e < d) {
+                const double ae = grid_x((wa >> (8 * e)) & 255u), be = grid_x((wb >> (8 * e)) & 255u);
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const double rv = r[k * rs + j + e];
+                    s[k][e] = __builtin_fma(ae, rv, s[k][e]);
+                    s[k + 3][e] = __builtin_fma(be, rv, s[k + 3][e]);
                 }
             }
         }

@@ -55,6 +55,36 @@ def test_build_matches_oracle(case):
     f.free()
 
 
+GRID_CASES = [
+    # points on the 1/255 grid, built with RPF_DIST_U8GRID: the projections read each row from
+    # the int8 copy (k - 128) instead of X and must give the same splits bit for bit
+    # name, n, d, T, n0, n_try
+    ("grid_d784", 5000, 784, 2, 512, 1),
+    ("grid_d50_multiblock", 40_000, 50, 3, 64, 1),
+    ("grid_d7_ntry3", 6000, 7, 2, 30, 3),
+]
+
+
+@pytest.mark.parametrize("case", GRID_CASES, ids=[c[0] for c in GRID_CASES])
+def test_grid_build_matches_oracle(case):
+    from paper_1812_11689_amd import rpf
+    name, n, d, T, n0, n_try = case
+    print(f"[build] {name} n={n} d={d} T={T} n0={n0} nTry={n_try} (int8 grid rows)", flush=True)
+    x, R = problem(n, d, T, n0, n_try, seed=len(name) + 50, kind="quant")
+    ref = oracle.build_forest(x, R, T, n0, n_try)
+    f = rpf.build(torch.from_numpy(x).cuda(), T, n0, torch.from_numpy(np.ascontiguousarray(R[:T])).cuda(),
+                  n_try=n_try, dist_prec="u8grid")
+    f.info()
+    for t in range(T):
+        g = {k: v.cpu().numpy() for k, v in f.tree_dump(t).items()}
+        np.testing.assert_array_equal(g["perm"], ref.perm[t])
+        np.testing.assert_array_equal(g["leaf_of"], ref.leaf_of[t])
+        assert np.array_equal(g["split"].view(np.uint64), ref.split[t].view(np.uint64))
+        np.testing.assert_array_equal(g["split_idx"], ref.split_idx[t])
+        np.testing.assert_array_equal(g["chosen"], ref.chosen[t])
+    f.free()
+
+
 SUBTREE_CASES = [c for c in CASES if c[5] == 1 and c[0] not in ("single_leaf", "n0_plus_1")] + [
     # every level one-block from the root; levels of mixed leaf and internal nodes
     ("all_small_levels", 3000, 6, 3, 10, 1, "mixture", 0),
