@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_level_small(
             const int ia = base + pt, ib = ia + 32;
             double p[6];
             if constexpr (Q8)
-                group8_dot64x3r2_q8(Xq + (int64_t)s_perm[ia < m ? ia : 0] * dq, Xq + (int64_t)s_perm[ib < m ? ib : 0] * dq,
+                group8_dot64x3r2_q8<VEC>(Xq + (int64_t)s_perm[ia < m ? ia : 0] * dq, Xq + (int64_t)s_perm[ib < m ? ib : 0] * dq,
                                     s_rd, ds, d, g, p);
             else
                 group8_dot64x3r2<VEC>(X + (int64_t)s_perm[ia < m ? ia : 0] * d, X + (int64_t)s_perm[ib < m ? ib : 0] * d,
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_level_small(
             int i = base + pt;
             int ii = i < m ? i : 0;
             double p;
-            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)s_perm[ii] * dq, s_r, d, g);
+            if constexpr (Q8) p = group8_dot64_q8<VEC>(Xq + (int64_t)s_perm[ii] * dq, s_r, d, g);
             else p = group8_dot64<VEC>(X + (int64_t)s_perm[ii] * d, s_r, d, g);
             if (g == 0 && i < m) s_key[i] = key_of(p);
         }
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
             const int ia = base + pt, ib = ia + 32;
             const int64_t sa = c.start + (ia < c.len ? ia : 0), sb = c.start + (ib < c.len ? ib : 0);
             double p[6];
-            if constexpr (Q8) group8_dot64x3r2_q8(Xq + (int64_t)pp[sa] * dq, Xq + (int64_t)pp[sb] * dq, s_rd, ds, d, g, p);
+            if constexpr (Q8) group8_dot64x3r2_q8<VEC>(Xq + (int64_t)pp[sa] * dq, Xq + (int64_t)pp[sb] * dq, s_rd, ds, d, g, p);
             else group8_dot64x3r2<VEC>(X + (int64_t)pp[sa] * d, X + (int64_t)pp[sb] * d, s_rd, ds, d, g, p);
 #pragma unroll
             for (int h = 0; h < 2; h++) {
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
             const int i = base + pt;
             const int64_t s = c.start + (i < c.len ? i : 0);
             double p;
-            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)pp[s] * dq, s_r, d, g);
+            if constexpr (Q8) p = group8_dot64_q8<VEC>(Xq + (int64_t)pp[s] * dq, s_r, d, g);
             else p = group8_dot64<VEC>(X + (int64_t)pp[s] * d, s_r, d, g);
             if (g == 0 && i < c.len) {
                 if (mode == 0) {
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256) void k_proj_chunks(
             const int i = base + pt;
             const int64_t s = c.start + (i < c.len ? i : 0);
             double p;
-            if constexpr (Q8) p = group8_dot64_q8(Xq + (int64_t)pp[s] * dq, Rn, d, g);
+            if constexpr (Q8) p = group8_dot64_q8<false>(Xq + (int64_t)pp[s] * dq, Rn, d, g);
             else p = group8_dot64<false>(X + (int64_t)pp[s] * d, Rn, d, g);
             if (g == 0 && i < c.len) {
                 if (mode == 0) {
@@ -1562,11 +1562,13 @@ void launch_level_small(hipStream_t s, bool vec, const float *X, int d, const fl
     };
     const bool q8 = lk.xq && n_try == 1;  // (several tries project through the binary32 rows)
     if (lk.look) {
-        if (q8) go(k_level_small<false, true, true>);
+        if (q8 && vec) go(k_level_small<true, true, true>);
+        else if (q8) go(k_level_small<false, true, true>);
         else if (vec) go(k_level_small<true, true>);
         else go(k_level_small<false, true>);
     } else {
-        if (q8) go(k_level_small<false, false, true>);
+        if (q8 && vec) go(k_level_small<true, false, true>);
+        else if (q8) go(k_level_small<false, false, true>);
         else if (vec) go(k_level_small<true, false>);
         else go(k_level_small<false, false>);
     }
@@ -1583,13 +1585,13 @@ static void proj_chunks(hipStream_t s, dim3 gc, const float *X, int d, const flo
     const size_t lds = d > 1024 ? 0 : lk.look ? 3 * ds * sizeof(double) : ds * sizeof(float);
     const bool q8 = lk.xq != nullptr;
     if (lk.look && q8)
-        hipLaunchKernelGGL((k_proj_chunks<false, true, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
+        hipLaunchKernelGGL((k_proj_chunks<VEC, true, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
                            pin, n, b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
     else if (lk.look)
         hipLaunchKernelGGL((k_proj_chunks<VEC, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,
                            b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
     else if (q8)
-        hipLaunchKernelGGL((k_proj_chunks<false, false, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
+        hipLaunchKernelGGL((k_proj_chunks<VEC, false, true>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks,
                            pin, n, b.state, nseg, mode, tr, b.keys, b.praw, b.hist, lk.look, lk.ahead, lk.xq, lk.dq);
     else
         hipLaunchKernelGGL((k_proj_chunks<VEC, false>), gc, dim3(256), lds, s, X, d, R, H, n_try, segs, chunks, pin, n,

@@ -526,13 +526,24 @@ __device__ inline double grid_x(uint32_t k) { return (double)(float)((double)k *
 
 // group8_dot64 over a row of the int8 grid copy (4-byte aligned, zero-padded past d): the
 // same lanes, elements and order as the binary32 forms, so the value is theirs bit for bit.
+// VEC: d % 4 == 0 (no element guards, r 16-byte aligned).
+template <bool VEC>
 __device__ inline double group8_dot64_q8(const int8_t *__restrict__ x, const float *__restrict__ r, int d, int g) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
     for (int j = 4 * g; j < d; j += 32) {
         const uint32_t w = *reinterpret_cast<const uint32_t *>(x + j) ^ 0x80808080u;
+        if (VEC) {
+            const float4 rv = *reinterpret_cast<const float4 *>(r + j);
+            s[0] = __builtin_fma(grid_x(w & 255u), (double)rv.x, s[0]);
+            s[1] = __builtin_fma(grid_x((w >> 8) & 255u), (double)rv.y, s[1]);
+            s[2] = __builtin_fma(grid_x((w >> 16) & 255u), (double)rv.z, s[2]);
+            s[3] = __builtin_fma(grid_x(w >> 24), (double)rv.w, s[3]);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; e++)
-            if (e == 0 || j + e < d) s[e] = __builtin_fma(grid_x((w >> (8 * e)) & 255u), (double)r[j + e], s[e]);
+            for (int e = 0; e < 4; e++)
+                if (e == 0 || j + e < d) s[e] = __builtin_fma(grid_x((w >> (8 * e)) & 255u), (double)r[j + e], s[e]);
+        }
     }
     double v = (s[0] + s[1]) + (s[2] + s[3]);
     v = v + shfl_xor_d(v, 1);
@@ -542,23 +553,47 @@ __device__ inline double group8_dot64_q8(const int8_t *__restrict__ x, const flo
 }
 
 // group8_dot64x3r2 over two rows of the int8 grid copy; bit for bit the binary32 form's values.
+template <bool VEC>
 __device__ inline void group8_dot64x3r2_q8(const int8_t *__restrict__ xa, const int8_t *__restrict__ xb,
                                            const double *__restrict__ r, int rs, int d, int g, double p[6]) {
     double s[6][4];
 #pragma unroll
     for (int k = 0; k < 6; k++) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0.0;
+#pragma unroll 2
     for (int j = 4 * g; j < d; j += 32) {
         const uint32_t wa = *reinterpret_cast<const uint32_t *>(xa + j) ^ 0x80808080u;
         const uint32_t wb = *reinterpret_cast<const uint32_t *>(xb + j) ^ 0x80808080u;
+        if (VEC) {
+            double a[4], b[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            if (e == 0 || j + e < d) {
-                const double ae = grid_x((wa >> (8 * e)) & 255u), be = grid_x((wb >> (8 * e)) & 255u);
+            for (int e = 0; e < 4; e++) {
+                a[e] = grid_x((wa >> (8 * e)) & 255u);
+                b[e] = grid_x((wb >> (8 * e)) & 255u);
+            }
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    const double rv = r[k * rs + j + e];
-                    s[k][e] = __builtin_fma(ae, rv, s[k][e]);
-                    s[k + 3][e] = __builtin_fma(be, rv, s[k + 3][e]);
+            for (int k = 0; k < 3; k++) {
+                const double2 r0 = *reinterpret_cast<const double2 *>(r + k * rs + j);
+                const double2 r1 = *reinterpret_cast<const double2 *>(r + k * rs + j + 2);
+                s[k][0] = __builtin_fma(a[0], r0.x, s[k][0]);
+                s[k][1] = __builtin_fma(a[1], r0.y, s[k][1]);
+                s[k][2] = __builtin_fma(a[2], r1.x, s[k][2]);
+                s[k][3] = __builtin_fma(a[3], r1.y, s[k][3]);
+                s[k + 3][0] = __builtin_fma(b[0], r0.x, s[k + 3][0]);
+                s[k + 3][1] = __builtin_fma(b[1], r0.y, s[k + 3][1]);
+                s[k + 3][2] = __builtin_fma(b[2], r1.x, s[k + 3][2]);
+                s[k + 3][3] = __builtin_fma(b[3], r1.y, s[k + 3][3]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (e == 0 || j + e < d) {
+                    const double ae = grid_x((wa >> (8 * e)) & 255u), be = grid_x((wb >> (8 * e)) & 255u);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const double rv = r[k * rs + j + e];
+                        s[k][e] = __builtin_fma(ae, rv, s[k][e]);
+                        s[k + 3][e] = __builtin_fma(be, rv, s[k + 3][e]);
+                    }
                 }
             }
         }
