@@ -45,8 +45,8 @@ PREC_INDEX = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "u8grid": 4}
 RECORD_KERNEL = {
     "tile_phase2": "k_tile_sym<8, {p}, 2, 0>",
     "tile_phase1": "k_tile_sym<8, {p}, 0, 0>",
-    "proj_chunks_x3": "k_proj_chunks<true, true>",
-    "level_small": "k_level_small<true, true>",
+    "proj_chunks_x3": "k_proj_chunks<true, true, false>",
+    "level_small": "k_level_small<true, true, false>",
     "leaf_finalize": "k_leaf_stats<",
     "merge_first": "k_merge_first<",
     "final_rerank": "k_final<true",
