@@ -55,6 +55,30 @@ def test_plan_replays_equal_each_alone(prec):
     plan.close()
 
 
+def test_plan_on_the_grid_equals_each_alone():
+    # data sets on the 1/255 grid with int8 tiles: the recorded graph quantises each part,
+    # grows its trees from the int8 rows and runs the int8 tiles; every replay gives each data
+    # set the trees and neighbours of a forest grown over it alone
+    from paper_1812_11689_amd import rpf
+    sizes = [2500, 900, 4000, 1800]
+    dims = [40, 40, 64, 24]
+    T, n0, K = 3, 100, 6
+    print(f"[plan] u8grid sizes={sizes} dims={dims}", flush=True)
+    xs = [W.sparse_quantized(4100 + i, n, d) for i, (n, d) in enumerate(zip(sizes, dims))]
+    Rs = [W.directions(4150 + i, T, heap_count(n, n0), 1, d) for i, (n, d) in enumerate(zip(sizes, dims))]
+    plan = rpf.Plan(sizes, dims, T, n0, K, dist_prec="u8grid", max_part_points=4000)
+    plan.set_inputs(xs, Rs)
+    for rep in range(2):
+        plan.launch()
+        plan.check()
+        torch.cuda.synchronize()
+        for i in range(len(sizes)):
+            gi, gd = plan.result(i)
+            ai, ad, _ = _alone(xs[i], Rs[i], T, n0, K, "u8grid")
+            assert torch.equal(gi, ai) and torch.equal(gd, ad), f"replay {rep} data set {i}"
+    plan.close()
+
+
 def test_plan_reports_nonfinite_input():
     from paper_1812_11689_amd import rpf
     sizes, dims, T, n0 = [500, 800], [8, 8], 2, 30
