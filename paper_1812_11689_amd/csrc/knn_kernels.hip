@@ -3331,8 +3331,9 @@ static int all_points_first_trees(const ForestView &v, int K) {
     int want = (v.prec != RPF_DIST_FP32 && v.T >= 64) ? 2 * kFirstTrees : kFirstTrees;
     // uniform-rule trees: leaves of every size up to n0 (at 10^6 x 128, n0 256, a median of
     // about 40 points), so four trees' leaves hold too few candidates for a tight threshold.
-    // (The slot stride follows the largest leaf of any tree, so a deep chain of uneven splits
-    // that ends in a large leaf at the depth cap still limits the count.)
+    // (The slot stride is capped at n0: a leaf above it, which a deep chain of uneven splits
+    // can leave at the depth cap, sends its rows to the exhaustive path instead of limiting
+    // the count.)
     if (v.leaf_stride > 0) want = 2 * kFirstTrees;
     return std::min(want, max_first_trees(v, K));
 }
