@@ -639,14 +639,14 @@ constexpr int kQ8LDW = 80;  // LDS row stride in bytes (16-byte aligned, padded 
 // dint = sum (k_a - k_b)^2.  With q = k / 255 and each coordinate x = q (1 + e), |e| <= 2^-24
 // (one correctly rounded division), the real distance of the binary32 points is within
 // 2^-24 (|q_a| + |q_b|) of sqrt(dint) / 255; dint / 255^2 in binary32 is off by at most 3
-// roundings (2^-24 each); the 1e-6 widening covers the square roots' roundings and the
-// binary64 canonical sum.
+// roundings (2^-24 each); the 1e-6 widening covers the square roots (the hardware
+// instruction, within 1 ulp: 2^-22 relative once squared) and the binary64 canonical sum.
 __device__ inline void lattice_bounds(int32_t dint, float ra, float rb, float &lb, float &ub) {
     constexpr float u = 5.9604645e-8f;  // 2^-24
     const float dt = (float)dint * (1.f / 65025.f);
     const float delta = u * 1.01f * (ra + rb);
-    const float lo = fmaxf(sqrtf(dt * (1.f - 4.f * u)) - delta, 0.f);
-    const float hi = sqrtf(dt * (1.f + 4.f * u)) + delta;
+    const float lo = fmaxf(__builtin_amdgcn_sqrtf(dt * (1.f - 4.f * u)) - delta, 0.f);
+    const float hi = __builtin_amdgcn_sqrtf(dt * (1.f + 4.f * u)) + delta;
     lb = fminf(lo * lo * (1.f - 1e-6f), 3.40282347e38f);
     ub = hi * hi * (1.f + 1e-6f);
 }
@@ -866,20 +866,30 @@ __global__ __launch_bounds__(64 * MB) void k_tile_q8(const TileJob *__restrict__
         const int col = 32 * cb + (lane & 31);
         const bool colok = col < job.b_rows;
         const int32_t nb = s_nb[col];
+        // wave-uniform: only the block on the diagonal holds self pairs, and only the tile's
+        // last block columns past the leaf; the others take the test alone
+        const bool full = (same && exclude_self != 0 && cb == wu) || 32 * cb + 32 > job.b_rows;
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             uint32_t bits = 0;
             uint64_t mk[8];
             uint32_t tot = 0;
+            auto test = [&](auto FULL) {
 #pragma unroll
-            for (int v8 = 0; v8 < 8; v8++) {
-                const int v = 8 * h + v8;
-                const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const bool p = colok & (nb - 2 * acc[cb][v] <= pr[v]) & !(same & (exclude_self != 0) & (row == col));
-                bits |= (p ? 1u : 0u) << v8;
-                mk[v8] = __ballot(p);
-                tot += (uint32_t)__popcll(mk[v8]);
-            }
+                for (int v8 = 0; v8 < 8; v8++) {
+                    const int v = 8 * h + v8;
+                    bool p = nb - 2 * acc[cb][v] <= pr[v];
+                    if constexpr (decltype(FULL)::value) {
+                        const int row = 32 * wu + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        p = p & colok & !(same & (exclude_self != 0) & (row == col));
+                    }
+                    bits |= (p ? 1u : 0u) << v8;
+                    mk[v8] = __ballot(p);
+                    tot += (uint32_t)__popcll(mk[v8]);
+                }
+            };
+            if (full) test(std::true_type{});
+            else test(std::false_type{});
             if (qc + tot > (uint32_t)kQueue) {
                 flush(qc);
                 qc = 0;
