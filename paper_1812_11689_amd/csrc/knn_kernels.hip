@@ -640,7 +640,8 @@ constexpr int kQ8LDW = 80;  // LDS row stride in bytes (16-byte aligned, padded 
 // (one correctly rounded division), the real distance of the binary32 points is within
 // 2^-24 (|q_a| + |q_b|) of sqrt(dint) / 255; dint / 255^2 in binary32 is off by at most 3
 // roundings (2^-24 each); the 1e-6 widening covers the square roots (the hardware
-// instruction, within 1 ulp: 2^-22 relative once squared) and the binary64 canonical sum.
+// instruction, within 1 ulp: 2^-22 relative once squared; its argument is 0 or at least
+// 1/65025, never subnormal) and the binary64 canonical sum.
 __device__ inline void lattice_bounds(int32_t dint, float ra, float rb, float &lb, float &ub) {
     constexpr float u = 5.9604645e-8f;  // 2^-24
     const float dt = (float)dint * (1.f / 65025.f);
